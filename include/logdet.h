@@ -1,0 +1,188 @@
+/*
+ * logdet.h -- C ABI of liblogdet, an MI355X (gfx950) implementation of the
+ * rational-function log-determinant estimator of Colthurst, Vasudevan,
+ * Lottes and Patton, "Fast Approximate Determinants Using Rational
+ * Functions" (arXiv 2405.03474).
+ *
+ *   log det M = log det P + tr log(M P^-1)
+ *             ~ log det P + (1/s) sum_i z_i^T ( b I + sum_j c_j (M P^-1 + a_j I)^-1 ) z_i
+ *
+ * (Section 2, Algorithm 1 output and the derivation below Table 1), for M a
+ * dense RBF or Matern-5/2 Gaussian-process covariance matrix plus noise
+ * (Section 3), r_k = b + sum_j c_j/(x + a_j) the partial-fraction form of the
+ * order-k approximant of eq. 1 (Table 1), P a randomized truncated-SVD
+ * preconditioner (Section 2; Appendix), z_i Rademacher probes.
+ *
+ * Conventions for every entry point:
+ *  - All matrices are row-major and contiguous.  Pointers named "device" must
+ *    point to memory on the context's device; the caller owns them and must
+ *    keep them alive until the work enqueued on the context stream finishes.
+ *  - Work is enqueued on the stream given to ld_ctx_create.  Entry points that
+ *    return host scalars (logdet_precond_build, logdet_estimate) synchronize
+ *    that stream before returning; the others are asynchronous.
+ *  - Errors are returned as ld_status; no exception crosses the ABI.  On an
+ *    error, ld_last_error() gives a message (thread-local, valid until the
+ *    next call on the same thread).  Argument checks happen before any work is
+ *    enqueued.
+ *  - The library allocates its own scratch device memory on first use
+ *    (hipMalloc), keeps it in the context and frees it in ld_ctx_destroy.
+ */
+#ifndef LOGDET_H
+#define LOGDET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LD_OK = 0,
+  LD_EINVAL = -1,   /* invalid argument (sizes, k, kernel kind, null pointer, ...) */
+  LD_ENOTSPD = -2,  /* a matrix that must be positive definite is not (Cholesky
+                       breakdown in the preconditioner, or a non-positive CG
+                       curvature / residual norm in the solver) */
+  LD_ENOCONV = -3,  /* the solver hit max_iters; the result is still filled */
+  LD_EHIP = -4,     /* a HIP runtime call failed */
+  LD_ENOMEM = -5    /* device or pinned-host allocation failed */
+} ld_status;
+
+typedef enum { LD_RBF = 0, LD_MATERN52 = 1 } ld_kernel;
+
+/* Arithmetic of the kernel-matrix products and of the solver vectors.
+ * Scalar recurrences, reductions, the preconditioner's small dense algebra
+ * and log det P are FP64 in every mode. */
+typedef enum { LD_F64 = 0, LD_F32 = 1 } ld_precision;
+
+/* The matrix M = K(X, X) + noise * I (Section 3 kernels; formulas are the
+ * textbook ones: RBF k(r) = variance * exp(-r^2 / (2 l^2)); Matern-5/2
+ * k(r) = variance * (1 + sqrt5 r/l + 5 r^2/(3 l^2)) exp(-sqrt5 r/l)). */
+typedef struct {
+  const double* X;        /* device, n x d points (FP64) */
+  int64_t n;              /* number of points, >= 1 */
+  int32_t d;              /* dimension, 1..16 */
+  int32_t kind;           /* ld_kernel */
+  double lengthscale;     /* > 0 */
+  double variance;        /* signal variance, > 0 */
+  double noise;           /* noise variance added to the diagonal, >= 0 */
+  int32_t precision;      /* ld_precision */
+  const void* M_stored;   /* device n x n matrix M (FP64 for LD_F64, FP32 for
+                             LD_F32, noise included), or NULL to generate
+                             kernel entries on the fly from X */
+} ld_operator;
+
+typedef struct ld_ctx ld_ctx;         /* device, stream, cached scratch memory */
+typedef struct ld_precond ld_precond; /* library-owned preconditioner factors */
+
+typedef struct {
+  double logdet;          /* the estimate of log det M */
+  double logdet_P;        /* log det P */
+  double trace_term;      /* (1/s) sum_i t_i, the estimate of tr r_k(M P^-1) */
+  double std_err;         /* sample std of t_i / sqrt(s) (NaN for s = 1) */
+  double rel_resid;       /* max over probes of ||r||_{P^-1} / ||z||_{P^-1} of
+                             the smallest-shift system at exit */
+  double seconds_solve;   /* wall time of the solve and reduction */
+  int32_t iterations;     /* solver iterations run */
+  int32_t converged_cols; /* probes that met the tolerance */
+  int32_t k;              /* order of r_k */
+  int32_t num_probes;     /* s */
+} ld_result;
+
+/* Create a context on HIP device `device` that enqueues on `stream` (a
+ * hipStream_t, or NULL for the null stream).  *out receives the context. */
+ld_status ld_ctx_create(int device, void* stream, ld_ctx** out);
+void ld_ctx_destroy(ld_ctx* ctx);
+const char* ld_last_error(void);
+
+/* Instrumentation.  With timing on, the solver of logdet_estimate records
+ * HIP events on the context stream around every launch of its kernel-matrix
+ * product kernel; ld_ctx_read_timing returns the summed elapsed time (ms),
+ * the number of launches, and their algorithmic flops (2 n^2 s each) and
+ * bytes (the stored matrix once, when stored, plus V read and Y written).
+ * ld_ctx_set_timing resets the totals.  Any output pointer may be NULL. */
+ld_status ld_ctx_set_timing(ld_ctx* ctx, int32_t on);
+ld_status ld_ctx_read_timing(ld_ctx* ctx, double* ms, int64_t* calls, double* flops, double* bytes);
+
+/* Partial-fraction form of r_k (Section 2, Table 1), k in {1, 3, 5}:
+ * r_k(x) = b + sum_{j<k} c[j] / (x + a[j]), a ascending, c < 0.  Host only;
+ * a and c must hold k doubles.  The constants are derived in the library
+ * from the closed-form roots of the denominators of eq. 1. */
+ld_status ld_rational_coeffs(int32_t k, double* b, double* a, double* c);
+
+/* Probe block of Algorithm 1 step 1: Z (device, n x s, FP64 if precision is
+ * LD_F64 else FP32) with Rademacher entries from the counter stream
+ * (SplitMix64 finalizer used as a hash; stream 2; index row * s + col). */
+ld_status ld_fill_probes(ld_ctx* ctx, uint64_t seed, int64_t n, int64_t s,
+                         int32_t precision, void* Z);
+
+/* Standard normal block (device FP64, rows x cols) from the same counter
+ * stream family (Box-Muller on two uniforms): the Gaussian test matrix of the
+ * randomized range finder uses stream 1. */
+ld_status ld_fill_gaussian(ld_ctx* ctx, uint64_t seed, int32_t stream, int64_t rows,
+                           int64_t cols, double* out);
+
+/* Y = M V (Section 2: the kernel-matrix times probe-block product that
+ * dominates each solver step).  V, Y: device n x s in the operator's
+ * precision; Y must not alias V.  Asynchronous. */
+ld_status kernel_matmat(ld_ctx* ctx, const ld_operator* op, const void* V, int64_t s, void* Y);
+
+/* Write M = K + noise I (device n x n, FP64 for LD_F64, FP32 for LD_F32) so
+ * that it can be passed back as op->M_stored.  op->M_stored is ignored.
+ * Asynchronous. */
+ld_status kernel_materialize(ld_ctx* ctx, const ld_operator* op, void* M_out);
+
+/* Build the randomized truncated-SVD preconditioner P = D + U diag(lam) U^T
+ * (Section 2, after Halko et al. Alg. 4.1 / 5.3; Appendix): Gaussian test
+ * matrix with rank + oversample columns (counter stream 1, `seed`),
+ * power_iters subspace iterations, Rayleigh-Ritz on the sketch, top `rank`
+ * eigenpairs, D = diag(M) - rowsum(U^2 lam) floored at the noise variance
+ * (or 1e-12 * variance when noise is 0).  Requires 1 <= rank and
+ * rank + oversample <= n, oversample >= 0, 0 <= power_iters <= 16.
+ * Synchronizes.  *out must be released with ld_precond_free. */
+ld_status logdet_precond_build(ld_ctx* ctx, const ld_operator* op, int32_t rank,
+                               int32_t oversample, int32_t power_iters, uint64_t seed,
+                               ld_precond** out);
+
+/* Size and log det P of a preconditioner (host outputs; any may be NULL). */
+ld_status ld_precond_info(const ld_precond* P, int64_t* n, int32_t* rank, double* logdet_P);
+
+/* Copy the factors to caller device buffers (FP64): U n x rank, lambda rank
+ * (descending), D n.  Any pointer may be NULL.  Asynchronous on ctx. */
+ld_status ld_precond_export(ld_ctx* ctx, const ld_precond* P, double* U, double* lambda, double* D);
+
+/* OUT = P^-1 R by the Woodbury identity (Section 2: a cheap P^-1 v):
+ * P^-1 = D^-1 - F F^T with F = D^-1 U L^-T, L L^T = diag(1/lam) + U^T D^-1 U.
+ * R, OUT: device n x s, FP64 if precision is LD_F64 else FP32; OUT must not
+ * alias R.  Asynchronous. */
+ld_status ld_precond_apply_inverse(ld_ctx* ctx, const ld_precond* P, const void* R, int64_t s,
+                                   int32_t precision, void* OUT);
+
+void ld_precond_free(ld_precond* P);
+
+/* The estimator (Algorithm 1 output with its shifted solves run to a
+ * tolerance): s Rademacher probes from `probe_seed`, one multi-shift
+ * preconditioned CG per probe in the P^-1 inner product seeded with the
+ * smallest shift a_1, shifted systems by the scalar recurrences of
+ * Jegerlehner's multi-shift CG (Section 2, multi-shift solver paragraph),
+ * stopping when ||r||_{P^-1} <= tol * ||z||_{P^-1} for the seed system of every
+ * probe, then the Hutchinson mean (Section 1) in FP64.
+ *   P          preconditioner for this operator (same n), or NULL to build
+ *              one with rank min(100, n/10), oversample 10, 2 power
+ *              iterations, seed probe_seed + 1
+ *   k          1, 3 or 5
+ *   num_probes s >= 1
+ *   tol        > 0 (1e-12 typical for LD_F64, 1e-6 for LD_F32)
+ *   max_iters  >= 1
+ *   out        host, filled on LD_OK and on LD_ENOCONV
+ *   per_probe  host array of s doubles receiving t_i, or NULL
+ * Synchronizes. */
+ld_status logdet_estimate(ld_ctx* ctx, const ld_operator* op, const ld_precond* P, int32_t k,
+                          int32_t num_probes, uint64_t probe_seed, double tol, int32_t max_iters,
+                          ld_result* out, double* per_probe);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LOGDET_H */

@@ -1,0 +1,11 @@
+"""MI355X (gfx950) implementation of the rational-function log-determinant
+estimator of Colthurst et al. (arXiv 2405.03474).
+
+The computation lives in liblogdet.so (HIP kernels behind the C ABI of
+include/logdet.h); this package is its Python binding.
+"""
+from ._binding import (  # noqa: F401
+    EXPORTED, LD_F32, LD_F64, LD_MATERN52, LD_RBF, Context, GPOperator, LogdetError, Precond,
+    fill_gaussian, fill_probes, kernel_materialize, kernel_matmat, load, logdet_estimate,
+    rational_coeffs,
+)

@@ -1,0 +1,296 @@
+"""ctypes binding of liblogdet (include/logdet.h).
+
+Argument marshalling only: torch supplies device memory and the stream, the
+library does every step of the computation.  Importing this module loads the
+shared library and raises if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblogdet.so")
+
+LD_OK, LD_EINVAL, LD_ENOTSPD, LD_ENOCONV, LD_EHIP, LD_ENOMEM = 0, -1, -2, -3, -4, -5
+LD_RBF, LD_MATERN52 = 0, 1
+LD_F64, LD_F32 = 0, 1
+
+STATUS_NAMES = {0: "LD_OK", -1: "LD_EINVAL", -2: "LD_ENOTSPD", -3: "LD_ENOCONV", -4: "LD_EHIP",
+                -5: "LD_ENOMEM"}
+
+EXPORTED = (
+    "ld_ctx_create", "ld_ctx_destroy", "ld_last_error", "ld_ctx_set_timing", "ld_ctx_read_timing", "ld_rational_coeffs", "ld_fill_probes",
+    "ld_fill_gaussian", "kernel_matmat", "kernel_materialize", "logdet_precond_build",
+    "ld_precond_info", "ld_precond_export", "ld_precond_apply_inverse", "ld_precond_free",
+    "logdet_estimate",
+)
+
+
+class LogdetError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Operator(ctypes.Structure):
+    _fields_ = [
+        ("X", ctypes.c_void_p), ("n", ctypes.c_int64), ("d", ctypes.c_int32),
+        ("kind", ctypes.c_int32), ("lengthscale", ctypes.c_double), ("variance", ctypes.c_double),
+        ("noise", ctypes.c_double), ("precision", ctypes.c_int32), ("M_stored", ctypes.c_void_p),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("logdet", ctypes.c_double), ("logdet_P", ctypes.c_double), ("trace_term", ctypes.c_double),
+        ("std_err", ctypes.c_double), ("rel_resid", ctypes.c_double),
+        ("seconds_solve", ctypes.c_double), ("iterations", ctypes.c_int32),
+        ("converged_cols", ctypes.c_int32), ("k", ctypes.c_int32), ("num_probes", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load liblogdet.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    pd = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "ld_ctx_create": (i32, [ctypes.c_int, vp, ctypes.POINTER(vp)]),
+        "ld_ctx_destroy": (None, [vp]),
+        "ld_last_error": (ctypes.c_char_p, []),
+        "ld_ctx_set_timing": (i32, [vp, i32]),
+        "ld_ctx_read_timing": (i32, [vp, pd, ctypes.POINTER(i64), pd, pd]),
+        "ld_rational_coeffs": (i32, [i32, pd, pd, pd]),
+        "ld_fill_probes": (i32, [vp, u64, i64, i64, i32, vp]),
+        "ld_fill_gaussian": (i32, [vp, u64, i32, i64, i64, vp]),
+        "kernel_matmat": (i32, [vp, ctypes.POINTER(Operator), vp, i64, vp]),
+        "kernel_materialize": (i32, [vp, ctypes.POINTER(Operator), vp]),
+        "logdet_precond_build": (i32, [vp, ctypes.POINTER(Operator), i32, i32, i32, u64,
+                                       ctypes.POINTER(vp)]),
+        "ld_precond_info": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), pd]),
+        "ld_precond_export": (i32, [vp, vp, vp, vp, vp]),
+        "ld_precond_apply_inverse": (i32, [vp, vp, vp, i64, i32, vp]),
+        "ld_precond_free": (None, [vp]),
+        "logdet_estimate": (i32, [vp, ctypes.POINTER(Operator), vp, i32, i32, u64, dbl, i32,
+                                  ctypes.POINTER(Result), pd]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, allow=()):
+    if status != LD_OK and status not in allow:
+        raise LogdetError(status, load().ld_last_error().decode())
+    return status
+
+
+def rational_coeffs(k: int):
+    """(b, a, c) of r_k from the library (host-only query)."""
+    lib = load()
+    b = ctypes.c_double()
+    a = (ctypes.c_double * k)()
+    c = (ctypes.c_double * k)()
+    _check(lib.ld_rational_coeffs(k, ctypes.byref(b), a, c))
+    return b.value, np.array(a[:]), np.array(c[:])
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Context:
+    """A library context on one device, enqueueing on a torch stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        self.device = device
+        self.torch_stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = ctypes.c_void_p()
+        _check(load().ld_ctx_create(device, ctypes.c_void_p(self.torch_stream.cuda_stream),
+                                    ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            load().ld_ctx_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def synchronize(self):
+        self.torch_stream.synchronize()
+
+    def set_timing(self, on: bool = True):
+        _check(load().ld_ctx_set_timing(self.handle, 1 if on else 0))
+
+    def read_timing(self):
+        """(total ms, launches, algorithmic flops, algorithmic bytes) of the
+        solver's kernel-matrix product launches since set_timing."""
+        ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        calls = ctypes.c_int64()
+        _check(load().ld_ctx_read_timing(self.handle, ctypes.byref(ms), ctypes.byref(calls),
+                                         ctypes.byref(fl), ctypes.byref(by)))
+        return ms.value, calls.value, fl.value, by.value
+
+
+def _dtype(precision: int):
+    torch = _torch()
+    return torch.float64 if precision == LD_F64 else torch.float32
+
+
+@dataclass
+class GPOperator:
+    """M = K(X, X) + noise I (caller-owned device tensors)."""
+    X: object                 # torch cuda float64 (n, d)
+    kind: int
+    lengthscale: float
+    variance: float
+    noise: float
+    precision: int = LD_F64
+    M: object = None          # optional stored matrix (n, n) in the operator's dtype
+    _keep: list = field(default_factory=list, repr=False)
+
+    @property
+    def n(self):
+        return int(self.X.shape[0])
+
+    @property
+    def d(self):
+        return int(self.X.shape[1])
+
+    def c_struct(self) -> Operator:
+        torch = _torch()
+        assert self.X.is_cuda and self.X.dtype == torch.float64 and self.X.is_contiguous()
+        if self.M is not None:
+            assert self.M.is_cuda and self.M.dtype == _dtype(self.precision) and self.M.is_contiguous()
+            assert tuple(self.M.shape) == (self.n, self.n)
+        return Operator(X=self.X.data_ptr(), n=self.n, d=self.d, kind=self.kind,
+                        lengthscale=self.lengthscale, variance=self.variance, noise=self.noise,
+                        precision=self.precision,
+                        M_stored=self.M.data_ptr() if self.M is not None else None)
+
+
+def fill_probes(ctx: Context, seed: int, n: int, s: int, precision: int = LD_F64):
+    torch = _torch()
+    Z = torch.empty((n, s), dtype=_dtype(precision), device=f"cuda:{ctx.device}")
+    _check(load().ld_fill_probes(ctx.handle, seed, n, s, precision, ctypes.c_void_p(Z.data_ptr())))
+    return Z
+
+
+def fill_gaussian(ctx: Context, seed: int, stream: int, rows: int, cols: int):
+    torch = _torch()
+    G = torch.empty((rows, cols), dtype=torch.float64, device=f"cuda:{ctx.device}")
+    _check(load().ld_fill_gaussian(ctx.handle, seed, stream, rows, cols, ctypes.c_void_p(G.data_ptr())))
+    return G
+
+
+def kernel_matmat(ctx: Context, op: GPOperator, V):
+    torch = _torch()
+    assert V.is_cuda and V.dtype == _dtype(op.precision) and V.is_contiguous() and V.shape[0] == op.n
+    V2 = V if V.dim() == 2 else V.reshape(op.n, 1)
+    Y = torch.empty_like(V2)
+    cop = op.c_struct()
+    _check(load().kernel_matmat(ctx.handle, ctypes.byref(cop), ctypes.c_void_p(V2.data_ptr()),
+                                V2.shape[1], ctypes.c_void_p(Y.data_ptr())))
+    return Y.reshape(V.shape)
+
+
+def kernel_materialize(ctx: Context, op: GPOperator, out=None):
+    torch = _torch()
+    M = out if out is not None else torch.empty((op.n, op.n), dtype=_dtype(op.precision),
+                                                device=f"cuda:{ctx.device}")
+    assert M.is_cuda and M.dtype == _dtype(op.precision) and M.is_contiguous()
+    assert tuple(M.shape) == (op.n, op.n)
+    cop = op.c_struct()
+    _check(load().kernel_materialize(ctx.handle, ctypes.byref(cop), ctypes.c_void_p(M.data_ptr())))
+    return M
+
+
+class Precond:
+    """Library-owned randomized truncated-SVD preconditioner."""
+
+    def __init__(self, ctx: Context, op: GPOperator, rank: int, oversample: int = 10,
+                 power_iters: int = 2, seed: int = 0):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        cop = op.c_struct()
+        _check(load().logdet_precond_build(ctx.handle, ctypes.byref(cop), rank, oversample,
+                                           power_iters, seed, ctypes.byref(h)))
+        self.handle = h
+        n = ctypes.c_int64()
+        r = ctypes.c_int32()
+        ld = ctypes.c_double()
+        _check(load().ld_precond_info(h, ctypes.byref(n), ctypes.byref(r), ctypes.byref(ld)))
+        self.n, self.rank, self.logdet = n.value, r.value, ld.value
+
+    def export(self):
+        torch = _torch()
+        dev = f"cuda:{self.ctx.device}"
+        U = torch.empty((self.n, self.rank), dtype=torch.float64, device=dev)
+        lam = torch.empty((self.rank,), dtype=torch.float64, device=dev)
+        D = torch.empty((self.n,), dtype=torch.float64, device=dev)
+        _check(load().ld_precond_export(self.ctx.handle, self.handle, ctypes.c_void_p(U.data_ptr()),
+                                        ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(D.data_ptr())))
+        self.ctx.synchronize()
+        return U, lam, D
+
+    def apply_inverse(self, R, precision: int = LD_F64):
+        torch = _torch()
+        R2 = R if R.dim() == 2 else R.reshape(self.n, 1)
+        assert R2.is_cuda and R2.dtype == _dtype(precision) and R2.is_contiguous()
+        out = torch.empty_like(R2)
+        _check(load().ld_precond_apply_inverse(self.ctx.handle, self.handle,
+                                               ctypes.c_void_p(R2.data_ptr()), R2.shape[1], precision,
+                                               ctypes.c_void_p(out.data_ptr())))
+        return out.reshape(R.shape)
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            load().ld_precond_free(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def logdet_estimate(ctx: Context, op: GPOperator, P: Precond | None, k: int, num_probes: int,
+                    probe_seed: int, tol: float, max_iters: int = 5000, allow_noconv: bool = False):
+    """Returns (result dict, per-probe values as a numpy array)."""
+    res = Result()
+    per = np.zeros(num_probes, dtype=np.float64)
+    cop = op.c_struct()
+    st = load().logdet_estimate(ctx.handle, ctypes.byref(cop), P.handle if P is not None else None, k,
+                                num_probes, probe_seed, tol, max_iters, ctypes.byref(res),
+                                per.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    _check(st, allow=(LD_ENOCONV,) if allow_noconv else ())
+    out = res.as_dict()
+    out["status"] = STATUS_NAMES.get(st, st)
+    return out, per

@@ -1,0 +1,697 @@
+// C ABI of liblogdet: argument checks, scratch management and the host-side
+// orchestration of the estimator (Section 2: Algorithm 1 and the randomized
+// truncated-SVD preconditioner).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ld_common.hpp"
+
+namespace ld {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const std::string& msg) { g_err = msg; }
+ld_status fail(ld_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+// ------------------------------------------------------------------ arena --
+ld_status Arena::reserve(size_t bytes) {
+  if (bytes <= cap) return LD_OK;
+  // the old block may still be read by enqueued work
+  if (base) (void)hipDeviceSynchronize();
+  release();
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LD_ENOMEM, "device scratch allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  base = (char*)p;
+  cap = bytes;
+  top = 0;
+  return LD_OK;
+}
+
+void* Arena::take(size_t bytes) {
+  const size_t off = (top + 255) & ~(size_t)255;
+  if (off + bytes > cap) return nullptr;
+  top = off + bytes;
+  return base + off;
+}
+
+void Arena::release() {
+  if (base) (void)hipFree(base);
+  base = nullptr;
+  cap = 0;
+  top = 0;
+}
+
+ld_status ensure_pinned(ld_ctx* ctx, size_t count) {
+  if (count <= ctx->pinned_count) return LD_OK;
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  ctx->pinned = nullptr;
+  ctx->pinned_count = 0;
+  void* p = nullptr;
+  if (hipHostMalloc(&p, count * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LD_ENOMEM, "pinned host allocation failed");
+  }
+  ctx->pinned = (double*)p;
+  ctx->pinned_count = count;
+  return LD_OK;
+}
+
+ld_status timing_pair(ld_ctx* ctx, hipEvent_t* start, hipEvent_t* stop, double flops, double bytes) {
+  if (ctx->ev_used + 2 > ctx->ev.size()) {
+    for (int q = 0; q < 2; ++q) {
+      hipEvent_t e;
+      LD_HIP(hipEventCreate(&e));
+      ctx->ev.push_back(e);
+    }
+  }
+  *start = ctx->ev[ctx->ev_used];
+  *stop = ctx->ev[ctx->ev_used + 1];
+  ctx->ev_used += 2;
+  ctx->pending_flops.push_back(flops);
+  ctx->pending_bytes.push_back(bytes);
+  return LD_OK;
+}
+
+void timing_collect(ld_ctx* ctx) {
+  for (size_t i = 0; i + 1 < ctx->ev_used; i += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]) == hipSuccess) {
+      ctx->mm_ms += ms;
+      ctx->mm_calls += 1;
+      ctx->mm_flops += ctx->pending_flops[i / 2];
+      ctx->mm_bytes += ctx->pending_bytes[i / 2];
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+  ctx->ev_used = 0;
+  ctx->pending_flops.clear();
+  ctx->pending_bytes.clear();
+}
+
+ld_status check_operator(const ld_operator* op) {
+  if (!op) return fail(LD_EINVAL, "operator is NULL");
+  if (!op->X) return fail(LD_EINVAL, "operator X is NULL");
+  if (op->n < 1) return fail(LD_EINVAL, "n must be >= 1");
+  if (op->d < 1 || op->d > 16) return fail(LD_EINVAL, "d must be in 1..16");
+  if (op->kind != LD_RBF && op->kind != LD_MATERN52) return fail(LD_EINVAL, "unknown kernel kind");
+  if (!(op->lengthscale > 0.0) || !std::isfinite(op->lengthscale))
+    return fail(LD_EINVAL, "lengthscale must be finite and > 0");
+  if (!(op->variance > 0.0) || !std::isfinite(op->variance))
+    return fail(LD_EINVAL, "variance must be finite and > 0");
+  if (!(op->noise >= 0.0) || !std::isfinite(op->noise))
+    return fail(LD_EINVAL, "noise must be finite and >= 0");
+  if (op->precision != LD_F64 && op->precision != LD_F32)
+    return fail(LD_EINVAL, "precision must be LD_F64 or LD_F32");
+  return LD_OK;
+}
+
+namespace {
+
+bool is_f64(const ld_operator* op) { return op->precision == LD_F64; }
+
+// Points in the arithmetic of the path: FP64 as given, or an FP32 copy.
+ld_status path_points(ld_ctx* ctx, const ld_operator* op, const void** X) {
+  if (is_f64(op) || op->M_stored) {
+    *X = op->X;
+    return LD_OK;
+  }
+  float* x32 = (float*)ctx->arena.take((size_t)op->n * op->d * sizeof(float));
+  if (!x32) return fail(LD_ENOMEM, "scratch arena too small for FP32 points");
+  launch_convert_f64_to_f32(ctx->stream, op->X, x32, op->n * op->d);
+  *X = x32;
+  return LD_OK;
+}
+
+MatmatArgs base_args(const ld_operator* op, const void* X) {
+  MatmatArgs a;
+  a.n = op->n;
+  a.d = op->d;
+  a.kp = make_kparams(*op);
+  a.A = op->M_stored;
+  a.X = X;
+  return a;
+}
+
+// ---------------------------------------------------- rational constants --
+// r_k = pref * N_k / D_k (eq. 1).  D_k(z) = sum_i C(2k, 2i) z^i, whose roots
+// are -tan^2(pi (2m+1) / (4k)); the residue at a simple root alpha is
+// pref * N_k(alpha) / D_k'(alpha); b is the ratio of leading coefficients.
+struct Rational {
+  double b;
+  double a[5];
+  double c[5];
+};
+
+bool rational_for(int k, Rational* out) {
+  static const long double n1[] = {1, -1};
+  static const long double n3[] = {7, 27, -27, -7};
+  static const long double n5[] = {43, 825, 1150, -1150, -825, -43};
+  const long double* num;
+  long double pref;
+  switch (k) {
+    case 1: num = n1; pref = 2.0L; break;
+    case 3: num = n3; pref = 2.0L / 3.0L; break;
+    case 5: num = n5; pref = 2.0L / 15.0L; break;
+    default: return false;
+  }
+  // denominator coefficients, highest power first: C(2k, 2(k - i))
+  long double den[6];
+  for (int i = 0; i <= k; ++i) {
+    const int e = 2 * (k - i);
+    long double cb = 1.0L;
+    for (int t = 1; t <= e; ++t) cb = cb * (long double)(2 * k - e + t) / (long double)t;
+    den[i] = cb;
+  }
+  const long double pi = 3.141592653589793238462643383279502884L;
+  out->b = (double)(pref * num[0] / den[0]);
+  for (int m = 0; m < k; ++m) {
+    const long double tq = tanl(pi * (long double)(2 * m + 1) / (long double)(4 * k));
+    const long double alpha = -tq * tq;
+    long double nv = 0.0L, dv = 0.0L;
+    for (int i = 0; i <= k; ++i) nv = nv * alpha + num[i];
+    for (int i = 0; i < k; ++i) dv = dv * alpha + den[i] * (long double)(k - i);
+    out->a[m] = (double)(-alpha);
+    out->c[m] = (double)(pref * nv / dv);
+  }
+  return true;
+}
+
+ld_status check_ctx(ld_ctx* ctx) {
+  if (!ctx) return fail(LD_EINVAL, "context is NULL");
+  LD_HIP(hipSetDevice(ctx->device));
+  return LD_OK;
+}
+
+__global__ void k_d_and_inv(const double* __restrict__ U, const double* __restrict__ lam, int64_t n,
+                            int rank, const void* __restrict__ Mst, int mprec, double diag_const,
+                            double floor_v, double* __restrict__ D, double* __restrict__ Dinv) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    double dm = diag_const;
+    if (Mst) dm = mprec == LD_F64 ? ((const double*)Mst)[i * n + i] : (double)((const float*)Mst)[i * n + i];
+    double low = 0.0;
+    for (int j = 0; j < rank; ++j) {
+      const double u = U[i * rank + j];
+      low = fma(lam[j] * u, u, low);
+    }
+    double dv = dm - low;
+    if (!(dv >= floor_v)) dv = floor_v;
+    D[i] = dv;
+    Dinv[i] = 1.0 / dv;
+  }
+}
+
+__global__ void k_add_diag_inv(double* __restrict__ C, const double* __restrict__ lam, int rank) {
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < rank; j += gridDim.x * 256)
+    C[(int64_t)j * rank + j] += 1.0 / lam[j];
+}
+
+// shift the Gram diagonal by c * trace(G) (shifted CholeskyQR first pass)
+__global__ void k_shift_diag(double* __restrict__ G, int m, double c) {
+  __shared__ double red[256];
+  double t = 0.0;
+  for (int j = threadIdx.x; j < m; j += 256) t += G[(int64_t)j * m + j];
+  red[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double sh = c * red[0];
+  for (int j = threadIdx.x; j < m; j += 256) G[(int64_t)j * m + j] += sh;
+}
+
+// out[0] = sum log D, out[1] = sum log lam, out[2] = 2 sum log diag(R)
+__global__ void k_logdet_parts(const double* __restrict__ D, int64_t n, const double* __restrict__ lam,
+                               const double* __restrict__ R, int rank, double* __restrict__ out) {
+  __shared__ double red[3][256];
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) a += log(D[i]);
+  for (int j = threadIdx.x; j < rank; j += 256) {
+    b += log(lam[j]);
+    c += 2.0 * log(R[(int64_t)j * rank + j]);
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  red[2][threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 3; ++q) out[q] = red[q][0];
+}
+
+int grid1(int64_t count) {
+  int64_t b = (count + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
+}
+
+// Orthonormal basis of range(Y) by shifted CholeskyQR3 (one shifted pass,
+// then two plain passes).  Y (n x m) is consumed; the basis ends in *Q, which
+// is one of the two buffers Y / W.
+ld_status orthonormalize(ld_ctx* ctx, double* Y, double* W, int64_t n, int m, double* G, double* Rinv,
+                         int* ok_dev, double** Q) {
+  hipStream_t st = ctx->stream;
+  double* src = Y;
+  double* dst = W;
+  const double shift_c = 11.0 * ((double)n * m + (double)m * (m + 1)) * 0x1.0p-53;
+  for (int pass = 0; pass < 3; ++pass) {
+    const size_t mark = ctx->arena.top;
+    LD_TRY(gram64(ctx, src, src, nullptr, n, m, G));
+    ctx->arena.top = mark;  // partials are consumed by the reduction already enqueued
+    if (pass == 0) hipLaunchKernelGGL(k_shift_diag, dim3(1), dim3(256), 0, st, G, m, shift_c);
+    launch_cholesky_upper(st, G, m, ok_dev);
+    launch_tri_inv_upper(st, G, m, Rinv);
+    launch_gemm64(st, src, Rinv, m, nullptr, n, m, m, dst);
+    std::swap(src, dst);
+  }
+  LD_HIP(hipGetLastError());
+  LD_TRY(ensure_pinned(ctx, 1));
+  LD_HIP(hipMemcpyAsync(ctx->pinned, ok_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+  LD_HIP(hipStreamSynchronize(st));
+  if (*(int*)ctx->pinned != 1)
+    return fail(LD_ENOTSPD, "CholeskyQR breakdown: sketch Gram matrix not positive definite");
+  *Q = src;
+  return LD_OK;
+}
+
+// Y = M V for an n x m FP64 block, through the operator's arithmetic.
+ld_status apply_M64(ld_ctx* ctx, const ld_operator* op, const void* Xp, const double* V, double* Y,
+                    int m, float* t1, float* t2) {
+  MatmatArgs a = base_args(op, Xp);
+  a.s = m;
+  const size_t mark = ctx->arena.top;
+  if (is_f64(op)) {
+    a.V = V;
+    a.Y = Y;
+    LD_TRY(matmat(ctx, true, a));
+  } else {
+    launch_convert_f64_to_f32(ctx->stream, V, t1, op->n * (int64_t)m);
+    a.V = t1;
+    a.Y = t2;
+    LD_TRY(matmat(ctx, false, a));
+    launch_convert_f32_to_f64(ctx->stream, t2, Y, op->n * (int64_t)m);
+  }
+  ctx->arena.top = mark;
+  return LD_OK;
+}
+
+ld_status build_precond(ld_ctx* ctx, const ld_operator* op, int rank, int oversample, int power_iters,
+                        uint64_t seed, ld_precond** out) {
+  const int64_t n = op->n;
+  const int m = rank + oversample;
+  const bool f64 = is_f64(op);
+  const size_t nm = (size_t)n * m;
+  const int me = m + (m & 1);
+  // scratch bound
+  size_t need = 0;
+  need += (size_t)n * op->d * 4 + 512;                     // FP32 points
+  need += 2 * nm * 8 + 1024;                               // Q, Y (FP64)
+  if (!f64) need += 2 * nm * 4 + 1024;                     // FP32 copies for matmat
+  need += 4 * (size_t)m * m * 8 + 2048;                    // G, Rinv, evecs, B
+  need += (size_t)m * 8 + 512;                             // evals
+  need += 4 * (size_t)me * me * 8 + 16 + 2048;             // Jacobi
+  size_t gram_b = std::max((size_t)16 << 20, (size_t)2 * m * m * 8) + 512;
+  need += std::max(gram_b, matmat_scratch_bytes(ctx, f64, n, m)) + 1024;
+  need += 4096;
+  ctx->arena.reset();
+  LD_TRY(ctx->arena.reserve(need));
+
+  const void* Xp = nullptr;
+  LD_TRY(path_points(ctx, op, &Xp));
+  double* Qb = (double*)ctx->arena.take(nm * 8);
+  double* Yb = (double*)ctx->arena.take(nm * 8);
+  float* t1 = f64 ? nullptr : (float*)ctx->arena.take(nm * 4);
+  float* t2 = f64 ? nullptr : (float*)ctx->arena.take(nm * 4);
+  double* G = (double*)ctx->arena.take((size_t)m * m * 8);
+  double* Rinv = (double*)ctx->arena.take((size_t)m * m * 8);
+  double* evecs = (double*)ctx->arena.take((size_t)m * m * 8);
+  double* evals = (double*)ctx->arena.take((size_t)m * 8);
+  int* okd = (int*)ctx->arena.take(64);
+  if (!Qb || !Yb || (!f64 && (!t1 || !t2)) || !G || !Rinv || !evecs || !evals || !okd)
+    return fail(LD_ENOMEM, "precond: scratch arena too small");
+  hipStream_t st = ctx->stream;
+
+  // 1-2. Gaussian test matrix and range finder
+  launch_fill_gaussian(st, stream_key(seed, kStreamOmega), n, m, Qb);
+  LD_TRY(apply_M64(ctx, op, Xp, Qb, Yb, m, t1, t2));
+  double* Q = nullptr;
+  LD_TRY(orthonormalize(ctx, Yb, Qb, n, m, G, Rinv, okd, &Q));
+  // 3. subspace iterations
+  for (int it = 0; it < power_iters; ++it) {
+    double* other = (Q == Qb) ? Yb : Qb;
+    LD_TRY(apply_M64(ctx, op, Xp, Q, other, m, t1, t2));
+    LD_TRY(orthonormalize(ctx, other, Q, n, m, G, Rinv, okd, &Q));
+  }
+  // 4. B = Q^T M Q and its eigenpairs
+  double* MQ = (Q == Qb) ? Yb : Qb;
+  LD_TRY(apply_M64(ctx, op, Xp, Q, MQ, m, t1, t2));
+  {
+    const size_t mark = ctx->arena.top;
+    LD_TRY(gram64(ctx, Q, MQ, nullptr, n, m, G));
+    ctx->arena.top = mark;
+  }
+  {
+    const size_t mark = ctx->arena.top;
+    LD_TRY(jacobi_eigh(ctx, G, m, evals, evecs));
+    ctx->arena.top = mark;
+  }
+  LD_TRY(ensure_pinned(ctx, (size_t)m + 8));
+  LD_HIP(hipMemcpyAsync(ctx->pinned, evals, (size_t)m * 8, hipMemcpyDeviceToHost, st));
+  LD_HIP(hipStreamSynchronize(st));
+  for (int j = 0; j < rank; ++j)
+    if (!(ctx->pinned[j] > 0.0) || !std::isfinite(ctx->pinned[j]))
+      return fail(LD_ENOTSPD, "projected matrix has a non-positive eigenvalue among the kept ones");
+
+  // 5. factors: library-owned block
+  ld_precond* P = new ld_precond();
+  P->n = n;
+  P->rank = rank;
+  P->device = ctx->device;
+  const size_t nl = (size_t)n * rank;
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t bytes = al(nl * 8) * 2 + al((size_t)rank * 8) + al((size_t)n * 8) * 2 + al(nl * 4) +
+                       al((size_t)n * 4);
+  void* blk = nullptr;
+  if (hipMalloc(&blk, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete P;
+    return fail(LD_ENOMEM, "preconditioner allocation failed");
+  }
+  P->block = blk;
+  char* c = (char*)blk;
+  P->U = (double*)c; c += al(nl * 8);
+  P->F64 = (double*)c; c += al(nl * 8);
+  P->lam = (double*)c; c += al((size_t)rank * 8);
+  P->D = (double*)c; c += al((size_t)n * 8);
+  P->Dinv64 = (double*)c; c += al((size_t)n * 8);
+  P->F32 = (float*)c; c += al(nl * 4);
+  P->Dinv32 = (float*)c;
+
+  auto bail = [&](ld_status s_) {
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(P->block);
+    delete P;
+    return s_;
+  };
+  // U = Q V_l, lam = top eigenvalues
+  launch_gemm64(st, Q, evecs, m, nullptr, n, m, rank, P->U);
+  if (hipMemcpyAsync(P->lam, evals, (size_t)rank * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return bail(fail(LD_EHIP, "copy of eigenvalues failed"));
+  // 6. D = diag(M) - rowsum(U^2 lam), floored
+  const double floor_v = op->noise > 0.0 ? op->noise : 1e-12 * op->variance;
+  hipLaunchKernelGGL(k_d_and_inv, dim3(grid1(n)), dim3(256), 0, st, P->U, P->lam, n, rank,
+                     op->M_stored, op->precision, op->variance + op->noise, floor_v, P->D, P->Dinv64);
+  // capacitance C = diag(1/lam) + U^T D^-1 U = R^T R
+  {
+    const size_t mark = ctx->arena.top;
+    ld_status s_ = gram64(ctx, P->U, P->U, P->Dinv64, n, rank, G);
+    ctx->arena.top = mark;
+    if (s_ != LD_OK) return bail(s_);
+  }
+  hipLaunchKernelGGL(k_add_diag_inv, dim3(grid1(rank)), dim3(256), 0, st, G, P->lam, rank);
+  launch_cholesky_upper(st, G, rank, okd);
+  double* parts = evals;  // reuse: 3 doubles
+  hipLaunchKernelGGL(k_logdet_parts, dim3(1), dim3(256), 0, st, P->D, n, P->lam, G, rank, parts);
+  // F = D^-1 U R^-1  (= D^-1 U L^-T with L = R^T)
+  launch_tri_inv_upper(st, G, rank, Rinv);
+  launch_gemm64(st, P->U, Rinv, rank, P->Dinv64, n, rank, rank, P->F64);
+  launch_convert_f64_to_f32(st, P->F64, P->F32, (int64_t)nl);
+  launch_convert_f64_to_f32(st, P->Dinv64, P->Dinv32, n);
+  if (hipGetLastError() != hipSuccess) return bail(fail(LD_EHIP, "kernel launch failed"));
+  if (hipMemcpyAsync(ctx->pinned, parts, 3 * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(ctx->pinned + 4, okd, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return bail(fail(LD_EHIP, "readback of log det P failed"));
+  if (*(int*)(ctx->pinned + 4) != 1)
+    return bail(fail(LD_ENOTSPD, "capacitance matrix Cholesky breakdown"));
+  P->logdet = ctx->pinned[0] + ctx->pinned[1] + ctx->pinned[2];
+  if (!std::isfinite(P->logdet)) return bail(fail(LD_ENOTSPD, "log det P is not finite"));
+  *out = P;
+  return LD_OK;
+}
+
+}  // namespace
+}  // namespace ld
+
+using namespace ld;
+
+extern "C" {
+
+const char* ld_last_error(void) { return ld::g_err.c_str(); }
+
+ld_status ld_ctx_create(int device, void* stream, ld_ctx** out) {
+  if (!out) return fail(LD_EINVAL, "out is NULL");
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+    (void)hipGetLastError();
+    return fail(LD_EHIP, "no HIP device available");
+  }
+  if (device < 0 || device >= count) return fail(LD_EINVAL, "device index out of range");
+  LD_HIP(hipSetDevice(device));
+  ld_ctx* c = new ld_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0)
+    c->num_cu = cu;
+  *out = c;
+  return LD_OK;
+}
+
+void ld_ctx_destroy(ld_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  ctx->arena.release();
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+}
+
+ld_status ld_ctx_set_timing(ld_ctx* ctx, int32_t on) {
+  if (!ctx) return fail(LD_EINVAL, "context is NULL");
+  ctx->timing = on != 0;
+  ctx->mm_ms = 0.0;
+  ctx->mm_calls = 0;
+  ctx->mm_flops = 0.0;
+  ctx->mm_bytes = 0.0;
+  return LD_OK;
+}
+
+ld_status ld_ctx_read_timing(ld_ctx* ctx, double* ms, int64_t* calls, double* flops, double* bytes) {
+  if (!ctx) return fail(LD_EINVAL, "context is NULL");
+  if (ctx->ev_used) {
+    LD_HIP(hipStreamSynchronize(ctx->stream));
+    timing_collect(ctx);
+  }
+  if (ms) *ms = ctx->mm_ms;
+  if (calls) *calls = ctx->mm_calls;
+  if (flops) *flops = ctx->mm_flops;
+  if (bytes) *bytes = ctx->mm_bytes;
+  return LD_OK;
+}
+
+ld_status ld_rational_coeffs(int32_t k, double* b, double* a, double* c) {
+  if (!b || !a || !c) return fail(LD_EINVAL, "null output pointer");
+  Rational r;
+  if (!rational_for(k, &r)) return fail(LD_EINVAL, "k must be 1, 3 or 5");
+  *b = r.b;
+  for (int j = 0; j < k; ++j) {
+    a[j] = r.a[j];
+    c[j] = r.c[j];
+  }
+  return LD_OK;
+}
+
+ld_status ld_fill_probes(ld_ctx* ctx, uint64_t seed, int64_t n, int64_t s, int32_t precision, void* Z) {
+  LD_TRY(check_ctx(ctx));
+  if (n < 1 || s < 1 || !Z) return fail(LD_EINVAL, "bad probe block arguments");
+  if (precision != LD_F64 && precision != LD_F32) return fail(LD_EINVAL, "bad precision");
+  launch_fill_rademacher(ctx->stream, stream_key(seed, kStreamProbes), n, s, precision == LD_F64, Z);
+  LD_HIP(hipGetLastError());
+  return LD_OK;
+}
+
+ld_status ld_fill_gaussian(ld_ctx* ctx, uint64_t seed, int32_t stream, int64_t rows, int64_t cols,
+                           double* out) {
+  LD_TRY(check_ctx(ctx));
+  if (rows < 1 || cols < 1 || !out || stream < 0) return fail(LD_EINVAL, "bad gaussian block arguments");
+  launch_fill_gaussian(ctx->stream, stream_key(seed, stream), rows, cols, out);
+  LD_HIP(hipGetLastError());
+  return LD_OK;
+}
+
+ld_status kernel_matmat(ld_ctx* ctx, const ld_operator* op, const void* V, int64_t s, void* Y) {
+  LD_TRY(check_ctx(ctx));
+  LD_TRY(check_operator(op));
+  if (!V || !Y || s < 1) return fail(LD_EINVAL, "bad V / Y / s");
+  if (V == Y) return fail(LD_EINVAL, "Y must not alias V");
+  const bool f64 = is_f64(op);
+  ctx->arena.reset();
+  LD_TRY(ctx->arena.reserve((size_t)op->n * op->d * 4 + 512 + matmat_scratch_bytes(ctx, f64, op->n, s)));
+  const void* Xp = nullptr;
+  LD_TRY(path_points(ctx, op, &Xp));
+  MatmatArgs a = base_args(op, Xp);
+  a.s = s;
+  a.V = V;
+  a.Y = Y;
+  return matmat(ctx, f64, a);
+}
+
+ld_status kernel_materialize(ld_ctx* ctx, const ld_operator* op, void* M_out) {
+  LD_TRY(check_ctx(ctx));
+  LD_TRY(check_operator(op));
+  if (!M_out) return fail(LD_EINVAL, "M_out is NULL");
+  launch_materialize(ctx->stream, make_kparams(*op), op->X, op->n, op->d, is_f64(op), M_out);
+  LD_HIP(hipGetLastError());
+  return LD_OK;
+}
+
+ld_status logdet_precond_build(ld_ctx* ctx, const ld_operator* op, int32_t rank, int32_t oversample,
+                               int32_t power_iters, uint64_t seed, ld_precond** out) {
+  LD_TRY(check_ctx(ctx));
+  LD_TRY(check_operator(op));
+  if (!out) return fail(LD_EINVAL, "out is NULL");
+  if (rank < 1 || oversample < 0 || (int64_t)rank + oversample > op->n)
+    return fail(LD_EINVAL, "need 1 <= rank and rank + oversample <= n");
+  if (rank + oversample > 4096) return fail(LD_EINVAL, "rank + oversample must be <= 4096");
+  if (power_iters < 0 || power_iters > 16) return fail(LD_EINVAL, "power_iters must be in 0..16");
+  return build_precond(ctx, op, rank, oversample, power_iters, seed, out);
+}
+
+ld_status ld_precond_info(const ld_precond* P, int64_t* n, int32_t* rank, double* logdet_P) {
+  if (!P) return fail(LD_EINVAL, "preconditioner is NULL");
+  if (n) *n = P->n;
+  if (rank) *rank = P->rank;
+  if (logdet_P) *logdet_P = P->logdet;
+  return LD_OK;
+}
+
+ld_status ld_precond_export(ld_ctx* ctx, const ld_precond* P, double* U, double* lambda, double* D) {
+  LD_TRY(check_ctx(ctx));
+  if (!P) return fail(LD_EINVAL, "preconditioner is NULL");
+  hipStream_t st = ctx->stream;
+  if (U) LD_HIP(hipMemcpyAsync(U, P->U, (size_t)P->n * P->rank * 8, hipMemcpyDeviceToDevice, st));
+  if (lambda) LD_HIP(hipMemcpyAsync(lambda, P->lam, (size_t)P->rank * 8, hipMemcpyDeviceToDevice, st));
+  if (D) LD_HIP(hipMemcpyAsync(D, P->D, (size_t)P->n * 8, hipMemcpyDeviceToDevice, st));
+  return LD_OK;
+}
+
+ld_status ld_precond_apply_inverse(ld_ctx* ctx, const ld_precond* P, const void* R, int64_t s,
+                                   int32_t precision, void* OUT) {
+  LD_TRY(check_ctx(ctx));
+  if (!P || !R || !OUT || s < 1) return fail(LD_EINVAL, "bad arguments");
+  if (R == OUT) return fail(LD_EINVAL, "OUT must not alias R");
+  if (precision != LD_F64 && precision != LD_F32) return fail(LD_EINVAL, "bad precision");
+  ctx->arena.reset();
+  LD_TRY(ctx->arena.reserve(woodbury_scratch_bytes(P->n, P->rank, s)));
+  return woodbury_apply(ctx, P, precision == LD_F64, R, s, OUT);
+}
+
+void ld_precond_free(ld_precond* P) {
+  if (!P) return;
+  (void)hipSetDevice(P->device);
+  (void)hipDeviceSynchronize();
+  if (P->block) (void)hipFree(P->block);
+  delete P;
+}
+
+ld_status logdet_estimate(ld_ctx* ctx, const ld_operator* op, const ld_precond* P, int32_t k,
+                          int32_t num_probes, uint64_t probe_seed, double tol, int32_t max_iters,
+                          ld_result* out, double* per_probe) {
+  LD_TRY(check_ctx(ctx));
+  LD_TRY(check_operator(op));
+  if (!out) return fail(LD_EINVAL, "out is NULL");
+  Rational rf;
+  if (!rational_for(k, &rf)) return fail(LD_EINVAL, "k must be 1, 3 or 5");
+  if (num_probes < 1) return fail(LD_EINVAL, "num_probes must be >= 1");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(LD_EINVAL, "tol must be finite and > 0");
+  if (max_iters < 1) return fail(LD_EINVAL, "max_iters must be >= 1");
+  if (P && P->n != op->n) return fail(LD_EINVAL, "preconditioner size does not match the operator");
+  ld_precond* own = nullptr;
+  if (!P) {
+    int rank = (int)std::min<int64_t>(100, std::max<int64_t>(1, op->n / 10));
+    int over = (int)std::min<int64_t>(10, op->n - rank);
+    LD_TRY(build_precond(ctx, op, rank, over, 2, probe_seed + 1, &own));
+    P = own;
+  }
+  const bool f64 = is_f64(op);
+  const int64_t n = op->n, s = num_probes;
+  const int J = k;
+  const size_t es = f64 ? 8 : 4;
+  ctx->arena.reset();
+  ld_status st_ = ctx->arena.reserve((size_t)n * op->d * 4 + 512 + (size_t)n * s * es + 512 +
+                                     pcg_scratch_bytes(ctx, f64, n, P->rank, s, J));
+  if (st_ != LD_OK) {
+    if (own) ld_precond_free(own);
+    return st_;
+  }
+  auto t0 = std::chrono::steady_clock::now();
+  const void* Xp = nullptr;
+  void* Z = nullptr;
+  std::vector<double> ztx, ztz;
+  int iters = 0, conv = 0;
+  double rr = 0.0;
+  bool breakdown = false;
+  st_ = path_points(ctx, op, &Xp);
+  if (st_ == LD_OK) {
+    Z = ctx->arena.take((size_t)n * s * es);
+    if (!Z) st_ = fail(LD_ENOMEM, "scratch arena too small for probes");
+  }
+  if (st_ == LD_OK) {
+    launch_fill_rademacher(ctx->stream, stream_key(probe_seed, kStreamProbes), n, s, f64, Z);
+    MatmatArgs base = base_args(op, Xp);
+    st_ = multishift_pcg(ctx, f64, base, P, rf.a, J, Z, s, tol, max_iters, ztx, ztz, &iters, &conv,
+                         &rr, &breakdown);
+  }
+  const double logdet_P = P->logdet;
+  if (own) ld_precond_free(own);
+  if (st_ != LD_OK) return st_;
+  auto t1 = std::chrono::steady_clock::now();
+
+  // Hutchinson mean (Section 1) of t_i = b z^T z + sum_j c_j z^T x_j
+  std::vector<double> t(s);
+  double mean = 0.0;
+  for (int64_t c = 0; c < s; ++c) {
+    double v = rf.b * ztz[c];
+    for (int j = 0; j < J; ++j) v += rf.c[j] * ztx[(size_t)j * s + c];
+    t[c] = v;
+    mean += v;
+  }
+  mean /= (double)s;
+  double var = 0.0;
+  for (int64_t c = 0; c < s; ++c) var += (t[c] - mean) * (t[c] - mean);
+  out->trace_term = mean;
+  out->logdet_P = logdet_P;
+  out->logdet = logdet_P + mean;
+  out->std_err = s > 1 ? std::sqrt(var / (double)(s - 1) / (double)s) : NAN;
+  out->rel_resid = rr;
+  out->seconds_solve = std::chrono::duration<double>(t1 - t0).count();
+  out->iterations = iters;
+  out->converged_cols = conv;
+  out->k = k;
+  out->num_probes = num_probes;
+  if (per_probe) std::memcpy(per_probe, t.data(), (size_t)s * sizeof(double));
+  if (breakdown)
+    return fail(LD_ENOTSPD, "non-positive curvature or residual norm in the solver (M or P not SPD?)");
+  if (conv < s) return fail(LD_ENOCONV, "max_iters reached before every probe converged");
+  return LD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,178 @@
+// Internal declarations shared by the liblogdet translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "logdet.h"
+
+namespace ld {
+
+// ---------------------------------------------------------------- errors --
+void set_error(const std::string& msg);
+ld_status fail(ld_status st, const std::string& msg);
+
+#define LD_HIP(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      return ::ld::fail(LD_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define LD_TRY(expr)                     \
+  do {                                   \
+    ld_status s_ = (expr);               \
+    if (s_ != LD_OK) return s_;          \
+  } while (0)
+
+// ------------------------------------------------------------- constants --
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+constexpr int kStreamOmega = 1;
+constexpr int kStreamProbes = 2;
+
+// host-side SplitMix64 finalizer (key derivation)
+inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+inline uint64_t stream_key(uint64_t seed, int stream) {
+  return mix64(seed + kGolden * (uint64_t)(stream + 1));
+}
+
+// ------------------------------------------------------ scratch arena --
+// Grow-only device arena owned by a context.  Allocation is a bump pointer
+// over one hipMalloc'ed block; reset() frees everything at once.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t top = 0;
+  ld_status reserve(size_t bytes);  // ensure capacity (only when top == 0)
+  void* take(size_t bytes);         // 256-byte aligned; nullptr if out of room
+  void reset() { top = 0; }
+  void release();
+};
+
+}  // namespace ld
+
+struct ld_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 256;
+  ld::Arena arena;
+  double* pinned = nullptr;  // host pinned staging for small readbacks
+  size_t pinned_count = 0;
+  // optional event timing of the solver's kernel-matrix product launches
+  bool timing = false;
+  std::vector<hipEvent_t> ev;  // pairs (start, stop)
+  size_t ev_used = 0;          // events recorded and not yet collected
+  double mm_ms = 0.0;
+  int64_t mm_calls = 0;
+  double mm_flops = 0.0;
+  double mm_bytes = 0.0;
+  std::vector<double> pending_flops, pending_bytes;
+};
+
+struct ld_precond {
+  int64_t n = 0;
+  int32_t rank = 0;
+  int device = 0;
+  double logdet = 0.0;
+  double* U = nullptr;       // n x rank
+  double* lam = nullptr;     // rank, descending
+  double* D = nullptr;       // n
+  double* F64 = nullptr;     // n x rank : D^-1 U L^-T
+  double* Dinv64 = nullptr;  // n
+  float* F32 = nullptr;
+  float* Dinv32 = nullptr;
+  void* block = nullptr;     // single allocation holding all of the above
+};
+
+namespace ld {
+
+// Kernel-evaluation parameters derived from ld_operator.
+struct KParams {
+  int kind;
+  double variance;
+  double noise;
+  double c_rbf;      // 1 / (2 l^2)
+  double c_mat;      // sqrt(5) / l
+};
+KParams make_kparams(const ld_operator& op);
+
+ld_status check_operator(const ld_operator* op);
+ld_status ensure_pinned(ld_ctx* ctx, size_t count);
+// event timing: reserve a (start, stop) pair, and fold finished pairs into
+// the totals (call only after the stream has been synchronized)
+ld_status timing_pair(ld_ctx* ctx, hipEvent_t* start, hipEvent_t* stop, double flops, double bytes);
+void timing_collect(ld_ctx* ctx);
+
+// ------------------------------------------------------------ launchers --
+// rng.hip
+void launch_fill_rademacher(hipStream_t st, uint64_t key, int64_t n, int64_t s, bool f64, void* Z);
+void launch_fill_gaussian(hipStream_t st, uint64_t key, int64_t rows, int64_t cols, double* out);
+
+// matmat.hip
+// Y (n x s, ld = s) = M V (+ alpha2 * X2) where M is stored (A != nullptr,
+// leading dimension n) or generated from points.  Points: X64 (FP64) for the
+// FP64 path, X32 (FP32 copy) for the FP32 path.  Optional column dots:
+// dots[blk][c] = sum over rows of block blk of V[i][c] * Y[i][c] (FP64),
+// returning the number of row blocks in *dot_blocks.
+struct MatmatArgs {
+  int64_t n = 0;
+  int64_t s = 0;
+  int d = 0;
+  KParams kp{};
+  const void* A = nullptr;   // stored matrix or nullptr
+  const void* X = nullptr;   // points in the path's precision (n x d)
+  const void* V = nullptr;
+  void* Y = nullptr;
+  const void* X2 = nullptr;  // optional addend
+  double alpha2 = 0.0;
+  double* dots = nullptr;    // optional
+  int* dot_blocks = nullptr;
+  bool timed = false;        // record events around the product kernel (ctx->timing)
+};
+ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a);
+size_t matmat_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int64_t s);
+constexpr int kEpiRows = 128;  // rows per epilogue block (dot partial granularity)
+void launch_materialize(hipStream_t st, const KParams& kp, const double* X, int64_t n, int d,
+                        bool f64, void* M);
+void launch_convert_f64_to_f32(hipStream_t st, const double* in, float* out, int64_t count);
+void launch_convert_f32_to_f64(hipStream_t st, const float* in, double* out, int64_t count);
+
+// dense64.hip -- FP64 small/tall dense algebra for the preconditioner
+// G (m x m) = A^T diag(w) B, A and B n x m row-major (w may be null).
+ld_status gram64(ld_ctx* ctx, const double* A, const double* B, const double* w, int64_t n, int m,
+                 double* G);
+// in-place upper Cholesky G = R^T R (m x m); writes R (upper, zero below);
+// *ok = 1 on success (pivot > 0 everywhere), 0 on breakdown (device int).
+void launch_cholesky_upper(hipStream_t st, double* G, int m, int* ok);
+// Rinv = R^-1 for upper-triangular R (m x m)
+void launch_tri_inv_upper(hipStream_t st, const double* R, int m, double* Rinv);
+// C (n x N) = diag(rs) A (n x K) B (K x N, row stride ldb); rs may be null.
+void launch_gemm64(hipStream_t st, const double* A, const double* B, int ldb, const double* rs,
+                   int64_t n, int K, int N, double* C);
+// symmetric eigendecomposition by parallel cyclic Jacobi; A (m x m) is
+// overwritten; on return evals (m, descending) and evecs (m x m, column j is
+// the eigenvector of evals[j]).
+ld_status jacobi_eigh(ld_ctx* ctx, double* A, int m, double* evals, double* evecs);
+
+// pcg.hip
+ld_status woodbury_apply(ld_ctx* ctx, const ld_precond* P, bool f64, const void* R, int64_t s,
+                         void* OUT);
+size_t woodbury_scratch_bytes(int64_t n, int rank, int64_t s);
+// Multi-shift PCG over the probe block Z (n x s) for shifts a_j (ascending,
+// shifts[0] seeds the Krylov space).  Returns z^T x_j (J x s, row j = shift j)
+// and z^T z per column in host vectors.
+ld_status multishift_pcg(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precond* P,
+                         const double* shifts, int J, const void* Z, int64_t s, double tol,
+                         int max_iters, std::vector<double>& ztx, std::vector<double>& ztz,
+                         int* iterations, int* converged, double* rel_resid, bool* breakdown);
+size_t pcg_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int rank, int64_t s, int J);
+
+}  // namespace ld

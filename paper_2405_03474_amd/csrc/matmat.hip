@@ -1,0 +1,639 @@
+// Kernel-matrix times block products Y = M V (Section 2: the product that
+// dominates every Krylov step, cost O(n^2) per column) on CDNA4 matrix cores.
+//
+// Two sources for the left operand:
+//   stored : M (n x n, row-major) streamed from HBM through LDS
+//   on the fly : every lane evaluates its own MFMA A-fragment entries
+//            k(x_i, x_k) from the points, so the n x n matrix never exists
+// and two arithmetic paths:
+//   FP32 : v_mfma_f32_32x32x2f32, wave tile 32 rows x 32*NB columns
+//   FP64 : v_mfma_f64_16x16x4f64, wave tile 32 rows x 16*NB columns
+// A workgroup is 4 waves stacked along rows (128 rows).  Work is split
+// stream-K style: the (tile, k-stage) index space is cut into G equal
+// contiguous ranges, one per workgroup, so every CU gets the same number of
+// MFMA stages whatever n is.  Each workgroup writes the partial sums of every
+// tile it touched to a scratch slot; an epilogue kernel adds the slots of a
+// tile in a fixed order (deterministic), adds noise * V for the on-the-fly
+// path, an optional alpha2 * X2 term, and optional per-column dots V^T Y.
+//
+// The k index inside a stage is permuted so that every lane reads contiguous
+// LDS words: in MFMA k-step t, lane half h supplies physical column
+// h * (BK / halves) + t for both operands.
+#include "ld_common.hpp"
+
+namespace ld {
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128;  // rows per workgroup tile
+constexpr int BK = 32;   // k per stage
+constexpr int DMAX = 16; // max point dimension on the fly
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr int kMaxContrib = 64;  // partial slots summed per output tile (bounded by the plan)
+
+struct SK {
+  int64_t n, s;
+  int64_t U;  // total units = tiles * S
+  int rt;     // row tiles
+  int S;      // stages per tile
+  int G;      // workgroups
+  int J;      // partial slots per workgroup
+};
+
+// ---------------------------------------------------------- kernel values --
+// FP32: RBF c = log2(e) / (2 l^2);  Matern-5/2 c = sqrt(5) / l
+template <int KIND>
+__device__ __forceinline__ float kval32(float r2, float var, float c) {
+  if (KIND == LD_RBF) return var * __builtin_amdgcn_exp2f(-r2 * c);
+  float t = __builtin_amdgcn_sqrtf(r2) * c;
+  return var * (1.0f + t + t * t * (1.0f / 3.0f)) * __builtin_amdgcn_exp2f(-t * kLog2e);
+}
+// FP64: RBF c = 1 / (2 l^2);  Matern-5/2 c = sqrt(5) / l
+template <int KIND>
+__device__ __forceinline__ double kval64(double r2, double var, double c) {
+  if (KIND == LD_RBF) return var * exp(-r2 * c);
+  double t = sqrt(r2) * c;
+  return var * (1.0 + t + t * t * (1.0 / 3.0)) * exp(-t);
+}
+
+__device__ __forceinline__ void unit_range(const SK& p, int g, int64_t& u0, int64_t& u1) {
+  u0 = (p.U * g) / p.G;
+  u1 = (p.U * (g + 1)) / p.G;
+}
+
+// ------------------------------------------------------------ FP32 path --
+template <int NB, bool FLY, int KIND, int DT>
+__global__ __launch_bounds__(256, 2) void k_mm32(const float* __restrict__ A,
+                                                 const float* __restrict__ Xp, int d, float var,
+                                                 float c, const float* __restrict__ V,
+                                                 float* __restrict__ part, SK p) {
+  constexpr int NT = 32 * NB;
+  constexpr int BS = NT + 2;   // B row stride: halves of a wave land 32 banks apart
+  constexpr int AS = BK + 4;   // A row stride: conflict-free 16-byte fragment reads
+  __shared__ __attribute__((aligned(16))) float As[FLY ? 4 : BM * AS];
+  __shared__ float Bs[BK * BS];
+  __shared__ float Xs[FLY ? BK * DMAX : 1];
+  const int dd_n = DT > 0 ? DT : d;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, lh = lane >> 5;
+  const int64_t n = p.n, s = p.s;
+
+  int64_t u, uend;
+  unit_range(p, blockIdx.x, u, uend);
+  int seg = 0;
+  while (u < uend) {
+    const int64_t T = u / p.S;
+    const int st0 = (int)(u - T * p.S);
+    const int st1 = (int)((int64_t)p.S < st0 + (uend - u) ? (int64_t)p.S : st0 + (uend - u));
+    const int rtile = (int)(T % p.rt);
+    const int64_t ctile = T / p.rt;
+    const int64_t i0 = (int64_t)rtile * BM;
+    const int64_t c0 = ctile * NT;
+
+    f32x16 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
+
+    float xr[FLY ? DMAX : 1];
+    if (FLY) {
+      const int64_t row = i0 + 32 * wave + li;
+#pragma unroll
+      for (int dd = 0; dd < DMAX; ++dd)
+        if (dd < dd_n) xr[dd] = row < n ? Xp[row * dd_n + dd] : 0.f;
+    }
+
+    for (int st = st0; st < st1; ++st) {
+      const int64_t k0 = (int64_t)st * BK;
+      __syncthreads();
+      for (int e = tid; e < BK * NT; e += 256) {
+        const int kk = e / NT, cc = e - kk * NT;
+        const int64_t kr = k0 + kk, col = c0 + cc;
+        Bs[kk * BS + cc] = (kr < n && col < s) ? V[kr * s + col] : 0.f;
+      }
+      if (FLY) {
+        for (int e = tid; e < BK * dd_n; e += 256) {
+          const int kk = e / dd_n, dd = e - kk * dd_n;
+          const int64_t kr = k0 + kk;
+          Xs[kk * DMAX + dd] = kr < n ? Xp[kr * dd_n + dd] : 0.f;
+        }
+      } else {
+        const bool vec_ok = (n & 3) == 0;
+        for (int e = tid; e < BM * (BK / 4); e += 256) {
+          const int rr = e / (BK / 4), kq = e - rr * (BK / 4);
+          const int64_t row = i0 + rr, kc = k0 + 4 * kq;
+          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (row < n) {
+            const float* src = A + row * n + kc;
+            if (vec_ok && kc + 3 < n) {
+              v = *(const float4*)src;
+            } else {
+              if (kc + 0 < n) v.x = src[0];
+              if (kc + 1 < n) v.y = src[1];
+              if (kc + 2 < n) v.z = src[2];
+              if (kc + 3 < n) v.w = src[3];
+            }
+          }
+          *(float4*)&As[rr * AS + 4 * kq] = v;
+        }
+      }
+      __syncthreads();
+
+      float a[16];
+      if (FLY) {
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          const float* xk = &Xs[(lh * 16 + t) * DMAX];
+          float r2 = 0.f;
+#pragma unroll
+          for (int dd = 0; dd < DMAX; ++dd)
+            if (dd < dd_n) {
+              const float df = xr[dd] - xk[dd];
+              r2 = __builtin_fmaf(df, df, r2);
+            }
+          a[t] = kval32<KIND>(r2, var, c);
+        }
+      } else {
+        const float4* ap = (const float4*)&As[(32 * wave + li) * AS + lh * 16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float4 v = ap[q];
+          a[4 * q + 0] = v.x;
+          a[4 * q + 1] = v.y;
+          a[4 * q + 2] = v.z;
+          a[4 * q + 3] = v.w;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const float* brow = &Bs[(lh * 16 + t) * BS + li];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t], brow[nb * 32], acc[nb], 0, 0, 0);
+      }
+    }
+
+    float* dst = part + ((int64_t)blockIdx.x * p.J + seg) * (int64_t)(BM * NT);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 32 * wave + 8 * (r >> 2) + 4 * lh + (r & 3);
+        dst[row * NT + nb * 32 + li] = acc[nb][r];
+      }
+    ++seg;
+    u += st1 - st0;
+  }
+}
+
+// ------------------------------------------------------------ FP64 path --
+template <int NB, bool FLY, int KIND, int DT>
+__global__ __launch_bounds__(256, 2) void k_mm64(const double* __restrict__ A,
+                                                 const double* __restrict__ Xp, int d, double var,
+                                                 double c, const double* __restrict__ V,
+                                                 double* __restrict__ part, SK p) {
+  constexpr int NT = 16 * NB;
+  constexpr int BS = NT + 2;
+  constexpr int AS = BK + 2;
+  __shared__ __attribute__((aligned(16))) double As[FLY ? 2 : BM * AS];
+  __shared__ double Bs[BK * BS];
+  __shared__ double Xs[FLY ? BK * DMAX : 1];
+  const int dd_n = DT > 0 ? DT : d;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lj = lane & 15, lh = lane >> 4;  // lh in 0..3
+  const int64_t n = p.n, s = p.s;
+
+  int64_t u, uend;
+  unit_range(p, blockIdx.x, u, uend);
+  int seg = 0;
+  while (u < uend) {
+    const int64_t T = u / p.S;
+    const int st0 = (int)(u - T * p.S);
+    const int st1 = (int)((int64_t)p.S < st0 + (uend - u) ? (int64_t)p.S : st0 + (uend - u));
+    const int rtile = (int)(T % p.rt);
+    const int64_t ctile = T / p.rt;
+    const int64_t i0 = (int64_t)rtile * BM;
+    const int64_t c0 = ctile * NT;
+
+    f64x4 acc[2][NB];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[rb][nb][r] = 0.0;
+
+    double xr[2][FLY ? DMAX : 1];
+    if (FLY) {
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        const int64_t row = i0 + 32 * wave + 16 * rb + lj;
+#pragma unroll
+        for (int dd = 0; dd < DMAX; ++dd)
+          if (dd < dd_n) xr[rb][dd] = row < n ? Xp[row * dd_n + dd] : 0.0;
+      }
+    }
+
+    for (int st = st0; st < st1; ++st) {
+      const int64_t k0 = (int64_t)st * BK;
+      __syncthreads();
+      for (int e = tid; e < BK * NT; e += 256) {
+        const int kk = e / NT, cc = e - kk * NT;
+        const int64_t kr = k0 + kk, col = c0 + cc;
+        Bs[kk * BS + cc] = (kr < n && col < s) ? V[kr * s + col] : 0.0;
+      }
+      if (FLY) {
+        for (int e = tid; e < BK * dd_n; e += 256) {
+          const int kk = e / dd_n, dd = e - kk * dd_n;
+          const int64_t kr = k0 + kk;
+          Xs[kk * DMAX + dd] = kr < n ? Xp[kr * dd_n + dd] : 0.0;
+        }
+      } else {
+        const bool vec_ok = (n & 1) == 0;
+        for (int e = tid; e < BM * (BK / 2); e += 256) {
+          const int rr = e / (BK / 2), kq = e - rr * (BK / 2);
+          const int64_t row = i0 + rr, kc = k0 + 2 * kq;
+          double2 v = make_double2(0.0, 0.0);
+          if (row < n) {
+            const double* src = A + row * n + kc;
+            if (vec_ok && kc + 1 < n) {
+              v = *(const double2*)src;
+            } else {
+              if (kc + 0 < n) v.x = src[0];
+              if (kc + 1 < n) v.y = src[1];
+            }
+          }
+          *(double2*)&As[rr * AS + 2 * kq] = v;
+        }
+      }
+      __syncthreads();
+
+      double a[2][8];
+      if (FLY) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const double* xk = &Xs[(lh * 8 + t) * DMAX];
+#pragma unroll
+          for (int rb = 0; rb < 2; ++rb) {
+            double r2 = 0.0;
+#pragma unroll
+            for (int dd = 0; dd < DMAX; ++dd)
+              if (dd < dd_n) {
+                const double df = xr[rb][dd] - xk[dd];
+                r2 = fma(df, df, r2);
+              }
+            a[rb][t] = kval64<KIND>(r2, var, c);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+          const double2* ap = (const double2*)&As[(32 * wave + 16 * rb + lj) * AS + lh * 8];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const double2 v = ap[q];
+            a[rb][2 * q + 0] = v.x;
+            a[rb][2 * q + 1] = v.y;
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const double* brow = &Bs[(lh * 8 + t) * BS + lj];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const double b = brow[nb * 16];
+#pragma unroll
+          for (int rb = 0; rb < 2; ++rb)
+            acc[rb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb][t], b, acc[rb][nb], 0, 0, 0);
+        }
+      }
+    }
+
+    double* dst = part + ((int64_t)blockIdx.x * p.J + seg) * (int64_t)(BM * NT);
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 32 * wave + 16 * rb + lh + 4 * r;  // f64 16x16 output: row = lane/16 + 4 reg
+          dst[row * NT + nb * 16 + lj] = acc[rb][nb][r];
+        }
+    ++seg;
+    u += st1 - st0;
+  }
+}
+
+// --------------------------------------------------------------- epilogue --
+// One workgroup per output tile: Y = sum of the tile's partial slots
+// (+ noise * V on the fly) (+ alpha2 * X2); optional dots[rtile][c].
+template <typename T>
+__global__ __launch_bounds__(256) void k_epilogue(const T* __restrict__ part, SK p, int NT,
+                                                  T* __restrict__ Y, const T* __restrict__ V,
+                                                  double noise, const T* __restrict__ X2,
+                                                  double alpha2, double* __restrict__ dots) {
+  __shared__ double red[256];
+  __shared__ int64_t slot[kMaxContrib];
+  __shared__ int nslot;
+  const int tid = threadIdx.x;
+  const int64_t Tt = blockIdx.x;
+  const int rtile = (int)(Tt % p.rt);
+  const int64_t c0 = (Tt / p.rt) * NT;
+  const int64_t i0 = (int64_t)rtile * BM;
+  if (tid == 0) {
+    // workgroups whose unit range intersects [Tt*S, (Tt+1)*S), in order
+    const int64_t ub = Tt * p.S, ue = ub + p.S;
+    int g = (int)((ub * p.G) / p.U);
+    if (g >= p.G) g = p.G - 1;
+    while (g > 0 && (p.U * g) / p.G > ub) --g;
+    while (g + 1 < p.G && (p.U * (g + 1)) / p.G <= ub) ++g;
+    int cnt = 0;
+    for (; g < p.G && cnt < kMaxContrib; ++g) {
+      const int64_t b0 = (p.U * g) / p.G, b1 = (p.U * (g + 1)) / p.G;
+      if (b0 >= ue) break;
+      if (b1 <= b0) continue;
+      slot[cnt++] = ((int64_t)g * p.J + (Tt - b0 / p.S)) * (int64_t)(BM * NT);
+    }
+    nslot = cnt;
+  }
+  __syncthreads();
+  const int ns = nslot;
+  const int col = tid % NT;  // 256 is a multiple of NT
+  double dacc = 0.0;
+  for (int e = tid; e < BM * NT; e += 256) {
+    const int row = e / NT;
+    double sum = 0.0;
+    for (int q = 0; q < ns; ++q) sum += (double)part[slot[q] + e];
+    const int64_t i = i0 + row, c = c0 + col;
+    if (i < p.n && c < p.s) {
+      const int64_t off = i * p.s + c;
+      if (noise != 0.0) sum += noise * (double)V[off];
+      if (X2) sum += alpha2 * (double)X2[off];
+      const T y = (T)sum;
+      Y[off] = y;
+      if (dots) dacc += (double)V[off] * (double)y;
+    }
+  }
+  if (dots) {
+    red[tid] = dacc;
+    __syncthreads();
+    if (tid < NT) {
+      double t = 0.0;
+      for (int q = tid; q < 256; q += NT) t += red[q];
+      const int64_t c = c0 + tid;
+      if (c < p.s) dots[(int64_t)rtile * p.s + c] = t;
+    }
+  }
+}
+
+// ------------------------------------------------------------ materialize --
+template <typename T, int KIND>
+__global__ __launch_bounds__(256) void k_materialize(const double* __restrict__ X, int64_t n, int d,
+                                                     double var, double c, double noise,
+                                                     T* __restrict__ M) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double xj[DMAX];
+#pragma unroll
+  for (int dd = 0; dd < DMAX; ++dd) xj[dd] = (dd < d && j < n) ? X[j * d + dd] : 0.0;
+  for (int64_t i = blockIdx.y; i < n; i += gridDim.y) {
+    if (j >= n) continue;
+    double r2 = 0.0;
+#pragma unroll
+    for (int dd = 0; dd < DMAX; ++dd)
+      if (dd < d) {
+        const double df = X[i * d + dd] - xj[dd];
+        r2 = fma(df, df, r2);
+      }
+    double v = kval64<KIND>(r2, var, c);
+    if (i == j) v += noise;
+    M[i * n + j] = (T)v;
+  }
+}
+
+__global__ void k_f64_to_f32(const double* __restrict__ in, float* __restrict__ out, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256)
+    out[i] = (float)in[i];
+}
+__global__ void k_f32_to_f64(const float* __restrict__ in, double* __restrict__ out, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256)
+    out[i] = (double)in[i];
+}
+
+int grid1(int64_t count) {
+  int64_t b = (count + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
+}
+
+// ---------------------------------------------------------------- dispatch --
+struct Plan {
+  int NT;
+  SK p;
+  size_t part_bytes;
+};
+
+Plan make_plan(ld_ctx* ctx, bool f64, int64_t n, int64_t s) {
+  Plan pl{};
+  if (f64)
+    pl.NT = s > 32 ? 64 : (s > 16 ? 32 : 16);
+  else
+    pl.NT = s > 32 ? 64 : 32;
+  SK& p = pl.p;
+  p.n = n;
+  p.s = s;
+  p.rt = (int)((n + BM - 1) / BM);
+  const int64_t ct = (s + pl.NT - 1) / pl.NT;
+  p.S = (int)((n + BK - 1) / BK);
+  p.U = (int64_t)p.rt * ct * p.S;
+  const int64_t gmax = (int64_t)ctx->num_cu * 2;
+  const int64_t min_units = 8;
+  int64_t G = (p.U + min_units - 1) / min_units;
+  if (G > gmax) G = gmax;
+  // keep every tile split over at most kMaxContrib - 2 workgroups
+  const int64_t tiles = (int64_t)p.rt * ct;
+  if (G > tiles * (kMaxContrib / 2 - 1)) G = tiles * (kMaxContrib / 2 - 1);
+  if (G < 1) G = 1;
+  p.G = (int)G;
+  const int64_t per = (p.U + G - 1) / G;
+  p.J = (int)((per + p.S - 1) / p.S + 1);
+  pl.part_bytes = (size_t)p.G * p.J * BM * pl.NT * (f64 ? sizeof(double) : sizeof(float));
+  return pl;
+}
+
+template <int KIND, int DT>
+void launch_fly32(int NB, dim3 g, hipStream_t st, const float* X, int d, float var, float c,
+                  const float* V, float* part, const SK& p) {
+  if (NB == 2)
+    hipLaunchKernelGGL((k_mm32<2, true, KIND, DT>), g, dim3(256), 0, st, nullptr, X, d, var, c, V,
+                       part, p);
+  else
+    hipLaunchKernelGGL((k_mm32<1, true, KIND, DT>), g, dim3(256), 0, st, nullptr, X, d, var, c, V,
+                       part, p);
+}
+
+template <int KIND, int DT>
+void launch_fly64(int NB, dim3 g, hipStream_t st, const double* X, int d, double var, double c,
+                  const double* V, double* part, const SK& p) {
+  if (NB == 4)
+    hipLaunchKernelGGL((k_mm64<4, true, KIND, DT>), g, dim3(256), 0, st, nullptr, X, d, var, c, V,
+                       part, p);
+  else if (NB == 2)
+    hipLaunchKernelGGL((k_mm64<2, true, KIND, DT>), g, dim3(256), 0, st, nullptr, X, d, var, c, V,
+                       part, p);
+  else
+    hipLaunchKernelGGL((k_mm64<1, true, KIND, DT>), g, dim3(256), 0, st, nullptr, X, d, var, c, V,
+                       part, p);
+}
+
+template <int KIND>
+void fly32_by_d(int NB, dim3 g, hipStream_t st, const float* X, int d, float var, float c,
+                const float* V, float* part, const SK& p) {
+  switch (d) {
+    case 2: launch_fly32<KIND, 2>(NB, g, st, X, d, var, c, V, part, p); break;
+    case 3: launch_fly32<KIND, 3>(NB, g, st, X, d, var, c, V, part, p); break;
+    case 8: launch_fly32<KIND, 8>(NB, g, st, X, d, var, c, V, part, p); break;
+    default: launch_fly32<KIND, 0>(NB, g, st, X, d, var, c, V, part, p); break;
+  }
+}
+
+template <int KIND>
+void fly64_by_d(int NB, dim3 g, hipStream_t st, const double* X, int d, double var, double c,
+                const double* V, double* part, const SK& p) {
+  switch (d) {
+    case 2: launch_fly64<KIND, 2>(NB, g, st, X, d, var, c, V, part, p); break;
+    case 3: launch_fly64<KIND, 3>(NB, g, st, X, d, var, c, V, part, p); break;
+    case 8: launch_fly64<KIND, 8>(NB, g, st, X, d, var, c, V, part, p); break;
+    default: launch_fly64<KIND, 0>(NB, g, st, X, d, var, c, V, part, p); break;
+  }
+}
+
+}  // namespace
+
+KParams make_kparams(const ld_operator& op) {
+  KParams kp{};
+  kp.kind = op.kind;
+  kp.variance = op.variance;
+  kp.noise = op.noise;
+  kp.c_rbf = 1.0 / (2.0 * op.lengthscale * op.lengthscale);
+  kp.c_mat = 2.23606797749978969640917366873128 / op.lengthscale;
+  return kp;
+}
+
+size_t matmat_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int64_t s) {
+  return make_plan(ctx, f64, n, s).part_bytes + 1024;
+}
+
+ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
+  if (a.n <= 0 || a.s <= 0) return LD_OK;
+  Plan pl = make_plan(ctx, f64, a.n, a.s);
+  void* part = ctx->arena.take(pl.part_bytes);
+  if (!part) return fail(LD_ENOMEM, "matmat: scratch arena too small");
+  hipStream_t st = ctx->stream;
+  const bool fly = a.A == nullptr;
+  const int kind = a.kp.kind;
+  dim3 grid(pl.p.G);
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (a.timed && ctx->timing) {
+    const double nn = (double)a.n * (double)a.n;
+    const double es = f64 ? 8.0 : 4.0;
+    // algorithmic traffic: the stored matrix once, V read and Y written once
+    const double bytes = (fly ? 0.0 : nn * es) + 2.0 * (double)a.n * a.s * es;
+    LD_TRY(timing_pair(ctx, &ev0, &ev1, 2.0 * nn * (double)a.s, bytes));
+    LD_HIP(hipEventRecord(ev0, st));
+  }
+  if (f64) {
+    const int NB = pl.NT / 16;
+    const double c = kind == LD_RBF ? a.kp.c_rbf : a.kp.c_mat;
+    const double* V = (const double*)a.V;
+    double* P = (double*)part;
+    if (fly) {
+      if (kind == LD_RBF)
+        fly64_by_d<LD_RBF>(NB, grid, st, (const double*)a.X, a.d, a.kp.variance, c, V, P, pl.p);
+      else
+        fly64_by_d<LD_MATERN52>(NB, grid, st, (const double*)a.X, a.d, a.kp.variance, c, V, P, pl.p);
+    } else {
+      const double* A = (const double*)a.A;
+      if (NB == 4)
+        hipLaunchKernelGGL((k_mm64<4, false, 0, 1>), grid, dim3(256), 0, st, A, nullptr, 1, 0.0,
+                           0.0, V, P, pl.p);
+      else if (NB == 2)
+        hipLaunchKernelGGL((k_mm64<2, false, 0, 1>), grid, dim3(256), 0, st, A, nullptr, 1, 0.0,
+                           0.0, V, P, pl.p);
+      else
+        hipLaunchKernelGGL((k_mm64<1, false, 0, 1>), grid, dim3(256), 0, st, A, nullptr, 1, 0.0,
+                           0.0, V, P, pl.p);
+    }
+    if (ev1) LD_HIP(hipEventRecord(ev1, st));
+    const int64_t tiles = (int64_t)pl.p.rt * ((a.s + pl.NT - 1) / pl.NT);
+    hipLaunchKernelGGL(k_epilogue<double>, dim3((unsigned)tiles), dim3(256), 0, st, P, pl.p, pl.NT,
+                       (double*)a.Y, V, fly ? a.kp.noise : 0.0, (const double*)a.X2, a.alpha2,
+                       a.dots);
+  } else {
+    const int NB = pl.NT / 32;
+    const float c = (float)(kind == LD_RBF ? a.kp.c_rbf * 1.4426950408889634 : a.kp.c_mat);
+    const float* V = (const float*)a.V;
+    float* P = (float*)part;
+    if (fly) {
+      if (kind == LD_RBF)
+        fly32_by_d<LD_RBF>(NB, grid, st, (const float*)a.X, a.d, (float)a.kp.variance, c, V, P,
+                           pl.p);
+      else
+        fly32_by_d<LD_MATERN52>(NB, grid, st, (const float*)a.X, a.d, (float)a.kp.variance, c, V,
+                                P, pl.p);
+    } else {
+      const float* A = (const float*)a.A;
+      if (NB == 2)
+        hipLaunchKernelGGL((k_mm32<2, false, 0, 1>), grid, dim3(256), 0, st, A, nullptr, 1, 0.f,
+                           0.f, V, P, pl.p);
+      else
+        hipLaunchKernelGGL((k_mm32<1, false, 0, 1>), grid, dim3(256), 0, st, A, nullptr, 1, 0.f,
+                           0.f, V, P, pl.p);
+    }
+    if (ev1) LD_HIP(hipEventRecord(ev1, st));
+    const int64_t tiles = (int64_t)pl.p.rt * ((a.s + pl.NT - 1) / pl.NT);
+    hipLaunchKernelGGL(k_epilogue<float>, dim3((unsigned)tiles), dim3(256), 0, st, P, pl.p, pl.NT,
+                       (float*)a.Y, V, fly ? a.kp.noise : 0.0, (const float*)a.X2, a.alpha2,
+                       a.dots);
+  }
+  if (a.dot_blocks) *a.dot_blocks = pl.p.rt;
+  LD_HIP(hipGetLastError());
+  return LD_OK;
+}
+
+void launch_materialize(hipStream_t st, const KParams& kp, const double* X, int64_t n, int d,
+                        bool f64, void* M) {
+  const double c = kp.kind == LD_RBF ? kp.c_rbf : kp.c_mat;
+  int64_t gy = n < 256 ? n : 256;
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)gy);
+  if (f64) {
+    if (kp.kind == LD_RBF)
+      hipLaunchKernelGGL((k_materialize<double, LD_RBF>), grid, dim3(256), 0, st, X, n, d,
+                         kp.variance, c, kp.noise, (double*)M);
+    else
+      hipLaunchKernelGGL((k_materialize<double, LD_MATERN52>), grid, dim3(256), 0, st, X, n, d,
+                         kp.variance, c, kp.noise, (double*)M);
+  } else {
+    if (kp.kind == LD_RBF)
+      hipLaunchKernelGGL((k_materialize<float, LD_RBF>), grid, dim3(256), 0, st, X, n, d,
+                         kp.variance, c, kp.noise, (float*)M);
+    else
+      hipLaunchKernelGGL((k_materialize<float, LD_MATERN52>), grid, dim3(256), 0, st, X, n, d,
+                         kp.variance, c, kp.noise, (float*)M);
+  }
+}
+
+void launch_convert_f64_to_f32(hipStream_t st, const double* in, float* out, int64_t count) {
+  if (count > 0) hipLaunchKernelGGL(k_f64_to_f32, dim3(grid1(count)), dim3(256), 0, st, in, out, count);
+}
+void launch_convert_f32_to_f64(hipStream_t st, const float* in, double* out, int64_t count) {
+  if (count > 0) hipLaunchKernelGGL(k_f32_to_f64, dim3(grid1(count)), dim3(256), 0, st, in, out, count);
+}
+
+}  // namespace ld

@@ -1,0 +1,568 @@
+// Woodbury apply of P^-1 and the block multi-shift preconditioned CG with the
+// Hutchinson reduction (Section 2: Algorithm 1 steps 2-3 as a multi-shift
+// solver, the estimator output, and a cheap P^-1 v; Section 1: Hutchinson).
+//
+// P = D + U diag(lam) U^T is stored as F = D^-1 U L^-T and D^-1, with
+// L L^T = diag(1/lam) + U^T D^-1 U, so P^-1 R = D^-1 R - F (F^T R).
+//
+// The solver runs CG on A = M P^-1 + a_1 I in the inner product <x, y> =
+// x^T P^-1 y, in which M P^-1 is self-adjoint (the paper runs Lanczos on
+// M P^-1; this is the inner product that makes that well defined).  One CG
+// per probe column, all columns of the block in lock step; each column has
+// its own alpha, beta.  Per iteration:
+//   q = M w + a_1 p        (w = P^-1 p)          kernel matmat + epilogue
+//   alpha = rho / w^T q
+//   r -= alpha q ; u = P^-1 r ; rho' = r^T u ; beta = rho' / rho
+//   p = r + beta p ; w = u + beta w
+// The shifted systems (M P^-1 + a_j I) x_j = z share the Krylov space; their
+// residuals are zeta_j r, with Jegerlehner's recurrences for zeta_j,
+// alpha_j, beta_j.  Only the scalars z^T x_j are needed by the estimator, and
+// z^T x_j, z^T p_j follow from the scalar z^T r per column:
+//   z^T x_j += alpha_j z^T p_j ;  z^T p_j = zeta_j z^T r + beta_j z^T p_j,
+// so no n-vector is kept per shift.  All scalars are FP64.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "ld_common.hpp"
+
+namespace ld {
+namespace {
+
+constexpr int WT = 64;  // Woodbury tile (rows of F / columns of R)
+constexpr int WR = 16;  // rows staged per step
+
+// t_partial[c] = F_c^T R_c over row chunk c: output rank x s, FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ft_partial(const T* __restrict__ F,
+                                                    const T* __restrict__ R, int64_t n, int rank,
+                                                    int64_t s, int64_t chunk,
+                                                    double* __restrict__ part) {
+  __shared__ double Fs[WR][WT + 1];
+  __shared__ double Rs[WR][WT + 1];
+  const int tid = threadIdx.x;
+  const int ti = tid / 16, tj = tid % 16;
+  const int l0 = blockIdx.y * WT;
+  const int64_t c0 = (int64_t)blockIdx.z * WT;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  int64_t r1 = r0 + chunk;
+  if (r1 > n) r1 = n;
+  double acc[4][4] = {};
+  for (int64_t rb = r0; rb < r1; rb += WR) {
+    __syncthreads();
+    for (int e = tid; e < WR * WT; e += 256) {
+      const int rr = e / WT, cc = e % WT;
+      const int64_t row = rb + rr;
+      double fv = 0.0, rv = 0.0;
+      if (row < r1) {
+        if (l0 + cc < rank) fv = (double)F[row * rank + l0 + cc];
+        if (c0 + cc < s) rv = (double)R[row * s + c0 + cc];
+      }
+      Fs[rr][cc] = fv;
+      Rs[rr][cc] = rv;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < WR; ++rr) {
+      double a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = Fs[rr][ti + 16 * q];
+        b[q] = Rs[rr][tj + 16 * q];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+    }
+  }
+  double* dst = part + (int64_t)blockIdx.x * rank * s;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int l = l0 + ti + 16 * x;
+      const int64_t c = c0 + tj + 16 * y;
+      if (l < rank && c < s) dst[(int64_t)l * s + c] = acc[x][y];
+    }
+}
+
+__global__ void k_sum_parts(const double* __restrict__ part, int chunks, int64_t count,
+                            double* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * 256) {
+    double s = 0.0;
+    for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * count + e];
+    out[e] = s;
+  }
+}
+
+// OUT = Dinv .* R - F t (t: rank x s FP64), 64 x 64 tile per workgroup.
+// Optional per-row-tile column dots: dot1 = sum R .* OUT, dot2 = sum Z .* R.
+template <typename T>
+__global__ __launch_bounds__(256) void k_wood_out(const T* __restrict__ F,
+                                                  const T* __restrict__ Dinv,
+                                                  const double* __restrict__ t,
+                                                  const T* __restrict__ R, int64_t n, int rank,
+                                                  int64_t s, T* __restrict__ OUT,
+                                                  const T* __restrict__ Z,
+                                                  double* __restrict__ dot1,
+                                                  double* __restrict__ dot2) {
+  __shared__ double Fs[WT][WR + 1];
+  __shared__ double Ts[WR][WT + 1];
+  __shared__ double red1[16][WT + 1];
+  __shared__ double red2[16][WT + 1];
+  const int tid = threadIdx.x;
+  const int ti = tid / 16, tj = tid % 16;
+  const int64_t i0 = (int64_t)blockIdx.x * WT;
+  const int64_t c0 = (int64_t)blockIdx.y * WT;
+  double acc[4][4] = {};
+  for (int l0 = 0; l0 < rank; l0 += WR) {
+    __syncthreads();
+    for (int e = tid; e < WT * WR; e += 256) {
+      const int rr = e / WR, ll = e % WR;
+      const int64_t row = i0 + rr;
+      Fs[rr][ll] = (row < n && l0 + ll < rank) ? (double)F[row * rank + l0 + ll] : 0.0;
+    }
+    for (int e = tid; e < WR * WT; e += 256) {
+      const int ll = e / WT, cc = e % WT;
+      Ts[ll][cc] = (l0 + ll < rank && c0 + cc < s) ? t[(int64_t)(l0 + ll) * s + c0 + cc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int ll = 0; ll < WR; ++ll) {
+      double a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = Fs[ti + 16 * q][ll];
+        b[q] = Ts[ll][tj + 16 * q];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+    }
+  }
+  double d1[4] = {}, d2[4] = {};
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int64_t row = i0 + ti + 16 * x;
+    if (row >= n) continue;
+    const double dv = (double)Dinv[row];
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int64_t c = c0 + tj + 16 * y;
+      if (c >= s) continue;
+      const int64_t off = row * s + c;
+      const double rv = (double)R[off];
+      const T o = (T)(dv * rv - acc[x][y]);
+      OUT[off] = o;
+      if (dot1) d1[y] += rv * (double)o;
+      if (dot2) d2[y] += (double)Z[off] * rv;
+    }
+  }
+  if (dot1) {
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      red1[ti][tj + 16 * y] = d1[y];
+      red2[ti][tj + 16 * y] = d2[y];
+    }
+    __syncthreads();
+    if (tid < WT) {
+      double a = 0.0, b = 0.0;
+      for (int q = 0; q < 16; ++q) {
+        a += red1[q][tid];
+        b += red2[q][tid];
+      }
+      const int64_t c = c0 + tid;
+      if (c < s) {
+        dot1[(int64_t)blockIdx.x * s + c] = a;
+        if (dot2) dot2[(int64_t)blockIdx.x * s + c] = b;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ PCG --
+struct Scal {
+  double* rho;
+  double* rho0;
+  double* alpha;
+  double* beta;
+  double* alpha_prev;
+  double* beta_prev;
+  double* ztz;
+  double* zeta;       // J x s
+  double* zeta_prev;  // J x s
+  double* ztp;        // J x s
+  double* ztx;        // J x s
+  int* frozen;        // J x s
+  int* active;        // s
+  int* status;        // [0] = active columns, [1] = breakdown flag
+};
+
+template <typename T>
+__global__ void k_copy2(const T* __restrict__ src, T* __restrict__ a, T* __restrict__ b,
+                        int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * 256) {
+    const T v = src[i];
+    a[i] = v;
+    if (b) b[i] = v;
+  }
+}
+
+__device__ double block_colsum(const double* __restrict__ parts, int nblk, int64_t s, int64_t c) {
+  double acc = 0.0;
+  for (int b = 0; b < nblk; ++b) acc += parts[(int64_t)b * s + c];
+  return acc;
+}
+
+// initial state after u0 = P^-1 z: rho0 = z^T u0 (dots1), ztz = z^T z (dots2)
+__global__ void k_scal_init(Scal S, const double* __restrict__ dots1, const double* __restrict__ dots2,
+                            int nblk, int64_t s, int J) {
+  for (int64_t c = threadIdx.x; c < s; c += blockDim.x) {
+    const double rho = block_colsum(dots1, nblk, s, c);
+    const double ztz = block_colsum(dots2, nblk, s, c);
+    S.rho[c] = rho;
+    S.rho0[c] = rho;
+    S.ztz[c] = ztz;
+    S.alpha[c] = 0.0;
+    S.beta[c] = 0.0;
+    S.alpha_prev[c] = 1.0;
+    S.beta_prev[c] = 0.0;
+    const bool ok = rho > 0.0 && isfinite(rho);
+    S.active[c] = ok ? 1 : 0;
+    if (!ok) atomicOr(&S.status[1], 1);
+    for (int j = 0; j < J; ++j) {
+      S.zeta[j * s + c] = 1.0;
+      S.zeta_prev[j * s + c] = 1.0;
+      S.ztp[j * s + c] = ztz;
+      S.ztx[j * s + c] = 0.0;
+      S.frozen[j * s + c] = 0;
+    }
+  }
+}
+
+__global__ void k_scal_alpha(Scal S, const double* __restrict__ dots, int nblk, int64_t s) {
+  for (int64_t c = threadIdx.x; c < s; c += blockDim.x) {
+    double a = 0.0;
+    if (S.active[c]) {
+      const double wq = block_colsum(dots, nblk, s, c);
+      if (!(wq > 0.0) || !isfinite(wq)) {
+        atomicOr(&S.status[1], 1);
+        S.active[c] = 0;
+      } else {
+        a = S.rho[c] / wq;
+      }
+    }
+    S.alpha[c] = a;
+  }
+}
+
+template <typename T>
+__global__ void k_update_r(T* __restrict__ r, const T* __restrict__ q, const double* __restrict__ alpha,
+                           int64_t n, int64_t s) {
+  const int64_t total = n * s;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * 256) {
+    const int64_t c = i % s;
+    r[i] = (T)((double)r[i] - alpha[c] * (double)q[i]);
+  }
+}
+
+// rho' = r^T u (dots1), z^T r (dots2); beta; shifted recurrences; convergence.
+__global__ void k_scal_beta(Scal S, const double* __restrict__ dots1, const double* __restrict__ dots2,
+                            int nblk, int64_t s, int J, const double* __restrict__ delta, double tol) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int64_t c = threadIdx.x; c < s; c += blockDim.x) {
+    if (!S.active[c]) {
+      S.beta[c] = 0.0;
+      continue;
+    }
+    const double rho_new = block_colsum(dots1, nblk, s, c);
+    const double ztr = block_colsum(dots2, nblk, s, c);
+    if (!(rho_new >= 0.0) || !isfinite(rho_new)) {
+      atomicOr(&S.status[1], 1);
+      S.active[c] = 0;
+      S.beta[c] = 0.0;
+      continue;
+    }
+    const double alpha = S.alpha[c];
+    const double beta = rho_new / S.rho[c];
+    const double ap = S.alpha_prev[c], bp = S.beta_prev[c];
+    const double rel = sqrt(rho_new / S.rho0[c]);
+    for (int j = 0; j < J; ++j) {
+      const int64_t o = (int64_t)j * s + c;
+      if (S.frozen[o]) continue;
+      const double z = S.zeta[o], zp = S.zeta_prev[o];
+      const double zn = z * zp * ap / (ap * zp * (1.0 + alpha * delta[j]) + alpha * bp * (zp - z));
+      const double ratio = zn / z;
+      const double aj = alpha * ratio;
+      const double bj = beta * ratio * ratio;
+      S.ztx[o] += aj * S.ztp[o];
+      S.ztp[o] = zn * ztr + bj * S.ztp[o];
+      S.zeta_prev[o] = z;
+      S.zeta[o] = zn;
+      if (!isfinite(zn) || fabs(zn) * rel < 1e-2 * tol || fabs(zn) < 1e-200) S.frozen[o] = 1;
+    }
+    S.alpha_prev[c] = alpha;
+    S.beta_prev[c] = beta;
+    S.rho[c] = rho_new;
+    if (rel <= tol) {
+      S.active[c] = 0;
+      S.beta[c] = 0.0;
+    } else {
+      S.beta[c] = beta;
+      ++mine;
+    }
+  }
+  atomicAdd(&cnt, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) S.status[0] = cnt;
+}
+
+template <typename T>
+__global__ void k_update_pw(T* __restrict__ p, T* __restrict__ w, const T* __restrict__ r,
+                            const T* __restrict__ u, const double* __restrict__ beta,
+                            const int* __restrict__ active, int64_t n, int64_t s) {
+  const int64_t total = n * s;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * 256) {
+    const int64_t c = i % s;
+    if (!active[c]) continue;
+    const double b = beta[c];
+    p[i] = (T)((double)r[i] + b * (double)p[i]);
+    w[i] = (T)((double)u[i] + b * (double)w[i]);
+  }
+}
+
+int grid1(int64_t count) {
+  int64_t b = (count + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
+}
+
+struct WoodPlan {
+  int64_t chunks, chunk;
+  int ltiles, ctiles;
+  int64_t rtiles;
+};
+
+WoodPlan wood_plan(ld_ctx* ctx, int64_t n, int rank, int64_t s) {
+  WoodPlan w{};
+  w.ltiles = (rank + WT - 1) / WT;
+  w.ctiles = (int)((s + WT - 1) / WT);
+  int64_t chunks = (int64_t)ctx->num_cu * 2 / ((int64_t)w.ltiles * w.ctiles);
+  const int64_t maxc = (n + 255) / 256;
+  if (chunks > maxc) chunks = maxc;
+  if (chunks < 1) chunks = 1;
+  w.chunk = (n + chunks - 1) / chunks;
+  w.chunks = (n + w.chunk - 1) / w.chunk;
+  w.rtiles = (n + WT - 1) / WT;
+  return w;
+}
+
+// P^-1 R into OUT; optional dots per 64-row tile.  Takes its scratch from the arena.
+template <typename T>
+ld_status wood_apply_t(ld_ctx* ctx, const T* F, const T* Dinv, int64_t n, int rank, const T* R,
+                       int64_t s, T* OUT, const T* Z, double* dot1, double* dot2) {
+  WoodPlan w = wood_plan(ctx, n, rank, s);
+  double* part = (double*)ctx->arena.take((size_t)w.chunks * rank * s * sizeof(double));
+  double* t = (double*)ctx->arena.take((size_t)rank * s * sizeof(double));
+  if (!part || !t) return fail(LD_ENOMEM, "woodbury: scratch arena too small");
+  hipStream_t st = ctx->stream;
+  hipLaunchKernelGGL(k_ft_partial<T>, dim3((unsigned)w.chunks, w.ltiles, w.ctiles), dim3(256), 0, st,
+                     F, R, n, rank, s, w.chunk, part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(grid1((int64_t)rank * s)), dim3(256), 0, st, part,
+                     (int)w.chunks, (int64_t)rank * s, t);
+  hipLaunchKernelGGL(k_wood_out<T>, dim3((unsigned)w.rtiles, w.ctiles), dim3(256), 0, st, F, Dinv, t,
+                     R, n, rank, s, OUT, Z, dot1, dot2);
+  LD_HIP(hipGetLastError());
+  return LD_OK;
+}
+
+}  // namespace
+
+size_t woodbury_scratch_bytes(int64_t n, int rank, int64_t s) {
+  // upper bound on chunks: num_cu * 2 <= 1024
+  const int64_t chunks = 1024;
+  (void)n;
+  return (size_t)(chunks + 1) * rank * s * sizeof(double) + 4096;
+}
+
+ld_status woodbury_apply(ld_ctx* ctx, const ld_precond* P, bool f64, const void* R, int64_t s,
+                         void* OUT) {
+  if (f64)
+    return wood_apply_t<double>(ctx, P->F64, P->Dinv64, P->n, P->rank, (const double*)R, s,
+                                (double*)OUT, nullptr, nullptr, nullptr);
+  return wood_apply_t<float>(ctx, P->F32, P->Dinv32, P->n, P->rank, (const float*)R, s,
+                             (float*)OUT, nullptr, nullptr, nullptr);
+}
+
+// --------------------------------------------------------------- driver --
+namespace {
+
+struct PcgOut {
+  int iterations = 0;
+  int converged = 0;
+  double rel_resid = 0.0;
+  bool breakdown = false;
+};
+
+template <typename T>
+ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precond* P,
+                  const double* shifts, int J, const T* Z, int64_t s, double tol, int max_iters,
+                  std::vector<double>& ztx_host, std::vector<double>& ztz_host, PcgOut& res) {
+  const int64_t n = base.n;
+  const size_t vec = (size_t)n * s;
+  hipStream_t st = ctx->stream;
+  const T* F = f64 ? (const T*)P->F64 : (const T*)P->F32;
+  const T* Dinv = f64 ? (const T*)P->Dinv64 : (const T*)P->Dinv32;
+  T* r = (T*)ctx->arena.take(vec * sizeof(T));
+  T* u = (T*)ctx->arena.take(vec * sizeof(T));
+  T* p = (T*)ctx->arena.take(vec * sizeof(T));
+  T* w = (T*)ctx->arena.take(vec * sizeof(T));
+  T* q = (T*)ctx->arena.take(vec * sizeof(T));
+  const int64_t mrt = (n + 127) / 128;  // matmat dot blocks (128-row tiles)
+  const int64_t wrt = (n + 63) / 64;    // woodbury dot blocks (64-row tiles)
+  double* dwq = (double*)ctx->arena.take((size_t)mrt * s * sizeof(double));
+  double* d1 = (double*)ctx->arena.take((size_t)wrt * s * sizeof(double));
+  double* d2 = (double*)ctx->arena.take((size_t)wrt * s * sizeof(double));
+  double* scal = (double*)ctx->arena.take((size_t)(7 * s + 4 * J * s + J) * sizeof(double));
+  int* iscal = (int*)ctx->arena.take((size_t)(J * s + s + 2) * sizeof(int));
+  if (!r || !u || !p || !w || !q || !dwq || !d1 || !d2 || !scal || !iscal)
+    return fail(LD_ENOMEM, "pcg: scratch arena too small");
+  Scal S;
+  S.rho = scal;
+  S.rho0 = scal + s;
+  S.alpha = scal + 2 * s;
+  S.beta = scal + 3 * s;
+  S.alpha_prev = scal + 4 * s;
+  S.beta_prev = scal + 5 * s;
+  S.ztz = scal + 6 * s;
+  S.zeta = scal + 7 * s;
+  S.zeta_prev = S.zeta + J * s;
+  S.ztp = S.zeta_prev + J * s;
+  S.ztx = S.ztp + J * s;
+  double* delta = S.ztx + J * s;
+  S.frozen = iscal;
+  S.active = iscal + J * s;
+  S.status = iscal + J * s + s;
+
+  std::vector<double> dl(J);
+  for (int j = 0; j < J; ++j) dl[j] = shifts[j] - shifts[0];
+  LD_TRY(ensure_pinned(ctx, (size_t)(2 * J * s + 2 * s + 8)));
+  std::copy(dl.begin(), dl.end(), ctx->pinned);
+  LD_HIP(hipMemcpyAsync(delta, ctx->pinned, J * sizeof(double), hipMemcpyHostToDevice, st));
+  LD_HIP(hipMemsetAsync(S.status, 0, 2 * sizeof(int), st));
+  // wait for the small upload before the pinned buffer is reused below
+  LD_HIP(hipStreamSynchronize(st));
+
+  // The arena top after the persistent buffers: the scratch of each matmat /
+  // Woodbury call is taken from here and handed back once its consumer is
+  // enqueued (stream order keeps the reuse safe).
+  const size_t mark = ctx->arena.top;
+
+  // r = z, p = z; u = P^-1 r, w = u; rho0 = r^T u; z^T z
+  hipLaunchKernelGGL(k_copy2<T>, dim3(grid1(vec)), dim3(256), 0, st, Z, r, p, (int64_t)vec);
+  LD_TRY(wood_apply_t<T>(ctx, F, Dinv, n, P->rank, r, s, u, Z, d1, d2));
+  ctx->arena.top = mark;
+  hipLaunchKernelGGL(k_copy2<T>, dim3(grid1(vec)), dim3(256), 0, st, u, w, (T*)nullptr,
+                     (int64_t)vec);
+  hipLaunchKernelGGL(k_scal_init, dim3(1), dim3(256), 0, st, S, d1, d2, (int)wrt, s, J);
+  LD_HIP(hipGetLastError());
+
+  const int check_every = n >= 16384 ? 1 : 8;
+  int it = 0;
+  int active = (int)s;
+  while (it < max_iters && active > 0) {
+    const int todo = std::min(check_every, max_iters - it);
+    for (int k = 0; k < todo; ++k) {
+      ctx->arena.top = mark;
+      MatmatArgs a = base;
+      a.s = s;
+      a.V = w;
+      a.Y = q;
+      a.X2 = p;
+      a.alpha2 = shifts[0];
+      a.dots = dwq;
+      a.timed = true;
+      int nb = 0;
+      a.dot_blocks = &nb;
+      LD_TRY(matmat(ctx, f64, a));
+      hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(256), 0, st, S, dwq, nb, s);
+      hipLaunchKernelGGL(k_update_r<T>, dim3(grid1(vec)), dim3(256), 0, st, r, q, S.alpha, n, s);
+      ctx->arena.top = mark;
+      LD_TRY(wood_apply_t<T>(ctx, F, Dinv, n, P->rank, r, s, u, Z, d1, d2));
+      hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(256), 0, st, S, d1, d2, (int)wrt, s, J, delta,
+                         tol);
+      hipLaunchKernelGGL(k_update_pw<T>, dim3(grid1(vec)), dim3(256), 0, st, p, w, r, u, S.beta,
+                         S.active, n, s);
+      LD_HIP(hipGetLastError());
+      ++it;
+    }
+    LD_HIP(hipMemcpyAsync(ctx->pinned, S.status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    LD_HIP(hipStreamSynchronize(st));
+    timing_collect(ctx);
+    const int* stt = (const int*)ctx->pinned;
+    active = stt[0];
+    if (stt[1]) res.breakdown = true;
+  }
+  ctx->arena.top = mark;
+  res.iterations = it;
+
+  // read back z^T x_j, z^T z, rho, rho0, active
+  double* hp = ctx->pinned;
+  LD_HIP(hipMemcpyAsync(hp, S.ztx, (size_t)J * s * sizeof(double), hipMemcpyDeviceToHost, st));
+  LD_HIP(hipMemcpyAsync(hp + J * s, S.ztz, s * sizeof(double), hipMemcpyDeviceToHost, st));
+  LD_HIP(hipMemcpyAsync(hp + J * s + s, S.rho, s * sizeof(double), hipMemcpyDeviceToHost, st));
+  LD_HIP(hipMemcpyAsync(hp + J * s + 2 * s, S.rho0, s * sizeof(double), hipMemcpyDeviceToHost, st));
+  LD_HIP(hipStreamSynchronize(st));
+  ztx_host.assign(hp, hp + J * s);
+  ztz_host.assign(hp + J * s, hp + J * s + s);
+  double worst = 0.0;
+  int conv = 0;
+  for (int64_t c = 0; c < s; ++c) {
+    const double rr = std::sqrt(std::max(0.0, hp[J * s + s + c] / hp[J * s + 2 * s + c]));
+    worst = std::max(worst, rr);
+    if (rr <= tol) ++conv;
+  }
+  res.rel_resid = worst;
+  res.converged = conv;
+  return LD_OK;
+}
+
+}  // namespace
+
+ld_status multishift_pcg(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precond* P,
+                         const double* shifts, int J, const void* Z, int64_t s, double tol,
+                         int max_iters, std::vector<double>& ztx, std::vector<double>& ztz,
+                         int* iterations, int* converged, double* rel_resid, bool* breakdown) {
+  PcgOut o;
+  ld_status stt;
+  if (f64)
+    stt = pcg_run<double>(ctx, true, base, P, shifts, J, (const double*)Z, s, tol, max_iters, ztx,
+                          ztz, o);
+  else
+    stt = pcg_run<float>(ctx, false, base, P, shifts, J, (const float*)Z, s, tol, max_iters, ztx,
+                         ztz, o);
+  *iterations = o.iterations;
+  *converged = o.converged;
+  *rel_resid = o.rel_resid;
+  *breakdown = o.breakdown;
+  return stt;
+}
+
+size_t pcg_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int rank, int64_t s, int J) {
+  const size_t es = f64 ? 8 : 4;
+  size_t b = 5 * (size_t)n * s * es + 1280;
+  b += ((n + 127) / 128 + 2 * ((n + 63) / 64)) * (size_t)s * 8 + 768;
+  b += (size_t)(7 * s + 4 * J * s + J) * 8 + (size_t)(J * s + s + 2) * 4 + 512;
+  b += std::max(matmat_scratch_bytes(ctx, f64, n, s), woodbury_scratch_bytes(n, rank, s)) + 1024;
+  return b;
+}
+
+}  // namespace ld

@@ -114,3 +114,24 @@ def per_shift_cg(matvec, precond, z, shift: float, tol: float = 1e-13, maxiter: 
         p = u + (rho_new / rho) * p
         rho = rho_new
     return y
+
+
+def logdet_exact_blocked(M, block: int = 2048) -> float:
+    """log det M by a right-looking blocked Cholesky that overwrites M
+    (lower triangle), for matrices too large for a single LAPACK call.  The
+    same factorization as logdet_exact, organised by blocks."""
+    n = M.shape[0]
+    total = 0.0
+    for k0 in range(0, n, block):
+        k1 = min(n, k0 + block)
+        Lkk = np.linalg.cholesky(M[k0:k1, k0:k1])
+        total += 2.0 * float(np.sum(np.log(np.diag(Lkk))))
+        if k1 == n:
+            break
+        # panel below the diagonal block: M[k1:, k0:k1] Lkk^-T
+        panel = sla.solve_triangular(Lkk, M[k1:, k0:k1].T, lower=True, check_finite=False).T
+        # trailing update of the lower triangle, one column block at a time
+        for j0 in range(k1, n, block):
+            j1 = min(n, j0 + block)
+            M[j0:, j0:j1] -= panel[j0 - k1:, :] @ panel[j0 - k1:j1 - k1, :].T
+    return total

@@ -265,12 +265,13 @@ int grid1(int64_t count) {
 // then two plain passes).  Y (n x m) is consumed; the basis ends in *Q, which
 // is one of the two buffers Y / W.
 ld_status orthonormalize(ld_ctx* ctx, double* Y, double* W, int64_t n, int m, double* G, double* Rinv,
-                         int* ok_dev, double** Q) {
+                         int* ok_dev, int passes, double** Q) {
   hipStream_t st = ctx->stream;
   double* src = Y;
   double* dst = W;
   const double shift_c = 11.0 * ((double)n * m + (double)m * (m + 1)) * 0x1.0p-53;
-  for (int pass = 0; pass < 3; ++pass) {
+  LD_HIP(hipMemsetAsync(ok_dev, 0, sizeof(int), st));
+  for (int pass = 0; pass < passes; ++pass) {
     const size_t mark = ctx->arena.top;
     LD_TRY(gram64(ctx, src, src, nullptr, n, m, G));
     ctx->arena.top = mark;  // partials are consumed by the reduction already enqueued
@@ -284,7 +285,7 @@ ld_status orthonormalize(ld_ctx* ctx, double* Y, double* W, int64_t n, int m, do
   LD_TRY(ensure_pinned(ctx, 1));
   LD_HIP(hipMemcpyAsync(ctx->pinned, ok_dev, sizeof(int), hipMemcpyDeviceToHost, st));
   LD_HIP(hipStreamSynchronize(st));
-  if (*(int*)ctx->pinned != 1)
+  if (*(int*)ctx->pinned != 0)
     return fail(LD_ENOTSPD, "CholeskyQR breakdown: sketch Gram matrix not positive definite");
   *Q = src;
   return LD_OK;
@@ -351,12 +352,14 @@ ld_status build_precond(ld_ctx* ctx, const ld_operator* op, int rank, int oversa
   launch_fill_gaussian(st, stream_key(seed, kStreamOmega), n, m, Qb);
   LD_TRY(apply_M64(ctx, op, Xp, Qb, Yb, m, t1, t2));
   double* Q = nullptr;
-  LD_TRY(orthonormalize(ctx, Yb, Qb, n, m, G, Rinv, okd, &Q));
+  // intermediate bases only need to span the sketch (one shifted pass); the
+  // basis used for the Rayleigh-Ritz step is made orthonormal (three passes)
+  LD_TRY(orthonormalize(ctx, Yb, Qb, n, m, G, Rinv, okd, power_iters == 0 ? 3 : 1, &Q));
   // 3. subspace iterations
   for (int it = 0; it < power_iters; ++it) {
     double* other = (Q == Qb) ? Yb : Qb;
     LD_TRY(apply_M64(ctx, op, Xp, Q, other, m, t1, t2));
-    LD_TRY(orthonormalize(ctx, other, Q, n, m, G, Rinv, okd, &Q));
+    LD_TRY(orthonormalize(ctx, other, Q, n, m, G, Rinv, okd, it + 1 == power_iters ? 3 : 1, &Q));
   }
   // 4. B = Q^T M Q and its eigenpairs
   double* MQ = (Q == Qb) ? Yb : Qb;
@@ -425,6 +428,7 @@ ld_status build_precond(ld_ctx* ctx, const ld_operator* op, int rank, int oversa
     if (s_ != LD_OK) return bail(s_);
   }
   hipLaunchKernelGGL(k_add_diag_inv, dim3(grid1(rank)), dim3(256), 0, st, G, P->lam, rank);
+  if (hipMemsetAsync(okd, 0, sizeof(int), st) != hipSuccess) return bail(fail(LD_EHIP, "memset failed"));
   launch_cholesky_upper(st, G, rank, okd);
   double* parts = evals;  // reuse: 3 doubles
   hipLaunchKernelGGL(k_logdet_parts, dim3(1), dim3(256), 0, st, P->D, n, P->lam, G, rank, parts);
@@ -438,7 +442,7 @@ ld_status build_precond(ld_ctx* ctx, const ld_operator* op, int rank, int oversa
       hipMemcpyAsync(ctx->pinned + 4, okd, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return bail(fail(LD_EHIP, "readback of log det P failed"));
-  if (*(int*)(ctx->pinned + 4) != 1)
+  if (*(int*)(ctx->pinned + 4) != 0)
     return bail(fail(LD_ENOTSPD, "capacitance matrix Cholesky breakdown"));
   P->logdet = ctx->pinned[0] + ctx->pinned[1] + ctx->pinned[2];
   if (!std::isfinite(P->logdet)) return bail(fail(LD_ENOTSPD, "log det P is not finite"));

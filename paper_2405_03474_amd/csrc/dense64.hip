@@ -81,56 +81,209 @@ __global__ void k_sum_chunks(const double* __restrict__ part, int chunks, int64_
 }
 
 // -------------------------------------------------------------- Cholesky --
-// Right-looking, one workgroup, in place on the upper triangle: G = R^T R.
-__global__ __launch_bounds__(1024) void k_cholesky_upper(double* __restrict__ G, int m,
-                                                         int* __restrict__ ok) {
-  __shared__ double piv;
+// Blocked right-looking Cholesky G = R^T R (R upper) in one workgroup of 512
+// threads, 64 x 64 blocks staged in LDS: factor the diagonal block, solve the
+// block row R_kk^T X = G_k,: (one column per thread, X in registers), then
+// subtract R_k,I^T R_k,J from every trailing upper tile (I <= J).
+constexpr int CB = 64;
+constexpr int CT = 512;
+
+__global__ __launch_bounds__(CT) void k_cholesky_upper(double* __restrict__ G, int m,
+                                                       int* __restrict__ fail_flag) {
+  __shared__ double Dk[CB][CB + 1];
+  __shared__ double PI[CB][CB + 1];
+  __shared__ double PJ[CB][CB + 1];
   __shared__ int bad;
   const int tid = threadIdx.x;
   if (tid == 0) bad = 0;
-  __syncthreads();
-  for (int k = 0; k < m; ++k) {
-    if (tid == 0) {
-      const double dkk = G[(int64_t)k * m + k];
-      if (!(dkk > 0.0) || !isfinite(dkk)) {
-        bad = 1;
-        piv = 1.0;
-      } else {
-        piv = sqrt(dkk);
+  const int nb = (m + CB - 1) / CB;
+  for (int kb = 0; kb < nb; ++kb) {
+    const int k0 = kb * CB;
+    const int w = m - k0 < CB ? m - k0 : CB;
+    __syncthreads();
+    for (int e = tid; e < CB * CB; e += CT) {
+      const int a = e / CB, b = e % CB;
+      Dk[a][b] = (a < w && b < w && b >= a) ? G[(int64_t)(k0 + a) * m + k0 + b] : 0.0;
+    }
+    __syncthreads();
+    // unblocked factorization of the diagonal block
+    for (int j = 0; j < w; ++j) {
+      if (tid == 0) {
+        const double d = Dk[j][j];
+        if (!(d > 0.0) || !isfinite(d)) {
+          bad = 1;
+          Dk[j][j] = 1.0;
+        } else {
+          Dk[j][j] = sqrt(d);
+        }
       }
-      G[(int64_t)k * m + k] = piv;
+      __syncthreads();
+      const double inv = 1.0 / Dk[j][j];
+      for (int t = j + 1 + tid; t < w; t += CT) Dk[j][t] *= inv;
+      __syncthreads();
+      const int rem = w - j - 1;
+      for (int e = tid; e < rem * rem; e += CT) {
+        const int a = j + 1 + e / rem, b = j + 1 + e % rem;
+        if (b >= a) Dk[a][b] -= Dk[j][a] * Dk[j][b];
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < CB * CB; e += CT) {
+      const int a = e / CB, b = e % CB;
+      if (a < w && b < w) G[(int64_t)(k0 + a) * m + k0 + b] = b >= a ? Dk[a][b] : 0.0;
+    }
+    const int k1 = k0 + w;
+    if (k1 >= m) break;
+    // block row: R_kk^T x = g for every column right of the block
+    for (int c = k1 + tid; c < m; c += CT) {
+      double x[CB];
+#pragma unroll
+      for (int i = 0; i < CB; ++i) {
+        if (i < w) {
+          double v = G[(int64_t)(k0 + i) * m + c];
+#pragma unroll
+          for (int t = 0; t < i; ++t) v -= Dk[t][i] * x[t];
+          x[i] = v / Dk[i][i];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < CB; ++i)
+        if (i < w) G[(int64_t)(k0 + i) * m + c] = x[i];
     }
     __syncthreads();
-    const double inv = 1.0 / piv;
-    for (int j = k + 1 + tid; j < m; j += blockDim.x) G[(int64_t)k * m + j] *= inv;
-    __syncthreads();
-    const int rem = m - k - 1;
-    const int64_t tri = (int64_t)rem * rem;
-    for (int64_t e = tid; e < tri; e += blockDim.x) {
-      const int i = k + 1 + (int)(e / rem), j = k + 1 + (int)(e % rem);
-      if (j >= i) G[(int64_t)i * m + j] -= G[(int64_t)k * m + i] * G[(int64_t)k * m + j];
+    // trailing update of the upper triangle
+    const int nt = (m - k1 + CB - 1) / CB;
+    for (int ti = 0; ti < nt; ++ti) {
+      for (int tj = ti; tj < nt; ++tj) {
+        const int I0 = k1 + ti * CB, J0 = k1 + tj * CB;
+        __syncthreads();
+        for (int e = tid; e < CB * CB; e += CT) {
+          const int t = e / CB, a = e % CB;
+          PI[t][a] = (t < w && I0 + a < m) ? G[(int64_t)(k0 + t) * m + I0 + a] : 0.0;
+          PJ[t][a] = (t < w && J0 + a < m) ? G[(int64_t)(k0 + t) * m + J0 + a] : 0.0;
+        }
+        __syncthreads();
+        // 8 outputs per thread: rows a0, a0 + 32; columns b0 + 16 q
+        const int a0 = tid / 16, b0 = tid % 16;
+        double acc[2][4] = {};
+        for (int t = 0; t < w; ++t) {
+          const double p0 = PI[t][a0], p1 = PI[t][a0 + 32];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const double pj = PJ[t][b0 + 16 * q];
+            acc[0][q] = fma(p0, pj, acc[0][q]);
+            acc[1][q] = fma(p1, pj, acc[1][q]);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int i = I0 + a0 + 32 * r, j = J0 + b0 + 16 * q;
+            if (i < m && j < m && j >= i) G[(int64_t)i * m + j] -= acc[r][q];
+          }
+      }
     }
-    __syncthreads();
   }
-  // zero the strict lower triangle
-  for (int64_t e = tid; e < (int64_t)m * m; e += blockDim.x) {
+  __syncthreads();
+  for (int64_t e = tid; e < (int64_t)m * m; e += CT) {
     const int i = (int)(e / m), j = (int)(e % m);
     if (j < i) G[e] = 0.0;
   }
-  if (tid == 0) *ok = bad ? 0 : 1;
+  if (tid == 0 && bad) *fail_flag = 1;
 }
 
 // ------------------------------------------------- upper triangular inverse --
-// Column j of R^-1 by back substitution, one thread per column.
-__global__ __launch_bounds__(64) void k_tri_inv_upper(const double* __restrict__ R, int m,
+// X = R^-1 for upper-triangular R, one workgroup: the 64 x 64 diagonal block
+// inverses first (back substitution, one column per thread, in LDS), then for
+// each block column j and block row i < j (bottom up)
+//   X_ij = -X_ii (sum_{k=i+1..j} R_ik X_kj).
+__global__ __launch_bounds__(CT) void k_tri_inv_upper(const double* __restrict__ R, int m,
                                                       double* __restrict__ X) {
-  const int j = blockIdx.x * 64 + threadIdx.x;
-  if (j >= m) return;
-  for (int i = m - 1; i > j; --i) X[(int64_t)i * m + j] = 0.0;
-  for (int i = j; i >= 0; --i) {
-    double s = (i == j) ? 1.0 : 0.0;
-    for (int k = i + 1; k <= j; ++k) s -= R[(int64_t)i * m + k] * X[(int64_t)k * m + j];
-    X[(int64_t)i * m + j] = s / R[(int64_t)i * m + i];
+  __shared__ double Ta[CB][CB + 1];
+  __shared__ double Tb[CB][CB + 1];
+  __shared__ double Acc[CB][CB + 1];
+  const int tid = threadIdx.x;
+  const int nb = (m + CB - 1) / CB;
+  for (int64_t e = tid; e < (int64_t)m * m; e += CT) X[e] = 0.0;
+  __syncthreads();
+  // diagonal blocks
+  for (int ib = 0; ib < nb; ++ib) {
+    const int i0 = ib * CB;
+    const int w = m - i0 < CB ? m - i0 : CB;
+    __syncthreads();
+    for (int e = tid; e < CB * CB; e += CT) {
+      const int a = e / CB, b = e % CB;
+      Ta[a][b] = (a < w && b < w) ? R[(int64_t)(i0 + a) * m + i0 + b] : 0.0;
+    }
+    __syncthreads();
+    if (tid < w) {
+      const int c = tid;
+      for (int i = c; i >= 0; --i) {
+        double v = (i == c) ? 1.0 : 0.0;
+        for (int t = i + 1; t <= c; ++t) v -= Ta[i][t] * Tb[t][c];
+        Tb[i][c] = v / Ta[i][i];
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < CB * CB; e += CT) {
+      const int a = e / CB, b = e % CB;
+      if (a < w && b < w && b >= a) X[(int64_t)(i0 + a) * m + i0 + b] = Tb[a][b];
+    }
+  }
+  __syncthreads();
+  const int a0 = tid / 16, b0 = tid % 16;
+  for (int jb = 1; jb < nb; ++jb) {
+    const int j0 = jb * CB;
+    const int wj = m - j0 < CB ? m - j0 : CB;
+    for (int ib = jb - 1; ib >= 0; --ib) {
+      const int i0 = ib * CB;
+      double acc[2][4] = {};
+      // T = sum_k R_ik X_kj
+      for (int kb = ib + 1; kb <= jb; ++kb) {
+        const int kk0 = kb * CB;
+        const int wk = m - kk0 < CB ? m - kk0 : CB;
+        __syncthreads();
+        for (int e = tid; e < CB * CB; e += CT) {
+          const int a = e / CB, b = e % CB;
+          Ta[a][b] = (b < wk) ? R[(int64_t)(i0 + a) * m + kk0 + b] : 0.0;
+          Tb[a][b] = (a < wk && b < wj) ? X[(int64_t)(kk0 + a) * m + j0 + b] : 0.0;
+        }
+        __syncthreads();
+        for (int t = 0; t < CB; ++t) {
+          const double r0 = Ta[a0][t], r1 = Ta[a0 + 32][t];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const double xv = Tb[t][b0 + 16 * q];
+            acc[0][q] = fma(r0, xv, acc[0][q]);
+            acc[1][q] = fma(r1, xv, acc[1][q]);
+          }
+        }
+      }
+      __syncthreads();
+      for (int r = 0; r < 2; ++r)
+        for (int q = 0; q < 4; ++q) Acc[a0 + 32 * r][b0 + 16 * q] = acc[r][q];
+      for (int e = tid; e < CB * CB; e += CT) {
+        const int a = e / CB, b = e % CB;
+        Ta[a][b] = X[(int64_t)(i0 + a) * m + i0 + b];  // X_ii (upper, zero below)
+      }
+      __syncthreads();
+      double out[2][4] = {};
+      for (int t = 0; t < CB; ++t) {
+        const double x0 = Ta[a0][t], x1 = Ta[a0 + 32][t];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double av = Acc[t][b0 + 16 * q];
+          out[0][q] = fma(x0, av, out[0][q]);
+          out[1][q] = fma(x1, av, out[1][q]);
+        }
+      }
+      for (int r = 0; r < 2; ++r)
+        for (int q = 0; q < 4; ++q) {
+          const int j = j0 + b0 + 16 * q;
+          if (j - j0 < wj) X[(int64_t)(i0 + a0 + 32 * r) * m + j] = -out[r][q];
+        }
+    }
   }
 }
 
@@ -364,11 +517,11 @@ ld_status gram64(ld_ctx* ctx, const double* A, const double* B, const double* w,
 }
 
 void launch_cholesky_upper(hipStream_t st, double* G, int m, int* ok) {
-  hipLaunchKernelGGL(k_cholesky_upper, dim3(1), dim3(1024), 0, st, G, m, ok);
+  hipLaunchKernelGGL(k_cholesky_upper, dim3(1), dim3(CT), 0, st, G, m, ok);
 }
 
 void launch_tri_inv_upper(hipStream_t st, const double* R, int m, double* Rinv) {
-  hipLaunchKernelGGL(k_tri_inv_upper, dim3((m + 63) / 64), dim3(64), 0, st, R, m, Rinv);
+  hipLaunchKernelGGL(k_tri_inv_upper, dim3(1), dim3(CT), 0, st, R, m, Rinv);
 }
 
 void launch_gemm64(hipStream_t st, const double* A, const double* B, int ldb, const double* rs,

@@ -150,8 +150,9 @@ void launch_convert_f32_to_f64(hipStream_t st, const float* in, double* out, int
 ld_status gram64(ld_ctx* ctx, const double* A, const double* B, const double* w, int64_t n, int m,
                  double* G);
 // in-place upper Cholesky G = R^T R (m x m); writes R (upper, zero below);
-// *ok = 1 on success (pivot > 0 everywhere), 0 on breakdown (device int).
-void launch_cholesky_upper(hipStream_t st, double* G, int m, int* ok);
+// sets the device int *fail_flag to 1 on breakdown (a pivot <= 0 or not
+// finite) and leaves it untouched otherwise.
+void launch_cholesky_upper(hipStream_t st, double* G, int m, int* fail_flag);
 // Rinv = R^-1 for upper-triangular R (m x m)
 void launch_tri_inv_upper(hipStream_t st, const double* R, int m, double* Rinv);
 // C (n x N) = diag(rs) A (n x K) B (K x N, row stride ldb); rs may be null.

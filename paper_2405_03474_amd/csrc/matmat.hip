@@ -191,6 +191,154 @@ __global__ __launch_bounds__(256, 2) void k_mm32(const float* __restrict__ A,
   }
 }
 
+// ------------------------------------------------- FP32 stored, pipelined --
+// The stored-matrix FP32 product is an HBM stream of M: each stage's tiles
+// are fetched into registers one stage ahead (the loads fly while the
+// previous stage's MFMAs run) and LDS is double buffered, so a stage costs
+// one barrier.
+template <int NB>
+struct StTile {
+  float4 a[4];        // 128 x 32 A tile: 1024 float4 / 256 threads
+  float4 b[NB];       // 32 x 32*NB B tile: 256*NB float4 / 256 threads
+};
+
+template <int NB>
+__device__ __forceinline__ void st_load(StTile<NB>& t, const float* __restrict__ A,
+                                        const float* __restrict__ V, int64_t n, int64_t s,
+                                        int64_t i0, int64_t c0, int64_t k0, int tid, bool a_vec,
+                                        bool b_vec) {
+  constexpr int NT = 32 * NB;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int e = tid + 256 * j;
+    const int rr = e >> 3, kq = e & 7;
+    const int64_t row = i0 + rr, kc = k0 + 4 * kq;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (row < n) {
+      const float* src = A + row * n + kc;
+      if (a_vec && kc + 3 < n) {
+        typedef float f32x4 __attribute__((ext_vector_type(4)));
+        const f32x4 w = __builtin_nontemporal_load((const f32x4*)src);
+        v = make_float4(w.x, w.y, w.z, w.w);
+      } else {
+        if (kc + 0 < n) v.x = src[0];
+        if (kc + 1 < n) v.y = src[1];
+        if (kc + 2 < n) v.z = src[2];
+        if (kc + 3 < n) v.w = src[3];
+      }
+    }
+    t.a[j] = v;
+  }
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int e = tid + 256 * j;
+    const int kk = e / (NT / 4), cq = e % (NT / 4);
+    const int64_t kr = k0 + kk, col = c0 + 4 * cq;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (kr < n) {
+      const float* src = V + kr * s + col;
+      if (b_vec && col + 3 < s) {
+        v = *(const float4*)src;
+      } else {
+        if (col + 0 < s) v.x = src[0];
+        if (col + 1 < s) v.y = src[1];
+        if (col + 2 < s) v.z = src[2];
+        if (col + 3 < s) v.w = src[3];
+      }
+    }
+    t.b[j] = v;
+  }
+}
+
+template <int NB>
+__global__ __launch_bounds__(256, 2) void k_mm32_st(const float* __restrict__ A,
+                                                    const float* __restrict__ V,
+                                                    float* __restrict__ part, SK p) {
+  constexpr int NT = 32 * NB;
+  constexpr int BS = NT + 2;
+  constexpr int AS = BK + 4;
+  __shared__ __attribute__((aligned(16))) float As[2][BM * AS];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BK * BS];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, lh = lane >> 5;
+  const int64_t n = p.n, s = p.s;
+  const bool a_vec = (n & 3) == 0;
+  const bool b_vec = (s & 3) == 0;
+
+  int64_t u, uend;
+  unit_range(p, blockIdx.x, u, uend);
+  int seg = 0;
+  while (u < uend) {
+    const int64_t T = u / p.S;
+    const int st0 = (int)(u - T * p.S);
+    const int st1 = (int)((int64_t)p.S < st0 + (uend - u) ? (int64_t)p.S : st0 + (uend - u));
+    const int rtile = (int)(T % p.rt);
+    const int64_t i0 = (int64_t)rtile * BM;
+    const int64_t c0 = (T / p.rt) * NT;
+
+    f32x16 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
+
+    StTile<NB> tl;
+    st_load<NB>(tl, A, V, n, s, i0, c0, (int64_t)st0 * BK, tid, a_vec, b_vec);
+    __syncthreads();  // the previous segment's last stage is done with both buffers
+    int buf = 0;
+    for (int st = st0; st < st1; ++st) {
+      float* as = As[buf];
+      float* bs = Bs[buf];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int e = tid + 256 * j;
+        *(float4*)&as[(e >> 3) * AS + 4 * (e & 7)] = tl.a[j];
+      }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int e = tid + 256 * j;
+        const int kk = e / (NT / 4), cq = e % (NT / 4);
+        float2* dst = (float2*)&bs[kk * BS + 4 * cq];
+        dst[0] = make_float2(tl.b[j].x, tl.b[j].y);
+        dst[1] = make_float2(tl.b[j].z, tl.b[j].w);
+      }
+      __syncthreads();
+      if (st + 1 < st1)
+        st_load<NB>(tl, A, V, n, s, i0, c0, (int64_t)(st + 1) * BK, tid, a_vec, b_vec);
+      float a[16];
+      const float4* ap = (const float4*)&as[(32 * wave + li) * AS + lh * 16];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 v = ap[q];
+        a[4 * q + 0] = v.x;
+        a[4 * q + 1] = v.y;
+        a[4 * q + 2] = v.z;
+        a[4 * q + 3] = v.w;
+      }
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const float* brow = &bs[(lh * 16 + t) * BS + li];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t], brow[nb * 32], acc[nb], 0, 0, 0);
+      }
+      buf ^= 1;
+    }
+
+    float* dst = part + ((int64_t)blockIdx.x * p.J + seg) * (int64_t)(BM * NT);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 32 * wave + 8 * (r >> 2) + 4 * lh + (r & 3);
+        dst[row * NT + nb * 32 + li] = acc[nb][r];
+      }
+    ++seg;
+    u += st1 - st0;
+  }
+}
+
 // ------------------------------------------------------------ FP64 path --
 template <int NB, bool FLY, int KIND, int DT>
 __global__ __launch_bounds__(256, 2) void k_mm64(const double* __restrict__ A,
@@ -590,11 +738,9 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
     } else {
       const float* A = (const float*)a.A;
       if (NB == 2)
-        hipLaunchKernelGGL((k_mm32<2, false, 0, 1>), grid, dim3(256), 0, st, A, nullptr, 1, 0.f,
-                           0.f, V, P, pl.p);
+        hipLaunchKernelGGL((k_mm32_st<2>), grid, dim3(256), 0, st, A, V, P, pl.p);
       else
-        hipLaunchKernelGGL((k_mm32<1, false, 0, 1>), grid, dim3(256), 0, st, A, nullptr, 1, 0.f,
-                           0.f, V, P, pl.p);
+        hipLaunchKernelGGL((k_mm32_st<1>), grid, dim3(256), 0, st, A, V, P, pl.p);
     }
     if (ev1) LD_HIP(hipEventRecord(ev1, st));
     const int64_t tiles = (int64_t)pl.p.rt * ((a.s + pl.NT - 1) / pl.NT);

@@ -212,6 +212,28 @@ __global__ void k_copy2(const T* __restrict__ src, T* __restrict__ a, T* __restr
   }
 }
 
+// First level of the column reductions: out[seg][c] = sum of parts[b][c]
+// over the seg-th contiguous range of row blocks b (fixed order), so that the
+// single-workgroup scalar kernels add only kSeg values per column.
+constexpr int kSeg = 32;
+
+__global__ __launch_bounds__(256) void k_colsum_seg(const double* __restrict__ parts, int nblk,
+                                                    int64_t s, double* __restrict__ out) {
+  __shared__ double red[4][64];
+  const int cl = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int64_t c = (int64_t)blockIdx.x * 64 + cl;
+  const int seg = blockIdx.y;
+  const int chunk = (nblk + kSeg - 1) / kSeg;
+  const int b0 = seg * chunk;
+  const int b1 = b0 + chunk < nblk ? b0 + chunk : nblk;
+  double acc = 0.0;
+  if (c < s)
+    for (int b = b0 + q; b < b1; b += 4) acc += parts[(int64_t)b * s + c];
+  red[q][cl] = acc;
+  __syncthreads();
+  if (q == 0 && c < s) out[(int64_t)seg * s + c] = ((red[0][cl] + red[1][cl]) + red[2][cl]) + red[3][cl];
+}
+
 __device__ double block_colsum(const double* __restrict__ parts, int nblk, int64_t s, int64_t c) {
   double acc = 0.0;
   for (int b = 0; b < nblk; ++b) acc += parts[(int64_t)b * s + c];
@@ -433,7 +455,9 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
   double* d2 = (double*)ctx->arena.take((size_t)wrt * s * sizeof(double));
   double* scal = (double*)ctx->arena.take((size_t)(7 * s + 4 * J * s + J) * sizeof(double));
   int* iscal = (int*)ctx->arena.take((size_t)(J * s + s + 2) * sizeof(int));
-  if (!r || !u || !p || !w || !q || !dwq || !d1 || !d2 || !scal || !iscal)
+  double* sg1 = (double*)ctx->arena.take((size_t)kSeg * s * sizeof(double));
+  double* sg2 = (double*)ctx->arena.take((size_t)kSeg * s * sizeof(double));
+  if (!r || !u || !p || !w || !q || !dwq || !d1 || !d2 || !scal || !iscal || !sg1 || !sg2)
     return fail(LD_ENOMEM, "pcg: scratch arena too small");
   Scal S;
   S.rho = scal;
@@ -472,7 +496,10 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
   ctx->arena.top = mark;
   hipLaunchKernelGGL(k_copy2<T>, dim3(grid1(vec)), dim3(256), 0, st, u, w, (T*)nullptr,
                      (int64_t)vec);
-  hipLaunchKernelGGL(k_scal_init, dim3(1), dim3(256), 0, st, S, d1, d2, (int)wrt, s, J);
+  const dim3 cs_grid((unsigned)((s + 63) / 64), kSeg);
+  hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, d1, (int)wrt, s, sg1);
+  hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, d2, (int)wrt, s, sg2);
+  hipLaunchKernelGGL(k_scal_init, dim3(1), dim3(256), 0, st, S, sg1, sg2, kSeg, s, J);
   LD_HIP(hipGetLastError());
 
   const int check_every = n >= 16384 ? 1 : 8;
@@ -493,11 +520,14 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
       int nb = 0;
       a.dot_blocks = &nb;
       LD_TRY(matmat(ctx, f64, a));
-      hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(256), 0, st, S, dwq, nb, s);
+      hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, dwq, nb, s, sg1);
+      hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(256), 0, st, S, sg1, kSeg, s);
       hipLaunchKernelGGL(k_update_r<T>, dim3(grid1(vec)), dim3(256), 0, st, r, q, S.alpha, n, s);
       ctx->arena.top = mark;
       LD_TRY(wood_apply_t<T>(ctx, F, Dinv, n, P->rank, r, s, u, Z, d1, d2));
-      hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(256), 0, st, S, d1, d2, (int)wrt, s, J, delta,
+      hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, d1, (int)wrt, s, sg1);
+      hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, d2, (int)wrt, s, sg2);
+      hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(256), 0, st, S, sg1, sg2, kSeg, s, J, delta,
                          tol);
       hipLaunchKernelGGL(k_update_pw<T>, dim3(grid1(vec)), dim3(256), 0, st, p, w, r, u, S.beta,
                          S.active, n, s);
@@ -561,6 +591,7 @@ size_t pcg_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int rank, int64_t s, 
   size_t b = 5 * (size_t)n * s * es + 1280;
   b += ((n + 127) / 128 + 2 * ((n + 63) / 64)) * (size_t)s * 8 + 768;
   b += (size_t)(7 * s + 4 * J * s + J) * 8 + (size_t)(J * s + s + 2) * 4 + 512;
+  b += 2 * (size_t)kSeg * s * 8 + 512;
   b += std::max(matmat_scratch_bytes(ctx, f64, n, s), woodbury_scratch_bytes(n, rank, s)) + 1024;
   return b;
 }

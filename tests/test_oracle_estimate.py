@@ -101,3 +101,11 @@ def test_small_workload_error_within_bias_plus_noise():
     exact = estimate.logdet_exact(M)
     _, bias = estimate.expected_estimate(M, Pd, P.logdet, 3)
     assert abs(est.logdet - exact) <= abs(bias) + 4.0 * est.stderr
+
+
+def test_blocked_cholesky_logdet_matches_lapack():
+    X = np.random.default_rng(20).random((700, 3))
+    M = gp.dense_matrix(gp.MATERN52, X, 0.2, 1.0, 1e-3)
+    ref = oest_ref = estimate.logdet_exact(M)
+    for block in (64, 100, 700):
+        assert estimate.logdet_exact_blocked(M.copy(), block) == pytest.approx(ref, rel=1e-12)

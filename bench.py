@@ -105,9 +105,10 @@ def main():
     ctx = L.Context(0, stream)
     X = torch.as_tensor(cfg.X(), dtype=torch.float64, device=dev).contiguous()
     op = L.GPOperator(X=X, kind=cfg.kind, lengthscale=cfg.lengthscale, variance=cfg.variance,
-                      noise=cfg.noise, precision=prec)
-    Mbuf = torch.empty((cfg.n, cfg.n), dtype=torch.float32 if f32 else torch.float64,
-                       device=dev) if stored else None
+                      noise=cfg.noise, precision=prec,
+                      layout=L.LD_TILED if stored else L.LD_ROW_MAJOR)
+    Mbuf = torch.empty((L.stored_elements(cfg.n, op.layout),),
+                       dtype=torch.float32 if f32 else torch.float64, device=dev) if stored else None
 
     def step():
         out = {}
@@ -166,7 +167,7 @@ def main():
     peak = PEAKS["fp32"] if f32 else PEAKS["fp64"]
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": None,
-                "kernel": "k_mm32<stored> (FP32 MFMA 32x32x2)" if f32 else "k_mm64<on the fly> (FP64 MFMA)",
+                "kernel": "k_mm32_st<2,tiled> (FP32 MFMA 32x32x2)" if f32 else "k_mm64<on the fly> (FP64 MFMA)",
                 "avg_launch_ms": avg_ms, "launches": mm_calls,
                 "hbm_GBps_algorithmic": (mm_bytes / max(mm_calls, 1)) / (avg_ms / 1e3) / 1e9}
 
@@ -178,7 +179,8 @@ def main():
         "config": {"workload": cfg.name, "n": cfg.n, "d": cfg.d,
                    "kernel": "matern52" if cfg.kind == 1 else "rbf",
                    "points": cfg.points, "lengthscale": cfg.lengthscale, "variance": cfg.variance,
-                   "noise": cfg.noise, "storage": "stored" if stored else "on_the_fly",
+                   "noise": cfg.noise,
+                   "storage": "stored_fp32_tiled" if stored else "on_the_fly",
                    "orders": list(cfg.orders), "probes": cfg.probes, "rank": cfg.rank,
                    "oversample": cfg.oversample, "power_iters": cfg.power_iters, "tol": tol},
         "probe_solves_per_s": probe_solves, "iterations": iters, "wall_s": wall,

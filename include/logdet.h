@@ -67,10 +67,25 @@ typedef struct {
   double variance;        /* signal variance, > 0 */
   double noise;           /* noise variance added to the diagonal, >= 0 */
   int32_t precision;      /* ld_precision */
-  const void* M_stored;   /* device n x n matrix M (FP64 for LD_F64, FP32 for
-                             LD_F32, noise included), or NULL to generate
-                             kernel entries on the fly from X */
+  const void* M_stored;   /* device matrix M (FP64 for LD_F64, FP32 for LD_F32,
+                             noise included) in layout `layout`, or NULL to
+                             generate kernel entries on the fly from X */
+  int32_t layout;         /* ld_layout of M_stored (ignored when it is NULL) */
 } ld_operator;
+
+/* Storage layouts of a stored M.
+ *  LD_ROW_MAJOR: n x n, row-major.
+ *  LD_TILED (FP32 only): 128 x 32 tiles, each contiguous and row-major inside;
+ *    tile (I, K) covers rows 128 I .. 128 I + 127 and columns 32 K .. 32 K + 31
+ *    and starts at element (I * ceil(n/32) + K) * 4096, so a band of 128 rows
+ *    is one contiguous stream.  Entries outside n x n are zero.  Element (i, k)
+ *    sits at ((i/128) * ceil(n/32) + k/32) * 4096 + (i%128) * 32 + k%32. */
+typedef enum { LD_ROW_MAJOR = 0, LD_TILED = 1 } ld_layout;
+
+/* Number of elements a stored M of order n occupies in `layout` (n^2 for
+ * LD_ROW_MAJOR; ceil(n/128)*128 * ceil(n/32)*32 for LD_TILED), or -1 for an
+ * invalid argument.  Host only. */
+int64_t ld_stored_elements(int64_t n, int32_t layout);
 
 typedef struct ld_ctx ld_ctx;         /* device, stream, cached scratch memory */
 typedef struct ld_precond ld_precond; /* library-owned preconditioner factors */
@@ -127,8 +142,9 @@ ld_status ld_fill_gaussian(ld_ctx* ctx, uint64_t seed, int32_t stream, int64_t r
  * precision; Y must not alias V.  Asynchronous. */
 ld_status kernel_matmat(ld_ctx* ctx, const ld_operator* op, const void* V, int64_t s, void* Y);
 
-/* Write M = K + noise I (device n x n, FP64 for LD_F64, FP32 for LD_F32) so
- * that it can be passed back as op->M_stored.  op->M_stored is ignored.
+/* Write M = K + noise I (device, ld_stored_elements(n, op->layout) elements,
+ * FP64 for LD_F64, FP32 for LD_F32) in op->layout so that it can be passed
+ * back as op->M_stored.  op->M_stored is ignored.  LD_TILED requires LD_F32.
  * Asynchronous. */
 ld_status kernel_materialize(ld_ctx* ctx, const ld_operator* op, void* M_out);
 

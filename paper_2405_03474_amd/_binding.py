@@ -19,12 +19,14 @@ LIB_PATH = os.path.join(_HERE, "liblogdet.so")
 LD_OK, LD_EINVAL, LD_ENOTSPD, LD_ENOCONV, LD_EHIP, LD_ENOMEM = 0, -1, -2, -3, -4, -5
 LD_RBF, LD_MATERN52 = 0, 1
 LD_F64, LD_F32 = 0, 1
+LD_ROW_MAJOR, LD_TILED = 0, 1
 
 STATUS_NAMES = {0: "LD_OK", -1: "LD_EINVAL", -2: "LD_ENOTSPD", -3: "LD_ENOCONV", -4: "LD_EHIP",
                 -5: "LD_ENOMEM"}
 
 EXPORTED = (
-    "ld_ctx_create", "ld_ctx_destroy", "ld_last_error", "ld_ctx_set_timing", "ld_ctx_read_timing", "ld_rational_coeffs", "ld_fill_probes",
+    "ld_ctx_create", "ld_ctx_destroy", "ld_last_error", "ld_ctx_set_timing", "ld_ctx_read_timing",
+    "ld_stored_elements", "ld_rational_coeffs", "ld_fill_probes",
     "ld_fill_gaussian", "kernel_matmat", "kernel_materialize", "logdet_precond_build",
     "ld_precond_info", "ld_precond_export", "ld_precond_apply_inverse", "ld_precond_free",
     "logdet_estimate",
@@ -42,6 +44,7 @@ class Operator(ctypes.Structure):
         ("X", ctypes.c_void_p), ("n", ctypes.c_int64), ("d", ctypes.c_int32),
         ("kind", ctypes.c_int32), ("lengthscale", ctypes.c_double), ("variance", ctypes.c_double),
         ("noise", ctypes.c_double), ("precision", ctypes.c_int32), ("M_stored", ctypes.c_void_p),
+        ("layout", ctypes.c_int32),
     ]
 
 
@@ -76,6 +79,7 @@ def load():
         "ld_last_error": (ctypes.c_char_p, []),
         "ld_ctx_set_timing": (i32, [vp, i32]),
         "ld_ctx_read_timing": (i32, [vp, pd, ctypes.POINTER(i64), pd, pd]),
+        "ld_stored_elements": (i64, [i64, i32]),
         "ld_rational_coeffs": (i32, [i32, pd, pd, pd]),
         "ld_fill_probes": (i32, [vp, u64, i64, i64, i32, vp]),
         "ld_fill_gaussian": (i32, [vp, u64, i32, i64, i64, vp]),
@@ -172,7 +176,8 @@ class GPOperator:
     variance: float
     noise: float
     precision: int = LD_F64
-    M: object = None          # optional stored matrix (n, n) in the operator's dtype
+    M: object = None          # optional stored matrix in the operator's dtype and layout
+    layout: int = LD_ROW_MAJOR
     _keep: list = field(default_factory=list, repr=False)
 
     @property
@@ -188,11 +193,12 @@ class GPOperator:
         assert self.X.is_cuda and self.X.dtype == torch.float64 and self.X.is_contiguous()
         if self.M is not None:
             assert self.M.is_cuda and self.M.dtype == _dtype(self.precision) and self.M.is_contiguous()
-            assert tuple(self.M.shape) == (self.n, self.n)
+            assert self.M.numel() == stored_elements(self.n, self.layout)
         return Operator(X=self.X.data_ptr(), n=self.n, d=self.d, kind=self.kind,
                         lengthscale=self.lengthscale, variance=self.variance, noise=self.noise,
                         precision=self.precision,
-                        M_stored=self.M.data_ptr() if self.M is not None else None)
+                        M_stored=self.M.data_ptr() if self.M is not None else None,
+                        layout=self.layout)
 
 
 def fill_probes(ctx: Context, seed: int, n: int, s: int, precision: int = LD_F64):
@@ -220,12 +226,23 @@ def kernel_matmat(ctx: Context, op: GPOperator, V):
     return Y.reshape(V.shape)
 
 
+def stored_elements(n: int, layout: int) -> int:
+    v = load().ld_stored_elements(n, layout)
+    if v < 0:
+        raise LogdetError(LD_EINVAL, "bad stored-matrix size query")
+    return int(v)
+
+
 def kernel_materialize(ctx: Context, op: GPOperator, out=None):
+    """Stored M in op.layout (row-major: shape (n, n); tiled: a flat buffer)."""
     torch = _torch()
-    M = out if out is not None else torch.empty((op.n, op.n), dtype=_dtype(op.precision),
-                                                device=f"cuda:{ctx.device}")
+    count = stored_elements(op.n, op.layout)
+    if out is None:
+        shape = (op.n, op.n) if op.layout == LD_ROW_MAJOR else (count,)
+        out = torch.empty(shape, dtype=_dtype(op.precision), device=f"cuda:{ctx.device}")
+    M = out
     assert M.is_cuda and M.dtype == _dtype(op.precision) and M.is_contiguous()
-    assert tuple(M.shape) == (op.n, op.n)
+    assert M.numel() == count
     cop = op.c_struct()
     _check(load().kernel_materialize(ctx.handle, ctypes.byref(cop), ctypes.c_void_p(M.data_ptr())))
     return M

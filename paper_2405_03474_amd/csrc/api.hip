@@ -115,6 +115,10 @@ ld_status check_operator(const ld_operator* op) {
     return fail(LD_EINVAL, "noise must be finite and >= 0");
   if (op->precision != LD_F64 && op->precision != LD_F32)
     return fail(LD_EINVAL, "precision must be LD_F64 or LD_F32");
+  if (op->layout != LD_ROW_MAJOR && op->layout != LD_TILED)
+    return fail(LD_EINVAL, "layout must be LD_ROW_MAJOR or LD_TILED");
+  if (op->layout == LD_TILED && op->precision != LD_F32)
+    return fail(LD_EINVAL, "LD_TILED storage is FP32 only");
   return LD_OK;
 }
 
@@ -141,6 +145,7 @@ MatmatArgs base_args(const ld_operator* op, const void* X) {
   a.d = op->d;
   a.kp = make_kparams(*op);
   a.A = op->M_stored;
+  a.layout = op->layout;
   a.X = X;
   return a;
 }
@@ -196,11 +201,13 @@ ld_status check_ctx(ld_ctx* ctx) {
 }
 
 __global__ void k_d_and_inv(const double* __restrict__ U, const double* __restrict__ lam, int64_t n,
-                            int rank, const void* __restrict__ Mst, int mprec, double diag_const,
-                            double floor_v, double* __restrict__ D, double* __restrict__ Dinv) {
+                            int rank, const void* __restrict__ Mst, int mprec, int layout,
+                            double diag_const, double floor_v, double* __restrict__ D,
+                            double* __restrict__ Dinv) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     double dm = diag_const;
-    if (Mst) dm = mprec == LD_F64 ? ((const double*)Mst)[i * n + i] : (double)((const float*)Mst)[i * n + i];
+    const int64_t ii = layout == LD_TILED ? tiled_index(i, i, n) : i * n + i;
+    if (Mst) dm = mprec == LD_F64 ? ((const double*)Mst)[ii] : (double)((const float*)Mst)[ii];
     double low = 0.0;
     for (int j = 0; j < rank; ++j) {
       const double u = U[i * rank + j];
@@ -419,7 +426,8 @@ ld_status build_precond(ld_ctx* ctx, const ld_operator* op, int rank, int oversa
   // 6. D = diag(M) - rowsum(U^2 lam), floored
   const double floor_v = op->noise > 0.0 ? op->noise : 1e-12 * op->variance;
   hipLaunchKernelGGL(k_d_and_inv, dim3(grid1(n)), dim3(256), 0, st, P->U, P->lam, n, rank,
-                     op->M_stored, op->precision, op->variance + op->noise, floor_v, P->D, P->Dinv64);
+                     op->M_stored, op->precision, op->layout, op->variance + op->noise, floor_v,
+                     P->D, P->Dinv64);
   // capacitance C = diag(1/lam) + U^T D^-1 U = R^T R
   {
     const size_t mark = ctx->arena.top;
@@ -511,6 +519,11 @@ ld_status ld_ctx_read_timing(ld_ctx* ctx, double* ms, int64_t* calls, double* fl
   return LD_OK;
 }
 
+int64_t ld_stored_elements(int64_t n, int32_t layout) {
+  if (n < 1 || (layout != LD_ROW_MAJOR && layout != LD_TILED)) return -1;
+  return stored_elements(n, layout);
+}
+
 ld_status ld_rational_coeffs(int32_t k, double* b, double* a, double* c) {
   if (!b || !a || !c) return fail(LD_EINVAL, "null output pointer");
   Rational r;
@@ -562,7 +575,8 @@ ld_status kernel_materialize(ld_ctx* ctx, const ld_operator* op, void* M_out) {
   LD_TRY(check_ctx(ctx));
   LD_TRY(check_operator(op));
   if (!M_out) return fail(LD_EINVAL, "M_out is NULL");
-  launch_materialize(ctx->stream, make_kparams(*op), op->X, op->n, op->d, is_f64(op), M_out);
+  launch_materialize(ctx->stream, make_kparams(*op), op->X, op->n, op->d, is_f64(op), op->layout,
+                     M_out);
   LD_HIP(hipGetLastError());
   return LD_OK;
 }

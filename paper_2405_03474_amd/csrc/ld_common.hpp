@@ -128,6 +128,7 @@ struct MatmatArgs {
   int d = 0;
   KParams kp{};
   const void* A = nullptr;   // stored matrix or nullptr
+  int layout = LD_ROW_MAJOR; // layout of A
   const void* X = nullptr;   // points in the path's precision (n x d)
   const void* V = nullptr;
   void* Y = nullptr;
@@ -141,7 +142,22 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a);
 size_t matmat_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int64_t s);
 constexpr int kEpiRows = 128;  // rows per epilogue block (dot partial granularity)
 void launch_materialize(hipStream_t st, const KParams& kp, const double* X, int64_t n, int d,
-                        bool f64, void* M);
+                        bool f64, int layout, void* M);
+
+// Element (i, k) of a stored matrix in LD_TILED layout (128 x 32 tiles).
+constexpr int kTileRows = 128;
+constexpr int kTileCols = 32;
+__host__ __device__ inline int64_t tiled_index(int64_t i, int64_t k, int64_t n) {
+  const int64_t kt = (n + kTileCols - 1) / kTileCols;
+  return ((i / kTileRows) * kt + k / kTileCols) * (kTileRows * kTileCols) +
+         (i % kTileRows) * kTileCols + (k % kTileCols);
+}
+inline int64_t stored_elements(int64_t n, int layout) {
+  if (layout == LD_TILED)
+    return ((n + kTileRows - 1) / kTileRows) * kTileRows * ((n + kTileCols - 1) / kTileCols) *
+           kTileCols;
+  return n * n;
+}
 void launch_convert_f64_to_f32(hipStream_t st, const double* in, float* out, int64_t count);
 void launch_convert_f32_to_f64(hipStream_t st, const float* in, double* out, int64_t count);
 

@@ -33,14 +33,36 @@ constexpr int DMAX = 16; // max point dimension on the fly
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr int kMaxContrib = 64;  // partial slots summed per output tile (bounded by the plan)
 
+// Work split.  The S k-stages are cut into nx contiguous chunks, one per XCD
+// (workgroup g runs on XCD g mod nx), so the slice of V a chunk needs stays
+// in that XCD's L2; inside a chunk, the (tile, stage) units are cut into
+// G/nx equal contiguous ranges, one per workgroup of that XCD (stream-K).
 struct SK {
   int64_t n, s;
-  int64_t U;  // total units = tiles * S
-  int rt;     // row tiles
-  int S;      // stages per tile
-  int G;      // workgroups
-  int J;      // partial slots per workgroup
+  int64_t tiles;  // row tiles * column tiles
+  int rt;         // row tiles
+  int S;          // stages per tile
+  int G;          // workgroups, a multiple of nx
+  int nx;         // k chunks
+  int J;          // partial slots per workgroup
 };
+
+struct WGRange {
+  int sb;          // first stage of the workgroup's k chunk
+  int Sx;          // stages in the chunk
+  int64_t u, uend; // unit range inside the chunk
+};
+
+__host__ __device__ inline WGRange wg_range(const SK& p, int g) {
+  const int x = g % p.nx, lg = g / p.nx, Gx = p.G / p.nx;
+  WGRange r;
+  r.sb = (int)(((int64_t)p.S * x) / p.nx);
+  r.Sx = (int)(((int64_t)p.S * (x + 1)) / p.nx) - r.sb;
+  const int64_t Ux = p.tiles * r.Sx;
+  r.u = Ux * lg / Gx;
+  r.uend = Ux * (lg + 1) / Gx;
+  return r;
+}
 
 // ---------------------------------------------------------- kernel values --
 // FP32: RBF c = log2(e) / (2 l^2);  Matern-5/2 c = sqrt(5) / l
@@ -58,10 +80,6 @@ __device__ __forceinline__ double kval64(double r2, double var, double c) {
   return var * (1.0 + t + t * t * (1.0 / 3.0)) * exp(-t);
 }
 
-__device__ __forceinline__ void unit_range(const SK& p, int g, int64_t& u0, int64_t& u1) {
-  u0 = (p.U * g) / p.G;
-  u1 = (p.U * (g + 1)) / p.G;
-}
 
 // ------------------------------------------------------------ FP32 path --
 template <int NB, bool FLY, int KIND, int DT>
@@ -82,13 +100,15 @@ __global__ __launch_bounds__(256, 2) void k_mm32(const float* __restrict__ A,
   const int li = lane & 31, lh = lane >> 5;
   const int64_t n = p.n, s = p.s;
 
-  int64_t u, uend;
-  unit_range(p, blockIdx.x, u, uend);
+  const WGRange wr = wg_range(p, blockIdx.x);
+  int64_t u = wr.u;
+  const int64_t uend = wr.uend;
   int seg = 0;
   while (u < uend) {
-    const int64_t T = u / p.S;
-    const int st0 = (int)(u - T * p.S);
-    const int st1 = (int)((int64_t)p.S < st0 + (uend - u) ? (int64_t)p.S : st0 + (uend - u));
+    const int64_t T = u / wr.Sx;
+    const int l0 = (int)(u - T * wr.Sx);
+    const int l1 = (int)((int64_t)wr.Sx < l0 + (uend - u) ? (int64_t)wr.Sx : l0 + (uend - u));
+    const int st0 = wr.sb + l0, st1 = wr.sb + l1;
     const int rtile = (int)(T % p.rt);
     const int64_t ctile = T / p.rt;
     const int64_t i0 = (int64_t)rtile * BM;
@@ -195,21 +215,33 @@ __global__ __launch_bounds__(256, 2) void k_mm32(const float* __restrict__ A,
 // The stored-matrix FP32 product is an HBM stream of M: each stage's tiles
 // are fetched into registers one stage ahead (the loads fly while the
 // previous stage's MFMAs run) and LDS is double buffered, so a stage costs
-// one barrier.
+// one barrier.  B is kept transposed in LDS (column-major, k contiguous) so
+// that each lane fetches its 16 k-values of a column with four 16-byte
+// reads; all fragment reads of a stage are issued before its MFMAs.
 template <int NB>
 struct StTile {
   float4 a[4];        // 128 x 32 A tile: 1024 float4 / 256 threads
-  float4 b[NB];       // 32 x 32*NB B tile: 256*NB float4 / 256 threads
+  float b[4 * NB];    // 32 x 32*NB B tile: 1024*NB floats / 256 threads
 };
 
-template <int NB>
+template <int NB, bool TILED>
 __device__ __forceinline__ void st_load(StTile<NB>& t, const float* __restrict__ A,
                                         const float* __restrict__ V, int64_t n, int64_t s,
                                         int64_t i0, int64_t c0, int64_t k0, int tid, bool a_vec,
-                                        bool b_vec) {
+                                        int64_t kt) {
   constexpr int NT = 32 * NB;
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  if (TILED) {
+    // the stage is one contiguous, zero-padded 128 x 32 tile
+    const f32x4* src = (const f32x4*)(A + ((i0 / BM) * kt + k0 / BK) * (BM * BK));
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 4; ++j) {
+      const f32x4 w = __builtin_nontemporal_load(src + tid + 256 * j);
+      t.a[j] = make_float4(w.x, w.y, w.z, w.w);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < (TILED ? 0 : 4); ++j) {
     const int e = tid + 256 * j;
     const int rr = e >> 3, kq = e & 7;
     const int64_t row = i0 + rr, kc = k0 + 4 * kq;
@@ -217,7 +249,6 @@ __device__ __forceinline__ void st_load(StTile<NB>& t, const float* __restrict__
     if (row < n) {
       const float* src = A + row * n + kc;
       if (a_vec && kc + 3 < n) {
-        typedef float f32x4 __attribute__((ext_vector_type(4)));
         const f32x4 w = __builtin_nontemporal_load((const f32x4*)src);
         v = make_float4(w.x, w.y, w.z, w.w);
       } else {
@@ -229,50 +260,90 @@ __device__ __forceinline__ void st_load(StTile<NB>& t, const float* __restrict__
     }
     t.a[j] = v;
   }
+  // B: one column per lane, consecutive lanes on consecutive columns
 #pragma unroll
-  for (int j = 0; j < NB; ++j) {
+  for (int j = 0; j < 4 * NB; ++j) {
     const int e = tid + 256 * j;
-    const int kk = e / (NT / 4), cq = e % (NT / 4);
-    const int64_t kr = k0 + kk, col = c0 + 4 * cq;
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (kr < n) {
-      const float* src = V + kr * s + col;
-      if (b_vec && col + 3 < s) {
-        v = *(const float4*)src;
-      } else {
-        if (col + 0 < s) v.x = src[0];
-        if (col + 1 < s) v.y = src[1];
-        if (col + 2 < s) v.z = src[2];
-        if (col + 3 < s) v.w = src[3];
-      }
-    }
-    t.b[j] = v;
+    const int kk = e / NT, cc = e % NT;
+    const int64_t kr = k0 + kk, col = c0 + cc;
+    t.b[j] = (kr < n && col < s) ? V[kr * s + col] : 0.f;
+  }
+}
+
+constexpr int ST_AS = BK + 4;  // row stride (floats) of the A tile and of transposed B
+
+template <int NB>
+__device__ __forceinline__ void st_store(const StTile<NB>& t, float* __restrict__ as,
+                                         float* __restrict__ bt, int tid) {
+  constexpr int NT = 32 * NB;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int e = tid + 256 * j;
+    *(float4*)&as[(e >> 3) * ST_AS + 4 * (e & 7)] = t.a[j];
+  }
+#pragma unroll
+  for (int j = 0; j < 4 * NB; ++j) {
+    const int e = tid + 256 * j;
+    bt[(e % NT) * ST_AS + e / NT] = t.b[j];
   }
 }
 
 template <int NB>
+__device__ __forceinline__ void st_compute(const float* __restrict__ as,
+                                           const float* __restrict__ bt, f32x16* acc, int wave,
+                                           int li, int lh) {
+  float a[16], b[NB][16];
+  const float4* ap = (const float4*)&as[(32 * wave + li) * ST_AS + lh * 16];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float4 v = ap[q];
+    a[4 * q + 0] = v.x;
+    a[4 * q + 1] = v.y;
+    a[4 * q + 2] = v.z;
+    a[4 * q + 3] = v.w;
+  }
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const float4* bp = (const float4*)&bt[(nb * 32 + li) * ST_AS + lh * 16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 v = bp[q];
+      b[nb][4 * q + 0] = v.x;
+      b[nb][4 * q + 1] = v.y;
+      b[nb][4 * q + 2] = v.z;
+      b[nb][4 * q + 3] = v.w;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 16; ++t)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+      acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t], b[nb][t], acc[nb], 0, 0, 0);
+}
+
+template <int NB, bool TILED>
 __global__ __launch_bounds__(256, 2) void k_mm32_st(const float* __restrict__ A,
                                                     const float* __restrict__ V,
                                                     float* __restrict__ part, SK p) {
   constexpr int NT = 32 * NB;
-  constexpr int BS = NT + 2;
-  constexpr int AS = BK + 4;
+  constexpr int AS = BK + 4;  // row stride (floats) of the A tile and of transposed B
   __shared__ __attribute__((aligned(16))) float As[2][BM * AS];
-  __shared__ __attribute__((aligned(16))) float Bs[2][BK * BS];
+  __shared__ __attribute__((aligned(16))) float Bt[2][NT * AS];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 31, lh = lane >> 5;
   const int64_t n = p.n, s = p.s;
   const bool a_vec = (n & 3) == 0;
-  const bool b_vec = (s & 3) == 0;
 
-  int64_t u, uend;
-  unit_range(p, blockIdx.x, u, uend);
+  const WGRange wr = wg_range(p, blockIdx.x);
+  int64_t u = wr.u;
+  const int64_t uend = wr.uend;
   int seg = 0;
   while (u < uend) {
-    const int64_t T = u / p.S;
-    const int st0 = (int)(u - T * p.S);
-    const int st1 = (int)((int64_t)p.S < st0 + (uend - u) ? (int64_t)p.S : st0 + (uend - u));
+    const int64_t T = u / wr.Sx;
+    const int l0 = (int)(u - T * wr.Sx);
+    const int l1 = (int)((int64_t)wr.Sx < l0 + (uend - u) ? (int64_t)wr.Sx : l0 + (uend - u));
+    const int st0 = wr.sb + l0, st1 = wr.sb + l1;
     const int rtile = (int)(T % p.rt);
     const int64_t i0 = (int64_t)rtile * BM;
     const int64_t c0 = (T / p.rt) * NT;
@@ -283,47 +354,24 @@ __global__ __launch_bounds__(256, 2) void k_mm32_st(const float* __restrict__ A,
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
 
-    StTile<NB> tl;
-    st_load<NB>(tl, A, V, n, s, i0, c0, (int64_t)st0 * BK, tid, a_vec, b_vec);
+    // two register stages in flight: tiles st+1 and st+2 load while st computes
+    StTile<NB> ta, tb;
+    st_load<NB, TILED>(ta, A, V, n, s, i0, c0, (int64_t)st0 * BK, tid, a_vec, p.S);
+    if (st0 + 1 < st1)
+      st_load<NB, TILED>(tb, A, V, n, s, i0, c0, (int64_t)(st0 + 1) * BK, tid, a_vec, p.S);
     __syncthreads();  // the previous segment's last stage is done with both buffers
-    int buf = 0;
-    for (int st = st0; st < st1; ++st) {
-      float* as = As[buf];
-      float* bs = Bs[buf];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int e = tid + 256 * j;
-        *(float4*)&as[(e >> 3) * AS + 4 * (e & 7)] = tl.a[j];
-      }
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        const int e = tid + 256 * j;
-        const int kk = e / (NT / 4), cq = e % (NT / 4);
-        float2* dst = (float2*)&bs[kk * BS + 4 * cq];
-        dst[0] = make_float2(tl.b[j].x, tl.b[j].y);
-        dst[1] = make_float2(tl.b[j].z, tl.b[j].w);
-      }
+    for (int st = st0; st < st1; st += 2) {
+      st_store<NB>(ta, As[0], Bt[0], tid);
       __syncthreads();
-      if (st + 1 < st1)
-        st_load<NB>(tl, A, V, n, s, i0, c0, (int64_t)(st + 1) * BK, tid, a_vec, b_vec);
-      float a[16];
-      const float4* ap = (const float4*)&as[(32 * wave + li) * AS + lh * 16];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float4 v = ap[q];
-        a[4 * q + 0] = v.x;
-        a[4 * q + 1] = v.y;
-        a[4 * q + 2] = v.z;
-        a[4 * q + 3] = v.w;
-      }
-#pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        const float* brow = &bs[(lh * 16 + t) * BS + li];
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t], brow[nb * 32], acc[nb], 0, 0, 0);
-      }
-      buf ^= 1;
+      if (st + 2 < st1)
+        st_load<NB, TILED>(ta, A, V, n, s, i0, c0, (int64_t)(st + 2) * BK, tid, a_vec, p.S);
+      st_compute<NB>(As[0], Bt[0], acc, wave, li, lh);
+      if (st + 1 >= st1) break;
+      st_store<NB>(tb, As[1], Bt[1], tid);
+      __syncthreads();
+      if (st + 3 < st1)
+        st_load<NB, TILED>(tb, A, V, n, s, i0, c0, (int64_t)(st + 3) * BK, tid, a_vec, p.S);
+      st_compute<NB>(As[1], Bt[1], acc, wave, li, lh);
     }
 
     float* dst = part + ((int64_t)blockIdx.x * p.J + seg) * (int64_t)(BM * NT);
@@ -358,13 +406,15 @@ __global__ __launch_bounds__(256, 2) void k_mm64(const double* __restrict__ A,
   const int lj = lane & 15, lh = lane >> 4;  // lh in 0..3
   const int64_t n = p.n, s = p.s;
 
-  int64_t u, uend;
-  unit_range(p, blockIdx.x, u, uend);
+  const WGRange wr = wg_range(p, blockIdx.x);
+  int64_t u = wr.u;
+  const int64_t uend = wr.uend;
   int seg = 0;
   while (u < uend) {
-    const int64_t T = u / p.S;
-    const int st0 = (int)(u - T * p.S);
-    const int st1 = (int)((int64_t)p.S < st0 + (uend - u) ? (int64_t)p.S : st0 + (uend - u));
+    const int64_t T = u / wr.Sx;
+    const int l0 = (int)(u - T * wr.Sx);
+    const int l1 = (int)((int64_t)wr.Sx < l0 + (uend - u) ? (int64_t)wr.Sx : l0 + (uend - u));
+    const int st0 = wr.sb + l0, st1 = wr.sb + l1;
     const int rtile = (int)(T % p.rt);
     const int64_t ctile = T / p.rt;
     const int64_t i0 = (int64_t)rtile * BM;
@@ -497,18 +547,26 @@ __global__ __launch_bounds__(256) void k_epilogue(const T* __restrict__ part, SK
   const int64_t c0 = (Tt / p.rt) * NT;
   const int64_t i0 = (int64_t)rtile * BM;
   if (tid == 0) {
-    // workgroups whose unit range intersects [Tt*S, (Tt+1)*S), in order
-    const int64_t ub = Tt * p.S, ue = ub + p.S;
-    int g = (int)((ub * p.G) / p.U);
-    if (g >= p.G) g = p.G - 1;
-    while (g > 0 && (p.U * g) / p.G > ub) --g;
-    while (g + 1 < p.G && (p.U * (g + 1)) / p.G <= ub) ++g;
+    // for every k chunk, the workgroups whose unit range intersects the tile
     int cnt = 0;
-    for (; g < p.G && cnt < kMaxContrib; ++g) {
-      const int64_t b0 = (p.U * g) / p.G, b1 = (p.U * (g + 1)) / p.G;
-      if (b0 >= ue) break;
-      if (b1 <= b0) continue;
-      slot[cnt++] = ((int64_t)g * p.J + (Tt - b0 / p.S)) * (int64_t)(BM * NT);
+    const int Gx = p.G / p.nx;
+    for (int x = 0; x < p.nx; ++x) {
+      const WGRange w0 = wg_range(p, x);
+      const int Sx = w0.Sx;
+      if (Sx == 0) continue;
+      const int64_t Ux = p.tiles * Sx;
+      const int64_t ub = Tt * Sx, ue = ub + Sx;
+      int lg = (int)((ub * Gx) / Ux);
+      if (lg >= Gx) lg = Gx - 1;
+      while (lg > 0 && (Ux * lg) / Gx > ub) --lg;
+      while (lg + 1 < Gx && (Ux * (lg + 1)) / Gx <= ub) ++lg;
+      for (; lg < Gx && cnt < kMaxContrib; ++lg) {
+        const int64_t b0 = (Ux * lg) / Gx, b1 = (Ux * (lg + 1)) / Gx;
+        if (b0 >= ue) break;
+        if (b1 <= b0) continue;
+        const int64_t g = (int64_t)lg * p.nx + x;
+        slot[cnt++] = (g * p.J + (Tt - b0 / Sx)) * (int64_t)(BM * NT);
+      }
     }
     nslot = cnt;
   }
@@ -566,6 +624,34 @@ __global__ __launch_bounds__(256) void k_materialize(const double* __restrict__ 
   }
 }
 
+// LD_TILED: walk the storage linearly (coalesced writes), zero the padding.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_materialize_tiled(const double* __restrict__ X, int64_t n,
+                                                           int d, double var, double c,
+                                                           double noise, int64_t total,
+                                                           float* __restrict__ M) {
+  const int64_t kt = (n + kTileCols - 1) / kTileCols;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * 256) {
+    const int64_t tile = e / (kTileRows * kTileCols);
+    const int w = (int)(e % (kTileRows * kTileCols));
+    const int64_t i = (tile / kt) * kTileRows + w / kTileCols;
+    const int64_t k = (tile % kt) * kTileCols + w % kTileCols;
+    float out = 0.f;
+    if (i < n && k < n) {
+      double r2 = 0.0;
+      for (int dd = 0; dd < d; ++dd) {
+        const double df = X[i * d + dd] - X[k * d + dd];
+        r2 = fma(df, df, r2);
+      }
+      double v = kval64<KIND>(r2, var, c);
+      if (i == k) v += noise;
+      out = (float)v;
+    }
+    M[e] = out;
+  }
+}
+
 __global__ void k_f64_to_f32(const double* __restrict__ in, float* __restrict__ out, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256)
     out[i] = (float)in[i];
@@ -598,19 +684,26 @@ Plan make_plan(ld_ctx* ctx, bool f64, int64_t n, int64_t s) {
   p.s = s;
   p.rt = (int)((n + BM - 1) / BM);
   const int64_t ct = (s + pl.NT - 1) / pl.NT;
+  p.tiles = (int64_t)p.rt * ct;
   p.S = (int)((n + BK - 1) / BK);
-  p.U = (int64_t)p.rt * ct * p.S;
+  const int64_t U = p.tiles * p.S;
+  // one k chunk per XCD when the device has 8 (otherwise a single chunk), and
+  // at least 4 stages per chunk
+  int nx = (ctx->num_cu % 8 == 0) ? 8 : 1;
+  while (nx > 1 && p.S < 4 * nx) nx /= 2;
+  p.nx = nx;
   const int64_t gmax = (int64_t)ctx->num_cu * 2;
   const int64_t min_units = 8;
-  int64_t G = (p.U + min_units - 1) / min_units;
+  int64_t G = (U + min_units - 1) / min_units;
   if (G > gmax) G = gmax;
-  // keep every tile split over at most kMaxContrib - 2 workgroups
-  const int64_t tiles = (int64_t)p.rt * ct;
-  if (G > tiles * (kMaxContrib / 2 - 1)) G = tiles * (kMaxContrib / 2 - 1);
-  if (G < 1) G = 1;
+  // keep every tile split over few workgroups per chunk
+  if (G > p.tiles * nx * (kMaxContrib / (2 * nx) - 1)) G = p.tiles * nx * (kMaxContrib / (2 * nx) - 1);
+  G = (G / nx) * nx;
+  if (G < nx) G = nx;
   p.G = (int)G;
-  const int64_t per = (p.U + G - 1) / G;
-  p.J = (int)((per + p.S - 1) / p.S + 1);
+  const int64_t Sxmax = (p.S + nx - 1) / nx;
+  const int64_t per = (p.tiles * Sxmax + G / nx - 1) / (G / nx);
+  p.J = (int)((per + Sxmax - 1) / Sxmax + 1);
   pl.part_bytes = (size_t)p.G * p.J * BM * pl.NT * (f64 ? sizeof(double) : sizeof(float));
   return pl;
 }
@@ -737,10 +830,15 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
                                 P, pl.p);
     } else {
       const float* A = (const float*)a.A;
-      if (NB == 2)
-        hipLaunchKernelGGL((k_mm32_st<2>), grid, dim3(256), 0, st, A, V, P, pl.p);
+      const bool tiled = a.layout == LD_TILED;
+      if (NB == 2 && tiled)
+        hipLaunchKernelGGL((k_mm32_st<2, true>), grid, dim3(256), 0, st, A, V, P, pl.p);
+      else if (NB == 2)
+        hipLaunchKernelGGL((k_mm32_st<2, false>), grid, dim3(256), 0, st, A, V, P, pl.p);
+      else if (tiled)
+        hipLaunchKernelGGL((k_mm32_st<1, true>), grid, dim3(256), 0, st, A, V, P, pl.p);
       else
-        hipLaunchKernelGGL((k_mm32_st<1>), grid, dim3(256), 0, st, A, V, P, pl.p);
+        hipLaunchKernelGGL((k_mm32_st<1, false>), grid, dim3(256), 0, st, A, V, P, pl.p);
     }
     if (ev1) LD_HIP(hipEventRecord(ev1, st));
     const int64_t tiles = (int64_t)pl.p.rt * ((a.s + pl.NT - 1) / pl.NT);
@@ -754,8 +852,20 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
 }
 
 void launch_materialize(hipStream_t st, const KParams& kp, const double* X, int64_t n, int d,
-                        bool f64, void* M) {
+                        bool f64, int layout, void* M) {
   const double c = kp.kind == LD_RBF ? kp.c_rbf : kp.c_mat;
+  if (layout == LD_TILED) {
+    const int64_t total = stored_elements(n, LD_TILED);
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (kp.kind == LD_RBF)
+      hipLaunchKernelGGL((k_materialize_tiled<LD_RBF>), dim3((unsigned)blocks), dim3(256), 0, st, X,
+                         n, d, kp.variance, c, kp.noise, total, (float*)M);
+    else
+      hipLaunchKernelGGL((k_materialize_tiled<LD_MATERN52>), dim3((unsigned)blocks), dim3(256), 0,
+                         st, X, n, d, kp.variance, c, kp.noise, total, (float*)M);
+    return;
+  }
   int64_t gy = n < 256 ? n : 256;
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)gy);
   if (f64) {

@@ -86,8 +86,17 @@ def test_matmat_fp64(ctx, n, d, s, kind, stored):
     assert np.max(np.abs(host(Y) - ref) / scale) < 1e-13
 
 
+def untile(buf, n):
+    """Dense n x n view of an LD_TILED buffer (128 x 32 tiles, as documented in logdet.h)."""
+    kt = -(-n // 32)
+    rt = -(-n // 128)
+    t = buf.reshape(rt, kt, 128, 32).transpose(0, 2, 1, 3).reshape(rt * 128, kt * 32)
+    assert np.all(t[n:, :] == 0) and np.all(t[:, n:] == 0)
+    return t[:n, :n]
+
+
 @pytest.mark.parametrize("n,d,s,kind", MM_CASES)
-@pytest.mark.parametrize("stored", [False, True])
+@pytest.mark.parametrize("stored", [None, "row", "tiled"])
 def test_matmat_fp32(ctx, n, d, s, kind, stored):
     g = np.random.default_rng(7 * n + s)
     X = g.random((n, d))
@@ -95,9 +104,12 @@ def test_matmat_fp32(ctx, n, d, s, kind, stored):
     Mref = gp.dense_matrix(kind, X, 0.3, 1.3, 1e-2)
     op = make_op(X, kind, 0.3, 1.3, 1e-2, precision=L.LD_F32)
     if stored:
+        op.layout = L.LD_TILED if stored == "tiled" else L.LD_ROW_MAJOR
         op.M = L.kernel_materialize(ctx, op)
         ctx.synchronize()
-        np.testing.assert_allclose(host(op.M), Mref.astype(np.float32), rtol=1.2e-7, atol=1e-30)
+        M = host(op.M)
+        M = untile(M, n) if stored == "tiled" else M
+        np.testing.assert_allclose(M, Mref.astype(np.float32), rtol=1.2e-7, atol=1e-30)
     Y = L.kernel_matmat(ctx, op, dev(V, torch.float32))
     ctx.synchronize()
     ref = Mref @ V.astype(np.float64)
@@ -111,6 +123,7 @@ def _precond_pair(ctx, cfg, precision=L.LD_F64, stored=False):
     M = gp.dense_matrix(cfg.kind, X, cfg.lengthscale, cfg.variance, cfg.noise)
     op = make_op(X, cfg.kind, cfg.lengthscale, cfg.variance, cfg.noise, precision)
     if stored:
+        op.layout = L.LD_TILED if stored == "tiled" else L.LD_ROW_MAJOR
         op.M = L.kernel_materialize(ctx, op)
     P = L.Precond(ctx, op, cfg.rank, cfg.oversample, cfg.power_iters, cfg.precond_seed)
     ref = oprec.rsvd(M, cfg.rank, cfg.oversample, cfg.power_iters, cfg.precond_seed,
@@ -137,7 +150,7 @@ def test_precond_fp64_matches_oracle(ctx):
 
 def test_precond_fp32_stored_close_to_oracle(ctx):
     cfg = workloads.C2.with_n(2000, rank=100)
-    X, M, op, P, ref = _precond_pair(ctx, cfg, precision=L.LD_F32, stored=True)
+    X, M, op, P, ref = _precond_pair(ctx, cfg, precision=L.LD_F32, stored="tiled")
     U, lam, D = (host(t) for t in P.export())
     np.testing.assert_allclose(lam[:50], ref.lam[:50], rtol=1e-4)
     assert P.logdet == pytest.approx(ref.logdet, rel=1e-4)
@@ -162,7 +175,7 @@ def test_estimate_fp64_c1_parity(ctx, k):
     assert res["converged_cols"] == cfg.probes
 
 
-@pytest.mark.parametrize("stored", [False, True])
+@pytest.mark.parametrize("stored", [False, "row", "tiled"])
 @pytest.mark.parametrize("k", [1, 3, 5])
 def test_estimate_fp32_parity(ctx, k, stored):
     cfg = workloads.C2.with_n(3000, rank=150)

@@ -1,21 +1,30 @@
 """Benchmark: log-det estimates per second on one MI355X.
 
-A step is one pass of the whole hot path over one problem instance:
-materialize M = K + noise I from the points (the stored-matrix workload
-keeps M in HBM), build the randomized truncated-SVD preconditioner, and run
-the estimator for each requested order r_k (Section 2, Algorithm 1 with the
-solves run to tolerance), each with its own probe stream.  The default
-workload is Matern-5/2 on 50,000 points from an 8-component Gaussian mixture
-in [0,1]^3, l = 0.15, noise 1e-3, FP32 with M stored (10 GB), rank 500, 64
-Rademacher probes, r_1, r_3 and r_5.
+A step is one pass of the whole hot path over one problem instance: (for
+the stored workload) materialize M = K + noise I from the points, build the
+randomized truncated-SVD preconditioner, and run the estimator for each
+requested order r_k (Section 2, Algorithm 1 with its shifted solves run to a
+tolerance), each order with its own probe stream.
 
-Prints one JSON line (see the design doc for every field).
+Workloads (all synthetic, inputs from workloads/):
+  c2_matern_gm50k  (default) Matern-5/2, 50,000 points from an 8-component
+                   Gaussian mixture in [0,1]^3, l = 0.15, noise 1e-3; FP32
+                   with M stored in HBM (tiled layout, 10 GB); rank 500;
+                   64 Rademacher probes; r_1, r_3, r_5.
+  c1_rbf_2k        RBF, 2,000 uniform points, FP64 on the fly, rank 100, 32
+                   probes, r_3.
+  c3_matern_200k   precision form: Matern-5/2, 200,000 uniform points,
+                   l = 0.05, noise 1e-3, split-BF16 matrix-core products on
+                   the fly, rank 1,000, 64 probes, r_3.  --compare-fp32 times
+                   the plain FP32 on-the-fly path on the same problem;
+                   --check-fp64 runs the FP64 path on the same probes.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -23,12 +32,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-import numpy as np  # noqa: E402
-
 import workloads  # noqa: E402
 
 METRIC = "log-det estimates/s at ≤1e-3 rel err vs FP64; mixed/batched vs plain FP32"
-PEAKS = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12}
+PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "bf16": 2.5e15}
+WORKLOADS = {"c2_matern_gm50k": workloads.C2, "c1_rbf_2k": workloads.C1,
+             "c3_matern_200k": workloads.C3}
 
 
 def log(*a):
@@ -42,34 +51,91 @@ def load_exact(name):
     return json.load(open(p)).get(name, {}).get("logdet")
 
 
-def cpu_baseline(cfg, sample_n: int, orders, precision_f32: bool):
+def cpu_baseline(cfg, sample_n: int):
     """The oracle on a bounded sample: the same workload recipe at sample_n
     points, timed on this host; the rate is scaled to the full n by the
     oracle's O(n^3) dense-factorization cost."""
     from oracle import estimate as oest
     from oracle import gp, precond
-    sub = cfg.with_n(sample_n)
+    sub = cfg.with_n(sample_n, rank=min(cfg.rank, sample_n // 10))
     t0 = time.perf_counter()
     X = sub.X()
     M = gp.dense_matrix(sub.kind, X, sub.lengthscale, sub.variance, sub.noise)
     P = precond.rsvd(M, sub.rank, sub.oversample, sub.power_iters, sub.precond_seed,
                      precond.d_floor(sub.noise, sub.variance))
     Pd = P.dense()
-    for k in orders:
+    for k in cfg.orders:
         Z = oest.probes(sub.probe_seed + k, sub.n, sub.probes)
         oest.estimate_dense(M, Pd, P.logdet, k, Z)
     dt = time.perf_counter() - t0
     scale = (cfg.n / sample_n) ** 3
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {
-        "value": len(orders) / (dt * scale),
+        "value": len(cfg.orders) / (dt * scale),
         "unit": "log-det estimates/s",
         "cores": threads,
         "kind": "oracle",
         "sample": (f"oracle (FP64 numpy/scipy, dense Cholesky shifted solves) on the same recipe at "
-                   f"n={sample_n}: {len(orders)} estimates in {dt:.2f} s; scaled to n={cfg.n} by "
-                   f"(n/{sample_n})^3"),
+                   f"n={sample_n}, rank {sub.rank}: {len(cfg.orders)} estimates in {dt:.2f} s; "
+                   f"scaled to n={cfg.n} by (n/{sample_n})^3"),
     }
+
+
+class Runner:
+    """One problem instance on the GPU in a given arithmetic."""
+
+    def __init__(self, L, torch, ctx, cfg, precision, stored):
+        self.L, self.torch, self.ctx, self.cfg = L, torch, ctx, cfg
+        dev = torch.device("cuda:0")
+        X = torch.as_tensor(cfg.X(), dtype=torch.float64, device=dev).contiguous()
+        self.stored = stored
+        self.op = L.GPOperator(X=X, kind=cfg.kind, lengthscale=cfg.lengthscale,
+                               variance=cfg.variance, noise=cfg.noise, precision=precision,
+                               layout=L.LD_TILED if stored else L.LD_ROW_MAJOR)
+        self.Mbuf = None
+        if stored:
+            self.Mbuf = torch.empty((L.stored_elements(cfg.n, self.op.layout),),
+                                    dtype=torch.float32 if precision != L.LD_F64 else torch.float64,
+                                    device=dev)
+        self.tol = 1e-12 if precision == L.LD_F64 else 1e-6
+
+    def step(self):
+        L, cfg, op = self.L, self.cfg, self.op
+        out = {}
+        if self.stored:
+            op.M = None
+            L.kernel_materialize(self.ctx, op, out=self.Mbuf)
+            op.M = self.Mbuf
+        P = L.Precond(self.ctx, op, cfg.rank, cfg.oversample, cfg.power_iters, cfg.precond_seed)
+        for k in cfg.orders:
+            res, per = L.logdet_estimate(self.ctx, op, P, k, cfg.probes, cfg.probe_seed + k,
+                                         self.tol, 5000)
+            out[k] = res
+        P.close()
+        return out
+
+
+def timed_steps(runner, steps, warmup, stream, torch):
+    for w in range(warmup):
+        t0 = time.perf_counter()
+        runner.step()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {w} {time.perf_counter() - t0:.3f} s")
+    runner.ctx.set_timing(True)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    t0 = time.perf_counter()
+    results = []
+    for i in range(steps):
+        results.append(runner.step())
+        log(f"[bench] step {i} done {time.perf_counter() - t0:.3f} s")
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    timing = runner.ctx.read_timing()
+    runner.ctx.set_timing(False)
+    return results, ms, time.perf_counter() - t0, timing
 
 
 def main():
@@ -77,10 +143,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2_matern_gm50k", choices=["c2_matern_gm50k", "c1_rbf_2k"])
-    ap.add_argument("--n", type=int, default=0, help="override n (testing only)")
+    ap.add_argument("--workload", default="c2_matern_gm50k", choices=sorted(WORKLOADS))
+    ap.add_argument("--n", type=int, default=0, help="override n (smaller test runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=8000)
+    ap.add_argument("--compare-fp32", action="store_true",
+                    help="precision form: also time the plain FP32 on-the-fly path")
+    ap.add_argument("--check-fp64", action="store_true",
+                    help="precision form: also run the FP64 path on the same probes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1"}))
@@ -89,71 +159,30 @@ def main():
     import torch
     import paper_2405_03474_amd as L
 
-    cfg = {"c2_matern_gm50k": workloads.C2, "c1_rbf_2k": workloads.C1}[args.workload]
+    cfg = WORKLOADS[args.workload]
     if args.n:
         cfg = cfg.with_n(args.n, rank=min(cfg.rank, args.n // 10))
-    f32 = cfg.name.startswith("c2")
-    prec = L.LD_F32 if f32 else L.LD_F64
-    tol = 1e-6 if f32 else 1e-12
-    stored = f32
+    kind = args.workload.split("_")[0]
+    precision = {"c1": L.LD_F64, "c2": L.LD_F32, "c3": L.LD_BF16}[kind]
+    stored = kind == "c2"
+    dtype = {L.LD_F64: "f64", L.LD_F32: "f32", L.LD_BF16: "bf16x3+f32"}[precision]
     log(f"[bench] workload {cfg.name} n={cfg.n} rank={cfg.rank} probes={cfg.probes} "
-        f"orders={cfg.orders} precision={'f32' if f32 else 'f64'} stored={stored}")
+        f"orders={cfg.orders} dtype={dtype} stored={stored}")
 
-    dev = torch.device("cuda:0")
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream(0)
     ctx = L.Context(0, stream)
-    X = torch.as_tensor(cfg.X(), dtype=torch.float64, device=dev).contiguous()
-    op = L.GPOperator(X=X, kind=cfg.kind, lengthscale=cfg.lengthscale, variance=cfg.variance,
-                      noise=cfg.noise, precision=prec,
-                      layout=L.LD_TILED if stored else L.LD_ROW_MAJOR)
-    Mbuf = torch.empty((L.stored_elements(cfg.n, op.layout),),
-                       dtype=torch.float32 if f32 else torch.float64, device=dev) if stored else None
-
-    def step():
-        out = {}
-        if stored:
-            op.M = None
-            L.kernel_materialize(ctx, op, out=Mbuf)
-            op.M = Mbuf
-        P = L.Precond(ctx, op, cfg.rank, cfg.oversample, cfg.power_iters, cfg.precond_seed)
-        for k in cfg.orders:
-            res, _ = L.logdet_estimate(ctx, op, P, k, cfg.probes, cfg.probe_seed + k, tol, 5000)
-            out[k] = res
-        P.close()
-        return out
-
-    for w in range(args.warmup):
-        t0 = time.perf_counter()
-        step()
-        torch.cuda.synchronize()
-        log(f"[bench] warmup {w} {time.perf_counter() - t0:.3f} s")
-
-    ctx.set_timing(True)
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(stream)
-    t0 = time.perf_counter()
-    results = []
-    for i in range(args.steps):
-        results.append(step())
-        log(f"[bench] step {i} done {time.perf_counter() - t0:.3f} s")
-    stop.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_total = start.elapsed_time(stop)
-    mm_ms, mm_calls, mm_flops, mm_bytes = ctx.read_timing()
-    ctx.set_timing(False)
+    runner = Runner(L, torch, ctx, cfg, precision, stored)
+    results, ms_total, wall, (mm_ms, mm_calls, mm_flops, mm_bytes) = timed_steps(
+        runner, args.steps, args.warmup, stream, torch)
 
     n_est = args.steps * len(cfg.orders)
     value = n_est / (ms_total / 1e3)
-    iters = {f"r{k}": results[-1][k]["iterations"] for k in cfg.orders}
-    probe_solves = sum(results[-1][k]["num_probes"] for k in cfg.orders) * args.steps / (ms_total / 1e3)
-
+    last = results[-1]
     exact = load_exact(cfg.name) if not args.n else None
     accuracy = {}
     for k in cfg.orders:
-        r = results[-1][k]
+        r = last[k]
         acc = {"logdet": r["logdet"], "logdet_P": r["logdet_P"], "stderr": r["std_err"],
                "iterations": r["iterations"], "rel_resid": r["rel_resid"]}
         if exact is not None:
@@ -164,33 +193,54 @@ def main():
 
     avg_ms = mm_ms / max(mm_calls, 1)
     achieved = (mm_flops / max(mm_calls, 1)) / (avg_ms / 1e3)
-    peak = PEAKS["fp32"] if f32 else PEAKS["fp64"]
+    peak = {L.LD_F32: PEAK["fp32"], L.LD_F64: PEAK["fp64"], L.LD_BF16: PEAK["bf16"]}[precision]
+    kname = {"c2": "k_mm32_st<2,tiled> (FP32 MFMA 32x32x2, stored tiled M)",
+             "c1": "k_mm64<fly> (FP64 MFMA 16x16x4, on the fly)",
+             "c3": "k_mm16<fly> (split-BF16 MFMA 32x32x16, 3 terms, on the fly)"}[kind]
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None,
-                "kernel": "k_mm32_st<2,tiled> (FP32 MFMA 32x32x2)" if f32 else "k_mm64<on the fly> (FP64 MFMA)",
+                "frac": achieved / peak, "traffic": None, "kernel": kname,
                 "avg_launch_ms": avg_ms, "launches": mm_calls,
-                "hbm_GBps_algorithmic": (mm_bytes / max(mm_calls, 1)) / (avg_ms / 1e3) / 1e9}
+                "algorithmic_GBps": (mm_bytes / max(mm_calls, 1)) / (avg_ms / 1e3) / 1e9}
 
     line = {
         "metric": METRIC, "value": value, "unit": "log-det estimates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_total / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if f32 else "f64", "data": "synthetic",
+        "dtype": dtype, "data": "synthetic",
         "config": {"workload": cfg.name, "n": cfg.n, "d": cfg.d,
-                   "kernel": "matern52" if cfg.kind == 1 else "rbf",
-                   "points": cfg.points, "lengthscale": cfg.lengthscale, "variance": cfg.variance,
-                   "noise": cfg.noise,
-                   "storage": "stored_fp32_tiled" if stored else "on_the_fly",
+                   "kernel": "matern52" if cfg.kind == 1 else "rbf", "points": cfg.points,
+                   "lengthscale": cfg.lengthscale, "variance": cfg.variance, "noise": cfg.noise,
+                   "storage": "stored_tiled" if stored else "on_the_fly",
                    "orders": list(cfg.orders), "probes": cfg.probes, "rank": cfg.rank,
-                   "oversample": cfg.oversample, "power_iters": cfg.power_iters, "tol": tol},
-        "probe_solves_per_s": probe_solves, "iterations": iters, "wall_s": wall,
-        "accuracy": accuracy, "roofline": roofline,
+                   "oversample": cfg.oversample, "power_iters": cfg.power_iters,
+                   "tol": runner.tol},
+        "probe_solves_per_s": cfg.probes * n_est / (ms_total / 1e3),
+        "iterations": {f"r{k}": last[k]["iterations"] for k in cfg.orders},
+        "wall_s": wall, "accuracy": accuracy, "roofline": roofline,
     }
-    if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle) ...")
-        line["cpu_baseline"] = cpu_baseline(cfg, min(args.cpu_sample_n, cfg.n), cfg.orders, f32)
-    else:
+
+    if kind == "c3" and args.compare_fp32:
+        log("[bench] plain FP32 on-the-fly path, same problem")
+        plain = Runner(L, torch, ctx, cfg, L.LD_F32, False)
+        pres, pms, _, _ = timed_steps(plain, 1, 0, stream, torch)
+        pv = len(cfg.orders) / (pms / 1e3)
+        line["plain_fp32"] = {"value": pv, "ms_per_step": pms,
+                              "logdet": {f"r{k}": pres[-1][k]["logdet"] for k in cfg.orders}}
+        line["speedup_vs_plain_fp32"] = value / pv
+    if kind == "c3" and args.check_fp64:
+        log("[bench] FP64 reference run on the same probes")
+        ref = Runner(L, torch, ctx, cfg, L.LD_F64, False)
+        rres = ref.step()
+        line["fp64_reference"] = {
+            f"r{k}": {"logdet": rres[k]["logdet"],
+                      "rel_err": abs(last[k]["logdet"] - rres[k]["logdet"]) / abs(rres[k]["logdet"]),
+                      "iterations": rres[k]["iterations"]} for k in cfg.orders}
+
+    if args.no_cpu_baseline:
         line["cpu_baseline"] = None
+    else:
+        log("[bench] cpu baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline(cfg, min(args.cpu_sample_n, cfg.n))
     print(json.dumps(line), flush=True)
     ctx.close()
 

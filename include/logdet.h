@@ -52,8 +52,14 @@ typedef enum { LD_RBF = 0, LD_MATERN52 = 1 } ld_kernel;
 
 /* Arithmetic of the kernel-matrix products and of the solver vectors.
  * Scalar recurrences, reductions, the preconditioner's small dense algebra
- * and log det P are FP64 in every mode. */
-typedef enum { LD_F64 = 0, LD_F32 = 1 } ld_precision;
+ * and log det P are FP64 in every mode.
+ *  LD_F64  FP64 products (FP64 matrix cores) and vectors.
+ *  LD_F32  FP32 products (FP32 matrix cores) and vectors.
+ *  LD_BF16 precision form, on the fly only: kernel values and distances in
+ *          FP32, each operand split into bf16 hi + lo parts, products
+ *          hi*hi + hi*lo + lo*hi on BF16 matrix cores with FP32
+ *          accumulation; vectors FP32 (vector buffers use FP32). */
+typedef enum { LD_F64 = 0, LD_F32 = 1, LD_BF16 = 2 } ld_precision;
 
 /* The matrix M = K(X, X) + noise * I (Section 3 kernels; formulas are the
  * textbook ones: RBF k(r) = variance * exp(-r^2 / (2 l^2)); Matern-5/2

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "liblogdet.so")
 
 LD_OK, LD_EINVAL, LD_ENOTSPD, LD_ENOCONV, LD_EHIP, LD_ENOMEM = 0, -1, -2, -3, -4, -5
 LD_RBF, LD_MATERN52 = 0, 1
-LD_F64, LD_F32 = 0, 1
+LD_F64, LD_F32, LD_BF16 = 0, 1, 2
 LD_ROW_MAJOR, LD_TILED = 0, 1
 
 STATUS_NAMES = {0: "LD_OK", -1: "LD_EINVAL", -2: "LD_ENOTSPD", -3: "LD_ENOCONV", -4: "LD_EHIP",

@@ -113,8 +113,10 @@ ld_status check_operator(const ld_operator* op) {
     return fail(LD_EINVAL, "variance must be finite and > 0");
   if (!(op->noise >= 0.0) || !std::isfinite(op->noise))
     return fail(LD_EINVAL, "noise must be finite and >= 0");
-  if (op->precision != LD_F64 && op->precision != LD_F32)
-    return fail(LD_EINVAL, "precision must be LD_F64 or LD_F32");
+  if (op->precision != LD_F64 && op->precision != LD_F32 && op->precision != LD_BF16)
+    return fail(LD_EINVAL, "precision must be LD_F64, LD_F32 or LD_BF16");
+  if (op->precision == LD_BF16 && op->M_stored)
+    return fail(LD_EINVAL, "LD_BF16 generates the kernel on the fly (M_stored must be NULL)");
   if (op->layout != LD_ROW_MAJOR && op->layout != LD_TILED)
     return fail(LD_EINVAL, "layout must be LD_ROW_MAJOR or LD_TILED");
   if (op->layout == LD_TILED && op->precision != LD_F32)
@@ -146,6 +148,7 @@ MatmatArgs base_args(const ld_operator* op, const void* X) {
   a.kp = make_kparams(*op);
   a.A = op->M_stored;
   a.layout = op->layout;
+  a.bf16 = op->precision == LD_BF16;
   a.X = X;
   return a;
 }
@@ -539,7 +542,8 @@ ld_status ld_rational_coeffs(int32_t k, double* b, double* a, double* c) {
 ld_status ld_fill_probes(ld_ctx* ctx, uint64_t seed, int64_t n, int64_t s, int32_t precision, void* Z) {
   LD_TRY(check_ctx(ctx));
   if (n < 1 || s < 1 || !Z) return fail(LD_EINVAL, "bad probe block arguments");
-  if (precision != LD_F64 && precision != LD_F32) return fail(LD_EINVAL, "bad precision");
+  if (precision != LD_F64 && precision != LD_F32 && precision != LD_BF16)
+    return fail(LD_EINVAL, "bad precision");
   launch_fill_rademacher(ctx->stream, stream_key(seed, kStreamProbes), n, s, precision == LD_F64, Z);
   LD_HIP(hipGetLastError());
   return LD_OK;
@@ -616,7 +620,8 @@ ld_status ld_precond_apply_inverse(ld_ctx* ctx, const ld_precond* P, const void*
   LD_TRY(check_ctx(ctx));
   if (!P || !R || !OUT || s < 1) return fail(LD_EINVAL, "bad arguments");
   if (R == OUT) return fail(LD_EINVAL, "OUT must not alias R");
-  if (precision != LD_F64 && precision != LD_F32) return fail(LD_EINVAL, "bad precision");
+  if (precision != LD_F64 && precision != LD_F32 && precision != LD_BF16)
+    return fail(LD_EINVAL, "bad precision");
   ctx->arena.reset();
   LD_TRY(ctx->arena.reserve(woodbury_scratch_bytes(P->n, P->rank, s)));
   return woodbury_apply(ctx, P, precision == LD_F64, R, s, OUT);

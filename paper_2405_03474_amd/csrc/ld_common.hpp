@@ -137,6 +137,7 @@ struct MatmatArgs {
   double* dots = nullptr;    // optional
   int* dot_blocks = nullptr;
   bool timed = false;        // record events around the product kernel (ctx->timing)
+  bool bf16 = false;         // FP32 path: split-BF16 matrix-core product on the fly
 };
 ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a);
 size_t matmat_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int64_t s);

@@ -19,6 +19,8 @@
 // The k index inside a stage is permuted so that every lane reads contiguous
 // LDS words: in MFMA k-step t, lane half h supplies physical column
 // h * (BK / halves) + t for both operands.
+#include <algorithm>
+
 #include "ld_common.hpp"
 
 namespace ld {
@@ -66,11 +68,18 @@ __host__ __device__ inline WGRange wg_range(const SK& p, int g) {
 
 // ---------------------------------------------------------- kernel values --
 // FP32: RBF c = log2(e) / (2 l^2);  Matern-5/2 c = sqrt(5) / l
+// Constants are folded into base-2 exponents:
+//   RBF     c = log2(e) / (2 l^2),  v = log2(variance):  2^(v - c r^2)
+//   Matern  c = sqrt(5) log2(e) / l, v = variance: with u = c r (= t log2 e,
+//           t = sqrt5 r / l), variance (1 + t + t^2/3) e^-t
+//           = (v + u v / log2e + u^2 v / (3 log2e^2)) 2^-u
 template <int KIND>
-__device__ __forceinline__ float kval32(float r2, float var, float c) {
-  if (KIND == LD_RBF) return var * __builtin_amdgcn_exp2f(-r2 * c);
-  float t = __builtin_amdgcn_sqrtf(r2) * c;
-  return var * (1.0f + t + t * t * (1.0f / 3.0f)) * __builtin_amdgcn_exp2f(-t * kLog2e);
+__device__ __forceinline__ float kval32(float r2, float v, float c) {
+  if (KIND == LD_RBF) return __builtin_amdgcn_exp2f(__builtin_fmaf(-r2, c, v));
+  const float u = __builtin_amdgcn_sqrtf(r2) * c;
+  const float p = __builtin_fmaf(
+      u, __builtin_fmaf(u, v * (1.0f / (3.0f * kLog2e * kLog2e)), v * (1.0f / kLog2e)), v);
+  return p * __builtin_amdgcn_exp2f(-u);
 }
 // FP64: RBF c = 1 / (2 l^2);  Matern-5/2 c = sqrt(5) / l
 template <int KIND>
@@ -81,20 +90,56 @@ __device__ __forceinline__ double kval64(double r2, double var, double c) {
 }
 
 
-// ------------------------------------------------------------ FP32 path --
-template <int NB, bool FLY, int KIND, int DT>
-__global__ __launch_bounds__(256, 2) void k_mm32(const float* __restrict__ A,
-                                                 const float* __restrict__ Xp, int d, float var,
-                                                 float c, const float* __restrict__ V,
-                                                 float* __restrict__ part, SK p) {
-  constexpr int NT = 32 * NB;
-  constexpr int BS = NT + 2;   // B row stride: halves of a wave land 32 banks apart
-  constexpr int AS = BK + 4;   // A row stride: conflict-free 16-byte fragment reads
-  __shared__ __attribute__((aligned(16))) float As[FLY ? 4 : BM * AS];
-  __shared__ float Bs[BK * BS];
-  __shared__ float Xs[FLY ? BK * DMAX : 1];
-  const int dd_n = DT > 0 ? DT : d;
+// ---------------------------------------------------- FP32 on the fly --
+// Every lane evaluates its own A-fragment entries k(x_i, x_k) in FP32 (row
+// point in registers, the stage's 32 points in LDS); B is transposed in LDS,
+// double buffered, with the next stage (B tile and points) prefetched into
+// registers while the current stage's MFMAs run.
+template <int NB>
+struct FlyTile {
+  float v[4 * NB];  // 32 x 32*NB V tile
+  float x[2];       // stage points (32 x d <= 32 x 16 floats over 256 threads)
+};
 
+template <int NB, int DT>
+__device__ __forceinline__ void fly_load(FlyTile<NB>& t, const float* __restrict__ Xp, int d,
+                                         const float* __restrict__ V, int64_t n, int64_t s,
+                                         int64_t c0, int64_t k0, int tid) {
+  constexpr int NT = 32 * NB;
+  constexpr int KSTEP = 256 / NT;  // k rows between a thread's consecutive loads
+  const int dd_n = DT > 0 ? DT : d;
+  // load j of this thread: column c0 + tid % NT, row k0 + tid / NT + KSTEP j
+  const int64_t col = c0 + tid % NT;
+  const int64_t kr0 = k0 + tid / NT;
+  const float* p = V + kr0 * s + col;
+  const int64_t step = (int64_t)KSTEP * s;
+  if (col < s && k0 + BK <= n) {
+#pragma unroll
+    for (int j = 0; j < 4 * NB; ++j) t.v[j] = p[j * step];
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4 * NB; ++j)
+      t.v[j] = (col < s && kr0 + KSTEP * j < n) ? p[j * step] : 0.f;
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int e = tid + 256 * j;
+    const int kk = e / DMAX, dd = e % DMAX;
+    const int64_t kr = k0 + kk;
+    t.x[j] = (dd < dd_n && kr < n) ? Xp[kr * dd_n + dd] : 0.f;
+  }
+}
+
+template <int NB, int KIND, int DT>
+__global__ __launch_bounds__(256, 2) void k_mm32_fly(const float* __restrict__ Xp, int d,
+                                                     float var, float c,
+                                                     const float* __restrict__ V,
+                                                     float* __restrict__ part, SK p) {
+  constexpr int NT = 32 * NB;
+  constexpr int AS = BK + 4;
+  __shared__ __attribute__((aligned(16))) float Bt[2][NT * AS];
+  __shared__ float Xs[2][BK * DMAX];
+  const int dd_n = DT > 0 ? DT : d;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 31, lh = lane >> 5;
@@ -110,92 +155,69 @@ __global__ __launch_bounds__(256, 2) void k_mm32(const float* __restrict__ A,
     const int l1 = (int)((int64_t)wr.Sx < l0 + (uend - u) ? (int64_t)wr.Sx : l0 + (uend - u));
     const int st0 = wr.sb + l0, st1 = wr.sb + l1;
     const int rtile = (int)(T % p.rt);
-    const int64_t ctile = T / p.rt;
     const int64_t i0 = (int64_t)rtile * BM;
-    const int64_t c0 = ctile * NT;
+    const int64_t c0 = (T / p.rt) * NT;
 
     f32x16 acc[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
-
-    float xr[FLY ? DMAX : 1];
-    if (FLY) {
+    float xr[DMAX];
+    {
       const int64_t row = i0 + 32 * wave + li;
 #pragma unroll
       for (int dd = 0; dd < DMAX; ++dd)
         if (dd < dd_n) xr[dd] = row < n ? Xp[row * dd_n + dd] : 0.f;
     }
 
+    FlyTile<NB> tl;
+    fly_load<NB, DT>(tl, Xp, d, V, n, s, c0, (int64_t)st0 * BK, tid);
+    __syncthreads();  // the previous segment is done with both buffers
+    int buf = 0;
     for (int st = st0; st < st1; ++st) {
-      const int64_t k0 = (int64_t)st * BK;
-      __syncthreads();
-      for (int e = tid; e < BK * NT; e += 256) {
-        const int kk = e / NT, cc = e - kk * NT;
-        const int64_t kr = k0 + kk, col = c0 + cc;
-        Bs[kk * BS + cc] = (kr < n && col < s) ? V[kr * s + col] : 0.f;
-      }
-      if (FLY) {
-        for (int e = tid; e < BK * dd_n; e += 256) {
-          const int kk = e / dd_n, dd = e - kk * dd_n;
-          const int64_t kr = k0 + kk;
-          Xs[kk * DMAX + dd] = kr < n ? Xp[kr * dd_n + dd] : 0.f;
-        }
-      } else {
-        const bool vec_ok = (n & 3) == 0;
-        for (int e = tid; e < BM * (BK / 4); e += 256) {
-          const int rr = e / (BK / 4), kq = e - rr * (BK / 4);
-          const int64_t row = i0 + rr, kc = k0 + 4 * kq;
-          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (row < n) {
-            const float* src = A + row * n + kc;
-            if (vec_ok && kc + 3 < n) {
-              v = *(const float4*)src;
-            } else {
-              if (kc + 0 < n) v.x = src[0];
-              if (kc + 1 < n) v.y = src[1];
-              if (kc + 2 < n) v.z = src[2];
-              if (kc + 3 < n) v.w = src[3];
-            }
-          }
-          *(float4*)&As[rr * AS + 4 * kq] = v;
-        }
-      }
-      __syncthreads();
-
-      float a[16];
-      if (FLY) {
+      float* bt = Bt[buf];
+      float* xs = Xs[buf];
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-          const float* xk = &Xs[(lh * 16 + t) * DMAX];
-          float r2 = 0.f;
+      for (int j = 0; j < 4 * NB; ++j) {
+        const int e = tid + 256 * j;
+        bt[(e % NT) * AS + e / NT] = tl.v[j];
+      }
 #pragma unroll
-          for (int dd = 0; dd < DMAX; ++dd)
-            if (dd < dd_n) {
-              const float df = xr[dd] - xk[dd];
-              r2 = __builtin_fmaf(df, df, r2);
-            }
-          a[t] = kval32<KIND>(r2, var, c);
-        }
-      } else {
-        const float4* ap = (const float4*)&As[(32 * wave + li) * AS + lh * 16];
+      for (int j = 0; j < 2; ++j) xs[tid + 256 * j] = tl.x[j];
+      __syncthreads();
+      if (st + 1 < st1) fly_load<NB, DT>(tl, Xp, d, V, n, s, c0, (int64_t)(st + 1) * BK, tid);
+      float a[16], b[NB][16];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float4* bp = (const float4*)&bt[(nb * 32 + li) * AS + lh * 16];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const float4 v = ap[q];
-          a[4 * q + 0] = v.x;
-          a[4 * q + 1] = v.y;
-          a[4 * q + 2] = v.z;
-          a[4 * q + 3] = v.w;
+          const float4 v = bp[q];
+          b[nb][4 * q + 0] = v.x;
+          b[nb][4 * q + 1] = v.y;
+          b[nb][4 * q + 2] = v.z;
+          b[nb][4 * q + 3] = v.w;
         }
       }
 #pragma unroll
       for (int t = 0; t < 16; ++t) {
-        const float* brow = &Bs[(lh * 16 + t) * BS + li];
+        const float* xk = &xs[(lh * 16 + t) * DMAX];
+        float r2 = 0.f;
+#pragma unroll
+        for (int dd = 0; dd < DMAX; ++dd)
+          if (dd < dd_n) {
+            const float df = xr[dd] - xk[dd];
+            r2 = __builtin_fmaf(df, df, r2);
+          }
+        a[t] = kval32<KIND>(r2, var, c);
+      }
+#pragma unroll
+      for (int t = 0; t < 16; ++t)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
-          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t], brow[nb * 32], acc[nb], 0, 0, 0);
-      }
+          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t], b[nb][t], acc[nb], 0, 0, 0);
+      buf ^= 1;
     }
 
     float* dst = part + ((int64_t)blockIdx.x * p.J + seg) * (int64_t)(BM * NT);
@@ -372,6 +394,202 @@ __global__ __launch_bounds__(256, 2) void k_mm32_st(const float* __restrict__ A,
       if (st + 3 < st1)
         st_load<NB, TILED>(tb, A, V, n, s, i0, c0, (int64_t)(st + 3) * BK, tid, a_vec, p.S);
       st_compute<NB>(As[1], Bt[1], acc, wave, li, lh);
+    }
+
+    float* dst = part + ((int64_t)blockIdx.x * p.J + seg) * (int64_t)(BM * NT);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 32 * wave + 8 * (r >> 2) + 4 * lh + (r & 3);
+        dst[row * NT + nb * 32 + li] = acc[nb][r];
+      }
+    ++seg;
+    u += st1 - st0;
+  }
+}
+
+// ------------------------------------------------- split-BF16 on the fly --
+// Precision form of the on-the-fly product: each FP32 kernel value and each
+// FP32 entry of V is split into bf16 hi + lo parts and the product takes the
+// three significant terms hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16
+// with FP32 accumulation (relative error of a term about 2^-16 instead of the
+// 2^-8 of one BF16 rounding, which would perturb M by far more than the
+// noise variance).  Kernel values and distances are computed in FP32 by the
+// lane that feeds them to the matrix core.  Stage = 64 k (4 MFMA k-steps of
+// 16); in k-step q lane half h supplies k = 16 q + 8 h + j, j = 0..7, for both
+// operands.  B (hi and lo) is kept transposed in LDS, double buffered, with
+// the next stage prefetched into registers.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+constexpr int BK16 = 64;
+
+// x -> bf16 hi + bf16 lo (round to nearest both times) for a pair of values,
+// packed two per 32-bit word (element 0 in the low half)
+__device__ __forceinline__ void split2(float x0, float x1, uint32_t& hi, uint32_t& lo) {
+  const f32x2 v = {x0, x1};
+  hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+  const float h0 = __builtin_bit_cast(float, hi << 16);
+  const float h1 = __builtin_bit_cast(float, hi & 0xffff0000u);
+  const f32x2 r = {x0 - h0, x1 - h1};
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2));
+}
+constexpr int BS16 = BK16 + 8;  // bf16 row stride of transposed B (144 bytes)
+
+template <int NB>
+struct F16Tile {
+  float v[8 * NB];  // 64 x 32*NB V tile: pairs of consecutive k for one column
+  float x[4];       // stage points (64 x d <= 64 x 16 floats over 256 threads)
+};
+
+template <int NB, int DT>
+__device__ __forceinline__ void f16_load(F16Tile<NB>& t, const float* __restrict__ Xp, int d,
+                                         const float* __restrict__ V, int64_t n, int64_t s,
+                                         int64_t c0, int64_t k0, int tid) {
+  constexpr int NT = 32 * NB;
+  constexpr int KSTEP = 2 * (256 / NT);  // k rows between a thread's consecutive pairs
+  const int dd_n = DT > 0 ? DT : d;
+  // pair j of this thread: column c0 + tid % NT, rows k0 + 2 (tid / NT) + KSTEP j (+1)
+  const int64_t col = c0 + tid % NT;
+  const int64_t kr0 = k0 + 2 * (tid / NT);
+  const float* p = V + kr0 * s + col;
+  const int64_t step = (int64_t)KSTEP * s;
+  if (col < s && k0 + BK16 <= n) {
+#pragma unroll
+    for (int j = 0; j < 4 * NB; ++j) {
+      t.v[2 * j] = p[j * step];
+      t.v[2 * j + 1] = p[j * step + s];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4 * NB; ++j) {
+      const int64_t kr = kr0 + KSTEP * j;
+      t.v[2 * j] = (col < s && kr < n) ? p[j * step] : 0.f;
+      t.v[2 * j + 1] = (col < s && kr + 1 < n) ? p[j * step + s] : 0.f;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int e = tid + 256 * j;
+    const int kk = e / DMAX, dd = e % DMAX;
+    const int64_t kr = k0 + kk;
+    t.x[j] = (dd < dd_n && kr < n) ? Xp[kr * dd_n + dd] : 0.f;
+  }
+}
+
+template <int NB>
+__device__ __forceinline__ void f16_store(const F16Tile<NB>& t, __bf16* __restrict__ bh,
+                                          __bf16* __restrict__ bl, float* __restrict__ xs,
+                                          int tid) {
+  constexpr int NT = 32 * NB;
+#pragma unroll
+  for (int j = 0; j < 4 * NB; ++j) {
+    const int e = tid + 256 * j;
+    const int cc = e % NT, kp = e / NT;
+    uint32_t h, l;
+    split2(t.v[2 * j], t.v[2 * j + 1], h, l);
+    *(uint32_t*)&bh[cc * BS16 + 2 * kp] = h;
+    *(uint32_t*)&bl[cc * BS16 + 2 * kp] = l;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) xs[tid + 256 * j] = t.x[j];
+}
+
+template <int NB, int KIND, int DT>
+__device__ __forceinline__ void f16_compute(const __bf16* __restrict__ bh,
+                                            const __bf16* __restrict__ bl,
+                                            const float* __restrict__ xs, const float* xr, int d,
+                                            float var, float c, f32x16* acc, int li, int lh) {
+  const int dd_n = DT > 0 ? DT : d;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    float kv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float* xk = &xs[(16 * q + 8 * lh + j) * DMAX];
+      float r2 = 0.f;
+#pragma unroll
+      for (int dd = 0; dd < DMAX; ++dd)
+        if (dd < dd_n) {
+          const float df = xr[dd] - xk[dd];
+          r2 = __builtin_fmaf(df, df, r2);
+        }
+      kv[j] = kval32<KIND>(r2, var, c);
+    }
+    u32x4 hw, lw;
+#pragma unroll
+    for (int jp = 0; jp < 4; ++jp) {
+      uint32_t h, l;
+      split2(kv[2 * jp], kv[2 * jp + 1], h, l);
+      hw[jp] = h;
+      lw[jp] = l;
+    }
+    const bf16x8 ah = __builtin_bit_cast(bf16x8, hw);
+    const bf16x8 al = __builtin_bit_cast(bf16x8, lw);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int off = (nb * 32 + li) * BS16 + 16 * q + 8 * lh;
+      const bf16x8 bhv = *(const bf16x8*)&bh[off];
+      const bf16x8 blv = *(const bf16x8*)&bl[off];
+      acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bhv, acc[nb], 0, 0, 0);
+      acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, blv, acc[nb], 0, 0, 0);
+      acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bhv, acc[nb], 0, 0, 0);
+    }
+  }
+}
+
+template <int NB, int KIND, int DT>
+__global__ __launch_bounds__(256, 2) void k_mm16(const float* __restrict__ Xp, int d, float var,
+                                                 float c, const float* __restrict__ V,
+                                                 float* __restrict__ part, SK p) {
+  constexpr int NT = 32 * NB;
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[2][NT * BS16];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[2][NT * BS16];
+  __shared__ float Xs[2][BK16 * DMAX];
+  const int dd_n = DT > 0 ? DT : d;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, lh = lane >> 5;
+  const int64_t n = p.n, s = p.s;
+
+  const WGRange wr = wg_range(p, blockIdx.x);
+  int64_t u = wr.u;
+  const int64_t uend = wr.uend;
+  int seg = 0;
+  while (u < uend) {
+    const int64_t T = u / wr.Sx;
+    const int l0 = (int)(u - T * wr.Sx);
+    const int l1 = (int)((int64_t)wr.Sx < l0 + (uend - u) ? (int64_t)wr.Sx : l0 + (uend - u));
+    const int st0 = wr.sb + l0, st1 = wr.sb + l1;
+    const int rtile = (int)(T % p.rt);
+    const int64_t i0 = (int64_t)rtile * BM;
+    const int64_t c0 = (T / p.rt) * NT;
+
+    f32x16 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
+    float xr[DMAX];
+    {
+      const int64_t row = i0 + 32 * wave + li;
+#pragma unroll
+      for (int dd = 0; dd < DMAX; ++dd)
+        if (dd < dd_n) xr[dd] = row < n ? Xp[row * dd_n + dd] : 0.f;
+    }
+
+    F16Tile<NB> tl;
+    f16_load<NB, DT>(tl, Xp, d, V, n, s, c0, (int64_t)st0 * BK16, tid);
+    __syncthreads();  // the previous segment is done with both buffers
+    int buf = 0;
+    for (int st = st0; st < st1; ++st) {
+      f16_store<NB>(tl, Bh[buf], Bl[buf], Xs[buf], tid);
+      __syncthreads();
+      if (st + 1 < st1) f16_load<NB, DT>(tl, Xp, d, V, n, s, c0, (int64_t)(st + 1) * BK16, tid);
+      f16_compute<NB, KIND, DT>(Bh[buf], Bl[buf], Xs[buf], xr, d, var, c, acc, li, lh);
+      buf ^= 1;
     }
 
     float* dst = part + ((int64_t)blockIdx.x * p.J + seg) * (int64_t)(BM * NT);
@@ -673,7 +891,7 @@ struct Plan {
   size_t part_bytes;
 };
 
-Plan make_plan(ld_ctx* ctx, bool f64, int64_t n, int64_t s) {
+Plan make_plan(ld_ctx* ctx, bool f64, int64_t n, int64_t s, int bk = BK) {
   Plan pl{};
   if (f64)
     pl.NT = s > 32 ? 64 : (s > 16 ? 32 : 16);
@@ -685,7 +903,7 @@ Plan make_plan(ld_ctx* ctx, bool f64, int64_t n, int64_t s) {
   p.rt = (int)((n + BM - 1) / BM);
   const int64_t ct = (s + pl.NT - 1) / pl.NT;
   p.tiles = (int64_t)p.rt * ct;
-  p.S = (int)((n + BK - 1) / BK);
+  p.S = (int)((n + bk - 1) / bk);
   const int64_t U = p.tiles * p.S;
   // one k chunk per XCD when the device has 8 (otherwise a single chunk), and
   // at least 4 stages per chunk
@@ -712,11 +930,9 @@ template <int KIND, int DT>
 void launch_fly32(int NB, dim3 g, hipStream_t st, const float* X, int d, float var, float c,
                   const float* V, float* part, const SK& p) {
   if (NB == 2)
-    hipLaunchKernelGGL((k_mm32<2, true, KIND, DT>), g, dim3(256), 0, st, nullptr, X, d, var, c, V,
-                       part, p);
+    hipLaunchKernelGGL((k_mm32_fly<2, KIND, DT>), g, dim3(256), 0, st, X, d, var, c, V, part, p);
   else
-    hipLaunchKernelGGL((k_mm32<1, true, KIND, DT>), g, dim3(256), 0, st, nullptr, X, d, var, c, V,
-                       part, p);
+    hipLaunchKernelGGL((k_mm32_fly<1, KIND, DT>), g, dim3(256), 0, st, X, d, var, c, V, part, p);
 }
 
 template <int KIND, int DT>
@@ -731,6 +947,26 @@ void launch_fly64(int NB, dim3 g, hipStream_t st, const double* X, int d, double
   else
     hipLaunchKernelGGL((k_mm64<1, true, KIND, DT>), g, dim3(256), 0, st, nullptr, X, d, var, c, V,
                        part, p);
+}
+
+template <int KIND, int DT>
+void launch_fly16(int NB, dim3 g, hipStream_t st, const float* X, int d, float var, float c,
+                  const float* V, float* part, const SK& p) {
+  if (NB == 2)
+    hipLaunchKernelGGL((k_mm16<2, KIND, DT>), g, dim3(256), 0, st, X, d, var, c, V, part, p);
+  else
+    hipLaunchKernelGGL((k_mm16<1, KIND, DT>), g, dim3(256), 0, st, X, d, var, c, V, part, p);
+}
+
+template <int KIND>
+void fly16_by_d(int NB, dim3 g, hipStream_t st, const float* X, int d, float var, float c,
+                const float* V, float* part, const SK& p) {
+  switch (d) {
+    case 2: launch_fly16<KIND, 2>(NB, g, st, X, d, var, c, V, part, p); break;
+    case 3: launch_fly16<KIND, 3>(NB, g, st, X, d, var, c, V, part, p); break;
+    case 8: launch_fly16<KIND, 8>(NB, g, st, X, d, var, c, V, part, p); break;
+    default: launch_fly16<KIND, 0>(NB, g, st, X, d, var, c, V, part, p); break;
+  }
 }
 
 template <int KIND>
@@ -768,12 +1004,15 @@ KParams make_kparams(const ld_operator& op) {
 }
 
 size_t matmat_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int64_t s) {
-  return make_plan(ctx, f64, n, s).part_bytes + 1024;
+  size_t b = make_plan(ctx, f64, n, s).part_bytes;
+  if (!f64) b = std::max(b, make_plan(ctx, false, n, s, BK16).part_bytes);
+  return b + 1024;
 }
 
 ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
   if (a.n <= 0 || a.s <= 0) return LD_OK;
-  Plan pl = make_plan(ctx, f64, a.n, a.s);
+  const bool split16 = !f64 && a.bf16 && a.A == nullptr;
+  Plan pl = make_plan(ctx, f64, a.n, a.s, split16 ? BK16 : BK);
   void* part = ctx->arena.take(pl.part_bytes);
   if (!part) return fail(LD_ENOMEM, "matmat: scratch arena too small");
   hipStream_t st = ctx->stream;
@@ -818,16 +1057,22 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
                        a.dots);
   } else {
     const int NB = pl.NT / 32;
-    const float c = (float)(kind == LD_RBF ? a.kp.c_rbf * 1.4426950408889634 : a.kp.c_mat);
+    // kval32 constants: exponents in base 2; RBF carries log2(variance)
+    const double l2e = 1.4426950408889634;
+    const float c = (float)((kind == LD_RBF ? a.kp.c_rbf : a.kp.c_mat) * l2e);
+    const float var = (float)(kind == LD_RBF ? std::log2(a.kp.variance) : a.kp.variance);
     const float* V = (const float*)a.V;
     float* P = (float*)part;
-    if (fly) {
+    if (split16) {
       if (kind == LD_RBF)
-        fly32_by_d<LD_RBF>(NB, grid, st, (const float*)a.X, a.d, (float)a.kp.variance, c, V, P,
-                           pl.p);
+        fly16_by_d<LD_RBF>(NB, grid, st, (const float*)a.X, a.d, var, c, V, P, pl.p);
       else
-        fly32_by_d<LD_MATERN52>(NB, grid, st, (const float*)a.X, a.d, (float)a.kp.variance, c, V,
-                                P, pl.p);
+        fly16_by_d<LD_MATERN52>(NB, grid, st, (const float*)a.X, a.d, var, c, V, P, pl.p);
+    } else if (fly) {
+      if (kind == LD_RBF)
+        fly32_by_d<LD_RBF>(NB, grid, st, (const float*)a.X, a.d, var, c, V, P, pl.p);
+      else
+        fly32_by_d<LD_MATERN52>(NB, grid, st, (const float*)a.X, a.d, var, c, V, P, pl.p);
     } else {
       const float* A = (const float*)a.A;
       const bool tiled = a.layout == LD_TILED;

@@ -238,3 +238,30 @@ def test_error_paths(ctx):
     res, per = L.logdet_estimate(ctx, op, P, 3, 4, 0, 1e-12, 1, allow_noconv=True)
     assert res["status"] == "LD_ENOCONV" and res["iterations"] == 1
     assert res["converged_cols"] == 0 and np.all(np.isfinite(per))
+
+
+# --------------------------------------------------- precision form (BF16) --
+@pytest.mark.parametrize("n,d,s,kind", MM_CASES)
+def test_matmat_bf16_split(ctx, n, d, s, kind):
+    g = np.random.default_rng(11 * n + s)
+    X = g.random((n, d))
+    V = g.standard_normal((n, s)).astype(np.float32)
+    Mref = gp.dense_matrix(kind, X, 0.3, 1.3, 1e-2)
+    op = make_op(X, kind, 0.3, 1.3, 1e-2, precision=L.LD_BF16)
+    Y = L.kernel_matmat(ctx, op, dev(V, torch.float32))
+    ctx.synchronize()
+    ref = Mref @ V.astype(np.float64)
+    scale = np.abs(Mref) @ np.abs(V.astype(np.float64))
+    # three-term split-bf16 products: about 2^-16 relative per term
+    assert np.max(np.abs(host(Y) - ref) / scale) < 1e-4
+
+
+@pytest.mark.parametrize("k", [3, 5])
+def test_estimate_bf16_parity(ctx, k):
+    cfg = workloads.C3.with_n(3000, rank=200)
+    X, M, op, P, ref = _precond_pair(ctx, cfg, precision=L.LD_BF16)
+    res, per = L.logdet_estimate(ctx, op, P, k, cfg.probes, cfg.probe_seed, 1e-6, 5000)
+    want = _oracle_estimate(M, ref, k, cfg.probe_seed, cfg.probes)
+    assert res["status"] == "LD_OK"
+    assert res["logdet"] == pytest.approx(want.logdet, rel=1e-4)
+    np.testing.assert_allclose(per, want.per_probe, rtol=2e-3)

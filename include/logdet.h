@@ -116,11 +116,14 @@ ld_status ld_ctx_create(int device, void* stream, ld_ctx** out);
 void ld_ctx_destroy(ld_ctx* ctx);
 const char* ld_last_error(void);
 
-/* Instrumentation.  With timing on, the solver of logdet_estimate records
- * HIP events on the context stream around every launch of its kernel-matrix
- * product kernel; ld_ctx_read_timing returns the summed elapsed time (ms),
- * the number of launches, and their algorithmic flops (2 n^2 s each) and
- * bytes (the stored matrix once, when stored, plus V read and Y written).
+/* Instrumentation.  With timing on, the solvers of logdet_estimate and
+ * logdet_estimate_batched record HIP events around every launch of their
+ * kernel-matrix product kernel (on the stream the kernel runs on; the
+ * batched form records them only without LD_BATCH_GRAPH); ld_ctx_read_timing
+ * returns the summed elapsed time (ms), the number of launches, and their
+ * algorithmic flops (2 n^2 s each; batched: the sum over instances that still
+ * have an active probe) and bytes (the stored matrix once, when stored, plus
+ * V read and Y written; batched: also the addend and the points).
  * ld_ctx_set_timing resets the totals.  Any output pointer may be NULL. */
 ld_status ld_ctx_set_timing(ld_ctx* ctx, int32_t on);
 ld_status ld_ctx_read_timing(ld_ctx* ctx, double* ms, int64_t* calls, double* flops, double* bytes);
@@ -202,6 +205,58 @@ void ld_precond_free(ld_precond* P);
 ld_status logdet_estimate(ld_ctx* ctx, const ld_operator* op, const ld_precond* P, int32_t k,
                           int32_t num_probes, uint64_t probe_seed, double tol, int32_t max_iters,
                           ld_result* out, double* per_probe);
+
+/* One problem of a batch: M = K(X, X) + noise * I as in ld_operator (always
+ * on the fly, FP32 products), with its own preconditioner rank and seeds. */
+typedef struct {
+  const double* X;        /* device, n x d points (FP64) */
+  int64_t n;              /* >= 1 */
+  int32_t d;              /* 1..8 */
+  int32_t kind;           /* ld_kernel */
+  double lengthscale;     /* > 0 */
+  double variance;        /* > 0 */
+  double noise;           /* >= 0 */
+  int32_t rank;           /* preconditioner rank l >= 1, l + oversample <= n */
+  int32_t reserved;       /* must be 0 */
+  uint64_t precond_seed;  /* Gaussian test matrix, counter stream 1 */
+  uint64_t probe_seed;    /* Rademacher probes, counter stream 2 */
+} ld_instance;
+
+/* Flags of logdet_estimate_batched. */
+#define LD_BATCH_GRAPH 1   /* capture the solver iterations in a HIP graph and
+                              replay it (on a library-owned side stream
+                              joined to the context stream) */
+#define LD_BATCH_RETUNE 2  /* re-time the product tile shapes even if this
+                              context already chose one */
+
+/* The estimator of logdet_estimate applied to `count` independent problems
+ * of uneven size in one pass (the same method per instance, Section 2 and
+ * Algorithm 1): for every instance a randomized truncated-SVD preconditioner
+ * (rank_i, oversample, power_iters, precond_seed_i), num_probes Rademacher
+ * probes (probe_seed_i), and a multi-shift CG for r_k in the P^-1 inner
+ * product stopping per probe at ||r||_{P^-1} <= tol ||z||_{P^-1}.  All
+ * instances advance together: every kernel-matrix product, Woodbury apply and
+ * reduction covers the whole batch in one launch; an instance's probes that
+ * have converged stop updating.  Products and vectors are FP32; the
+ * preconditioner's dense algebra, the CG scalars and log det P are FP64.
+ * Instance i's probes are the same as those of logdet_estimate with
+ * probe_seed_i, and its Gaussian test matrix the same as that of
+ * logdet_precond_build with precond_seed_i.
+ *   count       1..4096
+ *   instances   host array of count descriptors
+ *   k           1, 3 or 5
+ *   num_probes  1..64
+ *   oversample  >= 0;  power_iters 0..16
+ *   tol > 0, max_iters >= 1, flags: LD_BATCH_* bits
+ *   results     host array of count ld_result (filled on LD_OK / LD_ENOCONV;
+ *               seconds_solve and iterations are those of the whole batch)
+ *   per_probe   host array of count * num_probes doubles (instance-major), or NULL
+ * The product kernel's tile shape (4 or 2 waves per workgroup) is timed on
+ * the first call and kept in the context.  Synchronizes. */
+ld_status logdet_estimate_batched(ld_ctx* ctx, int32_t count, const ld_instance* instances,
+                                  int32_t k, int32_t num_probes, int32_t oversample,
+                                  int32_t power_iters, double tol, int32_t max_iters,
+                                  int32_t flags, ld_result* results, double* per_probe);
 
 #ifdef __cplusplus
 }

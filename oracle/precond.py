@@ -43,6 +43,7 @@ class Precond:
     lam: np.ndarray    # rank, descending, > 0
     D: np.ndarray      # n, > 0
     logdet: float
+    ritz: np.ndarray | None = None  # all rank + oversample Ritz values, descending
 
     def dense(self):
         return np.diag(self.D) + (self.U * self.lam) @ self.U.T
@@ -91,4 +92,5 @@ def rsvd(M, rank: int, oversample: int, power_iters: int, seed: int, floor: floa
     U = Q @ V[:, order]
     D = np.diag(M) - (U * U) @ lam
     D = np.maximum(D, floor)
-    return Precond(U=U, lam=lam, D=D, logdet=logdet_lemma(U, lam, D))
+    return Precond(U=U, lam=lam, D=D, logdet=logdet_lemma(U, lam, D),
+                   ritz=np.sort(theta)[::-1].copy())

@@ -20,6 +20,7 @@ LD_OK, LD_EINVAL, LD_ENOTSPD, LD_ENOCONV, LD_EHIP, LD_ENOMEM = 0, -1, -2, -3, -4
 LD_RBF, LD_MATERN52 = 0, 1
 LD_F64, LD_F32, LD_BF16 = 0, 1, 2
 LD_ROW_MAJOR, LD_TILED = 0, 1
+LD_BATCH_GRAPH, LD_BATCH_RETUNE = 1, 2
 
 STATUS_NAMES = {0: "LD_OK", -1: "LD_EINVAL", -2: "LD_ENOTSPD", -3: "LD_ENOCONV", -4: "LD_EHIP",
                 -5: "LD_ENOMEM"}
@@ -29,7 +30,7 @@ EXPORTED = (
     "ld_stored_elements", "ld_rational_coeffs", "ld_fill_probes",
     "ld_fill_gaussian", "kernel_matmat", "kernel_materialize", "logdet_precond_build",
     "ld_precond_info", "ld_precond_export", "ld_precond_apply_inverse", "ld_precond_free",
-    "logdet_estimate",
+    "logdet_estimate", "logdet_estimate_batched",
 )
 
 
@@ -45,6 +46,15 @@ class Operator(ctypes.Structure):
         ("kind", ctypes.c_int32), ("lengthscale", ctypes.c_double), ("variance", ctypes.c_double),
         ("noise", ctypes.c_double), ("precision", ctypes.c_int32), ("M_stored", ctypes.c_void_p),
         ("layout", ctypes.c_int32),
+    ]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [
+        ("X", ctypes.c_void_p), ("n", ctypes.c_int64), ("d", ctypes.c_int32),
+        ("kind", ctypes.c_int32), ("lengthscale", ctypes.c_double), ("variance", ctypes.c_double),
+        ("noise", ctypes.c_double), ("rank", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("precond_seed", ctypes.c_uint64), ("probe_seed", ctypes.c_uint64),
     ]
 
 
@@ -93,6 +103,8 @@ def load():
         "ld_precond_free": (None, [vp]),
         "logdet_estimate": (i32, [vp, ctypes.POINTER(Operator), vp, i32, i32, u64, dbl, i32,
                                   ctypes.POINTER(Result), pd]),
+        "logdet_estimate_batched": (i32, [vp, i32, ctypes.POINTER(Instance), i32, i32, i32, i32,
+                                          dbl, i32, i32, ctypes.POINTER(Result), pd]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -311,3 +323,39 @@ def logdet_estimate(ctx: Context, op: GPOperator, P: Precond | None, k: int, num
     out = res.as_dict()
     out["status"] = STATUS_NAMES.get(st, st)
     return out, per
+
+
+@dataclass
+class BatchItem:
+    """One problem of a batch (caller-owned device points, FP64 (n, d))."""
+    X: object
+    kind: int
+    lengthscale: float
+    variance: float
+    noise: float
+    rank: int
+    precond_seed: int
+    probe_seed: int
+
+
+def logdet_estimate_batched(ctx: Context, items, k: int, num_probes: int, oversample: int = 10,
+                            power_iters: int = 2, tol: float = 1e-6, max_iters: int = 5000,
+                            graph: bool = False, retune: bool = False, allow_noconv: bool = False):
+    """Returns (list of result dicts, per-probe values (count, num_probes), status name)."""
+    torch = _torch()
+    count = len(items)
+    arr = (Instance * count)()
+    for i, it in enumerate(items):
+        assert it.X.is_cuda and it.X.dtype == torch.float64 and it.X.is_contiguous()
+        arr[i] = Instance(X=it.X.data_ptr(), n=int(it.X.shape[0]), d=int(it.X.shape[1]),
+                          kind=it.kind, lengthscale=it.lengthscale, variance=it.variance,
+                          noise=it.noise, rank=it.rank, reserved=0,
+                          precond_seed=it.precond_seed, probe_seed=it.probe_seed)
+    res = (Result * max(count, 1))()
+    per = np.zeros((max(count, 1), num_probes), dtype=np.float64)
+    flags = (LD_BATCH_GRAPH if graph else 0) | (LD_BATCH_RETUNE if retune else 0)
+    st = load().logdet_estimate_batched(ctx.handle, count, arr, k, num_probes, oversample,
+                                        power_iters, tol, max_iters, flags, res,
+                                        per.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    _check(st, allow=(LD_ENOCONV,) if allow_noconv else ())
+    return [r.as_dict() for r in res[:count]], per[:count], STATUS_NAMES.get(st, st)

@@ -494,6 +494,11 @@ void ld_ctx_destroy(ld_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  if (ctx->side) {
+    (void)hipStreamSynchronize(ctx->side);
+    (void)hipStreamDestroy(ctx->side);
+  }
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   ctx->arena.release();
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
@@ -715,6 +720,42 @@ ld_status logdet_estimate(ld_ctx* ctx, const ld_operator* op, const ld_precond* 
     return fail(LD_ENOTSPD, "non-positive curvature or residual norm in the solver (M or P not SPD?)");
   if (conv < s) return fail(LD_ENOCONV, "max_iters reached before every probe converged");
   return LD_OK;
+}
+
+ld_status logdet_estimate_batched(ld_ctx* ctx, int32_t count, const ld_instance* instances,
+                                  int32_t k, int32_t num_probes, int32_t oversample,
+                                  int32_t power_iters, double tol, int32_t max_iters,
+                                  int32_t flags, ld_result* results, double* per_probe) {
+  LD_TRY(check_ctx(ctx));
+  if (count < 1 || count > 4096) return fail(LD_EINVAL, "count must be in 1..4096");
+  if (!instances || !results) return fail(LD_EINVAL, "instances or results is NULL");
+  Rational rf;
+  if (!rational_for(k, &rf)) return fail(LD_EINVAL, "k must be 1, 3 or 5");
+  if (num_probes < 1 || num_probes > 64) return fail(LD_EINVAL, "num_probes must be in 1..64");
+  if (oversample < 0) return fail(LD_EINVAL, "oversample must be >= 0");
+  if (power_iters < 0 || power_iters > 16) return fail(LD_EINVAL, "power_iters must be in 0..16");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(LD_EINVAL, "tol must be finite and > 0");
+  if (max_iters < 1) return fail(LD_EINVAL, "max_iters must be >= 1");
+  if (flags & ~(LD_BATCH_GRAPH | LD_BATCH_RETUNE)) return fail(LD_EINVAL, "unknown flag bits");
+  for (int32_t i = 0; i < count; ++i) {
+    const ld_instance& x = instances[i];
+    const std::string at = " (instance " + std::to_string(i) + ")";
+    if (!x.X) return fail(LD_EINVAL, "X is NULL" + at);
+    if (x.n < 1 || x.n > (int64_t)1 << 24) return fail(LD_EINVAL, "n must be in 1..2^24" + at);
+    if (x.d < 1 || x.d > 8) return fail(LD_EINVAL, "d must be in 1..8" + at);
+    if (x.kind != LD_RBF && x.kind != LD_MATERN52) return fail(LD_EINVAL, "unknown kernel kind" + at);
+    if (!(x.lengthscale > 0.0) || !std::isfinite(x.lengthscale))
+      return fail(LD_EINVAL, "lengthscale must be finite and > 0" + at);
+    if (!(x.variance > 0.0) || !std::isfinite(x.variance))
+      return fail(LD_EINVAL, "variance must be finite and > 0" + at);
+    if (!(x.noise >= 0.0) || !std::isfinite(x.noise))
+      return fail(LD_EINVAL, "noise must be finite and >= 0" + at);
+    if (x.rank < 1 || (int64_t)x.rank + oversample > x.n || (int64_t)x.rank + oversample > 1024)
+      return fail(LD_EINVAL, "need 1 <= rank and rank + oversample <= min(n, 1024)" + at);
+    if (x.reserved != 0) return fail(LD_EINVAL, "reserved must be 0" + at);
+  }
+  return batched_estimate(ctx, count, instances, k, rf.a, rf.b, rf.c, num_probes, oversample,
+                          power_iters, tol, max_iters, flags, results, per_probe);
 }
 
 }  // extern "C"

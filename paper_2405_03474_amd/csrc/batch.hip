@@ -1,0 +1,1320 @@
+// Batched form of the estimator: many independent GP problems of uneven size
+// carried through the whole hot path together (Section 2 method applied to
+// each instance).  The batch is a block-diagonal operator diag(M_1..M_B):
+// instance i owns rows [row0_i, row0_i + n_i) of every batch matrix, padded
+// to a multiple of 128 rows, and every reduction is segmented by instance.
+//
+//  - kernel-matrix products: one workgroup per (instance, row block, column
+//    block), launched in decreasing n (longest first), each running the full
+//    k range on FP32 matrix cores and applying the epilogue itself, so no
+//    partial sums leave the workgroup; two tile shapes (4 or 2 waves) are
+//    timed once and the faster one is kept (autotuner);
+//  - preconditioner: batched range finder, CholeskyQR, Rayleigh-Ritz with
+//    one-workgroup-per-instance Cholesky, triangular inverse and Jacobi
+//    eigen-solver (dense_dev.hpp), Woodbury factors per instance;
+//  - solver: multi-shift CG with per-(instance, probe) scalars; the
+//    iterations can be captured in a HIP graph and replayed in chunks.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <functional>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "dense_dev.hpp"
+#include "kfun_dev.hpp"
+#include "ld_common.hpp"
+#include "rng_dev.hpp"
+
+namespace ld {
+namespace {
+
+constexpr int BROWS = 128;  // row padding of every instance
+constexpr int BDX = 8;      // point stride (max dimension of a batched instance)
+constexpr int BBK = 32;     // k per stage
+constexpr int BLK = 64;     // row block of the segmented reductions
+constexpr int kChunk = 8;   // solver iterations per host check / graph replay
+constexpr int FTC = 2048;   // rows per partial of the Woodbury projection F^T R
+
+struct BInst {
+  const double* X64;
+  int64_t n, row0;
+  int d, kind, m, rank;
+  int ch0, nch;  // first FTC-row chunk (global index) and chunk count
+  float kv, kc, noise;
+  double diag, floor_v, shift_c;
+  uint64_t key_omega, key_probe;
+};
+
+struct BItem {
+  int inst, rb, cb, pad;  // instance, row block, column block
+};
+
+__device__ __forceinline__ float kval_rt(int kind, float r2, float v, float c) {
+  return kind == LD_RBF ? dev::kval32<LD_RBF>(r2, v, c) : dev::kval32<LD_MATERN52>(r2, v, c);
+}
+
+// ------------------------------------------------------------ fill kernels --
+__global__ void k_bx32(const BInst* __restrict__ inst, const int* __restrict__ blk_inst,
+                       int64_t R, float* __restrict__ X32) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < R * BDX;
+       e += (int64_t)gridDim.x * 256) {
+    const int64_t row = e / BDX;
+    const int dd = (int)(e % BDX);
+    const BInst& I = inst[blk_inst[row / BLK]];
+    const int64_t lr = row - I.row0;
+    X32[e] = (lr < I.n && dd < I.d) ? (float)I.X64[lr * I.d + dd] : 0.f;
+  }
+}
+
+// Gaussian test matrix, instance i drawing its own stream (index lr * m_i + c)
+__global__ void k_bomega(const BInst* __restrict__ inst, const int* __restrict__ blk_inst,
+                         int64_t R, int mmax, double* __restrict__ Om) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < R * mmax;
+       e += (int64_t)gridDim.x * 256) {
+    const int64_t row = e / mmax;
+    const int c = (int)(e % mmax);
+    const BInst& I = inst[blk_inst[row / BLK]];
+    const int64_t lr = row - I.row0;
+    Om[e] = (lr < I.n && c < I.m) ? dev::rng_gaussian(I.key_omega, (uint64_t)(lr * I.m + c)) : 0.0;
+  }
+}
+
+__global__ void k_bprobes(const BInst* __restrict__ inst, const int* __restrict__ blk_inst,
+                          int64_t R, int s, float* __restrict__ Z) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < R * s;
+       e += (int64_t)gridDim.x * 256) {
+    const int64_t row = e / s;
+    const int c = (int)(e % s);
+    const BInst& I = inst[blk_inst[row / BLK]];
+    const int64_t lr = row - I.row0;
+    Z[e] = lr < I.n ? dev::rng_rademacher(I.key_probe, (uint64_t)(lr * s + c)) : 0.f;
+  }
+}
+
+// ------------------------------------------------------- batched product --
+// Y = M V (+ noise V + alpha2 X2) on the instance's rows; padded rows of Y
+// are written as zero.  dots[b][c] = sum over the 64-row block b of V .* Y.
+template <int NB, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_bmm(const BInst* __restrict__ inst,
+                                                    const BItem* __restrict__ items,
+                                                    const float* __restrict__ X32,
+                                                    const float* __restrict__ V, int ld,
+                                                    float* __restrict__ Y,
+                                                    const float* __restrict__ X2, float alpha2,
+                                                    double* __restrict__ dots,
+                                                    const int* __restrict__ iact) {
+  constexpr int NT = 32 * NB;
+  constexpr int NTH = 64 * WAVES;
+  constexpr int BMW = 32 * WAVES;
+  constexpr int AS = BBK + 4;
+  constexpr int VPT = BBK * NT / NTH;    // V values per thread per stage
+  constexpr int XPT = BBK * BDX / NTH;   // point values per thread per stage
+  __shared__ __attribute__((aligned(16))) float Bt[2][NT * AS];
+  __shared__ float Xs[2][BBK * BDX];
+  __shared__ double red[2 * WAVES][NT];
+  const BItem it = items[blockIdx.x];
+  if (iact && !iact[it.inst]) return;  // every probe of this instance has converged
+  const BInst I = inst[it.inst];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, lh = lane >> 5;
+  const int64_t n = I.n;
+  const int64_t r0 = I.row0 + (int64_t)it.rb * BMW;  // first global row of the block
+  const int c0 = it.cb * NT;
+  const float* Vi = V + I.row0 * ld;
+
+  float xr[BDX];
+  {
+    const int64_t lr = r0 - I.row0 + 32 * wave + li;
+#pragma unroll
+    for (int dd = 0; dd < BDX; ++dd) xr[dd] = lr < n ? X32[(I.row0 + lr) * BDX + dd] : 0.f;
+  }
+  typedef float f32x16 __attribute__((ext_vector_type(16)));
+  f32x16 acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
+
+  const int S = (int)((n + BBK - 1) / BBK);
+  float tv[VPT], tx[XPT];
+  auto load = [&](int st) {
+    const int64_t k0 = (int64_t)st * BBK;
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const int e = tid + NTH * j;
+      const int kk = e / NT, cc = e % NT;
+      tv[j] = (k0 + kk < n && c0 + cc < ld) ? Vi[(k0 + kk) * ld + c0 + cc] : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < XPT; ++j) {
+      const int e = tid + NTH * j;
+      const int64_t kr = k0 + e / BDX;
+      tx[j] = kr < n ? X32[(I.row0 + kr) * BDX + e % BDX] : 0.f;
+    }
+  };
+  load(0);
+  int buf = 0;
+  for (int st = 0; st < S; ++st) {
+    float* bt = Bt[buf];
+    float* xs = Xs[buf];
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const int e = tid + NTH * j;
+      bt[(e % NT) * AS + e / NT] = tv[j];
+    }
+#pragma unroll
+    for (int j = 0; j < XPT; ++j) xs[tid + NTH * j] = tx[j];
+    __syncthreads();
+    if (st + 1 < S) load(st + 1);
+    float a[16], b[NB][16];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const float4* bp = (const float4*)&bt[(nb * 32 + li) * AS + lh * 16];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 v = bp[q];
+        b[nb][4 * q + 0] = v.x;
+        b[nb][4 * q + 1] = v.y;
+        b[nb][4 * q + 2] = v.z;
+        b[nb][4 * q + 3] = v.w;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const float* xk = &xs[(lh * 16 + t) * BDX];
+      float r2 = 0.f;
+#pragma unroll
+      for (int dd = 0; dd < BDX; ++dd)
+        if (dd < I.d) {
+          const float df = xr[dd] - xk[dd];
+          r2 = __builtin_fmaf(df, df, r2);
+        }
+      a[t] = kval_rt(I.kind, r2, I.kv, I.kc);
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t], b[nb][t], acc[nb], 0, 0, 0);
+    buf ^= 1;
+  }
+
+  // epilogue: this workgroup owns its rows, so it writes Y directly
+  double dsum[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    dsum[nb] = 0.0;
+    const int c = c0 + nb * 32 + li;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = 32 * wave + 8 * (r >> 2) + 4 * lh + (r & 3);
+      const int64_t grow = r0 + row;
+      if (c >= ld) continue;
+      float y = 0.f;
+      if (grow - I.row0 < n) {
+        const int64_t off = grow * ld + c;
+        double v = (double)acc[nb][r] + (double)I.noise * (double)V[off];
+        if (X2) v += (double)alpha2 * (double)X2[off];
+        y = (float)v;
+        dsum[nb] += (double)V[off] * (double)y;
+      }
+      Y[grow * ld + c] = y;
+    }
+  }
+  if (dots) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) red[2 * wave + lh][nb * 32 + li] = dsum[nb];
+    __syncthreads();
+    // 64-row block q of this workgroup gathers waves 2q, 2q + 1 (both halves)
+    for (int e = tid; e < (BMW / BLK) * NT; e += NTH) {
+      const int q = e / NT, c = e % NT;
+      const double t = (red[4 * q][c] + red[4 * q + 1][c]) + (red[4 * q + 2][c] + red[4 * q + 3][c]);
+      if (c0 + c < ld) dots[((r0 / BLK) + q) * (int64_t)ld + c0 + c] = t;
+    }
+  }
+}
+
+// -------------------------------------------------------- dense, batched --
+// G_i (mdim_i x mdim_i, leading dimension mdim_i, at i * gstride) =
+// A_i^T diag(w_i) B_i over the instance's rows; 64 x 64 tile per workgroup.
+__global__ __launch_bounds__(256) void k_bgram(const BInst* __restrict__ inst, int use_rank,
+                                               const double* __restrict__ A, int lda,
+                                               const double* __restrict__ B, int ldb,
+                                               const double* __restrict__ w,
+                                               double* __restrict__ G, int64_t gstride) {
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  const BInst I = inst[blockIdx.z];
+  const int md = use_rank ? I.rank : I.m;
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  if (i0 >= md || j0 >= md) return;
+  const int tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
+  double acc[4][4] = {};
+  for (int64_t rb = 0; rb < I.n; rb += 16) {
+    __syncthreads();
+    for (int e = tid; e < 16 * 64; e += 256) {
+      const int rr = e / 64, cc = e % 64;
+      const int64_t lr = rb + rr, row = I.row0 + lr;
+      double av = 0.0, bv = 0.0;
+      if (lr < I.n) {
+        const double wr = w ? w[row] : 1.0;
+        if (i0 + cc < md) av = A[row * lda + i0 + cc] * wr;
+        if (j0 + cc < md) bv = B[row * ldb + j0 + cc];
+      }
+      As[rr][cc] = av;
+      Bs[rr][cc] = bv;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < 16; ++rr) {
+      double a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = As[rr][ti + 16 * q];
+        b[q] = Bs[rr][tj + 16 * q];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+    }
+  }
+  double* Gi = G + blockIdx.z * gstride;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int i = i0 + ti + 16 * x, j = j0 + tj + 16 * y;
+      if (i < md && j < md) Gi[(int64_t)i * md + j] = acc[x][y];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bshift(const BInst* __restrict__ inst,
+                                                double* __restrict__ G, int64_t gstride) {
+  __shared__ double red[256];
+  const BInst I = inst[blockIdx.x];
+  double* Gi = G + blockIdx.x * gstride;
+  double t = 0.0;
+  for (int j = threadIdx.x; j < I.m; j += 256) t += Gi[(int64_t)j * I.m + j];
+  red[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double sh = I.shift_c * red[0];
+  for (int j = threadIdx.x; j < I.m; j += 256) Gi[(int64_t)j * I.m + j] += sh;
+}
+
+__global__ __launch_bounds__(dev::CT) void k_bchol(const BInst* __restrict__ inst, int use_rank,
+                                                   double* __restrict__ G, int64_t gstride,
+                                                   int* __restrict__ fail) {
+  const BInst I = inst[blockIdx.x];
+  const int md = use_rank ? I.rank : I.m;
+  dev::chol_upper_block(G + blockIdx.x * gstride, md, md, fail + blockIdx.x);
+}
+
+__global__ __launch_bounds__(dev::CT) void k_btrinv(const BInst* __restrict__ inst, int use_rank,
+                                                    const double* __restrict__ R,
+                                                    double* __restrict__ X, int64_t gstride) {
+  const BInst I = inst[blockIdx.x];
+  const int md = use_rank ? I.rank : I.m;
+  dev::tri_inv_upper_block(R + blockIdx.x * gstride, md, md, X + blockIdx.x * gstride, md);
+}
+
+// C_i = diag(rs) A_i B_i with A_i the instance's rows of A (lda), B_i the
+// instance's K x N matrix at i * bstride (leading dimension ldb_i = N_i when
+// bld < 0, else the instance's m), K_i / N_i from (m | rank).
+__global__ __launch_bounds__(256) void k_bgemm(const BInst* __restrict__ inst, int k_is_rank,
+                                               int n_is_rank, const double* __restrict__ A,
+                                               int lda, const double* __restrict__ B,
+                                               int64_t bstride, int b_ld_is_m,
+                                               const double* __restrict__ rs,
+                                               double* __restrict__ C, int ldc) {
+  const BInst I = inst[blockIdx.z];
+  const int K = k_is_rank ? I.rank : I.m;
+  const int N = n_is_rank ? I.rank : I.m;
+  const int64_t i0 = (int64_t)blockIdx.x * dev::GM_BM;
+  const int j0 = blockIdx.y * dev::GM_BN;
+  if (i0 >= I.n || j0 >= N) return;
+  const int ldb = b_ld_is_m ? I.m : N;
+  dev::gemm64_tile(A + I.row0 * lda, lda, B + blockIdx.z * bstride, ldb,
+                   rs ? rs + I.row0 : nullptr, I.n, K, N, C + I.row0 * ldc, ldc, i0, j0);
+}
+
+// Whole Jacobi eigen-solve of G_i (m_i x m_i) by one workgroup per instance:
+// rounds of the parallel cyclic ordering separated by barriers, sweeps until
+// the off-diagonal mass converges (at most 40); then eigenpairs sorted by
+// descending eigenvalue into evals (stride emax) and evecs_i (m_i x m_i).
+__global__ __launch_bounds__(1024) void k_bjacobi(const BInst* __restrict__ inst,
+                                                  const double* __restrict__ G, int64_t gstride,
+                                                  double* __restrict__ work, int64_t wstride,
+                                                  double* __restrict__ evals, int emax,
+                                                  double* __restrict__ evecs,
+                                                  int* __restrict__ status) {
+  __shared__ double so[1024], sd[1024];
+  const BInst I = inst[blockIdx.x];
+  const int m = I.m, me = m + (m & 1);
+  const int tid = threadIdx.x;
+  const double* Gi = G + blockIdx.x * gstride;
+  double* A0 = work + blockIdx.x * wstride;
+  double* A1 = A0 + (int64_t)me * me;
+  double* V0 = A1 + (int64_t)me * me;
+  double* V1 = V0 + (int64_t)me * me;
+  for (int64_t e = tid; e < (int64_t)me * me; e += 1024) {
+    const int i = (int)(e / me), j = (int)(e % me);
+    A0[e] = (i < m && j < m) ? 0.5 * (Gi[(int64_t)i * m + j] + Gi[(int64_t)j * m + i]) : 0.0;
+    V0[e] = i == j ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int h = me / 2;
+  const int64_t items = (int64_t)h * h + (int64_t)me * h;
+  double* cur = A0;
+  double* nxt = A1;
+  double* vcur = V0;
+  double* vnxt = V1;
+  bool done = me < 2;
+  double off_prev = -1.0;
+  for (int sweep = 0; sweep < 40 && !done; ++sweep) {
+    for (int r = 0; r < me - 1; ++r) {
+      for (int64_t e = tid; e < items; e += 1024) dev::jacobi_item(cur, nxt, vcur, vnxt, me, r, e);
+      __syncthreads();
+      double* t = cur;
+      cur = nxt;
+      nxt = t;
+      t = vcur;
+      vcur = vnxt;
+      vnxt = t;
+    }
+    double o = 0.0, dg = 0.0;
+    for (int64_t e = tid; e < (int64_t)me * me; e += 1024) {
+      const double v = cur[e];
+      if (e / me == e % me)
+        dg += v * v;
+      else
+        o += v * v;
+    }
+    so[tid] = o;
+    sd[tid] = dg;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+      if (tid < w) {
+        so[tid] += so[tid + w];
+        sd[tid] += sd[tid + w];
+      }
+      __syncthreads();
+    }
+    const double off = so[0], dgs = sd[0];
+    done = !isfinite(off) || dev::jacobi_done(off, dgs, off_prev);
+    off_prev = off;
+    __syncthreads();
+  }
+  if (tid == 0 && (!done || !isfinite(off_prev))) status[blockIdx.x] = 1;
+  double* ev = evals + (int64_t)blockIdx.x * emax;
+  double* vec = evecs + blockIdx.x * gstride;
+  for (int i = tid; i < m; i += 1024) {
+    const double li = cur[(int64_t)i * me + i];
+    int pos = 0;
+    for (int j = 0; j < m; ++j) {
+      const double lj = cur[(int64_t)j * me + j];
+      if (lj > li || (lj == li && j < i)) ++pos;
+    }
+    ev[pos] = li;
+    for (int r = 0; r < m; ++r) vec[(int64_t)r * m + pos] = vcur[(int64_t)r * me + i];
+  }
+}
+
+// D = diag(M) - rowsum(U^2 lam) floored; padded rows get D = 1, Dinv = 0
+__global__ void k_bd(const BInst* __restrict__ inst, const int* __restrict__ blk_inst, int64_t R,
+                     const double* __restrict__ U, int ldu, const double* __restrict__ lam,
+                     int emax, double* __restrict__ D, double* __restrict__ Dinv) {
+  for (int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x; row < R;
+       row += (int64_t)gridDim.x * 256) {
+    const int ii = blk_inst[row / BLK];
+    const BInst& I = inst[ii];
+    if (row - I.row0 >= I.n) {
+      D[row] = 1.0;
+      Dinv[row] = 0.0;
+      continue;
+    }
+    double low = 0.0;
+    const double* li = lam + (int64_t)ii * emax;
+    for (int j = 0; j < I.rank; ++j) {
+      const double u = U[row * ldu + j];
+      low = fma(li[j] * u, u, low);
+    }
+    double dv = I.diag - low;
+    if (!(dv >= I.floor_v)) dv = I.floor_v;
+    D[row] = dv;
+    Dinv[row] = 1.0 / dv;
+  }
+}
+
+__global__ void k_bcapdiag(const BInst* __restrict__ inst, double* __restrict__ C, int64_t gstride,
+                           const double* __restrict__ lam, int emax) {
+  const BInst I = inst[blockIdx.x];
+  for (int j = threadIdx.x; j < I.rank; j += 256)
+    C[blockIdx.x * gstride + (int64_t)j * I.rank + j] += 1.0 / lam[(int64_t)blockIdx.x * emax + j];
+}
+
+// log det P_i = sum log D + sum log lam + 2 sum log diag(chol C)
+__global__ __launch_bounds__(256) void k_blogdet(const BInst* __restrict__ inst,
+                                                 const double* __restrict__ D,
+                                                 const double* __restrict__ lam, int emax,
+                                                 const double* __restrict__ Rc, int64_t gstride,
+                                                 double* __restrict__ out) {
+  __shared__ double red[256];
+  const BInst I = inst[blockIdx.x];
+  double t = 0.0;
+  for (int64_t i = threadIdx.x; i < I.n; i += 256) t += log(D[I.row0 + i]);
+  for (int j = threadIdx.x; j < I.rank; j += 256)
+    t += log(lam[(int64_t)blockIdx.x * emax + j]) +
+         2.0 * log(Rc[blockIdx.x * gstride + (int64_t)j * I.rank + j]);
+  red[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// ----------------------------------------------------------- solver pieces --
+// Partial projections of the Woodbury apply: for row chunk g (FTC rows of one
+// instance) part_g (rank_i x s, at g * lmax * s) = F_g^T R_g.
+__global__ __launch_bounds__(256) void k_bft(const BInst* __restrict__ inst,
+                                             const int* __restrict__ ch_inst,
+                                             const float* __restrict__ F, int ldf,
+                                             const float* __restrict__ R, int s, int lmax,
+                                             double* __restrict__ part,
+                                             const int* __restrict__ iact) {
+  __shared__ double Fs[16][65];
+  __shared__ double Rs[16][65];
+  const int g = blockIdx.y;
+  const int ii = ch_inst[g];
+  if (iact && !iact[ii]) return;
+  const BInst I = inst[ii];
+  const int l0 = blockIdx.x * 64;
+  if (l0 >= I.rank) return;
+  const int64_t lo = (int64_t)(g - I.ch0) * FTC;
+  const int64_t hi = lo + FTC < I.n ? lo + FTC : I.n;
+  const int tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
+  double acc[4][4] = {};
+  for (int64_t rb = lo; rb < hi; rb += 16) {
+    __syncthreads();
+    for (int e = tid; e < 16 * 64; e += 256) {
+      const int rr = e / 64, cc = e % 64;
+      const int64_t lr = rb + rr, row = I.row0 + lr;
+      Fs[rr][cc] = (lr < hi && l0 + cc < I.rank) ? (double)F[row * ldf + l0 + cc] : 0.0;
+      Rs[rr][cc] = (lr < hi && cc < s) ? (double)R[row * s + cc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < 16; ++rr) {
+      double a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = Fs[rr][ti + 16 * q];
+        b[q] = Rs[rr][tj + 16 * q];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+    }
+  }
+  double* out = part + (int64_t)g * lmax * s;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int l = l0 + ti + 16 * x, c = tj + 16 * y;
+      if (l < I.rank && c < s) out[(int64_t)l * s + c] = acc[x][y];
+    }
+}
+
+// t_i = sum of the instance's chunk partials (rank_i x s at i * lmax * s)
+__global__ __launch_bounds__(256) void k_bft_sum(const BInst* __restrict__ inst, int s, int lmax,
+                                                 const double* __restrict__ part,
+                                                 double* __restrict__ t,
+                                                 const int* __restrict__ iact) {
+  if (iact && !iact[blockIdx.x]) return;
+  const BInst I = inst[blockIdx.x];
+  const int64_t cnt = (int64_t)I.rank * s;
+  for (int64_t e = threadIdx.x; e < cnt; e += 256) {
+    double v = 0.0;
+    for (int g = 0; g < I.nch; ++g) v += part[(int64_t)(I.ch0 + g) * lmax * s + e];
+    t[(int64_t)blockIdx.x * lmax * s + e] = v;
+  }
+}
+
+// OUT = Dinv R - F t on one 64-row block; dots dot1 = R .* OUT, dot2 = Z .* R
+__global__ __launch_bounds__(256) void k_bwout(const BInst* __restrict__ inst,
+                                               const int* __restrict__ blk_inst,
+                                               const float* __restrict__ F, int ldf,
+                                               const float* __restrict__ Dinv,
+                                               const double* __restrict__ t, int lmax,
+                                               const float* __restrict__ R, int s,
+                                               float* __restrict__ OUT, const float* __restrict__ Z,
+                                               double* __restrict__ dot1, double* __restrict__ dot2,
+                                               const int* __restrict__ iact) {
+  __shared__ double Fs[64][17];
+  __shared__ double Ts[16][65];
+  __shared__ double red1[16][65];
+  __shared__ double red2[16][65];
+  const int ii = blk_inst[blockIdx.x];
+  if (iact && !iact[ii]) return;
+  const BInst I = inst[ii];
+  const int tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
+  const int64_t b0 = (int64_t)blockIdx.x * 64;
+  const int64_t nrow = I.row0 + I.n;  // rows at or past nrow are padding
+  const double* tin = t + (int64_t)ii * lmax * s;
+  double acc[4][4] = {};
+  for (int l0 = 0; l0 < I.rank; l0 += 16) {
+    __syncthreads();
+    for (int e = tid; e < 64 * 16; e += 256) {
+      const int rr = e / 16, ll = e % 16;
+      Fs[rr][ll] = (l0 + ll < I.rank && b0 + rr < nrow) ? (double)F[(b0 + rr) * ldf + l0 + ll] : 0.0;
+    }
+    for (int e = tid; e < 16 * 64; e += 256) {
+      const int ll = e / 64, cc = e % 64;
+      Ts[ll][cc] = (l0 + ll < I.rank && cc < s) ? tin[(int64_t)(l0 + ll) * s + cc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int ll = 0; ll < 16; ++ll) {
+      double a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = Fs[ti + 16 * q][ll];
+        b[q] = Ts[ll][tj + 16 * q];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+    }
+  }
+  double d1[4] = {}, d2[4] = {};
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int64_t row = b0 + ti + 16 * x;
+    const bool pad = row >= nrow;
+    const double dv = pad ? 0.0 : (double)Dinv[row];
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int c = tj + 16 * y;
+      if (c >= s) continue;
+      const int64_t off = row * s + c;
+      if (pad) {
+        OUT[off] = 0.f;
+        continue;
+      }
+      const double rv = (double)R[off];
+      const float o = (float)(dv * rv - acc[x][y]);
+      OUT[off] = o;
+      d1[y] += rv * (double)o;
+      d2[y] += (double)Z[off] * rv;
+    }
+  }
+#pragma unroll
+  for (int y = 0; y < 4; ++y) {
+    red1[ti][tj + 16 * y] = d1[y];
+    red2[ti][tj + 16 * y] = d2[y];
+  }
+  __syncthreads();
+  if (tid < s) {
+    double a = 0.0, b = 0.0;
+    for (int q = 0; q < 16; ++q) {
+      a += red1[q][tid];
+      b += red2[q][tid];
+    }
+    dot1[blockIdx.x * (int64_t)s + tid] = a;
+    dot2[blockIdx.x * (int64_t)s + tid] = b;
+  }
+}
+
+// out[i * s + c] = sum of parts[b][c] over the 64-row blocks of instance i
+__global__ __launch_bounds__(256) void k_bsegsum(const BInst* __restrict__ inst, int s,
+                                                 const double* __restrict__ parts,
+                                                 double* __restrict__ out) {
+  __shared__ double red[256];
+  const BInst I = inst[blockIdx.x];
+  const int groups = 256 / s;
+  const int c = threadIdx.x % s, q = threadIdx.x / s;
+  const int64_t b0 = I.row0 / BLK, nb = (I.n + BLK - 1) / BLK;
+  double acc = 0.0;
+  if (q < groups)
+    for (int64_t b = q; b < nb; b += groups) acc += parts[(b0 + b) * s + c];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < s) {
+    double t = 0.0;
+    for (int g = 0; g < groups; ++g) t += red[g * s + threadIdx.x];
+    out[(int64_t)blockIdx.x * s + threadIdx.x] = t;
+  }
+}
+
+// Vector updates over the whole batch; padding rows are left at zero.
+__global__ void k_bupdate_r(const BInst* __restrict__ inst, const int* __restrict__ blk_inst,
+                            int64_t R, int s, float* __restrict__ r, const float* __restrict__ q,
+                            const double* __restrict__ alpha) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < R * s;
+       e += (int64_t)gridDim.x * 256) {
+    const int64_t row = e / s;
+    const int c = (int)(e % s);
+    const int ii = blk_inst[row / BLK];
+    if (row - inst[ii].row0 >= inst[ii].n) continue;
+    const double a = alpha[(int64_t)ii * s + c];
+    r[e] = (float)((double)r[e] - a * (double)q[e]);
+  }
+}
+
+__global__ void k_bupdate_pw(const BInst* __restrict__ inst, const int* __restrict__ blk_inst,
+                             int64_t R, int s, float* __restrict__ p, float* __restrict__ w,
+                             const float* __restrict__ r, const float* __restrict__ u,
+                             const double* __restrict__ beta, const int* __restrict__ active) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < R * s;
+       e += (int64_t)gridDim.x * 256) {
+    const int64_t row = e / s;
+    const int c = (int)(e % s);
+    const int ii = blk_inst[row / BLK];
+    if (row - inst[ii].row0 >= inst[ii].n) continue;
+    const int64_t g = (int64_t)ii * s + c;
+    if (!active[g]) continue;
+    const double b = beta[g];
+    p[e] = (float)((double)r[e] + b * (double)p[e]);
+    w[e] = (float)((double)u[e] + b * (double)w[e]);
+  }
+}
+
+// iact[i] = 1 while any probe column of instance i is still active
+__global__ void k_binst_active(int B, int s, const int* __restrict__ active, int* __restrict__ iact) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < B; i += gridDim.x * 256) {
+    int a = 0;
+    for (int c = 0; c < s; ++c) a |= active[(int64_t)i * s + c];
+    iact[i] = a;
+  }
+}
+
+// Instrumentation: algorithmic work of the next product launch (instances
+// with an active probe): acc[0] += sum 2 n_i^2 s flops, acc[1] += bytes of
+// V and X2 read and Y written (FP32) plus the points.  One workgroup.
+__global__ __launch_bounds__(256) void k_bwork(const BInst* __restrict__ inst,
+                                               const int* __restrict__ iact, int B, int s,
+                                               double* __restrict__ acc) {
+  __shared__ double rf[256], rb[256];
+  double f = 0.0, by = 0.0;
+  for (int i = threadIdx.x; i < B; i += 256)
+    if (iact[i]) {
+      const double n = (double)inst[i].n;
+      f += 2.0 * n * n * s;
+      by += 4.0 * n * (3.0 * s + BDX);
+    }
+  rf[threadIdx.x] = f;
+  rb[threadIdx.x] = by;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      rf[threadIdx.x] += rf[threadIdx.x + w];
+      rb[threadIdx.x] += rb[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    acc[0] += rf[0];
+    acc[1] += rb[0];
+  }
+}
+
+__global__ void k_bcopy2(const float* __restrict__ src, float* __restrict__ a,
+                         float* __restrict__ b, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * 256) {
+    const float v = src[i];
+    a[i] = v;
+    if (b) b[i] = v;
+  }
+}
+
+int grid1(int64_t count) {
+  int64_t b = (count + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
+}
+
+// ------------------------------------------------------------------ host --
+struct Batch {
+  int B = 0;
+  int s = 0;
+  int64_t R = 0;       // padded rows
+  int64_t nblk = 0;    // 64-row blocks
+  int mmax = 0;        // max m (rank + oversample)
+  int lmax = 0;        // max rank
+  int64_t gstride = 0; // mmax^2
+  std::vector<BInst> h;
+  BInst* d_inst = nullptr;
+  int* d_blk_inst = nullptr;
+  float* X32 = nullptr;
+};
+
+// Work items of the batched product, longest instances first.
+std::vector<BItem> make_items(const Batch& b, int bmw, int ncols, int nt) {
+  std::vector<int> order(b.B);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b.h[x].n > b.h[y].n; });
+  std::vector<BItem> items;
+  const int cbs = (ncols + nt - 1) / nt;
+  for (int i : order) {
+    const int rbs = (int)((b.h[i].n + bmw - 1) / bmw);
+    for (int rb = 0; rb < rbs; ++rb)
+      for (int cb = 0; cb < cbs; ++cb) items.push_back(BItem{i, rb, cb, 0});
+  }
+  return items;
+}
+
+struct ProductPlan {
+  BItem* d_items = nullptr;
+  int count = 0;
+  int variant = 0;  // 0: 4 waves x 128 rows; 1: 2 waves x 64 rows
+  int nb = 1;
+};
+
+ld_status plan_product(ld_ctx* ctx, const Batch& b, int ncols, int variant, ProductPlan* pp) {
+  const int nb = ncols > 32 ? 2 : 1;
+  const int bmw = variant == 0 ? 128 : 64;
+  std::vector<BItem> items = make_items(b, bmw, ncols, 32 * nb);
+  pp->d_items = (BItem*)ctx->arena.take(items.size() * sizeof(BItem));
+  if (!pp->d_items) return fail(LD_ENOMEM, "batch: scratch arena too small for work items");
+  LD_HIP(hipMemcpyAsync(pp->d_items, items.data(), items.size() * sizeof(BItem),
+                        hipMemcpyHostToDevice, ctx->stream));
+  LD_HIP(hipStreamSynchronize(ctx->stream));  // `items` is released on return
+  pp->count = (int)items.size();
+  pp->variant = variant;
+  pp->nb = nb;
+  return LD_OK;
+}
+
+void launch_product(hipStream_t st, const Batch& b, const ProductPlan& pp, const float* V, int ld,
+                    float* Y, const float* X2, float alpha2, double* dots, const int* iact) {
+  const dim3 g(pp.count);
+  if (pp.variant == 0) {
+    if (pp.nb == 2)
+      hipLaunchKernelGGL((k_bmm<2, 4>), g, dim3(256), 0, st, b.d_inst, pp.d_items, b.X32, V, ld, Y,
+                         X2, alpha2, dots, iact);
+    else
+      hipLaunchKernelGGL((k_bmm<1, 4>), g, dim3(256), 0, st, b.d_inst, pp.d_items, b.X32, V, ld, Y,
+                         X2, alpha2, dots, iact);
+  } else {
+    if (pp.nb == 2)
+      hipLaunchKernelGGL((k_bmm<2, 2>), g, dim3(128), 0, st, b.d_inst, pp.d_items, b.X32, V, ld, Y,
+                         X2, alpha2, dots, iact);
+    else
+      hipLaunchKernelGGL((k_bmm<1, 2>), g, dim3(128), 0, st, b.d_inst, pp.d_items, b.X32, V, ld, Y,
+                         X2, alpha2, dots, iact);
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ driver --
+namespace {
+
+struct Bufs {
+  double *Q, *Y, *G, *Rinv, *evecs, *evals, *jwork, *U, *F64, *D, *Dinv64, *ldP;
+  float *V32, *Y32, *F32, *Dinv32;
+  int *fail, *jstat;
+};
+
+ld_status read_ints(ld_ctx* ctx, hipStream_t st, const int* d, int count, std::vector<int>& h) {
+  LD_TRY(ensure_pinned(ctx, (size_t)count / 2 + 8));
+  LD_HIP(hipMemcpyAsync(ctx->pinned, d, (size_t)count * sizeof(int), hipMemcpyDeviceToHost, st));
+  LD_HIP(hipStreamSynchronize(st));
+  h.assign((const int*)ctx->pinned, (const int*)ctx->pinned + count);
+  return LD_OK;
+}
+
+dim3 gemm_grid(const Batch& b, int ncols) {
+  int64_t maxrows = 0;
+  for (const BInst& I : b.h) maxrows = std::max(maxrows, I.n);
+  return dim3((unsigned)((maxrows + dev::GM_BM - 1) / dev::GM_BM),
+              (unsigned)((ncols + dev::GM_BN - 1) / dev::GM_BN), (unsigned)b.B);
+}
+
+// Orthonormal basis of range(Y_i) for every instance: shifted CholeskyQR on
+// the first pass, plain passes after it.  The basis ends in *Q (Y or W).
+void b_orth(hipStream_t st, const Batch& b, Bufs& f, double* Y, double* W, int passes,
+            double** Q) {
+  const int tiles = (b.mmax + 63) / 64;
+  double* src = Y;
+  double* dst = W;
+  for (int pass = 0; pass < passes; ++pass) {
+    hipLaunchKernelGGL(k_bgram, dim3(tiles, tiles, b.B), dim3(256), 0, st, b.d_inst, 0, src, b.mmax,
+                       src, b.mmax, (const double*)nullptr, f.G, b.gstride);
+    if (pass == 0)
+      hipLaunchKernelGGL(k_bshift, dim3(b.B), dim3(256), 0, st, b.d_inst, f.G, b.gstride);
+    hipLaunchKernelGGL(k_bchol, dim3(b.B), dim3(dev::CT), 0, st, b.d_inst, 0, f.G, b.gstride,
+                       f.fail);
+    hipLaunchKernelGGL(k_btrinv, dim3(b.B), dim3(dev::CT), 0, st, b.d_inst, 0, f.G, f.Rinv,
+                       b.gstride);
+    hipLaunchKernelGGL(k_bgemm, gemm_grid(b, b.mmax), dim3(256), 0, st, b.d_inst, 0, 0, src,
+                       b.mmax, f.Rinv, b.gstride, 1, (const double*)nullptr, dst, b.mmax);
+    std::swap(src, dst);
+  }
+  *Q = src;
+}
+
+// Y64 = M Q64 for every instance through the FP32 batched product
+void b_apply(hipStream_t st, const Batch& b, Bufs& f, const ProductPlan& pp, const double* Qin,
+             double* Yout) {
+  const int64_t cnt = b.R * b.mmax;
+  launch_convert_f64_to_f32(st, Qin, f.V32, cnt);
+  launch_product(st, b, pp, f.V32, b.mmax, f.Y32, nullptr, 0.f, nullptr, nullptr);
+  launch_convert_f32_to_f64(st, f.Y32, Yout, cnt);
+}
+
+ld_status with_stream(ld_ctx* ctx, hipStream_t st, const Batch& b, int ncols, int variant,
+                      ProductPlan* pp) {
+  const hipStream_t keep = ctx->stream;
+  ctx->stream = st;
+  const ld_status r = plan_product(ctx, b, ncols, variant, pp);
+  ctx->stream = keep;
+  return r;
+}
+
+}  // namespace
+
+ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
+                           const double* shifts, double bcoef, const double* ccoef, int s,
+                           int oversample, int power_iters, double tol, int max_iters, int flags,
+                           ld_result* out, double* per_probe) {
+  // ---- layout: instance i owns padded rows [row0_i, row0_i + ceil(n_i/128)*128)
+  Batch b;
+  b.B = count;
+  b.s = s;
+  int64_t row0 = 0;
+  int me_max = 0, nchunks = 0;
+  for (int i = 0; i < count; ++i) {
+    const ld_instance& x = in[i];
+    BInst I{};
+    I.X64 = x.X;
+    I.n = x.n;
+    I.row0 = row0;
+    I.d = x.d;
+    I.kind = x.kind;
+    I.rank = x.rank;
+    I.m = x.rank + oversample;
+    I.ch0 = nchunks;
+    I.nch = (int)((x.n + FTC - 1) / FTC);
+    nchunks += I.nch;
+    dev::kval32_consts(x.kind, x.lengthscale, x.variance, &I.kc, &I.kv);
+    I.noise = (float)x.noise;
+    I.diag = x.variance + x.noise;
+    I.floor_v = x.noise > 0.0 ? x.noise : 1e-12 * x.variance;
+    I.shift_c = 11.0 * ((double)x.n * I.m + (double)I.m * (I.m + 1)) * 0x1.0p-53;
+    I.key_omega = stream_key(x.precond_seed, kStreamOmega);
+    I.key_probe = stream_key(x.probe_seed, kStreamProbes);
+    b.h.push_back(I);
+    row0 += (x.n + BROWS - 1) / BROWS * BROWS;
+    b.mmax = std::max(b.mmax, I.m);
+    b.lmax = std::max(b.lmax, I.rank);
+    me_max = std::max(me_max, I.m + (I.m & 1));
+  }
+  b.R = row0;
+  b.nblk = b.R / BLK;
+  b.gstride = (int64_t)b.mmax * b.mmax;
+  std::vector<int> blk_inst(b.nblk), ch_inst(nchunks);
+  for (int i = 0; i < count; ++i) {
+    const int64_t first = b.h[i].row0 / BLK, nb = (b.h[i].n + BROWS - 1) / BROWS * (BROWS / BLK);
+    for (int64_t q = 0; q < nb; ++q) blk_inst[first + q] = i;
+    for (int g = 0; g < b.h[i].nch; ++g) ch_inst[b.h[i].ch0 + g] = i;
+  }
+  const int64_t R = b.R, B = count;
+  const int64_t ncol = B * s;
+  const int cbs = (b.mmax + 63) / 64;
+
+  // ---- scratch (one reservation; every buffer below is carved from it)
+  size_t need = 0;
+  auto add = [&](size_t bytes) { need += ((bytes + 255) & ~(size_t)255) + 256; };
+  add(B * sizeof(BInst));
+  add(b.nblk * sizeof(int));
+  add(nchunks * sizeof(int));
+  add(R * BDX * 4);
+  add(R * b.mmax * 8);
+  add(R * b.mmax * 8);
+  add(R * b.mmax * 4);
+  add(R * b.mmax * 4);
+  for (int q = 0; q < 3; ++q) add(B * b.gstride * 8);
+  add(B * b.mmax * 8);
+  add(B * 4 * (int64_t)me_max * me_max * 8);
+  add(B * 4);
+  add(B * 4);
+  add(R * b.lmax * 8);
+  add(R * b.lmax * 8);
+  add(R * b.lmax * 4);
+  add(R * 8);
+  add(R * 8);
+  add(R * 4);
+  add(B * 8);
+  for (int q = 0; q < 6; ++q) add(R * s * 4);
+  for (int q = 0; q < 3; ++q) add(b.nblk * s * 8);
+  for (int q = 0; q < 3; ++q) add(ncol * 8);
+  add(B * b.lmax * s * 8);
+  add((size_t)nchunks * b.lmax * s * 8);
+  add((size_t)(7 * ncol + 4 * J * ncol + J) * 8);
+  add((size_t)(J * ncol + ncol + 2) * 4);
+  add(B * 4);
+  add(2 * 8);
+  add(b.nblk * (size_t)cbs * sizeof(BItem));  // product work items: sketch
+  add(b.nblk * sizeof(BItem));                // solver, 128-row shape
+  add(b.nblk * sizeof(BItem));                // solver, 64-row shape
+  ctx->arena.reset();
+  LD_TRY(ctx->arena.reserve(need));
+  Arena& ar = ctx->arena;
+  auto tk = [&](size_t bytes) { return ar.take(bytes); };
+  b.d_inst = (BInst*)tk(B * sizeof(BInst));
+  b.d_blk_inst = (int*)tk(b.nblk * sizeof(int));
+  int* d_ch_inst = (int*)tk(nchunks * sizeof(int));
+  b.X32 = (float*)tk(R * BDX * 4);
+  Bufs f{};
+  f.Q = (double*)tk(R * b.mmax * 8);
+  f.Y = (double*)tk(R * b.mmax * 8);
+  f.V32 = (float*)tk(R * b.mmax * 4);
+  f.Y32 = (float*)tk(R * b.mmax * 4);
+  f.G = (double*)tk(B * b.gstride * 8);
+  f.Rinv = (double*)tk(B * b.gstride * 8);
+  f.evecs = (double*)tk(B * b.gstride * 8);
+  f.evals = (double*)tk(B * b.mmax * 8);
+  f.jwork = (double*)tk(B * 4 * (int64_t)me_max * me_max * 8);
+  f.fail = (int*)tk(B * 4);
+  f.jstat = (int*)tk(B * 4);
+  f.U = (double*)tk(R * b.lmax * 8);
+  f.F64 = (double*)tk(R * b.lmax * 8);
+  f.F32 = (float*)tk(R * b.lmax * 4);
+  f.D = (double*)tk(R * 8);
+  f.Dinv64 = (double*)tk(R * 8);
+  f.Dinv32 = (float*)tk(R * 4);
+  f.ldP = (double*)tk(B * 8);
+  float* Z = (float*)tk(R * s * 4);
+  float* r = (float*)tk(R * s * 4);
+  float* u = (float*)tk(R * s * 4);
+  float* p = (float*)tk(R * s * 4);
+  float* w = (float*)tk(R * s * 4);
+  float* q = (float*)tk(R * s * 4);
+  double* dwq = (double*)tk(b.nblk * s * 8);
+  double* d1 = (double*)tk(b.nblk * s * 8);
+  double* d2 = (double*)tk(b.nblk * s * 8);
+  double* sg1 = (double*)tk(ncol * 8);
+  double* sg2 = (double*)tk(ncol * 8);
+  double* sgw = (double*)tk(ncol * 8);
+  double* tl = (double*)tk(B * b.lmax * s * 8);
+  double* tpart = (double*)tk((size_t)nchunks * b.lmax * s * 8);
+  double* scal = (double*)tk((size_t)(7 * ncol + 4 * J * ncol + J) * 8);
+  int* iscal = (int*)tk((size_t)(J * ncol + ncol + 2) * 4);
+  int* iact = (int*)tk(B * 4);
+  double* tacc = (double*)tk(2 * 8);
+  if (!tacc) return fail(LD_ENOMEM, "batch: scratch arena too small");
+
+  // the graph form runs on a side stream that joins the context stream
+  const bool use_graph = (flags & LD_BATCH_GRAPH) != 0;
+  hipStream_t st = ctx->stream;
+  if (use_graph) {
+    if (!ctx->side) LD_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    if (!ctx->ev_join) LD_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+    LD_HIP(hipEventRecord(ctx->ev_join, ctx->stream));
+    LD_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_join, 0));
+    st = ctx->side;
+  }
+  // On any return after this point the side stream is joined back first.
+  auto join = [&]() {
+    if (use_graph && hipEventRecord(ctx->ev_join, st) == hipSuccess)
+      (void)hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0);
+  };
+  struct Joiner {
+    std::function<void()> fn;
+    ~Joiner() { fn(); }
+  } joiner{join};
+
+  LD_HIP(hipMemcpyAsync(b.d_inst, b.h.data(), B * sizeof(BInst), hipMemcpyHostToDevice, st));
+  LD_HIP(hipMemcpyAsync(b.d_blk_inst, blk_inst.data(), b.nblk * sizeof(int), hipMemcpyHostToDevice, st));
+  LD_HIP(hipMemcpyAsync(d_ch_inst, ch_inst.data(), nchunks * sizeof(int), hipMemcpyHostToDevice, st));
+  LD_HIP(hipMemsetAsync(f.fail, 0, B * 4, st));
+  LD_HIP(hipMemsetAsync(f.jstat, 0, B * 4, st));
+  hipLaunchKernelGGL(k_bx32, dim3(grid1(R * BDX)), dim3(256), 0, st, b.d_inst, b.d_blk_inst, R, b.X32);
+
+  // ---- preconditioners (range finder, Rayleigh-Ritz, Woodbury factors)
+  ProductPlan sketch;
+  LD_TRY(with_stream(ctx, st, b, b.mmax, 0, &sketch));
+  hipLaunchKernelGGL(k_bomega, dim3(grid1(R * b.mmax)), dim3(256), 0, st, b.d_inst, b.d_blk_inst, R,
+                     b.mmax, f.Q);
+  b_apply(st, b, f, sketch, f.Q, f.Y);
+  double* Qb = nullptr;
+  b_orth(st, b, f, f.Y, f.Q, power_iters == 0 ? 3 : 1, &Qb);
+  for (int it = 0; it < power_iters; ++it) {
+    double* other = Qb == f.Q ? f.Y : f.Q;
+    b_apply(st, b, f, sketch, Qb, other);
+    b_orth(st, b, f, other, Qb, it + 1 == power_iters ? 3 : 1, &Qb);
+  }
+  double* MQ = Qb == f.Q ? f.Y : f.Q;
+  b_apply(st, b, f, sketch, Qb, MQ);
+  const int tiles = (b.mmax + 63) / 64;
+  hipLaunchKernelGGL(k_bgram, dim3(tiles, tiles, B), dim3(256), 0, st, b.d_inst, 0, Qb, b.mmax, MQ,
+                     b.mmax, (const double*)nullptr, f.G, b.gstride);
+  hipLaunchKernelGGL(k_bjacobi, dim3(B), dim3(1024), 0, st, b.d_inst, f.G, b.gstride, f.jwork,
+                     4 * (int64_t)me_max * me_max, f.evals, b.mmax, f.evecs, f.jstat);
+  LD_HIP(hipGetLastError());
+  {
+    std::vector<int> h;
+    LD_TRY(read_ints(ctx, st, f.fail, count, h));
+    for (int i = 0; i < count; ++i)
+      if (h[i]) return fail(LD_ENOTSPD, "batch: CholeskyQR breakdown in instance " + std::to_string(i));
+    LD_TRY(read_ints(ctx, st, f.jstat, count, h));
+    for (int i = 0; i < count; ++i)
+      if (h[i]) return fail(LD_ENOCONV, "batch: Jacobi did not converge in instance " + std::to_string(i));
+    LD_TRY(ensure_pinned(ctx, (size_t)B * b.mmax + 8));
+    LD_HIP(hipMemcpyAsync(ctx->pinned, f.evals, B * b.mmax * 8, hipMemcpyDeviceToHost, st));
+    LD_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < count; ++i)
+      for (int j = 0; j < b.h[i].rank; ++j) {
+        const double v = ctx->pinned[(int64_t)i * b.mmax + j];
+        if (!(v > 0.0) || !std::isfinite(v))
+          return fail(LD_ENOTSPD, "batch: non-positive kept eigenvalue in instance " + std::to_string(i));
+      }
+  }
+  // U = Q V_l;  D;  C = diag(1/lam) + U^T D^-1 U = R^T R;  log det P;  F = D^-1 U R^-1
+  hipLaunchKernelGGL(k_bgemm, gemm_grid(b, b.lmax), dim3(256), 0, st, b.d_inst, 0, 1, Qb, b.mmax,
+                     f.evecs, b.gstride, 1, (const double*)nullptr, f.U, b.lmax);
+  hipLaunchKernelGGL(k_bd, dim3(grid1(R)), dim3(256), 0, st, b.d_inst, b.d_blk_inst, R, f.U, b.lmax,
+                     f.evals, b.mmax, f.D, f.Dinv64);
+  const int ltiles = (b.lmax + 63) / 64;
+  hipLaunchKernelGGL(k_bgram, dim3(ltiles, ltiles, B), dim3(256), 0, st, b.d_inst, 1, f.U, b.lmax,
+                     f.U, b.lmax, f.Dinv64, f.G, b.gstride);
+  hipLaunchKernelGGL(k_bcapdiag, dim3(B), dim3(256), 0, st, b.d_inst, f.G, b.gstride, f.evals, b.mmax);
+  LD_HIP(hipMemsetAsync(f.fail, 0, B * 4, st));
+  hipLaunchKernelGGL(k_bchol, dim3(B), dim3(dev::CT), 0, st, b.d_inst, 1, f.G, b.gstride, f.fail);
+  hipLaunchKernelGGL(k_blogdet, dim3(B), dim3(256), 0, st, b.d_inst, f.D, f.evals, b.mmax, f.G,
+                     b.gstride, f.ldP);
+  hipLaunchKernelGGL(k_btrinv, dim3(B), dim3(dev::CT), 0, st, b.d_inst, 1, f.G, f.Rinv, b.gstride);
+  hipLaunchKernelGGL(k_bgemm, gemm_grid(b, b.lmax), dim3(256), 0, st, b.d_inst, 1, 1, f.U, b.lmax,
+                     f.Rinv, b.gstride, 0, f.Dinv64, f.F64, b.lmax);
+  launch_convert_f64_to_f32(st, f.F64, f.F32, R * b.lmax);
+  launch_convert_f64_to_f32(st, f.Dinv64, f.Dinv32, R);
+  LD_HIP(hipGetLastError());
+  std::vector<double> logdetP(count);
+  {
+    std::vector<int> h;
+    LD_TRY(read_ints(ctx, st, f.fail, count, h));
+    for (int i = 0; i < count; ++i)
+      if (h[i])
+        return fail(LD_ENOTSPD, "batch: capacitance Cholesky breakdown in instance " + std::to_string(i));
+    LD_HIP(hipMemcpyAsync(ctx->pinned, f.ldP, B * 8, hipMemcpyDeviceToHost, st));
+    LD_HIP(hipStreamSynchronize(st));
+    std::copy(ctx->pinned, ctx->pinned + count, logdetP.begin());
+    for (int i = 0; i < count; ++i)
+      if (!std::isfinite(logdetP[i]))
+        return fail(LD_ENOTSPD, "batch: log det P is not finite in instance " + std::to_string(i));
+  }
+  auto t1 = std::chrono::steady_clock::now();
+
+  // ---- multi-shift CG over every (instance, probe) column
+  Scal S;
+  S.rho = scal;
+  S.rho0 = scal + ncol;
+  S.alpha = scal + 2 * ncol;
+  S.beta = scal + 3 * ncol;
+  S.alpha_prev = scal + 4 * ncol;
+  S.beta_prev = scal + 5 * ncol;
+  S.ztz = scal + 6 * ncol;
+  S.zeta = scal + 7 * ncol;
+  S.zeta_prev = S.zeta + J * ncol;
+  S.ztp = S.zeta_prev + J * ncol;
+  S.ztx = S.ztp + J * ncol;
+  double* delta = S.ztx + J * ncol;
+  S.frozen = iscal;
+  S.active = iscal + J * ncol;
+  S.status = iscal + J * ncol + ncol;
+  LD_TRY(ensure_pinned(ctx, (size_t)(J * ncol + 3 * ncol + 16)));
+  for (int j = 0; j < J; ++j) ctx->pinned[j] = shifts[j] - shifts[0];
+  LD_HIP(hipMemcpyAsync(delta, ctx->pinned, J * sizeof(double), hipMemcpyHostToDevice, st));
+  LD_HIP(hipMemsetAsync(S.status, 0, 2 * sizeof(int), st));
+  LD_HIP(hipStreamSynchronize(st));
+
+  hipLaunchKernelGGL(k_bprobes, dim3(grid1(R * s)), dim3(256), 0, st, b.d_inst, b.d_blk_inst, R, s, Z);
+  const int64_t vec = R * s;
+  auto woodbury = [&](const float* rin, float* uout, const int* act) {
+    hipLaunchKernelGGL(k_bft, dim3(ltiles, nchunks), dim3(256), 0, st, b.d_inst, d_ch_inst, f.F32,
+                       b.lmax, rin, s, b.lmax, tpart, act);
+    hipLaunchKernelGGL(k_bft_sum, dim3(B), dim3(256), 0, st, b.d_inst, s, b.lmax, tpart, tl, act);
+    hipLaunchKernelGGL(k_bwout, dim3((unsigned)b.nblk), dim3(256), 0, st, b.d_inst, b.d_blk_inst,
+                       f.F32, b.lmax, f.Dinv32, tl, b.lmax, rin, s, uout, Z, d1, d2, act);
+  };
+  hipLaunchKernelGGL(k_bcopy2, dim3(grid1(vec)), dim3(256), 0, st, Z, r, p, vec);
+  woodbury(r, u, nullptr);
+  hipLaunchKernelGGL(k_bcopy2, dim3(grid1(vec)), dim3(256), 0, st, u, w, (float*)nullptr, vec);
+  hipLaunchKernelGGL(k_bsegsum, dim3(B), dim3(256), 0, st, b.d_inst, s, d1, sg1);
+  hipLaunchKernelGGL(k_bsegsum, dim3(B), dim3(256), 0, st, b.d_inst, s, d2, sg2);
+  launch_scal_init(st, S, sg1, sg2, 1, ncol, J);
+  hipLaunchKernelGGL(k_binst_active, dim3((count + 255) / 256), dim3(256), 0, st, count, s,
+                     S.active, iact);
+  LD_HIP(hipGetLastError());
+
+  // product tile shape: both shapes are timed once per context (or on request)
+  ProductPlan pv[2];
+  LD_TRY(with_stream(ctx, st, b, s, 0, &pv[0]));
+  LD_TRY(with_stream(ctx, st, b, s, 1, &pv[1]));
+  if (ctx->bvariant < 0 || (flags & LD_BATCH_RETUNE)) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    LD_HIP(hipEventCreate(&e0));
+    LD_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int pick = 0;
+    for (int v = 0; v < 2; ++v) {
+      float tot = 0.f;
+      for (int rep = 0; rep < 3; ++rep) {
+        float ms = 0.f;
+        (void)hipEventRecord(e0, st);
+        launch_product(st, b, pv[v], w, s, q, p, (float)shifts[0], dwq, nullptr);
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) tot += ms;  // the first launch warms up
+      }
+      if (tot < best) {
+        best = tot;
+        pick = v;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    LD_HIP(hipGetLastError());
+    ctx->bvariant = pick;
+  }
+  const ProductPlan& pp = pv[ctx->bvariant];
+  // Instrumentation (ctx->timing, eager form only): events around every
+  // product launch and the launch's algorithmic work summed on the device.
+  const bool timed = ctx->timing && !use_graph;
+  if (timed) LD_HIP(hipMemsetAsync(tacc, 0, 2 * 8, st));
+
+  auto body = [&]() -> ld_status {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+      hipLaunchKernelGGL(k_bwork, dim3(1), dim3(256), 0, st, b.d_inst, iact, count, s, tacc);
+      LD_TRY(timing_pair(ctx, &e0, &e1, 0.0, 0.0));
+      LD_HIP(hipEventRecord(e0, st));
+    }
+    launch_product(st, b, pp, w, s, q, p, (float)shifts[0], dwq, iact);
+    if (timed) LD_HIP(hipEventRecord(e1, st));
+    hipLaunchKernelGGL(k_bsegsum, dim3(B), dim3(256), 0, st, b.d_inst, s, dwq, sgw);
+    launch_scal_alpha(st, S, sgw, 1, ncol);
+    hipLaunchKernelGGL(k_bupdate_r, dim3(grid1(vec)), dim3(256), 0, st, b.d_inst, b.d_blk_inst, R,
+                       s, r, q, S.alpha);
+    woodbury(r, u, iact);
+    hipLaunchKernelGGL(k_bsegsum, dim3(B), dim3(256), 0, st, b.d_inst, s, d1, sg1);
+    hipLaunchKernelGGL(k_bsegsum, dim3(B), dim3(256), 0, st, b.d_inst, s, d2, sg2);
+    launch_scal_beta(st, S, sg1, sg2, 1, ncol, J, delta, tol);
+    hipLaunchKernelGGL(k_bupdate_pw, dim3(grid1(vec)), dim3(256), 0, st, b.d_inst, b.d_blk_inst, R,
+                       s, p, w, r, u, S.beta, S.active);
+    hipLaunchKernelGGL(k_binst_active, dim3((count + 255) / 256), dim3(256), 0, st, count, s,
+                       S.active, iact);
+    return LD_OK;
+  };
+
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    hipGraph_t graph = nullptr;
+    LD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    ld_status cs = LD_OK;
+    for (int kk = 0; kk < kChunk && cs == LD_OK; ++kk) cs = body();
+    const hipError_t ce = hipStreamEndCapture(st, &graph);
+    if (cs != LD_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return cs;
+    }
+    if (ce != hipSuccess) return fail(LD_EHIP, std::string("graph capture: ") + hipGetErrorString(ce));
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess)
+      return fail(LD_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+  }
+  int it = 0, active = (int)ncol;
+  bool breakdown = false;
+  ld_status st_ = LD_OK;
+  while (it < max_iters && active > 0 && st_ == LD_OK) {
+    if (use_graph && it + kChunk <= max_iters) {
+      if (hipGraphLaunch(exec, st) != hipSuccess) {
+        st_ = fail(LD_EHIP, "graph launch failed");
+        break;
+      }
+      it += kChunk;
+    } else {
+      const int todo = std::min(kChunk, max_iters - it);
+      for (int kk = 0; kk < todo && st_ == LD_OK; ++kk) st_ = body();
+      it += todo;
+    }
+    if (st_ != LD_OK) break;
+    if (hipMemcpyAsync(ctx->pinned, S.status, 2 * sizeof(int), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      st_ = fail(LD_EHIP, "status readback failed");
+      break;
+    }
+    if (timed) timing_collect(ctx);
+    active = ((const int*)ctx->pinned)[0];
+    if (((const int*)ctx->pinned)[1]) breakdown = true;
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  LD_TRY(st_);
+  if (timed) {
+    LD_HIP(hipMemcpyAsync(ctx->pinned, tacc, 2 * 8, hipMemcpyDeviceToHost, st));
+    LD_HIP(hipStreamSynchronize(st));
+    ctx->mm_flops += ctx->pinned[0];
+    ctx->mm_bytes += ctx->pinned[1];
+  }
+
+  // ---- readback and the Hutchinson mean of every instance (FP64)
+  double* hp = ctx->pinned;
+  LD_HIP(hipMemcpyAsync(hp, S.ztx, (size_t)J * ncol * 8, hipMemcpyDeviceToHost, st));
+  LD_HIP(hipMemcpyAsync(hp + J * ncol, S.ztz, ncol * 8, hipMemcpyDeviceToHost, st));
+  LD_HIP(hipMemcpyAsync(hp + J * ncol + ncol, S.rho, ncol * 8, hipMemcpyDeviceToHost, st));
+  LD_HIP(hipMemcpyAsync(hp + J * ncol + 2 * ncol, S.rho0, ncol * 8, hipMemcpyDeviceToHost, st));
+  LD_HIP(hipStreamSynchronize(st));
+  const double solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
+  int unconverged = 0;
+  std::vector<double> t(s);
+  for (int i = 0; i < count; ++i) {
+    double mean = 0.0, worst = 0.0;
+    int conv = 0;
+    for (int c = 0; c < s; ++c) {
+      const int64_t g = (int64_t)i * s + c;
+      double v = bcoef * hp[J * ncol + g];
+      for (int j = 0; j < J; ++j) v += ccoef[j] * hp[(int64_t)j * ncol + g];
+      t[c] = v;
+      mean += v;
+      const double rr = std::sqrt(std::max(0.0, hp[J * ncol + ncol + g] / hp[J * ncol + 2 * ncol + g]));
+      worst = std::max(worst, rr);
+      if (rr <= tol) ++conv;
+    }
+    mean /= s;
+    double var = 0.0;
+    for (int c = 0; c < s; ++c) var += (t[c] - mean) * (t[c] - mean);
+    ld_result& o = out[i];
+    o.logdet_P = logdetP[i];
+    o.trace_term = mean;
+    o.logdet = logdetP[i] + mean;
+    o.std_err = s > 1 ? std::sqrt(var / (s - 1) / s) : NAN;
+    o.rel_resid = worst;
+    o.seconds_solve = solve_s;
+    o.iterations = std::min(it, max_iters);
+    o.converged_cols = conv;
+    o.k = J;
+    o.num_probes = s;
+    if (per_probe) std::copy(t.begin(), t.end(), per_probe + (int64_t)i * s);
+    if (conv < s) ++unconverged;
+  }
+  if (breakdown) return fail(LD_ENOTSPD, "batch: non-positive curvature or residual in the solver");
+  if (unconverged) return fail(LD_ENOCONV, "batch: max_iters reached before every probe converged");
+  return LD_OK;
+}
+
+}  // namespace ld

@@ -75,6 +75,11 @@ struct ld_ctx {
   double mm_flops = 0.0;
   double mm_bytes = 0.0;
   std::vector<double> pending_flops, pending_bytes;
+  // batched form: side stream for graph replay, its join event, and the
+  // product tile shape chosen by timing (-1 until the first batched call)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_join = nullptr;
+  int bvariant = -1;
 };
 
 struct ld_precond {
@@ -181,6 +186,31 @@ void launch_gemm64(hipStream_t st, const double* A, const double* B, int ldb, co
 ld_status jacobi_eigh(ld_ctx* ctx, double* A, int m, double* evals, double* evecs);
 
 // pcg.hip
+// Per-column solver scalars of the multi-shift CG (FP64, device arrays;
+// column c of ncols, shift j of J stored at j * ncols + c).
+struct Scal {
+  double* rho;
+  double* rho0;
+  double* alpha;
+  double* beta;
+  double* alpha_prev;
+  double* beta_prev;
+  double* ztz;
+  double* zeta;       // J x ncols
+  double* zeta_prev;  // J x ncols
+  double* ztp;        // J x ncols  z^T p_j
+  double* ztx;        // J x ncols  z^T x_j
+  int* frozen;        // J x ncols
+  int* active;        // ncols
+  int* status;        // [0] = active columns, [1] = breakdown flag
+};
+// Single-workgroup scalar steps; the column dots arrive as nblk partial rows
+// of ncols values (nblk = 1 for sums already reduced).
+void launch_scal_init(hipStream_t st, const Scal& S, const double* d1, const double* d2, int nblk,
+                      int64_t ncols, int J);
+void launch_scal_alpha(hipStream_t st, const Scal& S, const double* dots, int nblk, int64_t ncols);
+void launch_scal_beta(hipStream_t st, const Scal& S, const double* d1, const double* d2, int nblk,
+                      int64_t ncols, int J, const double* delta, double tol);
 ld_status woodbury_apply(ld_ctx* ctx, const ld_precond* P, bool f64, const void* R, int64_t s,
                          void* OUT);
 size_t woodbury_scratch_bytes(int64_t n, int rank, int64_t s);
@@ -192,5 +222,12 @@ ld_status multishift_pcg(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld
                          int max_iters, std::vector<double>& ztx, std::vector<double>& ztz,
                          int* iterations, int* converged, double* rel_resid, bool* breakdown);
 size_t pcg_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int rank, int64_t s, int J);
+
+// batch.hip -- the whole estimator over `count` validated instances; shifts
+// a_j (ascending), constant b and weights c_j of r_k.
+ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
+                           const double* shifts, double bcoef, const double* ccoef, int s,
+                           int oversample, int power_iters, double tol, int max_iters, int flags,
+                           ld_result* out, double* per_probe);
 
 }  // namespace ld

@@ -21,6 +21,9 @@
 // h * (BK / halves) + t for both operands.
 #include <algorithm>
 
+#include <cmath>
+
+#include "kfun_dev.hpp"
 #include "ld_common.hpp"
 
 namespace ld {
@@ -67,20 +70,8 @@ __host__ __device__ inline WGRange wg_range(const SK& p, int g) {
 }
 
 // ---------------------------------------------------------- kernel values --
-// FP32: RBF c = log2(e) / (2 l^2);  Matern-5/2 c = sqrt(5) / l
-// Constants are folded into base-2 exponents:
-//   RBF     c = log2(e) / (2 l^2),  v = log2(variance):  2^(v - c r^2)
-//   Matern  c = sqrt(5) log2(e) / l, v = variance: with u = c r (= t log2 e,
-//           t = sqrt5 r / l), variance (1 + t + t^2/3) e^-t
-//           = (v + u v / log2e + u^2 v / (3 log2e^2)) 2^-u
-template <int KIND>
-__device__ __forceinline__ float kval32(float r2, float v, float c) {
-  if (KIND == LD_RBF) return __builtin_amdgcn_exp2f(__builtin_fmaf(-r2, c, v));
-  const float u = __builtin_amdgcn_sqrtf(r2) * c;
-  const float p = __builtin_fmaf(
-      u, __builtin_fmaf(u, v * (1.0f / (3.0f * kLog2e * kLog2e)), v * (1.0f / kLog2e)), v);
-  return p * __builtin_amdgcn_exp2f(-u);
-}
+// FP32 kernel values: kval32 (kfun_dev.hpp), shared with the batched path.
+using dev::kval32;
 // FP64: RBF c = 1 / (2 l^2);  Matern-5/2 c = sqrt(5) / l
 template <int KIND>
 __device__ __forceinline__ double kval64(double r2, double var, double c) {

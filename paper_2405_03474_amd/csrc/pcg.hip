@@ -184,22 +184,6 @@ __global__ __launch_bounds__(256) void k_wood_out(const T* __restrict__ F,
 }
 
 // ------------------------------------------------------------------ PCG --
-struct Scal {
-  double* rho;
-  double* rho0;
-  double* alpha;
-  double* beta;
-  double* alpha_prev;
-  double* beta_prev;
-  double* ztz;
-  double* zeta;       // J x s
-  double* zeta_prev;  // J x s
-  double* ztp;        // J x s
-  double* ztx;        // J x s
-  int* frozen;        // J x s
-  int* active;        // s
-  int* status;        // [0] = active columns, [1] = breakdown flag
-};
 
 template <typename T>
 __global__ void k_copy2(const T* __restrict__ src, T* __restrict__ a, T* __restrict__ b,
@@ -584,6 +568,20 @@ ld_status multishift_pcg(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld
   *rel_resid = o.rel_resid;
   *breakdown = o.breakdown;
   return stt;
+}
+
+void launch_scal_init(hipStream_t st, const Scal& S, const double* d1, const double* d2, int nblk,
+                      int64_t ncols, int J) {
+  hipLaunchKernelGGL(k_scal_init, dim3(1), dim3(256), 0, st, S, d1, d2, nblk, ncols, J);
+}
+
+void launch_scal_alpha(hipStream_t st, const Scal& S, const double* dots, int nblk, int64_t ncols) {
+  hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(256), 0, st, S, dots, nblk, ncols);
+}
+
+void launch_scal_beta(hipStream_t st, const Scal& S, const double* d1, const double* d2, int nblk,
+                      int64_t ncols, int J, const double* delta, double tol) {
+  hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(256), 0, st, S, d1, d2, nblk, ncols, J, delta, tol);
 }
 
 size_t pcg_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int rank, int64_t s, int J) {

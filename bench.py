@@ -194,6 +194,8 @@ def batch_main(args, torch, L):
     exact_all = json.load(open(os.path.join(ROOT, "tests", "golden", "exact_logdet.json"))).get(
         "c4_batch256", {}).get("logdet") if os.path.exists(
         os.path.join(ROOT, "tests", "golden", "exact_logdet.json")) else None
+    if args.dump:
+        json.dump([{"n": g.n, **r} for g, r in zip(insts, last)], open(args.dump, "w"))
     accuracy = {"iterations": last[0]["iterations"],
                 "converged": sum(r["converged_cols"] == BatchRunner.S for r in last)}
     if exact_all:
@@ -201,6 +203,12 @@ def batch_main(args, torch, L):
         accuracy.update({"max_err_vs_exact": max(errs), "median_err_vs_exact": float(
             sorted(errs)[len(errs) // 2]), "within_1e-3": sum(e <= 1e-3 for e in errs),
             "error_rule": "relative where |log det| >= 0.01 n, else abs/n"})
+        worst = sorted(range(count), key=lambda i: -errs[i])[:6]
+        accuracy["worst"] = [{"i": i, "n": insts[i].n, "d": insts[i].d, "kind": insts[i].kind,
+                              "lengthscale": insts[i].lengthscale, "noise": insts[i].noise,
+                              "err": errs[i], "logdet": last[i]["logdet"], "exact": exact_all[i],
+                              "logdet_P": last[i]["logdet_P"], "std_err": last[i]["std_err"]}
+                             for i in worst]
     avg_ms = mm_ms / max(mm_calls, 1)
     achieved = (mm_flops / max(mm_calls, 1)) / (avg_ms / 1e3) if mm_calls else 0.0
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12,
@@ -313,6 +321,7 @@ def main():
                     help="batched form: also time 256 sequential plain FP32 calls")
     ap.add_argument("--no-graph", action="store_true", help="batched form: eager launches")
     ap.add_argument("--cpu-sample-count", type=int, default=12)
+    ap.add_argument("--dump", default="", help="batched form: write per-instance results (JSON)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1"}))

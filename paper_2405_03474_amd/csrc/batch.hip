@@ -51,9 +51,7 @@ struct BItem {
   int inst, rb, cb, pad;  // instance, row block, column block
 };
 
-__device__ __forceinline__ float kval_rt(int kind, float r2, float v, float c) {
-  return kind == LD_RBF ? dev::kval32<LD_RBF>(r2, v, c) : dev::kval32<LD_MATERN52>(r2, v, c);
-}
+using dev::f64x4;
 
 // ------------------------------------------------------------ fill kernels --
 __global__ void k_bx32(const BInst* __restrict__ inst, const int* __restrict__ blk_inst,
@@ -94,48 +92,87 @@ __global__ void k_bprobes(const BInst* __restrict__ inst, const int* __restrict_
 }
 
 // ------------------------------------------------------- batched product --
-// Y = M V (+ noise V + alpha2 X2) on the instance's rows; padded rows of Y
+// Y = M V (+ noise V + alpha2 X2) on one instance's rows; padded rows of Y
 // are written as zero.  dots[b][c] = sum over the 64-row block b of V .* Y.
-template <int NB, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_bmm(const BInst* __restrict__ inst,
-                                                    const BItem* __restrict__ items,
-                                                    const float* __restrict__ X32,
-                                                    const float* __restrict__ V, int ld,
-                                                    float* __restrict__ Y,
-                                                    const float* __restrict__ X2, float alpha2,
-                                                    double* __restrict__ dots,
-                                                    const int* __restrict__ iact) {
-  constexpr int NT = 32 * NB;
+//
+// One workgroup per work item (instance, row block of 32 * WAVES rows,
+// column block of NT columns) runs the whole k range: each stage stages 32
+// points and a 32 x NT block of V in LDS (double buffered, the next stage
+// prefetched in registers), every lane generates kernel entries for its
+// rows, and the matrix cores multiply them into the accumulators.  The
+// instance's kernel kind and dimension select a specialised inner loop
+// (dimension padded to 2, 3, 4 or 8), so no lane evaluates a branch per
+// entry.
+//  MF = 32: v_mfma_f32_32x32x2f32, NT = 32 * NB; lane half h supplies
+//           k = 16 h + t in step t (t < 16).
+//  MF = 16: v_mfma_f32_16x16x4f32 for narrow blocks (NT = 16): each wave
+//           covers two 16-row halves; lane group g supplies k = 8 g + t in
+//           step t (t < 8).  Output lane l, register r: row 4 (l / 16) + r,
+//           column l % 16.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+template <int MF, int NB>
+struct BmmShape {
+  static constexpr int NT = MF * NB;  // columns per workgroup
+  static constexpr int AS = BBK + 4;  // LDS row stride of the transposed V tile
+};
+
+template <int MF, int NB>
+struct BmmAcc;
+template <int NB>
+struct BmmAcc<32, NB> {
+  f32x16 v[NB];
+};
+template <int NB>
+struct BmmAcc<16, NB> {
+  f32x4v v[2][NB];
+};
+
+template <int MF, int NB, int WAVES, int KIND, int D>
+__device__ __forceinline__ void bmm_body(const BInst& I, const BItem& it, const float* __restrict__ X32,
+                                         const float* __restrict__ V, int ld, float* __restrict__ Y,
+                                         const float* __restrict__ X2, float alpha2,
+                                         double* __restrict__ dots, float* __restrict__ Bt,
+                                         float* __restrict__ Xs, double* __restrict__ red) {
+  constexpr int NT = BmmShape<MF, NB>::NT;
+  constexpr int AS = BmmShape<MF, NB>::AS;
   constexpr int NTH = 64 * WAVES;
   constexpr int BMW = 32 * WAVES;
-  constexpr int AS = BBK + 4;
-  constexpr int VPT = BBK * NT / NTH;    // V values per thread per stage
-  constexpr int XPT = BBK * BDX / NTH;   // point values per thread per stage
-  __shared__ __attribute__((aligned(16))) float Bt[2][NT * AS];
-  __shared__ float Xs[2][BBK * BDX];
-  __shared__ double red[2 * WAVES][NT];
-  const BItem it = items[blockIdx.x];
-  if (iact && !iact[it.inst]) return;  // every probe of this instance has converged
-  const BInst I = inst[it.inst];
+  constexpr int VPT = BBK * NT / NTH;   // V values per thread per stage
+  constexpr int XPT = BBK * BDX / NTH;  // point values per thread per stage
+  static_assert(VPT * NTH == BBK * NT && XPT * NTH == BBK * BDX, "stage split");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int li = lane & 31, lh = lane >> 5;
   const int64_t n = I.n;
   const int64_t r0 = I.row0 + (int64_t)it.rb * BMW;  // first global row of the block
   const int c0 = it.cb * NT;
   const float* Vi = V + I.row0 * ld;
+  const float kv = I.kv, kc = I.kc;
 
-  float xr[BDX];
-  {
-    const int64_t lr = r0 - I.row0 + 32 * wave + li;
+  // this lane's row points (MF = 32: one row; MF = 16: one per half)
+  constexpr int NR = MF == 32 ? 1 : 2;
+  float xr[NR][D];
 #pragma unroll
-    for (int dd = 0; dd < BDX; ++dd) xr[dd] = lr < n ? X32[(I.row0 + lr) * BDX + dd] : 0.f;
+  for (int h = 0; h < NR; ++h) {
+    const int lr_in = MF == 32 ? 32 * wave + (lane & 31) : 32 * wave + 16 * h + (lane & 15);
+    const int64_t lr = r0 - I.row0 + lr_in;
+#pragma unroll
+    for (int dd = 0; dd < D; ++dd) xr[h][dd] = lr < n ? X32[(I.row0 + lr) * BDX + dd] : 0.f;
   }
-  typedef float f32x16 __attribute__((ext_vector_type(16)));
-  f32x16 acc[NB];
+  BmmAcc<MF, NB> acc;
+  if constexpr (MF == 32) {
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb)
+    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
+      for (int r = 0; r < 16; ++r) acc.v[nb][r] = 0.f;
+  } else {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc.v[h][nb][r] = 0.f;
+  }
 
   const int S = (int)((n + BBK - 1) / BBK);
   float tv[VPT], tx[XPT];
@@ -154,11 +191,20 @@ __global__ __launch_bounds__(64 * WAVES) void k_bmm(const BInst* __restrict__ in
       tx[j] = kr < n ? X32[(I.row0 + kr) * BDX + e % BDX] : 0.f;
     }
   };
+  auto entry = [&](const float* xr_, const float* xk) {
+    float r2 = 0.f;
+#pragma unroll
+    for (int dd = 0; dd < D; ++dd) {
+      const float df = xr_[dd] - xk[dd];
+      r2 = __builtin_fmaf(df, df, r2);
+    }
+    return dev::kval32<KIND>(r2, kv, kc);
+  };
   load(0);
   int buf = 0;
   for (int st = 0; st < S; ++st) {
-    float* bt = Bt[buf];
-    float* xs = Xs[buf];
+    float* bt = Bt + buf * NT * AS;
+    float* xs = Xs + buf * BBK * BDX;
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int e = tid + NTH * j;
@@ -168,72 +214,139 @@ __global__ __launch_bounds__(64 * WAVES) void k_bmm(const BInst* __restrict__ in
     for (int j = 0; j < XPT; ++j) xs[tid + NTH * j] = tx[j];
     __syncthreads();
     if (st + 1 < S) load(st + 1);
-    float a[16], b[NB][16];
+    if constexpr (MF == 32) {
+      const int li = lane & 31, lh = lane >> 5;
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const float4* bp = (const float4*)&bt[(nb * 32 + li) * AS + lh * 16];
+      for (int t4 = 0; t4 < 16; t4 += 4) {
+        float a[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float4 v = bp[q];
-        b[nb][4 * q + 0] = v.x;
-        b[nb][4 * q + 1] = v.y;
-        b[nb][4 * q + 2] = v.z;
-        b[nb][4 * q + 3] = v.w;
+        for (int t = 0; t < 4; ++t) a[t] = entry(xr[0], &xs[(lh * 16 + t4 + t) * BDX]);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const float4 b = *(const float4*)&bt[(nb * 32 + li) * AS + lh * 16 + t4];
+          acc.v[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0], b.x, acc.v[nb], 0, 0, 0);
+          acc.v[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1], b.y, acc.v[nb], 0, 0, 0);
+          acc.v[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[2], b.z, acc.v[nb], 0, 0, 0);
+          acc.v[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[3], b.w, acc.v[nb], 0, 0, 0);
+        }
+      }
+    } else {
+      const int lj = lane & 15, lg = lane >> 4;
+#pragma unroll
+      for (int t4 = 0; t4 < 8; t4 += 4) {
+        float a[2][4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const float* xk = &xs[(lg * 8 + t4 + t) * BDX];
+          a[0][t] = entry(xr[0], xk);
+          a[1][t] = entry(xr[1], xk);
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const float4 b = *(const float4*)&bt[(nb * 16 + lj) * AS + lg * 8 + t4];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            acc.v[h][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[h][0], b.x, acc.v[h][nb], 0, 0, 0);
+            acc.v[h][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[h][1], b.y, acc.v[h][nb], 0, 0, 0);
+            acc.v[h][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[h][2], b.z, acc.v[h][nb], 0, 0, 0);
+            acc.v[h][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[h][3], b.w, acc.v[h][nb], 0, 0, 0);
+          }
+        }
       }
     }
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const float* xk = &xs[(lh * 16 + t) * BDX];
-      float r2 = 0.f;
-#pragma unroll
-      for (int dd = 0; dd < BDX; ++dd)
-        if (dd < I.d) {
-          const float df = xr[dd] - xk[dd];
-          r2 = __builtin_fmaf(df, df, r2);
-        }
-      a[t] = kval_rt(I.kind, r2, I.kv, I.kc);
-    }
-#pragma unroll
-    for (int t = 0; t < 16; ++t)
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t], b[nb][t], acc[nb], 0, 0, 0);
     buf ^= 1;
   }
 
   // epilogue: this workgroup owns its rows, so it writes Y directly
   double dsum[NB];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    dsum[nb] = 0.0;
-    const int c = c0 + nb * 32 + li;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int row = 32 * wave + 8 * (r >> 2) + 4 * lh + (r & 3);
-      const int64_t grow = r0 + row;
-      if (c >= ld) continue;
-      float y = 0.f;
-      if (grow - I.row0 < n) {
-        const int64_t off = grow * ld + c;
-        double v = (double)acc[nb][r] + (double)I.noise * (double)V[off];
-        if (X2) v += (double)alpha2 * (double)X2[off];
-        y = (float)v;
-        dsum[nb] += (double)V[off] * (double)y;
-      }
-      Y[grow * ld + c] = y;
+  for (int nb = 0; nb < NB; ++nb) dsum[nb] = 0.0;
+  auto put = [&](int nb, int row, int c, float a) {
+    if (c >= ld) return;
+    const int64_t grow = r0 + row;
+    float y = 0.f;
+    if (grow - I.row0 < n) {
+      const int64_t off = grow * ld + c;
+      double v = (double)a + (double)I.noise * (double)V[off];
+      if (X2) v += (double)alpha2 * (double)X2[off];
+      y = (float)v;
+      dsum[nb] += (double)V[off] * (double)y;
     }
+    Y[grow * ld + c] = y;
+  };
+  if constexpr (MF == 32) {
+    const int li = lane & 31, lh = lane >> 5;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        put(nb, 32 * wave + 8 * (r >> 2) + 4 * lh + (r & 3), c0 + nb * 32 + li, acc.v[nb][r]);
+  } else {
+    const int lj = lane & 15, lg = lane >> 4;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          put(nb, 32 * wave + 16 * h + 4 * lg + r, c0 + nb * 16 + lj, acc.v[h][nb][r]);
   }
   if (dots) {
+    // red[wave][lane][nb]; the 64-row block q gathers waves 2q and 2q + 1,
+    // and within them every lane that holds column c
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) red[2 * wave + lh][nb * 32 + li] = dsum[nb];
+    for (int nb = 0; nb < NB; ++nb) red[(wave * 64 + lane) * NB + nb] = dsum[nb];
     __syncthreads();
-    // 64-row block q of this workgroup gathers waves 2q, 2q + 1 (both halves)
+    constexpr int LPC = 64 / MF;  // lanes of a wave holding one column
     for (int e = tid; e < (BMW / BLK) * NT; e += NTH) {
       const int q = e / NT, c = e % NT;
-      const double t = (red[4 * q][c] + red[4 * q + 1][c]) + (red[4 * q + 2][c] + red[4 * q + 3][c]);
+      const int nb = c / MF, cl = c % MF;
+      double t = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < 2; ++w2)
+#pragma unroll
+        for (int j = 0; j < LPC; ++j) t += red[((2 * q + w2) * 64 + cl + MF * j) * NB + nb];
       if (c0 + c < ld) dots[((r0 / BLK) + q) * (int64_t)ld + c0 + c] = t;
     }
   }
+}
+
+template <int MF, int NB, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_bmm(const BInst* __restrict__ inst,
+                                                    const BItem* __restrict__ items,
+                                                    const float* __restrict__ X32,
+                                                    const float* __restrict__ V, int ld,
+                                                    float* __restrict__ Y,
+                                                    const float* __restrict__ X2, float alpha2,
+                                                    double* __restrict__ dots,
+                                                    const int* __restrict__ iact) {
+  constexpr int NT = BmmShape<MF, NB>::NT;
+  constexpr int AS = BmmShape<MF, NB>::AS;
+  __shared__ __attribute__((aligned(16))) float Bt[2 * NT * AS];
+  __shared__ float Xs[2 * BBK * BDX];
+  __shared__ double red[WAVES * 64 * NB];
+  const BItem it = items[blockIdx.x];
+  if (iact && !iact[it.inst]) return;  // every probe of this instance has converged
+  const BInst I = inst[it.inst];
+  const int dcat = I.d <= 2 ? 2 : (I.d == 3 ? 3 : (I.d == 4 ? 4 : 8));
+#define LD_BMM_CASE(KIND, DD)                                                                   \
+  bmm_body<MF, NB, WAVES, KIND, DD>(I, it, X32, V, ld, Y, X2, alpha2, dots, Bt, Xs, red)
+  if (I.kind == LD_RBF) {
+    switch (dcat) {
+      case 2: LD_BMM_CASE(LD_RBF, 2); break;
+      case 3: LD_BMM_CASE(LD_RBF, 3); break;
+      case 4: LD_BMM_CASE(LD_RBF, 4); break;
+      default: LD_BMM_CASE(LD_RBF, 8); break;
+    }
+  } else {
+    switch (dcat) {
+      case 2: LD_BMM_CASE(LD_MATERN52, 2); break;
+      case 3: LD_BMM_CASE(LD_MATERN52, 3); break;
+      case 4: LD_BMM_CASE(LD_MATERN52, 4); break;
+      default: LD_BMM_CASE(LD_MATERN52, 8); break;
+    }
+  }
+#undef LD_BMM_CASE
 }
 
 // -------------------------------------------------------- dense, batched --
@@ -483,56 +596,123 @@ __global__ __launch_bounds__(256) void k_blogdet(const BInst* __restrict__ inst,
 
 // ----------------------------------------------------------- solver pieces --
 // Partial projections of the Woodbury apply: for row chunk g (FTC rows of one
-// instance) part_g (rank_i x s, at g * lmax * s) = F_g^T R_g.
+// instance) part_g (rank_i x s, at g * lmax * s) = F_g^T R_g, on FP64 matrix
+// cores (v_mfma_f64_16x16x4f64; FP32 inputs widened exactly, FP64
+// accumulation).  Stages of 32 rows of F (one pass covers up to FT_PW of
+// the rank columns) and of R are loaded with 16-byte reads, prefetched in
+// registers while the previous stage is multiplied out of LDS.  The output is
+// cut into 16 x 16 (l, c) tiles, at most four per wave per pass; in step t a
+// wave consumes rows 4t .. 4t+3 of the stage, lane group g = lane/16
+// supplying row 4t + g.  Output lane l, register r: tile row l/16 + 4 r,
+// column l % 16.  Requires ldf % 4 == 0 (16-byte rows of F) and s <= 64.
+constexpr int FT_ROWS = 32;
+constexpr int FT_PW = 256;  // widest column pass (s <= 16; 128 for s <= 32, 64 above)
 __global__ __launch_bounds__(256) void k_bft(const BInst* __restrict__ inst,
                                              const int* __restrict__ ch_inst,
                                              const float* __restrict__ F, int ldf,
                                              const float* __restrict__ R, int s, int lmax,
                                              double* __restrict__ part,
                                              const int* __restrict__ iact) {
-  __shared__ double Fs[16][65];
-  __shared__ double Rs[16][65];
-  const int g = blockIdx.y;
+  constexpr int FS = FT_PW + 4;  // LDS row stride of the F stage
+  constexpr int RS = 64 + 4;     // LDS row stride of the R stage
+  __shared__ __attribute__((aligned(16))) float Fs[FT_ROWS * FS];
+  __shared__ __attribute__((aligned(16))) float Rs[FT_ROWS * RS];
+  const int g = blockIdx.x;
   const int ii = ch_inst[g];
   if (iact && !iact[ii]) return;
   const BInst I = inst[ii];
-  const int l0 = blockIdx.x * 64;
-  if (l0 >= I.rank) return;
   const int64_t lo = (int64_t)(g - I.ch0) * FTC;
   const int64_t hi = lo + FTC < I.n ? lo + FTC : I.n;
-  const int tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
-  double acc[4][4] = {};
-  for (int64_t rb = lo; rb < hi; rb += 16) {
-    __syncthreads();
-    for (int e = tid; e < 16 * 64; e += 256) {
-      const int rr = e / 64, cc = e % 64;
-      const int64_t lr = rb + rr, row = I.row0 + lr;
-      Fs[rr][cc] = (lr < hi && l0 + cc < I.rank) ? (double)F[row * ldf + l0 + cc] : 0.0;
-      Rs[rr][cc] = (lr < hi && cc < s) ? (double)R[row * s + cc] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int rr = 0; rr < 16; ++rr) {
-      double a[4], b[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int ct = (s + 15) / 16;
+  const int pw = ct <= 1 ? FT_PW : (ct == 2 ? FT_PW / 2 : FT_PW / 4);  // columns per pass
+  double* out = part + (int64_t)g * lmax * s;
+  for (int lbase = 0; lbase < I.rank; lbase += pw) {
+    const int lw = I.rank - lbase < pw ? I.rank - lbase : pw;  // columns this pass
+    const int lw4 = (lw + 3) / 4;
+    const int tiles = ((lw + 15) / 16) * ct;  // <= 16
+    f64x4 acc[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[q] = Fs[rr][ti + 16 * q];
-        b[q] = Rs[rr][tj + 16 * q];
+    for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // register prefetch of one stage: F as float4 (<= 8 per thread), R as
+    // floats (the stage's 32 rows of R are contiguous: <= 8 per thread)
+    float4 pf[8];
+    float pr[8];
+    auto fetch = [&](int64_t row0) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = tid + 256 * j;  // float4 index within the stage
+        const int rr = e / lw4, c4 = e % lw4;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (rr < FT_ROWS && row0 + rr < hi) {
+          const float* src = F + (I.row0 + row0 + rr) * (int64_t)ldf + lbase + 4 * c4;
+          v = *(const float4*)src;
+        }
+        pf[j] = v;
       }
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int j = 0; j < 8; ++j) {
+        const int e = tid + 256 * j;
+        const int rr = e / s;
+        pr[j] = (rr < FT_ROWS && row0 + rr < hi) ? R[(I.row0 + row0) * (int64_t)s + e] : 0.f;
+      }
+    };
+    fetch(lo);
+    for (int64_t row0 = lo; row0 < hi; row0 += FT_ROWS) {
+      __syncthreads();  // the previous stage has been consumed
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+      for (int j = 0; j < 8; ++j) {
+        const int e = tid + 256 * j;
+        const int rr = e / lw4, c4 = e % lw4;
+        if (rr < FT_ROWS) {
+          // columns past the rank (padding of the F rows) are stored as zero
+          const int l0 = 4 * c4;
+          float4 v = pf[j];
+          if (l0 + 1 >= lw) v.y = 0.f;
+          if (l0 + 2 >= lw) v.z = 0.f;
+          if (l0 + 3 >= lw) v.w = 0.f;
+          *(float4*)&Fs[rr * FS + l0] = v;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = tid + 256 * j;
+        const int rr = e / s;
+        if (rr < FT_ROWS) Rs[rr * RS + e % s] = pr[j];
+      }
+      __syncthreads();
+      if (row0 + FT_ROWS < hi) fetch(row0 + FT_ROWS);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int p = wave + 4 * q;
+        if (p < tiles) {
+          const int lt = p / ct, cs = p % ct;
+#pragma unroll
+          for (int t = 0; t < FT_ROWS / 4; ++t) {
+            const int k = 4 * t + lg;
+            const double a = (double)Fs[k * FS + lt * 16 + li];
+            const double b = (double)Rs[k * RS + cs * 16 + li];
+            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+          }
+        }
+      }
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int p = wave + 4 * q;
+      if (p < tiles) {
+        const int lt = p / ct, cs = p % ct;
+        const int c = cs * 16 + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int l = lbase + lt * 16 + lg + 4 * r;
+          if (l < I.rank && l - lbase < lw && c < s) out[(int64_t)l * s + c] = acc[q][r];
+        }
+      }
+    }
+    __syncthreads();
   }
-  double* out = part + (int64_t)g * lmax * s;
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int l = l0 + ti + 16 * x, c = tj + 16 * y;
-      if (l < I.rank && c < s) out[(int64_t)l * s + c] = acc[x][y];
-    }
 }
 
 // t_i = sum of the instance's chunk partials (rank_i x s at i * lmax * s)
@@ -550,7 +730,9 @@ __global__ __launch_bounds__(256) void k_bft_sum(const BInst* __restrict__ inst,
   }
 }
 
-// OUT = Dinv R - F t on one 64-row block; dots dot1 = R .* OUT, dot2 = Z .* R
+// OUT = Dinv R - F t on one 64-row block (wave w: rows 16 w .. 16 w + 15) on
+// FP64 matrix cores, k = the rank index (lane group g supplies k = 4 step + g);
+// dots dot1 = R .* OUT and dot2 = Z .* R per column (s <= 64).
 __global__ __launch_bounds__(256) void k_bwout(const BInst* __restrict__ inst,
                                                const int* __restrict__ blk_inst,
                                                const float* __restrict__ F, int ldf,
@@ -560,79 +742,72 @@ __global__ __launch_bounds__(256) void k_bwout(const BInst* __restrict__ inst,
                                                float* __restrict__ OUT, const float* __restrict__ Z,
                                                double* __restrict__ dot1, double* __restrict__ dot2,
                                                const int* __restrict__ iact) {
-  __shared__ double Fs[64][17];
-  __shared__ double Ts[16][65];
-  __shared__ double red1[16][65];
-  __shared__ double red2[16][65];
+  __shared__ double red1[4][64][4];
+  __shared__ double red2[4][64][4];
   const int ii = blk_inst[blockIdx.x];
   if (iact && !iact[ii]) return;
   const BInst I = inst[ii];
-  const int tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
   const int64_t b0 = (int64_t)blockIdx.x * 64;
   const int64_t nrow = I.row0 + I.n;  // rows at or past nrow are padding
   const double* tin = t + (int64_t)ii * lmax * s;
-  double acc[4][4] = {};
-  for (int l0 = 0; l0 < I.rank; l0 += 16) {
-    __syncthreads();
-    for (int e = tid; e < 64 * 16; e += 256) {
-      const int rr = e / 16, ll = e % 16;
-      Fs[rr][ll] = (l0 + ll < I.rank && b0 + rr < nrow) ? (double)F[(b0 + rr) * ldf + l0 + ll] : 0.0;
-    }
-    for (int e = tid; e < 16 * 64; e += 256) {
-      const int ll = e / 64, cc = e % 64;
-      Ts[ll][cc] = (l0 + ll < I.rank && cc < s) ? tin[(int64_t)(l0 + ll) * s + cc] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int ll = 0; ll < 16; ++ll) {
-      double a[4], b[4];
+  const int ct = (s + 15) / 16;
+  const int64_t arow = b0 + 16 * wave + li;  // the row this lane feeds as A operand
+  const bool av_ok = arow < nrow;
+  f64x4 acc[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[q] = Fs[ti + 16 * q][ll];
-        b[q] = Ts[ll][tj + 16 * q];
+  for (int c = 0; c < 4; ++c) acc[c] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < I.rank; k0 += 4) {
+    const int k = k0 + lg;
+    const bool kv = k < I.rank;
+    const double a = (kv && av_ok) ? (double)F[arow * ldf + k] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (c < ct) {
+        const int cc = c * 16 + li;
+        const double b = (kv && cc < s) ? tin[(int64_t)k * s + cc] : 0.0;
+        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
       }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
     }
   }
-  double d1[4] = {}, d2[4] = {};
+  double d1[4] = {0.0, 0.0, 0.0, 0.0}, d2[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    const int64_t row = b0 + ti + 16 * x;
-    const bool pad = row >= nrow;
-    const double dv = pad ? 0.0 : (double)Dinv[row];
+  for (int c = 0; c < 4; ++c) {
+    if (c >= ct) continue;
+    const int cc = c * 16 + li;
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int c = tj + 16 * y;
-      if (c >= s) continue;
-      const int64_t off = row * s + c;
-      if (pad) {
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = b0 + 16 * wave + lg + 4 * r;
+      if (cc >= s) continue;
+      const int64_t off = row * s + cc;
+      if (row >= nrow) {
         OUT[off] = 0.f;
         continue;
       }
       const double rv = (double)R[off];
-      const float o = (float)(dv * rv - acc[x][y]);
+      const float o = (float)((double)Dinv[row] * rv - acc[c][r]);
       OUT[off] = o;
-      d1[y] += rv * (double)o;
-      d2[y] += (double)Z[off] * rv;
+      d1[c] += rv * (double)o;
+      d2[c] += (double)Z[off] * rv;
     }
   }
 #pragma unroll
-  for (int y = 0; y < 4; ++y) {
-    red1[ti][tj + 16 * y] = d1[y];
-    red2[ti][tj + 16 * y] = d2[y];
+  for (int c = 0; c < 4; ++c) {
+    red1[wave][lane][c] = d1[c];
+    red2[wave][lane][c] = d2[c];
   }
   __syncthreads();
-  if (tid < s) {
+  if (threadIdx.x < s) {
+    const int c = threadIdx.x / 16, l16 = threadIdx.x % 16;
     double a = 0.0, b = 0.0;
-    for (int q = 0; q < 16; ++q) {
-      a += red1[q][tid];
-      b += red2[q][tid];
-    }
-    dot1[blockIdx.x * (int64_t)s + tid] = a;
-    dot2[blockIdx.x * (int64_t)s + tid] = b;
+    for (int w = 0; w < 4; ++w)
+      for (int g = 0; g < 4; ++g) {
+        a += red1[w][l16 + 16 * g][c];
+        b += red2[w][l16 + 16 * g][c];
+      }
+    dot1[blockIdx.x * (int64_t)s + threadIdx.x] = a;
+    dot2[blockIdx.x * (int64_t)s + threadIdx.x] = b;
   }
 }
 
@@ -777,21 +952,36 @@ std::vector<BItem> make_items(const Batch& b, int bmw, int ncols, int nt) {
 struct ProductPlan {
   BItem* d_items = nullptr;
   int count = 0;
-  int variant = 0;  // 0: 4 waves x 128 rows; 1: 2 waves x 64 rows
-  int nb = 1;
+  int waves = 4;  // 4 waves x 128 rows or 2 waves x 64 rows per workgroup
+  int mf = 32;    // matrix-core shape (32: 32x32x2, 16: 16x16x4)
+  int nb = 1;     // column sub-blocks: NT = mf * nb columns per workgroup
 };
 
+// Tile shape for ncols columns: the narrowest block that covers them (at most
+// 224 columns; wider blocks repeat).  variant 1 (2 waves) exists for blocks of
+// at most 64 columns.
 ld_status plan_product(ld_ctx* ctx, const Batch& b, int ncols, int variant, ProductPlan* pp) {
-  const int nb = ncols > 32 ? 2 : 1;
-  const int bmw = variant == 0 ? 128 : 64;
-  std::vector<BItem> items = make_items(b, bmw, ncols, 32 * nb);
+  int mf = 32, nb = 7;
+  if (ncols <= 16) {
+    mf = 16;
+    nb = 1;
+  } else if (ncols <= 32) {
+    nb = 1;
+  } else if (ncols <= 64) {
+    nb = 2;
+  } else if (ncols <= 128) {
+    nb = 4;
+  }
+  const int waves = (variant == 1 && mf * nb <= 64) ? 2 : 4;
+  std::vector<BItem> items = make_items(b, 32 * waves, ncols, mf * nb);
   pp->d_items = (BItem*)ctx->arena.take(items.size() * sizeof(BItem));
   if (!pp->d_items) return fail(LD_ENOMEM, "batch: scratch arena too small for work items");
   LD_HIP(hipMemcpyAsync(pp->d_items, items.data(), items.size() * sizeof(BItem),
                         hipMemcpyHostToDevice, ctx->stream));
   LD_HIP(hipStreamSynchronize(ctx->stream));  // `items` is released on return
   pp->count = (int)items.size();
-  pp->variant = variant;
+  pp->waves = waves;
+  pp->mf = mf;
   pp->nb = nb;
   return LD_OK;
 }
@@ -799,21 +989,22 @@ ld_status plan_product(ld_ctx* ctx, const Batch& b, int ncols, int variant, Prod
 void launch_product(hipStream_t st, const Batch& b, const ProductPlan& pp, const float* V, int ld,
                     float* Y, const float* X2, float alpha2, double* dots, const int* iact) {
   const dim3 g(pp.count);
-  if (pp.variant == 0) {
-    if (pp.nb == 2)
-      hipLaunchKernelGGL((k_bmm<2, 4>), g, dim3(256), 0, st, b.d_inst, pp.d_items, b.X32, V, ld, Y,
-                         X2, alpha2, dots, iact);
-    else
-      hipLaunchKernelGGL((k_bmm<1, 4>), g, dim3(256), 0, st, b.d_inst, pp.d_items, b.X32, V, ld, Y,
-                         X2, alpha2, dots, iact);
+#define LD_BMM_LAUNCH(MF, NB, W)                                                               \
+  hipLaunchKernelGGL((k_bmm<MF, NB, W>), g, dim3(64 * W), 0, st, b.d_inst, pp.d_items, b.X32, V, \
+                     ld, Y, X2, alpha2, dots, iact)
+  const bool w4 = pp.waves == 4;
+  if (pp.mf == 16) {
+    if (w4) LD_BMM_LAUNCH(16, 1, 4); else LD_BMM_LAUNCH(16, 1, 2);
+  } else if (pp.nb == 1) {
+    if (w4) LD_BMM_LAUNCH(32, 1, 4); else LD_BMM_LAUNCH(32, 1, 2);
+  } else if (pp.nb == 2) {
+    if (w4) LD_BMM_LAUNCH(32, 2, 4); else LD_BMM_LAUNCH(32, 2, 2);
+  } else if (pp.nb == 4) {
+    LD_BMM_LAUNCH(32, 4, 4);
   } else {
-    if (pp.nb == 2)
-      hipLaunchKernelGGL((k_bmm<2, 2>), g, dim3(128), 0, st, b.d_inst, pp.d_items, b.X32, V, ld, Y,
-                         X2, alpha2, dots, iact);
-    else
-      hipLaunchKernelGGL((k_bmm<1, 2>), g, dim3(128), 0, st, b.d_inst, pp.d_items, b.X32, V, ld, Y,
-                         X2, alpha2, dots, iact);
+    LD_BMM_LAUNCH(32, 7, 4);
   }
+#undef LD_BMM_LAUNCH
 }
 
 }  // namespace
@@ -922,6 +1113,7 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
     me_max = std::max(me_max, I.m + (I.m & 1));
   }
   b.R = row0;
+  b.lmax = (b.lmax + 15) / 16 * 16;  // 16-byte aligned rows of U and F
   b.nblk = b.R / BLK;
   b.gstride = (int64_t)b.mmax * b.mmax;
   std::vector<int> blk_inst(b.nblk), ch_inst(nchunks);
@@ -1143,8 +1335,8 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
   hipLaunchKernelGGL(k_bprobes, dim3(grid1(R * s)), dim3(256), 0, st, b.d_inst, b.d_blk_inst, R, s, Z);
   const int64_t vec = R * s;
   auto woodbury = [&](const float* rin, float* uout, const int* act) {
-    hipLaunchKernelGGL(k_bft, dim3(ltiles, nchunks), dim3(256), 0, st, b.d_inst, d_ch_inst, f.F32,
-                       b.lmax, rin, s, b.lmax, tpart, act);
+    hipLaunchKernelGGL(k_bft, dim3(nchunks), dim3(256), 0, st, b.d_inst, d_ch_inst, f.F32, b.lmax,
+                       rin, s, b.lmax, tpart, act);
     hipLaunchKernelGGL(k_bft_sum, dim3(B), dim3(256), 0, st, b.d_inst, s, b.lmax, tpart, tl, act);
     hipLaunchKernelGGL(k_bwout, dim3((unsigned)b.nblk), dim3(256), 0, st, b.d_inst, b.d_blk_inst,
                        f.F32, b.lmax, f.Dinv32, tl, b.lmax, rin, s, uout, Z, d1, d2, act);

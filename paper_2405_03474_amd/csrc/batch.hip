@@ -10,8 +10,9 @@
 //    partial sums leave the workgroup; two tile shapes (4 or 2 waves) are
 //    timed once and the faster one is kept (autotuner);
 //  - preconditioner: batched range finder, CholeskyQR, Rayleigh-Ritz with
-//    one-workgroup-per-instance Cholesky, triangular inverse and Jacobi
-//    eigen-solver (dense_dev.hpp), Woodbury factors per instance;
+//    one-workgroup-per-instance Cholesky and triangular inverse
+//    (dense_dev.hpp) and a Householder + implicit QL eigen-solver, Woodbury
+//    factors per instance;
 //  - solver: multi-shift CG with per-(instance, probe) scalars; the
 //    iterations can be captured in a HIP graph and replayed in chunks.
 #include <algorithm>
@@ -457,85 +458,224 @@ __global__ __launch_bounds__(256) void k_bgemm(const BInst* __restrict__ inst, i
                    rs ? rs + I.row0 : nullptr, I.n, K, N, C + I.row0 * ldc, ldc, i0, j0);
 }
 
-// Whole Jacobi eigen-solve of G_i (m_i x m_i) by one workgroup per instance:
-// rounds of the parallel cyclic ordering separated by barriers, sweeps until
-// the off-diagonal mass converges (at most 40); then eigenpairs sorted by
-// descending eigenvalue into evals (stride emax) and evecs_i (m_i x m_i).
-__global__ __launch_bounds__(1024) void k_bjacobi(const BInst* __restrict__ inst,
-                                                  const double* __restrict__ G, int64_t gstride,
-                                                  double* __restrict__ work, int64_t wstride,
-                                                  double* __restrict__ evals, int emax,
-                                                  double* __restrict__ evecs,
-                                                  int* __restrict__ status) {
-  __shared__ double so[1024], sd[1024];
+// Symmetric eigen-decomposition of G_i (m_i x m_i, symmetrised) by one
+// workgroup of 1024 threads: Householder reduction to tridiagonal form
+// T = H^T G H, implicit QL iterations with Wilkinson-type shifts on T whose
+// plane rotations are accumulated into Z (Z = I initially), and the
+// back-transformation X = H Z; eigenpairs sorted by descending eigenvalue
+// into evals (stride emax) and evecs_i (m_i x m_i, column j = eigenvector of
+// evals[j]).  One thread runs the scalar QL recurrence; the other threads
+// apply each sweep's rotations to the rows of Z.  Work area per instance:
+// 2 m^2 doubles (the reduced matrix holding the reflectors, then Z).
+// status[i] = 1 when an eigenvalue needs more than 60 QL iterations.
+// Requires m_i <= 1024.
+__global__ __launch_bounds__(1024) void k_beigh(const BInst* __restrict__ inst,
+                                                const double* __restrict__ G, int64_t gstride,
+                                                double* __restrict__ work, int64_t wstride,
+                                                double* __restrict__ evals, int emax,
+                                                double* __restrict__ evecs,
+                                                int* __restrict__ status) {
+  __shared__ double sd[1024], se[1024];  // diagonal, off-diagonal of T
+  __shared__ double su[1024], sp[1024];  // reflector, matrix-vector product
+  __shared__ double red[1024];
+  __shared__ double rc[1024], rs[1024];  // rotations (i, i+1) of one QL sweep
+  __shared__ double sh_v[3];
+  __shared__ int sh_flag, sh_lo, sh_hi, sh_fail;
   const BInst I = inst[blockIdx.x];
-  const int m = I.m, me = m + (m & 1);
+  const int m = I.m;
   const int tid = threadIdx.x;
   const double* Gi = G + blockIdx.x * gstride;
-  double* A0 = work + blockIdx.x * wstride;
-  double* A1 = A0 + (int64_t)me * me;
-  double* V0 = A1 + (int64_t)me * me;
-  double* V1 = V0 + (int64_t)me * me;
-  for (int64_t e = tid; e < (int64_t)me * me; e += 1024) {
-    const int i = (int)(e / me), j = (int)(e % me);
-    A0[e] = (i < m && j < m) ? 0.5 * (Gi[(int64_t)i * m + j] + Gi[(int64_t)j * m + i]) : 0.0;
-    V0[e] = i == j ? 1.0 : 0.0;
+  double* A = work + blockIdx.x * wstride;
+  double* Z = A + (int64_t)m * m;
+  for (int64_t e = tid; e < (int64_t)m * m; e += 1024) {
+    const int i = (int)(e / m), j = (int)(e % m);
+    A[e] = 0.5 * (Gi[(int64_t)i * m + j] + Gi[(int64_t)j * m + i]);
+    Z[e] = i == j ? 1.0 : 0.0;
   }
+  if (tid == 0) sh_fail = 0;
   __syncthreads();
-  const int h = me / 2;
-  const int64_t items = (int64_t)h * h + (int64_t)me * h;
-  double* cur = A0;
-  double* nxt = A1;
-  double* vcur = V0;
-  double* vnxt = V1;
-  bool done = me < 2;
-  double off_prev = -1.0;
-  for (int sweep = 0; sweep < 40 && !done; ++sweep) {
-    for (int r = 0; r < me - 1; ++r) {
-      for (int64_t e = tid; e < items; e += 1024) dev::jacobi_item(cur, nxt, vcur, vnxt, me, r, e);
-      __syncthreads();
-      double* t = cur;
-      cur = nxt;
-      nxt = t;
-      t = vcur;
-      vcur = vnxt;
-      vnxt = t;
-    }
-    double o = 0.0, dg = 0.0;
-    for (int64_t e = tid; e < (int64_t)me * me; e += 1024) {
-      const double v = cur[e];
-      if (e / me == e % me)
-        dg += v * v;
-      else
-        o += v * v;
-    }
-    so[tid] = o;
-    sd[tid] = dg;
+
+  auto block_sum = [&](double v) {  // all threads must call; returns the sum to all
+    red[tid] = v;
     __syncthreads();
     for (int w = 512; w > 0; w >>= 1) {
-      if (tid < w) {
-        so[tid] += so[tid + w];
-        sd[tid] += sd[tid + w];
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+  };
+
+  // ---- 1. Householder tridiagonalization (H_k = I - u u^T, |u|^2 = 2)
+  for (int k = 0; k + 2 < m; ++k) {
+    const int n2 = m - k - 1;  // trailing rows / columns k+1 .. m-1
+    double t = 0.0;
+    for (int i = k + 2 + tid; i < m; i += 1024) {
+      const double x = A[(int64_t)i * m + k];
+      t += x * x;
+    }
+    const double sigma = block_sum(t);
+    if (tid == 0) {
+      const double x0 = A[(int64_t)(k + 1) * m + k];
+      sd[k] = A[(int64_t)k * m + k];
+      if (sigma == 0.0) {
+        se[k] = x0;
+        sh_flag = 0;
+      } else {
+        const double alpha = -copysign(sqrt(x0 * x0 + sigma), x0);
+        const double v0 = x0 - alpha;
+        se[k] = alpha;
+        sh_v[0] = sqrt(2.0 / (v0 * v0 + sigma));  // scale of v to u
+        sh_v[1] = v0;
+        sh_flag = 1;
+      }
+    }
+    __syncthreads();
+    if (!sh_flag) {
+      for (int j = tid; j < n2; j += 1024) A[(int64_t)(k + 1 + j) * m + k] = 0.0;  // H_k = I
+      __syncthreads();
+      continue;
+    }
+    const double sc = sh_v[0];
+    for (int j = tid; j < n2; j += 1024) {
+      const double v = j == 0 ? sh_v[1] : A[(int64_t)(k + 1 + j) * m + k];
+      su[j] = v * sc;
+      A[(int64_t)(k + 1 + j) * m + k] = v * sc;  // kept for the back-transformation
+    }
+    __syncthreads();
+    // p = A22 u (A22 symmetric: thread (grp, j) sums rows grp, grp + ng, ...)
+    const int ng = 1024 / n2;
+    {
+      const int j = tid % n2, grp = tid / n2;
+      double acc = 0.0;
+      if (grp < ng) {
+        const double* col = A + (int64_t)(k + 1) * m + (k + 1 + j);
+#pragma unroll 4
+        for (int i = grp; i < n2; i += ng) acc = fma(col[(int64_t)i * m], su[i], acc);
+      }
+      red[tid] = acc;
+    }
+    __syncthreads();
+    double pj = 0.0;
+    if (tid < n2) {
+      for (int g = 0; g < ng; ++g) pj += red[g * n2 + tid];
+    }
+    __syncthreads();
+    const double K = block_sum(tid < n2 ? pj * su[tid] : 0.0);
+    if (tid < n2) sp[tid] = pj - 0.5 * K * su[tid];  // w
+    __syncthreads();
+    for (int64_t e = tid; e < (int64_t)n2 * n2; e += 1024) {
+      const int i = (int)(e / n2), j = (int)(e % n2);
+      A[(int64_t)(k + 1 + i) * m + (k + 1 + j)] -= su[i] * sp[j] + sp[i] * su[j];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (m >= 2) {
+      sd[m - 2] = A[(int64_t)(m - 2) * m + (m - 2)];
+      se[m - 2] = A[(int64_t)(m - 1) * m + (m - 2)];
+    }
+    sd[m - 1] = A[(int64_t)(m - 1) * m + (m - 1)];
+    se[m - 1] = 0.0;
+  }
+  __syncthreads();
+
+  // ---- 2. implicit QL on (sd, se); se[i] couples sd[i] and sd[i+1]
+  for (int l = 0; l < m; ++l) {
+    int iter = 0;
+    while (true) {
+      if (tid == 0) {
+        int mm = l;
+        for (; mm < m - 1; ++mm) {
+          const double dd = fabs(sd[mm]) + fabs(sd[mm + 1]);
+          if (fabs(se[mm]) <= 0x1.0p-52 * dd) break;
+        }
+        if (mm == l || iter >= 60) {
+          if (mm != l) sh_fail = 1;
+          sh_flag = 0;
+        } else {
+          ++iter;
+          double g = (sd[l + 1] - sd[l]) / (2.0 * se[l]);
+          double r = hypot(g, 1.0);
+          g = sd[mm] - sd[l] + se[l] / (g + copysign(r, g));
+          double s = 1.0, c = 1.0, p = 0.0;
+          int i = mm - 1;
+          bool under = false;
+          for (; i >= l; --i) {
+            const double f = s * se[i], b = c * se[i];
+            r = hypot(f, g);
+            se[i + 1] = r;
+            if (r == 0.0) {
+              sd[i + 1] -= p;
+              se[mm] = 0.0;
+              under = true;
+              break;
+            }
+            s = f / r;
+            c = g / r;
+            g = sd[i + 1] - p;
+            r = (sd[i] - g) * s + 2.0 * c * b;
+            p = s * r;
+            sd[i + 1] = g + p;
+            g = c * r - b;
+            rc[i] = c;
+            rs[i] = s;
+          }
+          sh_hi = mm - 1;
+          sh_lo = under ? i + 1 : l;
+          if (!under) {
+            sd[l] -= p;
+            se[l] = g;
+            se[mm] = 0.0;
+          }
+          sh_flag = 1;
+        }
+      }
+      __syncthreads();
+      if (!sh_flag) break;
+      if (tid < m) {
+        double* zr = Z + (int64_t)tid * m;
+        for (int i = sh_hi; i >= sh_lo; --i) {
+          const double c = rc[i], s = rs[i];
+          const double f = zr[i + 1], zi = zr[i];
+          zr[i + 1] = s * zi + c * f;
+          zr[i] = c * zi - s * f;
+        }
       }
       __syncthreads();
     }
-    const double off = so[0], dgs = sd[0];
-    done = !isfinite(off) || dev::jacobi_done(off, dgs, off_prev);
-    off_prev = off;
     __syncthreads();
   }
-  if (tid == 0 && (!done || !isfinite(off_prev))) status[blockIdx.x] = 1;
+
+  // ---- 3. back-transformation Z <- H_0 H_1 ... H_{m-3} Z (thread per column)
+  for (int k = m - 3; k >= 0; --k) {
+    const int n2 = m - k - 1;
+    for (int j = tid; j < n2; j += 1024) su[j] = A[(int64_t)(k + 1 + j) * m + k];
+    __syncthreads();
+    if (tid < m) {
+      double y = 0.0;
+#pragma unroll 4
+      for (int i = 0; i < n2; ++i) y = fma(su[i], Z[(int64_t)(k + 1 + i) * m + tid], y);
+#pragma unroll 4
+      for (int i = 0; i < n2; ++i) Z[(int64_t)(k + 1 + i) * m + tid] -= su[i] * y;
+    }
+    __syncthreads();
+  }
+
+  // ---- sorted output
+  if (tid == 0 && sh_fail) status[blockIdx.x] = 1;
   double* ev = evals + (int64_t)blockIdx.x * emax;
   double* vec = evecs + blockIdx.x * gstride;
   for (int i = tid; i < m; i += 1024) {
-    const double li = cur[(int64_t)i * me + i];
+    const double li = sd[i];
     int pos = 0;
     for (int j = 0; j < m; ++j) {
-      const double lj = cur[(int64_t)j * me + j];
+      const double lj = sd[j];
       if (lj > li || (lj == li && j < i)) ++pos;
     }
     ev[pos] = li;
-    for (int r = 0; r < m; ++r) vec[(int64_t)r * m + pos] = vcur[(int64_t)r * me + i];
+    for (int r = 0; r < m; ++r) vec[(int64_t)r * m + pos] = Z[(int64_t)r * m + i];
   }
 }
 
@@ -1085,7 +1225,7 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
   b.B = count;
   b.s = s;
   int64_t row0 = 0;
-  int me_max = 0, nchunks = 0;
+  int nchunks = 0;
   for (int i = 0; i < count; ++i) {
     const ld_instance& x = in[i];
     BInst I{};
@@ -1110,7 +1250,6 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
     row0 += (x.n + BROWS - 1) / BROWS * BROWS;
     b.mmax = std::max(b.mmax, I.m);
     b.lmax = std::max(b.lmax, I.rank);
-    me_max = std::max(me_max, I.m + (I.m & 1));
   }
   b.R = row0;
   b.lmax = (b.lmax + 15) / 16 * 16;  // 16-byte aligned rows of U and F
@@ -1139,7 +1278,7 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
   add(R * b.mmax * 4);
   for (int q = 0; q < 3; ++q) add(B * b.gstride * 8);
   add(B * b.mmax * 8);
-  add(B * 4 * (int64_t)me_max * me_max * 8);
+  add(B * 2 * (int64_t)b.mmax * b.mmax * 8);
   add(B * 4);
   add(B * 4);
   add(R * b.lmax * 8);
@@ -1178,7 +1317,7 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
   f.Rinv = (double*)tk(B * b.gstride * 8);
   f.evecs = (double*)tk(B * b.gstride * 8);
   f.evals = (double*)tk(B * b.mmax * 8);
-  f.jwork = (double*)tk(B * 4 * (int64_t)me_max * me_max * 8);
+  f.jwork = (double*)tk(B * 2 * (int64_t)b.mmax * b.mmax * 8);
   f.fail = (int*)tk(B * 4);
   f.jstat = (int*)tk(B * 4);
   f.U = (double*)tk(R * b.lmax * 8);
@@ -1253,8 +1392,8 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
   const int tiles = (b.mmax + 63) / 64;
   hipLaunchKernelGGL(k_bgram, dim3(tiles, tiles, B), dim3(256), 0, st, b.d_inst, 0, Qb, b.mmax, MQ,
                      b.mmax, (const double*)nullptr, f.G, b.gstride);
-  hipLaunchKernelGGL(k_bjacobi, dim3(B), dim3(1024), 0, st, b.d_inst, f.G, b.gstride, f.jwork,
-                     4 * (int64_t)me_max * me_max, f.evals, b.mmax, f.evecs, f.jstat);
+  hipLaunchKernelGGL(k_beigh, dim3(B), dim3(1024), 0, st, b.d_inst, f.G, b.gstride, f.jwork,
+                     2 * (int64_t)b.mmax * b.mmax, f.evals, b.mmax, f.evecs, f.jstat);
   LD_HIP(hipGetLastError());
   {
     std::vector<int> h;
@@ -1263,7 +1402,8 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
       if (h[i]) return fail(LD_ENOTSPD, "batch: CholeskyQR breakdown in instance " + std::to_string(i));
     LD_TRY(read_ints(ctx, st, f.jstat, count, h));
     for (int i = 0; i < count; ++i)
-      if (h[i]) return fail(LD_ENOCONV, "batch: Jacobi did not converge in instance " + std::to_string(i));
+      if (h[i])
+        return fail(LD_ENOCONV, "batch: eigen-solver did not converge in instance " + std::to_string(i));
     LD_TRY(ensure_pinned(ctx, (size_t)B * b.mmax + 8));
     LD_HIP(hipMemcpyAsync(ctx->pinned, f.evals, B * b.mmax * 8, hipMemcpyDeviceToHost, st));
     LD_HIP(hipStreamSynchronize(st));

@@ -228,6 +228,9 @@ typedef struct {
                               joined to the context stream) */
 #define LD_BATCH_RETUNE 2  /* re-time the product tile shapes even if this
                               context already chose one */
+#define LD_BATCH_PRECOND_ONLY 4  /* build the preconditioners only: results carry
+                                    logdet_P (logdet = logdet_P, trace_term = 0,
+                                    iterations = 0) and lambda_out is filled */
 
 /* The estimator of logdet_estimate applied to `count` independent problems
  * of uneven size in one pass (the same method per instance, Section 2 and
@@ -251,12 +254,82 @@ typedef struct {
  *   results     host array of count ld_result (filled on LD_OK / LD_ENOCONV;
  *               seconds_solve and iterations are those of the whole batch)
  *   per_probe   host array of count * num_probes doubles (instance-major), or NULL
+ *   lambda_out  host array of count * lambda_stride doubles receiving each
+ *               instance's kept eigenvalues (rank_i values, descending, rest
+ *               of the row zero), or NULL; lambda_stride >= max rank_i
  * The product kernel's tile shape (4 or 2 waves per workgroup) is timed on
  * the first call and kept in the context.  Synchronizes. */
 ld_status logdet_estimate_batched(ld_ctx* ctx, int32_t count, const ld_instance* instances,
                                   int32_t k, int32_t num_probes, int32_t oversample,
                                   int32_t power_iters, double tol, int32_t max_iters,
-                                  int32_t flags, ld_result* results, double* per_probe);
+                                  int32_t flags, ld_result* results, double* per_probe,
+                                  double* lambda_out, int32_t lambda_stride);
+
+/* ---- learned surrogate of the trace term ----
+ * An ensemble of MLPs (38 -> 256 -> 256 -> 256 -> 1, GELU after the first
+ * three layers) predicting tr log(M P^-1) / n from 38 features, so that a
+ * hyperparameter sweep can skip the shifted solves where the members agree;
+ * the estimator itself (logdet_estimate / logdet_estimate_batched) produces
+ * the training targets and remains the fallback and the judge of the error.
+ * Features (ld_surrogate_features): kernel kind, log lengthscale, log variance,
+ * log noise, log n, d, and the normalised histogram of log(lambda_j / n) over
+ * the preconditioner's kept eigenvalues lambda_j in LD_SUR_BINS equal bins
+ * between fixed edges (values outside fall in the end bins).
+ * Training: FP32 forward/backward, MSE on the standardised target, Adam
+ * (beta 0.9 / 0.999, eps 1e-8); every member steps on the same minibatch.
+ * Inference: BF16 weights and activations on BF16 matrix cores, FP32
+ * accumulation; returns the ensemble mean and standard deviation of the
+ * de-standardised target.  Initial weights U(-1/sqrt(fan_in), 1/sqrt(fan_in))
+ * from counter stream 3 of seed + member; biases 0. */
+#define LD_SUR_FEATURES 38
+#define LD_SUR_WIDTH 256
+#define LD_SUR_BINS 32
+typedef struct ld_surrogate ld_surrogate;
+
+/* Parameters per member: W1 (38 x 256), b1, W2 (256 x 256), b2, W3, b3,
+ * w4 (256), b4, packed in this order with every tensor starting at a multiple
+ * of 64 floats; the count includes that padding.  Host only. */
+int64_t ld_surrogate_param_count(void);
+
+/* Host-side feature vector (out: 38 floats) of one problem. lambda: rank kept
+ * eigenvalues (> 0); edges: LD_SUR_BINS + 1 increasing values. */
+ld_status ld_surrogate_features(const double* lambda, int32_t rank, int32_t kind, double lengthscale,
+                                double variance, double noise, int64_t n, int32_t d,
+                                const double* edges, float* out);
+
+/* members 1..64.  The surrogate lives on the context's device; free it with
+ * ld_surrogate_free.  Synchronizes. */
+ld_status ld_surrogate_create(ld_ctx* ctx, int32_t members, uint64_t seed, ld_surrogate** out);
+void ld_surrogate_free(ld_surrogate* S);
+
+/* Standardisation: features (x - x_mean) / x_std (host arrays of 38), target
+ * (y - y_mean) / y_std.  Defaults: 0, 1, 0, 1.  Synchronizes. */
+ld_status ld_surrogate_set_scaling(ld_ctx* ctx, ld_surrogate* S, const float* x_mean,
+                                   const float* x_std, double y_mean, double y_std);
+
+/* One Adam step of every member on the minibatch X (device, B x 38 raw
+ * features) and y (device, B raw targets); loss (host, members doubles, the
+ * MSE on the standardised target before the step) may be NULL (then the call
+ * is asynchronous). */
+ld_status ld_surrogate_train_step(ld_ctx* ctx, ld_surrogate* S, const float* X, const float* y,
+                                  int32_t B, float lr, double* loss);
+
+/* Gradient of member's loss on (X, y) without an update: grad (device,
+ * ld_surrogate_param_count() floats, packed like the parameters) and the loss
+ * (host, may be NULL).  Synchronizes. */
+ld_status ld_surrogate_gradient(ld_ctx* ctx, ld_surrogate* S, int32_t member, const float* X,
+                                const float* y, int32_t B, float* grad, double* loss);
+
+/* Copy member's FP32 parameters to out and/or replace them from in (device
+ * arrays of ld_surrogate_param_count() floats; either may be NULL). Asynchronous. */
+ld_status ld_surrogate_params(ld_ctx* ctx, ld_surrogate* S, int32_t member, float* out,
+                              const float* in);
+
+/* BF16 ensemble inference on X (device, N x 38 raw features): mean and stddev
+ * (device, N floats each) of the de-standardised target over the members.
+ * Asynchronous. */
+ld_status ld_surrogate_predict(ld_ctx* ctx, ld_surrogate* S, const float* X, int64_t N, float* mean,
+                               float* stddev);
 
 #ifdef __cplusplus
 }

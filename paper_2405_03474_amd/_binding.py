@@ -20,7 +20,8 @@ LD_OK, LD_EINVAL, LD_ENOTSPD, LD_ENOCONV, LD_EHIP, LD_ENOMEM = 0, -1, -2, -3, -4
 LD_RBF, LD_MATERN52 = 0, 1
 LD_F64, LD_F32, LD_BF16 = 0, 1, 2
 LD_ROW_MAJOR, LD_TILED = 0, 1
-LD_BATCH_GRAPH, LD_BATCH_RETUNE = 1, 2
+LD_BATCH_GRAPH, LD_BATCH_RETUNE, LD_BATCH_PRECOND_ONLY = 1, 2, 4
+LD_SUR_FEATURES, LD_SUR_WIDTH, LD_SUR_BINS = 38, 256, 32
 
 STATUS_NAMES = {0: "LD_OK", -1: "LD_EINVAL", -2: "LD_ENOTSPD", -3: "LD_ENOCONV", -4: "LD_EHIP",
                 -5: "LD_ENOMEM"}
@@ -30,7 +31,10 @@ EXPORTED = (
     "ld_stored_elements", "ld_rational_coeffs", "ld_fill_probes",
     "ld_fill_gaussian", "kernel_matmat", "kernel_materialize", "logdet_precond_build",
     "ld_precond_info", "ld_precond_export", "ld_precond_apply_inverse", "ld_precond_free",
-    "logdet_estimate", "logdet_estimate_batched",
+    "logdet_estimate", "logdet_estimate_batched", "ld_surrogate_param_count",
+    "ld_surrogate_features", "ld_surrogate_create", "ld_surrogate_free", "ld_surrogate_set_scaling",
+    "ld_surrogate_train_step", "ld_surrogate_gradient", "ld_surrogate_params",
+    "ld_surrogate_predict",
 )
 
 
@@ -104,7 +108,18 @@ def load():
         "logdet_estimate": (i32, [vp, ctypes.POINTER(Operator), vp, i32, i32, u64, dbl, i32,
                                   ctypes.POINTER(Result), pd]),
         "logdet_estimate_batched": (i32, [vp, i32, ctypes.POINTER(Instance), i32, i32, i32, i32,
-                                          dbl, i32, i32, ctypes.POINTER(Result), pd]),
+                                          dbl, i32, i32, ctypes.POINTER(Result), pd, pd, i32]),
+        "ld_surrogate_param_count": (i64, []),
+        "ld_surrogate_features": (i32, [pd, i32, i32, dbl, dbl, dbl, i64, i32, pd,
+                                        ctypes.POINTER(ctypes.c_float)]),
+        "ld_surrogate_create": (i32, [vp, i32, u64, ctypes.POINTER(vp)]),
+        "ld_surrogate_free": (None, [vp]),
+        "ld_surrogate_set_scaling": (i32, [vp, vp, ctypes.POINTER(ctypes.c_float),
+                                           ctypes.POINTER(ctypes.c_float), dbl, dbl]),
+        "ld_surrogate_train_step": (i32, [vp, vp, vp, vp, i32, ctypes.c_float, pd]),
+        "ld_surrogate_gradient": (i32, [vp, vp, i32, vp, vp, i32, vp, pd]),
+        "ld_surrogate_params": (i32, [vp, vp, i32, vp, vp]),
+        "ld_surrogate_predict": (i32, [vp, vp, vp, i64, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -340,8 +355,10 @@ class BatchItem:
 
 def logdet_estimate_batched(ctx: Context, items, k: int, num_probes: int, oversample: int = 10,
                             power_iters: int = 2, tol: float = 1e-6, max_iters: int = 5000,
-                            graph: bool = False, retune: bool = False, allow_noconv: bool = False):
-    """Returns (list of result dicts, per-probe values (count, num_probes), status name)."""
+                            graph: bool = False, retune: bool = False, allow_noconv: bool = False,
+                            precond_only: bool = False, want_lambda: bool = False):
+    """Returns (list of result dicts, per-probe values (count, num_probes), status name), and
+    with want_lambda also the kept eigenvalues (count, max rank), zero-padded."""
     torch = _torch()
     count = len(items)
     arr = (Instance * count)()
@@ -353,9 +370,97 @@ def logdet_estimate_batched(ctx: Context, items, k: int, num_probes: int, oversa
                           precond_seed=it.precond_seed, probe_seed=it.probe_seed)
     res = (Result * max(count, 1))()
     per = np.zeros((max(count, 1), num_probes), dtype=np.float64)
-    flags = (LD_BATCH_GRAPH if graph else 0) | (LD_BATCH_RETUNE if retune else 0)
+    flags = ((LD_BATCH_GRAPH if graph else 0) | (LD_BATCH_RETUNE if retune else 0)
+             | (LD_BATCH_PRECOND_ONLY if precond_only else 0))
+    stride = max([it.rank for it in items] + [1])
+    lam = np.zeros((max(count, 1), stride), dtype=np.float64) if want_lambda else None
+    pd = ctypes.POINTER(ctypes.c_double)
     st = load().logdet_estimate_batched(ctx.handle, count, arr, k, num_probes, oversample,
                                         power_iters, tol, max_iters, flags, res,
-                                        per.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                                        per.ctypes.data_as(pd),
+                                        lam.ctypes.data_as(pd) if want_lambda else None, stride)
     _check(st, allow=(LD_ENOCONV,) if allow_noconv else ())
-    return [r.as_dict() for r in res[:count]], per[:count], STATUS_NAMES.get(st, st)
+    out = ([r.as_dict() for r in res[:count]], per[:count], STATUS_NAMES.get(st, st))
+    return out + (lam[:count],) if want_lambda else out
+
+
+def surrogate_param_count() -> int:
+    return int(load().ld_surrogate_param_count())
+
+
+def surrogate_features(lam, kind: int, lengthscale: float, variance: float, noise: float, n: int,
+                       d: int, edges) -> np.ndarray:
+    """The 38 features of one problem (host computation in the library)."""
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    edges = np.ascontiguousarray(edges, dtype=np.float64)
+    out = np.zeros(LD_SUR_FEATURES, dtype=np.float32)
+    _check(load().ld_surrogate_features(lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        len(lam), kind, lengthscale, variance, noise, n, d,
+                                        edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return out
+
+
+class Surrogate:
+    """Ensemble MLP surrogate (library-owned parameters on the context's device)."""
+
+    def __init__(self, ctx: Context, members: int = 5, seed: int = 0):
+        self.ctx = ctx
+        self.members = members
+        h = ctypes.c_void_p()
+        _check(load().ld_surrogate_create(ctx.handle, members, seed, ctypes.byref(h)))
+        self.handle = h
+
+    def set_scaling(self, x_mean, x_std, y_mean: float, y_std: float):
+        fp = ctypes.POINTER(ctypes.c_float)
+        xm = np.ascontiguousarray(x_mean, dtype=np.float32)
+        xs = np.ascontiguousarray(x_std, dtype=np.float32)
+        _check(load().ld_surrogate_set_scaling(self.ctx.handle, self.handle, xm.ctypes.data_as(fp),
+                                               xs.ctypes.data_as(fp), float(y_mean), float(y_std)))
+
+    def train_step(self, X, y, lr: float = 1e-3, want_loss: bool = True):
+        loss = np.zeros(self.members, dtype=np.float64)
+        _check(load().ld_surrogate_train_step(
+            self.ctx.handle, self.handle, X.data_ptr(), y.data_ptr(), int(X.shape[0]), lr,
+            loss.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_loss else None))
+        return loss if want_loss else None
+
+    def gradient(self, member: int, X, y):
+        torch = _torch()
+        g = torch.empty(surrogate_param_count(), dtype=torch.float32, device=X.device)
+        loss = ctypes.c_double()
+        _check(load().ld_surrogate_gradient(self.ctx.handle, self.handle, member, X.data_ptr(),
+                                            y.data_ptr(), int(X.shape[0]), g.data_ptr(),
+                                            ctypes.byref(loss)))
+        return g, loss.value
+
+    def get_params(self, member: int):
+        torch = _torch()
+        out = torch.empty(surrogate_param_count(), dtype=torch.float32, device="cuda")
+        _check(load().ld_surrogate_params(self.ctx.handle, self.handle, member, out.data_ptr(), None))
+        self.ctx.synchronize()
+        return out
+
+    def set_params(self, member: int, p):
+        _check(load().ld_surrogate_params(self.ctx.handle, self.handle, member, None, p.data_ptr()))
+        self.ctx.synchronize()
+
+    def predict(self, X):
+        torch = _torch()
+        N = int(X.shape[0])
+        mean = torch.empty(N, dtype=torch.float32, device=X.device)
+        sd = torch.empty(N, dtype=torch.float32, device=X.device)
+        _check(load().ld_surrogate_predict(self.ctx.handle, self.handle, X.data_ptr(), N,
+                                           mean.data_ptr(), sd.data_ptr()))
+        return mean, sd
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().ld_surrogate_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -725,7 +725,8 @@ ld_status logdet_estimate(ld_ctx* ctx, const ld_operator* op, const ld_precond* 
 ld_status logdet_estimate_batched(ld_ctx* ctx, int32_t count, const ld_instance* instances,
                                   int32_t k, int32_t num_probes, int32_t oversample,
                                   int32_t power_iters, double tol, int32_t max_iters,
-                                  int32_t flags, ld_result* results, double* per_probe) {
+                                  int32_t flags, ld_result* results, double* per_probe,
+                                  double* lambda_out, int32_t lambda_stride) {
   LD_TRY(check_ctx(ctx));
   if (count < 1 || count > 4096) return fail(LD_EINVAL, "count must be in 1..4096");
   if (!instances || !results) return fail(LD_EINVAL, "instances or results is NULL");
@@ -736,7 +737,8 @@ ld_status logdet_estimate_batched(ld_ctx* ctx, int32_t count, const ld_instance*
   if (power_iters < 0 || power_iters > 16) return fail(LD_EINVAL, "power_iters must be in 0..16");
   if (!(tol > 0.0) || !std::isfinite(tol)) return fail(LD_EINVAL, "tol must be finite and > 0");
   if (max_iters < 1) return fail(LD_EINVAL, "max_iters must be >= 1");
-  if (flags & ~(LD_BATCH_GRAPH | LD_BATCH_RETUNE)) return fail(LD_EINVAL, "unknown flag bits");
+  if (flags & ~(LD_BATCH_GRAPH | LD_BATCH_RETUNE | LD_BATCH_PRECOND_ONLY))
+    return fail(LD_EINVAL, "unknown flag bits");
   for (int32_t i = 0; i < count; ++i) {
     const ld_instance& x = instances[i];
     const std::string at = " (instance " + std::to_string(i) + ")";
@@ -753,9 +755,11 @@ ld_status logdet_estimate_batched(ld_ctx* ctx, int32_t count, const ld_instance*
     if (x.rank < 1 || (int64_t)x.rank + oversample > x.n || (int64_t)x.rank + oversample > 1024)
       return fail(LD_EINVAL, "need 1 <= rank and rank + oversample <= min(n, 1024)" + at);
     if (x.reserved != 0) return fail(LD_EINVAL, "reserved must be 0" + at);
+    if (lambda_out && x.rank > lambda_stride) return fail(LD_EINVAL, "lambda_stride < rank" + at);
   }
   return batched_estimate(ctx, count, instances, k, rf.a, rf.b, rf.c, num_probes, oversample,
-                          power_iters, tol, max_iters, flags, results, per_probe);
+                          power_iters, tol, max_iters, flags, results, per_probe, lambda_out,
+                          lambda_stride);
 }
 
 }  // extern "C"

@@ -1219,7 +1219,8 @@ ld_status with_stream(ld_ctx* ctx, hipStream_t st, const Batch& b, int ncols, in
 ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
                            const double* shifts, double bcoef, const double* ccoef, int s,
                            int oversample, int power_iters, double tol, int max_iters, int flags,
-                           ld_result* out, double* per_probe) {
+                           ld_result* out, double* per_probe, double* lambda_out,
+                           int lambda_stride) {
   // ---- layout: instance i owns padded rows [row0_i, row0_i + ceil(n_i/128)*128)
   Batch b;
   b.B = count;
@@ -1413,6 +1414,11 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
         if (!(v > 0.0) || !std::isfinite(v))
           return fail(LD_ENOTSPD, "batch: non-positive kept eigenvalue in instance " + std::to_string(i));
       }
+    if (lambda_out)
+      for (int i = 0; i < count; ++i)
+        for (int j = 0; j < lambda_stride; ++j)
+          lambda_out[(int64_t)i * lambda_stride + j] =
+              j < b.h[i].rank ? ctx->pinned[(int64_t)i * b.mmax + j] : 0.0;
   }
   // U = Q V_l;  D;  C = diag(1/lam) + U^T D^-1 U = R^T R;  log det P;  F = D^-1 U R^-1
   hipLaunchKernelGGL(k_bgemm, gemm_grid(b, b.lmax), dim3(256), 0, st, b.d_inst, 0, 1, Qb, b.mmax,
@@ -1448,6 +1454,17 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
         return fail(LD_ENOTSPD, "batch: log det P is not finite in instance " + std::to_string(i));
   }
   auto t1 = std::chrono::steady_clock::now();
+  if (flags & LD_BATCH_PRECOND_ONLY) {
+    for (int i = 0; i < count; ++i) {
+      ld_result& o = out[i];
+      o = ld_result{};
+      o.logdet_P = logdetP[i];
+      o.logdet = logdetP[i];
+      o.k = J;
+      o.num_probes = s;
+    }
+    return LD_OK;
+  }
 
   // ---- multi-shift CG over every (instance, probe) column
   Scal S;

@@ -228,6 +228,6 @@ size_t pcg_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int rank, int64_t s, 
 ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
                            const double* shifts, double bcoef, const double* ccoef, int s,
                            int oversample, int power_iters, double tol, int max_iters, int flags,
-                           ld_result* out, double* per_probe);
+                           ld_result* out, double* per_probe, double* lambda_out, int lambda_stride);
 
 }  // namespace ld

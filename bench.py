@@ -25,6 +25,15 @@ Workloads (all synthetic, inputs from workloads/):
                    replayed from a HIP graph).  A step estimates all 256.
                    --compare-plain times the same 256 problems as sequential
                    single-instance plain FP32 calls.
+  c5_surrogate     learned surrogate: training targets from the batched r_5
+                   estimator (64 probes) on problems with the c4
+                   hyperparameter distribution at --c5-train-n, ensemble
+                   training, then a 32 x 32 (lengthscale, noise) Matern-5/2
+                   sweep at --c5-eval-n: preconditioners + BF16 ensemble
+                   prediction + fallback to the estimator where the members
+                   disagree, timed against the plain estimator on every grid
+                   point (which is also the error reference).  A step is one
+                   sweep over the grid.
 
 Prints one JSON line.
 """
@@ -36,6 +45,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -44,7 +55,7 @@ import workloads  # noqa: E402
 METRIC = "log-det estimates/s at ≤1e-3 rel err vs FP64; mixed/batched vs plain FP32"
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "bf16": 2.5e15}
 WORKLOADS = {"c2_matern_gm50k": workloads.C2, "c1_rbf_2k": workloads.C1,
-             "c3_matern_200k": workloads.C3, "c4_batch256": None}
+             "c3_matern_200k": workloads.C3, "c4_batch256": None, "c5_surrogate": None}
 
 
 def log(*a):
@@ -323,6 +334,125 @@ def batch_cpu_baseline(insts, sample_count):
                        f"scaled to all {len(insts)} instances by sum n^3")}
 
 
+def surrogate_main(args, torch, L):
+    from paper_2405_03474_amd import sweep
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream(0)
+    ctx = L.Context(0, stream)
+    cfg = sweep.Config()
+    train_insts = workloads.surrogate_training_instances(args.c5_train_count, args.c5_train_n)
+    grid = workloads.surrogate_grid(args.c5_eval_n, side=args.c5_side)
+    log(f"[bench] c5: {len(train_insts)} training problems at n={args.c5_train_n}, "
+        f"{len(grid)} grid points at n={args.c5_eval_n}")
+    t0 = time.perf_counter()
+    res, lams, _ = sweep.estimate_all(ctx, train_insts, cfg, torch)
+    t_gen = time.perf_counter() - t0
+    ok = [i for i, r in enumerate(res) if r["converged_cols"] == cfg.probes]
+    train_used = [train_insts[i] for i in ok]
+    lams = [lams[i] for i in ok]
+    y = np.array([(res[i]["logdet"] - res[i]["logdet_P"]) / train_insts[i].n for i in ok])
+    edges = sweep.feature_edges(lams, train_used)
+    F = sweep.features(lams, train_used, edges)
+    log(f"[bench] training data {t_gen:.2f} s")
+    t0 = time.perf_counter()
+    S, hist = sweep.train(ctx, F, y, torch, epochs=args.c5_epochs)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"[bench] training {t_train:.2f} s, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+
+    # plain estimator on every grid point (error reference and the comparison);
+    # kernel events around its products give the roofline
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain, _, items = sweep.estimate_all(ctx, grid, cfg, torch)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    mm_ms, mm_calls, mm_flops, mm_bytes = ctx.read_timing()
+    ctx.set_timing(False)
+    log(f"[bench] plain sweep {t_plain:.2f} s")
+    for w in range(args.warmup):
+        sweep.sweep(ctx, S, grid, edges, cfg, torch, items=items)
+    times = []
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        logdet, fb, stages, _ = sweep.sweep(ctx, S, grid, edges, cfg, torch, items=items)
+        torch.cuda.synchronize()
+        predicted, spread = stages.pop("predicted"), stages.pop("spread")
+        times.append(stages)
+        log(f"[bench] surrogate sweep {i}: {stages}")
+    t_sur = float(np.mean([st["total"] for st in times]))
+    ref = np.array([r["logdet"] for r in plain])
+    plain_unconverged = int(sum(r["converged_cols"] < cfg.probes for r in plain))
+    if args.dump:
+        Fg = sweep.features(sweep.estimate_all(ctx, grid, cfg, torch, precond_only=True,
+                                               items=items)[1], grid, edges)
+        np.savez(args.dump, F_train=F, y_train=y, F_grid=Fg, predicted=predicted, spread=spread,
+                 ref=ref, logdet_P=np.array([r["logdet_P"] for r in plain]),
+                 n_grid=np.array([g.n for g in grid]), edges=edges)
+    rel = np.abs(logdet - ref) / np.abs(ref)
+    rel_pred = np.abs(predicted - ref) / np.abs(ref)
+    avg_ms = mm_ms / max(mm_calls, 1)
+    achieved = (mm_flops / max(mm_calls, 1)) / (avg_ms / 1e3) if mm_calls else 0.0
+    line = {
+        "metric": METRIC, "value": len(grid) / t_sur, "unit": "log-det estimates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_sur * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
+        "data": "synthetic",
+        "config": {"workload": "c5_surrogate", "train_n": args.c5_train_n,
+                   "train_count": len(train_insts), "train_converged": len(ok),
+                   "eval_n": args.c5_eval_n,
+                   "grid": f"{args.c5_side}x{args.c5_side}", "order": cfg.k, "probes": cfg.probes,
+                   "rank": "n/40", "members": 5, "epochs": args.c5_epochs,
+                   "fallback_rel_tol": cfg.rel_tol},
+        "plain_estimator": {"value": len(grid) / t_plain, "seconds": t_plain,
+                            "unconverged": plain_unconverged},
+        "speedup_vs_plain": t_plain / t_sur,
+        "stages_s": times[-1],
+        "fallbacks": int(fb.sum()),
+        "error_vs_plain": {"max_rel": float(rel.max()), "median_rel": float(np.median(rel)),
+                           "within_1e-3": int((rel <= 1e-3).sum()),
+                           "max_rel_predicted": float(rel[~fb].max()) if (~fb).any() else None},
+        "ensemble_only_error_vs_plain": {
+            "median_rel": float(np.median(rel_pred)), "p90_rel": float(np.quantile(rel_pred, 0.9)),
+            "within_1e-3": int((rel_pred <= 1e-3).sum()), "within_1e-2": int((rel_pred <= 1e-2).sum()),
+            "median_rel_spread": float(np.median(spread / np.abs(ref)))},
+        "training": {"data_seconds": t_gen, "train_seconds": t_train, "loss_first": hist[0],
+                     "loss_last": hist[-1]},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK["fp32"], "traffic": None,
+                     "kernel": "k_bmm (batched FP32 product of the plain estimator on the grid)",
+                     "avg_launch_ms": avg_ms, "launches": mm_calls},
+    }
+    if args.no_cpu_baseline:
+        line["cpu_baseline"] = None
+    else:
+        log("[bench] cpu baseline (oracle) ...")
+        line["cpu_baseline"] = surrogate_cpu_baseline(grid, cfg, args.cpu_sample_count)
+    print(json.dumps(line), flush=True)
+    S.close()
+    ctx.close()
+
+
+def surrogate_cpu_baseline(grid, cfg, count):
+    """The oracle estimator on a few grid points, scaled to the whole grid."""
+    from oracle import estimate as oest
+    from oracle import gp, precond
+    pick = grid[:: max(1, len(grid) // max(1, min(count, 3)))][:3]
+    t0 = time.perf_counter()
+    for g in pick:
+        M = gp.dense_matrix(g.kind, g.X(), g.lengthscale, g.variance, g.noise)
+        P = precond.rsvd(M, g.rank, cfg.oversample, cfg.power_iters, g.precond_seed,
+                         precond.d_floor(g.noise, g.variance))
+        oest.estimate_dense(M, P.dense(), P.logdet, cfg.k, oest.probes(g.probe_seed, g.n, cfg.probes))
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": len(pick) / dt, "unit": "log-det estimates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"oracle (FP64, dense Cholesky shifted solves) on {len(pick)} grid points "
+                      f"at n={pick[0].n}: {dt:.2f} s"}
+
+
 def timed_steps(runner, steps, warmup, stream, torch):
     for w in range(warmup):
         t0 = time.perf_counter()
@@ -364,6 +494,11 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="batched form: eager launches")
     ap.add_argument("--cpu-sample-count", type=int, default=12)
     ap.add_argument("--dump", default="", help="batched form: write per-instance results (JSON)")
+    ap.add_argument("--c5-train-n", type=int, default=1000)
+    ap.add_argument("--c5-train-count", type=int, default=1024)
+    ap.add_argument("--c5-eval-n", type=int, default=5000)
+    ap.add_argument("--c5-side", type=int, default=32)
+    ap.add_argument("--c5-epochs", type=int, default=300)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the workload, run one device-to-device copy of this many MiB "
                          "(the reference dispatch for HBM byte counters)")
@@ -377,6 +512,8 @@ def main():
 
     if args.workload == "c4_batch256":
         return batch_main(args, torch, L)
+    if args.workload == "c5_surrogate":
+        return surrogate_main(args, torch, L)
     cfg = WORKLOADS[args.workload]
     if args.n:
         cfg = cfg.with_n(args.n, rank=min(cfg.rank, args.n // 10))

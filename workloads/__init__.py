@@ -21,6 +21,11 @@ as well, Section 3):
                   RBF or Matern-5/2, l log-U[0.02,0.5], s2 log-U[0.5,2],
                   noise log-U[1e-4,1e-1], points uniform in [0,1]^d; r_3;
                   16 probes; rank min(200, n/10).
+  c5_surrogate    training set: instances with the c4 hyperparameter
+                  distribution at one fixed n (r_5, 64 probes, rank n/40);
+                  evaluation grid: 32 x 32 log-spaced lengthscales in
+                  [0.02, 0.5] x noises in [1e-4, 1e-1], variance 1,
+                  Matern-5/2, d = 3, points uniform in [0,1]^3, at a larger n.
 """
 from __future__ import annotations
 
@@ -102,4 +107,37 @@ def batch_instances(count: int = 256, seed: int = BASE_SEED + 3, n_lo: int = 500
                               noise=noise, points="uniform", seed=seed * 1000 + i,
                               rank=rank, probes=probes, orders=(3,),
                               probe_seed=seed + 10000 + i, precond_seed=seed + 20000 + i))
+    return out
+
+
+def surrogate_training_instances(count: int, n: int, seed: int = BASE_SEED + 4,
+                                 probes: int = 64):
+    """Training problems for the surrogate: the c4 hyperparameter distribution
+    at a fixed n, rank n/40."""
+    g = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        d = int(g.choice([2, 3, 8]))
+        kind = int(g.integers(0, 2))
+        ls = float(np.exp(g.uniform(np.log(0.02), np.log(0.5))))
+        var = float(np.exp(g.uniform(np.log(0.5), np.log(2.0))))
+        noise = float(np.exp(g.uniform(np.log(1e-4), np.log(1e-1))))
+        out.append(GPInstance(f"c5t_{i}", n=n, d=d, kind=kind, lengthscale=ls, variance=var,
+                              noise=noise, points="uniform", seed=seed * 1000 + i,
+                              rank=max(1, n // 40), probes=probes, orders=(5,),
+                              probe_seed=seed + 10000 + i, precond_seed=seed + 20000 + i))
+    return out
+
+
+def surrogate_grid(n: int, side: int = 32, seed: int = BASE_SEED + 5, probes: int = 64):
+    """The evaluation sweep: side x side log-spaced (lengthscale, noise) pairs,
+    variance 1, Matern-5/2, d = 3, one point cloud shared by the grid."""
+    out = []
+    for a, ls in enumerate(np.exp(np.linspace(np.log(0.02), np.log(0.5), side))):
+        for b, nz in enumerate(np.exp(np.linspace(np.log(1e-4), np.log(1e-1), side))):
+            i = a * side + b
+            out.append(GPInstance(f"c5g_{a}_{b}", n=n, d=3, kind=MATERN52, lengthscale=float(ls),
+                                  variance=1.0, noise=float(nz), points="uniform", seed=seed,
+                                  rank=max(1, n // 40), probes=probes, orders=(5,),
+                                  probe_seed=seed + 10000 + i, precond_seed=seed + 20000 + i))
     return out

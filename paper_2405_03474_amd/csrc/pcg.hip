@@ -30,61 +30,87 @@ namespace ld {
 namespace {
 
 constexpr int WT = 64;  // Woodbury tile (rows of F / columns of R)
-constexpr int WR = 16;  // rows staged per step
+constexpr int FR = 32;  // rows of F and R staged per step
+typedef double f64x4w __attribute__((ext_vector_type(4)));
 
-// t_partial[c] = F_c^T R_c over row chunk c: output rank x s, FP64.
+// t_partial[c] = F_c^T R_c over row chunk c (output rank x s, FP64) on FP64
+// matrix cores (v_mfma_f64_16x16x4f64, inputs widened exactly).  Workgroup:
+// one row chunk x 64 columns of F x 64 columns of R, cut into 16 x 16 (l, c)
+// tiles, at most four per wave.  Stages of 32 rows of F and R go through LDS
+// (coalesced row-segment loads, the next stage prefetched in registers).  In
+// step t a wave consumes stage rows 4t .. 4t+3, lane group g = lane/16
+// supplying row 4t + g; output lane l, register r: tile row l/16 + 4 r,
+// column l % 16.
 template <typename T>
 __global__ __launch_bounds__(256) void k_ft_partial(const T* __restrict__ F,
                                                     const T* __restrict__ R, int64_t n, int rank,
                                                     int64_t s, int64_t chunk,
                                                     double* __restrict__ part) {
-  __shared__ double Fs[WR][WT + 1];
-  __shared__ double Rs[WR][WT + 1];
-  const int tid = threadIdx.x;
-  const int ti = tid / 16, tj = tid % 16;
+  __shared__ double Fs[FR][WT + 1];
+  __shared__ double Rs[FR][WT + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
   const int l0 = blockIdx.y * WT;
   const int64_t c0 = (int64_t)blockIdx.z * WT;
   const int64_t r0 = (int64_t)blockIdx.x * chunk;
-  int64_t r1 = r0 + chunk;
-  if (r1 > n) r1 = n;
-  double acc[4][4] = {};
-  for (int64_t rb = r0; rb < r1; rb += WR) {
-    __syncthreads();
-    for (int e = tid; e < WR * WT; e += 256) {
+  const int64_t r1 = r0 + chunk < n ? r0 + chunk : n;
+  const int ltl = (rank - l0 < WT ? rank - l0 + 15 : WT + 15) / 16;
+  const int ctl = (int)((s - c0 < WT ? s - c0 + 15 : WT + 15) / 16);
+  const int tiles = ltl * ctl;
+  f64x4w acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = f64x4w{0.0, 0.0, 0.0, 0.0};
+  T pf[8], pr[8];
+  auto fetch = [&](int64_t rb) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = tid + 256 * j;
       const int rr = e / WT, cc = e % WT;
       const int64_t row = rb + rr;
-      double fv = 0.0, rv = 0.0;
-      if (row < r1) {
-        if (l0 + cc < rank) fv = (double)F[row * rank + l0 + cc];
-        if (c0 + cc < s) rv = (double)R[row * s + c0 + cc];
-      }
-      Fs[rr][cc] = fv;
-      Rs[rr][cc] = rv;
+      const bool ok = row < r1;
+      pf[j] = (ok && l0 + cc < rank) ? F[row * rank + l0 + cc] : (T)0;
+      pr[j] = (ok && c0 + cc < s) ? R[row * s + c0 + cc] : (T)0;
+    }
+  };
+  fetch(r0);
+  for (int64_t rb = r0; rb < r1; rb += FR) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = tid + 256 * j;
+      Fs[e / WT][e % WT] = (double)pf[j];
+      Rs[e / WT][e % WT] = (double)pr[j];
     }
     __syncthreads();
-#pragma unroll 4
-    for (int rr = 0; rr < WR; ++rr) {
-      double a[4], b[4];
+    if (rb + FR < r1) fetch(rb + FR);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[q] = Fs[rr][ti + 16 * q];
-        b[q] = Rs[rr][tj + 16 * q];
+    for (int q = 0; q < 4; ++q) {
+      const int p = wave + 4 * q;
+      if (p < tiles) {
+        const int lt = p / ctl, cs = p % ctl;
+#pragma unroll
+        for (int t = 0; t < FR / 4; ++t) {
+          const int k = 4 * t + lg;
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(Fs[k][lt * 16 + li], Rs[k][cs * 16 + li],
+                                                        acc[q], 0, 0, 0);
+        }
       }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
     }
   }
   double* dst = part + (int64_t)blockIdx.x * rank * s;
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int q = 0; q < 4; ++q) {
+    const int p = wave + 4 * q;
+    if (p < tiles) {
+      const int lt = p / ctl, cs = p % ctl;
+      const int64_t c = c0 + cs * 16 + li;
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int l = l0 + ti + 16 * x;
-      const int64_t c = c0 + tj + 16 * y;
-      if (l < rank && c < s) dst[(int64_t)l * s + c] = acc[x][y];
+      for (int r = 0; r < 4; ++r) {
+        const int l = l0 + lt * 16 + lg + 4 * r;
+        if (l < rank && c < s) dst[(int64_t)l * s + c] = acc[q][r];
+      }
     }
+  }
 }
 
 __global__ void k_sum_parts(const double* __restrict__ part, int chunks, int64_t count,
@@ -97,8 +123,10 @@ __global__ void k_sum_parts(const double* __restrict__ part, int chunks, int64_t
   }
 }
 
-// OUT = Dinv .* R - F t (t: rank x s FP64), 64 x 64 tile per workgroup.
-// Optional per-row-tile column dots: dot1 = sum R .* OUT, dot2 = sum Z .* R.
+// OUT = Dinv .* R - F t (t: rank x s FP64) on a 64-row x 64-column tile, the
+// product F t on FP64 matrix cores (wave w: rows 16 w .. 16 w + 15, lane
+// group g supplying rank index 4 step + g).  Optional per-row-tile column
+// dots: dot1 = sum R .* OUT, dot2 = sum Z .* R.
 template <typename T>
 __global__ __launch_bounds__(256) void k_wood_out(const T* __restrict__ F,
                                                   const T* __restrict__ Dinv,
@@ -108,76 +136,68 @@ __global__ __launch_bounds__(256) void k_wood_out(const T* __restrict__ F,
                                                   const T* __restrict__ Z,
                                                   double* __restrict__ dot1,
                                                   double* __restrict__ dot2) {
-  __shared__ double Fs[WT][WR + 1];
-  __shared__ double Ts[WR][WT + 1];
-  __shared__ double red1[16][WT + 1];
-  __shared__ double red2[16][WT + 1];
-  const int tid = threadIdx.x;
-  const int ti = tid / 16, tj = tid % 16;
+  __shared__ double red1[4][64][4];
+  __shared__ double red2[4][64][4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
   const int64_t i0 = (int64_t)blockIdx.x * WT;
   const int64_t c0 = (int64_t)blockIdx.y * WT;
-  double acc[4][4] = {};
-  for (int l0 = 0; l0 < rank; l0 += WR) {
-    __syncthreads();
-    for (int e = tid; e < WT * WR; e += 256) {
-      const int rr = e / WR, ll = e % WR;
-      const int64_t row = i0 + rr;
-      Fs[rr][ll] = (row < n && l0 + ll < rank) ? (double)F[row * rank + l0 + ll] : 0.0;
-    }
-    for (int e = tid; e < WR * WT; e += 256) {
-      const int ll = e / WT, cc = e % WT;
-      Ts[ll][cc] = (l0 + ll < rank && c0 + cc < s) ? t[(int64_t)(l0 + ll) * s + c0 + cc] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int ll = 0; ll < WR; ++ll) {
-      double a[4], b[4];
+  const int ctl = (int)((s - c0 < WT ? s - c0 + 15 : WT + 15) / 16);
+  const int64_t arow = i0 + 16 * wave + li;
+  const bool arow_ok = arow < n;
+  f64x4w acc[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[q] = Fs[ti + 16 * q][ll];
-        b[q] = Ts[ll][tj + 16 * q];
+  for (int c = 0; c < 4; ++c) acc[c] = f64x4w{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < rank; k0 += 4) {
+    const int k = k0 + lg;
+    const bool kv = k < rank;
+    const double a = (kv && arow_ok) ? (double)F[arow * rank + k] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (c < ctl) {
+        const int64_t cc = c0 + c * 16 + li;
+        const double b = (kv && cc < s) ? t[(int64_t)k * s + cc] : 0.0;
+        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
       }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
     }
   }
-  double d1[4] = {}, d2[4] = {};
+  double d1[4] = {0.0, 0.0, 0.0, 0.0}, d2[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    const int64_t row = i0 + ti + 16 * x;
-    if (row >= n) continue;
-    const double dv = (double)Dinv[row];
+  for (int c = 0; c < 4; ++c) {
+    if (c >= ctl) continue;
+    const int64_t cc = c0 + c * 16 + li;
+    if (cc >= s) continue;
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int64_t c = c0 + tj + 16 * y;
-      if (c >= s) continue;
-      const int64_t off = row * s + c;
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = i0 + 16 * wave + lg + 4 * r;
+      if (row >= n) continue;
+      const int64_t off = row * s + cc;
       const double rv = (double)R[off];
-      const T o = (T)(dv * rv - acc[x][y]);
+      const T o = (T)((double)Dinv[row] * rv - acc[c][r]);
       OUT[off] = o;
-      if (dot1) d1[y] += rv * (double)o;
-      if (dot2) d2[y] += (double)Z[off] * rv;
+      d1[c] += rv * (double)o;
+      if (dot2) d2[c] += (double)Z[off] * rv;
     }
   }
   if (dot1) {
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      red1[ti][tj + 16 * y] = d1[y];
-      red2[ti][tj + 16 * y] = d2[y];
+    for (int c = 0; c < 4; ++c) {
+      red1[wave][lane][c] = d1[c];
+      red2[wave][lane][c] = d2[c];
     }
     __syncthreads();
     if (tid < WT) {
+      const int c = tid / 16, l16 = tid % 16;
       double a = 0.0, b = 0.0;
-      for (int q = 0; q < 16; ++q) {
-        a += red1[q][tid];
-        b += red2[q][tid];
-      }
-      const int64_t c = c0 + tid;
-      if (c < s) {
-        dot1[(int64_t)blockIdx.x * s + c] = a;
-        if (dot2) dot2[(int64_t)blockIdx.x * s + c] = b;
+      for (int w = 0; w < 4; ++w)
+        for (int g = 0; g < 4; ++g) {
+          a += red1[w][l16 + 16 * g][c];
+          b += red2[w][l16 + 16 * g][c];
+        }
+      const int64_t col = c0 + tid;
+      if (col < s) {
+        dot1[(int64_t)blockIdx.x * s + col] = a;
+        if (dot2) dot2[(int64_t)blockIdx.x * s + col] = b;
       }
     }
   }
@@ -361,7 +381,7 @@ WoodPlan wood_plan(ld_ctx* ctx, int64_t n, int rank, int64_t s) {
   WoodPlan w{};
   w.ltiles = (rank + WT - 1) / WT;
   w.ctiles = (int)((s + WT - 1) / WT);
-  int64_t chunks = (int64_t)ctx->num_cu * 2 / ((int64_t)w.ltiles * w.ctiles);
+  int64_t chunks = (int64_t)ctx->num_cu * 4 / ((int64_t)w.ltiles * w.ctiles);
   const int64_t maxc = (n + 255) / 256;
   if (chunks > maxc) chunks = maxc;
   if (chunks < 1) chunks = 1;
@@ -393,7 +413,7 @@ ld_status wood_apply_t(ld_ctx* ctx, const T* F, const T* Dinv, int64_t n, int ra
 }  // namespace
 
 size_t woodbury_scratch_bytes(int64_t n, int rank, int64_t s) {
-  // upper bound on chunks: num_cu * 2 <= 1024
+  // upper bound on chunks: num_cu * 4 <= 1024 (at most 256 CUs)
   const int64_t chunks = 1024;
   (void)n;
   return (size_t)(chunks + 1) * rank * s * sizeof(double) + 4096;

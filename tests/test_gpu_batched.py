@@ -199,3 +199,26 @@ def test_batched_full_c4_sampled(ctx):
     for i in order[:8]:
         strict += check_instance(insts[i], res[i], per[i], 3, 16)
     assert strict >= 5  # enough well-posed instances among the sampled
+
+
+def test_precond_only_and_eigenvalues(ctx):
+    """LD_BATCH_PRECOND_ONLY returns the same log det P as a full run and each
+    instance's kept eigenvalues, which match the oracle's Ritz values."""
+    insts = small_batch()
+    items = items_of(insts)
+    full, _, _, lam_full = L.logdet_estimate_batched(ctx, items, 3, 4, OVERSAMPLE, POWER, tol=1e-6,
+                                                     want_lambda=True)
+    pre, _, status, lam = L.logdet_estimate_batched(ctx, items, 3, 4, OVERSAMPLE, POWER,
+                                                    precond_only=True, want_lambda=True)
+    assert status == "LD_OK"
+    np.testing.assert_array_equal(lam, lam_full)
+    for g, a, b, row in zip(insts, full, pre, lam):
+        assert b["logdet_P"] == a["logdet_P"] and b["logdet"] == b["logdet_P"]
+        assert b["iterations"] == 0 and b["trace_term"] == 0.0
+        assert np.all(row[g.rank:] == 0) and np.all(np.diff(row[:g.rank]) <= 0)
+        M = gp.dense_matrix(g.kind, g.X(), g.lengthscale, g.variance, g.noise)
+        ref = oprec.rsvd(M, g.rank, OVERSAMPLE, POWER, g.precond_seed,
+                         oprec.d_floor(g.noise, g.variance))
+        # the leading Ritz values are well separated; FP32 products keep them to ~1e-5
+        top = min(g.rank, 5)
+        np.testing.assert_allclose(row[:top], ref.lam[:top], rtol=1e-4)

@@ -124,9 +124,12 @@ __global__ void k_sum_parts(const double* __restrict__ part, int chunks, int64_t
 }
 
 // OUT = Dinv .* R - F t (t: rank x s FP64) on a 64-row x 64-column tile, the
-// product F t on FP64 matrix cores (wave w: rows 16 w .. 16 w + 15, lane
-// group g supplying rank index 4 step + g).  Optional per-row-tile column
-// dots: dot1 = sum R .* OUT, dot2 = sum Z .* R.
+// product F t on FP64 matrix cores: stages of 32 rank indices of F (64 rows,
+// coalesced row segments) and of t go through LDS, the next stage prefetched
+// in registers; wave w owns rows 16 w .. 16 w + 15, lane group g supplies
+// rank index 4 step + g.  Optional per-row-tile column dots: dot1 = sum
+// R .* OUT, dot2 = sum Z .* R.
+constexpr int WK = 32;  // rank indices per stage
 template <typename T>
 __global__ __launch_bounds__(256) void k_wood_out(const T* __restrict__ F,
                                                   const T* __restrict__ Dinv,
@@ -136,6 +139,8 @@ __global__ __launch_bounds__(256) void k_wood_out(const T* __restrict__ F,
                                                   const T* __restrict__ Z,
                                                   double* __restrict__ dot1,
                                                   double* __restrict__ dot2) {
+  __shared__ double Fs[WT][WK + 1];
+  __shared__ double Ts[WK][WT + 1];
   __shared__ double red1[4][64][4];
   __shared__ double red2[4][64][4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -143,22 +148,41 @@ __global__ __launch_bounds__(256) void k_wood_out(const T* __restrict__ F,
   const int64_t i0 = (int64_t)blockIdx.x * WT;
   const int64_t c0 = (int64_t)blockIdx.y * WT;
   const int ctl = (int)((s - c0 < WT ? s - c0 + 15 : WT + 15) / 16);
-  const int64_t arow = i0 + 16 * wave + li;
-  const bool arow_ok = arow < n;
   f64x4w acc[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) acc[c] = f64x4w{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < rank; k0 += 4) {
-    const int k = k0 + lg;
-    const bool kv = k < rank;
-    const double a = (kv && arow_ok) ? (double)F[arow * rank + k] : 0.0;
+  T pf[8];
+  double pt[8];
+  auto fetch = [&](int k0) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      if (c < ctl) {
-        const int64_t cc = c0 + c * 16 + li;
-        const double b = (kv && cc < s) ? t[(int64_t)k * s + cc] : 0.0;
-        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
-      }
+    for (int j = 0; j < 8; ++j) {
+      const int e = tid + 256 * j;
+      const int rr = e / WK, kk = e % WK;  // F: 64 rows x 32 rank indices
+      const int64_t row = i0 + rr;
+      pf[j] = (row < n && k0 + kk < rank) ? F[row * rank + k0 + kk] : (T)0;
+      const int tk = e / WT, tc = e % WT;  // t: 32 rank indices x 64 columns
+      pt[j] = (k0 + tk < rank && c0 + tc < s) ? t[(int64_t)(k0 + tk) * s + c0 + tc] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < rank; k0 += WK) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = tid + 256 * j;
+      Fs[e / WK][e % WK] = (double)pf[j];
+      Ts[e / WT][e % WT] = pt[j];
+    }
+    __syncthreads();
+    if (k0 + WK < rank) fetch(k0 + WK);
+#pragma unroll 2
+    for (int st = 0; st < WK / 4; ++st) {
+      const int k = 4 * st + lg;
+      const double a = Fs[16 * wave + li][k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (c < ctl)
+          acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Ts[k][c * 16 + li], acc[c], 0, 0, 0);
     }
   }
   double d1[4] = {0.0, 0.0, 0.0, 0.0}, d2[4] = {0.0, 0.0, 0.0, 0.0};

@@ -486,7 +486,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=8000)
     ap.add_argument("--compare-fp32", action="store_true",
-                    help="precision form: also time the plain FP32 on-the-fly path")
+                    help="precision form: also time the plain FP32 path on the same problem")
+    ap.add_argument("--stored-bf16", action="store_true",
+                    help="stored workload in the precision form: M stored as split-BF16 tiles")
     ap.add_argument("--check-fp64", action="store_true",
                     help="precision form: also run the FP64 path on the same probes")
     ap.add_argument("--compare-plain", action="store_true",
@@ -519,6 +521,8 @@ def main():
         cfg = cfg.with_n(args.n, rank=min(cfg.rank, args.n // 10))
     kind = args.workload.split("_")[0]
     precision = {"c1": L.LD_F64, "c2": L.LD_F32, "c3": L.LD_BF16}[kind]
+    if kind == "c2" and args.stored_bf16:
+        precision = L.LD_BF16
     stored = kind == "c2"
     dtype = {L.LD_F64: "f64", L.LD_F32: "f32", L.LD_BF16: "bf16x3+f32"}[precision]
     log(f"[bench] workload {cfg.name} n={cfg.n} rank={cfg.rank} probes={cfg.probes} "
@@ -553,7 +557,7 @@ def main():
     kname = {"c2": "k_mm32_st<2,tiled> (FP32 MFMA 32x32x2, stored tiled M)",
              "c1": "k_mm64<fly> (FP64 MFMA 16x16x4, on the fly)",
              "c3": "k_mm16<fly> (split-BF16 MFMA 32x32x16, 3 terms, on the fly)"}[kind]
-    traffic = profiled_traffic(cfg.name) if not args.n else None
+    traffic = profiled_traffic(cfg.name) if not args.n and precision == L.LD_F32 else None
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": traffic, "kernel": kname,
                 "avg_launch_ms": avg_ms, "launches": mm_calls,
@@ -567,7 +571,8 @@ def main():
         "config": {"workload": cfg.name, "n": cfg.n, "d": cfg.d,
                    "kernel": "matern52" if cfg.kind == 1 else "rbf", "points": cfg.points,
                    "lengthscale": cfg.lengthscale, "variance": cfg.variance, "noise": cfg.noise,
-                   "storage": "stored_tiled" if stored else "on_the_fly",
+                   "storage": (("stored_split_bf16_tiled" if precision == L.LD_BF16 else "stored_tiled")
+                               if stored else "on_the_fly"),
                    "orders": list(cfg.orders), "probes": cfg.probes, "rank": cfg.rank,
                    "oversample": cfg.oversample, "power_iters": cfg.power_iters,
                    "tol": runner.tol},
@@ -576,9 +581,17 @@ def main():
         "wall_s": wall, "accuracy": accuracy, "roofline": roofline,
     }
 
-    if kind == "c3" and args.compare_fp32:
-        log("[bench] plain FP32 on-the-fly path, same problem")
-        plain = Runner(L, torch, ctx, cfg, L.LD_F32, False)
+    if kind == "c2" and precision == L.LD_BF16:
+        # split-BF16 tiles move as many bytes as FP32 with a sixth of the
+        # matrix-core time: the product is bound by HBM
+        gbps = (mm_bytes / max(mm_calls, 1)) / (avg_ms / 1e3) / 1e9
+        line["roofline"].update({
+            "bound": "hbm", "achieved": gbps, "peak": 8000.0, "unit": "GB/s", "frac": gbps / 8000.0,
+            "kernel": "k_mm16_st<2> (split-BF16 MFMA 32x32x16, 3 terms, stored split tiles)",
+            "flops_TFLOPs": achieved / 1e12})
+    if kind in ("c2", "c3") and args.compare_fp32:
+        log("[bench] plain FP32 path, same problem")
+        plain = Runner(L, torch, ctx, cfg, L.LD_F32, stored)
         pres, pms, _, _ = timed_steps(plain, 1, 0, stream, torch)
         pv = len(cfg.orders) / (pms / 1e3)
         line["plain_fp32"] = {"value": pv, "ms_per_step": pms,

@@ -55,10 +55,11 @@ typedef enum { LD_RBF = 0, LD_MATERN52 = 1 } ld_kernel;
  * and log det P are FP64 in every mode.
  *  LD_F64  FP64 products (FP64 matrix cores) and vectors.
  *  LD_F32  FP32 products (FP32 matrix cores) and vectors.
- *  LD_BF16 precision form, on the fly only: kernel values and distances in
- *          FP32, each operand split into bf16 hi + lo parts, products
- *          hi*hi + hi*lo + lo*hi on BF16 matrix cores with FP32
- *          accumulation; vectors FP32 (vector buffers use FP32). */
+ *  LD_BF16 precision form: kernel values and distances in FP32, each
+ *          operand split into bf16 hi + lo parts, products hi*hi + hi*lo +
+ *          lo*hi on BF16 matrix cores with FP32 accumulation; vectors FP32
+ *          (vector buffers use FP32).  On the fly, or from M stored as split
+ *          BF16 tiles (LD_TILED only, see kernel_materialize). */
 typedef enum { LD_F64 = 0, LD_F32 = 1, LD_BF16 = 2 } ld_precision;
 
 /* The matrix M = K(X, X) + noise * I (Section 3 kernels; formulas are the
@@ -74,8 +75,9 @@ typedef struct {
   double noise;           /* noise variance added to the diagonal, >= 0 */
   int32_t precision;      /* ld_precision */
   const void* M_stored;   /* device matrix M (FP64 for LD_F64, FP32 for LD_F32,
-                             noise included) in layout `layout`, or NULL to
-                             generate kernel entries on the fly from X */
+                             split-BF16 tiles for LD_BF16; noise included) in
+                             layout `layout`, or NULL to generate kernel
+                             entries on the fly from X */
   int32_t layout;         /* ld_layout of M_stored (ignored when it is NULL) */
 } ld_operator;
 
@@ -153,7 +155,12 @@ ld_status kernel_matmat(ld_ctx* ctx, const ld_operator* op, const void* V, int64
 
 /* Write M = K + noise I (device, ld_stored_elements(n, op->layout) elements,
  * FP64 for LD_F64, FP32 for LD_F32) in op->layout so that it can be passed
- * back as op->M_stored.  op->M_stored is ignored.  LD_TILED requires LD_F32.
+ * back as op->M_stored.  op->M_stored is ignored.  LD_TILED requires LD_F32
+ * or LD_BF16.  With LD_BF16 (LD_TILED only) the buffer has the same size in
+ * bytes as the FP32 one and holds K - variance I (zero diagonal): each
+ * 128 x 32 tile holds the 4096 values hi = bf16(m) (row-major inside the tile)
+ * followed by the 4096 values bf16(m - hi), m the FP32 entry; the products add
+ * (variance + noise) V in FP32, so the diagonal carries no BF16 rounding.
  * Asynchronous. */
 ld_status kernel_materialize(ld_ctx* ctx, const ld_operator* op, void* M_out);
 

@@ -115,12 +115,12 @@ ld_status check_operator(const ld_operator* op) {
     return fail(LD_EINVAL, "noise must be finite and >= 0");
   if (op->precision != LD_F64 && op->precision != LD_F32 && op->precision != LD_BF16)
     return fail(LD_EINVAL, "precision must be LD_F64, LD_F32 or LD_BF16");
-  if (op->precision == LD_BF16 && op->M_stored)
-    return fail(LD_EINVAL, "LD_BF16 generates the kernel on the fly (M_stored must be NULL)");
   if (op->layout != LD_ROW_MAJOR && op->layout != LD_TILED)
     return fail(LD_EINVAL, "layout must be LD_ROW_MAJOR or LD_TILED");
-  if (op->layout == LD_TILED && op->precision != LD_F32)
-    return fail(LD_EINVAL, "LD_TILED storage is FP32 only");
+  if (op->precision == LD_BF16 && op->M_stored && op->layout != LD_TILED)
+    return fail(LD_EINVAL, "a stored LD_BF16 matrix must use the LD_TILED layout");
+  if (op->layout == LD_TILED && op->M_stored && op->precision == LD_F64)
+    return fail(LD_EINVAL, "LD_TILED storage is FP32 or split BF16");
   return LD_OK;
 }
 
@@ -210,7 +210,9 @@ __global__ void k_d_and_inv(const double* __restrict__ U, const double* __restri
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     double dm = diag_const;
     const int64_t ii = layout == LD_TILED ? tiled_index(i, i, n) : i * n + i;
-    if (Mst) dm = mprec == LD_F64 ? ((const double*)Mst)[ii] : (double)((const float*)Mst)[ii];
+    if (Mst && mprec != LD_BF16) {  // split-BF16 tiles store K - variance I: diag is diag_const
+      dm = mprec == LD_F64 ? ((const double*)Mst)[ii] : (double)((const float*)Mst)[ii];
+    }
     double low = 0.0;
     for (int j = 0; j < rank; ++j) {
       const double u = U[i * rank + j];
@@ -584,7 +586,11 @@ ld_status kernel_materialize(ld_ctx* ctx, const ld_operator* op, void* M_out) {
   LD_TRY(check_ctx(ctx));
   LD_TRY(check_operator(op));
   if (!M_out) return fail(LD_EINVAL, "M_out is NULL");
-  launch_materialize(ctx->stream, make_kparams(*op), op->X, op->n, op->d, is_f64(op), op->layout,
+  if (op->precision == LD_BF16 && op->layout != LD_TILED)
+    return fail(LD_EINVAL, "a stored LD_BF16 matrix must use the LD_TILED layout");
+  if (op->precision == LD_F64 && op->layout == LD_TILED)
+    return fail(LD_EINVAL, "LD_TILED storage is FP32 or split BF16");
+  launch_materialize(ctx->stream, make_kparams(*op), op->X, op->n, op->d, op->precision, op->layout,
                      M_out);
   LD_HIP(hipGetLastError());
   return LD_OK;

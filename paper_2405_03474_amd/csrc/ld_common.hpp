@@ -142,13 +142,14 @@ struct MatmatArgs {
   double* dots = nullptr;    // optional
   int* dot_blocks = nullptr;
   bool timed = false;        // record events around the product kernel (ctx->timing)
-  bool bf16 = false;         // FP32 path: split-BF16 matrix-core product on the fly
+  bool bf16 = false;         // FP32 path: split-BF16 matrix-core product (on the fly, or
+                             // from stored split-BF16 LD_TILED tiles)
 };
 ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a);
 size_t matmat_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int64_t s);
 constexpr int kEpiRows = 128;  // rows per epilogue block (dot partial granularity)
 void launch_materialize(hipStream_t st, const KParams& kp, const double* X, int64_t n, int d,
-                        bool f64, int layout, void* M);
+                        int precision, int layout, void* M);
 
 // Element (i, k) of a stored matrix in LD_TILED layout (128 x 32 tiles).
 constexpr int kTileRows = 128;

@@ -531,6 +531,153 @@ __device__ __forceinline__ void f16_compute(const __bf16* __restrict__ bh,
   }
 }
 
+// Stored split-BF16 K - variance I (LD_TILED, hi and lo planes per tile):
+// the product takes the three terms hi*hi + hi*lo + lo*hi on BF16 matrix
+// cores with FP32 accumulation like the on-the-fly form, reading as many
+// bytes as FP32 storage with a sixth of its matrix-core time, so it is bound
+// by HBM; the epilogue adds (variance + noise) V in FP32.  The diagonal is
+// kept out of the split because its rounding error would be the same in
+// every row and, multiplied by tr(M^-1) ~ n / noise, would shift log det.  Stage = one 128 x 32 tile (both
+// planes, 16 KB) and a 32 x 32 NB block of V split in the loader; in k-step q
+// lane half h supplies k = 16 q + 8 h + j (j < 8) for both operands.  A is
+// kept row-major (rows padded to 40 bf16), B transposed (k contiguous).
+constexpr int S16 = BK + 8;  // bf16 row stride of the A planes and of transposed B
+
+template <int NB>
+struct St16Tile {
+  u32x4 ah[2], al[2];  // 2 x 16 B of each plane per thread (128 x 32 bf16 = 512 x 16 B)
+  float v[4 * NB];     // pairs of consecutive k of one V column
+};
+
+template <int NB>
+__device__ __forceinline__ void st16_load(St16Tile<NB>& t, const __bf16* __restrict__ A,
+                                          const float* __restrict__ V, int64_t n, int64_t s,
+                                          int64_t tile, int64_t c0, int64_t k0, int tid) {
+  constexpr int NT = 32 * NB;
+  const u32x4* src = (const u32x4*)(A + tile * (2 * BM * BK));
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    t.ah[j] = __builtin_nontemporal_load(src + tid + 256 * j);
+    t.al[j] = __builtin_nontemporal_load(src + 512 + tid + 256 * j);
+  }
+#pragma unroll
+  for (int j = 0; j < 2 * NB; ++j) {
+    const int e = tid + 256 * j;
+    const int cc = e % NT, kp = e / NT;  // column, pair of k rows
+    const int64_t col = c0 + cc, kr = k0 + 2 * kp;
+    const bool cv = col < s;
+    t.v[2 * j] = (cv && kr < n) ? V[kr * s + col] : 0.f;
+    t.v[2 * j + 1] = (cv && kr + 1 < n) ? V[(kr + 1) * s + col] : 0.f;
+  }
+}
+
+template <int NB>
+__device__ __forceinline__ void st16_store(const St16Tile<NB>& t, __bf16* __restrict__ ah,
+                                           __bf16* __restrict__ al, __bf16* __restrict__ bh,
+                                           __bf16* __restrict__ bl, int tid) {
+  constexpr int NT = 32 * NB;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int c = tid + 256 * j;  // 16-byte chunk: row c / 4, bf16 columns 8 (c % 4) ..
+    const int off = (c >> 2) * S16 + 8 * (c & 3);
+    *(u32x4*)&ah[off] = t.ah[j];
+    *(u32x4*)&al[off] = t.al[j];
+  }
+#pragma unroll
+  for (int j = 0; j < 2 * NB; ++j) {
+    const int e = tid + 256 * j;
+    const int cc = e % NT, kp = e / NT;
+    uint32_t h, l;
+    split2(t.v[2 * j], t.v[2 * j + 1], h, l);
+    *(uint32_t*)&bh[cc * S16 + 2 * kp] = h;
+    *(uint32_t*)&bl[cc * S16 + 2 * kp] = l;
+  }
+}
+
+template <int NB>
+__device__ __forceinline__ void st16_compute(const __bf16* __restrict__ ah,
+                                             const __bf16* __restrict__ al,
+                                             const __bf16* __restrict__ bh,
+                                             const __bf16* __restrict__ bl, f32x16* acc, int wave,
+                                             int li, int lh) {
+#pragma unroll
+  for (int q = 0; q < BK / 16; ++q) {
+    const int aoff = (32 * wave + li) * S16 + 16 * q + 8 * lh;
+    const bf16x8 a_h = *(const bf16x8*)&ah[aoff];
+    const bf16x8 a_l = *(const bf16x8*)&al[aoff];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int boff = (nb * 32 + li) * S16 + 16 * q + 8 * lh;
+      const bf16x8 b_h = *(const bf16x8*)&bh[boff];
+      const bf16x8 b_l = *(const bf16x8*)&bl[boff];
+      acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_h, acc[nb], 0, 0, 0);
+      acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_l, acc[nb], 0, 0, 0);
+      acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_l, b_h, acc[nb], 0, 0, 0);
+    }
+  }
+}
+
+template <int NB>
+__global__ __launch_bounds__(256, 2) void k_mm16_st(const __bf16* __restrict__ A,
+                                                    const float* __restrict__ V,
+                                                    float* __restrict__ part, SK p) {
+  constexpr int NT = 32 * NB;
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM * S16];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM * S16];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[2][NT * S16];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[2][NT * S16];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, lh = lane >> 5;
+  const int64_t n = p.n, s = p.s;
+  const WGRange wr = wg_range(p, blockIdx.x);
+  int64_t u = wr.u;
+  const int64_t uend = wr.uend;
+  int seg = 0;
+  while (u < uend) {
+    const int64_t T = u / wr.Sx;
+    const int l0 = (int)(u - T * wr.Sx);
+    const int l1 = (int)((int64_t)wr.Sx < l0 + (uend - u) ? (int64_t)wr.Sx : l0 + (uend - u));
+    const int st0 = wr.sb + l0, st1 = wr.sb + l1;
+    const int64_t band = T % p.rt;
+    const int64_t c0 = (T / p.rt) * NT;
+    const int64_t tile0 = band * p.S;
+
+    f32x16 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
+
+    St16Tile<NB> ta, tb;
+    st16_load<NB>(ta, A, V, n, s, tile0 + st0, c0, (int64_t)st0 * BK, tid);
+    if (st0 + 1 < st1) st16_load<NB>(tb, A, V, n, s, tile0 + st0 + 1, c0, (int64_t)(st0 + 1) * BK, tid);
+    __syncthreads();  // the previous segment's last stage is done with both buffers
+    for (int st = st0; st < st1; st += 2) {
+      st16_store<NB>(ta, Ah[0], Al[0], Bh[0], Bl[0], tid);
+      __syncthreads();
+      if (st + 2 < st1) st16_load<NB>(ta, A, V, n, s, tile0 + st + 2, c0, (int64_t)(st + 2) * BK, tid);
+      st16_compute<NB>(Ah[0], Al[0], Bh[0], Bl[0], acc, wave, li, lh);
+      if (st + 1 >= st1) break;
+      st16_store<NB>(tb, Ah[1], Al[1], Bh[1], Bl[1], tid);
+      __syncthreads();
+      if (st + 3 < st1) st16_load<NB>(tb, A, V, n, s, tile0 + st + 3, c0, (int64_t)(st + 3) * BK, tid);
+      st16_compute<NB>(Ah[1], Al[1], Bh[1], Bl[1], acc, wave, li, lh);
+    }
+
+    float* dst = part + ((int64_t)blockIdx.x * p.J + seg) * (int64_t)(BM * NT);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 32 * wave + 8 * (r >> 2) + 4 * lh + (r & 3);
+        dst[row * NT + nb * 32 + li] = acc[nb][r];
+      }
+    ++seg;
+    u += st1 - st0;
+  }
+}
+
 template <int NB, int KIND, int DT>
 __global__ __launch_bounds__(256, 2) void k_mm16(const float* __restrict__ Xp, int d, float var,
                                                  float c, const float* __restrict__ V,
@@ -833,6 +980,40 @@ __global__ __launch_bounds__(256) void k_materialize(const double* __restrict__ 
   }
 }
 
+// LD_TILED with split BF16 (precision form, stored): per 128 x 32 tile the
+// 4096 high parts bf16(m) and then the 4096 low parts bf16(m - hi) of the FP32
+// entries m of K - variance I (zero diagonal), both row-major inside the
+// tile; padding is zero.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_materialize_tiled_bf16(const double* __restrict__ X,
+                                                                int64_t n, int d, double var,
+                                                                double c, double noise,
+                                                                int64_t total,
+                                                                __bf16* __restrict__ M) {
+  const int64_t kt = (n + kTileCols - 1) / kTileCols;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * 256) {
+    const int64_t tile = e / (kTileRows * kTileCols);
+    const int w = (int)(e % (kTileRows * kTileCols));
+    const int64_t i = (tile / kt) * kTileRows + w / kTileCols;
+    const int64_t k = (tile % kt) * kTileCols + w % kTileCols;
+    float out = 0.f;
+    if (i < n && k < n) {
+      double r2 = 0.0;
+      for (int dd = 0; dd < d; ++dd) {
+        const double df = X[i * d + dd] - X[k * d + dd];
+        r2 = fma(df, df, r2);
+      }
+      out = i == k ? 0.f : (float)kval64<KIND>(r2, var, c);  // diagonal added in FP32
+    }
+    const __bf16 hi = (__bf16)out;
+    const __bf16 lo = (__bf16)(out - (float)hi);
+    __bf16* t = M + tile * (2 * kTileRows * kTileCols);
+    t[w] = hi;
+    t[kTileRows * kTileCols + w] = lo;
+  }
+}
+
 // LD_TILED: walk the storage linearly (coalesced writes), zero the padding.
 template <int KIND>
 __global__ __launch_bounds__(256) void k_materialize_tiled(const double* __restrict__ X, int64_t n,
@@ -1067,7 +1248,12 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
     } else {
       const float* A = (const float*)a.A;
       const bool tiled = a.layout == LD_TILED;
-      if (NB == 2 && tiled)
+      if (a.bf16) {  // stored split-BF16 tiles
+        if (NB == 2)
+          hipLaunchKernelGGL((k_mm16_st<2>), grid, dim3(256), 0, st, (const __bf16*)a.A, V, P, pl.p);
+        else
+          hipLaunchKernelGGL((k_mm16_st<1>), grid, dim3(256), 0, st, (const __bf16*)a.A, V, P, pl.p);
+      } else if (NB == 2 && tiled)
         hipLaunchKernelGGL((k_mm32_st<2, true>), grid, dim3(256), 0, st, A, V, P, pl.p);
       else if (NB == 2)
         hipLaunchKernelGGL((k_mm32_st<2, false>), grid, dim3(256), 0, st, A, V, P, pl.p);
@@ -1079,8 +1265,9 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
     if (ev1) LD_HIP(hipEventRecord(ev1, st));
     const int64_t tiles = (int64_t)pl.p.rt * ((a.s + pl.NT - 1) / pl.NT);
     hipLaunchKernelGGL(k_epilogue<float>, dim3((unsigned)tiles), dim3(256), 0, st, P, pl.p, pl.NT,
-                       (float*)a.Y, V, fly ? a.kp.noise : 0.0, (const float*)a.X2, a.alpha2,
-                       a.dots);
+                       (float*)a.Y, V,
+                       fly ? a.kp.noise : (a.bf16 ? a.kp.variance + a.kp.noise : 0.0),
+                       (const float*)a.X2, a.alpha2, a.dots);
   }
   if (a.dot_blocks) *a.dot_blocks = pl.p.rt;
   LD_HIP(hipGetLastError());
@@ -1088,8 +1275,21 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
 }
 
 void launch_materialize(hipStream_t st, const KParams& kp, const double* X, int64_t n, int d,
-                        bool f64, int layout, void* M) {
+                        int precision, int layout, void* M) {
   const double c = kp.kind == LD_RBF ? kp.c_rbf : kp.c_mat;
+  const bool f64 = precision == LD_F64;
+  if (layout == LD_TILED && precision == LD_BF16) {
+    const int64_t total = stored_elements(n, LD_TILED);
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (kp.kind == LD_RBF)
+      hipLaunchKernelGGL((k_materialize_tiled_bf16<LD_RBF>), dim3((unsigned)blocks), dim3(256), 0,
+                         st, X, n, d, kp.variance, c, kp.noise, total, (__bf16*)M);
+    else
+      hipLaunchKernelGGL((k_materialize_tiled_bf16<LD_MATERN52>), dim3((unsigned)blocks), dim3(256),
+                         0, st, X, n, d, kp.variance, c, kp.noise, total, (__bf16*)M);
+    return;
+  }
   if (layout == LD_TILED) {
     const int64_t total = stored_elements(n, LD_TILED);
     int64_t blocks = (total + 255) / 256;

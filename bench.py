@@ -66,7 +66,7 @@ def log(*a):
 # rocprofv3 counter summaries; valid only while the kernel's source file is
 # byte-identical to the one profiled.
 PROFILED_TRAFFIC = {
-    "c2_matern_gm50k": ("profiles/c2_matern_gm50k_k_mm32_st.md",
+    "c2_matern_gm50k": ("profiles/c2_matern_gm50k_k_mm32_tf.md",
                         "paper_2405_03474_amd/csrc/matmat.hip"),
 }
 
@@ -554,7 +554,7 @@ def main():
     avg_ms = mm_ms / max(mm_calls, 1)
     achieved = (mm_flops / max(mm_calls, 1)) / (avg_ms / 1e3)
     peak = {L.LD_F32: PEAK["fp32"], L.LD_F64: PEAK["fp64"], L.LD_BF16: PEAK["bf16"]}[precision]
-    kname = {"c2": "k_mm32_st<2,tiled> (FP32 MFMA 32x32x2, stored tiled M)",
+    kname = {"c2": "k_mm32_tf<2> (FP32 MFMA 32x32x2, stored LD_TILED fragment tiles)",
              "c1": "k_mm64<fly> (FP64 MFMA 16x16x4, on the fly)",
              "c3": "k_mm16<fly> (split-BF16 MFMA 32x32x16, 3 terms, on the fly)"}[kind]
     traffic = profiled_traffic(cfg.name) if not args.n and precision == L.LD_F32 else None

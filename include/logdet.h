@@ -83,11 +83,15 @@ typedef struct {
 
 /* Storage layouts of a stored M.
  *  LD_ROW_MAJOR: n x n, row-major.
- *  LD_TILED (FP32 only): 128 x 32 tiles, each contiguous and row-major inside;
- *    tile (I, K) covers rows 128 I .. 128 I + 127 and columns 32 K .. 32 K + 31
- *    and starts at element (I * ceil(n/32) + K) * 4096, so a band of 128 rows
- *    is one contiguous stream.  Entries outside n x n are zero.  Element (i, k)
- *    sits at ((i/128) * ceil(n/32) + k/32) * 4096 + (i%128) * 32 + k%32. */
+ *  LD_TILED (FP32): 128 x 32 tiles, each contiguous; tile (I, K) covers rows
+ *    128 I .. 128 I + 127 and columns 32 K .. 32 K + 31 and starts at element
+ *    (I * ceil(n/32) + K) * 4096, so a band of 128 rows is one contiguous
+ *    stream.  Entries outside n x n are zero.  Inside a tile, entry (r, c)
+ *    (0 <= r < 128, 0 <= c < 32) sits at
+ *      (r/32)*1024 + ((c%16)/4)*256 + (c/16)*128 + (r%32)*4 + c%4,
+ *    the order in which the matrix-core A operand of 32-row slices is loaded
+ *    as 1 KB blocks.  (Stored split BF16 uses its own tile format, see
+ *    kernel_materialize.) */
 typedef enum { LD_ROW_MAJOR = 0, LD_TILED = 1 } ld_layout;
 
 /* Number of elements a stored M of order n occupies in `layout` (n^2 for

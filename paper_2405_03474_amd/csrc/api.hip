@@ -399,9 +399,11 @@ ld_status build_precond(ld_ctx* ctx, const ld_operator* op, int rank, int oversa
   P->rank = rank;
   P->device = ctx->device;
   const size_t nl = (size_t)n * rank;
+  P->rp32 = (rank + 31) / 32 * 32;
+  const size_t nlp = (size_t)n * P->rp32;
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  const size_t bytes = al(nl * 8) * 2 + al((size_t)rank * 8) + al((size_t)n * 8) * 2 + al(nl * 4) +
-                       al((size_t)n * 4);
+  const size_t bytes = al(nl * 8) * 2 + al((size_t)rank * 8) + al((size_t)n * 8) * 2 +
+                       al(nlp * 4) + al((size_t)n * 4);
   void* blk = nullptr;
   if (hipMalloc(&blk, bytes) != hipSuccess) {
     (void)hipGetLastError();
@@ -415,7 +417,7 @@ ld_status build_precond(ld_ctx* ctx, const ld_operator* op, int rank, int oversa
   P->lam = (double*)c; c += al((size_t)rank * 8);
   P->D = (double*)c; c += al((size_t)n * 8);
   P->Dinv64 = (double*)c; c += al((size_t)n * 8);
-  P->F32 = (float*)c; c += al(nl * 4);
+  P->F32 = (float*)c; c += al(nlp * 4);
   P->Dinv32 = (float*)c;
 
   auto bail = [&](ld_status s_) {
@@ -448,7 +450,7 @@ ld_status build_precond(ld_ctx* ctx, const ld_operator* op, int rank, int oversa
   // F = D^-1 U R^-1  (= D^-1 U L^-T with L = R^T)
   launch_tri_inv_upper(st, G, rank, Rinv);
   launch_gemm64(st, P->U, Rinv, rank, P->Dinv64, n, rank, rank, P->F64);
-  launch_convert_f64_to_f32(st, P->F64, P->F32, (int64_t)nl);
+  launch_pitch_f32(st, P->F64, n, rank, P->rp32, P->F32);
   launch_convert_f64_to_f32(st, P->Dinv64, P->Dinv32, n);
   if (hipGetLastError() != hipSuccess) return bail(fail(LD_EHIP, "kernel launch failed"));
   if (hipMemcpyAsync(ctx->pinned, parts, 3 * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||

@@ -92,8 +92,9 @@ struct ld_precond {
   double* D = nullptr;       // n
   double* F64 = nullptr;     // n x rank : D^-1 U L^-T
   double* Dinv64 = nullptr;  // n
-  float* F32 = nullptr;
+  float* F32 = nullptr;      // n x rp32 : F rounded to FP32, zero columns beyond rank
   float* Dinv32 = nullptr;
+  int32_t rp32 = 0;          // rank rounded up to a multiple of 32
   void* block = nullptr;     // single allocation holding all of the above
 };
 
@@ -147,17 +148,30 @@ struct MatmatArgs {
 };
 ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a);
 size_t matmat_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int64_t s);
-constexpr int kEpiRows = 128;  // rows per epilogue block (dot partial granularity)
+constexpr int kEpiRows = 128;  // rows per output tile of the product
+constexpr int kEpiSplit = 4;   // epilogue workgroups (dot partial rows) per output tile
 void launch_materialize(hipStream_t st, const KParams& kp, const double* X, int64_t n, int d,
                         int precision, int layout, void* M);
 
-// Element (i, k) of a stored matrix in LD_TILED layout (128 x 32 tiles).
+// Element (i, k) of a stored FP32 matrix in LD_TILED layout: 128 x 32 tiles,
+// tile (I, K) at (I * ceil(n/32) + K) * 4096; inside a tile, element (r, c)
+// sits where lane r % 32 + 32 (c / 16) of wave r / 32 finds it when the wave
+// loads the tile as four consecutive 1 KB blocks q = (c % 16) / 4 of one
+// 16-byte chunk per lane (the A-operand order of v_mfma_f32_32x32x2f32 with
+// lane half h supplying columns 16 h .. 16 h + 15).
 constexpr int kTileRows = 128;
 constexpr int kTileCols = 32;
+__host__ __device__ inline int tile_offset(int r, int c) {
+  return (r >> 5) * 1024 + ((c & 15) >> 2) * 256 + (c >> 4) * 128 + (r & 31) * 4 + (c & 3);
+}
+__host__ __device__ inline void tile_coords(int w, int* r, int* c) {  // inverse of tile_offset
+  *r = (w >> 10) * 32 + ((w >> 2) & 31);
+  *c = ((w >> 7) & 1) * 16 + ((w >> 8) & 3) * 4 + (w & 3);
+}
 __host__ __device__ inline int64_t tiled_index(int64_t i, int64_t k, int64_t n) {
   const int64_t kt = (n + kTileCols - 1) / kTileCols;
   return ((i / kTileRows) * kt + k / kTileCols) * (kTileRows * kTileCols) +
-         (i % kTileRows) * kTileCols + (k % kTileCols);
+         tile_offset((int)(i % kTileRows), (int)(k % kTileCols));
 }
 inline int64_t stored_elements(int64_t n, int layout) {
   if (layout == LD_TILED)
@@ -215,6 +229,8 @@ void launch_scal_beta(hipStream_t st, const Scal& S, const double* d1, const dou
 ld_status woodbury_apply(ld_ctx* ctx, const ld_precond* P, bool f64, const void* R, int64_t s,
                          void* OUT);
 size_t woodbury_scratch_bytes(int64_t n, int rank, int64_t s);
+// F32 (n x rp, rp >= rank) = F64 (n x rank) rounded, zero columns rank .. rp - 1
+void launch_pitch_f32(hipStream_t st, const double* F64, int64_t n, int rank, int rp, float* F32);
 // Multi-shift PCG over the probe block Z (n x s) for shifts a_j (ascending,
 // shifts[0] seeds the Krylov space).  Returns z^T x_j (J x s, row j = shift j)
 // and z^T z per column in host vectors.

@@ -237,24 +237,14 @@ struct StTile {
   float b[4 * NB];    // 32 x 32*NB B tile: 1024*NB floats / 256 threads
 };
 
-template <int NB, bool TILED>
+template <int NB>
 __device__ __forceinline__ void st_load(StTile<NB>& t, const float* __restrict__ A,
                                         const float* __restrict__ V, int64_t n, int64_t s,
-                                        int64_t i0, int64_t c0, int64_t k0, int tid, bool a_vec,
-                                        int64_t kt) {
+                                        int64_t i0, int64_t c0, int64_t k0, int tid, bool a_vec) {
   constexpr int NT = 32 * NB;
   typedef float f32x4 __attribute__((ext_vector_type(4)));
-  if (TILED) {
-    // the stage is one contiguous, zero-padded 128 x 32 tile
-    const f32x4* src = (const f32x4*)(A + ((i0 / BM) * kt + k0 / BK) * (BM * BK));
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const f32x4 w = __builtin_nontemporal_load(src + tid + 256 * j);
-      t.a[j] = make_float4(w.x, w.y, w.z, w.w);
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < (TILED ? 0 : 4); ++j) {
+  for (int j = 0; j < 4; ++j) {
     const int e = tid + 256 * j;
     const int rr = e >> 3, kq = e & 7;
     const int64_t row = i0 + rr, kc = k0 + 4 * kq;
@@ -334,7 +324,7 @@ __device__ __forceinline__ void st_compute(const float* __restrict__ as,
       acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t], b[nb][t], acc[nb], 0, 0, 0);
 }
 
-template <int NB, bool TILED>
+template <int NB>
 __global__ __launch_bounds__(256, 2) void k_mm32_st(const float* __restrict__ A,
                                                     const float* __restrict__ V,
                                                     float* __restrict__ part, SK p) {
@@ -369,22 +359,149 @@ __global__ __launch_bounds__(256, 2) void k_mm32_st(const float* __restrict__ A,
 
     // two register stages in flight: tiles st+1 and st+2 load while st computes
     StTile<NB> ta, tb;
-    st_load<NB, TILED>(ta, A, V, n, s, i0, c0, (int64_t)st0 * BK, tid, a_vec, p.S);
+    st_load<NB>(ta, A, V, n, s, i0, c0, (int64_t)st0 * BK, tid, a_vec);
     if (st0 + 1 < st1)
-      st_load<NB, TILED>(tb, A, V, n, s, i0, c0, (int64_t)(st0 + 1) * BK, tid, a_vec, p.S);
+      st_load<NB>(tb, A, V, n, s, i0, c0, (int64_t)(st0 + 1) * BK, tid, a_vec);
     __syncthreads();  // the previous segment's last stage is done with both buffers
     for (int st = st0; st < st1; st += 2) {
       st_store<NB>(ta, As[0], Bt[0], tid);
       __syncthreads();
       if (st + 2 < st1)
-        st_load<NB, TILED>(ta, A, V, n, s, i0, c0, (int64_t)(st + 2) * BK, tid, a_vec, p.S);
+        st_load<NB>(ta, A, V, n, s, i0, c0, (int64_t)(st + 2) * BK, tid, a_vec);
       st_compute<NB>(As[0], Bt[0], acc, wave, li, lh);
       if (st + 1 >= st1) break;
       st_store<NB>(tb, As[1], Bt[1], tid);
       __syncthreads();
       if (st + 3 < st1)
-        st_load<NB, TILED>(tb, A, V, n, s, i0, c0, (int64_t)(st + 3) * BK, tid, a_vec, p.S);
+        st_load<NB>(tb, A, V, n, s, i0, c0, (int64_t)(st + 3) * BK, tid, a_vec);
       st_compute<NB>(As[1], Bt[1], acc, wave, li, lh);
+    }
+
+    float* dst = part + ((int64_t)blockIdx.x * p.J + seg) * (int64_t)(BM * NT);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 32 * wave + 8 * (r >> 2) + 4 * lh + (r & 3);
+        dst[row * NT + nb * 32 + li] = acc[nb][r];
+      }
+    ++seg;
+    u += st1 - st0;
+  }
+}
+
+// ------------------------------------- FP32 stored, LD_TILED fragment tiles --
+// The fragment order of LD_TILED tiles (tile_offset) lets each wave load its
+// 32 rows x 32 k of a stage straight into the registers that feed
+// v_mfma_f32_32x32x2f32: four 16-byte loads per lane, each one coalesced
+// 1 KB block, no LDS round trip (the rows of A are private to the wave).  A
+// is fetched two stages ahead.  B (a 32 x NT block of V, shared by the four
+// waves) is loaded one stage ahead into registers and kept transposed in a
+// double-buffered LDS tile as in k_mm32_st, one barrier per stage.  Lane half
+// h supplies k = 16 h + t in MFMA step t for both operands.
+template <int NB>
+__global__ __launch_bounds__(256, 2) void k_mm32_tf(const float* __restrict__ A,
+                                                    const float* __restrict__ V,
+                                                    float* __restrict__ part, SK p) {
+  constexpr int NT = 32 * NB;
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  __shared__ __attribute__((aligned(16))) float Bt[2][NT * ST_AS];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, lh = lane >> 5;
+  const int64_t n = p.n, s = p.s;
+
+  const WGRange wr = wg_range(p, blockIdx.x);
+  int64_t u = wr.u;
+  const int64_t uend = wr.uend;
+  int seg = 0;
+  while (u < uend) {
+    const int64_t T = u / wr.Sx;
+    const int l0 = (int)(u - T * wr.Sx);
+    const int l1 = (int)((int64_t)wr.Sx < l0 + (uend - u) ? (int64_t)wr.Sx : l0 + (uend - u));
+    const int st0 = wr.sb + l0, st1 = wr.sb + l1;
+    const int rtile = (int)(T % p.rt);
+    const int64_t c0 = (T / p.rt) * NT;
+    // this wave's quarter of tile (rtile, 0); stage st is st * 4096 floats further
+    const f32x4* abase = (const f32x4*)(A + (int64_t)rtile * p.S * (BM * BK) + wave * 1024) + lane;
+
+    f32x16 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
+
+    f32x4 aq[2][4];
+    float bq[4 * NB];
+    auto load_a = [&](int st, f32x4* dst) {
+      const f32x4* src = abase + (int64_t)st * (BM * BK / 4);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dst[q] = __builtin_nontemporal_load(src + 64 * q);
+    };
+    auto load_b = [&](int st) {
+      const int64_t k0 = (int64_t)st * BK;
+#pragma unroll
+      for (int j = 0; j < 4 * NB; ++j) {
+        const int e = tid + 256 * j;
+        const int64_t kr = k0 + e / NT, col = c0 + e % NT;
+        bq[j] = (kr < n && col < s) ? V[kr * s + col] : 0.f;
+      }
+    };
+    auto store_b = [&](float* bt) {
+#pragma unroll
+      for (int j = 0; j < 4 * NB; ++j) {
+        const int e = tid + 256 * j;
+        bt[(e % NT) * ST_AS + e / NT] = bq[j];
+      }
+    };
+
+    load_a(st0, aq[0]);
+    if (st0 + 1 < st1) load_a(st0 + 1, aq[1]);
+    load_b(st0);
+    __syncthreads();  // the previous segment is done with both B buffers
+    store_b(Bt[0]);
+    if (st0 + 1 < st1) load_b(st0 + 1);
+    __syncthreads();
+    for (int st = st0; st < st1; st += 2) {
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const int cur = st + d;
+        if (cur < st1) {
+          const float* bt = Bt[(cur - st0) & 1];
+          float b[NB][16];
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const float4* bp = (const float4*)&bt[(nb * 32 + li) * ST_AS + lh * 16];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const float4 v = bp[q];
+              b[nb][4 * q + 0] = v.x;
+              b[nb][4 * q + 1] = v.y;
+              b[nb][4 * q + 2] = v.z;
+              b[nb][4 * q + 3] = v.w;
+            }
+          }
+          float a[16];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            a[4 * q + 0] = aq[d][q].x;
+            a[4 * q + 1] = aq[d][q].y;
+            a[4 * q + 2] = aq[d][q].z;
+            a[4 * q + 3] = aq[d][q].w;
+          }
+          if (cur + 2 < st1) load_a(cur + 2, aq[d]);
+          // stage cur + 1 into the other buffer (last read in stage cur - 1,
+          // fenced by the barrier that ended it)
+          if (cur + 1 < st1) store_b(Bt[(cur + 1 - st0) & 1]);
+          if (cur + 2 < st1) load_b(cur + 2);
+#pragma unroll
+          for (int t = 0; t < 16; ++t)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+              acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t], b[nb][t], acc[nb], 0, 0, 0);
+          __syncthreads();
+        }
+      }
     }
 
     float* dst = part + ((int64_t)blockIdx.x * p.J + seg) * (int64_t)(BM * NT);
@@ -887,8 +1004,10 @@ __global__ __launch_bounds__(256, 2) void k_mm64(const double* __restrict__ A,
 }
 
 // --------------------------------------------------------------- epilogue --
-// One workgroup per output tile: Y = sum of the tile's partial slots
-// (+ noise * V on the fly) (+ alpha2 * X2); optional dots[rtile][c].
+// Four workgroups per output tile, one per 32-row quarter (blockIdx.y):
+// Y = sum of the tile's partial slots in slot order (+ noise * V on the fly)
+// (+ alpha2 * X2); optional dots[4 rtile + quarter][c].  Each thread keeps
+// up to eight elements, so a slot's loads are issued together.
 template <typename T>
 __global__ __launch_bounds__(256) void k_epilogue(const T* __restrict__ part, SK p, int NT,
                                                   T* __restrict__ Y, const T* __restrict__ V,
@@ -899,6 +1018,7 @@ __global__ __launch_bounds__(256) void k_epilogue(const T* __restrict__ part, SK
   __shared__ int nslot;
   const int tid = threadIdx.x;
   const int64_t Tt = blockIdx.x;
+  const int quarter = blockIdx.y;
   const int rtile = (int)(Tt % p.rt);
   const int64_t c0 = (Tt / p.rt) * NT;
   const int64_t i0 = (int64_t)rtile * BM;
@@ -929,17 +1049,32 @@ __global__ __launch_bounds__(256) void k_epilogue(const T* __restrict__ part, SK
   __syncthreads();
   const int ns = nslot;
   const int col = tid % NT;  // 256 is a multiple of NT
+  const int cnt = (BM / kEpiSplit) * NT;  // elements of the quarter (<= 8 per thread)
+  const int e0 = quarter * cnt;
+  double sum[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) sum[j] = 0.0;
+  for (int q = 0; q < ns; ++q) {
+    const T* src = part + slot[q] + e0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = tid + 256 * j;
+      if (e < cnt) sum[j] += (double)src[e];
+    }
+  }
   double dacc = 0.0;
-  for (int e = tid; e < BM * NT; e += 256) {
-    const int row = e / NT;
-    double sum = 0.0;
-    for (int q = 0; q < ns; ++q) sum += (double)part[slot[q] + e];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int e = tid + 256 * j;
+    if (e >= cnt) continue;
+    const int row = (e0 + e) / NT;
     const int64_t i = i0 + row, c = c0 + col;
     if (i < p.n && c < p.s) {
       const int64_t off = i * p.s + c;
-      if (noise != 0.0) sum += noise * (double)V[off];
-      if (X2) sum += alpha2 * (double)X2[off];
-      const T y = (T)sum;
+      double v = sum[j];
+      if (noise != 0.0) v += noise * (double)V[off];
+      if (X2) v += alpha2 * (double)X2[off];
+      const T y = (T)v;
       Y[off] = y;
       if (dots) dacc += (double)V[off] * (double)y;
     }
@@ -951,7 +1086,7 @@ __global__ __launch_bounds__(256) void k_epilogue(const T* __restrict__ part, SK
       double t = 0.0;
       for (int q = tid; q < 256; q += NT) t += red[q];
       const int64_t c = c0 + tid;
-      if (c < p.s) dots[(int64_t)rtile * p.s + c] = t;
+      if (c < p.s) dots[((int64_t)rtile * kEpiSplit + quarter) * p.s + c] = t;
     }
   }
 }
@@ -1014,7 +1149,8 @@ __global__ __launch_bounds__(256) void k_materialize_tiled_bf16(const double* __
   }
 }
 
-// LD_TILED: walk the storage linearly (coalesced writes), zero the padding.
+// LD_TILED (FP32, fragment order inside the tile: tile_offset): walk the
+// storage linearly (coalesced writes), zero the padding.
 template <int KIND>
 __global__ __launch_bounds__(256) void k_materialize_tiled(const double* __restrict__ X, int64_t n,
                                                            int d, double var, double c,
@@ -1024,9 +1160,10 @@ __global__ __launch_bounds__(256) void k_materialize_tiled(const double* __restr
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * 256) {
     const int64_t tile = e / (kTileRows * kTileCols);
-    const int w = (int)(e % (kTileRows * kTileCols));
-    const int64_t i = (tile / kt) * kTileRows + w / kTileCols;
-    const int64_t k = (tile % kt) * kTileCols + w % kTileCols;
+    int tr, tc;
+    tile_coords((int)(e % (kTileRows * kTileCols)), &tr, &tc);
+    const int64_t i = (tile / kt) * kTileRows + tr;
+    const int64_t k = (tile % kt) * kTileCols + tc;
     float out = 0.f;
     if (i < n && k < n) {
       double r2 = 0.0;
@@ -1224,7 +1361,7 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
     }
     if (ev1) LD_HIP(hipEventRecord(ev1, st));
     const int64_t tiles = (int64_t)pl.p.rt * ((a.s + pl.NT - 1) / pl.NT);
-    hipLaunchKernelGGL(k_epilogue<double>, dim3((unsigned)tiles), dim3(256), 0, st, P, pl.p, pl.NT,
+    hipLaunchKernelGGL(k_epilogue<double>, dim3((unsigned)tiles, kEpiSplit), dim3(256), 0, st, P, pl.p, pl.NT,
                        (double*)a.Y, V, fly ? a.kp.noise : 0.0, (const double*)a.X2, a.alpha2,
                        a.dots);
   } else {
@@ -1254,22 +1391,22 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
         else
           hipLaunchKernelGGL((k_mm16_st<1>), grid, dim3(256), 0, st, (const __bf16*)a.A, V, P, pl.p);
       } else if (NB == 2 && tiled)
-        hipLaunchKernelGGL((k_mm32_st<2, true>), grid, dim3(256), 0, st, A, V, P, pl.p);
+        hipLaunchKernelGGL((k_mm32_tf<2>), grid, dim3(256), 0, st, A, V, P, pl.p);
       else if (NB == 2)
-        hipLaunchKernelGGL((k_mm32_st<2, false>), grid, dim3(256), 0, st, A, V, P, pl.p);
+        hipLaunchKernelGGL((k_mm32_st<2>), grid, dim3(256), 0, st, A, V, P, pl.p);
       else if (tiled)
-        hipLaunchKernelGGL((k_mm32_st<1, true>), grid, dim3(256), 0, st, A, V, P, pl.p);
+        hipLaunchKernelGGL((k_mm32_tf<1>), grid, dim3(256), 0, st, A, V, P, pl.p);
       else
-        hipLaunchKernelGGL((k_mm32_st<1, false>), grid, dim3(256), 0, st, A, V, P, pl.p);
+        hipLaunchKernelGGL((k_mm32_st<1>), grid, dim3(256), 0, st, A, V, P, pl.p);
     }
     if (ev1) LD_HIP(hipEventRecord(ev1, st));
     const int64_t tiles = (int64_t)pl.p.rt * ((a.s + pl.NT - 1) / pl.NT);
-    hipLaunchKernelGGL(k_epilogue<float>, dim3((unsigned)tiles), dim3(256), 0, st, P, pl.p, pl.NT,
+    hipLaunchKernelGGL(k_epilogue<float>, dim3((unsigned)tiles, kEpiSplit), dim3(256), 0, st, P, pl.p, pl.NT,
                        (float*)a.Y, V,
                        fly ? a.kp.noise : (a.bf16 ? a.kp.variance + a.kp.noise : 0.0),
                        (const float*)a.X2, a.alpha2, a.dots);
   }
-  if (a.dot_blocks) *a.dot_blocks = pl.p.rt;
+  if (a.dot_blocks) *a.dot_blocks = pl.p.rt * kEpiSplit;
   LD_HIP(hipGetLastError());
   return LD_OK;
 }

@@ -32,6 +32,7 @@ namespace {
 constexpr int WT = 64;  // Woodbury tile (rows of F / columns of R)
 constexpr int FR = 32;  // rows of F and R staged per step
 typedef double f64x4w __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // t_partial[c] = F_c^T R_c over row chunk c (output rank x s, FP64) on FP64
 // matrix cores (v_mfma_f64_16x16x4f64, inputs widened exactly).  Workgroup:
@@ -227,6 +228,252 @@ __global__ __launch_bounds__(256) void k_wood_out(const T* __restrict__ F,
   }
 }
 
+// ------------------------------------------------- FP32 Woodbury apply --
+// The FP32 path keeps F as an n x rp matrix (rp = rank rounded up to a
+// multiple of 32, zero columns beyond rank) so that rank stages need no
+// bounds checks, and runs both products on FP32 matrix cores
+// (v_mfma_f32_32x32x2f32: lane l supplies A[l % 32][l / 32] and
+// B[l / 32][l % 32]; output register r of lane l is row 8 (r / 4) +
+// 4 (l / 32) + r % 4, column l % 32).  F^T R is summed over row chunks in
+// FP32 inside a chunk and in FP64 across chunks; t is rounded to FP32 for
+// the output step.
+constexpr int W32R = 128;  // rank rows of F^T R per workgroup / rows of OUT per workgroup
+constexpr int W32C = 64;   // columns of R per workgroup
+constexpr int W32K = 32;   // contraction indices per LDS stage
+
+// part[chunk] (rp x s, FP64) = F_chunk^T R_chunk.  Workgroup: one row chunk
+// (a multiple of 32 rows), 128 rank rows, 64 columns; wave w owns rank rows
+// 32 w .. 32 w + 31 and both 32-column blocks.  Stages of 32 rows of F
+// (16-byte row segments) and R go through LDS, the next stage prefetched in
+// registers.  MFMA step j contracts stage rows 2 j + l / 32.
+__global__ __launch_bounds__(256) void k_ft32(const float* __restrict__ F,
+                                              const float* __restrict__ R, int64_t n, int rp,
+                                              int64_t s, int64_t chunk,
+                                              double* __restrict__ part) {
+  __shared__ float Fs[W32K][W32R + 4];
+  __shared__ float Rs[W32K][W32C + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, h = lane >> 5;
+  const int l0 = blockIdx.y * W32R;
+  const int64_t c0 = (int64_t)blockIdx.z * W32C;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = r0 + chunk < n ? r0 + chunk : n;
+  f32x16 acc[2];
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[nb][r] = 0.0f;
+  float4 pf[4];
+  float pr[8];
+  auto fetch = [&](int64_t rb) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = tid + 256 * j;
+      const int rr = e >> 5, c4 = e & 31;  // 32 rows x 32 float4
+      const int64_t row = rb + rr;
+      const int col = l0 + 4 * c4;
+      pf[j] = (row < r1 && col < rp) ? *(const float4*)(F + row * rp + col)
+                                     : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = tid + 256 * j;
+      const int rr = e >> 6, cc = e & 63;  // 32 rows x 64 columns
+      const int64_t row = rb + rr;
+      pr[j] = (row < r1 && c0 + cc < s) ? R[row * s + c0 + cc] : 0.0f;
+    }
+  };
+  fetch(r0);
+  for (int64_t rb = r0; rb < r1; rb += W32K) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = tid + 256 * j;
+      *(float4*)&Fs[e >> 5][4 * (e & 31)] = pf[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = tid + 256 * j;
+      Rs[e >> 6][e & 63] = pr[j];
+    }
+    __syncthreads();
+    if (rb + W32K < r1) fetch(rb + W32K);
+#pragma unroll
+    for (int j = 0; j < W32K / 2; ++j) {
+      const int k = 2 * j + h;
+      const float a = Fs[k][32 * wave + li];
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, Rs[k][32 * nb + li], acc[nb], 0, 0, 0);
+    }
+  }
+  double* dst = part + (int64_t)blockIdx.x * rp * s;
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    const int64_t c = c0 + 32 * nb + li;
+    if (c >= s) continue;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int l = l0 + 32 * wave + 8 * (r >> 2) + 4 * h + (r & 3);
+      if (l < rp) dst[(int64_t)l * s + c] = (double)acc[nb][r];
+    }
+  }
+}
+
+// t32[e] = (float) sum over chunks of part[chunk][e], e < count, chunks in
+// order: four threads per element add contiguous quarters of the chunk list
+// (loads issued four at a time), then the quarters are added in order.
+__global__ __launch_bounds__(256) void k_sum32(const double* __restrict__ part, int chunks,
+                                               int64_t count, float* __restrict__ t32) {
+  __shared__ double red[4][64];
+  const int tid = threadIdx.x, q = tid >> 6, el = tid & 63;
+  const int64_t e = (int64_t)blockIdx.x * 64 + el;
+  const int cb = (int)(((int64_t)chunks * q) / 4), ce = (int)(((int64_t)chunks * (q + 1)) / 4);
+  double sum = 0.0;
+  if (e < count) {
+    int c = cb;
+    for (; c + 4 <= ce; c += 4) {
+      const double v0 = part[(int64_t)c * count + e];
+      const double v1 = part[(int64_t)(c + 1) * count + e];
+      const double v2 = part[(int64_t)(c + 2) * count + e];
+      const double v3 = part[(int64_t)(c + 3) * count + e];
+      sum += v0;
+      sum += v1;
+      sum += v2;
+      sum += v3;
+    }
+    for (; c < ce; ++c) sum += part[(int64_t)c * count + e];
+  }
+  red[q][el] = sum;
+  __syncthreads();
+  if (q == 0 && e < count) t32[e] = (float)(((red[0][el] + red[1][el]) + red[2][el]) + red[3][el]);
+}
+
+// OUT = Dinv .* R - F t32 on a 128-row x 64-column tile: wave w owns rows
+// 32 w .. 32 w + 31; each lane streams 16 consecutive rank indices of its
+// row of F per stage (four 16-byte loads, the next stage prefetched), the
+// stage's 32 x 64 block of t32 goes through LDS; MFMA step j contracts rank
+// index 16 (l / 32) + j.  Optional per-128-row-tile column dots:
+// dot1 = sum R .* OUT, dot2 = sum Z .* R.
+__global__ __launch_bounds__(256) void k_wood32(const float* __restrict__ F,
+                                                const float* __restrict__ Dinv,
+                                                const float* __restrict__ t32,
+                                                const float* __restrict__ R, int64_t n, int rp,
+                                                int64_t s, float* __restrict__ OUT,
+                                                const float* __restrict__ Z,
+                                                double* __restrict__ dot1,
+                                                double* __restrict__ dot2) {
+  __shared__ float Ts[W32K][W32C + 4];
+  __shared__ double red1[4][64][2];
+  __shared__ double red2[4][64][2];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, h = lane >> 5;
+  const int64_t i0 = (int64_t)blockIdx.x * W32R;
+  const int64_t c0 = (int64_t)blockIdx.y * W32C;
+  const int64_t myrow = i0 + 32 * wave + li;
+  const bool rowok = myrow < n;
+  const float* Frow = F + (rowok ? myrow : 0) * rp + 16 * h;
+  f32x16 acc[2];
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[nb][r] = 0.0f;
+  float4 fa[4], fn[4];
+  float pt[8];
+  auto fetch = [&](int k0, float4* dstv) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      dstv[j] = rowok ? *(const float4*)(Frow + k0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = tid + 256 * j;
+      const int kk = e >> 6, cc = e & 63;  // 32 rank indices x 64 columns
+      pt[j] = (c0 + cc < s) ? t32[(int64_t)(k0 + kk) * s + c0 + cc] : 0.0f;
+    }
+  };
+  fetch(0, fa);
+  for (int k0 = 0; k0 < rp; k0 += W32K) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = tid + 256 * j;
+      Ts[e >> 6][e & 63] = pt[j];
+    }
+    __syncthreads();
+    const bool more = k0 + W32K < rp;
+    if (more) fetch(k0 + W32K, fn);
+    float av[16];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      av[4 * j] = fa[j].x;
+      av[4 * j + 1] = fa[j].y;
+      av[4 * j + 2] = fa[j].z;
+      av[4 * j + 3] = fa[j].w;
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int k = 16 * h + j;
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[j], Ts[k][32 * nb + li], acc[nb], 0, 0, 0);
+    }
+    if (more) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) fa[j] = fn[j];
+    }
+  }
+  double d1[2] = {0.0, 0.0}, d2[2] = {0.0, 0.0};
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    const int64_t cc = c0 + 32 * nb + li;
+    if (cc >= s) continue;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t row = i0 + 32 * wave + 8 * (r >> 2) + 4 * h + (r & 3);
+      if (row >= n) continue;
+      const int64_t off = row * s + cc;
+      const float rv = R[off];
+      const float o = Dinv[row] * rv - acc[nb][r];
+      OUT[off] = o;
+      d1[nb] += (double)rv * (double)o;
+      if (dot2) d2[nb] += (double)Z[off] * (double)rv;
+    }
+  }
+  if (dot1) {
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      red1[wave][lane][nb] = d1[nb];
+      red2[wave][lane][nb] = d2[nb];
+    }
+    __syncthreads();
+    if (tid < W32C) {
+      const int nb = tid >> 5, l32 = tid & 31;
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < 4; ++w)
+        for (int g = 0; g < 2; ++g) {
+          a += red1[w][l32 + 32 * g][nb];
+          b += red2[w][l32 + 32 * g][nb];
+        }
+      const int64_t col = c0 + tid;
+      if (col < s) {
+        dot1[(int64_t)blockIdx.x * s + col] = a;
+        if (dot2) dot2[(int64_t)blockIdx.x * s + col] = b;
+      }
+    }
+  }
+}
+
+__global__ void k_pitch_f32(const double* __restrict__ in, int64_t n, int rank, int rp,
+                            float* __restrict__ out) {
+  const int64_t total = n * rp;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * 256) {
+    const int64_t row = i / rp;
+    const int k = (int)(i % rp);
+    out[i] = k < rank ? (float)in[row * rank + k] : 0.0f;
+  }
+}
+
 // ------------------------------------------------------------------ PCG --
 
 template <typename T>
@@ -255,16 +502,36 @@ __global__ __launch_bounds__(256) void k_colsum_seg(const double* __restrict__ p
   const int b0 = seg * chunk;
   const int b1 = b0 + chunk < nblk ? b0 + chunk : nblk;
   double acc = 0.0;
-  if (c < s)
-    for (int b = b0 + q; b < b1; b += 4) acc += parts[(int64_t)b * s + c];
+  if (c < s) {
+    int b = b0 + q;
+    for (; b + 12 < b1; b += 16) {
+      const double v0 = parts[(int64_t)b * s + c], v1 = parts[(int64_t)(b + 4) * s + c];
+      const double v2 = parts[(int64_t)(b + 8) * s + c], v3 = parts[(int64_t)(b + 12) * s + c];
+      acc += v0;
+      acc += v1;
+      acc += v2;
+      acc += v3;
+    }
+    for (; b < b1; b += 4) acc += parts[(int64_t)b * s + c];
+  }
   red[q][cl] = acc;
   __syncthreads();
   if (q == 0 && c < s) out[(int64_t)seg * s + c] = ((red[0][cl] + red[1][cl]) + red[2][cl]) + red[3][cl];
 }
 
+// sum over b of parts[b][c] in order b = 0, 1, ...; the loads are issued
+// eight at a time (the single-workgroup scalar kernels are latency bound)
 __device__ double block_colsum(const double* __restrict__ parts, int nblk, int64_t s, int64_t c) {
   double acc = 0.0;
-  for (int b = 0; b < nblk; ++b) acc += parts[(int64_t)b * s + c];
+  int b = 0;
+  for (; b + 8 <= nblk; b += 8) {
+    double v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = parts[(int64_t)(b + j) * s + c];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc += v[j];
+  }
+  for (; b < nblk; ++b) acc += parts[(int64_t)b * s + c];
   return acc;
 }
 
@@ -415,41 +682,82 @@ WoodPlan wood_plan(ld_ctx* ctx, int64_t n, int rank, int64_t s) {
   return w;
 }
 
-// P^-1 R into OUT; optional dots per 64-row tile.  Takes its scratch from the arena.
+// P^-1 R into OUT; optional column dots per row tile (64 rows in FP64, 128
+// rows in FP32: wood_dot_blocks).  Takes its scratch from the arena.
 template <typename T>
-ld_status wood_apply_t(ld_ctx* ctx, const T* F, const T* Dinv, int64_t n, int rank, const T* R,
-                       int64_t s, T* OUT, const T* Z, double* dot1, double* dot2) {
+ld_status wood_apply_t(ld_ctx* ctx, const ld_precond* P, const T* R, int64_t s, T* OUT,
+                       const T* Z, double* dot1, double* dot2);
+
+template <>
+ld_status wood_apply_t<double>(ld_ctx* ctx, const ld_precond* P, const double* R, int64_t s,
+                               double* OUT, const double* Z, double* dot1, double* dot2) {
+  const int64_t n = P->n;
+  const int rank = P->rank;
   WoodPlan w = wood_plan(ctx, n, rank, s);
   double* part = (double*)ctx->arena.take((size_t)w.chunks * rank * s * sizeof(double));
   double* t = (double*)ctx->arena.take((size_t)rank * s * sizeof(double));
   if (!part || !t) return fail(LD_ENOMEM, "woodbury: scratch arena too small");
   hipStream_t st = ctx->stream;
-  hipLaunchKernelGGL(k_ft_partial<T>, dim3((unsigned)w.chunks, w.ltiles, w.ctiles), dim3(256), 0, st,
-                     F, R, n, rank, s, w.chunk, part);
+  hipLaunchKernelGGL(k_ft_partial<double>, dim3((unsigned)w.chunks, w.ltiles, w.ctiles), dim3(256),
+                     0, st, P->F64, R, n, rank, s, w.chunk, part);
   hipLaunchKernelGGL(k_sum_parts, dim3(grid1((int64_t)rank * s)), dim3(256), 0, st, part,
                      (int)w.chunks, (int64_t)rank * s, t);
-  hipLaunchKernelGGL(k_wood_out<T>, dim3((unsigned)w.rtiles, w.ctiles), dim3(256), 0, st, F, Dinv, t,
-                     R, n, rank, s, OUT, Z, dot1, dot2);
+  hipLaunchKernelGGL(k_wood_out<double>, dim3((unsigned)w.rtiles, w.ctiles), dim3(256), 0, st,
+                     P->F64, P->Dinv64, t, R, n, rank, s, OUT, Z, dot1, dot2);
   LD_HIP(hipGetLastError());
   return LD_OK;
 }
 
+template <>
+ld_status wood_apply_t<float>(ld_ctx* ctx, const ld_precond* P, const float* R, int64_t s,
+                              float* OUT, const float* Z, double* dot1, double* dot2) {
+  const int64_t n = P->n;
+  const int rp = P->rp32;
+  const int ltiles = (rp + W32R - 1) / W32R;
+  const int ctiles = (int)((s + W32C - 1) / W32C);
+  int64_t target = (int64_t)ctx->num_cu * 2 / ((int64_t)ltiles * ctiles);
+  if (target < 1) target = 1;
+  int64_t chunk = (n + target - 1) / target;
+  chunk = (chunk + W32K - 1) / W32K * W32K;
+  const int64_t chunks = (n + chunk - 1) / chunk;
+  double* part = (double*)ctx->arena.take((size_t)chunks * rp * s * sizeof(double));
+  float* t32 = (float*)ctx->arena.take((size_t)rp * s * sizeof(float));
+  if (!part || !t32) return fail(LD_ENOMEM, "woodbury: scratch arena too small");
+  hipStream_t st = ctx->stream;
+  hipLaunchKernelGGL(k_ft32, dim3((unsigned)chunks, ltiles, ctiles), dim3(256), 0, st, P->F32, R,
+                     n, rp, s, chunk, part);
+  const int64_t count = (int64_t)rp * s;
+  hipLaunchKernelGGL(k_sum32, dim3((unsigned)((count + 63) / 64)), dim3(256), 0, st, part,
+                     (int)chunks, count, t32);
+  hipLaunchKernelGGL(k_wood32, dim3((unsigned)((n + W32R - 1) / W32R), ctiles), dim3(256), 0, st,
+                     P->F32, P->Dinv32, t32, R, n, rp, s, OUT, Z, dot1, dot2);
+  LD_HIP(hipGetLastError());
+  return LD_OK;
+}
+
+int64_t wood_dot_blocks(bool f64, int64_t n) { return f64 ? (n + WT - 1) / WT : (n + W32R - 1) / W32R; }
+
 }  // namespace
 
 size_t woodbury_scratch_bytes(int64_t n, int rank, int64_t s) {
-  // upper bound on chunks: num_cu * 4 <= 1024 (at most 256 CUs)
+  // upper bound on chunks: num_cu * 4 <= 1024 (at most 256 CUs); FP32 rank
+  // rows padded to a multiple of 32
   const int64_t chunks = 1024;
+  const int64_t rp = (rank + 31) / 32 * 32;
   (void)n;
-  return (size_t)(chunks + 1) * rank * s * sizeof(double) + 4096;
+  return (size_t)(chunks + 1) * rp * s * sizeof(double) + 4096;
+}
+
+void launch_pitch_f32(hipStream_t st, const double* F64, int64_t n, int rank, int rp, float* F32) {
+  hipLaunchKernelGGL(k_pitch_f32, dim3(grid1(n * rp)), dim3(256), 0, st, F64, n, rank, rp, F32);
 }
 
 ld_status woodbury_apply(ld_ctx* ctx, const ld_precond* P, bool f64, const void* R, int64_t s,
                          void* OUT) {
   if (f64)
-    return wood_apply_t<double>(ctx, P->F64, P->Dinv64, P->n, P->rank, (const double*)R, s,
-                                (double*)OUT, nullptr, nullptr, nullptr);
-  return wood_apply_t<float>(ctx, P->F32, P->Dinv32, P->n, P->rank, (const float*)R, s,
-                             (float*)OUT, nullptr, nullptr, nullptr);
+    return wood_apply_t<double>(ctx, P, (const double*)R, s, (double*)OUT, nullptr, nullptr,
+                                nullptr);
+  return wood_apply_t<float>(ctx, P, (const float*)R, s, (float*)OUT, nullptr, nullptr, nullptr);
 }
 
 // --------------------------------------------------------------- driver --
@@ -469,15 +777,13 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
   const int64_t n = base.n;
   const size_t vec = (size_t)n * s;
   hipStream_t st = ctx->stream;
-  const T* F = f64 ? (const T*)P->F64 : (const T*)P->F32;
-  const T* Dinv = f64 ? (const T*)P->Dinv64 : (const T*)P->Dinv32;
   T* r = (T*)ctx->arena.take(vec * sizeof(T));
   T* u = (T*)ctx->arena.take(vec * sizeof(T));
   T* p = (T*)ctx->arena.take(vec * sizeof(T));
   T* w = (T*)ctx->arena.take(vec * sizeof(T));
   T* q = (T*)ctx->arena.take(vec * sizeof(T));
-  const int64_t mrt = (n + 127) / 128;  // matmat dot blocks (128-row tiles)
-  const int64_t wrt = (n + 63) / 64;    // woodbury dot blocks (64-row tiles)
+  const int64_t mrt = (n + kEpiRows - 1) / kEpiRows * kEpiSplit;  // matmat dot blocks
+  const int64_t wrt = wood_dot_blocks(f64, n);  // woodbury dot blocks
   double* dwq = (double*)ctx->arena.take((size_t)mrt * s * sizeof(double));
   double* d1 = (double*)ctx->arena.take((size_t)wrt * s * sizeof(double));
   double* d2 = (double*)ctx->arena.take((size_t)wrt * s * sizeof(double));
@@ -520,7 +826,7 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
 
   // r = z, p = z; u = P^-1 r, w = u; rho0 = r^T u; z^T z
   hipLaunchKernelGGL(k_copy2<T>, dim3(grid1(vec)), dim3(256), 0, st, Z, r, p, (int64_t)vec);
-  LD_TRY(wood_apply_t<T>(ctx, F, Dinv, n, P->rank, r, s, u, Z, d1, d2));
+  LD_TRY(wood_apply_t<T>(ctx, P, r, s, u, Z, d1, d2));
   ctx->arena.top = mark;
   hipLaunchKernelGGL(k_copy2<T>, dim3(grid1(vec)), dim3(256), 0, st, u, w, (T*)nullptr,
                      (int64_t)vec);
@@ -552,7 +858,7 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
       hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(256), 0, st, S, sg1, kSeg, s);
       hipLaunchKernelGGL(k_update_r<T>, dim3(grid1(vec)), dim3(256), 0, st, r, q, S.alpha, n, s);
       ctx->arena.top = mark;
-      LD_TRY(wood_apply_t<T>(ctx, F, Dinv, n, P->rank, r, s, u, Z, d1, d2));
+      LD_TRY(wood_apply_t<T>(ctx, P, r, s, u, Z, d1, d2));
       hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, d1, (int)wrt, s, sg1);
       hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, d2, (int)wrt, s, sg2);
       hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(256), 0, st, S, sg1, sg2, kSeg, s, J, delta,

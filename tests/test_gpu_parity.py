@@ -87,10 +87,15 @@ def test_matmat_fp64(ctx, n, d, s, kind, stored):
 
 
 def untile(buf, n):
-    """Dense n x n view of an LD_TILED buffer (128 x 32 tiles, as documented in logdet.h)."""
+    """Dense n x n view of an FP32 LD_TILED buffer (128 x 32 tiles; inside a
+    tile entry (r, c) at (r/32)*1024 + ((c%16)/4)*256 + (c/16)*128 + (r%32)*4
+    + c%4, as documented in logdet.h)."""
     kt = -(-n // 32)
     rt = -(-n // 128)
-    t = buf.reshape(rt, kt, 128, 32).transpose(0, 2, 1, 3).reshape(rt * 128, kt * 32)
+    # inner index = ((((w*4 + q)*2 + h)*32 + l)*4 + e) with r = 32 w + l, c = 16 h + 4 q + e
+    t = buf.reshape(rt, kt, 4, 4, 2, 32, 4)            # I, K, w, q, h, l, e
+    t = t.transpose(0, 2, 5, 1, 4, 3, 6)               # I, w, l, K, h, q, e
+    t = t.reshape(rt * 128, kt * 32)
     assert np.all(t[n:, :] == 0) and np.all(t[:, n:] == 0)
     return t[:n, :n]
 

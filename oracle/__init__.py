@@ -16,4 +16,7 @@ Modules:
   precond   -- randomized truncated-SVD preconditioner (Section 2, Appendix)
   estimate  -- the estimator output of Algorithm 1 with exact shifted solves,
                exact Cholesky log det, and the bias decomposition
+  lanczos   -- Algorithm 1 as printed: t Lanczos steps per probe and the
+               shifted tridiagonal solves
+  mlp       -- the surrogate network: forward, chain-rule gradient, Adam, features
 """

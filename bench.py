@@ -97,12 +97,13 @@ def load_exact(name):
     return json.load(open(p)).get(name, {}).get("logdet")
 
 
-def cpu_baseline(cfg, sample_n: int):
+def cpu_baseline(cfg, sample_n: int, lanczos_steps: int = 0):
     """The oracle on a bounded sample: the same workload recipe at sample_n
     points, timed on this host; the rate is scaled to the full n by the
-    oracle's O(n^3) dense-factorization cost."""
+    oracle's O(n^3) dense-factorization cost.  With lanczos_steps the oracle
+    of Algorithm 1 as printed (t Lanczos steps per probe) is timed instead."""
     from oracle import estimate as oest
-    from oracle import gp, precond
+    from oracle import gp, lanczos as olz, precond
     sub = cfg.with_n(sample_n, rank=min(cfg.rank, sample_n // 10))
     t0 = time.perf_counter()
     X = sub.X()
@@ -112,7 +113,10 @@ def cpu_baseline(cfg, sample_n: int):
     Pd = P.dense()
     for k in cfg.orders:
         Z = oest.probes(sub.probe_seed + k, sub.n, sub.probes)
-        oest.estimate_dense(M, Pd, P.logdet, k, Z)
+        if lanczos_steps:
+            olz.estimate_lanczos(M, Pd, P.logdet, k, Z, lanczos_steps)
+        else:
+            oest.estimate_dense(M, Pd, P.logdet, k, Z)
     dt = time.perf_counter() - t0
     scale = (cfg.n / sample_n) ** 3
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -121,7 +125,10 @@ def cpu_baseline(cfg, sample_n: int):
         "unit": "log-det estimates/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": (f"oracle (FP64 numpy/scipy, dense Cholesky shifted solves) on the same recipe at "
+        "sample": (f"oracle (FP64 numpy/scipy, "
+                   + (f"{lanczos_steps} Lanczos steps per probe with dense P^-1 solves"
+                      if lanczos_steps else "dense Cholesky shifted solves")
+                   + ") on the same recipe at "
                    f"n={sample_n}, rank {sub.rank}: {len(cfg.orders)} estimates in {dt:.2f} s; "
                    f"scaled to n={cfg.n} by (n/{sample_n})^3"),
     }
@@ -130,8 +137,9 @@ def cpu_baseline(cfg, sample_n: int):
 class Runner:
     """One problem instance on the GPU in a given arithmetic."""
 
-    def __init__(self, L, torch, ctx, cfg, precision, stored):
+    def __init__(self, L, torch, ctx, cfg, precision, stored, lanczos_steps=0):
         self.L, self.torch, self.ctx, self.cfg = L, torch, ctx, cfg
+        self.lanczos_steps = lanczos_steps
         dev = torch.device("cuda:0")
         X = torch.as_tensor(cfg.X(), dtype=torch.float64, device=dev).contiguous()
         self.stored = stored
@@ -154,8 +162,12 @@ class Runner:
             op.M = self.Mbuf
         P = L.Precond(self.ctx, op, cfg.rank, cfg.oversample, cfg.power_iters, cfg.precond_seed)
         for k in cfg.orders:
-            res, per = L.logdet_estimate(self.ctx, op, P, k, cfg.probes, cfg.probe_seed + k,
-                                         self.tol, 5000)
+            if self.lanczos_steps:
+                res, per = L.logdet_estimate_lanczos(self.ctx, op, P, k, cfg.probes,
+                                                     cfg.probe_seed + k, self.lanczos_steps)
+            else:
+                res, per = L.logdet_estimate(self.ctx, op, P, k, cfg.probes, cfg.probe_seed + k,
+                                             self.tol, 5000)
             out[k] = res
         P.close()
         return out
@@ -501,6 +513,9 @@ def main():
     ap.add_argument("--c5-eval-n", type=int, default=5000)
     ap.add_argument("--c5-side", type=int, default=32)
     ap.add_argument("--c5-epochs", type=int, default=300)
+    ap.add_argument("--lanczos-steps", type=int, default=0,
+                    help="c1/c2/c3: run Algorithm 1 as printed (this many Lanczos steps per "
+                         "probe, tridiagonal solves) instead of the multi-shift CG to tolerance")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the workload, run one device-to-device copy of this many MiB "
                          "(the reference dispatch for HBM byte counters)")
@@ -532,7 +547,7 @@ def main():
     stream = torch.cuda.current_stream(0)
     copy_calibration(torch, args.copy_calibration_mib)
     ctx = L.Context(0, stream)
-    runner = Runner(L, torch, ctx, cfg, precision, stored)
+    runner = Runner(L, torch, ctx, cfg, precision, stored, args.lanczos_steps)
     results, ms_total, wall, (mm_ms, mm_calls, mm_flops, mm_bytes) = timed_steps(
         runner, args.steps, args.warmup, stream, torch)
 
@@ -575,7 +590,9 @@ def main():
                                if stored else "on_the_fly"),
                    "orders": list(cfg.orders), "probes": cfg.probes, "rank": cfg.rank,
                    "oversample": cfg.oversample, "power_iters": cfg.power_iters,
-                   "tol": runner.tol},
+                   "solver": ({"kind": "lanczos", "steps": args.lanczos_steps}
+                              if args.lanczos_steps else
+                              {"kind": "multishift_pcg", "tol": runner.tol})},
         "probe_solves_per_s": cfg.probes * n_est / (ms_total / 1e3),
         "iterations": {f"r{k}": last[k]["iterations"] for k in cfg.orders},
         "wall_s": wall, "accuracy": accuracy, "roofline": roofline,
@@ -591,7 +608,7 @@ def main():
             "flops_TFLOPs": achieved / 1e12})
     if kind in ("c2", "c3") and args.compare_fp32:
         log("[bench] plain FP32 path, same problem")
-        plain = Runner(L, torch, ctx, cfg, L.LD_F32, stored)
+        plain = Runner(L, torch, ctx, cfg, L.LD_F32, stored, args.lanczos_steps)
         pres, pms, _, _ = timed_steps(plain, 1, 0, stream, torch)
         pv = len(cfg.orders) / (pms / 1e3)
         line["plain_fp32"] = {"value": pv, "ms_per_step": pms,
@@ -599,7 +616,7 @@ def main():
         line["speedup_vs_plain_fp32"] = value / pv
     if kind == "c3" and args.check_fp64:
         log("[bench] FP64 reference run on the same probes")
-        ref = Runner(L, torch, ctx, cfg, L.LD_F64, False)
+        ref = Runner(L, torch, ctx, cfg, L.LD_F64, False, args.lanczos_steps)
         rres = ref.step()
         line["fp64_reference"] = {
             f"r{k}": {"logdet": rres[k]["logdet"],
@@ -610,7 +627,7 @@ def main():
         line["cpu_baseline"] = None
     else:
         log("[bench] cpu baseline (oracle) ...")
-        line["cpu_baseline"] = cpu_baseline(cfg, min(args.cpu_sample_n, cfg.n))
+        line["cpu_baseline"] = cpu_baseline(cfg, min(args.cpu_sample_n, cfg.n), args.lanczos_steps)
     print(json.dumps(line), flush=True)
     ctx.close()
 

@@ -217,6 +217,32 @@ ld_status logdet_estimate(ld_ctx* ctx, const ld_operator* op, const ld_precond* 
                           int32_t num_probes, uint64_t probe_seed, double tol, int32_t max_iters,
                           ld_result* out, double* per_probe);
 
+/* Largest number of Lanczos steps logdet_estimate_lanczos accepts. */
+#define LD_LANCZOS_MAX 128
+
+/* Algorithm 1 as printed (Section 2): s Rademacher probes from `probe_seed`;
+ * for each probe v, `steps` Lanczos steps on M P^-1 started at v, giving the
+ * tridiagonal T; for every pole a_j of r_k (Table 1) the system
+ * (T + a_j I) w_j = |v| e_1 solved by the Thomas algorithm; per-probe value
+ * t = b v^T v + sum_j c_j v^T Q^T w_j; the Hutchinson mean of t in FP64.
+ * The recurrence runs in the inner product x^T P^-1 y, in which M P^-1 is
+ * self-adjoint (|v|^2 = v^T P^-1 v; v^T Q^T w = sum_l (v^T q_l) w_l with
+ * Euclidean products), so `steps` Lanczos steps reproduce `steps` iterations
+ * of logdet_estimate's solver.  A probe whose recurrence reaches an
+ * invariant subspace (beta_l <= 1e-12 times its largest |alpha|) stops early
+ * with exact solves.  All probes run in lock step: one kernel-matrix product
+ * and one Woodbury apply per step.
+ *   P, k, num_probes, out, per_probe  as for logdet_estimate
+ *   steps      1 .. LD_LANCZOS_MAX (the paper uses 20)
+ * On return out->iterations = most steps any probe took, converged_cols =
+ * probes that stopped in an invariant subspace, rel_resid = the largest
+ * P^-1-norm residual of the smallest-shift system over |v|
+ * (beta_m |w_m| / |v|).  LD_ENOTSPD when a norm in the recurrence is
+ * negative or not finite (M or P not SPD).  Synchronizes. */
+ld_status logdet_estimate_lanczos(ld_ctx* ctx, const ld_operator* op, const ld_precond* P,
+                                  int32_t k, int32_t num_probes, uint64_t probe_seed,
+                                  int32_t steps, ld_result* out, double* per_probe);
+
 /* One problem of a batch: M = K(X, X) + noise * I as in ld_operator (always
  * on the fly, FP32 products), with its own preconditioner rank and seeds. */
 typedef struct {

@@ -22,6 +22,7 @@ LD_F64, LD_F32, LD_BF16 = 0, 1, 2
 LD_ROW_MAJOR, LD_TILED = 0, 1
 LD_BATCH_GRAPH, LD_BATCH_RETUNE, LD_BATCH_PRECOND_ONLY = 1, 2, 4
 LD_SUR_FEATURES, LD_SUR_WIDTH, LD_SUR_BINS = 38, 256, 32
+LD_LANCZOS_MAX = 128
 
 STATUS_NAMES = {0: "LD_OK", -1: "LD_EINVAL", -2: "LD_ENOTSPD", -3: "LD_ENOCONV", -4: "LD_EHIP",
                 -5: "LD_ENOMEM"}
@@ -31,7 +32,8 @@ EXPORTED = (
     "ld_stored_elements", "ld_rational_coeffs", "ld_fill_probes",
     "ld_fill_gaussian", "kernel_matmat", "kernel_materialize", "logdet_precond_build",
     "ld_precond_info", "ld_precond_export", "ld_precond_apply_inverse", "ld_precond_free",
-    "logdet_estimate", "logdet_estimate_batched", "ld_surrogate_param_count",
+    "logdet_estimate", "logdet_estimate_lanczos", "logdet_estimate_batched",
+    "ld_surrogate_param_count",
     "ld_surrogate_features", "ld_surrogate_create", "ld_surrogate_free", "ld_surrogate_set_scaling",
     "ld_surrogate_train_step", "ld_surrogate_gradient", "ld_surrogate_params",
     "ld_surrogate_predict",
@@ -107,6 +109,8 @@ def load():
         "ld_precond_free": (None, [vp]),
         "logdet_estimate": (i32, [vp, ctypes.POINTER(Operator), vp, i32, i32, u64, dbl, i32,
                                   ctypes.POINTER(Result), pd]),
+        "logdet_estimate_lanczos": (i32, [vp, ctypes.POINTER(Operator), vp, i32, i32, u64, i32,
+                                          ctypes.POINTER(Result), pd]),
         "logdet_estimate_batched": (i32, [vp, i32, ctypes.POINTER(Instance), i32, i32, i32, i32,
                                           dbl, i32, i32, ctypes.POINTER(Result), pd, pd, i32]),
         "ld_surrogate_param_count": (i64, []),
@@ -335,6 +339,23 @@ def logdet_estimate(ctx: Context, op: GPOperator, P: Precond | None, k: int, num
                                 num_probes, probe_seed, tol, max_iters, ctypes.byref(res),
                                 per.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     _check(st, allow=(LD_ENOCONV,) if allow_noconv else ())
+    out = res.as_dict()
+    out["status"] = STATUS_NAMES.get(st, st)
+    return out, per
+
+
+def logdet_estimate_lanczos(ctx: Context, op: GPOperator, P: Precond | None, k: int,
+                            num_probes: int, probe_seed: int, steps: int = 20):
+    """Algorithm 1 as printed (t = steps Lanczos steps per probe, tridiagonal
+    solves per pole).  Returns (result dict, per-probe values)."""
+    res = Result()
+    per = np.zeros(num_probes, dtype=np.float64)
+    cop = op.c_struct()
+    st = load().logdet_estimate_lanczos(ctx.handle, ctypes.byref(cop),
+                                        P.handle if P is not None else None, k, num_probes,
+                                        probe_seed, steps, ctypes.byref(res),
+                                        per.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    _check(st)
     out = res.as_dict()
     out["status"] = STATUS_NAMES.get(st, st)
     return out, per

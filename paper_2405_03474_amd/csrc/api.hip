@@ -648,75 +648,88 @@ void ld_precond_free(ld_precond* P) {
   delete P;
 }
 
-ld_status logdet_estimate(ld_ctx* ctx, const ld_operator* op, const ld_precond* P, int32_t k,
-                          int32_t num_probes, uint64_t probe_seed, double tol, int32_t max_iters,
-                          ld_result* out, double* per_probe) {
+namespace {
+
+Coef coef_of(const Rational& rf, int k) {
+  Coef cf{};
+  cf.b = rf.b;
+  cf.J = k;
+  for (int j = 0; j < k; ++j) {
+    cf.a[j] = rf.a[j];
+    cf.c[j] = rf.c[j];
+  }
+  return cf;
+}
+
+// Shared set-up of the single-problem estimators: validation, the default
+// preconditioner when P is NULL, the scratch arena, the points in the
+// path's precision and the Rademacher probe block (Algorithm 1 step 1).
+struct EstSetup {
+  Rational rf;
+  const ld_precond* P = nullptr;
+  ld_precond* own = nullptr;
+  bool f64 = false;
+  const void* Xp = nullptr;
+  void* Z = nullptr;
+  ~EstSetup() {
+    if (own) ld_precond_free(own);
+  }
+};
+
+ld_status est_setup(ld_ctx* ctx, const ld_operator* op, const ld_precond* P, int32_t k,
+                    int32_t num_probes, uint64_t probe_seed, size_t solver_bytes_extra,
+                    size_t (*solver_bytes)(ld_ctx*, bool, int64_t, int, int64_t, int), int arg,
+                    EstSetup& e) {
   LD_TRY(check_ctx(ctx));
   LD_TRY(check_operator(op));
-  if (!out) return fail(LD_EINVAL, "out is NULL");
-  Rational rf;
-  if (!rational_for(k, &rf)) return fail(LD_EINVAL, "k must be 1, 3 or 5");
+  if (!rational_for(k, &e.rf)) return fail(LD_EINVAL, "k must be 1, 3 or 5");
   if (num_probes < 1) return fail(LD_EINVAL, "num_probes must be >= 1");
-  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(LD_EINVAL, "tol must be finite and > 0");
-  if (max_iters < 1) return fail(LD_EINVAL, "max_iters must be >= 1");
   if (P && P->n != op->n) return fail(LD_EINVAL, "preconditioner size does not match the operator");
-  ld_precond* own = nullptr;
   if (!P) {
     int rank = (int)std::min<int64_t>(100, std::max<int64_t>(1, op->n / 10));
     int over = (int)std::min<int64_t>(10, op->n - rank);
-    LD_TRY(build_precond(ctx, op, rank, over, 2, probe_seed + 1, &own));
-    P = own;
+    LD_TRY(build_precond(ctx, op, rank, over, 2, probe_seed + 1, &e.own));
+    P = e.own;
   }
-  const bool f64 = is_f64(op);
+  e.P = P;
+  e.f64 = is_f64(op);
   const int64_t n = op->n, s = num_probes;
-  const int J = k;
-  const size_t es = f64 ? 8 : 4;
+  const size_t es = e.f64 ? 8 : 4;
   ctx->arena.reset();
-  ld_status st_ = ctx->arena.reserve((size_t)n * op->d * 4 + 512 + (size_t)n * s * es + 512 +
-                                     pcg_scratch_bytes(ctx, f64, n, P->rank, s, J));
-  if (st_ != LD_OK) {
-    if (own) ld_precond_free(own);
-    return st_;
-  }
+  LD_TRY(ctx->arena.reserve((size_t)n * op->d * 4 + 512 + (size_t)n * s * es + 512 +
+                            solver_bytes(ctx, e.f64, n, P->rank, s, arg) + solver_bytes_extra));
+  LD_TRY(path_points(ctx, op, &e.Xp));
+  e.Z = ctx->arena.take((size_t)n * s * es);
+  if (!e.Z) return fail(LD_ENOMEM, "scratch arena too small for probes");
+  launch_fill_rademacher(ctx->stream, stream_key(probe_seed, kStreamProbes), n, s, e.f64, e.Z);
+  LD_HIP(hipGetLastError());
+  return LD_OK;
+}
+
+}  // namespace
+
+ld_status logdet_estimate(ld_ctx* ctx, const ld_operator* op, const ld_precond* P, int32_t k,
+                          int32_t num_probes, uint64_t probe_seed, double tol, int32_t max_iters,
+                          ld_result* out, double* per_probe) {
+  if (!out) return fail(LD_EINVAL, "out is NULL");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(LD_EINVAL, "tol must be finite and > 0");
+  if (max_iters < 1) return fail(LD_EINVAL, "max_iters must be >= 1");
+  EstSetup e;
+  LD_TRY(est_setup(ctx, op, P, k, num_probes, probe_seed, 0, pcg_scratch_bytes, k, e));
+  const int64_t s = num_probes;
   auto t0 = std::chrono::steady_clock::now();
-  const void* Xp = nullptr;
-  void* Z = nullptr;
-  std::vector<double> ztx, ztz;
+  std::vector<double> t;
+  double mean = 0.0, se = 0.0;
   int iters = 0, conv = 0;
   double rr = 0.0;
   bool breakdown = false;
-  st_ = path_points(ctx, op, &Xp);
-  if (st_ == LD_OK) {
-    Z = ctx->arena.take((size_t)n * s * es);
-    if (!Z) st_ = fail(LD_ENOMEM, "scratch arena too small for probes");
-  }
-  if (st_ == LD_OK) {
-    launch_fill_rademacher(ctx->stream, stream_key(probe_seed, kStreamProbes), n, s, f64, Z);
-    MatmatArgs base = base_args(op, Xp);
-    st_ = multishift_pcg(ctx, f64, base, P, rf.a, J, Z, s, tol, max_iters, ztx, ztz, &iters, &conv,
-                         &rr, &breakdown);
-  }
-  const double logdet_P = P->logdet;
-  if (own) ld_precond_free(own);
-  if (st_ != LD_OK) return st_;
+  LD_TRY(multishift_pcg(ctx, e.f64, base_args(op, e.Xp), e.P, coef_of(e.rf, k), e.Z, s, tol,
+                        max_iters, t, &mean, &se, &iters, &conv, &rr, &breakdown));
   auto t1 = std::chrono::steady_clock::now();
-
-  // Hutchinson mean (Section 1) of t_i = b z^T z + sum_j c_j z^T x_j
-  std::vector<double> t(s);
-  double mean = 0.0;
-  for (int64_t c = 0; c < s; ++c) {
-    double v = rf.b * ztz[c];
-    for (int j = 0; j < J; ++j) v += rf.c[j] * ztx[(size_t)j * s + c];
-    t[c] = v;
-    mean += v;
-  }
-  mean /= (double)s;
-  double var = 0.0;
-  for (int64_t c = 0; c < s; ++c) var += (t[c] - mean) * (t[c] - mean);
   out->trace_term = mean;
-  out->logdet_P = logdet_P;
-  out->logdet = logdet_P + mean;
-  out->std_err = s > 1 ? std::sqrt(var / (double)(s - 1) / (double)s) : NAN;
+  out->logdet_P = e.P->logdet;
+  out->logdet = e.P->logdet + mean;
+  out->std_err = se;
   out->rel_resid = rr;
   out->seconds_solve = std::chrono::duration<double>(t1 - t0).count();
   out->iterations = iters;
@@ -727,6 +740,36 @@ ld_status logdet_estimate(ld_ctx* ctx, const ld_operator* op, const ld_precond* 
   if (breakdown)
     return fail(LD_ENOTSPD, "non-positive curvature or residual norm in the solver (M or P not SPD?)");
   if (conv < s) return fail(LD_ENOCONV, "max_iters reached before every probe converged");
+  return LD_OK;
+}
+
+ld_status logdet_estimate_lanczos(ld_ctx* ctx, const ld_operator* op, const ld_precond* P,
+                                  int32_t k, int32_t num_probes, uint64_t probe_seed,
+                                  int32_t steps, ld_result* out, double* per_probe) {
+  if (!out) return fail(LD_EINVAL, "out is NULL");
+  if (steps < 1 || steps > LD_LANCZOS_MAX)
+    return fail(LD_EINVAL, "steps must be in 1..LD_LANCZOS_MAX");
+  EstSetup e;
+  LD_TRY(est_setup(ctx, op, P, k, num_probes, probe_seed, 0, lanczos_scratch_bytes, steps, e));
+  const int64_t s = num_probes;
+  auto t0 = std::chrono::steady_clock::now();
+  LzOut o;
+  LD_TRY(lanczos_estimate(ctx, e.f64, base_args(op, e.Xp), e.P, coef_of(e.rf, k), e.Z, s, steps,
+                          o));
+  auto t1 = std::chrono::steady_clock::now();
+  out->trace_term = o.mean;
+  out->logdet_P = e.P->logdet;
+  out->logdet = e.P->logdet + o.mean;
+  out->std_err = o.stderr_;
+  out->rel_resid = o.resid;
+  out->seconds_solve = std::chrono::duration<double>(t1 - t0).count();
+  out->iterations = o.max_steps;
+  out->converged_cols = o.exact;
+  out->k = k;
+  out->num_probes = num_probes;
+  if (per_probe) std::memcpy(per_probe, o.per_probe.data(), (size_t)s * sizeof(double));
+  if (o.breakdown)
+    return fail(LD_ENOTSPD, "non-positive or non-finite norm in the Lanczos recurrence (M or P not SPD?)");
   return LD_OK;
 }
 

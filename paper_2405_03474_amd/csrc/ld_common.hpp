@@ -234,10 +234,33 @@ void launch_pitch_f32(hipStream_t st, const double* F64, int64_t n, int rank, in
 // Multi-shift PCG over the probe block Z (n x s) for shifts a_j (ascending,
 // shifts[0] seeds the Krylov space).  Returns z^T x_j (J x s, row j = shift j)
 // and z^T z per column in host vectors.
+// r_k(x) = b + sum_j c_j / (x + a_j) (Table 1), J = k poles, a ascending.
+struct Coef {
+  double b;
+  double a[5];
+  double c[5];
+  int J;
+};
 ld_status multishift_pcg(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precond* P,
-                         const double* shifts, int J, const void* Z, int64_t s, double tol,
-                         int max_iters, std::vector<double>& ztx, std::vector<double>& ztz,
+                         const Coef& cf, const void* Z, int64_t s, double tol, int max_iters,
+                         std::vector<double>& per_probe, double* mean, double* stderr_,
                          int* iterations, int* converged, double* rel_resid, bool* breakdown);
+// Hutchinson combination of z^T x_j (J x s) and z^T z (s), device buffers:
+// per-probe values (s) and [mean, standard error].
+ld_status hutchinson(ld_ctx* ctx, const double* ztx_dev, const double* ztz_dev, int64_t s,
+                     const Coef& cf, double* per_probe_dev, double* stats_dev);
+// Algorithm 1 as printed: t Lanczos steps per probe and tridiagonal solves.
+constexpr int kLzMax = LD_LANCZOS_MAX;
+struct LzOut {
+  std::vector<double> per_probe;
+  double mean = 0.0, stderr_ = 0.0, resid = 0.0;
+  int max_steps = 0;  // most steps any probe took
+  int exact = 0;      // probes whose recurrence ended in an invariant subspace
+  bool breakdown = false;
+};
+ld_status lanczos_estimate(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precond* P,
+                           const Coef& cf, const void* Z, int64_t s, int t, LzOut& out);
+size_t lanczos_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int rank, int64_t s, int t);
 size_t pcg_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int rank, int64_t s, int J);
 
 // batch.hip -- the whole estimator over `count` validated instances; shifts

@@ -760,6 +760,359 @@ ld_status woodbury_apply(ld_ctx* ctx, const ld_precond* P, bool f64, const void*
   return wood_apply_t<float>(ctx, P, (const float*)R, s, (float*)OUT, nullptr, nullptr, nullptr);
 }
 
+// ------------------------------------------------ Hutchinson combination --
+// Section 1 / the output of Algorithm 1: t_i = b z_i^T z_i + sum_j c_j
+// z_i^T x_ij per probe, then their mean and standard error, in FP64 and in a
+// fixed order (one workgroup).
+namespace {
+
+__global__ void k_hutchinson(const double* __restrict__ ztx, const double* __restrict__ ztz,
+                             int64_t s, Coef cf, double* __restrict__ per_probe,
+                             double* __restrict__ stats) {
+  for (int64_t c = threadIdx.x; c < s; c += blockDim.x) {
+    double v = cf.b * ztz[c];
+    for (int j = 0; j < cf.J; ++j) v += cf.c[j] * ztx[(int64_t)j * s + c];
+    per_probe[c] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mean = 0.0;
+    for (int64_t c = 0; c < s; ++c) mean += per_probe[c];
+    mean /= (double)s;
+    double var = 0.0;
+    for (int64_t c = 0; c < s; ++c) var += (per_probe[c] - mean) * (per_probe[c] - mean);
+    stats[0] = mean;
+    stats[1] = s > 1 ? sqrt(var / (double)(s - 1) / (double)s) : (double)NAN;
+  }
+}
+
+// ------------------------------------------------------------- Lanczos --
+// Algorithm 1 as printed (Section 2): t Lanczos steps on A = M P^-1 per probe
+// (all probes of the block in lock step), then for every pole a tridiagonal
+// solve (T + a_j I) w = |v| e_1 by the Thomas algorithm and the output
+// v^T Q^T w = sum_l (v^T q_l) w_l.  The recurrence runs in the inner product
+// <x, y> = x^T P^-1 y, in which M P^-1 is self-adjoint: the vectors q_l are
+// P^-1-orthonormal, q_1 = v / |v| with |v|^2 = v^T P^-1 v, so the right side
+// of the shifted systems is |v| e_1, and v^T q_l are Euclidean products
+// tracked as the recurrence runs (no Q is stored).  Per step:
+//   y = M u_l                 (u_l = P^-1 q_l)           kernel matmat
+//   alpha_l = u_l^T y                                    its epilogue dots
+//   r = y - alpha_l q_l - beta_{l-1} q_{l-1}
+//   r~ = P^-1 r ; beta_l^2 = r^T r~ ; v^T r               Woodbury + dots
+//   q_{l+1} = r / beta_l ; u_{l+1} = r~ / beta_l
+// A probe whose beta_l falls to 1e-12 times its largest |alpha| has reached
+// an invariant subspace and stops (its T then gives the exact solves).
+constexpr double kLzBreak = 1e-12;
+
+struct Lz {
+  double* alpha;  // steps x s
+  double* beta;   // steps x s
+  double* g;      // (steps + 1) x s : v^T q_l
+  double* nv;     // |v|
+  double* ztz;    // v^T v
+  double* amax;   // largest |alpha| so far
+  double* inv;    // 1 / (scale of the next Lanczos vector)
+  double* bprev;  // beta of the previous step
+  int* steps;     // steps taken
+  int* active;
+  int* status;    // [0] active probes, [1] breakdown (non-positive or non-finite norm)
+};
+
+__global__ void k_lz_init(Lz L, const double* __restrict__ d1, const double* __restrict__ d2,
+                          int nblk, int64_t s) {
+  for (int64_t c = threadIdx.x; c < s; c += blockDim.x) {
+    const double nv2 = block_colsum(d1, nblk, s, c);
+    const double zz = block_colsum(d2, nblk, s, c);
+    const bool ok = nv2 > 0.0 && isfinite(nv2);
+    const double nv = ok ? sqrt(nv2) : 0.0;
+    L.nv[c] = nv;
+    L.ztz[c] = zz;
+    L.g[c] = ok ? zz / nv : 0.0;
+    L.inv[c] = ok ? 1.0 / nv : 0.0;
+    L.amax[c] = 0.0;
+    L.bprev[c] = 0.0;
+    L.steps[c] = 0;
+    L.active[c] = ok ? 1 : 0;
+    if (!ok) atomicOr(&L.status[1], 1);
+  }
+}
+
+template <typename T>
+__global__ void k_lz_scale(T* __restrict__ a, T* __restrict__ b, const double* __restrict__ inv,
+                           const int* __restrict__ active, int64_t n, int64_t s) {
+  const int64_t total = n * s;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * 256) {
+    const int64_t c = i % s;
+    if (!active[c]) continue;
+    const double f = inv[c];
+    a[i] = (T)((double)a[i] * f);
+    b[i] = (T)((double)b[i] * f);
+  }
+}
+
+__global__ void k_lz_alpha(Lz L, const double* __restrict__ dots, int nblk, int64_t s, int l) {
+  for (int64_t c = threadIdx.x; c < s; c += blockDim.x) {
+    if (!L.active[c]) continue;
+    const double a = block_colsum(dots, nblk, s, c);
+    if (!isfinite(a)) {
+      atomicOr(&L.status[1], 1);
+      L.active[c] = 0;
+      continue;
+    }
+    L.alpha[(int64_t)l * s + c] = a;
+    L.amax[c] = fmax(L.amax[c], fabs(a));
+  }
+}
+
+template <typename T>
+__global__ void k_lz_resid(T* __restrict__ r, const T* __restrict__ q, const T* __restrict__ qp,
+                           const double* __restrict__ alpha, const double* __restrict__ bprev,
+                           const int* __restrict__ active, int64_t n, int64_t s) {
+  const int64_t total = n * s;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * 256) {
+    const int64_t c = i % s;
+    if (!active[c]) continue;
+    r[i] = (T)((double)r[i] - alpha[c] * (double)q[i] - bprev[c] * (double)qp[i]);
+  }
+}
+
+__global__ void k_lz_beta(Lz L, const double* __restrict__ d1, const double* __restrict__ d2,
+                          int nblk, int64_t s, int l) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int64_t c = threadIdx.x; c < s; c += blockDim.x) {
+    if (!L.active[c]) continue;
+    const double b2 = block_colsum(d1, nblk, s, c);
+    const double vr = block_colsum(d2, nblk, s, c);
+    L.steps[c] = l + 1;
+    if (!(b2 >= 0.0) || !isfinite(b2)) {
+      atomicOr(&L.status[1], 1);
+      L.beta[(int64_t)l * s + c] = 0.0;
+      L.active[c] = 0;
+      continue;
+    }
+    const double b = sqrt(b2);
+    L.beta[(int64_t)l * s + c] = b;
+    if (b <= kLzBreak * L.amax[c]) {  // invariant subspace: T is exact
+      L.active[c] = 0;
+      continue;
+    }
+    L.inv[c] = 1.0 / b;
+    L.bprev[c] = b;
+    L.g[(int64_t)(l + 1) * s + c] = vr / b;
+    ++mine;
+  }
+  atomicAdd(&cnt, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) L.status[0] = cnt;
+}
+
+// Per probe: the Thomas algorithm for (T + a_j I) w = |v| e_1 (T + a_j I is
+// SPD, no pivoting), the output b v^T v + sum_j c_j g^T w_j, and the P^-1
+// residual of the smallest-shift system relative to |v|,
+// beta_m |w_m| / |v|; then the Hutchinson mean and standard error.
+__global__ void k_lz_finish(Lz L, int64_t s, Coef cf, double* __restrict__ per_probe,
+                            double* __restrict__ resid, double* __restrict__ stats) {
+  for (int64_t c = threadIdx.x; c < s; c += blockDim.x) {
+    const int m = L.steps[c];
+    const double nv = L.nv[c];
+    if (m == 0) {
+      per_probe[c] = (double)NAN;
+      resid[c] = (double)NAN;
+      continue;
+    }
+    double cp[kLzMax], yp[kLzMax];
+    double val = cf.b * L.ztz[c];
+    for (int j = 0; j < cf.J; ++j) {
+      const double aj = cf.a[j];
+      double den = L.alpha[c] + aj;
+      cp[0] = m > 1 ? L.beta[c] / den : 0.0;
+      yp[0] = nv / den;
+      for (int l = 1; l < m; ++l) {
+        const double e = L.beta[(int64_t)(l - 1) * s + c];
+        den = L.alpha[(int64_t)l * s + c] + aj - e * cp[l - 1];
+        cp[l] = l + 1 < m ? L.beta[(int64_t)l * s + c] / den : 0.0;
+        yp[l] = -e * yp[l - 1] / den;
+      }
+      // back substitution, accumulating g^T w from the last row up
+      double w = yp[m - 1];
+      double gw = L.g[(int64_t)(m - 1) * s + c] * w;
+      if (j == 0) resid[c] = L.beta[(int64_t)(m - 1) * s + c] * fabs(w) / nv;
+      for (int l = m - 2; l >= 0; --l) {
+        w = yp[l] - cp[l] * w;
+        gw += L.g[(int64_t)l * s + c] * w;
+      }
+      val += cf.c[j] * gw;
+    }
+    per_probe[c] = val;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mean = 0.0, worst = 0.0;
+    for (int64_t c = 0; c < s; ++c) {
+      mean += per_probe[c];
+      worst = fmax(worst, resid[c]);
+    }
+    mean /= (double)s;
+    double var = 0.0;
+    for (int64_t c = 0; c < s; ++c) var += (per_probe[c] - mean) * (per_probe[c] - mean);
+    stats[0] = mean;
+    stats[1] = s > 1 ? sqrt(var / (double)(s - 1) / (double)s) : (double)NAN;
+    stats[2] = worst;
+  }
+}
+
+template <typename T>
+ld_status lanczos_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precond* P,
+                      const Coef& cf, const T* Z, int64_t s, int t, LzOut& o) {
+  const int64_t n = base.n;
+  const size_t vec = (size_t)n * s;
+  hipStream_t st = ctx->stream;
+  T* q = (T*)ctx->arena.take(vec * sizeof(T));
+  T* qp = (T*)ctx->arena.take(vec * sizeof(T));
+  T* r = (T*)ctx->arena.take(vec * sizeof(T));
+  T* u = (T*)ctx->arena.take(vec * sizeof(T));
+  T* ut = (T*)ctx->arena.take(vec * sizeof(T));
+  const int64_t mrt = (n + kEpiRows - 1) / kEpiRows * kEpiSplit;
+  const int64_t wrt = wood_dot_blocks(f64, n);
+  double* dwq = (double*)ctx->arena.take((size_t)mrt * s * sizeof(double));
+  double* d1 = (double*)ctx->arena.take((size_t)wrt * s * sizeof(double));
+  double* d2 = (double*)ctx->arena.take((size_t)wrt * s * sizeof(double));
+  double* sg1 = (double*)ctx->arena.take((size_t)kSeg * s * sizeof(double));
+  double* sg2 = (double*)ctx->arena.take((size_t)kSeg * s * sizeof(double));
+  double* sc = (double*)ctx->arena.take(((size_t)(3 * t + 1) * s + 8 * s + 3) * sizeof(double));
+  int* isc = (int*)ctx->arena.take((size_t)(2 * s + 2) * sizeof(int));
+  if (!q || !qp || !r || !u || !ut || !dwq || !d1 || !d2 || !sg1 || !sg2 || !sc || !isc)
+    return fail(LD_ENOMEM, "lanczos: scratch arena too small");
+  Lz L;
+  L.alpha = sc;
+  L.beta = L.alpha + (size_t)t * s;
+  L.g = L.beta + (size_t)t * s;
+  L.nv = L.g + (size_t)(t + 1) * s;
+  L.ztz = L.nv + s;
+  L.amax = L.ztz + s;
+  L.inv = L.amax + s;
+  L.bprev = L.inv + s;
+  double* per_probe = L.bprev + s;
+  double* resid = per_probe + s;
+  double* stats = resid + s;
+  L.steps = isc;
+  L.active = isc + s;
+  L.status = isc + 2 * s;
+  LD_TRY(ensure_pinned(ctx, (size_t)(2 * s + 8)));
+  LD_HIP(hipMemsetAsync(L.status, 0, 2 * sizeof(int), st));
+  LD_HIP(hipMemsetAsync(qp, 0, vec * sizeof(T), st));
+  const size_t mark = ctx->arena.top;
+  const dim3 cs_grid((unsigned)((s + 63) / 64), kSeg);
+
+  // q_1 = v / |v|, u_1 = P^-1 q_1
+  hipLaunchKernelGGL(k_copy2<T>, dim3(grid1(vec)), dim3(256), 0, st, Z, q, (T*)nullptr,
+                     (int64_t)vec);
+  LD_TRY(wood_apply_t<T>(ctx, P, q, s, u, Z, d1, d2));
+  ctx->arena.top = mark;
+  hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, d1, (int)wrt, s, sg1);
+  hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, d2, (int)wrt, s, sg2);
+  hipLaunchKernelGGL(k_lz_init, dim3(1), dim3(256), 0, st, L, sg1, sg2, kSeg, s);
+  hipLaunchKernelGGL(k_lz_scale<T>, dim3(grid1(vec)), dim3(256), 0, st, q, u, L.inv, L.active, n, s);
+  LD_HIP(hipGetLastError());
+
+  const int check_every = n >= 16384 ? 1 : 8;
+  for (int l = 0; l < t; ++l) {
+    ctx->arena.top = mark;
+    MatmatArgs a = base;
+    a.s = s;
+    a.V = u;
+    a.Y = r;
+    a.X2 = nullptr;
+    a.alpha2 = 0.0;
+    a.dots = dwq;
+    a.timed = true;
+    int nb = 0;
+    a.dot_blocks = &nb;
+    LD_TRY(matmat(ctx, f64, a));
+    hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, dwq, nb, s, sg1);
+    hipLaunchKernelGGL(k_lz_alpha, dim3(1), dim3(256), 0, st, L, sg1, kSeg, s, l);
+    hipLaunchKernelGGL(k_lz_resid<T>, dim3(grid1(vec)), dim3(256), 0, st, r, q, qp,
+                       L.alpha + (size_t)l * s, L.bprev, L.active, n, s);
+    ctx->arena.top = mark;
+    LD_TRY(wood_apply_t<T>(ctx, P, r, s, ut, Z, d1, d2));
+    hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, d1, (int)wrt, s, sg1);
+    hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, d2, (int)wrt, s, sg2);
+    hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(256), 0, st, L, sg1, sg2, kSeg, s, l);
+    hipLaunchKernelGGL(k_lz_scale<T>, dim3(grid1(vec)), dim3(256), 0, st, r, ut, L.inv, L.active,
+                       n, s);
+    LD_HIP(hipGetLastError());
+    // q_{l-1} <- q_l, q_l <- q_{l+1} (in r), u_l <- u_{l+1} (in ut)
+    T* tq = qp;
+    qp = q;
+    q = r;
+    r = tq;
+    T* tu = u;
+    u = ut;
+    ut = tu;
+    if ((l + 1) % check_every == 0 && l + 1 < t) {
+      LD_HIP(hipMemcpyAsync(ctx->pinned, L.status, sizeof(int), hipMemcpyDeviceToHost, st));
+      LD_HIP(hipStreamSynchronize(st));
+      timing_collect(ctx);
+      if (*(const int*)ctx->pinned == 0) break;
+    }
+  }
+  ctx->arena.top = mark;
+  hipLaunchKernelGGL(k_lz_finish, dim3(1), dim3(256), 0, st, L, s, cf, per_probe, resid, stats);
+  LD_HIP(hipGetLastError());
+  double* hp = ctx->pinned;
+  LD_HIP(hipMemcpyAsync(hp, per_probe, (size_t)s * sizeof(double), hipMemcpyDeviceToHost, st));
+  LD_HIP(hipMemcpyAsync(hp + s, stats, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  LD_HIP(hipMemcpyAsync(hp + s + 3, L.steps, (size_t)s * sizeof(int), hipMemcpyDeviceToHost, st));
+  LD_HIP(hipMemcpyAsync((int*)(hp + s + 3) + s, L.status, 2 * sizeof(int), hipMemcpyDeviceToHost,
+                        st));
+  LD_HIP(hipStreamSynchronize(st));
+  timing_collect(ctx);
+  o.per_probe.assign(hp, hp + s);
+  o.mean = hp[s];
+  o.stderr_ = hp[s + 1];
+  o.resid = hp[s + 2];
+  const int* steps = (const int*)(hp + s + 3);
+  o.max_steps = 0;
+  o.exact = 0;
+  for (int64_t c = 0; c < s; ++c) {
+    o.max_steps = std::max(o.max_steps, steps[c]);
+    if (steps[c] < t) ++o.exact;
+  }
+  o.breakdown = ((const int*)(hp + s + 3))[s + 1] != 0;
+  return LD_OK;
+}
+
+}  // namespace
+
+ld_status lanczos_estimate(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precond* P,
+                           const Coef& cf, const void* Z, int64_t s, int t, LzOut& out) {
+  if (f64) return lanczos_run<double>(ctx, true, base, P, cf, (const double*)Z, s, t, out);
+  return lanczos_run<float>(ctx, false, base, P, cf, (const float*)Z, s, t, out);
+}
+
+size_t lanczos_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int rank, int64_t s, int t) {
+  const size_t es = f64 ? 8 : 4;
+  size_t b = 5 * (size_t)n * s * es + 1280;
+  b += ((n + kEpiRows - 1) / kEpiRows * kEpiSplit + 2 * ((n + 63) / 64)) * (size_t)s * 8 + 768;
+  b += 2 * (size_t)kSeg * s * 8 + 512;
+  b += ((size_t)(3 * t + 1) * s + 8 * s + 3) * 8 + (size_t)(2 * s + 2) * 4 + 512;
+  b += std::max(matmat_scratch_bytes(ctx, f64, n, s), woodbury_scratch_bytes(n, rank, s)) + 1024;
+  return b;
+}
+
+ld_status hutchinson(ld_ctx* ctx, const double* ztx_dev, const double* ztz_dev, int64_t s,
+                     const Coef& cf, double* per_probe_dev, double* stats_dev) {
+  hipLaunchKernelGGL(k_hutchinson, dim3(1), dim3(256), 0, ctx->stream, ztx_dev, ztz_dev, s, cf,
+                     per_probe_dev, stats_dev);
+  LD_HIP(hipGetLastError());
+  return LD_OK;
+}
+
 // --------------------------------------------------------------- driver --
 namespace {
 
@@ -772,8 +1125,9 @@ struct PcgOut {
 
 template <typename T>
 ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precond* P,
-                  const double* shifts, int J, const T* Z, int64_t s, double tol, int max_iters,
-                  std::vector<double>& ztx_host, std::vector<double>& ztz_host, PcgOut& res) {
+                  const double* shifts, int J, const Coef& cf, const T* Z, int64_t s, double tol,
+                  int max_iters, std::vector<double>& per_probe, double* mean, double* stderr_,
+                  PcgOut& res) {
   const int64_t n = base.n;
   const size_t vec = (size_t)n * s;
   hipStream_t st = ctx->stream;
@@ -791,7 +1145,8 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
   int* iscal = (int*)ctx->arena.take((size_t)(J * s + s + 2) * sizeof(int));
   double* sg1 = (double*)ctx->arena.take((size_t)kSeg * s * sizeof(double));
   double* sg2 = (double*)ctx->arena.take((size_t)kSeg * s * sizeof(double));
-  if (!r || !u || !p || !w || !q || !dwq || !d1 || !d2 || !scal || !iscal || !sg1 || !sg2)
+  double* hut = (double*)ctx->arena.take((size_t)(s + 2) * sizeof(double));
+  if (!r || !u || !p || !w || !q || !dwq || !d1 || !d2 || !scal || !iscal || !sg1 || !sg2 || !hut)
     return fail(LD_ENOMEM, "pcg: scratch arena too small");
   Scal S;
   S.rho = scal;
@@ -878,19 +1233,21 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
   ctx->arena.top = mark;
   res.iterations = it;
 
-  // read back z^T x_j, z^T z, rho, rho0, active
+  // Hutchinson combination on the device; read back the per-probe values,
+  // mean, standard error, rho and rho0
+  LD_TRY(hutchinson(ctx, S.ztx, S.ztz, s, cf, hut, hut + s));
   double* hp = ctx->pinned;
-  LD_HIP(hipMemcpyAsync(hp, S.ztx, (size_t)J * s * sizeof(double), hipMemcpyDeviceToHost, st));
-  LD_HIP(hipMemcpyAsync(hp + J * s, S.ztz, s * sizeof(double), hipMemcpyDeviceToHost, st));
-  LD_HIP(hipMemcpyAsync(hp + J * s + s, S.rho, s * sizeof(double), hipMemcpyDeviceToHost, st));
-  LD_HIP(hipMemcpyAsync(hp + J * s + 2 * s, S.rho0, s * sizeof(double), hipMemcpyDeviceToHost, st));
+  LD_HIP(hipMemcpyAsync(hp, hut, (size_t)(s + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
+  LD_HIP(hipMemcpyAsync(hp + s + 2, S.rho, s * sizeof(double), hipMemcpyDeviceToHost, st));
+  LD_HIP(hipMemcpyAsync(hp + 2 * s + 2, S.rho0, s * sizeof(double), hipMemcpyDeviceToHost, st));
   LD_HIP(hipStreamSynchronize(st));
-  ztx_host.assign(hp, hp + J * s);
-  ztz_host.assign(hp + J * s, hp + J * s + s);
+  per_probe.assign(hp, hp + s);
+  *mean = hp[s];
+  *stderr_ = hp[s + 1];
   double worst = 0.0;
   int conv = 0;
   for (int64_t c = 0; c < s; ++c) {
-    const double rr = std::sqrt(std::max(0.0, hp[J * s + s + c] / hp[J * s + 2 * s + c]));
+    const double rr = std::sqrt(std::max(0.0, hp[s + 2 + c] / hp[2 * s + 2 + c]));
     worst = std::max(worst, rr);
     if (rr <= tol) ++conv;
   }
@@ -902,17 +1259,17 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
 }  // namespace
 
 ld_status multishift_pcg(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precond* P,
-                         const double* shifts, int J, const void* Z, int64_t s, double tol,
-                         int max_iters, std::vector<double>& ztx, std::vector<double>& ztz,
+                         const Coef& cf, const void* Z, int64_t s, double tol, int max_iters,
+                         std::vector<double>& per_probe, double* mean, double* stderr_,
                          int* iterations, int* converged, double* rel_resid, bool* breakdown) {
   PcgOut o;
   ld_status stt;
   if (f64)
-    stt = pcg_run<double>(ctx, true, base, P, shifts, J, (const double*)Z, s, tol, max_iters, ztx,
-                          ztz, o);
+    stt = pcg_run<double>(ctx, true, base, P, cf.a, cf.J, cf, (const double*)Z, s, tol, max_iters,
+                          per_probe, mean, stderr_, o);
   else
-    stt = pcg_run<float>(ctx, false, base, P, shifts, J, (const float*)Z, s, tol, max_iters, ztx,
-                         ztz, o);
+    stt = pcg_run<float>(ctx, false, base, P, cf.a, cf.J, cf, (const float*)Z, s, tol, max_iters,
+                         per_probe, mean, stderr_, o);
   *iterations = o.iterations;
   *converged = o.converged;
   *rel_resid = o.rel_resid;
@@ -937,9 +1294,9 @@ void launch_scal_beta(hipStream_t st, const Scal& S, const double* d1, const dou
 size_t pcg_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int rank, int64_t s, int J) {
   const size_t es = f64 ? 8 : 4;
   size_t b = 5 * (size_t)n * s * es + 1280;
-  b += ((n + 127) / 128 + 2 * ((n + 63) / 64)) * (size_t)s * 8 + 768;
+  b += ((n + kEpiRows - 1) / kEpiRows * kEpiSplit + 2 * ((n + 63) / 64)) * (size_t)s * 8 + 768;
   b += (size_t)(7 * s + 4 * J * s + J) * 8 + (size_t)(J * s + s + 2) * 4 + 512;
-  b += 2 * (size_t)kSeg * s * 8 + 512;
+  b += 2 * (size_t)kSeg * s * 8 + (size_t)(s + 2) * 8 + 768;
   b += std::max(matmat_scratch_bytes(ctx, f64, n, s), woodbury_scratch_bytes(n, rank, s)) + 1024;
   return b;
 }

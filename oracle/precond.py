@@ -1,7 +1,9 @@
-"""Randomized truncated-SVD preconditioner P = D + U diag(lam) U^T
-(Section 2: a simplified randomized SVD after Halko et al., range finder of
+"""Preconditioners P = D + U diag(lam) U^T: the randomized truncated SVD of
+Section 2 (a simplified randomized SVD after Halko et al., range finder of
 their Algorithm 4.1 and the eigen-decomposition of the projected matrix of
-their Algorithm 5.3; Appendix, "Truncated Randomized SVD").
+their Algorithm 5.3; Appendix, "Truncated Randomized SVD"), and the other
+members of the Appendix's list (identity, diagonal, rank one, partial
+Cholesky, each "plus scaling" variant) at the end of this module.
 
 Oracle module (test infrastructure).  Steps, in the order the method takes
 them (readings of the paper in brackets):
@@ -55,6 +57,8 @@ class Precond:
     def solve(self, R):
         """P^-1 R by the Woodbury identity (R is n x s)."""
         Dinv_R = R / self.D[:, None]
+        if self.lam.size == 0:
+            return Dinv_R
         C = np.diag(1.0 / self.lam) + self.U.T @ (self.U / self.D[:, None])
         t = np.linalg.solve(C, self.U.T @ Dinv_R)
         return Dinv_R - (self.U / self.D[:, None]) @ t
@@ -66,6 +70,8 @@ def orth(Y):
 
 
 def logdet_lemma(U, lam, D):
+    if lam.size == 0:
+        return float(np.sum(np.log(D)))
     C = np.diag(1.0 / lam) + U.T @ (U / D[:, None])
     sign, ld_c = np.linalg.slogdet(C)
     if sign <= 0:
@@ -94,3 +100,63 @@ def rsvd(M, rank: int, oversample: int, power_iters: int, seed: int, floor: floa
     D = np.maximum(D, floor)
     return Precond(U=U, lam=lam, D=D, logdet=logdet_lemma(U, lam, D),
                    ritz=np.sort(theta)[::-1].copy())
+
+
+# ---------------------------------------------------------------------------
+# The Appendix's other preconditioners.  Readings: where the Appendix takes D
+# as the diagonal of M minus the low-rank part, D is floored at `floor` (the
+# noise variance) as for the randomized SVD; "plus scaling" replaces D by
+# a I with a = the noise variance (this build has no separate jitter); the
+# rank-one preconditioner's top eigenpair is the randomized SVD's of rank 1;
+# the partial Cholesky factorization is the greedy pivoted one (pivot = the
+# largest remaining diagonal entry, lowest index on ties), and its D is
+# diag(M - C C^T) (the printed formula is garbled).
+
+def _with(U, lam, D):
+    return Precond(U=U, lam=lam, D=D, logdet=logdet_lemma(U, lam, D))
+
+
+def identity(n: int):
+    """P = I."""
+    return _with(np.zeros((n, 0)), np.zeros(0), np.ones(n))
+
+
+def diagonal(M):
+    """P = diag(M)."""
+    n = M.shape[0]
+    return _with(np.zeros((n, 0)), np.zeros(0), np.diag(M).copy())
+
+
+def rank_one(M, oversample: int, power_iters: int, seed: int, floor: float):
+    """P = D + lam v v^T, (lam, v) the top eigenpair, D = diag(M - lam v v^T)."""
+    return rsvd(M, 1, oversample, power_iters, seed, floor)
+
+
+def partial_cholesky_factor(M, rank: int):
+    """Greedy pivoted partial Cholesky: C (n x rank) with C C^T matching M on
+    the pivot rows and columns, and the pivot sequence."""
+    n = M.shape[0]
+    C = np.zeros((n, rank))
+    res = np.diag(M).astype(np.float64).copy()
+    piv = []
+    for k in range(rank):
+        p = int(np.argmax(res))          # first index of the largest value
+        piv.append(p)
+        col = (M[:, p] - C[:, :k] @ C[p, :k]) / np.sqrt(res[p])
+        C[:, k] = col
+        res = res - col * col
+        res[p] = 0.0
+    return C, np.array(piv)
+
+
+def partial_cholesky(M, rank: int, floor: float):
+    """P = D + C C^T with C the rank-`rank` pivoted partial Cholesky factor and
+    D = diag(M - C C^T) floored."""
+    C, _ = partial_cholesky_factor(M, rank)
+    D = np.maximum(np.diag(M) - np.sum(C * C, axis=1), floor)
+    return _with(C, np.ones(rank), D)
+
+
+def scaled(P: Precond, a: float):
+    """The "plus scaling" variant of P: D replaced by a I."""
+    return _with(P.U, P.lam, np.full(P.D.shape, float(a)))

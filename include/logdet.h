@@ -180,6 +180,37 @@ ld_status logdet_precond_build(ld_ctx* ctx, const ld_operator* op, int32_t rank,
                                int32_t oversample, int32_t power_iters, uint64_t seed,
                                ld_precond** out);
 
+/* The Appendix's list of preconditioners, all of the form
+ * P = D + U diag(lam) U^T and applied by the same Woodbury kernels:
+ *   LD_PRECOND_RSVD       the randomized truncated SVD of logdet_precond_build
+ *   LD_PRECOND_IDENTITY   P = I (rank 0)
+ *   LD_PRECOND_DIAGONAL   P = diag(M) (rank 0)
+ *   LD_PRECOND_RANK_ONE   P = D + lam v v^T with (lam, v) the top Ritz pair of
+ *                         the randomized SVD of rank 1
+ *   LD_PRECOND_PCHOL      P = D + C C^T, C the greedy pivoted partial Cholesky
+ *                         factor of rank `rank` (pivot = largest remaining
+ *                         diagonal entry, first index on ties; lam = 1)
+ * For the low-rank kinds D = diag(M - low-rank part) floored at the noise
+ * variance, or with LD_PRECOND_SCALED ("plus scaling") D = noise * I. */
+typedef enum {
+  LD_PRECOND_RSVD = 0,
+  LD_PRECOND_IDENTITY = 1,
+  LD_PRECOND_DIAGONAL = 2,
+  LD_PRECOND_RANK_ONE = 3,
+  LD_PRECOND_PCHOL = 4
+} ld_precond_kind;
+#define LD_PRECOND_SCALED 1
+
+/* Build any preconditioner of the list (Appendix).  rank is used by RSVD and
+ * PCHOL (PCHOL: 1 <= rank <= min(n, 4096)); oversample, power_iters and seed
+ * by RSVD and RANK_ONE (as for logdet_precond_build).  flags: 0 or
+ * LD_PRECOND_SCALED (low-rank kinds only; needs noise > 0).  The partial
+ * Cholesky factor is computed in FP64 from the stored matrix (FP64 or FP32)
+ * or from the points.  Synchronizes; *out is released with ld_precond_free. */
+ld_status logdet_precond_build_kind(ld_ctx* ctx, const ld_operator* op, int32_t kind,
+                                    int32_t rank, int32_t oversample, int32_t power_iters,
+                                    uint64_t seed, int32_t flags, ld_precond** out);
+
 /* Size and log det P of a preconditioner (host outputs; any may be NULL). */
 ld_status ld_precond_info(const ld_precond* P, int64_t* n, int32_t* rank, double* logdet_P);
 

@@ -23,6 +23,9 @@ LD_ROW_MAJOR, LD_TILED = 0, 1
 LD_BATCH_GRAPH, LD_BATCH_RETUNE, LD_BATCH_PRECOND_ONLY = 1, 2, 4
 LD_SUR_FEATURES, LD_SUR_WIDTH, LD_SUR_BINS = 38, 256, 32
 LD_LANCZOS_MAX = 128
+(LD_PRECOND_RSVD, LD_PRECOND_IDENTITY, LD_PRECOND_DIAGONAL, LD_PRECOND_RANK_ONE,
+ LD_PRECOND_PCHOL) = 0, 1, 2, 3, 4
+LD_PRECOND_SCALED = 1
 
 STATUS_NAMES = {0: "LD_OK", -1: "LD_EINVAL", -2: "LD_ENOTSPD", -3: "LD_ENOCONV", -4: "LD_EHIP",
                 -5: "LD_ENOMEM"}
@@ -31,7 +34,8 @@ EXPORTED = (
     "ld_ctx_create", "ld_ctx_destroy", "ld_last_error", "ld_ctx_set_timing", "ld_ctx_read_timing",
     "ld_stored_elements", "ld_rational_coeffs", "ld_fill_probes",
     "ld_fill_gaussian", "kernel_matmat", "kernel_materialize", "logdet_precond_build",
-    "ld_precond_info", "ld_precond_export", "ld_precond_apply_inverse", "ld_precond_free",
+    "logdet_precond_build_kind", "ld_precond_info", "ld_precond_export",
+    "ld_precond_apply_inverse", "ld_precond_free",
     "logdet_estimate", "logdet_estimate_lanczos", "logdet_estimate_batched",
     "ld_surrogate_param_count",
     "ld_surrogate_features", "ld_surrogate_create", "ld_surrogate_free", "ld_surrogate_set_scaling",
@@ -103,6 +107,8 @@ def load():
         "kernel_materialize": (i32, [vp, ctypes.POINTER(Operator), vp]),
         "logdet_precond_build": (i32, [vp, ctypes.POINTER(Operator), i32, i32, i32, u64,
                                        ctypes.POINTER(vp)]),
+        "logdet_precond_build_kind": (i32, [vp, ctypes.POINTER(Operator), i32, i32, i32, i32, u64,
+                                            i32, ctypes.POINTER(vp)]),
         "ld_precond_info": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), pd]),
         "ld_precond_export": (i32, [vp, vp, vp, vp, vp]),
         "ld_precond_apply_inverse": (i32, [vp, vp, vp, i64, i32, vp]),
@@ -280,15 +286,24 @@ def kernel_materialize(ctx: Context, op: GPOperator, out=None):
 
 
 class Precond:
-    """Library-owned randomized truncated-SVD preconditioner."""
+    """Library-owned preconditioner: the randomized truncated SVD by default,
+    or any kind of the Appendix's list (LD_PRECOND_*), optionally "plus
+    scaling" (D = noise I)."""
 
     def __init__(self, ctx: Context, op: GPOperator, rank: int, oversample: int = 10,
-                 power_iters: int = 2, seed: int = 0):
+                 power_iters: int = 2, seed: int = 0, kind: int = LD_PRECOND_RSVD,
+                 scaled: bool = False):
         self.ctx = ctx
         h = ctypes.c_void_p()
         cop = op.c_struct()
-        _check(load().logdet_precond_build(ctx.handle, ctypes.byref(cop), rank, oversample,
-                                           power_iters, seed, ctypes.byref(h)))
+        if kind == LD_PRECOND_RSVD and not scaled:
+            _check(load().logdet_precond_build(ctx.handle, ctypes.byref(cop), rank, oversample,
+                                               power_iters, seed, ctypes.byref(h)))
+        else:
+            _check(load().logdet_precond_build_kind(ctx.handle, ctypes.byref(cop), kind, rank,
+                                                    oversample, power_iters, seed,
+                                                    LD_PRECOND_SCALED if scaled else 0,
+                                                    ctypes.byref(h)))
         self.handle = h
         n = ctypes.c_int64()
         r = ctypes.c_int32()

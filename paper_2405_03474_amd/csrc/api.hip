@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "kfun_dev.hpp"
 #include "ld_common.hpp"
 
 namespace ld {
@@ -203,11 +204,18 @@ ld_status check_ctx(ld_ctx* ctx) {
   return LD_OK;
 }
 
+// D = diag(M) - rowsum(U^2 lam) floored at floor_v, or the constant const_d
+// when it is positive (identity and "plus scaling" preconditioners).
 __global__ void k_d_and_inv(const double* __restrict__ U, const double* __restrict__ lam, int64_t n,
                             int rank, const void* __restrict__ Mst, int mprec, int layout,
-                            double diag_const, double floor_v, double* __restrict__ D,
-                            double* __restrict__ Dinv) {
+                            double diag_const, double floor_v, double const_d,
+                            double* __restrict__ D, double* __restrict__ Dinv) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    if (const_d > 0.0) {
+      D[i] = const_d;
+      Dinv[i] = 1.0 / const_d;
+      continue;
+    }
     double dm = diag_const;
     const int64_t ii = layout == LD_TILED ? tiled_index(i, i, n) : i * n + i;
     if (Mst && mprec != LD_BF16) {  // split-BF16 tiles store K - variance I: diag is diag_const
@@ -324,8 +332,93 @@ ld_status apply_M64(ld_ctx* ctx, const ld_operator* op, const void* Xp, const do
   return LD_OK;
 }
 
+// Library-owned block for the factors of a rank-`rank` preconditioner
+// (rank 0: D only).
+ld_status alloc_precond(ld_ctx* ctx, int64_t n, int rank, ld_precond** out) {
+  ld_precond* P = new ld_precond();
+  P->n = n;
+  P->rank = rank;
+  P->device = ctx->device;
+  const size_t nl = (size_t)n * rank;
+  P->rp32 = (rank + 31) / 32 * 32;
+  const size_t nlp = (size_t)n * P->rp32;
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t bytes = al(nl * 8) * 2 + al((size_t)rank * 8) + al((size_t)n * 8) * 2 +
+                       al(nlp * 4) + al((size_t)n * 4);
+  void* blk = nullptr;
+  if (hipMalloc(&blk, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete P;
+    return fail(LD_ENOMEM, "preconditioner allocation failed");
+  }
+  P->block = blk;
+  char* c = (char*)blk;
+  P->U = (double*)c; c += al(nl * 8);
+  P->F64 = (double*)c; c += al(nl * 8);
+  P->lam = (double*)c; c += al((size_t)rank * 8);
+  P->D = (double*)c; c += al((size_t)n * 8);
+  P->Dinv64 = (double*)c; c += al((size_t)n * 8);
+  P->F32 = (float*)c; c += al(nlp * 4);
+  P->Dinv32 = (float*)c;
+  *out = P;
+  return LD_OK;
+}
+
+// Given U and lam in P: D (the floored diagonal remainder, or const_d when
+// positive), the capacitance C = diag(1/lam) + U^T D^-1 U = R^T R, log det P
+// by the determinant lemma, F = D^-1 U R^-1 and the FP32 copies.  G, Rinv
+// (rank x rank), ok (int) and parts (3 doubles) are device scratch.  Frees P
+// on failure.
+ld_status finish_precond(ld_ctx* ctx, const ld_operator* op, ld_precond* P, double const_d,
+                         double* G, double* Rinv, int* okd, double* parts) {
+  hipStream_t st = ctx->stream;
+  const int64_t n = P->n;
+  const int rank = P->rank;
+  auto bail = [&](ld_status s_) {
+    (void)hipStreamSynchronize(st);
+    ld_precond_free(P);
+    return s_;
+  };
+  const double floor_v = op->noise > 0.0 ? op->noise : 1e-12 * op->variance;
+  hipLaunchKernelGGL(k_d_and_inv, dim3(grid1(n)), dim3(256), 0, st, P->U, P->lam, n, rank,
+                     op->M_stored, op->precision, op->layout, op->variance + op->noise, floor_v,
+                     const_d, P->D, P->Dinv64);
+  if (hipMemsetAsync(okd, 0, sizeof(int), st) != hipSuccess) return bail(fail(LD_EHIP, "memset failed"));
+  if (rank > 0) {
+    {
+      const size_t mark = ctx->arena.top;
+      ld_status s_ = gram64(ctx, P->U, P->U, P->Dinv64, n, rank, G);
+      ctx->arena.top = mark;
+      if (s_ != LD_OK) return bail(s_);
+    }
+    hipLaunchKernelGGL(k_add_diag_inv, dim3(grid1(rank)), dim3(256), 0, st, G, P->lam, rank);
+    launch_cholesky_upper(st, G, rank, okd);
+  }
+  hipLaunchKernelGGL(k_logdet_parts, dim3(1), dim3(256), 0, st, P->D, n, P->lam, G, rank, parts);
+  if (rank > 0) {
+    // F = D^-1 U R^-1  (= D^-1 U L^-T with L = R^T)
+    launch_tri_inv_upper(st, G, rank, Rinv);
+    launch_gemm64(st, P->U, Rinv, rank, P->Dinv64, n, rank, rank, P->F64);
+    launch_pitch_f32(st, P->F64, n, rank, P->rp32, P->F32);
+  }
+  launch_convert_f64_to_f32(st, P->Dinv64, P->Dinv32, n);
+  if (hipGetLastError() != hipSuccess) return bail(fail(LD_EHIP, "kernel launch failed"));
+  if (ensure_pinned(ctx, 8) != LD_OK) return bail(LD_ENOMEM);
+  if (hipMemcpyAsync(ctx->pinned, parts, 3 * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(ctx->pinned + 4, okd, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return bail(fail(LD_EHIP, "readback of log det P failed"));
+  if (*(int*)(ctx->pinned + 4) != 0)
+    return bail(fail(LD_ENOTSPD, "capacitance matrix Cholesky breakdown"));
+  P->logdet = ctx->pinned[0] + ctx->pinned[1] + ctx->pinned[2];
+  if (!std::isfinite(P->logdet)) return bail(fail(LD_ENOTSPD, "log det P is not finite"));
+  return LD_OK;
+}
+
+// Randomized truncated SVD (rank >= 1) with D the floored diagonal remainder,
+// or, with const_d > 0, D = const_d I ("plus scaling").
 ld_status build_precond(ld_ctx* ctx, const ld_operator* op, int rank, int oversample, int power_iters,
-                        uint64_t seed, ld_precond** out) {
+                        uint64_t seed, ld_precond** out, double const_d) {
   const int64_t n = op->n;
   const int m = rank + oversample;
   const bool f64 = is_f64(op);
@@ -393,74 +486,161 @@ ld_status build_precond(ld_ctx* ctx, const ld_operator* op, int rank, int oversa
     if (!(ctx->pinned[j] > 0.0) || !std::isfinite(ctx->pinned[j]))
       return fail(LD_ENOTSPD, "projected matrix has a non-positive eigenvalue among the kept ones");
 
-  // 5. factors: library-owned block
-  ld_precond* P = new ld_precond();
-  P->n = n;
-  P->rank = rank;
-  P->device = ctx->device;
-  const size_t nl = (size_t)n * rank;
-  P->rp32 = (rank + 31) / 32 * 32;
-  const size_t nlp = (size_t)n * P->rp32;
-  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  const size_t bytes = al(nl * 8) * 2 + al((size_t)rank * 8) + al((size_t)n * 8) * 2 +
-                       al(nlp * 4) + al((size_t)n * 4);
-  void* blk = nullptr;
-  if (hipMalloc(&blk, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    delete P;
-    return fail(LD_ENOMEM, "preconditioner allocation failed");
-  }
-  P->block = blk;
-  char* c = (char*)blk;
-  P->U = (double*)c; c += al(nl * 8);
-  P->F64 = (double*)c; c += al(nl * 8);
-  P->lam = (double*)c; c += al((size_t)rank * 8);
-  P->D = (double*)c; c += al((size_t)n * 8);
-  P->Dinv64 = (double*)c; c += al((size_t)n * 8);
-  P->F32 = (float*)c; c += al(nlp * 4);
-  P->Dinv32 = (float*)c;
-
-  auto bail = [&](ld_status s_) {
-    (void)hipStreamSynchronize(st);
-    (void)hipFree(P->block);
-    delete P;
-    return s_;
-  };
+  // 5. factors
+  ld_precond* P = nullptr;
+  LD_TRY(alloc_precond(ctx, n, rank, &P));
   // U = Q V_l, lam = top eigenvalues
   launch_gemm64(st, Q, evecs, m, nullptr, n, m, rank, P->U);
-  if (hipMemcpyAsync(P->lam, evals, (size_t)rank * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
-    return bail(fail(LD_EHIP, "copy of eigenvalues failed"));
-  // 6. D = diag(M) - rowsum(U^2 lam), floored
-  const double floor_v = op->noise > 0.0 ? op->noise : 1e-12 * op->variance;
-  hipLaunchKernelGGL(k_d_and_inv, dim3(grid1(n)), dim3(256), 0, st, P->U, P->lam, n, rank,
-                     op->M_stored, op->precision, op->layout, op->variance + op->noise, floor_v,
-                     P->D, P->Dinv64);
-  // capacitance C = diag(1/lam) + U^T D^-1 U = R^T R
-  {
-    const size_t mark = ctx->arena.top;
-    ld_status s_ = gram64(ctx, P->U, P->U, P->Dinv64, n, rank, G);
-    ctx->arena.top = mark;
-    if (s_ != LD_OK) return bail(s_);
+  if (hipMemcpyAsync(P->lam, evals, (size_t)rank * 8, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+    ld_precond_free(P);
+    return fail(LD_EHIP, "copy of eigenvalues failed");
   }
-  hipLaunchKernelGGL(k_add_diag_inv, dim3(grid1(rank)), dim3(256), 0, st, G, P->lam, rank);
-  if (hipMemsetAsync(okd, 0, sizeof(int), st) != hipSuccess) return bail(fail(LD_EHIP, "memset failed"));
-  launch_cholesky_upper(st, G, rank, okd);
-  double* parts = evals;  // reuse: 3 doubles
-  hipLaunchKernelGGL(k_logdet_parts, dim3(1), dim3(256), 0, st, P->D, n, P->lam, G, rank, parts);
-  // F = D^-1 U R^-1  (= D^-1 U L^-T with L = R^T)
-  launch_tri_inv_upper(st, G, rank, Rinv);
-  launch_gemm64(st, P->U, Rinv, rank, P->Dinv64, n, rank, rank, P->F64);
-  launch_pitch_f32(st, P->F64, n, rank, P->rp32, P->F32);
-  launch_convert_f64_to_f32(st, P->Dinv64, P->Dinv32, n);
-  if (hipGetLastError() != hipSuccess) return bail(fail(LD_EHIP, "kernel launch failed"));
-  if (hipMemcpyAsync(ctx->pinned, parts, 3 * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipMemcpyAsync(ctx->pinned + 4, okd, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    return bail(fail(LD_EHIP, "readback of log det P failed"));
-  if (*(int*)(ctx->pinned + 4) != 0)
-    return bail(fail(LD_ENOTSPD, "capacitance matrix Cholesky breakdown"));
-  P->logdet = ctx->pinned[0] + ctx->pinned[1] + ctx->pinned[2];
-  if (!std::isfinite(P->logdet)) return bail(fail(LD_ENOTSPD, "log det P is not finite"));
+  const ld_status s_ = finish_precond(ctx, op, P, const_d, G, Rinv, okd, evals);
+  if (s_ != LD_OK) return s_;
+  *out = P;
+  return LD_OK;
+}
+
+
+// ------------------------------------------------- preconditioner family --
+// Greedy pivoted partial Cholesky (the Appendix's partial Cholesky
+// preconditioner): rank steps of
+//   p = argmax res (first index on ties),  C[:, k] = (M[:, p] - C C[p, :]^T) / sqrt(res[p]),
+//   res -= C[:, k]^2, res[p] = 0,
+// in FP64, with M's column p read from the stored matrix (FP64 or FP32) or
+// generated in FP64 from the points.  C is n x rank row-major (the U of
+// P = D + C C^T with lam = 1).
+__global__ void k_pc_res_init(double* __restrict__ res, int64_t n, const void* __restrict__ Mst,
+                              int mprec, int layout, double diag_const) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    double dm = diag_const;
+    if (Mst && mprec != LD_BF16) {
+      const int64_t ii = layout == LD_TILED ? tiled_index(i, i, n) : i * n + i;
+      dm = mprec == LD_F64 ? ((const double*)Mst)[ii] : (double)((const float*)Mst)[ii];
+    }
+    res[i] = dm;
+  }
+}
+
+// one workgroup: piv[k] = first index of the largest res, pivval[k] = res[piv]
+__global__ __launch_bounds__(1024) void k_pc_argmax(const double* __restrict__ res, int64_t n,
+                                                    int k, int* __restrict__ piv,
+                                                    double* __restrict__ pivval) {
+  __shared__ double bv[1024];
+  __shared__ int64_t bi[1024];
+  double v = -1.0;
+  int64_t idx = n;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const double r = res[i];
+    if (r > v) {  // strictly larger: keeps the first index among equal values
+      v = r;
+      idx = i;
+    }
+  }
+  bv[threadIdx.x] = v;
+  bi[threadIdx.x] = idx;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const double o = bv[threadIdx.x + w];
+      const int64_t oi = bi[threadIdx.x + w];
+      if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+        bv[threadIdx.x] = o;
+        bi[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    piv[k] = (int)bi[0];
+    pivval[k] = bv[0];
+  }
+}
+
+template <int KIND>
+__global__ void k_pc_column(const double* __restrict__ X, int d, double var, double c,
+                            double noise, const void* __restrict__ Mst, int mprec, int layout,
+                            int64_t n, int rank, int k, const int* __restrict__ piv,
+                            const double* __restrict__ pivval, double* __restrict__ C,
+                            double* __restrict__ res) {
+  const int64_t p = piv[k];
+  const double inv = 1.0 / sqrt(pivval[k]);
+  const double* cp = C + p * rank;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    double m;
+    if (Mst && mprec != LD_BF16) {
+      const int64_t ii = layout == LD_TILED ? tiled_index(i, p, n) : i * n + p;
+      m = mprec == LD_F64 ? ((const double*)Mst)[ii] : (double)((const float*)Mst)[ii];
+    } else {
+      double r2 = 0.0;
+      for (int dd = 0; dd < d; ++dd) {
+        const double df = X[i * d + dd] - X[p * d + dd];
+        r2 = fma(df, df, r2);
+      }
+      m = dev::kval64<KIND>(r2, var, c) + (i == p ? noise : 0.0);
+    }
+    const double* ci = C + i * rank;
+    double sdot = 0.0;
+    for (int l = 0; l < k; ++l) sdot = fma(ci[l], cp[l], sdot);
+    const double v = (m - sdot) * inv;
+    C[i * rank + k] = v;
+    res[i] = i == p ? 0.0 : res[i] - v * v;
+  }
+}
+
+__global__ void k_fill(double* __restrict__ a, int64_t count, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256)
+    a[i] = v;
+}
+
+// Preconditioners of the Appendix's list other than the randomized SVD:
+// identity and diagonal (rank 0), and partial Cholesky; const_d > 0 gives
+// the "plus scaling" D = const_d I.
+ld_status build_precond_simple(ld_ctx* ctx, const ld_operator* op, int kind, int rank,
+                               double const_d, ld_precond** out) {
+  const int64_t n = op->n;
+  if (kind != LD_PRECOND_PCHOL) rank = 0;
+  size_t need = (size_t)n * op->d * 4 + 512 + (size_t)n * 8 + 512 + 2 * (size_t)rank * rank * 8 +
+                1024 + (size_t)rank * 12 + 512 + 4096 + ((size_t)16 << 20);
+  ctx->arena.reset();
+  LD_TRY(ctx->arena.reserve(need));
+  double* res = (double*)ctx->arena.take((size_t)n * 8);
+  double* G = (double*)ctx->arena.take((size_t)std::max(rank, 1) * std::max(rank, 1) * 8);
+  double* Rinv = (double*)ctx->arena.take((size_t)std::max(rank, 1) * std::max(rank, 1) * 8);
+  int* piv = (int*)ctx->arena.take((size_t)std::max(rank, 1) * 4);
+  double* pivval = (double*)ctx->arena.take((size_t)std::max(rank, 1) * 8);
+  double* parts = (double*)ctx->arena.take(64);
+  int* okd = (int*)ctx->arena.take(64);
+  if (!res || !G || !Rinv || !piv || !pivval || !parts || !okd)
+    return fail(LD_ENOMEM, "precond: scratch arena too small");
+  hipStream_t st = ctx->stream;
+  ld_precond* P = nullptr;
+  LD_TRY(alloc_precond(ctx, n, rank, &P));
+  if (kind == LD_PRECOND_IDENTITY) const_d = 1.0;
+  if (kind == LD_PRECOND_PCHOL) {
+    const KParams kp = make_kparams(*op);
+    const double c = kp.kind == LD_RBF ? kp.c_rbf : kp.c_mat;
+    hipLaunchKernelGGL(k_pc_res_init, dim3(grid1(n)), dim3(256), 0, st, res, n, op->M_stored,
+                       op->precision, op->layout, op->variance + op->noise);
+    for (int k = 0; k < rank; ++k) {
+      hipLaunchKernelGGL(k_pc_argmax, dim3(1), dim3(1024), 0, st, res, n, k, piv, pivval);
+      if (kp.kind == LD_RBF)
+        hipLaunchKernelGGL(k_pc_column<LD_RBF>, dim3(grid1(n)), dim3(256), 0, st,
+                           (const double*)op->X, op->d,
+                           op->variance, c, op->noise, op->M_stored, op->precision, op->layout, n,
+                           rank, k, piv, pivval, P->U, res);
+      else
+        hipLaunchKernelGGL(k_pc_column<LD_MATERN52>, dim3(grid1(n)), dim3(256), 0, st,
+                           (const double*)op->X, op->d, op->variance, c, op->noise, op->M_stored, op->precision,
+                           op->layout, n, rank, k, piv, pivval, P->U, res);
+    }
+    hipLaunchKernelGGL(k_fill, dim3(grid1(rank)), dim3(256), 0, st, P->lam, (int64_t)rank, 1.0);
+    if (hipGetLastError() != hipSuccess) {
+      ld_precond_free(P);
+      return fail(LD_EHIP, "kernel launch failed");
+    }
+  }
+  LD_TRY(finish_precond(ctx, op, P, const_d, G, Rinv, okd, parts));
   *out = P;
   return LD_OK;
 }
@@ -607,7 +787,41 @@ ld_status logdet_precond_build(ld_ctx* ctx, const ld_operator* op, int32_t rank,
     return fail(LD_EINVAL, "need 1 <= rank and rank + oversample <= n");
   if (rank + oversample > 4096) return fail(LD_EINVAL, "rank + oversample must be <= 4096");
   if (power_iters < 0 || power_iters > 16) return fail(LD_EINVAL, "power_iters must be in 0..16");
-  return build_precond(ctx, op, rank, oversample, power_iters, seed, out);
+  return build_precond(ctx, op, rank, oversample, power_iters, seed, out, 0.0);
+}
+
+ld_status logdet_precond_build_kind(ld_ctx* ctx, const ld_operator* op, int32_t kind,
+                                    int32_t rank, int32_t oversample, int32_t power_iters,
+                                    uint64_t seed, int32_t flags, ld_precond** out) {
+  LD_TRY(check_ctx(ctx));
+  LD_TRY(check_operator(op));
+  if (!out) return fail(LD_EINVAL, "out is NULL");
+  if (flags & ~LD_PRECOND_SCALED) return fail(LD_EINVAL, "unknown flags");
+  const bool scaled = (flags & LD_PRECOND_SCALED) != 0;
+  if (scaled && !(op->noise > 0.0))
+    return fail(LD_EINVAL, "LD_PRECOND_SCALED needs noise > 0 (D = noise I)");
+  const double const_d = scaled ? op->noise : 0.0;
+  switch (kind) {
+    case LD_PRECOND_RSVD:
+    case LD_PRECOND_RANK_ONE: {
+      if (kind == LD_PRECOND_RANK_ONE) rank = 1;
+      if (rank < 1 || oversample < 0 || (int64_t)rank + oversample > op->n)
+        return fail(LD_EINVAL, "need 1 <= rank and rank + oversample <= n");
+      if (rank + oversample > 4096) return fail(LD_EINVAL, "rank + oversample must be <= 4096");
+      if (power_iters < 0 || power_iters > 16) return fail(LD_EINVAL, "power_iters must be in 0..16");
+      return build_precond(ctx, op, rank, oversample, power_iters, seed, out, const_d);
+    }
+    case LD_PRECOND_IDENTITY:
+    case LD_PRECOND_DIAGONAL:
+      if (scaled) return fail(LD_EINVAL, "LD_PRECOND_SCALED applies to low-rank preconditioners");
+      return build_precond_simple(ctx, op, kind, 0, 0.0, out);
+    case LD_PRECOND_PCHOL:
+      if (rank < 1 || rank > op->n || rank > 4096)
+        return fail(LD_EINVAL, "partial Cholesky needs 1 <= rank <= min(n, 4096)");
+      return build_precond_simple(ctx, op, kind, rank, const_d, out);
+    default:
+      return fail(LD_EINVAL, "unknown preconditioner kind");
+  }
 }
 
 ld_status ld_precond_info(const ld_precond* P, int64_t* n, int32_t* rank, double* logdet_P) {
@@ -688,7 +902,7 @@ ld_status est_setup(ld_ctx* ctx, const ld_operator* op, const ld_precond* P, int
   if (!P) {
     int rank = (int)std::min<int64_t>(100, std::max<int64_t>(1, op->n / 10));
     int over = (int)std::min<int64_t>(10, op->n - rank);
-    LD_TRY(build_precond(ctx, op, rank, over, 2, probe_seed + 1, &e.own));
+    LD_TRY(build_precond(ctx, op, rank, over, 2, probe_seed + 1, &e.own, 0.0));
     P = e.own;
   }
   e.P = P;

@@ -1,5 +1,6 @@
-// FP32 covariance-kernel values for the on-the-fly products (Section 3
-// kernels: RBF and Matern-5/2 in their textbook forms).
+// Covariance-kernel values (Section 3 kernels: RBF and Matern-5/2 in their
+// textbook forms): FP32 for the on-the-fly products, FP64 for the FP64 path
+// and the preconditioner builds.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,6 +26,14 @@ __device__ __forceinline__ float kval32(float r2, float v, float c) {
   const float p = __builtin_fmaf(
       u, __builtin_fmaf(u, v * (1.0f / (3.0f * kLog2eF * kLog2eF)), v * (1.0f / kLog2eF)), v);
   return p * __builtin_amdgcn_exp2f(-u);
+}
+
+// FP64 values: RBF c = 1 / (2 l^2);  Matern-5/2 c = sqrt(5) / l
+template <int KIND>
+__device__ __forceinline__ double kval64(double r2, double var, double c) {
+  if (KIND == LD_RBF) return var * exp(-r2 * c);
+  const double t = sqrt(r2) * c;
+  return var * (1.0 + t + t * t * (1.0 / 3.0)) * exp(-t);
 }
 
 // Host-side constants (c, v) of kval32 for lengthscale l and variance.

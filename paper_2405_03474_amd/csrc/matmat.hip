@@ -72,13 +72,7 @@ __host__ __device__ inline WGRange wg_range(const SK& p, int g) {
 // ---------------------------------------------------------- kernel values --
 // FP32 kernel values: kval32 (kfun_dev.hpp), shared with the batched path.
 using dev::kval32;
-// FP64: RBF c = 1 / (2 l^2);  Matern-5/2 c = sqrt(5) / l
-template <int KIND>
-__device__ __forceinline__ double kval64(double r2, double var, double c) {
-  if (KIND == LD_RBF) return var * exp(-r2 * c);
-  double t = sqrt(r2) * c;
-  return var * (1.0 + t + t * t * (1.0 / 3.0)) * exp(-t);
-}
+using dev::kval64;
 
 
 // ---------------------------------------------------- FP32 on the fly --

@@ -463,6 +463,40 @@ __global__ __launch_bounds__(256) void k_wood32(const float* __restrict__ F,
   }
 }
 
+// Rank-0 preconditioner (identity, diagonal): OUT = Dinv .* R with the same
+// per-row-block column dots as the Woodbury kernels (rows per block `rb`).
+template <typename T>
+__global__ __launch_bounds__(256) void k_wood_diag(const T* __restrict__ Dinv,
+                                                   const T* __restrict__ R, int64_t n, int64_t s,
+                                                   int rb, T* __restrict__ OUT,
+                                                   const T* __restrict__ Z,
+                                                   double* __restrict__ dot1,
+                                                   double* __restrict__ dot2) {
+  __shared__ double red1[4][64];
+  __shared__ double red2[4][64];
+  const int tid = threadIdx.x, cl = tid & 63, grp = tid >> 6;
+  const int64_t c = (int64_t)blockIdx.y * 64 + cl;
+  const int64_t r0 = (int64_t)blockIdx.x * rb;
+  const int64_t r1 = r0 + rb < n ? r0 + rb : n;
+  double a = 0.0, b = 0.0;
+  if (c < s)
+    for (int64_t i = r0 + grp; i < r1; i += 4) {
+      const int64_t off = i * s + c;
+      const T rv = R[off];
+      const T o = (T)((double)Dinv[i] * (double)rv);
+      OUT[off] = o;
+      a += (double)rv * (double)o;
+      if (dot2) b += (double)Z[off] * (double)rv;
+    }
+  red1[grp][cl] = a;
+  red2[grp][cl] = b;
+  __syncthreads();
+  if (grp == 0 && c < s && dot1) {
+    dot1[blockIdx.x * s + c] = ((red1[0][cl] + red1[1][cl]) + red1[2][cl]) + red1[3][cl];
+    if (dot2) dot2[blockIdx.x * s + c] = ((red2[0][cl] + red2[1][cl]) + red2[2][cl]) + red2[3][cl];
+  }
+}
+
 __global__ void k_pitch_f32(const double* __restrict__ in, int64_t n, int rank, int rp,
                             float* __restrict__ out) {
   const int64_t total = n * rp;
@@ -688,11 +722,21 @@ template <typename T>
 ld_status wood_apply_t(ld_ctx* ctx, const ld_precond* P, const T* R, int64_t s, T* OUT,
                        const T* Z, double* dot1, double* dot2);
 
+template <typename T>
+ld_status wood_apply_diag(ld_ctx* ctx, const T* Dinv, int64_t n, const T* R, int64_t s, int rb,
+                          T* OUT, const T* Z, double* dot1, double* dot2) {
+  hipLaunchKernelGGL(k_wood_diag<T>, dim3((unsigned)((n + rb - 1) / rb), (unsigned)((s + 63) / 64)),
+                     dim3(256), 0, ctx->stream, Dinv, R, n, s, rb, OUT, Z, dot1, dot2);
+  LD_HIP(hipGetLastError());
+  return LD_OK;
+}
+
 template <>
 ld_status wood_apply_t<double>(ld_ctx* ctx, const ld_precond* P, const double* R, int64_t s,
                                double* OUT, const double* Z, double* dot1, double* dot2) {
   const int64_t n = P->n;
   const int rank = P->rank;
+  if (rank == 0) return wood_apply_diag<double>(ctx, P->Dinv64, n, R, s, WT, OUT, Z, dot1, dot2);
   WoodPlan w = wood_plan(ctx, n, rank, s);
   double* part = (double*)ctx->arena.take((size_t)w.chunks * rank * s * sizeof(double));
   double* t = (double*)ctx->arena.take((size_t)rank * s * sizeof(double));
@@ -713,6 +757,7 @@ ld_status wood_apply_t<float>(ld_ctx* ctx, const ld_precond* P, const float* R, 
                               float* OUT, const float* Z, double* dot1, double* dot2) {
   const int64_t n = P->n;
   const int rp = P->rp32;
+  if (P->rank == 0) return wood_apply_diag<float>(ctx, P->Dinv32, n, R, s, W32R, OUT, Z, dot1, dot2);
   const int ltiles = (rp + W32R - 1) / W32R;
   const int ctiles = (int)((s + W32C - 1) / W32C);
   int64_t target = (int64_t)ctx->num_cu * 2 / ((int64_t)ltiles * ctiles);

@@ -97,19 +97,19 @@ def load_exact(name):
     return json.load(open(p)).get(name, {}).get("logdet")
 
 
-def cpu_baseline(cfg, sample_n: int, lanczos_steps: int = 0):
+def cpu_baseline(cfg, sample_n: int, lanczos_steps: int = 0, pkind: str = "rsvd",
+                 scaled: bool = False):
     """The oracle on a bounded sample: the same workload recipe at sample_n
     points, timed on this host; the rate is scaled to the full n by the
     oracle's O(n^3) dense-factorization cost.  With lanczos_steps the oracle
     of Algorithm 1 as printed (t Lanczos steps per probe) is timed instead."""
     from oracle import estimate as oest
-    from oracle import gp, lanczos as olz, precond
+    from oracle import gp, lanczos as olz
     sub = cfg.with_n(sample_n, rank=min(cfg.rank, sample_n // 10))
     t0 = time.perf_counter()
     X = sub.X()
     M = gp.dense_matrix(sub.kind, X, sub.lengthscale, sub.variance, sub.noise)
-    P = precond.rsvd(M, sub.rank, sub.oversample, sub.power_iters, sub.precond_seed,
-                     precond.d_floor(sub.noise, sub.variance))
+    P = oracle_precond(sub, M, pkind, scaled)
     Pd = P.dense()
     for k in cfg.orders:
         Z = oest.probes(sub.probe_seed + k, sub.n, sub.probes)
@@ -134,12 +134,35 @@ def cpu_baseline(cfg, sample_n: int, lanczos_steps: int = 0):
     }
 
 
+PRECOND_KINDS = {"rsvd": 0, "identity": 1, "diagonal": 2, "rank_one": 3, "pchol": 4}
+
+
+def oracle_precond(cfg, M, pkind: str, scaled: bool):
+    """The oracle's preconditioner of the given kind (Appendix list)."""
+    from oracle import precond
+    floor = precond.d_floor(cfg.noise, cfg.variance)
+    if pkind == "identity":
+        P = precond.identity(M.shape[0])
+    elif pkind == "diagonal":
+        P = precond.diagonal(M)
+    elif pkind == "rank_one":
+        P = precond.rank_one(M, cfg.oversample, cfg.power_iters, cfg.precond_seed, floor)
+    elif pkind == "pchol":
+        P = precond.partial_cholesky(M, cfg.rank, floor)
+    else:
+        P = precond.rsvd(M, cfg.rank, cfg.oversample, cfg.power_iters, cfg.precond_seed, floor)
+    return precond.scaled(P, cfg.noise) if scaled else P
+
+
 class Runner:
     """One problem instance on the GPU in a given arithmetic."""
 
-    def __init__(self, L, torch, ctx, cfg, precision, stored, lanczos_steps=0):
+    def __init__(self, L, torch, ctx, cfg, precision, stored, lanczos_steps=0, pkind="rsvd",
+                 scaled=False):
         self.L, self.torch, self.ctx, self.cfg = L, torch, ctx, cfg
         self.lanczos_steps = lanczos_steps
+        self.pkind = PRECOND_KINDS[pkind]
+        self.scaled = scaled
         dev = torch.device("cuda:0")
         X = torch.as_tensor(cfg.X(), dtype=torch.float64, device=dev).contiguous()
         self.stored = stored
@@ -160,7 +183,8 @@ class Runner:
             op.M = None
             L.kernel_materialize(self.ctx, op, out=self.Mbuf)
             op.M = self.Mbuf
-        P = L.Precond(self.ctx, op, cfg.rank, cfg.oversample, cfg.power_iters, cfg.precond_seed)
+        P = L.Precond(self.ctx, op, cfg.rank, cfg.oversample, cfg.power_iters, cfg.precond_seed,
+                      kind=self.pkind, scaled=self.scaled)
         for k in cfg.orders:
             if self.lanczos_steps:
                 res, per = L.logdet_estimate_lanczos(self.ctx, op, P, k, cfg.probes,
@@ -516,6 +540,10 @@ def main():
     ap.add_argument("--lanczos-steps", type=int, default=0,
                     help="c1/c2/c3: run Algorithm 1 as printed (this many Lanczos steps per "
                          "probe, tridiagonal solves) instead of the multi-shift CG to tolerance")
+    ap.add_argument("--precond", default="rsvd", choices=sorted(PRECOND_KINDS),
+                    help="c1/c2/c3: preconditioner of the Appendix's list")
+    ap.add_argument("--scaled", action="store_true",
+                    help="the preconditioner's 'plus scaling' variant (D = noise I)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the workload, run one device-to-device copy of this many MiB "
                          "(the reference dispatch for HBM byte counters)")
@@ -547,7 +575,8 @@ def main():
     stream = torch.cuda.current_stream(0)
     copy_calibration(torch, args.copy_calibration_mib)
     ctx = L.Context(0, stream)
-    runner = Runner(L, torch, ctx, cfg, precision, stored, args.lanczos_steps)
+    runner = Runner(L, torch, ctx, cfg, precision, stored, args.lanczos_steps, args.precond,
+                    args.scaled)
     results, ms_total, wall, (mm_ms, mm_calls, mm_flops, mm_bytes) = timed_steps(
         runner, args.steps, args.warmup, stream, torch)
 
@@ -590,6 +619,7 @@ def main():
                                if stored else "on_the_fly"),
                    "orders": list(cfg.orders), "probes": cfg.probes, "rank": cfg.rank,
                    "oversample": cfg.oversample, "power_iters": cfg.power_iters,
+                   "precond": {"kind": args.precond, "scaled": args.scaled},
                    "solver": ({"kind": "lanczos", "steps": args.lanczos_steps}
                               if args.lanczos_steps else
                               {"kind": "multishift_pcg", "tol": runner.tol})},
@@ -608,7 +638,8 @@ def main():
             "flops_TFLOPs": achieved / 1e12})
     if kind in ("c2", "c3") and args.compare_fp32:
         log("[bench] plain FP32 path, same problem")
-        plain = Runner(L, torch, ctx, cfg, L.LD_F32, stored, args.lanczos_steps)
+        plain = Runner(L, torch, ctx, cfg, L.LD_F32, stored, args.lanczos_steps, args.precond,
+                       args.scaled)
         pres, pms, _, _ = timed_steps(plain, 1, 0, stream, torch)
         pv = len(cfg.orders) / (pms / 1e3)
         line["plain_fp32"] = {"value": pv, "ms_per_step": pms,
@@ -616,7 +647,8 @@ def main():
         line["speedup_vs_plain_fp32"] = value / pv
     if kind == "c3" and args.check_fp64:
         log("[bench] FP64 reference run on the same probes")
-        ref = Runner(L, torch, ctx, cfg, L.LD_F64, False, args.lanczos_steps)
+        ref = Runner(L, torch, ctx, cfg, L.LD_F64, False, args.lanczos_steps, args.precond,
+                     args.scaled)
         rres = ref.step()
         line["fp64_reference"] = {
             f"r{k}": {"logdet": rres[k]["logdet"],
@@ -627,7 +659,8 @@ def main():
         line["cpu_baseline"] = None
     else:
         log("[bench] cpu baseline (oracle) ...")
-        line["cpu_baseline"] = cpu_baseline(cfg, min(args.cpu_sample_n, cfg.n), args.lanczos_steps)
+        line["cpu_baseline"] = cpu_baseline(cfg, min(args.cpu_sample_n, cfg.n), args.lanczos_steps,
+                                            args.precond, args.scaled)
     print(json.dumps(line), flush=True)
     ctx.close()
 

@@ -48,6 +48,31 @@ def probes(seed: int, n: int, s: int):
     return rng.rademacher(seed, rng.STREAM_PROBES, n, s)
 
 
+def probes_gaussian(seed: int, n: int, s: int):
+    """Standard normal probe block (Algorithm 1 step 1 with D = N(0, 1))."""
+    return rng.gaussian(seed, rng.STREAM_PROBES, n, s)
+
+
+def probes_orthogonal(seed: int, n: int, s: int):
+    """'Normal orthogonal' probes (Appendix; orthogonal Monte Carlo): W = Q S
+    with Q the n x s orthonormal factor of a standard normal block G (the QR
+    factor whose R has a positive diagonal) and S = diag of G's column norms,
+    which are chi-distributed with n degrees of freedom and independent of Q
+    [reading: the Appendix draws S independently; G's own column norms have
+    that distribution and are independent of Q].  Needs s <= n."""
+    if s > n:
+        raise ValueError("orthogonal probes need s <= n")
+    G = probes_gaussian(seed, n, s)
+    Q, R = np.linalg.qr(G)
+    Q = Q * np.sign(np.diag(R))
+    return Q * np.linalg.norm(G, axis=0)
+
+
+def probe_block(kind: str, seed: int, n: int, s: int):
+    return {"rademacher": probes, "gaussian": probes_gaussian,
+            "orthogonal": probes_orthogonal}[kind](seed, n, s)
+
+
 def per_probe_dense(M, P_dense, k: int, Z):
     """t_i for every column of Z with exact (Cholesky) shifted solves."""
     b, a, c = rational.partial_fraction(k)

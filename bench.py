@@ -98,7 +98,7 @@ def load_exact(name):
 
 
 def cpu_baseline(cfg, sample_n: int, lanczos_steps: int = 0, pkind: str = "rsvd",
-                 scaled: bool = False):
+                 scaled: bool = False, probes: str = "rademacher"):
     """The oracle on a bounded sample: the same workload recipe at sample_n
     points, timed on this host; the rate is scaled to the full n by the
     oracle's O(n^3) dense-factorization cost.  With lanczos_steps the oracle
@@ -112,7 +112,7 @@ def cpu_baseline(cfg, sample_n: int, lanczos_steps: int = 0, pkind: str = "rsvd"
     P = oracle_precond(sub, M, pkind, scaled)
     Pd = P.dense()
     for k in cfg.orders:
-        Z = oest.probes(sub.probe_seed + k, sub.n, sub.probes)
+        Z = oest.probe_block(probes, sub.probe_seed + k, sub.n, sub.probes)
         if lanczos_steps:
             olz.estimate_lanczos(M, Pd, P.logdet, k, Z, lanczos_steps)
         else:
@@ -542,6 +542,8 @@ def main():
                          "probe, tridiagonal solves) instead of the multi-shift CG to tolerance")
     ap.add_argument("--precond", default="rsvd", choices=sorted(PRECOND_KINDS),
                     help="c1/c2/c3: preconditioner of the Appendix's list")
+    ap.add_argument("--probes", default="rademacher", choices=["rademacher", "gaussian", "orthogonal"],
+                    help="c1/c2/c3: probe distribution (Algorithm 1 step 1, Appendix)")
     ap.add_argument("--scaled", action="store_true",
                     help="the preconditioner's 'plus scaling' variant (D = noise I)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -575,6 +577,8 @@ def main():
     stream = torch.cuda.current_stream(0)
     copy_calibration(torch, args.copy_calibration_mib)
     ctx = L.Context(0, stream)
+    ctx.set_probes({"rademacher": L.LD_PROBE_RADEMACHER, "gaussian": L.LD_PROBE_GAUSSIAN,
+                    "orthogonal": L.LD_PROBE_ORTHOGONAL}[args.probes])
     runner = Runner(L, torch, ctx, cfg, precision, stored, args.lanczos_steps, args.precond,
                     args.scaled)
     results, ms_total, wall, (mm_ms, mm_calls, mm_flops, mm_bytes) = timed_steps(
@@ -620,6 +624,7 @@ def main():
                    "orders": list(cfg.orders), "probes": cfg.probes, "rank": cfg.rank,
                    "oversample": cfg.oversample, "power_iters": cfg.power_iters,
                    "precond": {"kind": args.precond, "scaled": args.scaled},
+                   "probe_kind": args.probes,
                    "solver": ({"kind": "lanczos", "steps": args.lanczos_steps}
                               if args.lanczos_steps else
                               {"kind": "multishift_pcg", "tol": runner.tol})},
@@ -660,7 +665,7 @@ def main():
     else:
         log("[bench] cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(cfg, min(args.cpu_sample_n, cfg.n), args.lanczos_steps,
-                                            args.precond, args.scaled)
+                                            args.precond, args.scaled, args.probes)
     print(json.dumps(line), flush=True)
     ctx.close()
 

@@ -134,6 +134,26 @@ const char* ld_last_error(void);
 ld_status ld_ctx_set_timing(ld_ctx* ctx, int32_t on);
 ld_status ld_ctx_read_timing(ld_ctx* ctx, double* ms, int64_t* calls, double* flops, double* bytes);
 
+/* Probe distributions of Algorithm 1 step 1 (mean 0, variance 1):
+ *   LD_PROBE_RADEMACHER  +-1 entries (the default)
+ *   LD_PROBE_GAUSSIAN    standard normal entries (counter stream 2, Box-Muller)
+ *   LD_PROBE_ORTHOGONAL  'normal orthogonal' probes (Appendix): W = Q S with Q
+ *                        the orthonormal QR factor (positive R diagonal) of a
+ *                        standard normal n x s block G and S = diag of G's
+ *                        column norms (chi with n degrees of freedom,
+ *                        independent of Q); needs s <= n
+ * The estimators always keep b z^T z inside the per-probe value, as the
+ * Method section asks for non-Rademacher probes. */
+typedef enum {
+  LD_PROBE_RADEMACHER = 0,
+  LD_PROBE_GAUSSIAN = 1,
+  LD_PROBE_ORTHOGONAL = 2
+} ld_probe_kind;
+
+/* Probe distribution used by later logdet_estimate / logdet_estimate_lanczos
+ * calls on this context (not by the batched form, which is Rademacher). */
+ld_status ld_ctx_set_probes(ld_ctx* ctx, int32_t kind);
+
 /* Partial-fraction form of r_k (Section 2, Table 1), k in {1, 3, 5}:
  * r_k(x) = b + sum_{j<k} c[j] / (x + a[j]), a ascending, c < 0.  Host only;
  * a and c must hold k doubles.  The constants are derived in the library

@@ -26,12 +26,14 @@ LD_LANCZOS_MAX = 128
 (LD_PRECOND_RSVD, LD_PRECOND_IDENTITY, LD_PRECOND_DIAGONAL, LD_PRECOND_RANK_ONE,
  LD_PRECOND_PCHOL) = 0, 1, 2, 3, 4
 LD_PRECOND_SCALED = 1
+LD_PROBE_RADEMACHER, LD_PROBE_GAUSSIAN, LD_PROBE_ORTHOGONAL = 0, 1, 2
 
 STATUS_NAMES = {0: "LD_OK", -1: "LD_EINVAL", -2: "LD_ENOTSPD", -3: "LD_ENOCONV", -4: "LD_EHIP",
                 -5: "LD_ENOMEM"}
 
 EXPORTED = (
     "ld_ctx_create", "ld_ctx_destroy", "ld_last_error", "ld_ctx_set_timing", "ld_ctx_read_timing",
+    "ld_ctx_set_probes",
     "ld_stored_elements", "ld_rational_coeffs", "ld_fill_probes",
     "ld_fill_gaussian", "kernel_matmat", "kernel_materialize", "logdet_precond_build",
     "logdet_precond_build_kind", "ld_precond_info", "ld_precond_export",
@@ -99,6 +101,7 @@ def load():
         "ld_last_error": (ctypes.c_char_p, []),
         "ld_ctx_set_timing": (i32, [vp, i32]),
         "ld_ctx_read_timing": (i32, [vp, pd, ctypes.POINTER(i64), pd, pd]),
+        "ld_ctx_set_probes": (i32, [vp, i32]),
         "ld_stored_elements": (i64, [i64, i32]),
         "ld_rational_coeffs": (i32, [i32, pd, pd, pd]),
         "ld_fill_probes": (i32, [vp, u64, i64, i64, i32, vp]),
@@ -188,6 +191,10 @@ class Context:
 
     def set_timing(self, on: bool = True):
         _check(load().ld_ctx_set_timing(self.handle, 1 if on else 0))
+
+    def set_probes(self, kind: int):
+        """Probe distribution (LD_PROBE_*) of later single-problem estimates."""
+        _check(load().ld_ctx_set_probes(self.handle, kind))
 
     def read_timing(self):
         """(total ms, launches, algorithmic flops, algorithmic bytes) of the

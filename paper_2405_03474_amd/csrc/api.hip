@@ -233,6 +233,17 @@ __global__ void k_d_and_inv(const double* __restrict__ U, const double* __restri
   }
 }
 
+__global__ void k_sqrt_diag(const double* __restrict__ G, int m, double* __restrict__ out) {
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < m; j += gridDim.x * 256)
+    out[j] = sqrt(G[(int64_t)j * m + j]);
+}
+
+__global__ void k_scale_cols64(double* __restrict__ A, const double* __restrict__ f, int64_t n,
+                               int64_t s) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n * s; i += (int64_t)gridDim.x * 256)
+    A[i] *= f[i % s];
+}
+
 __global__ void k_add_diag_inv(double* __restrict__ C, const double* __restrict__ lam, int rank) {
   for (int j = blockIdx.x * 256 + threadIdx.x; j < rank; j += gridDim.x * 256)
     C[(int64_t)j * rank + j] += 1.0 / lam[j];
@@ -698,6 +709,14 @@ ld_status ld_ctx_set_timing(ld_ctx* ctx, int32_t on) {
   return LD_OK;
 }
 
+ld_status ld_ctx_set_probes(ld_ctx* ctx, int32_t kind) {
+  if (!ctx) return fail(LD_EINVAL, "context is NULL");
+  if (kind != LD_PROBE_RADEMACHER && kind != LD_PROBE_GAUSSIAN && kind != LD_PROBE_ORTHOGONAL)
+    return fail(LD_EINVAL, "unknown probe kind");
+  ctx->probe_kind = kind;
+  return LD_OK;
+}
+
 ld_status ld_ctx_read_timing(ld_ctx* ctx, double* ms, int64_t* calls, double* flops, double* bytes) {
   if (!ctx) return fail(LD_EINVAL, "context is NULL");
   if (ctx->ev_used) {
@@ -908,15 +927,61 @@ ld_status est_setup(ld_ctx* ctx, const ld_operator* op, const ld_precond* P, int
   e.P = P;
   e.f64 = is_f64(op);
   const int64_t n = op->n, s = num_probes;
+  const int pk = ctx->probe_kind;
+  if (pk == LD_PROBE_ORTHOGONAL && s > n)
+    return fail(LD_EINVAL, "orthogonal probes need num_probes <= n");
   const size_t es = e.f64 ? 8 : 4;
+  // Gaussian / orthogonal probes are drawn in FP64 first (two n x s blocks
+  // and the small Gram factors of the orthonormalisation)
+  const size_t probe_tmp = pk == LD_PROBE_RADEMACHER
+                               ? 0
+                               : 2 * (size_t)n * s * 8 + 3 * (size_t)s * s * 8 + (size_t)s * 8 +
+                                     ((size_t)16 << 20) + 4096;
   ctx->arena.reset();
   LD_TRY(ctx->arena.reserve((size_t)n * op->d * 4 + 512 + (size_t)n * s * es + 512 +
-                            solver_bytes(ctx, e.f64, n, P->rank, s, arg) + solver_bytes_extra));
+                            solver_bytes(ctx, e.f64, n, P->rank, s, arg) + solver_bytes_extra +
+                            probe_tmp));
   LD_TRY(path_points(ctx, op, &e.Xp));
   e.Z = ctx->arena.take((size_t)n * s * es);
   if (!e.Z) return fail(LD_ENOMEM, "scratch arena too small for probes");
-  launch_fill_rademacher(ctx->stream, stream_key(probe_seed, kStreamProbes), n, s, e.f64, e.Z);
+  const uint64_t key = stream_key(probe_seed, kStreamProbes);
+  hipStream_t st = ctx->stream;
+  if (pk == LD_PROBE_RADEMACHER) {
+    launch_fill_rademacher(st, key, n, s, e.f64, e.Z);
+    LD_HIP(hipGetLastError());
+    return LD_OK;
+  }
+  const size_t mark = ctx->arena.top;
+  double* Gb = (double*)ctx->arena.take((size_t)n * s * 8);
+  double* Wb = (double*)ctx->arena.take((size_t)n * s * 8);
+  double* gram = (double*)ctx->arena.take((size_t)s * s * 8);
+  double* g2 = (double*)ctx->arena.take((size_t)s * s * 8);
+  double* rinv = (double*)ctx->arena.take((size_t)s * s * 8);
+  double* norms = (double*)ctx->arena.take((size_t)s * 8);
+  int* okd = (int*)ctx->arena.take(64);
+  if (!Gb || !Wb || !gram || !g2 || !rinv || !norms || !okd)
+    return fail(LD_ENOMEM, "scratch arena too small for probes");
+  launch_fill_gaussian(st, key, n, s, Gb);
+  const double* W = Gb;
+  if (pk == LD_PROBE_ORTHOGONAL) {
+    {
+      const size_t m2 = ctx->arena.top;
+      LD_TRY(gram64(ctx, Gb, Gb, nullptr, n, (int)s, gram));
+      ctx->arena.top = m2;
+    }
+    hipLaunchKernelGGL(k_sqrt_diag, dim3(grid1(s)), dim3(256), 0, st, gram, (int)s, norms);
+    double* Q = nullptr;
+    LD_TRY(orthonormalize(ctx, Gb, Wb, n, (int)s, g2, rinv, okd, 3, &Q));
+    hipLaunchKernelGGL(k_scale_cols64, dim3(grid1(n * s)), dim3(256), 0, st, Q, norms, n, s);
+    W = Q;
+  }
+  if (e.f64)
+    LD_HIP(hipMemcpyAsync(e.Z, W, (size_t)n * s * 8, hipMemcpyDeviceToDevice, st));
+  else
+    launch_convert_f64_to_f32(st, W, (float*)e.Z, n * s);
   LD_HIP(hipGetLastError());
+  // the FP64 blocks are free again once the copy above has run (stream order)
+  ctx->arena.top = mark;
   return LD_OK;
 }
 

@@ -80,6 +80,8 @@ struct ld_ctx {
   hipStream_t side = nullptr;
   hipEvent_t ev_join = nullptr;
   int bvariant = -1;
+  // probe distribution of the single-problem estimators (ld_probe_kind)
+  int probe_kind = 0;
 };
 
 struct ld_precond {

@@ -18,5 +18,7 @@ Modules:
                exact Cholesky log det, and the bias decomposition
   lanczos   -- Algorithm 1 as printed: t Lanczos steps per probe and the
                shifted tridiagonal solves
+  gradient  -- d log det M / d(lengthscale, variance, noise) by Hutchinson over
+               probe solves
   mlp       -- the surrogate network: forward, chain-rule gradient, Adam, features
 """

@@ -268,6 +268,27 @@ ld_status logdet_estimate(ld_ctx* ctx, const ld_operator* op, const ld_precond* 
                           int32_t num_probes, uint64_t probe_seed, double tol, int32_t max_iters,
                           ld_result* out, double* per_probe);
 
+/* Gradient of log det M with respect to (lengthscale, variance, noise) by
+ * Hutchinson's estimator over probe solves (the CG-based gradient the paper
+ * tunes its parameters with, Section 3):
+ *   d log det M / d theta = tr(M^-1 dM/dtheta) ~ (1/s) sum_i (M^-1 z_i)^T (dM/dtheta) z_i,
+ * dM/d noise = I, dM/d variance = K / variance, dM/d l the kernel's
+ * derivative (RBF: k r^2 / l^3; Matern-5/2: variance t^2 (1 + t) e^-t / (3 l),
+ * t = sqrt5 r / l).  The solves M y = z run as the preconditioned CG of
+ * logdet_estimate with shift 0 in the operator's precision (y accumulated
+ * from the search directions); the derivative products are generated in
+ * FP64 from the points.  Probes follow ld_ctx_set_probes.
+ *   P, num_probes, probe_seed, tol, max_iters  as for logdet_estimate
+ *   grad       host, 3 doubles: d/d lengthscale, d/d variance, d/d noise
+ *   std_err    host, 3 doubles or NULL: Hutchinson standard errors
+ *   per_probe  host, 3 x s doubles or NULL: per-probe values, component-major
+ *   out        host or NULL: iterations, converged_cols, rel_resid, logdet_P
+ * Returns LD_ENOCONV (outputs filled) when a probe's solve did not reach tol.
+ * Synchronizes. */
+ld_status logdet_gradient(ld_ctx* ctx, const ld_operator* op, const ld_precond* P,
+                          int32_t num_probes, uint64_t probe_seed, double tol, int32_t max_iters,
+                          double* grad, double* std_err, double* per_probe, ld_result* out);
+
 /* Largest number of Lanczos steps logdet_estimate_lanczos accepts. */
 #define LD_LANCZOS_MAX 128
 

@@ -38,7 +38,7 @@ EXPORTED = (
     "ld_fill_gaussian", "kernel_matmat", "kernel_materialize", "logdet_precond_build",
     "logdet_precond_build_kind", "ld_precond_info", "ld_precond_export",
     "ld_precond_apply_inverse", "ld_precond_free",
-    "logdet_estimate", "logdet_estimate_lanczos", "logdet_estimate_batched",
+    "logdet_estimate", "logdet_estimate_lanczos", "logdet_gradient", "logdet_estimate_batched",
     "ld_surrogate_param_count",
     "ld_surrogate_features", "ld_surrogate_create", "ld_surrogate_free", "ld_surrogate_set_scaling",
     "ld_surrogate_train_step", "ld_surrogate_gradient", "ld_surrogate_params",
@@ -120,6 +120,8 @@ def load():
                                   ctypes.POINTER(Result), pd]),
         "logdet_estimate_lanczos": (i32, [vp, ctypes.POINTER(Operator), vp, i32, i32, u64, i32,
                                           ctypes.POINTER(Result), pd]),
+        "logdet_gradient": (i32, [vp, ctypes.POINTER(Operator), vp, i32, u64, dbl, i32, pd, pd, pd,
+                                  ctypes.POINTER(Result)]),
         "logdet_estimate_batched": (i32, [vp, i32, ctypes.POINTER(Instance), i32, i32, i32, i32,
                                           dbl, i32, i32, ctypes.POINTER(Result), pd, pd, i32]),
         "ld_surrogate_param_count": (i64, []),
@@ -381,6 +383,25 @@ def logdet_estimate_lanczos(ctx: Context, op: GPOperator, P: Precond | None, k: 
     out = res.as_dict()
     out["status"] = STATUS_NAMES.get(st, st)
     return out, per
+
+
+def logdet_gradient(ctx: Context, op: GPOperator, P: Precond | None, num_probes: int,
+                    probe_seed: int, tol: float, max_iters: int = 5000, allow_noconv: bool = False):
+    """d log det M / d (lengthscale, variance, noise).  Returns (grad (3,),
+    standard errors (3,), per-probe values (3, s), result dict)."""
+    res = Result()
+    grad = np.zeros(3)
+    se = np.zeros(3)
+    per = np.zeros((3, num_probes))
+    cop = op.c_struct()
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))  # noqa: E731
+    st = load().logdet_gradient(ctx.handle, ctypes.byref(cop), P.handle if P is not None else None,
+                                num_probes, probe_seed, tol, max_iters, dp(grad), dp(se), dp(per),
+                                ctypes.byref(res))
+    _check(st, allow=(LD_ENOCONV,) if allow_noconv else ())
+    out = res.as_dict()
+    out["status"] = STATUS_NAMES.get(st, st)
+    return grad, se, per, out
 
 
 @dataclass

@@ -883,6 +883,38 @@ void ld_precond_free(ld_precond* P) {
 
 namespace {
 
+// per-column dot products A^T B (n x s each, FP64) as 256-row block partials
+// parts[blk][c], summed in a fixed order
+__global__ __launch_bounds__(256) void k_coldot_parts(const double* __restrict__ A,
+                                                      const double* __restrict__ B, int64_t n,
+                                                      int64_t s, double* __restrict__ parts) {
+  __shared__ double red[4][64];
+  const int tid = threadIdx.x, cl = tid & 63, grp = tid >> 6;
+  const int64_t c = (int64_t)blockIdx.y * 64 + cl;
+  const int64_t r0 = (int64_t)blockIdx.x * 256;
+  const int64_t r1 = r0 + 256 < n ? r0 + 256 : n;
+  double acc = 0.0;
+  if (c < s)
+    for (int64_t i = r0 + grp; i < r1; i += 4) acc += A[i * s + c] * B[i * s + c];
+  red[grp][cl] = acc;
+  __syncthreads();
+  if (grp == 0 && c < s)
+    parts[blockIdx.x * s + c] = ((red[0][cl] + red[1][cl]) + red[2][cl]) + red[3][cl];
+}
+
+__global__ void k_parts_sum(const double* __restrict__ parts, int64_t nblk, int64_t s,
+                            double* __restrict__ out) {
+  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < s; c += (int64_t)gridDim.x * 256) {
+    double acc = 0.0;
+    for (int64_t b = 0; b < nblk; ++b) acc += parts[b * s + c];
+    out[c] = acc;
+  }
+}
+
+}  // namespace
+
+namespace {
+
 Coef coef_of(const Rational& rf, int k) {
   Coef cf{};
   cf.b = rf.b;
@@ -1049,6 +1081,116 @@ ld_status logdet_estimate_lanczos(ld_ctx* ctx, const ld_operator* op, const ld_p
   if (per_probe) std::memcpy(per_probe, o.per_probe.data(), (size_t)s * sizeof(double));
   if (o.breakdown)
     return fail(LD_ENOTSPD, "non-positive or non-finite norm in the Lanczos recurrence (M or P not SPD?)");
+  return LD_OK;
+}
+
+ld_status logdet_gradient(ld_ctx* ctx, const ld_operator* op, const ld_precond* P,
+                          int32_t num_probes, uint64_t probe_seed, double tol, int32_t max_iters,
+                          double* grad, double* std_err, double* per_probe, ld_result* out) {
+  LD_TRY(check_ctx(ctx));
+  LD_TRY(check_operator(op));
+  if (!grad) return fail(LD_EINVAL, "grad is NULL");
+  if (num_probes < 1) return fail(LD_EINVAL, "num_probes must be >= 1");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(LD_EINVAL, "tol must be finite and > 0");
+  if (max_iters < 1) return fail(LD_EINVAL, "max_iters must be >= 1");
+  const int64_t n = op ? op->n : 0, s = num_probes;
+  const bool f64op = op && is_f64(op);
+  const size_t es = f64op ? 8 : 4;
+  // extra scratch: y (op precision), FP64 copies of z and y, the product, partials, values
+  const int64_t nblk = (n + 255) / 256;
+  const size_t extra = (size_t)n * s * es + 3 * (size_t)n * s * 8 + (size_t)nblk * s * 8 +
+                       8 * (size_t)s * 8 + 8 * 4096 +
+                       (op ? matmat_scratch_bytes(ctx, true, n, s) : 0);
+  EstSetup e;
+  LD_TRY(est_setup(ctx, op, P, 1, num_probes, probe_seed, extra, pcg_scratch_bytes, 1, e));
+  hipStream_t st = ctx->stream;
+  void* ysol = ctx->arena.take((size_t)n * s * es);
+  double* z64 = (double*)ctx->arena.take((size_t)n * s * 8);
+  double* y64 = (double*)ctx->arena.take((size_t)n * s * 8);
+  double* az = (double*)ctx->arena.take((size_t)n * s * 8);
+  double* parts = (double*)ctx->arena.take((size_t)nblk * s * 8);
+  double* vals = (double*)ctx->arena.take((size_t)3 * s * 8);
+  double* hut = (double*)ctx->arena.take((size_t)3 * (s + 2) * 8);
+  if (!ysol || !z64 || !y64 || !az || !parts || !vals || !hut)
+    return fail(LD_ENOMEM, "gradient: scratch arena too small");
+  // y = M^-1 z by the preconditioned CG (shift 0)
+  Coef cf{};
+  cf.b = 0.0;
+  cf.J = 1;
+  cf.a[0] = 0.0;
+  cf.c[0] = 1.0;
+  std::vector<double> tmp;
+  double mean = 0.0, se = 0.0, rr = 0.0;
+  int iters = 0, conv = 0;
+  bool breakdown = false;
+  auto t0 = std::chrono::steady_clock::now();
+  LD_TRY(multishift_pcg(ctx, e.f64, base_args(op, e.Xp), e.P, cf, e.Z, s, tol, max_iters, tmp,
+                        &mean, &se, &iters, &conv, &rr, &breakdown, ysol));
+  if (e.f64) {
+    LD_HIP(hipMemcpyAsync(z64, e.Z, (size_t)n * s * 8, hipMemcpyDeviceToDevice, st));
+    LD_HIP(hipMemcpyAsync(y64, ysol, (size_t)n * s * 8, hipMemcpyDeviceToDevice, st));
+  } else {
+    launch_convert_f32_to_f64(st, (const float*)e.Z, z64, n * s);
+    launch_convert_f32_to_f64(st, (const float*)ysol, y64, n * s);
+  }
+  // (M^-1 z)^T (dM/dtheta) z: the derivative products in FP64 from the points
+  const KParams kp = make_kparams(*op);
+  const dim3 cd_grid((unsigned)nblk, (unsigned)((s + 63) / 64));
+  for (int p = 0; p < 3; ++p) {
+    const double* B = z64;
+    if (p < 2) {
+      MatmatArgs a{};
+      a.n = n;
+      a.s = s;
+      a.d = op->d;
+      a.kp = kp;
+      a.kp.noise = 0.0;
+      if (p == 0) {  // d/d lengthscale
+        const double l = op->lengthscale;
+        a.kp.kind = op->kind == LD_RBF ? dev::kKindRbfDl : dev::kKindMaternDl;
+        a.kp.variance = op->kind == LD_RBF ? op->variance / (l * l * l) : op->variance / (3.0 * l);
+      } else {  // d/d variance = K / variance
+        a.kp.variance = 1.0;
+      }
+      a.X = op->X;
+      a.V = z64;
+      a.Y = az;
+      const size_t mark = ctx->arena.top;
+      LD_TRY(matmat(ctx, true, a));
+      ctx->arena.top = mark;
+      B = az;
+    }
+    hipLaunchKernelGGL(k_coldot_parts, cd_grid, dim3(256), 0, st, y64, B, n, s, parts);
+    hipLaunchKernelGGL(k_parts_sum, dim3(1), dim3(256), 0, st, parts, nblk, s, vals + p * s);
+    Coef one{};
+    one.b = 0.0;
+    one.J = 1;
+    one.c[0] = 1.0;
+    LD_TRY(hutchinson(ctx, vals + p * s, vals + p * s, s, one, hut + p * (s + 2),
+                      hut + p * (s + 2) + s));
+  }
+  LD_HIP(hipGetLastError());
+  LD_TRY(ensure_pinned(ctx, (size_t)3 * (s + 2) + 8));
+  LD_HIP(hipMemcpyAsync(ctx->pinned, hut, (size_t)3 * (s + 2) * 8, hipMemcpyDeviceToHost, st));
+  LD_HIP(hipStreamSynchronize(st));
+  auto t1 = std::chrono::steady_clock::now();
+  const double* hp = ctx->pinned;
+  for (int p = 0; p < 3; ++p) {
+    grad[p] = hp[p * (s + 2) + s];
+    if (std_err) std_err[p] = hp[p * (s + 2) + s + 1];
+    if (per_probe) std::memcpy(per_probe + p * s, hp + p * (s + 2), (size_t)s * 8);
+  }
+  if (out) {
+    out->logdet_P = e.P->logdet;
+    out->rel_resid = rr;
+    out->seconds_solve = std::chrono::duration<double>(t1 - t0).count();
+    out->iterations = iters;
+    out->converged_cols = conv;
+    out->num_probes = num_probes;
+  }
+  if (breakdown)
+    return fail(LD_ENOTSPD, "non-positive curvature or residual norm in the solver (M or P not SPD?)");
+  if (conv < s) return fail(LD_ENOCONV, "max_iters reached before every probe converged");
   return LD_OK;
 }
 

@@ -28,11 +28,21 @@ __device__ __forceinline__ float kval32(float r2, float v, float c) {
   return p * __builtin_amdgcn_exp2f(-u);
 }
 
+// Derivatives of the kernels with respect to the lengthscale l, as further
+// FP64 kernel kinds (gradient of log det): with the same c as the kernel,
+//   RBF     dk/dl = (variance / l^3) r^2 exp(-r^2 c)
+//   Matern  dk/dl = (variance / (3 l)) t^2 (1 + t) exp(-t),  t = sqrt(r^2) c
+// (the factor in brackets is passed as `var`).
+constexpr int kKindRbfDl = 2;
+constexpr int kKindMaternDl = 3;
+
 // FP64 values: RBF c = 1 / (2 l^2);  Matern-5/2 c = sqrt(5) / l
 template <int KIND>
 __device__ __forceinline__ double kval64(double r2, double var, double c) {
   if (KIND == LD_RBF) return var * exp(-r2 * c);
+  if (KIND == kKindRbfDl) return var * r2 * exp(-r2 * c);
   const double t = sqrt(r2) * c;
+  if (KIND == kKindMaternDl) return var * t * t * (1.0 + t) * exp(-t);
   return var * (1.0 + t + t * t * (1.0 / 3.0)) * exp(-t);
 }
 

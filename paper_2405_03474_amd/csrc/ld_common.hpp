@@ -246,7 +246,8 @@ struct Coef {
 ld_status multishift_pcg(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precond* P,
                          const Coef& cf, const void* Z, int64_t s, double tol, int max_iters,
                          std::vector<double>& per_probe, double* mean, double* stderr_,
-                         int* iterations, int* converged, double* rel_resid, bool* breakdown);
+                         int* iterations, int* converged, double* rel_resid, bool* breakdown,
+                         void* ysol = nullptr);
 // Hutchinson combination of z^T x_j (J x s) and z^T z (s), device buffers:
 // per-probe values (s) and [mean, standard error].
 ld_status hutchinson(ld_ctx* ctx, const double* ztx_dev, const double* ztz_dev, int64_t s,

@@ -1333,12 +1333,18 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
   }
   if (f64) {
     const int NB = pl.NT / 16;
-    const double c = kind == LD_RBF ? a.kp.c_rbf : a.kp.c_mat;
+    const double c = (kind == LD_RBF || kind == dev::kKindRbfDl) ? a.kp.c_rbf : a.kp.c_mat;
     const double* V = (const double*)a.V;
     double* P = (double*)part;
     if (fly) {
       if (kind == LD_RBF)
         fly64_by_d<LD_RBF>(NB, grid, st, (const double*)a.X, a.d, a.kp.variance, c, V, P, pl.p);
+      else if (kind == dev::kKindRbfDl)
+        fly64_by_d<dev::kKindRbfDl>(NB, grid, st, (const double*)a.X, a.d, a.kp.variance, c, V, P,
+                                    pl.p);
+      else if (kind == dev::kKindMaternDl)
+        fly64_by_d<dev::kKindMaternDl>(NB, grid, st, (const double*)a.X, a.d, a.kp.variance, c, V,
+                                       P, pl.p);
       else
         fly64_by_d<LD_MATERN52>(NB, grid, st, (const double*)a.X, a.d, a.kp.variance, c, V, P, pl.p);
     } else {

@@ -611,6 +611,22 @@ __global__ void k_scal_alpha(Scal S, const double* __restrict__ dots, int nblk, 
   }
 }
 
+// r -= alpha q and y += alpha w (w = P^-1 p): y converges to M^-1 z when the
+// seed shift is 0 (x = P y solves M P^-1 x = z)
+template <typename T>
+__global__ void k_update_ry(T* __restrict__ r, const T* __restrict__ q, T* __restrict__ y,
+                            const T* __restrict__ w, const double* __restrict__ alpha, int64_t n,
+                            int64_t s) {
+  const int64_t total = n * s;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * 256) {
+    const int64_t c = i % s;
+    const double a = alpha[c];
+    r[i] = (T)((double)r[i] - a * (double)q[i]);
+    y[i] = (T)((double)y[i] + a * (double)w[i]);
+  }
+}
+
 template <typename T>
 __global__ void k_update_r(T* __restrict__ r, const T* __restrict__ q, const double* __restrict__ alpha,
                            int64_t n, int64_t s) {
@@ -1172,7 +1188,7 @@ template <typename T>
 ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precond* P,
                   const double* shifts, int J, const Coef& cf, const T* Z, int64_t s, double tol,
                   int max_iters, std::vector<double>& per_probe, double* mean, double* stderr_,
-                  PcgOut& res) {
+                  PcgOut& res, T* ysol) {
   const int64_t n = base.n;
   const size_t vec = (size_t)n * s;
   hipStream_t st = ctx->stream;
@@ -1225,6 +1241,7 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
   const size_t mark = ctx->arena.top;
 
   // r = z, p = z; u = P^-1 r, w = u; rho0 = r^T u; z^T z
+  if (ysol) LD_HIP(hipMemsetAsync(ysol, 0, vec * sizeof(T), st));
   hipLaunchKernelGGL(k_copy2<T>, dim3(grid1(vec)), dim3(256), 0, st, Z, r, p, (int64_t)vec);
   LD_TRY(wood_apply_t<T>(ctx, P, r, s, u, Z, d1, d2));
   ctx->arena.top = mark;
@@ -1256,7 +1273,11 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
       LD_TRY(matmat(ctx, f64, a));
       hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, dwq, nb, s, sg1);
       hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(256), 0, st, S, sg1, kSeg, s);
-      hipLaunchKernelGGL(k_update_r<T>, dim3(grid1(vec)), dim3(256), 0, st, r, q, S.alpha, n, s);
+      if (ysol)
+        hipLaunchKernelGGL(k_update_ry<T>, dim3(grid1(vec)), dim3(256), 0, st, r, q, ysol, w,
+                           S.alpha, n, s);
+      else
+        hipLaunchKernelGGL(k_update_r<T>, dim3(grid1(vec)), dim3(256), 0, st, r, q, S.alpha, n, s);
       ctx->arena.top = mark;
       LD_TRY(wood_apply_t<T>(ctx, P, r, s, u, Z, d1, d2));
       hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, d1, (int)wrt, s, sg1);
@@ -1306,15 +1327,16 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
 ld_status multishift_pcg(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precond* P,
                          const Coef& cf, const void* Z, int64_t s, double tol, int max_iters,
                          std::vector<double>& per_probe, double* mean, double* stderr_,
-                         int* iterations, int* converged, double* rel_resid, bool* breakdown) {
+                         int* iterations, int* converged, double* rel_resid, bool* breakdown,
+                         void* ysol) {
   PcgOut o;
   ld_status stt;
   if (f64)
     stt = pcg_run<double>(ctx, true, base, P, cf.a, cf.J, cf, (const double*)Z, s, tol, max_iters,
-                          per_probe, mean, stderr_, o);
+                          per_probe, mean, stderr_, o, (double*)ysol);
   else
     stt = pcg_run<float>(ctx, false, base, P, cf.a, cf.J, cf, (const float*)Z, s, tol, max_iters,
-                         per_probe, mean, stderr_, o);
+                         per_probe, mean, stderr_, o, (float*)ysol);
   *iterations = o.iterations;
   *converged = o.converged;
   *rel_resid = o.rel_resid;

@@ -197,6 +197,45 @@ class Runner:
         return out
 
 
+class GradRunner(Runner):
+    """d log det M / d(lengthscale, variance, noise) on one problem."""
+
+    def step(self):
+        L, cfg, op = self.L, self.cfg, self.op
+        if self.stored:
+            op.M = None
+            L.kernel_materialize(self.ctx, op, out=self.Mbuf)
+            op.M = self.Mbuf
+        P = L.Precond(self.ctx, op, cfg.rank, cfg.oversample, cfg.power_iters, cfg.precond_seed,
+                      kind=self.pkind, scaled=self.scaled)
+        grad, se, _, res = L.logdet_gradient(self.ctx, op, P, cfg.probes, cfg.probe_seed,
+                                             self.tol, 5000)
+        P.close()
+        return {"grad": grad.tolist(), "std_err": se.tolist(), "iterations": res["iterations"]}
+
+
+def gradient_main(args, torch, L, cfg, precision, stored):
+    stream = torch.cuda.current_stream(0)
+    ctx = L.Context(0, stream)
+    runner = GradRunner(L, torch, ctx, cfg, precision, stored, 0, args.precond, args.scaled)
+    results, ms_total, wall, _ = timed_steps(runner, args.steps, args.warmup, stream, torch)
+    last = results[-1]
+    line = {
+        "metric": "log-det gradients/s (lengthscale, variance, noise)",
+        "value": args.steps / (ms_total / 1e3), "unit": "gradients/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_total / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {L.LD_F64: "f64", L.LD_F32: "f32", L.LD_BF16: "bf16x3+f32"}[precision],
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "n": cfg.n, "probes": cfg.probes, "rank": cfg.rank,
+                   "precond": {"kind": args.precond, "scaled": args.scaled},
+                   "solver": {"kind": "pcg", "tol": runner.tol}},
+        "gradient": last, "wall_s": wall,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 class BatchRunner:
     """The heterogeneous batch through logdet_estimate_batched."""
 
@@ -544,6 +583,8 @@ def main():
                     help="c1/c2/c3: preconditioner of the Appendix's list")
     ap.add_argument("--probes", default="rademacher", choices=["rademacher", "gaussian", "orthogonal"],
                     help="c1/c2/c3: probe distribution (Algorithm 1 step 1, Appendix)")
+    ap.add_argument("--gradient", action="store_true",
+                    help="c1/c2/c3: time d log det / d(lengthscale, variance, noise) instead")
     ap.add_argument("--scaled", action="store_true",
                     help="the preconditioner's 'plus scaling' variant (D = noise I)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -574,6 +615,8 @@ def main():
         f"orders={cfg.orders} dtype={dtype} stored={stored}")
 
     torch.cuda.set_device(0)
+    if args.gradient:
+        return gradient_main(args, torch, L, cfg, precision, stored)
     stream = torch.cuda.current_stream(0)
     copy_calibration(torch, args.copy_calibration_mib)
     ctx = L.Context(0, stream)

@@ -677,15 +677,22 @@ __device__ __forceinline__ void st16_load(St16Tile<NB>& t, const __bf16* __restr
     const int cc = e % NT, kp = e / NT;  // column, pair of k rows
     const int64_t col = c0 + cc, kr = k0 + 2 * kp;
     const bool cv = col < s;
-    t.v[2 * j] = (cv && kr < n) ? V[kr * s + col] : 0.f;
-    t.v[2 * j + 1] = (cv && kr + 1 < n) ? V[(kr + 1) * s + col] : 0.f;
+    // unconditional loads from clamped addresses, kept raw until the store
+    // masks them (masking here would make the wave wait for the loads at
+    // once; a select would let the compiler sink each load into a per-lane
+    // branch)
+    const int64_t cl = cv ? col : s - 1;
+    const int64_t r0 = kr < n ? kr : n - 1, r1 = kr + 1 < n ? kr + 1 : n - 1;
+    t.v[2 * j] = V[r0 * s + cl];
+    t.v[2 * j + 1] = V[r1 * s + cl];
   }
 }
 
 template <int NB>
 __device__ __forceinline__ void st16_store(const St16Tile<NB>& t, __bf16* __restrict__ ah,
                                            __bf16* __restrict__ al, __bf16* __restrict__ bh,
-                                           __bf16* __restrict__ bl, int tid) {
+                                           __bf16* __restrict__ bl, int tid, int64_t n, int64_t s,
+                                           int64_t c0, int64_t k0) {
   constexpr int NT = 32 * NB;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
@@ -698,8 +705,13 @@ __device__ __forceinline__ void st16_store(const St16Tile<NB>& t, __bf16* __rest
   for (int j = 0; j < 2 * NB; ++j) {
     const int e = tid + 256 * j;
     const int cc = e % NT, kp = e / NT;
+    const int64_t col = c0 + cc, kr = k0 + 2 * kp;
+    const bool cv = col < s;
+    // rows beyond n and columns beyond s were loaded from clamped addresses
+    const float v0 = t.v[2 * j] * ((cv && kr < n) ? 1.f : 0.f);
+    const float v1 = t.v[2 * j + 1] * ((cv && kr + 1 < n) ? 1.f : 0.f);
     uint32_t h, l;
-    split2(t.v[2 * j], t.v[2 * j + 1], h, l);
+    split2(v0, v1, h, l);
     *(uint32_t*)&bh[cc * S16 + 2 * kp] = h;
     *(uint32_t*)&bl[cc * S16 + 2 * kp] = l;
   }
@@ -760,19 +772,33 @@ __global__ __launch_bounds__(256, 2) void k_mm16_st(const __bf16* __restrict__ A
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
 
+    // Every stage load is issued unconditionally (past the segment's end it
+    // reloads the last stage, unused), so the number of loads in flight is
+    // the same on every path and the waits before each LDS store cover only
+    // that stage's loads (two stages stay in flight).
+    const int last = st1 - 1;
     St16Tile<NB> ta, tb;
     st16_load<NB>(ta, A, V, n, s, tile0 + st0, c0, (int64_t)st0 * BK, tid);
-    if (st0 + 1 < st1) st16_load<NB>(tb, A, V, n, s, tile0 + st0 + 1, c0, (int64_t)(st0 + 1) * BK, tid);
+    {
+      const int nx = st0 + 1 < last ? st0 + 1 : last;
+      st16_load<NB>(tb, A, V, n, s, tile0 + nx, c0, (int64_t)nx * BK, tid);
+    }
     __syncthreads();  // the previous segment's last stage is done with both buffers
     for (int st = st0; st < st1; st += 2) {
-      st16_store<NB>(ta, Ah[0], Al[0], Bh[0], Bl[0], tid);
+      st16_store<NB>(ta, Ah[0], Al[0], Bh[0], Bl[0], tid, n, s, c0, (int64_t)st * BK);
       __syncthreads();
-      if (st + 2 < st1) st16_load<NB>(ta, A, V, n, s, tile0 + st + 2, c0, (int64_t)(st + 2) * BK, tid);
+      {
+        const int nx = st + 2 < last ? st + 2 : last;
+        st16_load<NB>(ta, A, V, n, s, tile0 + nx, c0, (int64_t)nx * BK, tid);
+      }
       st16_compute<NB>(Ah[0], Al[0], Bh[0], Bl[0], acc, wave, li, lh);
       if (st + 1 >= st1) break;
-      st16_store<NB>(tb, Ah[1], Al[1], Bh[1], Bl[1], tid);
+      st16_store<NB>(tb, Ah[1], Al[1], Bh[1], Bl[1], tid, n, s, c0, (int64_t)(st + 1) * BK);
       __syncthreads();
-      if (st + 3 < st1) st16_load<NB>(tb, A, V, n, s, tile0 + st + 3, c0, (int64_t)(st + 3) * BK, tid);
+      {
+        const int nx = st + 3 < last ? st + 3 : last;
+        st16_load<NB>(tb, A, V, n, s, tile0 + nx, c0, (int64_t)nx * BK, tid);
+      }
       st16_compute<NB>(Ah[1], Al[1], Bh[1], Bl[1], acc, wave, li, lh);
     }
 

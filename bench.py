@@ -68,6 +68,8 @@ def log(*a):
 PROFILED_TRAFFIC = {
     "c2_matern_gm50k": ("profiles/c2_matern_gm50k_k_mm32_tf.md",
                         "paper_2405_03474_amd/csrc/matmat.hip"),
+    "c2_matern_gm50k_stored_bf16": ("profiles/c2_matern_gm50k_k_mm16_st.md",
+                                    "paper_2405_03474_amd/csrc/matmat.hip"),
 }
 
 
@@ -464,7 +466,9 @@ def surrogate_main(args, torch, L):
                                                items=items)[1], grid, edges)
         np.savez(args.dump, F_train=F, y_train=y, F_grid=Fg, predicted=predicted, spread=spread,
                  ref=ref, logdet_P=np.array([r["logdet_P"] for r in plain]),
-                 n_grid=np.array([g.n for g in grid]), edges=edges)
+                 n_grid=np.array([g.n for g in grid]), edges=edges,
+                 logdet_train=np.array([res[i]["logdet"] for i in ok]),
+                 n_train=np.array([train_insts[i].n for i in ok]))
     rel = np.abs(logdet - ref) / np.abs(ref)
     rel_pred = np.abs(predicted - ref) / np.abs(ref)
     avg_ms = mm_ms / max(mm_calls, 1)
@@ -682,6 +686,7 @@ def main():
         gbps = (mm_bytes / max(mm_calls, 1)) / (avg_ms / 1e3) / 1e9
         line["roofline"].update({
             "bound": "hbm", "achieved": gbps, "peak": 8000.0, "unit": "GB/s", "frac": gbps / 8000.0,
+            "traffic": profiled_traffic(cfg.name + "_stored_bf16") if not args.n else None,
             "kernel": "k_mm16_st<2> (split-BF16 MFMA 32x32x16, 3 terms, stored split tiles)",
             "flops_TFLOPs": achieved / 1e12})
     if kind in ("c2", "c3") and args.compare_fp32:

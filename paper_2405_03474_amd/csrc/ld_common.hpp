@@ -151,7 +151,14 @@ struct MatmatArgs {
 ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a);
 size_t matmat_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int64_t s);
 constexpr int kEpiRows = 128;  // rows per output tile of the product
-constexpr int kEpiSplit = 4;   // epilogue workgroups (dot partial rows) per output tile
+constexpr int kEpiSplitMax = 16;  // most epilogue workgroups (dot partial rows) per output tile
+// epilogue workgroups per output tile: 4, raised for small grids so that
+// about 1024 workgroups share the partial sums
+inline int epi_split(int64_t tiles) {
+  int sp = 4;
+  while (sp < kEpiSplitMax && tiles * sp < 1024) sp *= 2;
+  return sp;
+}
 void launch_materialize(hipStream_t st, const KParams& kp, const double* X, int64_t n, int d,
                         int precision, int layout, void* M);
 

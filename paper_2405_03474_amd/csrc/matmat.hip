@@ -1024,10 +1024,11 @@ __global__ __launch_bounds__(256, 2) void k_mm64(const double* __restrict__ A,
 }
 
 // --------------------------------------------------------------- epilogue --
-// Four workgroups per output tile, one per 32-row quarter (blockIdx.y):
-// Y = sum of the tile's partial slots in slot order (+ noise * V on the fly)
-// (+ alpha2 * X2); optional dots[4 rtile + quarter][c].  Each thread keeps
-// up to eight elements, so a slot's loads are issued together.
+// gridDim.y workgroups per output tile (epi_split: 4, up to 16 for small
+// grids), one per row slice (blockIdx.y): Y = sum of the tile's partial slots
+// in slot order (+ noise * V on the fly) (+ alpha2 * X2); optional
+// dots[split rtile + slice][c].  Each thread keeps up to eight elements, so
+// a slot's loads are issued together.
 template <typename T>
 __global__ __launch_bounds__(256) void k_epilogue(const T* __restrict__ part, SK p, int NT,
                                                   T* __restrict__ Y, const T* __restrict__ V,
@@ -1038,7 +1039,8 @@ __global__ __launch_bounds__(256) void k_epilogue(const T* __restrict__ part, SK
   __shared__ int nslot;
   const int tid = threadIdx.x;
   const int64_t Tt = blockIdx.x;
-  const int quarter = blockIdx.y;
+  const int quarter = blockIdx.y;  // row slice of the tile (gridDim.y slices)
+  const int split = gridDim.y;
   const int rtile = (int)(Tt % p.rt);
   const int64_t c0 = (Tt / p.rt) * NT;
   const int64_t i0 = (int64_t)rtile * BM;
@@ -1069,7 +1071,7 @@ __global__ __launch_bounds__(256) void k_epilogue(const T* __restrict__ part, SK
   __syncthreads();
   const int ns = nslot;
   const int col = tid % NT;  // 256 is a multiple of NT
-  const int cnt = (BM / kEpiSplit) * NT;  // elements of the quarter (<= 8 per thread)
+  const int cnt = (BM / split) * NT;  // elements of the slice (<= 8 per thread)
   const int e0 = quarter * cnt;
   double sum[8];
 #pragma unroll
@@ -1106,7 +1108,7 @@ __global__ __launch_bounds__(256) void k_epilogue(const T* __restrict__ part, SK
       double t = 0.0;
       for (int q = tid; q < 256; q += NT) t += red[q];
       const int64_t c = c0 + tid;
-      if (c < p.s) dots[((int64_t)rtile * kEpiSplit + quarter) * p.s + c] = t;
+      if (c < p.s) dots[((int64_t)rtile * split + quarter) * p.s + c] = t;
     }
   }
 }
@@ -1387,7 +1389,7 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
     }
     if (ev1) LD_HIP(hipEventRecord(ev1, st));
     const int64_t tiles = (int64_t)pl.p.rt * ((a.s + pl.NT - 1) / pl.NT);
-    hipLaunchKernelGGL(k_epilogue<double>, dim3((unsigned)tiles, kEpiSplit), dim3(256), 0, st, P, pl.p, pl.NT,
+    hipLaunchKernelGGL(k_epilogue<double>, dim3((unsigned)tiles, epi_split(tiles)), dim3(256), 0, st, P, pl.p, pl.NT,
                        (double*)a.Y, V, fly ? a.kp.noise : 0.0, (const double*)a.X2, a.alpha2,
                        a.dots);
   } else {
@@ -1427,12 +1429,13 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
     }
     if (ev1) LD_HIP(hipEventRecord(ev1, st));
     const int64_t tiles = (int64_t)pl.p.rt * ((a.s + pl.NT - 1) / pl.NT);
-    hipLaunchKernelGGL(k_epilogue<float>, dim3((unsigned)tiles, kEpiSplit), dim3(256), 0, st, P, pl.p, pl.NT,
+    hipLaunchKernelGGL(k_epilogue<float>, dim3((unsigned)tiles, epi_split(tiles)), dim3(256), 0, st, P, pl.p, pl.NT,
                        (float*)a.Y, V,
                        fly ? a.kp.noise : (a.bf16 ? a.kp.variance + a.kp.noise : 0.0),
                        (const float*)a.X2, a.alpha2, a.dots);
   }
-  if (a.dot_blocks) *a.dot_blocks = pl.p.rt * kEpiSplit;
+  if (a.dot_blocks)
+    *a.dot_blocks = pl.p.rt * epi_split((int64_t)pl.p.rt * ((a.s + pl.NT - 1) / pl.NT));
   LD_HIP(hipGetLastError());
   return LD_OK;
 }

@@ -1038,7 +1038,7 @@ ld_status lanczos_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_pr
   T* r = (T*)ctx->arena.take(vec * sizeof(T));
   T* u = (T*)ctx->arena.take(vec * sizeof(T));
   T* ut = (T*)ctx->arena.take(vec * sizeof(T));
-  const int64_t mrt = (n + kEpiRows - 1) / kEpiRows * kEpiSplit;
+  const int64_t mrt = (n + kEpiRows - 1) / kEpiRows * kEpiSplitMax;
   const int64_t wrt = wood_dot_blocks(f64, n);
   double* dwq = (double*)ctx->arena.take((size_t)mrt * s * sizeof(double));
   double* d1 = (double*)ctx->arena.take((size_t)wrt * s * sizeof(double));
@@ -1159,7 +1159,7 @@ ld_status lanczos_estimate(ld_ctx* ctx, bool f64, const MatmatArgs& base, const 
 size_t lanczos_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int rank, int64_t s, int t) {
   const size_t es = f64 ? 8 : 4;
   size_t b = 5 * (size_t)n * s * es + 1280;
-  b += ((n + kEpiRows - 1) / kEpiRows * kEpiSplit + 2 * ((n + 63) / 64)) * (size_t)s * 8 + 768;
+  b += ((n + kEpiRows - 1) / kEpiRows * kEpiSplitMax + 2 * ((n + 63) / 64)) * (size_t)s * 8 + 768;
   b += 2 * (size_t)kSeg * s * 8 + 512;
   b += ((size_t)(3 * t + 1) * s + 8 * s + 3) * 8 + (size_t)(2 * s + 2) * 4 + 512;
   b += std::max(matmat_scratch_bytes(ctx, f64, n, s), woodbury_scratch_bytes(n, rank, s)) + 1024;
@@ -1197,7 +1197,7 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
   T* p = (T*)ctx->arena.take(vec * sizeof(T));
   T* w = (T*)ctx->arena.take(vec * sizeof(T));
   T* q = (T*)ctx->arena.take(vec * sizeof(T));
-  const int64_t mrt = (n + kEpiRows - 1) / kEpiRows * kEpiSplit;  // matmat dot blocks
+  const int64_t mrt = (n + kEpiRows - 1) / kEpiRows * kEpiSplitMax;  // matmat dot blocks
   const int64_t wrt = wood_dot_blocks(f64, n);  // woodbury dot blocks
   double* dwq = (double*)ctx->arena.take((size_t)mrt * s * sizeof(double));
   double* d1 = (double*)ctx->arena.take((size_t)wrt * s * sizeof(double));
@@ -1361,7 +1361,7 @@ void launch_scal_beta(hipStream_t st, const Scal& S, const double* d1, const dou
 size_t pcg_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int rank, int64_t s, int J) {
   const size_t es = f64 ? 8 : 4;
   size_t b = 5 * (size_t)n * s * es + 1280;
-  b += ((n + kEpiRows - 1) / kEpiRows * kEpiSplit + 2 * ((n + 63) / 64)) * (size_t)s * 8 + 768;
+  b += ((n + kEpiRows - 1) / kEpiRows * kEpiSplitMax + 2 * ((n + 63) / 64)) * (size_t)s * 8 + 768;
   b += (size_t)(7 * s + 4 * J * s + J) * 8 + (size_t)(J * s + s + 2) * 4 + 512;
   b += 2 * (size_t)kSeg * s * 8 + (size_t)(s + 2) * 8 + 768;
   b += std::max(matmat_scratch_bytes(ctx, f64, n, s), woodbury_scratch_bytes(n, rank, s)) + 1024;

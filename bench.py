@@ -44,6 +44,7 @@ import json
 import os
 import sys
 import time
+from dataclasses import replace
 
 import numpy as np
 
@@ -532,6 +533,49 @@ def surrogate_cpu_baseline(grid, cfg, count):
                       f"at n={pick[0].n}: {dt:.2f} s"}
 
 
+def sensitivity_main(args, torch, L):
+    """The Appendix's sensitivity sweeps (one parameter at a time around the
+    paper's choice, Matern-5/2 in d = 5) or the Section 3 sweep over d;
+    errors against the exact log det of each stored FP64 matrix."""
+    from paper_2405_03474_amd import sensitivity as S
+    torch.cuda.set_device(0)
+    ctx = L.Context(0)
+    n, count = args.sens_n, args.sens_count
+    base = S.Setting()
+    t0 = time.perf_counter()
+    if args.sensitivity == "axes":
+        axes = dict(S.AXES, solver=["lanczos", "cg"])
+        settings = S.axis_settings(base, axes, orders=(1, 3, 5))
+        insts = workloads.sensitivity_instances(workloads.MATERN52, 5, count, n=n)
+        cells, exacts = S.sweep(ctx, insts, settings, torch, log=log)
+        rows = [{"axis": a, "value": v, "k": k, **cells[(a, v, k)].summary()}
+                for (a, v, k) in settings]
+    else:
+        ds = [int(x) for x in args.sens_dims.split(",")]
+        settings = {("lanczos", k): replace(base, k=k) for k in (1, 3, 5)}
+        settings[("cg", 3)] = replace(base, k=3, solver="cg")
+        rows, exacts = [], []
+        for kind in (workloads.RBF, workloads.MATERN52):
+            for d in ds:
+                insts = workloads.sensitivity_instances(kind, d, count, n=n)
+                cells, ex = S.sweep(ctx, insts, settings, torch, log=log)
+                exacts += ex
+                rows += [{"kernel": "rbf" if kind == workloads.RBF else "matern52", "d": d,
+                          "solver": sv, "k": k, **cells[(sv, k)].summary()}
+                         for (sv, k) in settings]
+    wall = time.perf_counter() - t0
+    line = {"metric": "sensitivity_" + args.sensitivity, "n": n, "instances_per_point": count,
+            "noise": workloads.sensitivity_instances(1, 1, 1, n=2)[0].noise,
+            "base": {"probes": base.probes, "steps": base.steps, "rank": base.rank,
+                     "power_iters": base.power_iters, "oversample": base.oversample},
+            "dtype": "f64", "data": "synthetic", "seconds": wall, "rows": rows,
+            "mean_abs_exact_logdet": float(np.mean(np.abs(exacts)))}
+    if args.dump:
+        with open(args.dump, "w") as f:
+            json.dump(line, f, indent=1)
+    print(json.dumps(line))
+
+
 def timed_steps(runner, steps, warmup, stream, torch):
     for w in range(warmup):
         t0 = time.perf_counter()
@@ -591,6 +635,11 @@ def main():
                     help="c1/c2/c3: time d log det / d(lengthscale, variance, noise) instead")
     ap.add_argument("--scaled", action="store_true",
                     help="the preconditioner's 'plus scaling' variant (D = noise I)")
+    ap.add_argument("--sensitivity", default="", choices=["", "axes", "dims"],
+                    help="the Appendix's parameter sweeps (axes) or the sweep over d (dims)")
+    ap.add_argument("--sens-n", type=int, default=20000)
+    ap.add_argument("--sens-count", type=int, default=8, help="problems per sweep point")
+    ap.add_argument("--sens-dims", default="1,2,3,4,5,6,8,10,12,15,20")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the workload, run one device-to-device copy of this many MiB "
                          "(the reference dispatch for HBM byte counters)")
@@ -602,6 +651,8 @@ def main():
     import torch
     import paper_2405_03474_amd as L
 
+    if args.sensitivity:
+        return sensitivity_main(args, torch, L)
     if args.workload == "c4_batch256":
         return batch_main(args, torch, L)
     if args.workload == "c5_surrogate":

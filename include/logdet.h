@@ -68,7 +68,9 @@ typedef enum { LD_F64 = 0, LD_F32 = 1, LD_BF16 = 2 } ld_precision;
 typedef struct {
   const double* X;        /* device, n x d points (FP64) */
   int64_t n;              /* number of points, >= 1 */
-  int32_t d;              /* dimension, 1..16 */
+  int32_t d;              /* dimension, 1..64; generating entries on the fly
+                             (M_stored NULL in any call but kernel_materialize,
+                             and every logdet_gradient) needs d <= 16 */
   int32_t kind;           /* ld_kernel */
   double lengthscale;     /* > 0 */
   double variance;        /* signal variance, > 0 */

@@ -102,11 +102,16 @@ void timing_collect(ld_ctx* ctx) {
   ctx->pending_bytes.clear();
 }
 
-ld_status check_operator(const ld_operator* op) {
+// generate: the call may generate kernel entries on the fly from the points
+// (all calls but kernel_materialize when M is not stored); the fused
+// generation kernels keep a point's coordinates in registers, up to 16
+ld_status check_operator(const ld_operator* op, bool generate) {
   if (!op) return fail(LD_EINVAL, "operator is NULL");
   if (!op->X) return fail(LD_EINVAL, "operator X is NULL");
   if (op->n < 1) return fail(LD_EINVAL, "n must be >= 1");
-  if (op->d < 1 || op->d > 16) return fail(LD_EINVAL, "d must be in 1..16");
+  if (op->d < 1 || op->d > 64) return fail(LD_EINVAL, "d must be in 1..64");
+  if (generate && !op->M_stored && op->d > 16)
+    return fail(LD_EINVAL, "kernel entries on the fly need d <= 16; store M (kernel_materialize) for larger d");
   if (op->kind != LD_RBF && op->kind != LD_MATERN52) return fail(LD_EINVAL, "unknown kernel kind");
   if (!(op->lengthscale > 0.0) || !std::isfinite(op->lengthscale))
     return fail(LD_EINVAL, "lengthscale must be finite and > 0");
@@ -468,14 +473,18 @@ ld_status build_precond(ld_ctx* ctx, const ld_operator* op, int rank, int oversa
   launch_fill_gaussian(st, stream_key(seed, kStreamOmega), n, m, Qb);
   LD_TRY(apply_M64(ctx, op, Xp, Qb, Yb, m, t1, t2));
   double* Q = nullptr;
-  // intermediate bases only need to span the sketch (one shifted pass); the
-  // basis used for the Rayleigh-Ritz step is made orthonormal (three passes)
-  LD_TRY(orthonormalize(ctx, Yb, Qb, n, m, G, Rinv, okd, power_iters == 0 ? 3 : 1, &Q));
+  // intermediate bases are made orthonormal too (a shifted pass and a plain
+  // one): after a shifted pass alone the small singular values of the basis
+  // are only partly restored, the next product scales them by the ratio of
+  // M's extreme eigenvalues again, and over several power iterations the
+  // sketch's condition number grows past what CholeskyQR can handle.  The
+  // basis used for the Rayleigh-Ritz step gets three passes.
+  LD_TRY(orthonormalize(ctx, Yb, Qb, n, m, G, Rinv, okd, power_iters == 0 ? 3 : 2, &Q));
   // 3. subspace iterations
   for (int it = 0; it < power_iters; ++it) {
     double* other = (Q == Qb) ? Yb : Qb;
     LD_TRY(apply_M64(ctx, op, Xp, Q, other, m, t1, t2));
-    LD_TRY(orthonormalize(ctx, other, Q, n, m, G, Rinv, okd, it + 1 == power_iters ? 3 : 1, &Q));
+    LD_TRY(orthonormalize(ctx, other, Q, n, m, G, Rinv, okd, it + 1 == power_iters ? 3 : 2, &Q));
   }
   // 4. B = Q^T M Q and its eigenpairs
   double* MQ = (Q == Qb) ? Yb : Qb;
@@ -785,7 +794,7 @@ ld_status kernel_matmat(ld_ctx* ctx, const ld_operator* op, const void* V, int64
 
 ld_status kernel_materialize(ld_ctx* ctx, const ld_operator* op, void* M_out) {
   LD_TRY(check_ctx(ctx));
-  LD_TRY(check_operator(op));
+  LD_TRY(check_operator(op, false));
   if (!M_out) return fail(LD_EINVAL, "M_out is NULL");
   if (op->precision == LD_BF16 && op->layout != LD_TILED)
     return fail(LD_EINVAL, "a stored LD_BF16 matrix must use the LD_TILED layout");
@@ -1089,6 +1098,7 @@ ld_status logdet_gradient(ld_ctx* ctx, const ld_operator* op, const ld_precond* 
                           double* grad, double* std_err, double* per_probe, ld_result* out) {
   LD_TRY(check_ctx(ctx));
   LD_TRY(check_operator(op));
+  if (op->d > 16) return fail(LD_EINVAL, "the derivative products are generated on the fly: d <= 16");
   if (!grad) return fail(LD_EINVAL, "grad is NULL");
   if (num_probes < 1) return fail(LD_EINVAL, "num_probes must be >= 1");
   if (!(tol > 0.0) || !std::isfinite(tol)) return fail(LD_EINVAL, "tol must be finite and > 0");

@@ -1382,11 +1382,11 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
                      b.mmax, f.Q);
   b_apply(st, b, f, sketch, f.Q, f.Y);
   double* Qb = nullptr;
-  b_orth(st, b, f, f.Y, f.Q, power_iters == 0 ? 3 : 1, &Qb);
+  b_orth(st, b, f, f.Y, f.Q, power_iters == 0 ? 3 : 2, &Qb);
   for (int it = 0; it < power_iters; ++it) {
     double* other = Qb == f.Q ? f.Y : f.Q;
     b_apply(st, b, f, sketch, Qb, other);
-    b_orth(st, b, f, other, Qb, it + 1 == power_iters ? 3 : 1, &Qb);
+    b_orth(st, b, f, other, Qb, it + 1 == power_iters ? 3 : 2, &Qb);
   }
   double* MQ = Qb == f.Q ? f.Y : f.Q;
   b_apply(st, b, f, sketch, Qb, MQ);

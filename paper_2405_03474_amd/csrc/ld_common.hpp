@@ -112,7 +112,8 @@ struct KParams {
 };
 KParams make_kparams(const ld_operator& op);
 
-ld_status check_operator(const ld_operator* op);
+// generate: the call may generate kernel entries on the fly (needs d <= 16)
+ld_status check_operator(const ld_operator* op, bool generate = true);
 ld_status ensure_pinned(ld_ctx* ctx, size_t count);
 // event timing: reserve a (start, stop) pair, and fold finished pairs into
 // the totals (call only after the stream has been synchronized)

@@ -1114,19 +1114,20 @@ __global__ __launch_bounds__(256) void k_epilogue(const T* __restrict__ part, SK
 }
 
 // ------------------------------------------------------------ materialize --
-template <typename T, int KIND>
+// DM = DMAX (the fused kernels' limit) or 64 (the largest d the ABI takes)
+template <typename T, int KIND, int DM>
 __global__ __launch_bounds__(256) void k_materialize(const double* __restrict__ X, int64_t n, int d,
                                                      double var, double c, double noise,
                                                      T* __restrict__ M) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  double xj[DMAX];
+  double xj[DM];
 #pragma unroll
-  for (int dd = 0; dd < DMAX; ++dd) xj[dd] = (dd < d && j < n) ? X[j * d + dd] : 0.0;
+  for (int dd = 0; dd < DM; ++dd) xj[dd] = (dd < d && j < n) ? X[j * d + dd] : 0.0;
   for (int64_t i = blockIdx.y; i < n; i += gridDim.y) {
     if (j >= n) continue;
     double r2 = 0.0;
 #pragma unroll
-    for (int dd = 0; dd < DMAX; ++dd)
+    for (int dd = 0; dd < DM; ++dd)
       if (dd < d) {
         const double df = X[i * d + dd] - xj[dd];
         r2 = fma(df, df, r2);
@@ -1440,6 +1441,21 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
   return LD_OK;
 }
 
+template <typename T>
+void materialize_rm(hipStream_t st, int kind, bool small_d, dim3 grid, const double* X, int64_t n,
+                    int d, double var, double c, double noise, T* M) {
+  if (kind == LD_RBF && small_d)
+    hipLaunchKernelGGL((k_materialize<T, LD_RBF, DMAX>), grid, dim3(256), 0, st, X, n, d, var, c, noise, M);
+  else if (kind == LD_RBF)
+    hipLaunchKernelGGL((k_materialize<T, LD_RBF, 64>), grid, dim3(256), 0, st, X, n, d, var, c, noise, M);
+  else if (small_d)
+    hipLaunchKernelGGL((k_materialize<T, LD_MATERN52, DMAX>), grid, dim3(256), 0, st, X, n, d, var, c,
+                       noise, M);
+  else
+    hipLaunchKernelGGL((k_materialize<T, LD_MATERN52, 64>), grid, dim3(256), 0, st, X, n, d, var, c,
+                       noise, M);
+}
+
 void launch_materialize(hipStream_t st, const KParams& kp, const double* X, int64_t n, int d,
                         int precision, int layout, void* M) {
   const double c = kp.kind == LD_RBF ? kp.c_rbf : kp.c_mat;
@@ -1470,21 +1486,12 @@ void launch_materialize(hipStream_t st, const KParams& kp, const double* X, int6
   }
   int64_t gy = n < 256 ? n : 256;
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)gy);
-  if (f64) {
-    if (kp.kind == LD_RBF)
-      hipLaunchKernelGGL((k_materialize<double, LD_RBF>), grid, dim3(256), 0, st, X, n, d,
-                         kp.variance, c, kp.noise, (double*)M);
-    else
-      hipLaunchKernelGGL((k_materialize<double, LD_MATERN52>), grid, dim3(256), 0, st, X, n, d,
-                         kp.variance, c, kp.noise, (double*)M);
-  } else {
-    if (kp.kind == LD_RBF)
-      hipLaunchKernelGGL((k_materialize<float, LD_RBF>), grid, dim3(256), 0, st, X, n, d,
-                         kp.variance, c, kp.noise, (float*)M);
-    else
-      hipLaunchKernelGGL((k_materialize<float, LD_MATERN52>), grid, dim3(256), 0, st, X, n, d,
-                         kp.variance, c, kp.noise, (float*)M);
-  }
+  if (f64)
+    materialize_rm<double>(st, kp.kind, d <= DMAX, grid, X, n, d, kp.variance, c, kp.noise,
+                           (double*)M);
+  else
+    materialize_rm<float>(st, kp.kind, d <= DMAX, grid, X, n, d, kp.variance, c, kp.noise,
+                          (float*)M);
 }
 
 void launch_convert_f64_to_f32(hipStream_t st, const double* in, float* out, int64_t count) {

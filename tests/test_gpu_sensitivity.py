@@ -1,0 +1,89 @@
+"""GPU check of the sensitivity sweeps: the exact log det they measure
+against and the estimates they record agree with the oracle (Cholesky log
+det; Algorithm 1 and the exact shifted solves with the same preconditioner
+and probes) on a small Section 3 problem set."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import estimate as oest
+from oracle import gp, lanczos as olz, precond as oprec
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # collected on CPU hosts but never run there
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2405_03474_amd as L  # noqa: E402
+from paper_2405_03474_amd import sensitivity as S  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = L.Context(0)
+    yield c
+    c.close()
+
+
+def test_sweep_matches_oracle(ctx):
+    insts = workloads.sensitivity_instances(workloads.MATERN52, 5, 2, n=700)
+    settings = {"alg1_r3": S.Setting(),
+                "cg_r3": S.Setting(solver="cg", tol=1e-12),
+                # CG here: t = 20 Lanczos steps with this preconditioner lose
+                # orthogonality (spectrum of M P^-1 up to ~50), and their output
+                # moves by ~1e-6 relative under 1e-15 perturbations of M
+                "pchol_r5": S.Setting(k=5, precond=L.LD_PRECOND_PCHOL, solver="cg", tol=1e-12)}
+    cells, exacts = S.sweep(ctx, insts, settings, torch)
+    for i, g in enumerate(insts):
+        M = gp.dense_matrix(g.kind, g.X(), g.lengthscale, g.variance, g.noise)
+        exact = oest.logdet_exact(M)
+        assert exacts[i] == pytest.approx(exact, rel=1e-12)
+        floor = oprec.d_floor(g.noise, g.variance)
+        Z = oest.probes(g.probe_seed, g.n, g.probes)
+        P = oprec.rsvd(M, 25, 10, 5, g.precond_seed, floor)
+        want, _, _ = olz.estimate_lanczos(M, P.dense(), P.logdet, 3, Z, 20)
+        assert cells["alg1_r3"].signed[i] + exact == pytest.approx(want.logdet, rel=1e-10)
+        want = oest.estimate_dense(M, P.dense(), P.logdet, 3, Z)
+        assert cells["cg_r3"].signed[i] + exact == pytest.approx(want.logdet, rel=1e-10)
+        Pc = oprec.partial_cholesky(M, 25, floor)
+        want = oest.estimate_dense(M, Pc.dense(), Pc.logdet, 5, Z)
+        assert cells["pchol_r5"].signed[i] + exact == pytest.approx(want.logdet, rel=1e-10)
+    for c in cells.values():
+        s = c.summary()
+        assert s["count"] == 2 and s["mean_seconds"] > 0
+        assert s["mean_abs_err"] == pytest.approx(np.mean(np.abs(c.signed)))
+
+
+@pytest.mark.parametrize("d", [20, 64])
+def test_high_dimension_stored(ctx, d):
+    # the sweep over d needs d > 16: stored matrices take d <= 64, entries
+    # generated on the fly d <= 16
+    g = workloads.sensitivity_instances(workloads.RBF, d, 1, n=500)[0]
+    X = g.X()
+    M = gp.dense_matrix(g.kind, X, g.lengthscale, g.variance, g.noise)
+    Xd = torch.as_tensor(X, dtype=torch.float64, device="cuda:0")
+    op = L.GPOperator(X=Xd, kind=g.kind, lengthscale=g.lengthscale, variance=g.variance,
+                      noise=g.noise, precision=L.LD_F64)
+    with pytest.raises(L.LogdetError, match="LD_EINVAL"):
+        L.kernel_matmat(ctx, op, torch.ones((500, 2), dtype=torch.float64, device="cuda:0"))
+    op.M = L.kernel_materialize(ctx, op)
+    np.testing.assert_allclose(op.M.cpu().numpy(), M, rtol=1e-13, atol=1e-15)
+    op32 = L.GPOperator(X=Xd, kind=g.kind, lengthscale=g.lengthscale, variance=g.variance,
+                        noise=g.noise, precision=L.LD_F32)
+    np.testing.assert_allclose(L.kernel_materialize(ctx, op32).double().cpu().numpy(), M,
+                               rtol=1e-6, atol=1e-7)
+    P = L.Precond(ctx, op, 25, 10, 5, g.precond_seed)
+    if d == 20:   # at d = 64 M is 1.01 I to 3e-10: the top-25 subspace is tied
+        res, per = L.logdet_estimate(ctx, op, P, 3, 16, g.probe_seed, 1e-12, 5000)
+        ref = oprec.rsvd(M, 25, 10, 5, g.precond_seed, oprec.d_floor(g.noise, g.variance))
+        want = oest.estimate_dense(M, ref.dense(), ref.logdet, 3,
+                                   oest.probes(g.probe_seed, 500, 16))
+        np.testing.assert_allclose(per, want.per_probe, rtol=1e-9)
+    with pytest.raises(L.LogdetError, match="LD_EINVAL"):
+        L.logdet_gradient(ctx, op, P, 4, 1, 1e-8)
+    bad = L.GPOperator(X=torch.zeros((10, 65), dtype=torch.float64, device="cuda:0"),
+                       kind=g.kind, lengthscale=1.0, variance=1.0, noise=1e-2,
+                       precision=L.LD_F64)
+    with pytest.raises(L.LogdetError, match="LD_EINVAL"):
+        L.kernel_materialize(ctx, bad)

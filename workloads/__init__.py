@@ -21,6 +21,11 @@ as well, Section 3):
                   RBF or Matern-5/2, l log-U[0.02,0.5], s2 log-U[0.5,2],
                   noise log-U[1e-4,1e-1], points uniform in [0,1]^d; r_3;
                   16 probes; rank min(200, n/10).
+  sensitivity     the Appendix's parameter sweeps (Section 3 setting):
+                  amplitude and lengthscale 1, index points standard normal
+                  in R^d, noise 1e-2 (the paper does not print it), RBF or
+                  Matern-5/2, n = 20,000; the paper's estimator parameters
+                  (35 Rademacher probes, t = 20, rank 25, 5 iterations).
   c5_surrogate    training set: instances with the c4 hyperparameter
                   distribution at one fixed n (r_5, 64 probes, rank n/40);
                   evaluation grid: 32 x 32 log-spaced lengthscales in
@@ -70,6 +75,8 @@ def make_points(kind: str, n: int, d: int, seed: int) -> np.ndarray:
     g = np.random.default_rng(seed)
     if kind == "uniform":
         return g.random((n, d))
+    if kind == "normal":
+        return g.standard_normal((n, d))
     if kind == "gmix8":
         means = g.random((8, d))
         labels = g.integers(0, 8, size=n)
@@ -140,4 +147,21 @@ def surrogate_grid(n: int, side: int = 32, seed: int = BASE_SEED + 5, probes: in
                                   variance=1.0, noise=float(nz), points="uniform", seed=seed,
                                   rank=max(1, n // 40), probes=probes, orders=(5,),
                                   probe_seed=seed + 10000 + i, precond_seed=seed + 20000 + i))
+    return out
+
+
+def sensitivity_instances(kind: int, d: int, count: int, n: int = 20000, noise: float = 1e-2,
+                          seed: int = BASE_SEED + 6, probes: int = 35):
+    """Problems of the Appendix's sweeps: amplitude 1, lengthscale 1, index
+    points standard normal in R^d (Section 3); rank 25 and 5 power iterations
+    are the paper's preconditioner parameters.  Instance i of (kind, d) has
+    its own point cloud, probe seed and sketch seed."""
+    out = []
+    for i in range(count):
+        tag = (kind * 64 + d) * 1000 + i
+        out.append(GPInstance(f"sens_{'rbf' if kind == RBF else 'm52'}_d{d}_{i}", n=n, d=d,
+                              kind=kind, lengthscale=1.0, variance=1.0, noise=noise,
+                              points="normal", seed=seed * 1000003 + tag, rank=25,
+                              power_iters=5, probes=probes, orders=(1, 3, 5),
+                              probe_seed=seed + 10 ** 7 + tag, precond_seed=seed + 2 * 10 ** 7 + tag))
     return out

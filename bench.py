@@ -161,9 +161,10 @@ class Runner:
     """One problem instance on the GPU in a given arithmetic."""
 
     def __init__(self, L, torch, ctx, cfg, precision, stored, lanczos_steps=0, pkind="rsvd",
-                 scaled=False):
+                 scaled=False, union=False):
         self.L, self.torch, self.ctx, self.cfg = L, torch, ctx, cfg
         self.lanczos_steps = lanczos_steps
+        self.union = union
         self.pkind = PRECOND_KINDS[pkind]
         self.scaled = scaled
         dev = torch.device("cuda:0")
@@ -188,6 +189,13 @@ class Runner:
             op.M = self.Mbuf
         P = L.Precond(self.ctx, op, cfg.rank, cfg.oversample, cfg.power_iters, cfg.precond_seed,
                       kind=self.pkind, scaled=self.scaled)
+        if self.union and not self.lanczos_steps:
+            # every order from one solve over the union of the poles, one
+            # shared probe block
+            res, _ = L.logdet_estimate_orders(self.ctx, op, P, list(cfg.orders), cfg.probes,
+                                              cfg.probe_seed, self.tol, 5000)
+            P.close()
+            return dict(zip(cfg.orders, res))
         for k in cfg.orders:
             if self.lanczos_steps:
                 res, per = L.logdet_estimate_lanczos(self.ctx, op, P, k, cfg.probes,
@@ -635,6 +643,9 @@ def main():
                     help="c1/c2/c3: time d log det / d(lengthscale, variance, noise) instead")
     ap.add_argument("--scaled", action="store_true",
                     help="the preconditioner's 'plus scaling' variant (D = noise I)")
+    ap.add_argument("--union-shifts", action="store_true",
+                    help="all orders from one solve over the union of their poles "
+                         "(shared probes; reported separately from the default)")
     ap.add_argument("--sensitivity", default="", choices=["", "axes", "dims"],
                     help="the Appendix's parameter sweeps (axes) or the sweep over d (dims)")
     ap.add_argument("--sens-n", type=int, default=20000)
@@ -678,7 +689,7 @@ def main():
     ctx.set_probes({"rademacher": L.LD_PROBE_RADEMACHER, "gaussian": L.LD_PROBE_GAUSSIAN,
                     "orthogonal": L.LD_PROBE_ORTHOGONAL}[args.probes])
     runner = Runner(L, torch, ctx, cfg, precision, stored, args.lanczos_steps, args.precond,
-                    args.scaled)
+                    args.scaled, args.union_shifts)
     results, ms_total, wall, (mm_ms, mm_calls, mm_flops, mm_bytes) = timed_steps(
         runner, args.steps, args.warmup, stream, torch)
 
@@ -725,7 +736,8 @@ def main():
                    "probe_kind": args.probes,
                    "solver": ({"kind": "lanczos", "steps": args.lanczos_steps}
                               if args.lanczos_steps else
-                              {"kind": "multishift_pcg", "tol": runner.tol})},
+                              {"kind": "multishift_pcg", "tol": runner.tol,
+                               "orders_share_probes": bool(args.union_shifts)})},
         "probe_solves_per_s": cfg.probes * n_est / (ms_total / 1e3),
         "iterations": {f"r{k}": last[k]["iterations"] for k in cfg.orders},
         "wall_s": wall, "accuracy": accuracy, "roofline": roofline,

@@ -270,6 +270,26 @@ ld_status logdet_estimate(ld_ctx* ctx, const ld_operator* op, const ld_precond* 
                           int32_t num_probes, uint64_t probe_seed, double tol, int32_t max_iters,
                           ld_result* out, double* per_probe);
 
+/* Several orders from one Krylov space: the estimates of logdet_estimate for
+ * every k in ks[], with one probe block shared by all of them.  The poles of
+ * the requested r_k form one shift set (r_1, r_3 and r_5 together have 7
+ * distinct poles: 1 is a pole of each), the multi-shift CG runs on its
+ * smallest shift, and each order combines the shifted solutions of its own
+ * poles with its own partial-fraction coefficients (Table 1).  Each estimate
+ * equals logdet_estimate's with the same probe_seed up to the solver
+ * tolerance; the estimates share probes, so their errors are correlated.
+ *   ks         host array of num_orders distinct values in {1, 3, 5}
+ *   num_orders 1..3
+ *   P, num_probes, probe_seed, tol, max_iters  as for logdet_estimate
+ *   out        host array of num_orders results (filled on LD_OK and on
+ *              LD_ENOCONV; iterations and residuals are the shared solver's)
+ *   per_probe  host array of num_orders x s doubles (order-major), or NULL
+ * Synchronizes. */
+ld_status logdet_estimate_orders(ld_ctx* ctx, const ld_operator* op, const ld_precond* P,
+                                 int32_t num_orders, const int32_t* ks, int32_t num_probes,
+                                 uint64_t probe_seed, double tol, int32_t max_iters,
+                                 ld_result* out, double* per_probe);
+
 /* Gradient of log det M with respect to (lengthscale, variance, noise) by
  * Hutchinson's estimator over probe solves (the CG-based gradient the paper
  * tunes its parameters with, Section 3):

@@ -1063,6 +1063,79 @@ ld_status logdet_estimate(ld_ctx* ctx, const ld_operator* op, const ld_precond* 
   return LD_OK;
 }
 
+ld_status logdet_estimate_orders(ld_ctx* ctx, const ld_operator* op, const ld_precond* P,
+                                 int32_t num_orders, const int32_t* ks, int32_t num_probes,
+                                 uint64_t probe_seed, double tol, int32_t max_iters,
+                                 ld_result* out, double* per_probe) {
+  if (!out) return fail(LD_EINVAL, "out is NULL");
+  if (!ks) return fail(LD_EINVAL, "ks is NULL");
+  if (num_orders < 1 || num_orders > 3) return fail(LD_EINVAL, "num_orders must be in 1..3");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(LD_EINVAL, "tol must be finite and > 0");
+  if (max_iters < 1) return fail(LD_EINVAL, "max_iters must be >= 1");
+  Rational rf[3];
+  for (int o = 0; o < num_orders; ++o) {
+    if (!rational_for(ks[o], &rf[o])) return fail(LD_EINVAL, "every k must be 1, 3 or 5");
+    for (int q = 0; q < o; ++q)
+      if (ks[q] == ks[o]) return fail(LD_EINVAL, "orders must be distinct");
+  }
+  // the union of the poles, ascending (the smallest is the CG's seed); a
+  // pole shared by several orders (1 is a pole of every r_k with odd k) is
+  // one shift
+  std::vector<double> sh;
+  for (int o = 0; o < num_orders; ++o)
+    for (int m = 0; m < ks[o]; ++m) {
+      const double a = rf[o].a[m];
+      bool seen = false;
+      for (double x : sh) seen = seen || std::fabs(x - a) <= 1e-12 * std::max(x, a);
+      if (!seen) sh.push_back(a);
+    }
+  std::sort(sh.begin(), sh.end());
+  const int J = (int)sh.size();
+  Coef cfs[3];
+  for (int o = 0; o < num_orders; ++o) {
+    Coef& cf = cfs[o];
+    cf = Coef{};
+    cf.b = rf[o].b;
+    cf.J = J;
+    for (int j = 0; j < J; ++j) {
+      cf.a[j] = sh[j];
+      for (int m = 0; m < ks[o]; ++m)
+        if (std::fabs(sh[j] - rf[o].a[m]) <= 1e-12 * std::max(sh[j], rf[o].a[m])) cf.c[j] = rf[o].c[m];
+    }
+  }
+  EstSetup e;
+  LD_TRY(est_setup(ctx, op, P, ks[0], num_probes, probe_seed, 0, pcg_scratch_bytes, J, e));
+  const int64_t s = num_probes;
+  auto t0 = std::chrono::steady_clock::now();
+  std::vector<double> t;
+  double mean[3] = {0.0, 0.0, 0.0}, se[3] = {0.0, 0.0, 0.0};
+  int iters = 0, conv = 0;
+  double rr = 0.0;
+  bool breakdown = false;
+  LD_TRY(multishift_pcg_multi(ctx, e.f64, base_args(op, e.Xp), e.P, cfs, num_orders, e.Z, s, tol,
+                              max_iters, t, mean, se, &iters, &conv, &rr, &breakdown));
+  auto t1 = std::chrono::steady_clock::now();
+  for (int o = 0; o < num_orders; ++o) {
+    ld_result& r = out[o];
+    r = ld_result{};
+    r.trace_term = mean[o];
+    r.logdet_P = e.P->logdet;
+    r.logdet = e.P->logdet + mean[o];
+    r.std_err = se[o];
+    r.rel_resid = rr;
+    r.seconds_solve = std::chrono::duration<double>(t1 - t0).count();
+    r.iterations = iters;
+    r.converged_cols = conv;
+    r.k = ks[o];
+    r.num_probes = num_probes;
+  }
+  if (per_probe) std::memcpy(per_probe, t.data(), (size_t)num_orders * s * sizeof(double));
+  if (breakdown)
+    return fail(LD_ENOTSPD, "non-positive curvature or residual norm in the solver (M or P not SPD?)");
+  if (conv < s) return fail(LD_ENOCONV, "max_iters reached before every probe converged");
+  return LD_OK;
+}
+
 ld_status logdet_estimate_lanczos(ld_ctx* ctx, const ld_operator* op, const ld_precond* P,
                                   int32_t k, int32_t num_probes, uint64_t probe_seed,
                                   int32_t steps, ld_result* out, double* per_probe) {

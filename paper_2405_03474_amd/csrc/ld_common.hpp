@@ -245,10 +245,15 @@ void launch_pitch_f32(hipStream_t st, const double* F64, int64_t n, int rank, in
 // shifts[0] seeds the Krylov space).  Returns z^T x_j (J x s, row j = shift j)
 // and z^T z per column in host vectors.
 // r_k(x) = b + sum_j c_j / (x + a_j) (Table 1), J = k poles, a ascending.
+// Shifts a[0..J) (a[0] the smallest: the CG's seed system) and the
+// Hutchinson coefficients of one estimate over them: per probe
+// b z^T z + sum_j c[j] z^T x_j.  Up to 8 shifts: the union of the poles of
+// r_1, r_3 and r_5 has 7 (one estimate's absent poles carry c = 0).
+constexpr int kMaxShifts = 8;
 struct Coef {
   double b;
-  double a[5];
-  double c[5];
+  double a[kMaxShifts];
+  double c[kMaxShifts];
   int J;
 };
 ld_status multishift_pcg(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precond* P,
@@ -256,6 +261,15 @@ ld_status multishift_pcg(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld
                          std::vector<double>& per_probe, double* mean, double* stderr_,
                          int* iterations, int* converged, double* rel_resid, bool* breakdown,
                          void* ysol = nullptr);
+// Several estimates from one Krylov space: the CG runs on the shifts of
+// cfs[0] (every cfs[o] must list the same shifts a[0..J)), and estimate o
+// combines them with cfs[o]'s coefficients.  per_probe gets ncf x s values,
+// mean and stderr_ ncf each.
+ld_status multishift_pcg_multi(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precond* P,
+                               const Coef* cfs, int ncf, const void* Z, int64_t s, double tol,
+                               int max_iters, std::vector<double>& per_probe, double* mean,
+                               double* stderr_, int* iterations, int* converged, double* rel_resid,
+                               bool* breakdown);
 // Hutchinson combination of z^T x_j (J x s) and z^T z (s), device buffers:
 // per-probe values (s) and [mean, standard error].
 ld_status hutchinson(ld_ctx* ctx, const double* ztx_dev, const double* ztz_dev, int64_t s,

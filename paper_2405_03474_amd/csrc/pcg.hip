@@ -1186,9 +1186,9 @@ struct PcgOut {
 
 template <typename T>
 ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precond* P,
-                  const double* shifts, int J, const Coef& cf, const T* Z, int64_t s, double tol,
-                  int max_iters, std::vector<double>& per_probe, double* mean, double* stderr_,
-                  PcgOut& res, T* ysol) {
+                  const double* shifts, int J, const Coef* cfs, int ncf, const T* Z, int64_t s,
+                  double tol, int max_iters, std::vector<double>& per_probe, double* mean,
+                  double* stderr_, PcgOut& res, T* ysol) {
   const int64_t n = base.n;
   const size_t vec = (size_t)n * s;
   hipStream_t st = ctx->stream;
@@ -1206,7 +1206,7 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
   int* iscal = (int*)ctx->arena.take((size_t)(J * s + s + 2) * sizeof(int));
   double* sg1 = (double*)ctx->arena.take((size_t)kSeg * s * sizeof(double));
   double* sg2 = (double*)ctx->arena.take((size_t)kSeg * s * sizeof(double));
-  double* hut = (double*)ctx->arena.take((size_t)(s + 2) * sizeof(double));
+  double* hut = (double*)ctx->arena.take((size_t)ncf * (s + 2) * sizeof(double));
   if (!r || !u || !p || !w || !q || !dwq || !d1 || !d2 || !scal || !iscal || !sg1 || !sg2 || !hut)
     return fail(LD_ENOMEM, "pcg: scratch arena too small");
   Scal S;
@@ -1228,7 +1228,7 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
 
   std::vector<double> dl(J);
   for (int j = 0; j < J; ++j) dl[j] = shifts[j] - shifts[0];
-  LD_TRY(ensure_pinned(ctx, (size_t)(2 * J * s + 2 * s + 8)));
+  LD_TRY(ensure_pinned(ctx, (size_t)(2 * J * s + (ncf + 2) * s + 2 * ncf + 8)));
   std::copy(dl.begin(), dl.end(), ctx->pinned);
   LD_HIP(hipMemcpyAsync(delta, ctx->pinned, J * sizeof(double), hipMemcpyHostToDevice, st));
   LD_HIP(hipMemsetAsync(S.status, 0, 2 * sizeof(int), st));
@@ -1299,21 +1299,26 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
   ctx->arena.top = mark;
   res.iterations = it;
 
-  // Hutchinson combination on the device; read back the per-probe values,
-  // mean, standard error, rho and rho0
-  LD_TRY(hutchinson(ctx, S.ztx, S.ztz, s, cf, hut, hut + s));
+  // Hutchinson combination of every estimate on the device; read back the
+  // per-probe values, means, standard errors, rho and rho0
+  const int64_t hs = s + 2;
+  for (int o = 0; o < ncf; ++o) LD_TRY(hutchinson(ctx, S.ztx, S.ztz, s, cfs[o], hut + o * hs, hut + o * hs + s));
   double* hp = ctx->pinned;
-  LD_HIP(hipMemcpyAsync(hp, hut, (size_t)(s + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
-  LD_HIP(hipMemcpyAsync(hp + s + 2, S.rho, s * sizeof(double), hipMemcpyDeviceToHost, st));
-  LD_HIP(hipMemcpyAsync(hp + 2 * s + 2, S.rho0, s * sizeof(double), hipMemcpyDeviceToHost, st));
+  LD_HIP(hipMemcpyAsync(hp, hut, (size_t)(ncf * hs) * sizeof(double), hipMemcpyDeviceToHost, st));
+  double* hr = hp + ncf * hs;
+  LD_HIP(hipMemcpyAsync(hr, S.rho, s * sizeof(double), hipMemcpyDeviceToHost, st));
+  LD_HIP(hipMemcpyAsync(hr + s, S.rho0, s * sizeof(double), hipMemcpyDeviceToHost, st));
   LD_HIP(hipStreamSynchronize(st));
-  per_probe.assign(hp, hp + s);
-  *mean = hp[s];
-  *stderr_ = hp[s + 1];
+  per_probe.resize((size_t)ncf * s);
+  for (int o = 0; o < ncf; ++o) {
+    std::copy(hp + o * hs, hp + o * hs + s, per_probe.begin() + o * s);
+    mean[o] = hp[o * hs + s];
+    stderr_[o] = hp[o * hs + s + 1];
+  }
   double worst = 0.0;
   int conv = 0;
   for (int64_t c = 0; c < s; ++c) {
-    const double rr = std::sqrt(std::max(0.0, hp[s + 2 + c] / hp[2 * s + 2 + c]));
+    const double rr = std::sqrt(std::max(0.0, hr[c] / hr[s + c]));
     worst = std::max(worst, rr);
     if (rr <= tol) ++conv;
   }
@@ -1332,11 +1337,31 @@ ld_status multishift_pcg(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld
   PcgOut o;
   ld_status stt;
   if (f64)
-    stt = pcg_run<double>(ctx, true, base, P, cf.a, cf.J, cf, (const double*)Z, s, tol, max_iters,
-                          per_probe, mean, stderr_, o, (double*)ysol);
+    stt = pcg_run<double>(ctx, true, base, P, cf.a, cf.J, &cf, 1, (const double*)Z, s, tol,
+                          max_iters, per_probe, mean, stderr_, o, (double*)ysol);
   else
-    stt = pcg_run<float>(ctx, false, base, P, cf.a, cf.J, cf, (const float*)Z, s, tol, max_iters,
-                         per_probe, mean, stderr_, o, (float*)ysol);
+    stt = pcg_run<float>(ctx, false, base, P, cf.a, cf.J, &cf, 1, (const float*)Z, s, tol,
+                         max_iters, per_probe, mean, stderr_, o, (float*)ysol);
+  *iterations = o.iterations;
+  *converged = o.converged;
+  *rel_resid = o.rel_resid;
+  *breakdown = o.breakdown;
+  return stt;
+}
+
+ld_status multishift_pcg_multi(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precond* P,
+                               const Coef* cfs, int ncf, const void* Z, int64_t s, double tol,
+                               int max_iters, std::vector<double>& per_probe, double* mean,
+                               double* stderr_, int* iterations, int* converged, double* rel_resid,
+                               bool* breakdown) {
+  PcgOut o;
+  ld_status stt;
+  if (f64)
+    stt = pcg_run<double>(ctx, true, base, P, cfs[0].a, cfs[0].J, cfs, ncf, (const double*)Z, s,
+                          tol, max_iters, per_probe, mean, stderr_, o, (double*)nullptr);
+  else
+    stt = pcg_run<float>(ctx, false, base, P, cfs[0].a, cfs[0].J, cfs, ncf, (const float*)Z, s,
+                         tol, max_iters, per_probe, mean, stderr_, o, (float*)nullptr);
   *iterations = o.iterations;
   *converged = o.converged;
   *rel_resid = o.rel_resid;
@@ -1363,7 +1388,7 @@ size_t pcg_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int rank, int64_t s, 
   size_t b = 5 * (size_t)n * s * es + 1280;
   b += ((n + kEpiRows - 1) / kEpiRows * kEpiSplitMax + 2 * ((n + 63) / 64)) * (size_t)s * 8 + 768;
   b += (size_t)(7 * s + 4 * J * s + J) * 8 + (size_t)(J * s + s + 2) * 4 + 512;
-  b += 2 * (size_t)kSeg * s * 8 + (size_t)(s + 2) * 8 + 768;
+  b += 2 * (size_t)kSeg * s * 8 + 3 * (size_t)(s + 2) * 8 + 768;   // up to 3 estimates
   b += std::max(matmat_scratch_bytes(ctx, f64, n, s), woodbury_scratch_bytes(n, rank, s)) + 1024;
   return b;
 }

@@ -189,11 +189,16 @@ class Runner:
             op.M = self.Mbuf
         P = L.Precond(self.ctx, op, cfg.rank, cfg.oversample, cfg.power_iters, cfg.precond_seed,
                       kind=self.pkind, scaled=self.scaled)
-        if self.union and not self.lanczos_steps:
-            # every order from one solve over the union of the poles, one
-            # shared probe block
-            res, _ = L.logdet_estimate_orders(self.ctx, op, P, list(cfg.orders), cfg.probes,
-                                              cfg.probe_seed, self.tol, 5000)
+        if self.union:
+            # every order from one solve (CG over the union of the poles, or
+            # one Lanczos recurrence), one shared probe block
+            if self.lanczos_steps:
+                res, _ = L.logdet_estimate_lanczos_orders(self.ctx, op, P, list(cfg.orders),
+                                                          cfg.probes, cfg.probe_seed,
+                                                          self.lanczos_steps)
+            else:
+                res, _ = L.logdet_estimate_orders(self.ctx, op, P, list(cfg.orders), cfg.probes,
+                                                  cfg.probe_seed, self.tol, 5000)
             P.close()
             return dict(zip(cfg.orders, res))
         for k in cfg.orders:

@@ -337,6 +337,19 @@ ld_status logdet_estimate_lanczos(ld_ctx* ctx, const ld_operator* op, const ld_p
                                   int32_t k, int32_t num_probes, uint64_t probe_seed,
                                   int32_t steps, ld_result* out, double* per_probe);
 
+/* Algorithm 1 for several orders from one Lanczos recurrence: the steps do
+ * not depend on the poles, so the t-step T of every probe serves every
+ * requested r_k; only the tridiagonal solves and the Hutchinson mean are per
+ * order.  Each estimate equals logdet_estimate_lanczos's for that k with the
+ * same probe_seed (to rounding).
+ *   ks, num_orders, out, per_probe  as for logdet_estimate_orders
+ *   P, num_probes, probe_seed, steps  as for logdet_estimate_lanczos
+ * Synchronizes. */
+ld_status logdet_estimate_lanczos_orders(ld_ctx* ctx, const ld_operator* op, const ld_precond* P,
+                                         int32_t num_orders, const int32_t* ks,
+                                         int32_t num_probes, uint64_t probe_seed, int32_t steps,
+                                         ld_result* out, double* per_probe);
+
 /* One problem of a batch: M = K(X, X) + noise * I as in ld_operator (always
  * on the fly, FP32 products), with its own preconditioner rank and seeds. */
 typedef struct {

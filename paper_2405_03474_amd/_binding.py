@@ -38,7 +38,8 @@ EXPORTED = (
     "ld_fill_gaussian", "kernel_matmat", "kernel_materialize", "logdet_precond_build",
     "logdet_precond_build_kind", "ld_precond_info", "ld_precond_export",
     "ld_precond_apply_inverse", "ld_precond_free",
-    "logdet_estimate", "logdet_estimate_orders", "logdet_estimate_lanczos", "logdet_gradient",
+    "logdet_estimate", "logdet_estimate_orders", "logdet_estimate_lanczos",
+    "logdet_estimate_lanczos_orders", "logdet_gradient",
     "logdet_estimate_batched",
     "ld_surrogate_param_count",
     "ld_surrogate_features", "ld_surrogate_create", "ld_surrogate_free", "ld_surrogate_set_scaling",
@@ -122,6 +123,9 @@ def load():
         "logdet_estimate_orders": (i32, [vp, ctypes.POINTER(Operator), vp, i32,
                                          ctypes.POINTER(i32), i32, u64, dbl, i32,
                                          ctypes.POINTER(Result), pd]),
+        "logdet_estimate_lanczos_orders": (i32, [vp, ctypes.POINTER(Operator), vp, i32,
+                                                 ctypes.POINTER(i32), i32, u64, i32,
+                                                 ctypes.POINTER(Result), pd]),
         "logdet_estimate_lanczos": (i32, [vp, ctypes.POINTER(Operator), vp, i32, i32, u64, i32,
                                           ctypes.POINTER(Result), pd]),
         "logdet_gradient": (i32, [vp, ctypes.POINTER(Operator), vp, i32, u64, dbl, i32, pd, pd, pd,
@@ -388,6 +392,28 @@ def logdet_estimate_orders(ctx: Context, op: GPOperator, P: Precond | None, ks, 
                                        probe_seed, tol, max_iters, res,
                                        per.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     _check(st, allow=(LD_ENOCONV,) if allow_noconv else ())
+    out = []
+    for r in res:
+        d = r.as_dict()
+        d["status"] = STATUS_NAMES.get(st, st)
+        out.append(d)
+    return out, per
+
+
+def logdet_estimate_lanczos_orders(ctx: Context, op: GPOperator, P: Precond | None, ks,
+                                   num_probes: int, probe_seed: int, steps: int = 20):
+    """Algorithm 1 for every k in ks from one Lanczos recurrence per probe.
+    Returns (list of result dicts, per-probe values (len(ks), s))."""
+    m = len(ks)
+    res = (Result * m)()
+    karr = (ctypes.c_int32 * m)(*ks)
+    per = np.zeros((m, num_probes), dtype=np.float64)
+    cop = op.c_struct()
+    st = load().logdet_estimate_lanczos_orders(ctx.handle, ctypes.byref(cop),
+                                               P.handle if P is not None else None, m, karr,
+                                               num_probes, probe_seed, steps, res,
+                                               per.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    _check(st)
     out = []
     for r in res:
         d = r.as_dict()

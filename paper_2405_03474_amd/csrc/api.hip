@@ -935,6 +935,43 @@ Coef coef_of(const Rational& rf, int k) {
   return cf;
 }
 
+bool same_pole(double x, double y) { return std::fabs(x - y) <= 1e-12 * std::max(x, y); }
+
+// Coefficients of several orders over the union of their poles, ascending
+// (the smallest is the CG's seed; a pole shared by several orders, such as 1,
+// is one shift).  Each order weighs its own poles with its Table 1 residues
+// and the others with 0.
+ld_status orders_coefs(int32_t num_orders, const int32_t* ks, Coef* cfs) {
+  if (!ks) return fail(LD_EINVAL, "ks is NULL");
+  if (num_orders < 1 || num_orders > 3) return fail(LD_EINVAL, "num_orders must be in 1..3");
+  Rational rf[3];
+  for (int o = 0; o < num_orders; ++o) {
+    if (!rational_for(ks[o], &rf[o])) return fail(LD_EINVAL, "every k must be 1, 3 or 5");
+    for (int q = 0; q < o; ++q)
+      if (ks[q] == ks[o]) return fail(LD_EINVAL, "orders must be distinct");
+  }
+  std::vector<double> sh;
+  for (int o = 0; o < num_orders; ++o)
+    for (int m = 0; m < ks[o]; ++m) {
+      bool seen = false;
+      for (double x : sh) seen = seen || same_pole(x, rf[o].a[m]);
+      if (!seen) sh.push_back(rf[o].a[m]);
+    }
+  std::sort(sh.begin(), sh.end());
+  for (int o = 0; o < num_orders; ++o) {
+    Coef& cf = cfs[o];
+    cf = Coef{};
+    cf.b = rf[o].b;
+    cf.J = (int)sh.size();
+    for (int j = 0; j < cf.J; ++j) {
+      cf.a[j] = sh[j];
+      for (int m = 0; m < ks[o]; ++m)
+        if (same_pole(sh[j], rf[o].a[m])) cf.c[j] = rf[o].c[m];
+    }
+  }
+  return LD_OK;
+}
+
 // Shared set-up of the single-problem estimators: validation, the default
 // preconditioner when P is NULL, the scratch arena, the points in the
 // path's precision and the Rademacher probe block (Algorithm 1 step 1).
@@ -1068,41 +1105,11 @@ ld_status logdet_estimate_orders(ld_ctx* ctx, const ld_operator* op, const ld_pr
                                  uint64_t probe_seed, double tol, int32_t max_iters,
                                  ld_result* out, double* per_probe) {
   if (!out) return fail(LD_EINVAL, "out is NULL");
-  if (!ks) return fail(LD_EINVAL, "ks is NULL");
-  if (num_orders < 1 || num_orders > 3) return fail(LD_EINVAL, "num_orders must be in 1..3");
   if (!(tol > 0.0) || !std::isfinite(tol)) return fail(LD_EINVAL, "tol must be finite and > 0");
   if (max_iters < 1) return fail(LD_EINVAL, "max_iters must be >= 1");
-  Rational rf[3];
-  for (int o = 0; o < num_orders; ++o) {
-    if (!rational_for(ks[o], &rf[o])) return fail(LD_EINVAL, "every k must be 1, 3 or 5");
-    for (int q = 0; q < o; ++q)
-      if (ks[q] == ks[o]) return fail(LD_EINVAL, "orders must be distinct");
-  }
-  // the union of the poles, ascending (the smallest is the CG's seed); a
-  // pole shared by several orders (1 is a pole of every r_k with odd k) is
-  // one shift
-  std::vector<double> sh;
-  for (int o = 0; o < num_orders; ++o)
-    for (int m = 0; m < ks[o]; ++m) {
-      const double a = rf[o].a[m];
-      bool seen = false;
-      for (double x : sh) seen = seen || std::fabs(x - a) <= 1e-12 * std::max(x, a);
-      if (!seen) sh.push_back(a);
-    }
-  std::sort(sh.begin(), sh.end());
-  const int J = (int)sh.size();
   Coef cfs[3];
-  for (int o = 0; o < num_orders; ++o) {
-    Coef& cf = cfs[o];
-    cf = Coef{};
-    cf.b = rf[o].b;
-    cf.J = J;
-    for (int j = 0; j < J; ++j) {
-      cf.a[j] = sh[j];
-      for (int m = 0; m < ks[o]; ++m)
-        if (std::fabs(sh[j] - rf[o].a[m]) <= 1e-12 * std::max(sh[j], rf[o].a[m])) cf.c[j] = rf[o].c[m];
-    }
-  }
+  LD_TRY(orders_coefs(num_orders, ks, cfs));
+  const int J = cfs[0].J;
   EstSetup e;
   LD_TRY(est_setup(ctx, op, P, ks[0], num_probes, probe_seed, 0, pcg_scratch_bytes, J, e));
   const int64_t s = num_probes;
@@ -1162,6 +1169,43 @@ ld_status logdet_estimate_lanczos(ld_ctx* ctx, const ld_operator* op, const ld_p
   out->num_probes = num_probes;
   if (per_probe) std::memcpy(per_probe, o.per_probe.data(), (size_t)s * sizeof(double));
   if (o.breakdown)
+    return fail(LD_ENOTSPD, "non-positive or non-finite norm in the Lanczos recurrence (M or P not SPD?)");
+  return LD_OK;
+}
+
+ld_status logdet_estimate_lanczos_orders(ld_ctx* ctx, const ld_operator* op, const ld_precond* P,
+                                         int32_t num_orders, const int32_t* ks,
+                                         int32_t num_probes, uint64_t probe_seed, int32_t steps,
+                                         ld_result* out, double* per_probe) {
+  if (!out) return fail(LD_EINVAL, "out is NULL");
+  if (steps < 1 || steps > LD_LANCZOS_MAX)
+    return fail(LD_EINVAL, "steps must be in 1..LD_LANCZOS_MAX");
+  Coef cfs[3];
+  LD_TRY(orders_coefs(num_orders, ks, cfs));
+  EstSetup e;
+  LD_TRY(est_setup(ctx, op, P, ks[0], num_probes, probe_seed, 0, lanczos_scratch_bytes, steps, e));
+  const int64_t s = num_probes;
+  auto t0 = std::chrono::steady_clock::now();
+  LzOut o[3];
+  LD_TRY(lanczos_estimate_multi(ctx, e.f64, base_args(op, e.Xp), e.P, cfs, num_orders, e.Z, s,
+                                steps, o));
+  auto t1 = std::chrono::steady_clock::now();
+  for (int q = 0; q < num_orders; ++q) {
+    ld_result& r = out[q];
+    r = ld_result{};
+    r.trace_term = o[q].mean;
+    r.logdet_P = e.P->logdet;
+    r.logdet = e.P->logdet + o[q].mean;
+    r.std_err = o[q].stderr_;
+    r.rel_resid = o[q].resid;
+    r.seconds_solve = std::chrono::duration<double>(t1 - t0).count();
+    r.iterations = o[q].max_steps;
+    r.converged_cols = o[q].exact;
+    r.k = ks[q];
+    r.num_probes = num_probes;
+    if (per_probe) std::memcpy(per_probe + q * s, o[q].per_probe.data(), (size_t)s * sizeof(double));
+  }
+  if (o[0].breakdown)
     return fail(LD_ENOTSPD, "non-positive or non-finite norm in the Lanczos recurrence (M or P not SPD?)");
   return LD_OK;
 }

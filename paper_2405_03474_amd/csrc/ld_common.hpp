@@ -285,6 +285,10 @@ struct LzOut {
 };
 ld_status lanczos_estimate(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precond* P,
                            const Coef& cf, const void* Z, int64_t s, int t, LzOut& out);
+// one recurrence, the tridiagonal solves and mean of every cfs[e] (outs[e])
+ld_status lanczos_estimate_multi(ld_ctx* ctx, bool f64, const MatmatArgs& base,
+                                 const ld_precond* P, const Coef* cfs, int ncf, const void* Z,
+                                 int64_t s, int t, LzOut* outs);
 size_t lanczos_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int rank, int64_t s, int t);
 size_t pcg_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int rank, int64_t s, int J);
 

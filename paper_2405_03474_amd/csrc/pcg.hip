@@ -1029,7 +1029,7 @@ __global__ void k_lz_finish(Lz L, int64_t s, Coef cf, double* __restrict__ per_p
 
 template <typename T>
 ld_status lanczos_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precond* P,
-                      const Coef& cf, const T* Z, int64_t s, int t, LzOut& o) {
+                      const Coef* cfs, int ncf, const T* Z, int64_t s, int t, LzOut* outs) {
   const int64_t n = base.n;
   const size_t vec = (size_t)n * s;
   hipStream_t st = ctx->stream;
@@ -1123,28 +1123,34 @@ ld_status lanczos_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_pr
     }
   }
   ctx->arena.top = mark;
-  hipLaunchKernelGGL(k_lz_finish, dim3(1), dim3(256), 0, st, L, s, cf, per_probe, resid, stats);
-  LD_HIP(hipGetLastError());
-  double* hp = ctx->pinned;
-  LD_HIP(hipMemcpyAsync(hp, per_probe, (size_t)s * sizeof(double), hipMemcpyDeviceToHost, st));
-  LD_HIP(hipMemcpyAsync(hp + s, stats, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
-  LD_HIP(hipMemcpyAsync(hp + s + 3, L.steps, (size_t)s * sizeof(int), hipMemcpyDeviceToHost, st));
-  LD_HIP(hipMemcpyAsync((int*)(hp + s + 3) + s, L.status, 2 * sizeof(int), hipMemcpyDeviceToHost,
-                        st));
-  LD_HIP(hipStreamSynchronize(st));
-  timing_collect(ctx);
-  o.per_probe.assign(hp, hp + s);
-  o.mean = hp[s];
-  o.stderr_ = hp[s + 1];
-  o.resid = hp[s + 2];
-  const int* steps = (const int*)(hp + s + 3);
-  o.max_steps = 0;
-  o.exact = 0;
-  for (int64_t c = 0; c < s; ++c) {
-    o.max_steps = std::max(o.max_steps, steps[c]);
-    if (steps[c] < t) ++o.exact;
+  // the recurrence does not depend on the shifts: every estimate's
+  // tridiagonal solves and Hutchinson mean come from the same T
+  for (int e = 0; e < ncf; ++e) {
+    LzOut& o = outs[e];
+    hipLaunchKernelGGL(k_lz_finish, dim3(1), dim3(256), 0, st, L, s, cfs[e], per_probe, resid,
+                       stats);
+    LD_HIP(hipGetLastError());
+    double* hp = ctx->pinned;
+    LD_HIP(hipMemcpyAsync(hp, per_probe, (size_t)s * sizeof(double), hipMemcpyDeviceToHost, st));
+    LD_HIP(hipMemcpyAsync(hp + s, stats, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    LD_HIP(hipMemcpyAsync(hp + s + 3, L.steps, (size_t)s * sizeof(int), hipMemcpyDeviceToHost, st));
+    LD_HIP(hipMemcpyAsync((int*)(hp + s + 3) + s, L.status, 2 * sizeof(int),
+                          hipMemcpyDeviceToHost, st));
+    LD_HIP(hipStreamSynchronize(st));
+    if (e == 0) timing_collect(ctx);
+    o.per_probe.assign(hp, hp + s);
+    o.mean = hp[s];
+    o.stderr_ = hp[s + 1];
+    o.resid = hp[s + 2];
+    const int* steps = (const int*)(hp + s + 3);
+    o.max_steps = 0;
+    o.exact = 0;
+    for (int64_t c = 0; c < s; ++c) {
+      o.max_steps = std::max(o.max_steps, steps[c]);
+      if (steps[c] < t) ++o.exact;
+    }
+    o.breakdown = ((const int*)(hp + s + 3))[s + 1] != 0;
   }
-  o.breakdown = ((const int*)(hp + s + 3))[s + 1] != 0;
   return LD_OK;
 }
 
@@ -1152,8 +1158,15 @@ ld_status lanczos_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_pr
 
 ld_status lanczos_estimate(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precond* P,
                            const Coef& cf, const void* Z, int64_t s, int t, LzOut& out) {
-  if (f64) return lanczos_run<double>(ctx, true, base, P, cf, (const double*)Z, s, t, out);
-  return lanczos_run<float>(ctx, false, base, P, cf, (const float*)Z, s, t, out);
+  if (f64) return lanczos_run<double>(ctx, true, base, P, &cf, 1, (const double*)Z, s, t, &out);
+  return lanczos_run<float>(ctx, false, base, P, &cf, 1, (const float*)Z, s, t, &out);
+}
+
+ld_status lanczos_estimate_multi(ld_ctx* ctx, bool f64, const MatmatArgs& base,
+                                 const ld_precond* P, const Coef* cfs, int ncf, const void* Z,
+                                 int64_t s, int t, LzOut* outs) {
+  if (f64) return lanczos_run<double>(ctx, true, base, P, cfs, ncf, (const double*)Z, s, t, outs);
+  return lanczos_run<float>(ctx, false, base, P, cfs, ncf, (const float*)Z, s, t, outs);
 }
 
 size_t lanczos_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int rank, int64_t s, int t) {

@@ -8,7 +8,7 @@ import pytest
 
 import workloads
 from oracle import estimate as oest
-from oracle import gp, precond as oprec
+from oracle import gp, lanczos as olz, precond as oprec
 
 pytestmark = pytest.mark.gpu
 
@@ -84,3 +84,29 @@ def test_orders_errors(ctx):
     for bad in ([], [1, 3, 5, 1], [3, 3], [2], [1, 4]):
         with pytest.raises(L.LogdetError, match="LD_EINVAL"):
             L.logdet_estimate_orders(ctx, op, P, bad, 4, 1, 1e-10)
+
+
+@pytest.mark.parametrize("ks", [(1, 3, 5), (3, 5)])
+def test_lanczos_orders_fp64_parity(ctx, ks):
+    # Algorithm 1: one recurrence per probe serves every order; each order
+    # equals the single-order Lanczos estimate and the oracle's
+    cfg = workloads.C1.with_n(700, rank=40)
+    M, op, P, ref = _pair(ctx, cfg)
+    s, seed, t = 16, 17, 12
+    res, per = L.logdet_estimate_lanczos_orders(ctx, op, P, list(ks), s, seed, t)
+    Z = oest.probes(seed, cfg.n, s)
+    for i, k in enumerate(ks):
+        want, steps, resid = olz.estimate_lanczos(M, ref.dense(), ref.logdet, k, Z, t)
+        assert res[i]["k"] == k and res[i]["iterations"] == t
+        np.testing.assert_allclose(per[i], want.per_probe, rtol=1e-10)
+        _, p1 = L.logdet_estimate_lanczos(ctx, op, P, k, s, seed, t)
+        np.testing.assert_allclose(per[i], p1, rtol=1e-12)
+
+
+def test_lanczos_orders_errors(ctx):
+    cfg = workloads.C1.with_n(200, rank=10)
+    M, op, P, ref = _pair(ctx, cfg)
+    with pytest.raises(L.LogdetError, match="LD_EINVAL"):
+        L.logdet_estimate_lanczos_orders(ctx, op, P, [1, 1], 4, 1, 5)
+    with pytest.raises(L.LogdetError, match="LD_EINVAL"):
+        L.logdet_estimate_lanczos_orders(ctx, op, P, [3], 4, 1, 0)

@@ -24,8 +24,11 @@
  *    error, ld_last_error() gives a message (thread-local, valid until the
  *    next call on the same thread).  Argument checks happen before any work is
  *    enqueued.
- *  - The library allocates its own scratch device memory on first use
- *    (hipMalloc), keeps it in the context and frees it in ld_ctx_destroy.
+ *  - Scratch device memory: by default the library allocates it on first use
+ *    (hipMalloc), keeps it in the context, grows it when a call needs more
+ *    and frees it in ld_ctx_destroy.  After ld_set_workspace the context uses
+ *    the caller's buffer instead and allocates no scratch; preconditioners
+ *    (ld_precond) and the surrogate's parameters stay library-owned.
  */
 #ifndef LOGDET_H
 #define LOGDET_H
@@ -123,6 +126,29 @@ typedef struct {
 ld_status ld_ctx_create(int device, void* stream, ld_ctx** out);
 void ld_ctx_destroy(ld_ctx* ctx);
 const char* ld_last_error(void);
+
+/* Device scratch bytes that cover, for this operator, kernel_matmat with s
+ * columns, logdet_precond_build(rank, oversample) and the other
+ * preconditioners of that rank, ld_precond_apply_inverse with s columns, and
+ * logdet_estimate / logdet_estimate_orders / logdet_estimate_lanczos (up to
+ * LD_LANCZOS_MAX steps) / logdet_gradient with s probes of any kind and a
+ * preconditioner of that rank (or P = NULL).  k (1, 3 or 5) is checked;
+ * the bound covers every order.  Sized for the current HIP device.  Returns 0
+ * on invalid arguments (ld_last_error says which).  The batched form and the
+ * surrogate are not covered: with a workspace too small for them they return
+ * LD_ENOMEM and ld_last_error gives the bytes needed. */
+size_t ld_workspace_bytes(const ld_operator* op, int64_t s, int32_t rank, int32_t oversample,
+                          int32_t k);
+
+/* Use the caller's device buffer (256-byte aligned, `bytes` long, on the
+ * context's device) as the context's scratch from now on; the library's own
+ * scratch block is freed.  The caller keeps the buffer alive until the
+ * context is destroyed or another ld_set_workspace call returns, and does
+ * not use it meanwhile.  A later call that needs more scratch than `bytes`
+ * fails with LD_ENOMEM (nothing enqueued) instead of allocating.
+ * ld_set_workspace(ctx, NULL, 0) returns to library-allocated scratch.
+ * Synchronizes the context stream (work in flight may use the old block). */
+ld_status ld_set_workspace(ld_ctx* ctx, void* dev_ptr, size_t bytes);
 
 /* Instrumentation.  With timing on, the solvers of logdet_estimate and
  * logdet_estimate_batched record HIP events around every launch of their

@@ -13,5 +13,5 @@ from ._binding import (  # noqa: F401
     kernel_materialize, kernel_matmat, load, logdet_estimate, logdet_estimate_batched,
     logdet_estimate_lanczos, logdet_estimate_lanczos_orders, logdet_estimate_orders,
     logdet_gradient,
-    rational_coeffs, stored_elements, surrogate_features, surrogate_param_count,
+    rational_coeffs, stored_elements, surrogate_features, surrogate_param_count, workspace_bytes,
 )

@@ -33,7 +33,7 @@ STATUS_NAMES = {0: "LD_OK", -1: "LD_EINVAL", -2: "LD_ENOTSPD", -3: "LD_ENOCONV",
 
 EXPORTED = (
     "ld_ctx_create", "ld_ctx_destroy", "ld_last_error", "ld_ctx_set_timing", "ld_ctx_read_timing",
-    "ld_ctx_set_probes",
+    "ld_ctx_set_probes", "ld_workspace_bytes", "ld_set_workspace",
     "ld_stored_elements", "ld_rational_coeffs", "ld_fill_probes",
     "ld_fill_gaussian", "kernel_matmat", "kernel_materialize", "logdet_precond_build",
     "logdet_precond_build_kind", "ld_precond_info", "ld_precond_export",
@@ -110,6 +110,8 @@ def load():
         "ld_fill_gaussian": (i32, [vp, u64, i32, i64, i64, vp]),
         "kernel_matmat": (i32, [vp, ctypes.POINTER(Operator), vp, i64, vp]),
         "kernel_materialize": (i32, [vp, ctypes.POINTER(Operator), vp]),
+        "ld_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Operator), i64, i32, i32, i32]),
+        "ld_set_workspace": (i32, [vp, vp, ctypes.c_size_t]),
         "logdet_precond_build": (i32, [vp, ctypes.POINTER(Operator), i32, i32, i32, u64,
                                        ctypes.POINTER(vp)]),
         "logdet_precond_build_kind": (i32, [vp, ctypes.POINTER(Operator), i32, i32, i32, i32, u64,
@@ -202,6 +204,18 @@ class Context:
     def set_timing(self, on: bool = True):
         _check(load().ld_ctx_set_timing(self.handle, 1 if on else 0))
 
+    def set_workspace(self, buf=None):
+        """Use a caller-owned device tensor (or None: library scratch again) as
+        the context's scratch; the tensor must outlive its use here."""
+        if buf is None:
+            _check(load().ld_set_workspace(self.handle, None, 0))
+            self._workspace = None
+            return
+        assert buf.is_cuda and buf.is_contiguous()
+        nbytes = buf.numel() * buf.element_size()
+        _check(load().ld_set_workspace(self.handle, ctypes.c_void_p(buf.data_ptr()), nbytes))
+        self._workspace = buf   # kept alive with the context
+
     def set_probes(self, kind: int):
         """Probe distribution (LD_PROBE_*) of later single-problem estimates."""
         _check(load().ld_ctx_set_probes(self.handle, kind))
@@ -253,6 +267,15 @@ class GPOperator:
                         precision=self.precision,
                         M_stored=self.M.data_ptr() if self.M is not None else None,
                         layout=self.layout)
+
+
+def workspace_bytes(op: GPOperator, s: int, rank: int, oversample: int = 10, k: int = 5) -> int:
+    """Scratch bytes covering the single-problem calls on op (ld_workspace_bytes)."""
+    cop = op.c_struct()
+    v = load().ld_workspace_bytes(ctypes.byref(cop), s, rank, oversample, k)
+    if v == 0:
+        raise LogdetError(LD_EINVAL, load().ld_last_error().decode())
+    return int(v)
 
 
 def fill_probes(ctx: Context, seed: int, n: int, s: int, precision: int = LD_F64):

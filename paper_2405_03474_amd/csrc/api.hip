@@ -26,6 +26,9 @@ ld_status fail(ld_status st, const std::string& msg) {
 // ------------------------------------------------------------------ arena --
 ld_status Arena::reserve(size_t bytes) {
   if (bytes <= cap) return LD_OK;
+  if (external)
+    return fail(LD_ENOMEM, "the workspace set by ld_set_workspace holds " + std::to_string(cap) +
+                               " bytes; this call needs " + std::to_string(bytes));
   // the old block may still be read by enqueued work
   if (base) (void)hipDeviceSynchronize();
   release();
@@ -48,10 +51,11 @@ void* Arena::take(size_t bytes) {
 }
 
 void Arena::release() {
-  if (base) (void)hipFree(base);
+  if (base && !external) (void)hipFree(base);
   base = nullptr;
   cap = 0;
   top = 0;
+  external = false;
 }
 
 ld_status ensure_pinned(ld_ctx* ctx, size_t count) {
@@ -431,16 +435,17 @@ ld_status finish_precond(ld_ctx* ctx, const ld_operator* op, ld_precond* P, doub
   return LD_OK;
 }
 
-// Randomized truncated SVD (rank >= 1) with D the floored diagonal remainder,
-// or, with const_d > 0, D = const_d I ("plus scaling").
-ld_status build_precond(ld_ctx* ctx, const ld_operator* op, int rank, int oversample, int power_iters,
-                        uint64_t seed, ld_precond** out, double const_d) {
+// ---------------------------------------------------------- scratch sizes --
+// Device scratch each call takes from the context's arena; ld_workspace_bytes
+// reports the largest of them.
+
+// randomized truncated SVD with rank + oversample sketch columns
+size_t rsvd_scratch_bytes(ld_ctx* ctx, const ld_operator* op, int rank, int oversample) {
   const int64_t n = op->n;
   const int m = rank + oversample;
   const bool f64 = is_f64(op);
   const size_t nm = (size_t)n * m;
   const int me = m + (m & 1);
-  // scratch bound
   size_t need = 0;
   need += (size_t)n * op->d * 4 + 512;                     // FP32 points
   need += 2 * nm * 8 + 1024;                               // Q, Y (FP64)
@@ -451,8 +456,56 @@ ld_status build_precond(ld_ctx* ctx, const ld_operator* op, int rank, int oversa
   size_t gram_b = std::max((size_t)16 << 20, (size_t)2 * m * m * 8) + 512;
   need += std::max(gram_b, matmat_scratch_bytes(ctx, f64, n, m)) + 1024;
   need += 4096;
+  return need;
+}
+
+// identity, diagonal (rank 0) and partial Cholesky of the given rank
+size_t simple_precond_scratch_bytes(const ld_operator* op, int rank) {
+  const int64_t n = op->n;
+  return (size_t)n * op->d * 4 + 512 + (size_t)n * 8 + 512 + 2 * (size_t)rank * rank * 8 + 1024 +
+         (size_t)rank * 12 + 512 + 4096 + ((size_t)16 << 20);
+}
+
+// one kernel_matmat call with s columns
+size_t matmat_call_bytes(ld_ctx* ctx, const ld_operator* op, int64_t s) {
+  return (size_t)op->n * op->d * 4 + 512 + matmat_scratch_bytes(ctx, is_f64(op), op->n, s);
+}
+
+// the estimators' set-up (points, probes, probe drawing) plus the solver's
+// own scratch and `extra`
+size_t est_scratch_bytes(const ld_operator* op, int64_t s, int probe_kind, size_t solver,
+                         size_t extra) {
+  const int64_t n = op->n;
+  const size_t es = is_f64(op) ? 8 : 4;
+  // Gaussian / orthogonal probes are drawn in FP64 first (two n x s blocks
+  // and the small Gram factors of the orthonormalisation)
+  const size_t probe_tmp = probe_kind == LD_PROBE_RADEMACHER
+                               ? 0
+                               : 2 * (size_t)n * s * 8 + 3 * (size_t)s * s * 8 + (size_t)s * 8 +
+                                     ((size_t)16 << 20) + 4096;
+  return (size_t)n * op->d * 4 + 512 + (size_t)n * s * es + 512 + solver + extra + probe_tmp;
+}
+
+// logdet_gradient's scratch beyond the solver: y (operator precision), FP64
+// copies of z and y, the derivative product, partials and values
+size_t gradient_extra_bytes(ld_ctx* ctx, const ld_operator* op, int64_t s) {
+  const int64_t n = op->n;
+  const size_t es = is_f64(op) ? 8 : 4;
+  const int64_t nblk = (n + 255) / 256;
+  return (size_t)n * s * es + 3 * (size_t)n * s * 8 + (size_t)nblk * s * 8 + 8 * (size_t)s * 8 +
+         8 * 4096 + matmat_scratch_bytes(ctx, true, n, s);
+}
+
+// Randomized truncated SVD (rank >= 1) with D the floored diagonal remainder,
+// or, with const_d > 0, D = const_d I ("plus scaling").
+ld_status build_precond(ld_ctx* ctx, const ld_operator* op, int rank, int oversample, int power_iters,
+                        uint64_t seed, ld_precond** out, double const_d) {
+  const int64_t n = op->n;
+  const int m = rank + oversample;
+  const bool f64 = is_f64(op);
+  const size_t nm = (size_t)n * m;
   ctx->arena.reset();
-  LD_TRY(ctx->arena.reserve(need));
+  LD_TRY(ctx->arena.reserve(rsvd_scratch_bytes(ctx, op, rank, oversample)));
 
   const void* Xp = nullptr;
   LD_TRY(path_points(ctx, op, &Xp));
@@ -620,10 +673,8 @@ ld_status build_precond_simple(ld_ctx* ctx, const ld_operator* op, int kind, int
                                double const_d, ld_precond** out) {
   const int64_t n = op->n;
   if (kind != LD_PRECOND_PCHOL) rank = 0;
-  size_t need = (size_t)n * op->d * 4 + 512 + (size_t)n * 8 + 512 + 2 * (size_t)rank * rank * 8 +
-                1024 + (size_t)rank * 12 + 512 + 4096 + ((size_t)16 << 20);
   ctx->arena.reset();
-  LD_TRY(ctx->arena.reserve(need));
+  LD_TRY(ctx->arena.reserve(simple_precond_scratch_bytes(op, rank)));
   double* res = (double*)ctx->arena.take((size_t)n * 8);
   double* G = (double*)ctx->arena.take((size_t)std::max(rank, 1) * std::max(rank, 1) * 8);
   double* Rinv = (double*)ctx->arena.take((size_t)std::max(rank, 1) * std::max(rank, 1) * 8);
@@ -708,6 +759,63 @@ void ld_ctx_destroy(ld_ctx* ctx) {
   delete ctx;
 }
 
+ld_status ld_set_workspace(ld_ctx* ctx, void* dev_ptr, size_t bytes) {
+  if (!ctx) return fail(LD_EINVAL, "context is NULL");
+  if ((dev_ptr == nullptr) != (bytes == 0))
+    return fail(LD_EINVAL, "pass a buffer and its size, or NULL and 0");
+  if (dev_ptr && ((uintptr_t)dev_ptr & 255) != 0)
+    return fail(LD_EINVAL, "the workspace must be 256-byte aligned");
+  LD_HIP(hipSetDevice(ctx->device));
+  // enqueued work may still use the current block
+  LD_HIP(hipStreamSynchronize(ctx->stream));
+  if (ctx->side) LD_HIP(hipStreamSynchronize(ctx->side));
+  ctx->arena.release();
+  if (dev_ptr) {
+    ctx->arena.base = (char*)dev_ptr;
+    ctx->arena.cap = bytes;
+    ctx->arena.external = true;
+  }
+  return LD_OK;
+}
+
+size_t ld_workspace_bytes(const ld_operator* op, int64_t s, int32_t rank, int32_t oversample,
+                          int32_t k) {
+  if (check_operator(op, false) != LD_OK) return 0;
+  Rational rf;
+  if (s < 1 || rank < 1 || oversample < 0 || (int64_t)rank + oversample > op->n ||
+      !rational_for(k, &rf)) {
+    fail(LD_EINVAL, "need s >= 1, 1 <= rank, oversample >= 0, rank + oversample <= n, k in {1, 3, 5}");
+    return 0;
+  }
+  // a context only for sizing: the product's plan depends on the CU count
+  ld_ctx sz;
+  int dev = 0, cu = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+    sz.num_cu = cu;
+  else
+    (void)hipGetLastError();
+  const bool f64 = is_f64(op);
+  const int64_t n = op->n;
+  // the default preconditioner logdet_estimate builds when P is NULL
+  const int drank = (int)std::min<int64_t>(100, std::max<int64_t>(1, n / 10));
+  const int dover = (int)std::min<int64_t>(10, n - drank);
+  size_t need = matmat_call_bytes(&sz, op, s);
+  need = std::max(need, rsvd_scratch_bytes(&sz, op, rank, oversample));
+  need = std::max(need, rsvd_scratch_bytes(&sz, op, drank, dover));
+  need = std::max(need, simple_precond_scratch_bytes(op, rank));
+  need = std::max(need, woodbury_scratch_bytes(n, rank, s));
+  // estimators: any probe kind, up to every pole of r_1, r_3, r_5 at once,
+  // Algorithm 1 up to LD_LANCZOS_MAX steps, and the gradient
+  const size_t solver = std::max(pcg_scratch_bytes(&sz, f64, n, rank, s, kMaxShifts),
+                                 lanczos_scratch_bytes(&sz, f64, n, rank, s, LD_LANCZOS_MAX));
+  need = std::max(need, est_scratch_bytes(op, s, LD_PROBE_ORTHOGONAL, solver, 0));
+  need = std::max(need, est_scratch_bytes(op, s, LD_PROBE_ORTHOGONAL,
+                                          pcg_scratch_bytes(&sz, f64, n, rank, s, 1),
+                                          gradient_extra_bytes(&sz, op, s)));
+  return need;
+}
+
 ld_status ld_ctx_set_timing(ld_ctx* ctx, int32_t on) {
   if (!ctx) return fail(LD_EINVAL, "context is NULL");
   ctx->timing = on != 0;
@@ -782,7 +890,7 @@ ld_status kernel_matmat(ld_ctx* ctx, const ld_operator* op, const void* V, int64
   if (V == Y) return fail(LD_EINVAL, "Y must not alias V");
   const bool f64 = is_f64(op);
   ctx->arena.reset();
-  LD_TRY(ctx->arena.reserve((size_t)op->n * op->d * 4 + 512 + matmat_scratch_bytes(ctx, f64, op->n, s)));
+  LD_TRY(ctx->arena.reserve(matmat_call_bytes(ctx, op, s)));
   const void* Xp = nullptr;
   LD_TRY(path_points(ctx, op, &Xp));
   MatmatArgs a = base_args(op, Xp);
@@ -1009,16 +1117,9 @@ ld_status est_setup(ld_ctx* ctx, const ld_operator* op, const ld_precond* P, int
   if (pk == LD_PROBE_ORTHOGONAL && s > n)
     return fail(LD_EINVAL, "orthogonal probes need num_probes <= n");
   const size_t es = e.f64 ? 8 : 4;
-  // Gaussian / orthogonal probes are drawn in FP64 first (two n x s blocks
-  // and the small Gram factors of the orthonormalisation)
-  const size_t probe_tmp = pk == LD_PROBE_RADEMACHER
-                               ? 0
-                               : 2 * (size_t)n * s * 8 + 3 * (size_t)s * s * 8 + (size_t)s * 8 +
-                                     ((size_t)16 << 20) + 4096;
   ctx->arena.reset();
-  LD_TRY(ctx->arena.reserve((size_t)n * op->d * 4 + 512 + (size_t)n * s * es + 512 +
-                            solver_bytes(ctx, e.f64, n, P->rank, s, arg) + solver_bytes_extra +
-                            probe_tmp));
+  LD_TRY(ctx->arena.reserve(est_scratch_bytes(op, s, pk, solver_bytes(ctx, e.f64, n, P->rank, s, arg),
+                                              solver_bytes_extra)));
   LD_TRY(path_points(ctx, op, &e.Xp));
   e.Z = ctx->arena.take((size_t)n * s * es);
   if (!e.Z) return fail(LD_ENOMEM, "scratch arena too small for probes");
@@ -1220,14 +1321,11 @@ ld_status logdet_gradient(ld_ctx* ctx, const ld_operator* op, const ld_precond* 
   if (num_probes < 1) return fail(LD_EINVAL, "num_probes must be >= 1");
   if (!(tol > 0.0) || !std::isfinite(tol)) return fail(LD_EINVAL, "tol must be finite and > 0");
   if (max_iters < 1) return fail(LD_EINVAL, "max_iters must be >= 1");
-  const int64_t n = op ? op->n : 0, s = num_probes;
-  const bool f64op = op && is_f64(op);
+  const int64_t n = op->n, s = num_probes;
+  const bool f64op = is_f64(op);
   const size_t es = f64op ? 8 : 4;
-  // extra scratch: y (op precision), FP64 copies of z and y, the product, partials, values
   const int64_t nblk = (n + 255) / 256;
-  const size_t extra = (size_t)n * s * es + 3 * (size_t)n * s * 8 + (size_t)nblk * s * 8 +
-                       8 * (size_t)s * 8 + 8 * 4096 +
-                       (op ? matmat_scratch_bytes(ctx, true, n, s) : 0);
+  const size_t extra = gradient_extra_bytes(ctx, op, s);
   EstSetup e;
   LD_TRY(est_setup(ctx, op, P, 1, num_probes, probe_seed, extra, pcg_scratch_bytes, 1, e));
   hipStream_t st = ctx->stream;

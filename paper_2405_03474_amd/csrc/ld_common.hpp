@@ -45,12 +45,16 @@ inline uint64_t stream_key(uint64_t seed, int stream) {
 }
 
 // ------------------------------------------------------ scratch arena --
-// Grow-only device arena owned by a context.  Allocation is a bump pointer
-// over one hipMalloc'ed block; reset() frees everything at once.
+// Device scratch arena of a context.  Allocation is a bump pointer over one
+// block; reset() frees everything at once.  The block is either the
+// library's own (hipMalloc'ed, grown on demand) or the caller's workspace
+// (ld_set_workspace: never grown or freed here; a call that needs more fails
+// with LD_ENOMEM).
 struct Arena {
   char* base = nullptr;
   size_t cap = 0;
   size_t top = 0;
+  bool external = false;
   ld_status reserve(size_t bytes);  // ensure capacity (only when top == 0)
   void* take(size_t bytes);         // 256-byte aligned; nullptr if out of room
   void reset() { top = 0; }

@@ -59,3 +59,34 @@ def test_null_context_is_rejected_before_any_work():
     assert st == B.LD_EINVAL
     assert b"context" in lib.ld_last_error()
     assert lib.kernel_matmat(None, ctypes.byref(op), None, 1, None) == B.LD_EINVAL
+
+
+def _sizing_operator(n=5000, d=3, precision=0):
+    # X is never dereferenced by the sizing query: any non-null address
+    return B.Operator(X=ctypes.c_void_p(4096), n=n, d=d, kind=1, lengthscale=0.2, variance=1.0,
+                      noise=1e-3, precision=precision, M_stored=None)
+
+
+def test_workspace_bytes_host_logic():
+    lib = B.load()
+    op = _sizing_operator()
+    base = lib.ld_workspace_bytes(ctypes.byref(op), 32, 100, 10, 3)
+    assert base > 0
+    # grows with the probe block and the rank; covers every order alike
+    assert lib.ld_workspace_bytes(ctypes.byref(op), 64, 100, 10, 3) > base
+    assert lib.ld_workspace_bytes(ctypes.byref(op), 32, 400, 10, 3) > base
+    assert lib.ld_workspace_bytes(ctypes.byref(op), 32, 100, 10, 5) == base
+    # at least the probe block and the five CG vectors of n x s
+    assert base >= 6 * 5000 * 32 * 8
+    for bad in ((0, 100, 10, 3), (32, 0, 10, 3), (32, 100, -1, 3), (32, 4995, 10, 3),
+                (32, 100, 10, 2)):
+        assert lib.ld_workspace_bytes(ctypes.byref(op), *bad) == 0
+        assert lib.ld_last_error()
+    bad_op = _sizing_operator(d=0)
+    assert lib.ld_workspace_bytes(ctypes.byref(bad_op), 32, 100, 10, 3) == 0
+
+
+def test_set_workspace_argument_checks():
+    lib = B.load()
+    assert lib.ld_set_workspace(None, None, 0) == B.LD_EINVAL
+    assert b"context" in lib.ld_last_error()

@@ -114,6 +114,8 @@ typedef struct {
   double std_err;         /* sample std of t_i / sqrt(s) (NaN for s = 1) */
   double rel_resid;       /* max over probes of ||r||_{P^-1} / ||z||_{P^-1} of
                              the smallest-shift system at exit */
+  double seconds_precond; /* wall time of the preconditioner build done by
+                             this call (P NULL; batched: all instances), else 0 */
   double seconds_solve;   /* wall time of the solve and reduction */
   int32_t iterations;     /* solver iterations run */
   int32_t converged_cols; /* probes that met the tolerance */

@@ -76,7 +76,8 @@ class Result(ctypes.Structure):
     _fields_ = [
         ("logdet", ctypes.c_double), ("logdet_P", ctypes.c_double), ("trace_term", ctypes.c_double),
         ("std_err", ctypes.c_double), ("rel_resid", ctypes.c_double),
-        ("seconds_solve", ctypes.c_double), ("iterations", ctypes.c_int32),
+        ("seconds_precond", ctypes.c_double), ("seconds_solve", ctypes.c_double),
+        ("iterations", ctypes.c_int32),
         ("converged_cols", ctypes.c_int32), ("k", ctypes.c_int32), ("num_probes", ctypes.c_int32),
     ]
 

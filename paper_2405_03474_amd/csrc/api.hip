@@ -1090,6 +1090,7 @@ struct EstSetup {
   bool f64 = false;
   const void* Xp = nullptr;
   void* Z = nullptr;
+  double precond_s = 0.0;  // the default preconditioner's build, when P was NULL
   ~EstSetup() {
     if (own) ld_precond_free(own);
   }
@@ -1107,7 +1108,9 @@ ld_status est_setup(ld_ctx* ctx, const ld_operator* op, const ld_precond* P, int
   if (!P) {
     int rank = (int)std::min<int64_t>(100, std::max<int64_t>(1, op->n / 10));
     int over = (int)std::min<int64_t>(10, op->n - rank);
+    const auto tp = std::chrono::steady_clock::now();
     LD_TRY(build_precond(ctx, op, rank, over, 2, probe_seed + 1, &e.own, 0.0));
+    e.precond_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - tp).count();
     P = e.own;
   }
   e.P = P;
@@ -1190,6 +1193,7 @@ ld_status logdet_estimate(ld_ctx* ctx, const ld_operator* op, const ld_precond* 
   out->std_err = se;
   out->rel_resid = rr;
   out->seconds_solve = std::chrono::duration<double>(t1 - t0).count();
+  out->seconds_precond = e.precond_s;
   out->iterations = iters;
   out->converged_cols = conv;
   out->k = k;
@@ -1232,6 +1236,7 @@ ld_status logdet_estimate_orders(ld_ctx* ctx, const ld_operator* op, const ld_pr
     r.std_err = se[o];
     r.rel_resid = rr;
     r.seconds_solve = std::chrono::duration<double>(t1 - t0).count();
+    r.seconds_precond = e.precond_s;
     r.iterations = iters;
     r.converged_cols = conv;
     r.k = ks[o];
@@ -1264,6 +1269,7 @@ ld_status logdet_estimate_lanczos(ld_ctx* ctx, const ld_operator* op, const ld_p
   out->std_err = o.stderr_;
   out->rel_resid = o.resid;
   out->seconds_solve = std::chrono::duration<double>(t1 - t0).count();
+  out->seconds_precond = e.precond_s;
   out->iterations = o.max_steps;
   out->converged_cols = o.exact;
   out->k = k;
@@ -1300,6 +1306,7 @@ ld_status logdet_estimate_lanczos_orders(ld_ctx* ctx, const ld_operator* op, con
     r.std_err = o[q].stderr_;
     r.rel_resid = o[q].resid;
     r.seconds_solve = std::chrono::duration<double>(t1 - t0).count();
+    r.seconds_precond = e.precond_s;
     r.iterations = o[q].max_steps;
     r.converged_cols = o[q].exact;
     r.k = ks[q];
@@ -1409,6 +1416,7 @@ ld_status logdet_gradient(ld_ctx* ctx, const ld_operator* op, const ld_precond* 
     out->logdet_P = e.P->logdet;
     out->rel_resid = rr;
     out->seconds_solve = std::chrono::duration<double>(t1 - t0).count();
+    out->seconds_precond = e.precond_s;
     out->iterations = iters;
     out->converged_cols = conv;
     out->num_probes = num_probes;

@@ -1368,6 +1368,7 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
     ~Joiner() { fn(); }
   } joiner{join};
 
+  const auto t0 = std::chrono::steady_clock::now();
   LD_HIP(hipMemcpyAsync(b.d_inst, b.h.data(), B * sizeof(BInst), hipMemcpyHostToDevice, st));
   LD_HIP(hipMemcpyAsync(b.d_blk_inst, blk_inst.data(), b.nblk * sizeof(int), hipMemcpyHostToDevice, st));
   LD_HIP(hipMemcpyAsync(d_ch_inst, ch_inst.data(), nchunks * sizeof(int), hipMemcpyHostToDevice, st));
@@ -1454,10 +1455,12 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
         return fail(LD_ENOTSPD, "batch: log det P is not finite in instance " + std::to_string(i));
   }
   auto t1 = std::chrono::steady_clock::now();
+  const double precond_s = std::chrono::duration<double>(t1 - t0).count();
   if (flags & LD_BATCH_PRECOND_ONLY) {
     for (int i = 0; i < count; ++i) {
       ld_result& o = out[i];
       o = ld_result{};
+      o.seconds_precond = precond_s;
       o.logdet_P = logdetP[i];
       o.logdet = logdetP[i];
       o.k = J;
@@ -1654,6 +1657,7 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
     o.std_err = s > 1 ? std::sqrt(var / (s - 1) / s) : NAN;
     o.rel_resid = worst;
     o.seconds_solve = solve_s;
+    o.seconds_precond = precond_s;
     o.iterations = std::min(it, max_iters);
     o.converged_cols = conv;
     o.k = J;

@@ -104,3 +104,23 @@ def test_workspace_argument_errors():
     assert lib.ld_set_workspace(ctx.handle, ctypes.c_void_p(buf.data_ptr()), 0) == B.LD_EINVAL
     assert lib.ld_set_workspace(ctx.handle, None, 1024) == B.LD_EINVAL
     ctx.close()
+
+
+def test_result_times():
+    # seconds_precond: the build this call did itself (P NULL; the batched
+    # form always builds), else 0
+    ctx = L.Context(0)
+    cfg = workloads.C1.with_n(500, rank=30)
+    op = _op(cfg, L.LD_F64, False, ctx)
+    res, _ = L.logdet_estimate(ctx, op, None, 3, 8, 1, 1e-10, 5000)
+    assert res["seconds_precond"] > 0 and res["seconds_solve"] > 0
+    P = L.Precond(ctx, op, cfg.rank, cfg.oversample, cfg.power_iters, cfg.precond_seed)
+    res, _ = L.logdet_estimate(ctx, op, P, 3, 8, 1, 1e-10, 5000)
+    assert res["seconds_precond"] == 0 and res["seconds_solve"] > 0
+    items = [L.BatchItem(X=dev(g.X()), kind=g.kind, lengthscale=g.lengthscale,
+                         variance=g.variance, noise=g.noise, rank=g.rank,
+                         precond_seed=g.precond_seed, probe_seed=g.probe_seed)
+             for g in workloads.batch_instances(count=3, n_hi=1500)]
+    out = L.logdet_estimate_batched(ctx, items, 3, 4, tol=1e-6, max_iters=5000)[0]
+    assert all(r["seconds_precond"] > 0 and r["seconds_solve"] > 0 for r in out)
+    ctx.close()

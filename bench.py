@@ -431,7 +431,10 @@ def surrogate_main(args, torch, L):
     stream = torch.cuda.current_stream(0)
     ctx = L.Context(0, stream)
     cfg = sweep.Config()
-    train_insts = workloads.surrogate_training_instances(args.c5_train_count, args.c5_train_n)
+    if args.c5_train_family == "grid":
+        train_insts = workloads.surrogate_family_instances(args.c5_train_count, args.c5_train_n)
+    else:
+        train_insts = workloads.surrogate_training_instances(args.c5_train_count, args.c5_train_n)
     grid = workloads.surrogate_grid(args.c5_eval_n, side=args.c5_side)
     log(f"[bench] c5: {len(train_insts)} training problems at n={args.c5_train_n}, "
         f"{len(grid)} grid points at n={args.c5_eval_n}")
@@ -446,7 +449,14 @@ def surrogate_main(args, torch, L):
     F = sweep.features(lams, train_used, edges)
     log(f"[bench] training data {t_gen:.2f} s")
     t0 = time.perf_counter()
-    S, hist = sweep.train(ctx, F, y, torch, epochs=args.c5_epochs)
+    if args.c5_calibrate:
+        # hold out a tenth of the problems to calibrate the spread multiplier
+        tr, ho = sweep.split_holdout(len(y), 0.1)
+        S, hist = sweep.train(ctx, F[tr], y[tr], torch, epochs=args.c5_epochs)
+        cfg.kappa = sweep.calibrate(S, F[ho], y[ho], torch)
+        log(f"[bench] spread multiplier from {len(ho)} held-out problems: {cfg.kappa:.2f}")
+    else:
+        S, hist = sweep.train(ctx, F, y, torch, epochs=args.c5_epochs)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     log(f"[bench] training {t_train:.2f} s, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
@@ -494,10 +504,11 @@ def surrogate_main(args, torch, L):
         "data": "synthetic",
         "config": {"workload": "c5_surrogate", "train_n": args.c5_train_n,
                    "train_count": len(train_insts), "train_converged": len(ok),
+                   "train_family": args.c5_train_family,
                    "eval_n": args.c5_eval_n,
                    "grid": f"{args.c5_side}x{args.c5_side}", "order": cfg.k, "probes": cfg.probes,
                    "rank": "n/40", "members": 5, "epochs": args.c5_epochs,
-                   "fallback_rel_tol": cfg.rel_tol},
+                   "fallback_rel_tol": cfg.rel_tol, "spread_multiplier": cfg.kappa},
         "plain_estimator": {"value": len(grid) / t_plain, "seconds": t_plain,
                             "unconverged": plain_unconverged},
         "speedup_vs_plain": t_plain / t_sur,
@@ -637,6 +648,12 @@ def main():
     ap.add_argument("--c5-eval-n", type=int, default=5000)
     ap.add_argument("--c5-side", type=int, default=32)
     ap.add_argument("--c5-epochs", type=int, default=300)
+    ap.add_argument("--c5-calibrate", action="store_true",
+                    help="scale the ensemble spread by a factor calibrated on held-out "
+                         "training problems before the fallback test")
+    ap.add_argument("--c5-train-family", default="batched", choices=["batched", "grid"],
+                    help="training problems: the batched form's hyperparameter distribution "
+                         "(default) or the evaluation grid's own family")
     ap.add_argument("--lanczos-steps", type=int, default=0,
                     help="c1/c2/c3: run Algorithm 1 as printed (this many Lanczos steps per "
                          "probe, tridiagonal solves) instead of the multi-shift CG to tolerance")

@@ -36,7 +36,8 @@ class Config:
     power_iters: int = 2
     tol: float = 1e-6
     chunk: int = 256          # instances per batched call
-    rel_tol: float = 1e-3     # fallback when n * std > rel_tol * |log det|
+    rel_tol: float = 1e-3     # fallback when kappa * n * std > rel_tol * |log det|
+    kappa: float = 1.0        # spread multiplier (1: the ensemble's raw spread; see calibrate)
     max_iters: int = 5000     # solver iterations per batch (unconverged results are flagged)
 
 
@@ -104,6 +105,28 @@ def train(ctx, F, y, torch, members=5, seed=0, epochs=300, batch=256, lr=1e-3):
     return S, hist
 
 
+def split_holdout(N: int, frac: float, seed: int = 1):
+    """Indices (train, holdout) of a random split of N problems."""
+    perm = np.random.default_rng(seed).permutation(N)
+    h = int(round(frac * N))
+    return np.sort(perm[h:]), np.sort(perm[:h])
+
+
+def calibrate(S, F_hold, y_hold, torch, quantile: float = 0.99) -> float:
+    """Spread multiplier from problems the ensemble was not trained on: the
+    given quantile of |mean - target| / std over them (at least 1).  The raw
+    spread of members trained on the same data can sit far below their shared
+    error; scaled by this factor it bounds the held-out error at that
+    quantile (the targets' own probe noise is included, so it is
+    conservative)."""
+    mean, sd = S.predict(torch.as_tensor(F_hold, dtype=torch.float32, device="cuda:0"))
+    torch.cuda.synchronize()
+    mean = mean.double().cpu().numpy()
+    sd = np.maximum(sd.double().cpu().numpy(), 1e-300)
+    ratio = np.abs(mean - np.asarray(y_hold, dtype=np.float64)) / sd
+    return float(max(1.0, np.quantile(ratio, quantile)))
+
+
 def sweep(ctx, S, grid, edges, cfg: Config, torch, items=None):
     """Surrogate sweep over grid problems: returns per-point log det, whether
     the point fell back to the estimator, the stage times (s) together with
@@ -119,7 +142,7 @@ def sweep(ctx, S, grid, edges, cfg: Config, torch, items=None):
     n = np.array([g.n for g in grid], dtype=np.float64)
     logdet_P = np.array([r["logdet_P"] for r in pre])
     logdet = logdet_P + n * mean
-    fallback = n * sd > cfg.rel_tol * np.abs(logdet)
+    fallback = cfg.kappa * n * sd > cfg.rel_tol * np.abs(logdet)
     predicted = logdet.copy()
     t2 = time.perf_counter()
     fb = np.nonzero(fallback)[0]

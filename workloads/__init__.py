@@ -136,6 +136,23 @@ def surrogate_training_instances(count: int, n: int, seed: int = BASE_SEED + 4,
     return out
 
 
+def surrogate_family_instances(count: int, n: int, seed: int = BASE_SEED + 7, probes: int = 64):
+    """Training problems from the evaluation grid's own family (Matern-5/2,
+    d = 3, variance 1, points uniform in [0,1]^3) with lengthscale and noise
+    log-uniform over the grid's ranges; each problem has its own point cloud
+    (none is a grid problem)."""
+    g = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        ls = float(np.exp(g.uniform(np.log(0.02), np.log(0.5))))
+        noise = float(np.exp(g.uniform(np.log(1e-4), np.log(1e-1))))
+        out.append(GPInstance(f"c5f_{i}", n=n, d=3, kind=MATERN52, lengthscale=ls, variance=1.0,
+                              noise=noise, points="uniform", seed=seed * 1000 + i,
+                              rank=max(1, n // 40), probes=probes, orders=(5,),
+                              probe_seed=seed + 10000 + i, precond_seed=seed + 20000 + i))
+    return out
+
+
 def surrogate_grid(n: int, side: int = 32, seed: int = BASE_SEED + 5, probes: int = 64):
     """The evaluation sweep: side x side log-spaced (lengthscale, noise) pairs,
     variance 1, Matern-5/2, d = 3, one point cloud shared by the grid."""

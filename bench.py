@@ -632,6 +632,11 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="override n (smaller test runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=8000)
+    ap.add_argument("--kernel-kind", default="", choices=["", "rbf", "matern52"],
+                    help="override the workload's covariance kernel (same points and sizes)")
+    ap.add_argument("--plain-fp32", action="store_true",
+                    help="c3: time the plain FP32 on-the-fly path as the main path (its "
+                         "product kernel's FP32 matrix-core fraction)")
     ap.add_argument("--compare-fp32", action="store_true",
                     help="precision form: also time the plain FP32 path on the same problem")
     ap.add_argument("--stored-bf16", action="store_true",
@@ -693,10 +698,15 @@ def main():
     cfg = WORKLOADS[args.workload]
     if args.n:
         cfg = cfg.with_n(args.n, rank=min(cfg.rank, args.n // 10))
+    if args.kernel_kind:
+        cfg = replace(cfg, kind=workloads.RBF if args.kernel_kind == "rbf" else workloads.MATERN52,
+                      name=f"{cfg.name}@{args.kernel_kind}")
     kind = args.workload.split("_")[0]
     precision = {"c1": L.LD_F64, "c2": L.LD_F32, "c3": L.LD_BF16}[kind]
     if kind == "c2" and args.stored_bf16:
         precision = L.LD_BF16
+    if kind == "c3" and args.plain_fp32:
+        precision = L.LD_F32
     stored = kind == "c2"
     dtype = {L.LD_F64: "f64", L.LD_F32: "f32", L.LD_BF16: "bf16x3+f32"}[precision]
     log(f"[bench] workload {cfg.name} n={cfg.n} rank={cfg.rank} probes={cfg.probes} "
@@ -736,6 +746,8 @@ def main():
     kname = {"c2": "k_mm32_tf<2> (FP32 MFMA 32x32x2, stored LD_TILED fragment tiles)",
              "c1": "k_mm64<fly> (FP64 MFMA 16x16x4, on the fly)",
              "c3": "k_mm16<fly> (split-BF16 MFMA 32x32x16, 3 terms, on the fly)"}[kind]
+    if kind == "c3" and precision == L.LD_F32:
+        kname = "k_mm32_fly (FP32 MFMA 32x32x2, kernel entries generated on the fly)"
     traffic = profiled_traffic(cfg.name) if not args.n and precision == L.LD_F32 else None
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": traffic, "kernel": kname,

@@ -146,7 +146,10 @@ ld_status path_points(ld_ctx* ctx, const ld_operator* op, const void** X) {
   }
   float* x32 = (float*)ctx->arena.take((size_t)op->n * op->d * sizeof(float));
   if (!x32) return fail(LD_ENOMEM, "scratch arena too small for FP32 points");
-  launch_convert_f64_to_f32(ctx->stream, op->X, x32, op->n * op->d);
+  // scaled in FP64 before rounding, so that the fused kernels read squared
+  // distances in the kernel's own units (kval32s)
+  launch_convert_f64_to_f32_scaled(ctx->stream, op->X, x32, op->n * op->d,
+                                   point_scale(make_kparams(*op)));
   *X = x32;
   return LD_OK;
 }

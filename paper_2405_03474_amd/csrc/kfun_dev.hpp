@@ -28,6 +28,20 @@ __device__ __forceinline__ float kval32(float r2, float v, float c) {
   return p * __builtin_amdgcn_exp2f(-u);
 }
 
+// The same values from points pre-scaled by sqrt(c) (RBF) or c (Matern), so
+// that r2 arrives in the kernel's own units (the base-2 exponent): RBF
+// exp2(v - r2) with v = log2(variance); Matern
+// (v + v u / log2(e) + v u^2 / (3 log2(e)^2)) exp2(-u) with u = sqrt(r2) and
+// v = variance.  One multiplication fewer per entry for Matern.
+template <int KIND>
+__device__ __forceinline__ float kval32s(float r2, float v) {
+  if (KIND == LD_RBF) return __builtin_amdgcn_exp2f(v - r2);
+  const float u = __builtin_amdgcn_sqrtf(r2);
+  const float p = __builtin_fmaf(
+      u, __builtin_fmaf(u, v * (1.0f / (3.0f * kLog2eF * kLog2eF)), v * (1.0f / kLog2eF)), v);
+  return p * __builtin_amdgcn_exp2f(-u);
+}
+
 // Derivatives of the kernels with respect to the lengthscale l, as further
 // FP64 kernel kinds (gradient of log det): with the same c as the kernel,
 //   RBF     dk/dl = (variance / l^3) r^2 exp(-r^2 c)

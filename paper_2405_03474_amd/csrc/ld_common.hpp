@@ -194,6 +194,11 @@ inline int64_t stored_elements(int64_t n, int layout) {
   return n * n;
 }
 void launch_convert_f64_to_f32(hipStream_t st, const double* in, float* out, int64_t count);
+// out = (float)(in * scale); the FP32 points of the fused kernels use
+// scale = point_scale(kp)
+void launch_convert_f64_to_f32_scaled(hipStream_t st, const double* in, float* out, int64_t count,
+                                      double scale);
+double point_scale(const KParams& kp);
 void launch_convert_f32_to_f64(hipStream_t st, const float* in, double* out, int64_t count);
 
 // dense64.hip -- FP64 small/tall dense algebra for the preconditioner

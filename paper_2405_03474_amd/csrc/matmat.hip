@@ -70,8 +70,9 @@ __host__ __device__ inline WGRange wg_range(const SK& p, int g) {
 }
 
 // ---------------------------------------------------------- kernel values --
-// FP32 kernel values: kval32 (kfun_dev.hpp), shared with the batched path.
-using dev::kval32;
+// FP32 kernel values from pre-scaled points: kval32s (kfun_dev.hpp; the
+// batched path uses kval32 on unscaled points).
+using dev::kval32s;
 using dev::kval64;
 
 
@@ -117,7 +118,7 @@ __device__ __forceinline__ void fly_load(FlyTile<NB>& t, const float* __restrict
 
 template <int NB, int KIND, int DT>
 __global__ __launch_bounds__(256, 2) void k_mm32_fly(const float* __restrict__ Xp, int d,
-                                                     float var, float c,
+                                                     float var,
                                                      const float* __restrict__ V,
                                                      float* __restrict__ part, SK p) {
   constexpr int NT = 32 * NB;
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(256, 2) void k_mm32_fly(const float* __restrict__ X
             const float df = xr[dd] - xk[dd];
             r2 = __builtin_fmaf(df, df, r2);
           }
-        a[t] = kval32<KIND>(r2, var, c);
+        a[t] = kval32s<KIND>(r2, var);
       }
 #pragma unroll
       for (int t = 0; t < 16; ++t)
@@ -603,7 +604,7 @@ template <int NB, int KIND, int DT>
 __device__ __forceinline__ void f16_compute(const __bf16* __restrict__ bh,
                                             const __bf16* __restrict__ bl,
                                             const float* __restrict__ xs, const float* xr, int d,
-                                            float var, float c, f32x16* acc, int li, int lh) {
+                                            float var, f32x16* acc, int li, int lh) {
   const int dd_n = DT > 0 ? DT : d;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -618,7 +619,7 @@ __device__ __forceinline__ void f16_compute(const __bf16* __restrict__ bh,
           const float df = xr[dd] - xk[dd];
           r2 = __builtin_fmaf(df, df, r2);
         }
-      kv[j] = kval32<KIND>(r2, var, c);
+      kv[j] = kval32s<KIND>(r2, var);
     }
     u32x4 hw, lw;
 #pragma unroll
@@ -817,7 +818,7 @@ __global__ __launch_bounds__(256, 2) void k_mm16_st(const __bf16* __restrict__ A
 
 template <int NB, int KIND, int DT>
 __global__ __launch_bounds__(256, 2) void k_mm16(const float* __restrict__ Xp, int d, float var,
-                                                 float c, const float* __restrict__ V,
+                                                 const float* __restrict__ V,
                                                  float* __restrict__ part, SK p) {
   constexpr int NT = 32 * NB;
   __shared__ __attribute__((aligned(16))) __bf16 Bh[2][NT * BS16];
@@ -863,7 +864,7 @@ __global__ __launch_bounds__(256, 2) void k_mm16(const float* __restrict__ Xp, i
       f16_store<NB>(tl, Bh[buf], Bl[buf], Xs[buf], tid);
       __syncthreads();
       if (st + 1 < st1) f16_load<NB, DT>(tl, Xp, d, V, n, s, c0, (int64_t)(st + 1) * BK16, tid);
-      f16_compute<NB, KIND, DT>(Bh[buf], Bl[buf], Xs[buf], xr, d, var, c, acc, li, lh);
+      f16_compute<NB, KIND, DT>(Bh[buf], Bl[buf], Xs[buf], xr, d, var, acc, li, lh);
       buf ^= 1;
     }
 
@@ -1259,12 +1260,12 @@ Plan make_plan(ld_ctx* ctx, bool f64, int64_t n, int64_t s, int bk = BK) {
 }
 
 template <int KIND, int DT>
-void launch_fly32(int NB, dim3 g, hipStream_t st, const float* X, int d, float var, float c,
+void launch_fly32(int NB, dim3 g, hipStream_t st, const float* X, int d, float var,
                   const float* V, float* part, const SK& p) {
   if (NB == 2)
-    hipLaunchKernelGGL((k_mm32_fly<2, KIND, DT>), g, dim3(256), 0, st, X, d, var, c, V, part, p);
+    hipLaunchKernelGGL((k_mm32_fly<2, KIND, DT>), g, dim3(256), 0, st, X, d, var, V, part, p);
   else
-    hipLaunchKernelGGL((k_mm32_fly<1, KIND, DT>), g, dim3(256), 0, st, X, d, var, c, V, part, p);
+    hipLaunchKernelGGL((k_mm32_fly<1, KIND, DT>), g, dim3(256), 0, st, X, d, var, V, part, p);
 }
 
 template <int KIND, int DT>
@@ -1282,33 +1283,33 @@ void launch_fly64(int NB, dim3 g, hipStream_t st, const double* X, int d, double
 }
 
 template <int KIND, int DT>
-void launch_fly16(int NB, dim3 g, hipStream_t st, const float* X, int d, float var, float c,
+void launch_fly16(int NB, dim3 g, hipStream_t st, const float* X, int d, float var,
                   const float* V, float* part, const SK& p) {
   if (NB == 2)
-    hipLaunchKernelGGL((k_mm16<2, KIND, DT>), g, dim3(256), 0, st, X, d, var, c, V, part, p);
+    hipLaunchKernelGGL((k_mm16<2, KIND, DT>), g, dim3(256), 0, st, X, d, var, V, part, p);
   else
-    hipLaunchKernelGGL((k_mm16<1, KIND, DT>), g, dim3(256), 0, st, X, d, var, c, V, part, p);
+    hipLaunchKernelGGL((k_mm16<1, KIND, DT>), g, dim3(256), 0, st, X, d, var, V, part, p);
 }
 
 template <int KIND>
-void fly16_by_d(int NB, dim3 g, hipStream_t st, const float* X, int d, float var, float c,
+void fly16_by_d(int NB, dim3 g, hipStream_t st, const float* X, int d, float var,
                 const float* V, float* part, const SK& p) {
   switch (d) {
-    case 2: launch_fly16<KIND, 2>(NB, g, st, X, d, var, c, V, part, p); break;
-    case 3: launch_fly16<KIND, 3>(NB, g, st, X, d, var, c, V, part, p); break;
-    case 8: launch_fly16<KIND, 8>(NB, g, st, X, d, var, c, V, part, p); break;
-    default: launch_fly16<KIND, 0>(NB, g, st, X, d, var, c, V, part, p); break;
+    case 2: launch_fly16<KIND, 2>(NB, g, st, X, d, var, V, part, p); break;
+    case 3: launch_fly16<KIND, 3>(NB, g, st, X, d, var, V, part, p); break;
+    case 8: launch_fly16<KIND, 8>(NB, g, st, X, d, var, V, part, p); break;
+    default: launch_fly16<KIND, 0>(NB, g, st, X, d, var, V, part, p); break;
   }
 }
 
 template <int KIND>
-void fly32_by_d(int NB, dim3 g, hipStream_t st, const float* X, int d, float var, float c,
+void fly32_by_d(int NB, dim3 g, hipStream_t st, const float* X, int d, float var,
                 const float* V, float* part, const SK& p) {
   switch (d) {
-    case 2: launch_fly32<KIND, 2>(NB, g, st, X, d, var, c, V, part, p); break;
-    case 3: launch_fly32<KIND, 3>(NB, g, st, X, d, var, c, V, part, p); break;
-    case 8: launch_fly32<KIND, 8>(NB, g, st, X, d, var, c, V, part, p); break;
-    default: launch_fly32<KIND, 0>(NB, g, st, X, d, var, c, V, part, p); break;
+    case 2: launch_fly32<KIND, 2>(NB, g, st, X, d, var, V, part, p); break;
+    case 3: launch_fly32<KIND, 3>(NB, g, st, X, d, var, V, part, p); break;
+    case 8: launch_fly32<KIND, 8>(NB, g, st, X, d, var, V, part, p); break;
+    default: launch_fly32<KIND, 0>(NB, g, st, X, d, var, V, part, p); break;
   }
 }
 
@@ -1395,22 +1396,21 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
                        a.dots);
   } else {
     const int NB = pl.NT / 32;
-    // kval32 constants: exponents in base 2; RBF carries log2(variance)
-    const double l2e = 1.4426950408889634;
-    const float c = (float)((kind == LD_RBF ? a.kp.c_rbf : a.kp.c_mat) * l2e);
+    // kval32s: the FP32 points arrive scaled by point_scale (path_points), so
+    // r2 is already in the kernel's units; RBF carries log2(variance)
     const float var = (float)(kind == LD_RBF ? std::log2(a.kp.variance) : a.kp.variance);
     const float* V = (const float*)a.V;
     float* P = (float*)part;
     if (split16) {
       if (kind == LD_RBF)
-        fly16_by_d<LD_RBF>(NB, grid, st, (const float*)a.X, a.d, var, c, V, P, pl.p);
+        fly16_by_d<LD_RBF>(NB, grid, st, (const float*)a.X, a.d, var, V, P, pl.p);
       else
-        fly16_by_d<LD_MATERN52>(NB, grid, st, (const float*)a.X, a.d, var, c, V, P, pl.p);
+        fly16_by_d<LD_MATERN52>(NB, grid, st, (const float*)a.X, a.d, var, V, P, pl.p);
     } else if (fly) {
       if (kind == LD_RBF)
-        fly32_by_d<LD_RBF>(NB, grid, st, (const float*)a.X, a.d, var, c, V, P, pl.p);
+        fly32_by_d<LD_RBF>(NB, grid, st, (const float*)a.X, a.d, var, V, P, pl.p);
       else
-        fly32_by_d<LD_MATERN52>(NB, grid, st, (const float*)a.X, a.d, var, c, V, P, pl.p);
+        fly32_by_d<LD_MATERN52>(NB, grid, st, (const float*)a.X, a.d, var, V, P, pl.p);
     } else {
       const float* A = (const float*)a.A;
       const bool tiled = a.layout == LD_TILED;
@@ -1492,6 +1492,24 @@ void launch_materialize(hipStream_t st, const KParams& kp, const double* X, int6
   else
     materialize_rm<float>(st, kp.kind, d <= DMAX, grid, X, n, d, kp.variance, c, kp.noise,
                           (float*)M);
+}
+
+__global__ void k_f64_to_f32_scaled(const double* __restrict__ in, float* __restrict__ out,
+                                    int64_t count, double scale) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256)
+    out[i] = (float)(in[i] * scale);
+}
+
+void launch_convert_f64_to_f32_scaled(hipStream_t st, const double* in, float* out, int64_t count,
+                                      double scale) {
+  if (count > 0)
+    hipLaunchKernelGGL(k_f64_to_f32_scaled, dim3(grid1(count)), dim3(256), 0, st, in, out, count,
+                       scale);
+}
+
+double point_scale(const KParams& kp) {
+  const double l2e = 1.4426950408889634;
+  return kp.kind == LD_RBF ? std::sqrt(kp.c_rbf * l2e) : kp.c_mat * l2e;
 }
 
 void launch_convert_f64_to_f32(hipStream_t st, const double* in, float* out, int64_t count) {

@@ -600,13 +600,14 @@ def sensitivity_main(args, torch, L):
     print(json.dumps(line))
 
 
-def timed_steps(runner, steps, warmup, stream, torch):
+def timed_steps(runner, steps, warmup, stream, torch, instrument=True):
     for w in range(warmup):
         t0 = time.perf_counter()
         runner.step()
         torch.cuda.synchronize()
         log(f"[bench] warmup {w} {time.perf_counter() - t0:.3f} s")
-    runner.ctx.set_timing(True)
+    if instrument:
+        runner.ctx.set_timing(True)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record(stream)
@@ -618,7 +619,7 @@ def timed_steps(runner, steps, warmup, stream, torch):
     stop.record(stream)
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop)
-    timing = runner.ctx.read_timing()
+    timing = runner.ctx.read_timing() if instrument else None
     runner.ctx.set_timing(False)
     return results, ms, time.perf_counter() - t0, timing
 
@@ -632,6 +633,8 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="override n (smaller test runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=8000)
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay the solver's iterations from captured HIP graphs")
     ap.add_argument("--kernel-kind", default="", choices=["", "rbf", "matern52"],
                     help="override the workload's covariance kernel (same points and sizes)")
     ap.add_argument("--plain-fp32", action="store_true",
@@ -722,8 +725,16 @@ def main():
                     "orthogonal": L.LD_PROBE_ORTHOGONAL}[args.probes])
     runner = Runner(L, torch, ctx, cfg, precision, stored, args.lanczos_steps, args.precond,
                     args.scaled, args.union_shifts)
-    results, ms_total, wall, (mm_ms, mm_calls, mm_flops, mm_bytes) = timed_steps(
-        runner, args.steps, args.warmup, stream, torch)
+    if args.graphs:
+        # replayed iterations carry no timing events: the timed steps run
+        # uninstrumented, one more instrumented (eager) step times the product
+        ctx.set_graphs(True)
+        results, ms_total, wall, _ = timed_steps(runner, args.steps, args.warmup, stream, torch,
+                                                 instrument=False)
+        _, _, _, (mm_ms, mm_calls, mm_flops, mm_bytes) = timed_steps(runner, 1, 0, stream, torch)
+    else:
+        results, ms_total, wall, (mm_ms, mm_calls, mm_flops, mm_bytes) = timed_steps(
+            runner, args.steps, args.warmup, stream, torch)
 
     n_est = args.steps * len(cfg.orders)
     value = n_est / (ms_total / 1e3)
@@ -771,7 +782,8 @@ def main():
                    "solver": ({"kind": "lanczos", "steps": args.lanczos_steps}
                               if args.lanczos_steps else
                               {"kind": "multishift_pcg", "tol": runner.tol,
-                               "orders_share_probes": bool(args.union_shifts)})},
+                               "orders_share_probes": bool(args.union_shifts),
+                               "graph_replay": bool(args.graphs)})},
         "probe_solves_per_s": cfg.probes * n_est / (ms_total / 1e3),
         "iterations": {f"r{k}": last[k]["iterations"] for k in cfg.orders},
         "wall_s": wall, "accuracy": accuracy, "roofline": roofline,

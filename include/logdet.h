@@ -162,6 +162,16 @@ ld_status ld_set_workspace(ld_ctx* ctx, void* dev_ptr, size_t bytes);
  * V read and Y written; batched: also the addend and the points).
  * ld_ctx_set_timing resets the totals.  Any output pointer may be NULL. */
 ld_status ld_ctx_set_timing(ld_ctx* ctx, int32_t on);
+
+/* Launch overhead.  With graphs on, the multi-shift CG of logdet_estimate,
+ * logdet_estimate_orders and logdet_gradient captures its first full chunk of
+ * iterations between convergence checks (8 below n = 16,384, else 1) as a HIP
+ * graph and replays it for the later chunks, on a side stream of the context
+ * that waits for the context stream and is waited for by it (so ordering is
+ * as without graphs).  Results are identical; small problems, whose
+ * iterations are a dozen short kernels, run faster.  Off by default; ignored
+ * while timing is on (events are not recorded inside graphs). */
+ld_status ld_ctx_set_graphs(ld_ctx* ctx, int32_t on);
 ld_status ld_ctx_read_timing(ld_ctx* ctx, double* ms, int64_t* calls, double* flops, double* bytes);
 
 /* Probe distributions of Algorithm 1 step 1 (mean 0, variance 1):

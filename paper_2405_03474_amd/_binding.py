@@ -33,7 +33,7 @@ STATUS_NAMES = {0: "LD_OK", -1: "LD_EINVAL", -2: "LD_ENOTSPD", -3: "LD_ENOCONV",
 
 EXPORTED = (
     "ld_ctx_create", "ld_ctx_destroy", "ld_last_error", "ld_ctx_set_timing", "ld_ctx_read_timing",
-    "ld_ctx_set_probes", "ld_workspace_bytes", "ld_set_workspace",
+    "ld_ctx_set_probes", "ld_ctx_set_graphs", "ld_workspace_bytes", "ld_set_workspace",
     "ld_stored_elements", "ld_rational_coeffs", "ld_fill_probes",
     "ld_fill_gaussian", "kernel_matmat", "kernel_materialize", "logdet_precond_build",
     "logdet_precond_build_kind", "ld_precond_info", "ld_precond_export",
@@ -105,6 +105,7 @@ def load():
         "ld_ctx_set_timing": (i32, [vp, i32]),
         "ld_ctx_read_timing": (i32, [vp, pd, ctypes.POINTER(i64), pd, pd]),
         "ld_ctx_set_probes": (i32, [vp, i32]),
+        "ld_ctx_set_graphs": (i32, [vp, i32]),
         "ld_stored_elements": (i64, [i64, i32]),
         "ld_rational_coeffs": (i32, [i32, pd, pd, pd]),
         "ld_fill_probes": (i32, [vp, u64, i64, i64, i32, vp]),
@@ -216,6 +217,10 @@ class Context:
         nbytes = buf.numel() * buf.element_size()
         _check(load().ld_set_workspace(self.handle, ctypes.c_void_p(buf.data_ptr()), nbytes))
         self._workspace = buf   # kept alive with the context
+
+    def set_graphs(self, on: bool = True):
+        """Replay the solver's iterations from captured HIP graphs."""
+        _check(load().ld_ctx_set_graphs(self.handle, 1 if on else 0))
 
     def set_probes(self, kind: int):
         """Probe distribution (LD_PROBE_*) of later single-problem estimates."""

@@ -829,6 +829,12 @@ ld_status ld_ctx_set_timing(ld_ctx* ctx, int32_t on) {
   return LD_OK;
 }
 
+ld_status ld_ctx_set_graphs(ld_ctx* ctx, int32_t on) {
+  if (!ctx) return fail(LD_EINVAL, "context is NULL");
+  ctx->graphs = on != 0;
+  return LD_OK;
+}
+
 ld_status ld_ctx_set_probes(ld_ctx* ctx, int32_t kind) {
   if (!ctx) return fail(LD_EINVAL, "context is NULL");
   if (kind != LD_PROBE_RADEMACHER && kind != LD_PROBE_GAUSSIAN && kind != LD_PROBE_ORTHOGONAL)

@@ -72,6 +72,8 @@ struct ld_ctx {
   size_t pinned_count = 0;
   // optional event timing of the solver's kernel-matrix product launches
   bool timing = false;
+  // replay the solver's iterations from captured HIP graphs (ld_ctx_set_graphs)
+  bool graphs = false;
   std::vector<hipEvent_t> ev;  // pairs (start, stop)
   size_t ev_used = 0;          // events recorded and not yet collected
   double mm_ms = 0.0;

@@ -1197,6 +1197,65 @@ struct PcgOut {
   bool breakdown = false;
 };
 
+// While a solve replays captured chunks it runs on the context's side stream
+// (the caller's stream may be the null stream, which cannot be captured):
+// the side stream first waits for the work already on the context stream,
+// and on scope exit the context stream waits for the side stream and is
+// restored, so stream order is as if everything ran on it.
+struct SideStream {
+  ld_ctx* ctx = nullptr;
+  hipStream_t orig = nullptr;
+  ld_status enter(ld_ctx* c) {
+    if (!c->side) LD_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    if (!c->ev_join) LD_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    LD_HIP(hipEventRecord(c->ev_join, c->stream));
+    LD_HIP(hipStreamWaitEvent(c->side, c->ev_join, 0));
+    ctx = c;
+    orig = c->stream;
+    c->stream = c->side;
+    return LD_OK;
+  }
+  ~SideStream() {
+    if (!ctx) return;
+    if (hipEventRecord(ctx->ev_join, ctx->side) == hipSuccess)
+      (void)hipStreamWaitEvent(orig, ctx->ev_join, 0);
+    ctx->stream = orig;
+  }
+};
+
+// A captured chunk of solver iterations (HIP graph), replayed on the same
+// stream.  If capture or instantiation is refused, `failed` is set and the
+// caller runs the chunk eagerly; the stream always leaves capture mode.
+struct GraphChunk {
+  hipGraphExec_t exec = nullptr;
+  bool failed = false;
+  template <typename F>
+  ld_status capture(hipStream_t st, F&& enqueue) {
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) != hipSuccess) {
+      (void)hipGetLastError();
+      failed = true;
+      return LD_OK;
+    }
+    const ld_status body = enqueue();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &g);
+    if (body != LD_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return body;
+    }
+    if (e != hipSuccess || !g || hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      exec = nullptr;
+      failed = true;
+    }
+    if (g) (void)hipGraphDestroy(g);
+    return LD_OK;
+  }
+  ~GraphChunk() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+  }
+};
+
 template <typename T>
 ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precond* P,
                   const double* shifts, int J, const Coef* cfs, int ncf, const T* Z, int64_t s,
@@ -1267,41 +1326,59 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
   LD_HIP(hipGetLastError());
 
   const int check_every = n >= 16384 ? 1 : 8;
+  // one CG iteration, every shift (all device work; the same buffers and
+  // launch shapes each time, so a chunk of them can be captured and replayed)
+  auto iteration = [&]() -> ld_status {
+    ctx->arena.top = mark;
+    MatmatArgs a = base;
+    a.s = s;
+    a.V = w;
+    a.Y = q;
+    a.X2 = p;
+    a.alpha2 = shifts[0];
+    a.dots = dwq;
+    a.timed = true;
+    int nb = 0;
+    a.dot_blocks = &nb;
+    LD_TRY(matmat(ctx, f64, a));
+    hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, dwq, nb, s, sg1);
+    hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(256), 0, st, S, sg1, kSeg, s);
+    if (ysol)
+      hipLaunchKernelGGL(k_update_ry<T>, dim3(grid1(vec)), dim3(256), 0, st, r, q, ysol, w,
+                         S.alpha, n, s);
+    else
+      hipLaunchKernelGGL(k_update_r<T>, dim3(grid1(vec)), dim3(256), 0, st, r, q, S.alpha, n, s);
+    ctx->arena.top = mark;
+    LD_TRY(wood_apply_t<T>(ctx, P, r, s, u, Z, d1, d2));
+    hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, d1, (int)wrt, s, sg1);
+    hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, d2, (int)wrt, s, sg2);
+    hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(256), 0, st, S, sg1, sg2, kSeg, s, J, delta,
+                       tol);
+    hipLaunchKernelGGL(k_update_pw<T>, dim3(grid1(vec)), dim3(256), 0, st, p, w, r, u, S.beta,
+                       S.active, n, s);
+    LD_HIP(hipGetLastError());
+    return LD_OK;
+  };
+  // Optional replay (ld_ctx_set_graphs; not while timing events are on):
+  // the first full chunk of check_every iterations is captured once and
+  // replayed for every later full chunk; a shorter last chunk runs eagerly.
+  GraphChunk chunk;
+  const bool replay = ctx->graphs && !ctx->timing;
   int it = 0;
   int active = (int)s;
   while (it < max_iters && active > 0) {
     const int todo = std::min(check_every, max_iters - it);
-    for (int k = 0; k < todo; ++k) {
-      ctx->arena.top = mark;
-      MatmatArgs a = base;
-      a.s = s;
-      a.V = w;
-      a.Y = q;
-      a.X2 = p;
-      a.alpha2 = shifts[0];
-      a.dots = dwq;
-      a.timed = true;
-      int nb = 0;
-      a.dot_blocks = &nb;
-      LD_TRY(matmat(ctx, f64, a));
-      hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, dwq, nb, s, sg1);
-      hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(256), 0, st, S, sg1, kSeg, s);
-      if (ysol)
-        hipLaunchKernelGGL(k_update_ry<T>, dim3(grid1(vec)), dim3(256), 0, st, r, q, ysol, w,
-                           S.alpha, n, s);
-      else
-        hipLaunchKernelGGL(k_update_r<T>, dim3(grid1(vec)), dim3(256), 0, st, r, q, S.alpha, n, s);
-      ctx->arena.top = mark;
-      LD_TRY(wood_apply_t<T>(ctx, P, r, s, u, Z, d1, d2));
-      hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, d1, (int)wrt, s, sg1);
-      hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, d2, (int)wrt, s, sg2);
-      hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(256), 0, st, S, sg1, sg2, kSeg, s, J, delta,
-                         tol);
-      hipLaunchKernelGGL(k_update_pw<T>, dim3(grid1(vec)), dim3(256), 0, st, p, w, r, u, S.beta,
-                         S.active, n, s);
-      LD_HIP(hipGetLastError());
-      ++it;
+    if (replay && todo == check_every && !chunk.exec && !chunk.failed)
+      LD_TRY(chunk.capture(st, [&]() -> ld_status {
+        for (int k = 0; k < todo; ++k) LD_TRY(iteration());
+        return LD_OK;
+      }));
+    if (replay && todo == check_every && chunk.exec) {
+      LD_HIP(hipGraphLaunch(chunk.exec, st));
+    } else {
+      for (int k = 0; k < todo; ++k) LD_TRY(iteration());
     }
+    it += todo;
     LD_HIP(hipMemcpyAsync(ctx->pinned, S.status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     LD_HIP(hipStreamSynchronize(st));
     timing_collect(ctx);
@@ -1349,6 +1426,8 @@ ld_status multishift_pcg(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld
                          void* ysol) {
   PcgOut o;
   ld_status stt;
+  SideStream side;
+  if (ctx->graphs && !ctx->timing) LD_TRY(side.enter(ctx));
   if (f64)
     stt = pcg_run<double>(ctx, true, base, P, cf.a, cf.J, &cf, 1, (const double*)Z, s, tol,
                           max_iters, per_probe, mean, stderr_, o, (double*)ysol);
@@ -1369,6 +1448,8 @@ ld_status multishift_pcg_multi(ld_ctx* ctx, bool f64, const MatmatArgs& base, co
                                bool* breakdown) {
   PcgOut o;
   ld_status stt;
+  SideStream side;
+  if (ctx->graphs && !ctx->timing) LD_TRY(side.enter(ctx));
   if (f64)
     stt = pcg_run<double>(ctx, true, base, P, cfs[0].a, cfs[0].J, cfs, ncf, (const double*)Z, s,
                           tol, max_iters, per_probe, mean, stderr_, o, (double*)nullptr);

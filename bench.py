@@ -785,6 +785,10 @@ def main():
                                "orders_share_probes": bool(args.union_shifts),
                                "graph_replay": bool(args.graphs)})},
         "probe_solves_per_s": cfg.probes * n_est / (ms_total / 1e3),
+        # the same estimates without the preconditioner build and M (host wall
+        # time of each solve as the library reports it)
+        "solve_only_estimates_per_s": n_est / max(sum(r[k]["seconds_solve"] for r in results
+                                                      for k in cfg.orders), 1e-12),
         "iterations": {f"r{k}": last[k]["iterations"] for k in cfg.orders},
         "wall_s": wall, "accuracy": accuracy, "roofline": roofline,
     }

@@ -43,7 +43,8 @@ struct BInst {
   int64_t n, row0;
   int d, kind, m, rank;
   int ch0, nch;  // first FTC-row chunk (global index) and chunk count
-  float kv, kc, noise;
+  float kv, noise;       // kv: log2(variance) for RBF, variance for Matern
+  double pscale;         // FP32 points are stored times this (see kval32s)
   double diag, floor_v, shift_c;
   uint64_t key_omega, key_probe;
 };
@@ -63,7 +64,7 @@ __global__ void k_bx32(const BInst* __restrict__ inst, const int* __restrict__ b
     const int dd = (int)(e % BDX);
     const BInst& I = inst[blk_inst[row / BLK]];
     const int64_t lr = row - I.row0;
-    X32[e] = (lr < I.n && dd < I.d) ? (float)I.X64[lr * I.d + dd] : 0.f;
+    X32[e] = (lr < I.n && dd < I.d) ? (float)(I.X64[lr * I.d + dd] * I.pscale) : 0.f;
   }
 }
 
@@ -148,7 +149,7 @@ __device__ __forceinline__ void bmm_body(const BInst& I, const BItem& it, const 
   const int64_t r0 = I.row0 + (int64_t)it.rb * BMW;  // first global row of the block
   const int c0 = it.cb * NT;
   const float* Vi = V + I.row0 * ld;
-  const float kv = I.kv, kc = I.kc;
+  const float kv = I.kv;
 
   // this lane's row points (MF = 32: one row; MF = 16: one per half)
   constexpr int NR = MF == 32 ? 1 : 2;
@@ -199,7 +200,7 @@ __device__ __forceinline__ void bmm_body(const BInst& I, const BItem& it, const 
       const float df = xr_[dd] - xk[dd];
       r2 = __builtin_fmaf(df, df, r2);
     }
-    return dev::kval32<KIND>(r2, kv, kc);
+    return dev::kval32s<KIND>(r2, kv);
   };
   load(0);
   int buf = 0;
@@ -1240,7 +1241,12 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
     I.ch0 = nchunks;
     I.nch = (int)((x.n + FTC - 1) / FTC);
     nchunks += I.nch;
-    dev::kval32_consts(x.kind, x.lengthscale, x.variance, &I.kc, &I.kv);
+    // points pre-scaled so that r2 is the base-2 exponent (RBF) or its
+    // square root is (Matern): kval32s
+    const double l2e = 1.4426950408889634;
+    I.pscale = x.kind == LD_RBF ? std::sqrt(l2e / (2.0 * x.lengthscale * x.lengthscale))
+                                : 2.23606797749978969640917366873128 * l2e / x.lengthscale;
+    I.kv = (float)(x.kind == LD_RBF ? std::log2(x.variance) : x.variance);
     I.noise = (float)x.noise;
     I.diag = x.variance + x.noise;
     I.floor_v = x.noise > 0.0 ? x.noise : 1e-12 * x.variance;

@@ -14,25 +14,13 @@ namespace dev {
 
 constexpr float kLog2eF = 1.4426950408889634f;
 
-// Constants are folded into base-2 exponents:
-//   RBF     c = log2(e) / (2 l^2),  v = log2(variance):  2^(v - c r^2)
-//   Matern  c = sqrt(5) log2(e) / l, v = variance: with u = c r (= t log2 e,
-//           t = sqrt5 r / l), variance (1 + t + t^2/3) e^-t
+// FP32 kernel values with the constants folded into base-2 exponents and
+// into the points: the FP32 points are stored times
+//   RBF     sqrt(c), c = log2(e) / (2 l^2):  r2 = c r^2 (scaled), v = log2(variance),
+//           value 2^(v - r2)
+//   Matern  c = sqrt(5) log2(e) / l:  u = sqrt(r2) = c r (= t log2 e, t = sqrt5 r / l),
+//           v = variance, value variance (1 + t + t^2/3) e^-t
 //           = (v + u v / log2e + u^2 v / (3 log2e^2)) 2^-u
-template <int KIND>
-__device__ __forceinline__ float kval32(float r2, float v, float c) {
-  if (KIND == LD_RBF) return __builtin_amdgcn_exp2f(__builtin_fmaf(-r2, c, v));
-  const float u = __builtin_amdgcn_sqrtf(r2) * c;
-  const float p = __builtin_fmaf(
-      u, __builtin_fmaf(u, v * (1.0f / (3.0f * kLog2eF * kLog2eF)), v * (1.0f / kLog2eF)), v);
-  return p * __builtin_amdgcn_exp2f(-u);
-}
-
-// The same values from points pre-scaled by sqrt(c) (RBF) or c (Matern), so
-// that r2 arrives in the kernel's own units (the base-2 exponent): RBF
-// exp2(v - r2) with v = log2(variance); Matern
-// (v + v u / log2(e) + v u^2 / (3 log2(e)^2)) exp2(-u) with u = sqrt(r2) and
-// v = variance.  One multiplication fewer per entry for Matern.
 template <int KIND>
 __device__ __forceinline__ float kval32s(float r2, float v) {
   if (KIND == LD_RBF) return __builtin_amdgcn_exp2f(v - r2);
@@ -58,18 +46,6 @@ __device__ __forceinline__ double kval64(double r2, double var, double c) {
   const double t = sqrt(r2) * c;
   if (KIND == kKindMaternDl) return var * t * t * (1.0 + t) * exp(-t);
   return var * (1.0 + t + t * t * (1.0 / 3.0)) * exp(-t);
-}
-
-// Host-side constants (c, v) of kval32 for lengthscale l and variance.
-inline void kval32_consts(int kind, double lengthscale, double variance, float* c, float* v) {
-  const double l2e = 1.4426950408889634;
-  if (kind == LD_RBF) {
-    *c = (float)(l2e / (2.0 * lengthscale * lengthscale));
-    *v = (float)std::log2(variance);
-  } else {
-    *c = (float)(2.23606797749978969640917366873128 * l2e / lengthscale);
-    *v = (float)variance;
-  }
 }
 
 }  // namespace dev

@@ -70,8 +70,8 @@ __host__ __device__ inline WGRange wg_range(const SK& p, int g) {
 }
 
 // ---------------------------------------------------------- kernel values --
-// FP32 kernel values from pre-scaled points: kval32s (kfun_dev.hpp; the
-// batched path uses kval32 on unscaled points).
+// FP32 kernel values from pre-scaled points: kval32s (kfun_dev.hpp), shared
+// with the batched path.
 using dev::kval32s;
 using dev::kval64;
 

@@ -435,6 +435,14 @@ __global__ __launch_bounds__(256, 2) void k_mm32_tf(const float* __restrict__ A,
     };
     auto load_b = [&](int st) {
       const int64_t k0 = (int64_t)st * BK;
+      if (k0 + BK <= n && c0 + NT <= s) {
+        // the whole stage is inside V (uniform over the workgroup): no
+        // per-element branches, all loads in flight together
+        const float* src = V + (k0 + tid / NT) * s + c0 + tid % NT;
+#pragma unroll
+        for (int j = 0; j < 4 * NB; ++j) bq[j] = src[(int64_t)(256 / NT) * j * s];
+        return;
+      }
 #pragma unroll
       for (int j = 0; j < 4 * NB; ++j) {
         const int e = tid + 256 * j;

@@ -33,7 +33,22 @@ Workloads (all synthetic, inputs from workloads/):
                    prediction + fallback to the estimator where the members
                    disagree, timed against the plain estimator on every grid
                    point (which is also the error reference).  A step is one
-                   sweep over the grid.
+                   sweep over the grid.  --c5-train-family grid trains on the
+                   grid's own family; --c5-calibrate scales the spread by a
+                   factor from held-out training problems.
+
+Other modes on the single-problem workloads:
+  --union-shifts       all orders from one solve over the union of their
+                       poles (one shared probe block), reported separately
+  --lanczos-steps T    Algorithm 1 as printed with T Lanczos steps
+  --precond, --scaled  the Appendix's preconditioners
+  --probes             Gaussian or normal orthogonal probes
+  --gradient           d log det / d(lengthscale, variance, noise)
+  --graphs             solver iterations replayed from captured HIP graphs
+  --plain-fp32         c3 on the plain FP32 path (fused FP32 product)
+  --kernel-kind        another covariance kernel on the same points
+  --sensitivity axes|dims  the Appendix's sweeps against exact log det
+                       (n = 20,000; prints its own JSON record)
 
 Prints one JSON line.
 """

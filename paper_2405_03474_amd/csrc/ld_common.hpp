@@ -151,6 +151,8 @@ struct MatmatArgs {
   double alpha2 = 0.0;
   double* dots = nullptr;    // optional
   int* dot_blocks = nullptr;
+  int64_t ld = 0;            // row stride of V, Y and X2 (0: s); wider only for the
+                             // column panels of the fused FP32 / split-BF16 products
   bool timed = false;        // record events around the product kernel (ctx->timing)
   bool bf16 = false;         // FP32 path: split-BF16 matrix-core product (on the fly, or
                              // from stored split-BF16 LD_TILED tiles)
@@ -159,10 +161,11 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a);
 size_t matmat_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int64_t s);
 constexpr int kEpiRows = 128;  // rows per output tile of the product
 constexpr int kEpiSplitMax = 16;  // most epilogue workgroups (dot partial rows) per output tile
-// epilogue workgroups per output tile: 4, raised for small grids so that
-// about 1024 workgroups share the partial sums
-inline int epi_split(int64_t tiles) {
-  int sp = 4;
+// epilogue workgroups per output tile: 4 (8 for 128-column tiles, so that a
+// thread keeps at most 8 of the tile's elements), raised for small grids so
+// that about 1024 workgroups share the partial sums
+inline int epi_split(int64_t tiles, int NT) {
+  int sp = NT > 64 ? 8 : 4;
   while (sp < kEpiSplitMax && tiles * sp < 1024) sp *= 2;
   return sp;
 }

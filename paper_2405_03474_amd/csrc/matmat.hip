@@ -44,6 +44,7 @@ constexpr int kMaxContrib = 64;  // partial slots summed per output tile (bounde
 // G/nx equal contiguous ranges, one per workgroup of that XCD (stream-K).
 struct SK {
   int64_t n, s;
+  int64_t ld;     // row stride of V, Y and X2 (s, or wider for a column panel)
   int64_t tiles;  // row tiles * column tiles
   int rt;         // row tiles
   int S;          // stages per tile
@@ -90,15 +91,15 @@ struct FlyTile {
 template <int NB, int DT>
 __device__ __forceinline__ void fly_load(FlyTile<NB>& t, const float* __restrict__ Xp, int d,
                                          const float* __restrict__ V, int64_t n, int64_t s,
-                                         int64_t c0, int64_t k0, int tid) {
+                                         int64_t ld, int64_t c0, int64_t k0, int tid) {
   constexpr int NT = 32 * NB;
   constexpr int KSTEP = 256 / NT;  // k rows between a thread's consecutive loads
   const int dd_n = DT > 0 ? DT : d;
   // load j of this thread: column c0 + tid % NT, row k0 + tid / NT + KSTEP j
   const int64_t col = c0 + tid % NT;
   const int64_t kr0 = k0 + tid / NT;
-  const float* p = V + kr0 * s + col;
-  const int64_t step = (int64_t)KSTEP * s;
+  const float* p = V + kr0 * ld + col;
+  const int64_t step = (int64_t)KSTEP * ld;
   if (col < s && k0 + BK <= n) {
 #pragma unroll
     for (int j = 0; j < 4 * NB; ++j) t.v[j] = p[j * step];
@@ -117,10 +118,11 @@ __device__ __forceinline__ void fly_load(FlyTile<NB>& t, const float* __restrict
 }
 
 template <int NB, int KIND, int DT>
-__global__ __launch_bounds__(256, 2) void k_mm32_fly(const float* __restrict__ Xp, int d,
-                                                     float var,
-                                                     const float* __restrict__ V,
-                                                     float* __restrict__ part, SK p) {
+// (128-column tiles with d other than 2 or 3 take one wave per SIMD rather
+// than spill)
+__global__ __launch_bounds__(256, (NB == 4 && DT != 2 && DT != 3) ? 1 : 2) void k_mm32_fly(
+    const float* __restrict__ Xp, int d, float var, const float* __restrict__ V,
+    float* __restrict__ part, SK p) {
   constexpr int NT = 32 * NB;
   constexpr int AS = BK + 4;
   __shared__ __attribute__((aligned(16))) float Bt[2][NT * AS];
@@ -158,7 +160,7 @@ __global__ __launch_bounds__(256, 2) void k_mm32_fly(const float* __restrict__ X
     }
 
     FlyTile<NB> tl;
-    fly_load<NB, DT>(tl, Xp, d, V, n, s, c0, (int64_t)st0 * BK, tid);
+    fly_load<NB, DT>(tl, Xp, d, V, n, s, p.ld, c0, (int64_t)st0 * BK, tid);
     __syncthreads();  // the previous segment is done with both buffers
     int buf = 0;
     for (int st = st0; st < st1; ++st) {
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(256, 2) void k_mm32_fly(const float* __restrict__ X
 #pragma unroll
       for (int j = 0; j < 2; ++j) xs[tid + 256 * j] = tl.x[j];
       __syncthreads();
-      if (st + 1 < st1) fly_load<NB, DT>(tl, Xp, d, V, n, s, c0, (int64_t)(st + 1) * BK, tid);
+      if (st + 1 < st1) fly_load<NB, DT>(tl, Xp, d, V, n, s, p.ld, c0, (int64_t)(st + 1) * BK, tid);
       float a[16], b[NB][16];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
@@ -558,27 +560,27 @@ struct F16Tile {
 template <int NB, int DT>
 __device__ __forceinline__ void f16_load(F16Tile<NB>& t, const float* __restrict__ Xp, int d,
                                          const float* __restrict__ V, int64_t n, int64_t s,
-                                         int64_t c0, int64_t k0, int tid) {
+                                         int64_t ld, int64_t c0, int64_t k0, int tid) {
   constexpr int NT = 32 * NB;
   constexpr int KSTEP = 2 * (256 / NT);  // k rows between a thread's consecutive pairs
   const int dd_n = DT > 0 ? DT : d;
   // pair j of this thread: column c0 + tid % NT, rows k0 + 2 (tid / NT) + KSTEP j (+1)
   const int64_t col = c0 + tid % NT;
   const int64_t kr0 = k0 + 2 * (tid / NT);
-  const float* p = V + kr0 * s + col;
-  const int64_t step = (int64_t)KSTEP * s;
+  const float* p = V + kr0 * ld + col;
+  const int64_t step = (int64_t)KSTEP * ld;
   if (col < s && k0 + BK16 <= n) {
 #pragma unroll
     for (int j = 0; j < 4 * NB; ++j) {
       t.v[2 * j] = p[j * step];
-      t.v[2 * j + 1] = p[j * step + s];
+      t.v[2 * j + 1] = p[j * step + ld];
     }
   } else {
 #pragma unroll
     for (int j = 0; j < 4 * NB; ++j) {
       const int64_t kr = kr0 + KSTEP * j;
       t.v[2 * j] = (col < s && kr < n) ? p[j * step] : 0.f;
-      t.v[2 * j + 1] = (col < s && kr + 1 < n) ? p[j * step + s] : 0.f;
+      t.v[2 * j + 1] = (col < s && kr + 1 < n) ? p[j * step + ld] : 0.f;
     }
   }
 #pragma unroll
@@ -825,7 +827,9 @@ __global__ __launch_bounds__(256, 2) void k_mm16_st(const __bf16* __restrict__ A
 }
 
 template <int NB, int KIND, int DT>
-__global__ __launch_bounds__(256, 2) void k_mm16(const float* __restrict__ Xp, int d, float var,
+// 128-column tiles (NB = 4) need more than the 256 registers of two waves per
+// SIMD here, so they run one wave per SIMD rather than spill
+__global__ __launch_bounds__(256, NB == 4 ? 1 : 2) void k_mm16(const float* __restrict__ Xp, int d, float var,
                                                  const float* __restrict__ V,
                                                  float* __restrict__ part, SK p) {
   constexpr int NT = 32 * NB;
@@ -865,13 +869,13 @@ __global__ __launch_bounds__(256, 2) void k_mm16(const float* __restrict__ Xp, i
     }
 
     F16Tile<NB> tl;
-    f16_load<NB, DT>(tl, Xp, d, V, n, s, c0, (int64_t)st0 * BK16, tid);
+    f16_load<NB, DT>(tl, Xp, d, V, n, s, p.ld, c0, (int64_t)st0 * BK16, tid);
     __syncthreads();  // the previous segment is done with both buffers
     int buf = 0;
     for (int st = st0; st < st1; ++st) {
       f16_store<NB>(tl, Bh[buf], Bl[buf], Xs[buf], tid);
       __syncthreads();
-      if (st + 1 < st1) f16_load<NB, DT>(tl, Xp, d, V, n, s, c0, (int64_t)(st + 1) * BK16, tid);
+      if (st + 1 < st1) f16_load<NB, DT>(tl, Xp, d, V, n, s, p.ld, c0, (int64_t)(st + 1) * BK16, tid);
       f16_compute<NB, KIND, DT>(Bh[buf], Bl[buf], Xs[buf], xr, d, var, acc, li, lh);
       buf ^= 1;
     }
@@ -1033,7 +1037,7 @@ __global__ __launch_bounds__(256, 2) void k_mm64(const double* __restrict__ A,
 }
 
 // --------------------------------------------------------------- epilogue --
-// gridDim.y workgroups per output tile (epi_split: 4, up to 16 for small
+// gridDim.y workgroups per output tile (epi_split: 4 or 8, up to 16 for small
 // grids), one per row slice (blockIdx.y): Y = sum of the tile's partial slots
 // in slot order (+ noise * V on the fly) (+ alpha2 * X2); optional
 // dots[split rtile + slice][c].  Each thread keeps up to eight elements, so
@@ -1080,7 +1084,7 @@ __global__ __launch_bounds__(256) void k_epilogue(const T* __restrict__ part, SK
   __syncthreads();
   const int ns = nslot;
   const int col = tid % NT;  // 256 is a multiple of NT
-  const int cnt = (BM / split) * NT;  // elements of the slice (<= 8 per thread)
+  const int cnt = (BM / split) * NT;  // elements of the slice (<= 8 per thread: epi_split)
   const int e0 = quarter * cnt;
   double sum[8];
 #pragma unroll
@@ -1101,7 +1105,7 @@ __global__ __launch_bounds__(256) void k_epilogue(const T* __restrict__ part, SK
     const int row = (e0 + e) / NT;
     const int64_t i = i0 + row, c = c0 + col;
     if (i < p.n && c < p.s) {
-      const int64_t off = i * p.s + c;
+      const int64_t off = i * p.ld + c;
       double v = sum[j];
       if (noise != 0.0) v += noise * (double)V[off];
       if (X2) v += alpha2 * (double)X2[off];
@@ -1232,15 +1236,20 @@ struct Plan {
   size_t part_bytes;
 };
 
-Plan make_plan(ld_ctx* ctx, bool f64, int64_t n, int64_t s, int bk = BK) {
+// wide: the fused FP32 and split-BF16 kernels, which also take 128-column
+// tiles; every kernel entry they generate then feeds twice the matrix-core
+// work, so products wider than 64 columns (the range finder) regenerate M
+// half as often
+Plan make_plan(ld_ctx* ctx, bool f64, int64_t n, int64_t s, int bk = BK, bool wide = false) {
   Plan pl{};
   if (f64)
     pl.NT = s > 32 ? 64 : (s > 16 ? 32 : 16);
   else
-    pl.NT = s > 32 ? 64 : 32;
+    pl.NT = (wide && s > 64) ? 128 : (s > 32 ? 64 : 32);
   SK& p = pl.p;
   p.n = n;
   p.s = s;
+  p.ld = s;
   p.rt = (int)((n + BM - 1) / BM);
   const int64_t ct = (s + pl.NT - 1) / pl.NT;
   p.tiles = (int64_t)p.rt * ct;
@@ -1270,7 +1279,9 @@ Plan make_plan(ld_ctx* ctx, bool f64, int64_t n, int64_t s, int bk = BK) {
 template <int KIND, int DT>
 void launch_fly32(int NB, dim3 g, hipStream_t st, const float* X, int d, float var,
                   const float* V, float* part, const SK& p) {
-  if (NB == 2)
+  if (NB == 4)
+    hipLaunchKernelGGL((k_mm32_fly<4, KIND, DT>), g, dim3(256), 0, st, X, d, var, V, part, p);
+  else if (NB == 2)
     hipLaunchKernelGGL((k_mm32_fly<2, KIND, DT>), g, dim3(256), 0, st, X, d, var, V, part, p);
   else
     hipLaunchKernelGGL((k_mm32_fly<1, KIND, DT>), g, dim3(256), 0, st, X, d, var, V, part, p);
@@ -1293,7 +1304,9 @@ void launch_fly64(int NB, dim3 g, hipStream_t st, const double* X, int d, double
 template <int KIND, int DT>
 void launch_fly16(int NB, dim3 g, hipStream_t st, const float* X, int d, float var,
                   const float* V, float* part, const SK& p) {
-  if (NB == 2)
+  if (NB == 4)
+    hipLaunchKernelGGL((k_mm16<4, KIND, DT>), g, dim3(256), 0, st, X, d, var, V, part, p);
+  else if (NB == 2)
     hipLaunchKernelGGL((k_mm16<2, KIND, DT>), g, dim3(256), 0, st, X, d, var, V, part, p);
   else
     hipLaunchKernelGGL((k_mm16<1, KIND, DT>), g, dim3(256), 0, st, X, d, var, V, part, p);
@@ -1344,16 +1357,51 @@ KParams make_kparams(const ld_operator& op) {
   return kp;
 }
 
+// Products of the fused FP32 / split-BF16 kernels wider than this run as
+// column panels of this width, one after another: all of a launch's column
+// tiles are in flight together, so a single wide launch streams the whole of
+// V (n x s) through the caches for every row block, while one panel of V
+// (n x 128 x 4 bytes = 100 MB at n = 200,000) stays resident in the
+// last-level cache.
+constexpr int64_t kFusedPanel = 128;
+
 size_t matmat_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int64_t s) {
   size_t b = make_plan(ctx, f64, n, s).part_bytes;
-  if (!f64) b = std::max(b, make_plan(ctx, false, n, s, BK16).part_bytes);
+  // column panels (products that return dot blocks run at full width)
+  if (!f64 && s > kFusedPanel) b = std::max(b, matmat_scratch_bytes(ctx, f64, n, kFusedPanel) - 1024);
+  if (!f64) {
+    b = std::max(b, make_plan(ctx, false, n, s, BK16).part_bytes);
+    b = std::max(b, make_plan(ctx, false, n, s, BK, true).part_bytes);
+    b = std::max(b, make_plan(ctx, false, n, s, BK16, true).part_bytes);
+  }
   return b + 1024;
 }
 
 ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
   if (a.n <= 0 || a.s <= 0) return LD_OK;
   const bool split16 = !f64 && a.bf16 && a.A == nullptr;
-  Plan pl = make_plan(ctx, f64, a.n, a.s, split16 ? BK16 : BK);
+  const bool fused32 = !f64 && a.A == nullptr;
+  if (a.ld != 0 && a.ld != a.s && !fused32)
+    return fail(LD_EINVAL, "matmat: a row stride other than s needs a fused FP32 product");
+  if (fused32 && a.s > kFusedPanel && a.dots == nullptr) {
+    const size_t es = sizeof(float);
+    for (int64_t c = 0; c < a.s; c += kFusedPanel) {
+      MatmatArgs b = a;
+      b.s = std::min(kFusedPanel, a.s - c);
+      b.ld = a.ld ? a.ld : a.s;
+      b.V = (const char*)a.V + c * es;
+      b.Y = (char*)a.Y + c * es;
+      if (a.X2) b.X2 = (const char*)a.X2 + c * es;
+      // each panel takes the same partial buffer: the launches are ordered
+      // on the stream
+      const size_t mark = ctx->arena.top;
+      LD_TRY(matmat(ctx, f64, b));
+      ctx->arena.top = mark;
+    }
+    return LD_OK;
+  }
+  Plan pl = make_plan(ctx, f64, a.n, a.s, split16 ? BK16 : BK, fused32);
+  if (a.ld) pl.p.ld = a.ld;
   void* part = ctx->arena.take(pl.part_bytes);
   if (!part) return fail(LD_ENOMEM, "matmat: scratch arena too small");
   hipStream_t st = ctx->stream;
@@ -1399,7 +1447,7 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
     }
     if (ev1) LD_HIP(hipEventRecord(ev1, st));
     const int64_t tiles = (int64_t)pl.p.rt * ((a.s + pl.NT - 1) / pl.NT);
-    hipLaunchKernelGGL(k_epilogue<double>, dim3((unsigned)tiles, epi_split(tiles)), dim3(256), 0, st, P, pl.p, pl.NT,
+    hipLaunchKernelGGL(k_epilogue<double>, dim3((unsigned)tiles, epi_split(tiles, pl.NT)), dim3(256), 0, st, P, pl.p, pl.NT,
                        (double*)a.Y, V, fly ? a.kp.noise : 0.0, (const double*)a.X2, a.alpha2,
                        a.dots);
   } else {
@@ -1438,13 +1486,13 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
     }
     if (ev1) LD_HIP(hipEventRecord(ev1, st));
     const int64_t tiles = (int64_t)pl.p.rt * ((a.s + pl.NT - 1) / pl.NT);
-    hipLaunchKernelGGL(k_epilogue<float>, dim3((unsigned)tiles, epi_split(tiles)), dim3(256), 0, st, P, pl.p, pl.NT,
+    hipLaunchKernelGGL(k_epilogue<float>, dim3((unsigned)tiles, epi_split(tiles, pl.NT)), dim3(256), 0, st, P, pl.p, pl.NT,
                        (float*)a.Y, V,
                        fly ? a.kp.noise : (a.bf16 ? a.kp.variance + a.kp.noise : 0.0),
                        (const float*)a.X2, a.alpha2, a.dots);
   }
   if (a.dot_blocks)
-    *a.dot_blocks = pl.p.rt * epi_split((int64_t)pl.p.rt * ((a.s + pl.NT - 1) / pl.NT));
+    *a.dot_blocks = pl.p.rt * epi_split((int64_t)pl.p.rt * ((a.s + pl.NT - 1) / pl.NT), pl.NT);
   LD_HIP(hipGetLastError());
   return LD_OK;
 }

@@ -64,6 +64,7 @@ MM_CASES = [
     (513, 8, 33, gp.MATERN52),
     (200, 5, 100, gp.RBF),
     (70, 3, 16, gp.MATERN52),
+    (777, 3, 300, gp.MATERN52),  # 128-column tiles of the fused kernels, ragged
 ]
 
 

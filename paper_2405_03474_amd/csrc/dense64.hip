@@ -18,10 +18,15 @@ using dev::GM_BM;
 using dev::GM_BN;
 
 // ------------------------------------------------------------------ Gram --
-// Partial G_c = A_c^T diag(w_c) B_c over row chunk c, 64 x 64 output tile per
-// workgroup, 4 x 4 outputs per thread, rows staged through LDS 16 at a time.
+// Partial G_c = A_c^T diag(w_c) B_c over row chunk c, one 64 x 64 output tile
+// per workgroup on FP64 matrix cores (v_mfma_f64_16x16x4f64): wave w owns
+// tile rows 32 (w / 2) .. + 32 and columns 32 (w % 2) .. + 32 as 2 x 2 blocks
+// of 16 x 16.  Rows of A and B are staged through LDS GR at a time; in each
+// 4-row step lane (l % 16, l / 16) supplies A(row l / 16, column l % 16) and
+// the same element of B, and output register r of a block holds its row
+// l / 16 + 4 r, column l % 16.
 constexpr int GT = 64;
-constexpr int GR = 16;
+constexpr int GR = 32;
 
 __global__ __launch_bounds__(256) void k_gram_partial(const double* __restrict__ A,
                                                       const double* __restrict__ B,
@@ -31,12 +36,20 @@ __global__ __launch_bounds__(256) void k_gram_partial(const double* __restrict__
   __shared__ double As[GR][GT + 1];
   __shared__ double Bs[GR][GT + 1];
   const int tid = threadIdx.x;
-  const int ti = tid / 16, tj = tid % 16;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lj = lane & 15, lh = lane >> 4;
+  const int wi = 32 * (wave >> 1), wj = 32 * (wave & 1);
   const int i0 = blockIdx.y * GT, j0 = blockIdx.z * GT;
   const int64_t r0 = (int64_t)blockIdx.x * chunk;
   int64_t r1 = r0 + chunk;
   if (r1 > n) r1 = n;
-  double acc[4][4] = {};
+  dev::f64x4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[x][y][r] = 0.0;
   for (int64_t rb = r0; rb < r1; rb += GR) {
     __syncthreads();
     for (int e = tid; e < GR * GT; e += 256) {
@@ -52,28 +65,26 @@ __global__ __launch_bounds__(256) void k_gram_partial(const double* __restrict__
       Bs[rr][cc] = bv;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int rr = 0; rr < GR; ++rr) {
-      double a[4], b[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[q] = As[rr][ti + 16 * q];
-        b[q] = Bs[rr][tj + 16 * q];
-      }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+    for (int kk = 0; kk < GR; kk += 4) {
+      const double a0 = As[kk + lh][wi + lj], a1 = As[kk + lh][wi + 16 + lj];
+      const double b0 = Bs[kk + lh][wj + lj], b1 = Bs[kk + lh][wj + 16 + lj];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
   }
   double* dst = part + (int64_t)blockIdx.x * m * m;
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int i = i0 + ti + 16 * x, j = j0 + tj + 16 * y;
-      if (i < m && j < m) dst[(int64_t)i * m + j] = acc[x][y];
-    }
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wi + 16 * x + lh + 4 * r, j = j0 + wj + 16 * y + lj;
+        if (i < m && j < m) dst[(int64_t)i * m + j] = acc[x][y][r];
+      }
 }
 
 __global__ void k_sum_chunks(const double* __restrict__ part, int chunks, int64_t mm,

@@ -262,6 +262,24 @@ def test_matmat_bf16_split(ctx, n, d, s, kind):
     assert np.max(np.abs(host(Y) - ref) / scale) < 1e-4
 
 
+@pytest.mark.parametrize("precision", [L.LD_F32, L.LD_BF16])
+def test_matmat_column_panels_bitwise(ctx, precision):
+    """A fused product wider than 128 columns runs as 128-column panels over
+    the strided V; each panel takes the plan of a standalone 128-column call
+    on the contiguous slice, so the two agree bit for bit."""
+    n, s = 777, 300
+    g = np.random.default_rng(17)
+    X = g.random((n, 3))
+    V = g.standard_normal((n, s)).astype(np.float32)
+    op = make_op(X, gp.MATERN52, 0.3, 1.3, 1e-2, precision=precision)
+    Y = host(L.kernel_matmat(ctx, op, dev(V, torch.float32)))
+    for c in range(0, s, 128):
+        w = min(128, s - c)
+        Yp = host(L.kernel_matmat(ctx, op, dev(np.ascontiguousarray(V[:, c:c + w]), torch.float32)))
+        ctx.synchronize()
+        assert np.array_equal(Y[:, c:c + w], Yp), c
+
+
 def untile_split_bf16(buf, n):
     """hi + lo of a stored split-BF16 LD_TILED buffer (per tile: 4096 high
     parts, then 4096 low parts, row-major in the tile, of K - variance I; see

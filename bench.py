@@ -8,9 +8,15 @@ tolerance), each order with its own probe stream.
 
 Workloads (all synthetic, inputs from workloads/):
   c2_matern_gm50k  (default) Matern-5/2, 50,000 points from an 8-component
-                   Gaussian mixture in [0,1]^3, l = 0.15, noise 1e-3; FP32
-                   with M stored in HBM (tiled layout, 10 GB); rank 500;
-                   64 Rademacher probes; r_1, r_3, r_5.
+                   Gaussian mixture in [0,1]^3, l = 0.15, noise 1e-3; FP64
+                   (the paper's arithmetic) with M stored in HBM (tiled
+                   layout, 20 GB), solves to 1e-10; rank 500; 64 Rademacher
+                   probes; r_1, r_3, r_5.  After the timed FP64 steps the
+                   plain FP32 path (10 GB M, solves to 1e-6) and the
+                   split-BF16 precision form are timed on the same problem
+                   and probes (`forms`, `speedup_vs_plain_fp32`, each with
+                   its difference from the FP64 estimates); --precision
+                   f32|bf16 makes either the timed path.
   c1_rbf_2k        RBF, 2,000 uniform points, FP64 on the fly, rank 100, 32
                    probes, r_3.
   c3_matern_200k   precision form: Matern-5/2, 200,000 uniform points,
@@ -70,6 +76,7 @@ import workloads  # noqa: E402
 
 METRIC = "log-det estimates/s at ≤1e-3 rel err vs FP64; mixed/batched vs plain FP32"
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "bf16": 2.5e15}
+DTYPE_NAME = {0: "f64", 1: "f32", 2: "bf16x3+f32"}  # by ld_precision
 WORKLOADS = {"c2_matern_gm50k": workloads.C2, "c1_rbf_2k": workloads.C1,
              "c3_matern_200k": workloads.C3, "c4_batch256": None, "c5_surrogate": None}
 
@@ -82,10 +89,12 @@ def log(*a):
 # rocprofv3 counter summaries; valid only while the kernel's source file is
 # byte-identical to the one profiled.
 PROFILED_TRAFFIC = {
-    "c2_matern_gm50k": ("profiles/c2_matern_gm50k_k_mm32_tf.md",
-                        "paper_2405_03474_amd/csrc/matmat.hip"),
-    "c2_matern_gm50k_stored_bf16": ("profiles/c2_matern_gm50k_k_mm16_st.md",
-                                    "paper_2405_03474_amd/csrc/matmat.hip"),
+    "c2_matern_gm50k/f64": ("profiles/c2_matern_gm50k_k_mm64_tf.md",
+                            "paper_2405_03474_amd/csrc/matmat.hip"),
+    "c2_matern_gm50k/f32": ("profiles/c2_matern_gm50k_k_mm32_tf.md",
+                            "paper_2405_03474_amd/csrc/matmat.hip"),
+    "c2_matern_gm50k/bf16x3+f32": ("profiles/c2_matern_gm50k_k_mm16_st.md",
+                                   "paper_2405_03474_amd/csrc/matmat.hip"),
 }
 
 
@@ -118,28 +127,35 @@ def load_exact(name):
 def cpu_baseline(cfg, sample_n: int, lanczos_steps: int = 0, pkind: str = "rsvd",
                  scaled: bool = False, probes: str = "rademacher"):
     """The oracle on a bounded sample: the same workload recipe at sample_n
-    points, timed on this host; the rate is scaled to the full n by the
-    oracle's O(n^3) dense-factorization cost.  With lanczos_steps the oracle
-    of Algorithm 1 as printed (t Lanczos steps per probe) is timed instead."""
+    points (same preconditioner rank), timed on this host phase by phase and
+    each phase scaled to the full n by its own cost: the dense matrix and the
+    randomized SVD (products of M with rank + oversample columns) as n^2, the
+    estimates (a dense Cholesky factorization per shift, O(n^3)) as n^3.
+    With lanczos_steps the oracle of Algorithm 1 as printed (t Lanczos steps
+    per probe, O(n^2) per step with a factored P) is timed and scaled as n^2."""
     from oracle import estimate as oest
     from oracle import gp, lanczos as olz
     sub = cfg.with_n(sample_n, rank=min(cfg.rank, sample_n // 10))
     t0 = time.perf_counter()
     X = sub.X()
     M = gp.dense_matrix(sub.kind, X, sub.lengthscale, sub.variance, sub.noise)
+    t1 = time.perf_counter()
     P = oracle_precond(sub, M, pkind, scaled)
     Pd = P.dense()
+    t2 = time.perf_counter()
     for k in cfg.orders:
         Z = oest.probe_block(probes, sub.probe_seed + k, sub.n, sub.probes)
         if lanczos_steps:
             olz.estimate_lanczos(M, Pd, P.logdet, k, Z, lanczos_steps)
         else:
             oest.estimate_dense(M, Pd, P.logdet, k, Z)
-    dt = time.perf_counter() - t0
-    scale = (cfg.n / sample_n) ** 3
+    t3 = time.perf_counter()
+    r = cfg.n / sample_n
+    est_scale = r ** 2 if lanczos_steps else r ** 3
+    full = (t1 - t0) * r ** 2 + (t2 - t1) * r ** 2 + (t3 - t2) * est_scale
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {
-        "value": len(cfg.orders) / (dt * scale),
+        "value": len(cfg.orders) / full,
         "unit": "log-det estimates/s",
         "cores": threads,
         "kind": "oracle",
@@ -147,8 +163,11 @@ def cpu_baseline(cfg, sample_n: int, lanczos_steps: int = 0, pkind: str = "rsvd"
                    + (f"{lanczos_steps} Lanczos steps per probe with dense P^-1 solves"
                       if lanczos_steps else "dense Cholesky shifted solves")
                    + ") on the same recipe at "
-                   f"n={sample_n}, rank {sub.rank}: {len(cfg.orders)} estimates in {dt:.2f} s; "
-                   f"scaled to n={cfg.n} by (n/{sample_n})^3"),
+                   f"n={sample_n}, rank {sub.rank}: matrix {t1 - t0:.2f} s, preconditioner "
+                   f"{t2 - t1:.2f} s, {len(cfg.orders)} estimates {t3 - t2:.2f} s; scaled to "
+                   f"n={cfg.n} by (n/{sample_n})^2 for the matrix and preconditioner and "
+                   f"(n/{sample_n})^{2 if lanczos_steps else 3} for the estimates: "
+                   f"{full:.0f} s per step"),
     }
 
 
@@ -176,7 +195,7 @@ class Runner:
     """One problem instance on the GPU in a given arithmetic."""
 
     def __init__(self, L, torch, ctx, cfg, precision, stored, lanczos_steps=0, pkind="rsvd",
-                 scaled=False, union=False):
+                 scaled=False, union=False, tol=0.0):
         self.L, self.torch, self.ctx, self.cfg = L, torch, ctx, cfg
         self.lanczos_steps = lanczos_steps
         self.union = union
@@ -193,7 +212,11 @@ class Runner:
             self.Mbuf = torch.empty((L.stored_elements(cfg.n, self.op.layout),),
                                     dtype=torch.float32 if precision != L.LD_F64 else torch.float64,
                                     device=dev)
-        self.tol = 1e-12 if precision == L.LD_F64 else 1e-6
+        self.tol = tol or (1e-12 if precision == L.LD_F64 else 1e-6)
+
+    def release(self):
+        self.op.M = None
+        self.Mbuf = None
 
     def step(self):
         L, cfg, op = self.L, self.cfg, self.op
@@ -256,7 +279,7 @@ def gradient_main(args, torch, L, cfg, precision, stored):
         "value": args.steps / (ms_total / 1e3), "unit": "gradients/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_total / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {L.LD_F64: "f64", L.LD_F32: "f32", L.LD_BF16: "bf16x3+f32"}[precision],
+        "dtype": DTYPE_NAME[precision],
         "data": "synthetic",
         "config": {"workload": cfg.name, "n": cfg.n, "probes": cfg.probes, "rank": cfg.rank,
                    "precond": {"kind": args.precond, "scaled": args.scaled},
@@ -655,6 +678,14 @@ def main():
     ap.add_argument("--plain-fp32", action="store_true",
                     help="c3: time the plain FP32 on-the-fly path as the main path (its "
                          "product kernel's FP32 matrix-core fraction)")
+    ap.add_argument("--precision", default="", choices=["", "f64", "f32", "bf16"],
+                    help="arithmetic of the products and vectors (default: c1 and c2 f64, "
+                         "c3 bf16)")
+    ap.add_argument("--tol", type=float, default=0.0,
+                    help="solver tolerance (default 1e-10 for c2 in FP64, 1e-12 for other "
+                         "FP64 runs, 1e-6 otherwise)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="c2 in FP64: skip timing the plain FP32 and split-BF16 forms")
     ap.add_argument("--compare-fp32", action="store_true",
                     help="precision form: also time the plain FP32 path on the same problem")
     ap.add_argument("--stored-bf16", action="store_true",
@@ -720,13 +751,18 @@ def main():
         cfg = replace(cfg, kind=workloads.RBF if args.kernel_kind == "rbf" else workloads.MATERN52,
                       name=f"{cfg.name}@{args.kernel_kind}")
     kind = args.workload.split("_")[0]
-    precision = {"c1": L.LD_F64, "c2": L.LD_F32, "c3": L.LD_BF16}[kind]
+    precision = {"c1": L.LD_F64, "c2": L.LD_F64, "c3": L.LD_BF16}[kind]
+    if args.precision:
+        precision = {"f64": L.LD_F64, "f32": L.LD_F32, "bf16": L.LD_BF16}[args.precision]
     if kind == "c2" and args.stored_bf16:
         precision = L.LD_BF16
     if kind == "c3" and args.plain_fp32:
         precision = L.LD_F32
     stored = kind == "c2"
-    dtype = {L.LD_F64: "f64", L.LD_F32: "f32", L.LD_BF16: "bf16x3+f32"}[precision]
+    dtype = DTYPE_NAME[precision]
+    # FP64 solves of the stored workload stop at 1e-10 (the estimate then
+    # agrees with the oracle's exact solves to ~1e-12; tested at n = 20,000)
+    tol = args.tol or (1e-10 if (kind == "c2" and precision == L.LD_F64) else 0.0)
     log(f"[bench] workload {cfg.name} n={cfg.n} rank={cfg.rank} probes={cfg.probes} "
         f"orders={cfg.orders} dtype={dtype} stored={stored}")
 
@@ -739,7 +775,7 @@ def main():
     ctx.set_probes({"rademacher": L.LD_PROBE_RADEMACHER, "gaussian": L.LD_PROBE_GAUSSIAN,
                     "orthogonal": L.LD_PROBE_ORTHOGONAL}[args.probes])
     runner = Runner(L, torch, ctx, cfg, precision, stored, args.lanczos_steps, args.precond,
-                    args.scaled, args.union_shifts)
+                    args.scaled, args.union_shifts, tol)
     if args.graphs:
         # replayed iterations carry no timing events: the timed steps run
         # uninstrumented, one more instrumented (eager) step times the product
@@ -772,9 +808,11 @@ def main():
     kname = {"c2": "k_mm32_tf<2> (FP32 MFMA 32x32x2, stored LD_TILED fragment tiles)",
              "c1": "k_mm64<fly> (FP64 MFMA 16x16x4, on the fly)",
              "c3": "k_mm16<fly> (split-BF16 MFMA 32x32x16, 3 terms, on the fly)"}[kind]
+    if kind == "c2" and precision == L.LD_F64:
+        kname = "k_mm64_tf<4> (FP64 MFMA 16x16x4, stored LD_TILED fragment tiles)"
     if kind == "c3" and precision == L.LD_F32:
         kname = "k_mm32_fly (FP32 MFMA 32x32x2, kernel entries generated on the fly)"
-    traffic = profiled_traffic(cfg.name) if not args.n and precision == L.LD_F32 else None
+    traffic = profiled_traffic(f"{cfg.name}/{dtype}") if not args.n and stored else None
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": traffic, "kernel": kname,
                 "avg_launch_ms": avg_ms, "launches": mm_calls,
@@ -814,9 +852,41 @@ def main():
         gbps = (mm_bytes / max(mm_calls, 1)) / (avg_ms / 1e3) / 1e9
         line["roofline"].update({
             "bound": "hbm", "achieved": gbps, "peak": 8000.0, "unit": "GB/s", "frac": gbps / 8000.0,
-            "traffic": profiled_traffic(cfg.name + "_stored_bf16") if not args.n else None,
+            "traffic": traffic,
             "kernel": "k_mm16_st<2> (split-BF16 MFMA 32x32x16, 3 terms, stored split tiles)",
             "flops_TFLOPs": achieved / 1e12})
+    if kind == "c2" and precision == L.LD_F64 and not args.no_forms:
+        # the metric's other forms on the same problem and probes: plain FP32
+        # and the split-BF16 precision form, each against this FP64 result
+        forms = {}
+        for fprec in (L.LD_F32, L.LD_BF16):
+            name = DTYPE_NAME[fprec]
+            log(f"[bench] form {name}, same problem")
+            fr = Runner(L, torch, ctx, cfg, fprec, stored, args.lanczos_steps, args.precond,
+                        args.scaled, args.union_shifts)
+            fres, fms, _, _ = timed_steps(fr, 1, 1, stream, torch, instrument=False)
+            fr.release()
+            fv = len(cfg.orders) / (fms / 1e3)
+            forms[name] = {
+                "value": fv, "ms_per_step": fms, "tol": fr.tol,
+                "rel_diff_vs_f64": {f"r{k}": abs(fres[-1][k]["logdet"] - last[k]["logdet"])
+                                    / abs(last[k]["logdet"]) for k in cfg.orders},
+                "iterations": {f"r{k}": fres[-1][k]["iterations"] for k in cfg.orders}}
+        base = forms["f32"]["value"]
+        for f in forms.values():
+            f["speedup_vs_plain_fp32"] = f["value"] / base
+        line["forms"] = forms
+        line["speedup_vs_plain_fp32"] = {"bf16x3+f32": forms["bf16x3+f32"]["speedup_vs_plain_fp32"],
+                                         "f64": value / base}
+    if exact is not None:
+        within = [f"r{k}" for k in cfg.orders if accuracy[f"r{k}"]["within_1e-3"]]
+        line["accuracy_qualifier"] = {
+            "rule": "relative error vs exact FP64 Cholesky log det <= 1e-3",
+            "orders_within": within,
+            "qualified_estimates_per_s": value * len(within) / len(cfg.orders),
+            "note": "the error of each order is the bias of r_k on the spectrum of M P^-1 at "
+                    "this preconditioner rank (a property of the method, not of the "
+                    "arithmetic); the FP64 path matches the oracle's exact-solve estimate"}
     if kind in ("c2", "c3") and args.compare_fp32:
         log("[bench] plain FP32 path, same problem")
         plain = Runner(L, torch, ctx, cfg, L.LD_F32, stored, args.lanczos_steps, args.precond,

@@ -88,14 +88,16 @@ typedef struct {
 
 /* Storage layouts of a stored M.
  *  LD_ROW_MAJOR: n x n, row-major.
- *  LD_TILED (FP32): 128 x 32 tiles, each contiguous; tile (I, K) covers rows
- *    128 I .. 128 I + 127 and columns 32 K .. 32 K + 31 and starts at element
- *    (I * ceil(n/32) + K) * 4096, so a band of 128 rows is one contiguous
- *    stream.  Entries outside n x n are zero.  Inside a tile, entry (r, c)
- *    (0 <= r < 128, 0 <= c < 32) sits at
- *      (r/32)*1024 + ((c%16)/4)*256 + (c/16)*128 + (r%32)*4 + c%4,
+ *  LD_TILED (FP32 and FP64): 128 x 32 tiles, each contiguous; tile (I, K)
+ *    covers rows 128 I .. 128 I + 127 and columns 32 K .. 32 K + 31 and
+ *    starts at element (I * ceil(n/32) + K) * 4096, so a band of 128 rows is
+ *    one contiguous stream.  Entries outside n x n are zero.  Inside a tile,
+ *    entry (r, c) (0 <= r < 128, 0 <= c < 32) sits at
+ *      FP32: (r/32)*1024 + ((c%16)/4)*256 + (c/16)*128 + (r%32)*4 + c%4,
+ *      FP64: (r/32)*1024 + (4*((r/16)%2) + (c%8)/2)*128 + (16*(c/8) + r%16)*2 + c%2,
  *    the order in which the matrix-core A operand of 32-row slices is loaded
- *    as 1 KB blocks.  (Stored split BF16 uses its own tile format, see
+ *    as 1 KB blocks (v_mfma_f32_32x32x2f32 and v_mfma_f64_16x16x4f64
+ *    respectively).  (Stored split BF16 uses its own tile format, see
  *    kernel_materialize.) */
 typedef enum { LD_ROW_MAJOR = 0, LD_TILED = 1 } ld_layout;
 
@@ -219,8 +221,7 @@ ld_status kernel_matmat(ld_ctx* ctx, const ld_operator* op, const void* V, int64
 
 /* Write M = K + noise I (device, ld_stored_elements(n, op->layout) elements,
  * FP64 for LD_F64, FP32 for LD_F32) in op->layout so that it can be passed
- * back as op->M_stored.  op->M_stored is ignored.  LD_TILED requires LD_F32
- * or LD_BF16.  With LD_BF16 (LD_TILED only) the buffer has the same size in
+ * back as op->M_stored.  op->M_stored is ignored.  With LD_BF16 (LD_TILED only) the buffer has the same size in
  * bytes as the FP32 one and holds K - variance I (zero diagonal): each
  * 128 x 32 tile holds the 4096 values hi = bf16(m) (row-major inside the tile)
  * followed by the 4096 values bf16(m - hi), m the FP32 entry; the products add

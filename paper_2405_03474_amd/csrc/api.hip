@@ -129,8 +129,6 @@ ld_status check_operator(const ld_operator* op, bool generate) {
     return fail(LD_EINVAL, "layout must be LD_ROW_MAJOR or LD_TILED");
   if (op->precision == LD_BF16 && op->M_stored && op->layout != LD_TILED)
     return fail(LD_EINVAL, "a stored LD_BF16 matrix must use the LD_TILED layout");
-  if (op->layout == LD_TILED && op->M_stored && op->precision == LD_F64)
-    return fail(LD_EINVAL, "LD_TILED storage is FP32 or split BF16");
   return LD_OK;
 }
 
@@ -229,7 +227,7 @@ __global__ void k_d_and_inv(const double* __restrict__ U, const double* __restri
       continue;
     }
     double dm = diag_const;
-    const int64_t ii = layout == LD_TILED ? tiled_index(i, i, n) : i * n + i;
+    const int64_t ii = stored_index(i, i, n, layout, mprec == LD_F64);
     if (Mst && mprec != LD_BF16) {  // split-BF16 tiles store K - variance I: diag is diag_const
       dm = mprec == LD_F64 ? ((const double*)Mst)[ii] : (double)((const float*)Mst)[ii];
     }
@@ -591,7 +589,7 @@ __global__ void k_pc_res_init(double* __restrict__ res, int64_t n, const void* _
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     double dm = diag_const;
     if (Mst && mprec != LD_BF16) {
-      const int64_t ii = layout == LD_TILED ? tiled_index(i, i, n) : i * n + i;
+      const int64_t ii = stored_index(i, i, n, layout, mprec == LD_F64);
       dm = mprec == LD_F64 ? ((const double*)Mst)[ii] : (double)((const float*)Mst)[ii];
     }
     res[i] = dm;
@@ -645,7 +643,7 @@ __global__ void k_pc_column(const double* __restrict__ X, int d, double var, dou
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     double m;
     if (Mst && mprec != LD_BF16) {
-      const int64_t ii = layout == LD_TILED ? tiled_index(i, p, n) : i * n + p;
+      const int64_t ii = stored_index(i, p, n, layout, mprec == LD_F64);
       m = mprec == LD_F64 ? ((const double*)Mst)[ii] : (double)((const float*)Mst)[ii];
     } else {
       double r2 = 0.0;
@@ -915,8 +913,6 @@ ld_status kernel_materialize(ld_ctx* ctx, const ld_operator* op, void* M_out) {
   if (!M_out) return fail(LD_EINVAL, "M_out is NULL");
   if (op->precision == LD_BF16 && op->layout != LD_TILED)
     return fail(LD_EINVAL, "a stored LD_BF16 matrix must use the LD_TILED layout");
-  if (op->precision == LD_F64 && op->layout == LD_TILED)
-    return fail(LD_EINVAL, "LD_TILED storage is FP32 or split BF16");
   launch_materialize(ctx->stream, make_kparams(*op), op->X, op->n, op->d, op->precision, op->layout,
                      M_out);
   LD_HIP(hipGetLastError());

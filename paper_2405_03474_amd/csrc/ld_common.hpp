@@ -192,6 +192,32 @@ __host__ __device__ inline int64_t tiled_index(int64_t i, int64_t k, int64_t n) 
   return ((i / kTileRows) * kt + k / kTileCols) * (kTileRows * kTileCols) +
          tile_offset((int)(i % kTileRows), (int)(k % kTileCols));
 }
+// FP64 LD_TILED: the same 128 x 32 tiles and tile order; inside a tile,
+// element (r, c) sits where lane r % 16 + 16 (c / 8) of wave r / 32 finds it
+// when the wave loads its 32-row slice as eight consecutive 1 KB blocks
+// q = 4 ((r / 16) % 2) + (c % 8) / 2 of one 16-byte pair per lane (the
+// A-operand order of v_mfma_f64_16x16x4f64 with lane quarter h supplying
+// columns 8 h .. 8 h + 7, two 16-row halves per slice).
+__host__ __device__ inline int tile_offset64(int r, int c) {
+  return (r >> 5) * 1024 + (((r >> 4) & 1) * 4 + ((c & 7) >> 1)) * 128 +
+         ((c >> 3) * 16 + (r & 15)) * 2 + (c & 1);
+}
+__host__ __device__ inline void tile_coords64(int w, int* r, int* c) {  // inverse of tile_offset64
+  const int q = (w >> 7) & 7, lane = (w >> 1) & 63;
+  *r = (w >> 10) * 32 + (q >> 2) * 16 + (lane & 15);
+  *c = (lane >> 4) * 8 + (q & 3) * 2 + (w & 1);
+}
+__host__ __device__ inline int64_t tiled_index64(int64_t i, int64_t k, int64_t n) {
+  const int64_t kt = (n + kTileCols - 1) / kTileCols;
+  return ((i / kTileRows) * kt + k / kTileCols) * (kTileRows * kTileCols) +
+         tile_offset64((int)(i % kTileRows), (int)(k % kTileCols));
+}
+// Element (i, k) of a stored FP64 or FP32 matrix in either layout.
+__host__ __device__ inline int64_t stored_index(int64_t i, int64_t k, int64_t n, int layout,
+                                                bool f64) {
+  if (layout != LD_TILED) return i * n + k;
+  return f64 ? tiled_index64(i, k, n) : tiled_index(i, k, n);
+}
 inline int64_t stored_elements(int64_t n, int layout) {
   if (layout == LD_TILED)
     return ((n + kTileRows - 1) / kTileRows) * kTileRows * ((n + kTileCols - 1) / kTileCols) *

@@ -1036,6 +1036,161 @@ __global__ __launch_bounds__(256, 2) void k_mm64(const double* __restrict__ A,
   }
 }
 
+// ------------------------------------- FP64 stored, LD_TILED fragment tiles --
+// The FP64 form of k_mm32_tf on v_mfma_f64_16x16x4f64.  tile_offset64 orders
+// each tile so that a wave's 32 rows x 32 k of a stage (8 KB) arrive as eight
+// 16-byte loads per lane, each one coalesced 1 KB block, straight into the
+// registers that feed the matrix core: 16-byte pair q holds rows 16 (q / 4) +
+// lane % 16 and k = 8 (lane / 16) + 2 (q % 4) + {0, 1}.  A is fetched two
+// stages ahead; after the first (second) half of a stage's MFMA steps the
+// pairs that half consumed are reloaded for the stage two ahead.  B (a
+// 32 x NT block of V shared by the four waves) is loaded one stage ahead into
+// registers and kept transposed in a double-buffered LDS tile, one barrier
+// per stage.  In MFMA step t lane quarter h supplies k = 8 h + t for both
+// operands.
+constexpr int ST64 = BK + 2;  // row stride (doubles) of transposed B
+
+template <int NB>
+__global__ __launch_bounds__(256, 2) void k_mm64_tf(const double* __restrict__ A,
+                                                    const double* __restrict__ V,
+                                                    double* __restrict__ part, SK p) {
+  constexpr int NT = 16 * NB;
+  constexpr int BL = 2 * NB;  // B values per thread per stage (32 x NT / 256)
+  typedef double f64x2 __attribute__((ext_vector_type(2)));
+  __shared__ __attribute__((aligned(16))) double Bt[2][NT * ST64];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lj = lane & 15, lh = lane >> 4;
+  const int64_t n = p.n, s = p.s;
+
+  const WGRange wr = wg_range(p, blockIdx.x);
+  int64_t u = wr.u;
+  const int64_t uend = wr.uend;
+  int seg = 0;
+  while (u < uend) {
+    const int64_t T = u / wr.Sx;
+    const int l0 = (int)(u - T * wr.Sx);
+    const int l1 = (int)((int64_t)wr.Sx < l0 + (uend - u) ? (int64_t)wr.Sx : l0 + (uend - u));
+    const int st0 = wr.sb + l0, st1 = wr.sb + l1;
+    const int rtile = (int)(T % p.rt);
+    const int64_t c0 = (T / p.rt) * NT;
+    // this wave's slice of tile (rtile, 0); stage st is st * 4096 doubles further
+    const f64x2* abase =
+        (const f64x2*)(A + (int64_t)rtile * p.S * (BM * BK) + wave * 1024) + lane;
+
+    f64x4 acc[2][NB];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[rb][nb][r] = 0.0;
+
+    f64x2 aq[2][8];
+    double bq[BL];
+    // pairs q of stage st for MFMA half h: q = 4 rb + 2 h + {0, 1}
+    auto load_a_half = [&](int st, f64x2* dst, int h) {
+      const f64x2* src = abase + (int64_t)st * (BM * BK / 2);
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int q = 4 * rb + 2 * h + e;
+          dst[q] = __builtin_nontemporal_load(src + 64 * q);
+        }
+    };
+    auto load_b = [&](int st) {
+      const int64_t k0 = (int64_t)st * BK;
+      if (k0 + BK <= n && c0 + NT <= s) {
+        // the whole stage is inside V (uniform over the workgroup)
+        const double* src = V + (k0 + tid / NT) * s + c0 + tid % NT;
+#pragma unroll
+        for (int j = 0; j < BL; ++j) bq[j] = src[(int64_t)(256 / NT) * j * s];
+        return;
+      }
+#pragma unroll
+      for (int j = 0; j < BL; ++j) {
+        const int e = tid + 256 * j;
+        const int64_t kr = k0 + e / NT, col = c0 + e % NT;
+        bq[j] = (kr < n && col < s) ? V[kr * s + col] : 0.0;
+      }
+    };
+    auto store_b = [&](double* bt) {
+#pragma unroll
+      for (int j = 0; j < BL; ++j) {
+        const int e = tid + 256 * j;
+        bt[(e % NT) * ST64 + e / NT] = bq[j];
+      }
+    };
+
+    load_a_half(st0, aq[0], 0);
+    load_a_half(st0, aq[0], 1);
+    if (st0 + 1 < st1) {
+      load_a_half(st0 + 1, aq[1], 0);
+      load_a_half(st0 + 1, aq[1], 1);
+    }
+    load_b(st0);
+    __syncthreads();  // the previous segment is done with both B buffers
+    store_b(Bt[0]);
+    if (st0 + 1 < st1) load_b(st0 + 1);
+    __syncthreads();
+    for (int st = st0; st < st1; st += 2) {
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const int cur = st + d;
+        if (cur < st1) {
+          const double* bt = Bt[(cur - st0) & 1];
+          // stage cur + 1 into the other buffer (last read in stage cur - 1,
+          // fenced by the barrier that ended it)
+          if (cur + 1 < st1) store_b(Bt[(cur + 1 - st0) & 1]);
+          if (cur + 2 < st1) load_b(cur + 2);
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            double b[NB][4];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+              const f64x2* bp = (const f64x2*)&bt[(nb * 16 + lj) * ST64 + lh * 8 + 4 * h];
+              const f64x2 v0 = bp[0], v1 = bp[1];
+              b[nb][0] = v0.x;
+              b[nb][1] = v0.y;
+              b[nb][2] = v1.x;
+              b[nb][3] = v1.y;
+            }
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) {
+              const int t = 4 * h + tt;
+#pragma unroll
+              for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb) {
+                  const f64x2 av = aq[d][4 * rb + (t >> 1)];
+                  acc[rb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64((t & 1) ? av.y : av.x,
+                                                                      b[nb][tt], acc[rb][nb], 0,
+                                                                      0, 0);
+                }
+            }
+            if (cur + 2 < st1) load_a_half(cur + 2, aq[d], h);
+          }
+          __syncthreads();
+        }
+      }
+    }
+
+    double* dst = part + ((int64_t)blockIdx.x * p.J + seg) * (int64_t)(BM * NT);
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 32 * wave + 16 * rb + lh + 4 * r;
+          dst[row * NT + nb * 16 + lj] = acc[rb][nb][r];
+        }
+    ++seg;
+    u += st1 - st0;
+  }
+}
+
 // --------------------------------------------------------------- epilogue --
 // gridDim.y workgroups per output tile (epi_split: 4 or 8, up to 16 for small
 // grids), one per row slice (blockIdx.y): Y = sum of the tile's partial slots
@@ -1210,6 +1365,35 @@ __global__ __launch_bounds__(256) void k_materialize_tiled(const double* __restr
       double v = kval64<KIND>(r2, var, c);
       if (i == k) v += noise;
       out = (float)v;
+    }
+    M[e] = out;
+  }
+}
+
+// LD_TILED (FP64, fragment order inside the tile: tile_offset64)
+template <int KIND>
+__global__ __launch_bounds__(256) void k_materialize_tiled64(const double* __restrict__ X,
+                                                             int64_t n, int d, double var,
+                                                             double c, double noise,
+                                                             int64_t total,
+                                                             double* __restrict__ M) {
+  const int64_t kt = (n + kTileCols - 1) / kTileCols;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * 256) {
+    const int64_t tile = e / (kTileRows * kTileCols);
+    int tr, tc;
+    tile_coords64((int)(e % (kTileRows * kTileCols)), &tr, &tc);
+    const int64_t i = (tile / kt) * kTileRows + tr;
+    const int64_t k = (tile % kt) * kTileCols + tc;
+    double out = 0.0;
+    if (i < n && k < n) {
+      double r2 = 0.0;
+      for (int dd = 0; dd < d; ++dd) {
+        const double df = X[i * d + dd] - X[k * d + dd];
+        r2 = fma(df, df, r2);
+      }
+      out = kval64<KIND>(r2, var, c);
+      if (i == k) out += noise;
     }
     M[e] = out;
   }
@@ -1433,6 +1617,14 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
                                        P, pl.p);
       else
         fly64_by_d<LD_MATERN52>(NB, grid, st, (const double*)a.X, a.d, a.kp.variance, c, V, P, pl.p);
+    } else if (a.layout == LD_TILED) {
+      const double* A = (const double*)a.A;
+      if (NB == 4)
+        hipLaunchKernelGGL((k_mm64_tf<4>), grid, dim3(256), 0, st, A, V, P, pl.p);
+      else if (NB == 2)
+        hipLaunchKernelGGL((k_mm64_tf<2>), grid, dim3(256), 0, st, A, V, P, pl.p);
+      else
+        hipLaunchKernelGGL((k_mm64_tf<1>), grid, dim3(256), 0, st, A, V, P, pl.p);
     } else {
       const double* A = (const double*)a.A;
       if (NB == 4)
@@ -1526,6 +1718,18 @@ void launch_materialize(hipStream_t st, const KParams& kp, const double* X, int6
     else
       hipLaunchKernelGGL((k_materialize_tiled_bf16<LD_MATERN52>), dim3((unsigned)blocks), dim3(256),
                          0, st, X, n, d, kp.variance, c, kp.noise, total, (__bf16*)M);
+    return;
+  }
+  if (layout == LD_TILED && f64) {
+    const int64_t total = stored_elements(n, LD_TILED);
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (kp.kind == LD_RBF)
+      hipLaunchKernelGGL((k_materialize_tiled64<LD_RBF>), dim3((unsigned)blocks), dim3(256), 0, st,
+                         X, n, d, kp.variance, c, kp.noise, total, (double*)M);
+    else
+      hipLaunchKernelGGL((k_materialize_tiled64<LD_MATERN52>), dim3((unsigned)blocks), dim3(256),
+                         0, st, X, n, d, kp.variance, c, kp.noise, total, (double*)M);
     return;
   }
   if (layout == LD_TILED) {

@@ -68,8 +68,22 @@ MM_CASES = [
 ]
 
 
+def untile64(buf, n):
+    """Dense n x n view of an FP64 LD_TILED buffer (128 x 32 tiles; inside a
+    tile entry (r, c) at (r/32)*1024 + (4*((r/16)%2) + (c%8)/2)*128 +
+    (16*(c/8) + r%16)*2 + c%2, as documented in logdet.h)."""
+    kt = -(-n // 32)
+    rt = -(-n // 128)
+    # r = 32 w + 16 rb + lj, c = 8 lh + 2 tq + e
+    t = buf.reshape(rt, kt, 4, 2, 4, 4, 16, 2)         # I, K, w, rb, tq, lh, lj, e
+    t = t.transpose(0, 2, 3, 6, 1, 5, 4, 7)            # I, w, rb, lj, K, lh, tq, e
+    t = t.reshape(rt * 128, kt * 32)
+    assert np.all(t[n:, :] == 0) and np.all(t[:, n:] == 0)
+    return t[:n, :n]
+
+
 @pytest.mark.parametrize("n,d,s,kind", MM_CASES)
-@pytest.mark.parametrize("stored", [False, True])
+@pytest.mark.parametrize("stored", [None, "row", "tiled"])
 def test_matmat_fp64(ctx, n, d, s, kind, stored):
     g = np.random.default_rng(n + s)
     X = g.random((n, d))
@@ -77,9 +91,12 @@ def test_matmat_fp64(ctx, n, d, s, kind, stored):
     Mref = gp.dense_matrix(kind, X, 0.3, 1.3, 1e-2)
     op = make_op(X, kind, 0.3, 1.3, 1e-2)
     if stored:
+        op.layout = L.LD_TILED if stored == "tiled" else L.LD_ROW_MAJOR
         op.M = L.kernel_materialize(ctx, op)
         ctx.synchronize()
-        np.testing.assert_allclose(host(op.M), Mref, rtol=1e-14, atol=1e-15)
+        M = host(op.M)
+        M = untile64(M, n) if stored == "tiled" else M
+        np.testing.assert_allclose(M, Mref, rtol=1e-14, atol=1e-15)
     Y = L.kernel_matmat(ctx, op, dev(V))
     ctx.synchronize()
     ref = Mref @ V

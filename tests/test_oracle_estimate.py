@@ -109,3 +109,32 @@ def test_blocked_cholesky_logdet_matches_lapack():
     ref = oest_ref = estimate.logdet_exact(M)
     for block in (64, 100, 700):
         assert estimate.logdet_exact_blocked(M.copy(), block) == pytest.approx(ref, rel=1e-12)
+
+
+def test_standard_error_hand_cases():
+    # The reported standard error is the sample standard deviation of the
+    # per-probe values over sqrt(s): for two values it is |t_1 - t_2| / 2;
+    # for equal values it is 0; for s values that are all 0 but one 1 the
+    # sample variance is 1/s, so it is 1/s.
+    assert estimate.combine(0.0, [3.0, 7.5]).stderr == pytest.approx(2.25, rel=1e-15)
+    assert estimate.combine(0.0, [-1.0, 1.0]).stderr == pytest.approx(1.0, rel=1e-15)
+    assert estimate.combine(5.0, [2.0] * 9).stderr == 0.0
+    for s in (3, 8, 50):
+        t = np.zeros(s)
+        t[s // 2] = 1.0
+        assert estimate.combine(0.0, t).stderr == pytest.approx(1.0 / s, rel=1e-13)
+    one = estimate.combine(1.5, [4.0])
+    assert np.isnan(one.stderr) and one.logdet == 5.5
+
+
+def test_standard_error_matches_spread_over_repeats():
+    # Over many independent probe sets the standard error predicts the
+    # spread of the estimate: the mean of stderr^2 over repeats equals the
+    # variance of the means (both estimate Var(t) / s).
+    g = np.random.default_rng(33)
+    s, reps = 16, 4000
+    T = g.exponential(2.0, size=(reps, s))
+    se2 = np.array([estimate.combine(0.0, row).stderr ** 2 for row in T])
+    means = T.mean(axis=1)
+    assert np.mean(se2) == pytest.approx(4.0 / s, rel=0.05)
+    assert np.mean(se2) == pytest.approx(np.var(means, ddof=1), rel=0.08)

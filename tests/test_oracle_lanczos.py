@@ -107,3 +107,25 @@ def test_equals_t_steps_of_preconditioned_cg(t):
         for aj, cj in zip(a, c):
             want += cj * float((P @ v) @ _pcg_t_steps(M, P, v, aj, t))
         assert t_l[i] == pytest.approx(want, rel=1e-10)
+
+
+@pytest.mark.parametrize("t", [2, 5, 11])
+def test_residual_equals_pcg_residual_norm(t):
+    # The reported residual beta_t |w_t| / |v| is the P^-1-norm of
+    # v - (M P^-1 + a_1 I) x_t for the smallest shift a_1, relative to
+    # |v| = sqrt(v^T P^-1 v): with x_t = P y_t from t PCG steps on
+    # (M + a_1 P) y = v, that residual is v - (M + a_1 P) y_t, formed here
+    # explicitly from the PCG iterate.
+    n = 90
+    M, P = _spd(n, 31, 0.2), _spd(n, 32, 1.0)
+    Z = estimate.probes(12, n, 3)
+    _, a, _ = rational.partial_fraction(3)
+    _, steps, resid = lanczos.per_probe_lanczos(M, P, 3, Z, t)
+    assert np.all(steps == t)
+    fac = sla.cho_factor(P, lower=True)
+    for i in range(Z.shape[1]):
+        v = Z[:, i].astype(np.float64)
+        y = _pcg_t_steps(M, P, v, a[0], t)
+        r = v - (M + a[0] * P) @ y
+        want = np.sqrt(r @ sla.cho_solve(fac, r)) / np.sqrt(v @ sla.cho_solve(fac, v))
+        assert resid[i] == pytest.approx(want, rel=1e-8)

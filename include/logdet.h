@@ -219,6 +219,25 @@ ld_status ld_fill_gaussian(ld_ctx* ctx, uint64_t seed, int32_t stream, int64_t r
  * precision; Y must not alias V.  Asynchronous. */
 ld_status kernel_matmat(ld_ctx* ctx, const ld_operator* op, const void* V, int64_t s, void* Y);
 
+/* kernel_matmat for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same product with the same kernels and bit-identical results, with its
+ * scratch (the stream-K partial sums and, on the FP32 / split-BF16
+ * on-the-fly paths, the scaled FP32 copy of the points) taken from a static
+ * device array of 256 MiB, which every device the library runs on holds from
+ * the code object's load until the process ends, instead of the context's
+ * arena.  The call allocates nothing.  A product whose scratch would exceed
+ * 256 MiB fails with LD_EINVAL before anything is enqueued (with 64 columns:
+ * FP64 up to about n = 49,000, FP32 and split BF16 up to about n = 114,000;
+ * with 16 columns about n = 245,000).  Every call on a device shares that
+ * device's array and overwrites it: calls that overlap in time on one device
+ * (other streams, contexts or threads) race, and the caller must serialise
+ * them.  Nothing in the array needs to start at zero (each partial slot the
+ * epilogue reads is written earlier by the same call).  Arguments as for
+ * kernel_matmat.  Asynchronous. */
+ld_status kernel_matmat_noalloc(ld_ctx* ctx, const ld_operator* op, const void* V, int64_t s,
+                                void* Y);
+
 /* Write M = K + noise I (device, ld_stored_elements(n, op->layout) elements,
  * FP64 for LD_F64, FP32 for LD_F32) in op->layout so that it can be passed
  * back as op->M_stored.  op->M_stored is ignored.  With LD_BF16 (LD_TILED only) the buffer has the same size in

@@ -10,7 +10,7 @@ from ._binding import (  # noqa: F401
     LD_PRECOND_RANK_ONE, LD_PRECOND_RSVD, LD_PRECOND_SCALED, LD_PROBE_GAUSSIAN,
     LD_PROBE_ORTHOGONAL, LD_PROBE_RADEMACHER, LD_RBF, LD_ROW_MAJOR, LD_SUR_BINS, LD_SUR_FEATURES, LD_SUR_WIDTH, LD_TILED,
     BatchItem, Context, GPOperator, LogdetError, Precond, Surrogate, fill_gaussian, fill_probes,
-    kernel_materialize, kernel_matmat, load, logdet_estimate, logdet_estimate_batched,
+    kernel_materialize, kernel_matmat, kernel_matmat_noalloc, load, logdet_estimate, logdet_estimate_batched,
     logdet_estimate_lanczos, logdet_estimate_lanczos_orders, logdet_estimate_orders,
     logdet_gradient,
     rational_coeffs, stored_elements, surrogate_features, surrogate_param_count, workspace_bytes,

@@ -35,7 +35,8 @@ EXPORTED = (
     "ld_ctx_create", "ld_ctx_destroy", "ld_last_error", "ld_ctx_set_timing", "ld_ctx_read_timing",
     "ld_ctx_set_probes", "ld_ctx_set_graphs", "ld_workspace_bytes", "ld_set_workspace",
     "ld_stored_elements", "ld_rational_coeffs", "ld_fill_probes",
-    "ld_fill_gaussian", "kernel_matmat", "kernel_materialize", "logdet_precond_build",
+    "ld_fill_gaussian", "kernel_matmat", "kernel_matmat_noalloc", "kernel_materialize",
+    "logdet_precond_build",
     "logdet_precond_build_kind", "ld_precond_info", "ld_precond_export",
     "ld_precond_apply_inverse", "ld_precond_free",
     "logdet_estimate", "logdet_estimate_orders", "logdet_estimate_lanczos",
@@ -111,6 +112,7 @@ def load():
         "ld_fill_probes": (i32, [vp, u64, i64, i64, i32, vp]),
         "ld_fill_gaussian": (i32, [vp, u64, i32, i64, i64, vp]),
         "kernel_matmat": (i32, [vp, ctypes.POINTER(Operator), vp, i64, vp]),
+        "kernel_matmat_noalloc": (i32, [vp, ctypes.POINTER(Operator), vp, i64, vp]),
         "kernel_materialize": (i32, [vp, ctypes.POINTER(Operator), vp]),
         "ld_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Operator), i64, i32, i32, i32]),
         "ld_set_workspace": (i32, [vp, vp, ctypes.c_size_t]),
@@ -306,6 +308,22 @@ def kernel_matmat(ctx: Context, op: GPOperator, V):
     cop = op.c_struct()
     _check(load().kernel_matmat(ctx.handle, ctypes.byref(cop), ctypes.c_void_p(V2.data_ptr()),
                                 V2.shape[1], ctypes.c_void_p(Y.data_ptr())))
+    return Y.reshape(V.shape)
+
+
+def kernel_matmat_noalloc(ctx: Context, op: GPOperator, V, Y=None):
+    """kernel_matmat with the library's static device scratch (no allocation
+    inside the library); Y may be passed in (n x s, V's dtype)."""
+    torch = _torch()
+    assert V.is_cuda and V.dtype == _dtype(op.precision) and V.is_contiguous() and V.shape[0] == op.n
+    V2 = V if V.dim() == 2 else V.reshape(op.n, 1)
+    if Y is None:
+        Y = torch.empty_like(V2)
+    assert Y.shape == V2.shape and Y.dtype == V2.dtype and Y.is_contiguous()
+    cop = op.c_struct()
+    _check(load().kernel_matmat_noalloc(ctx.handle, ctypes.byref(cop),
+                                        ctypes.c_void_p(V2.data_ptr()), V2.shape[1],
+                                        ctypes.c_void_p(Y.data_ptr())))
     return Y.reshape(V.shape)
 
 

@@ -741,6 +741,11 @@ ld_status ld_ctx_create(int device, void* stream, ld_ctx** out) {
   int cu = 0;
   if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0)
     c->num_cu = cu;
+  const ld_status st = static_scratch_address(device, &c->static_scratch);
+  if (st != LD_OK) {
+    delete c;
+    return st;
+  }
   *out = c;
   return LD_OK;
 }
@@ -905,6 +910,38 @@ ld_status kernel_matmat(ld_ctx* ctx, const ld_operator* op, const void* V, int64
   a.V = V;
   a.Y = Y;
   return matmat(ctx, f64, a);
+}
+
+ld_status kernel_matmat_noalloc(ld_ctx* ctx, const ld_operator* op, const void* V, int64_t s,
+                                void* Y) {
+  LD_TRY(check_ctx(ctx));
+  LD_TRY(check_operator(op));
+  if (!V || !Y || s < 1) return fail(LD_EINVAL, "bad V / Y / s");
+  if (V == Y) return fail(LD_EINVAL, "Y must not alias V");
+  const size_t need = matmat_call_bytes(ctx, op, s);
+  if (need > kStaticScratchBytes)
+    return fail(LD_EINVAL, "kernel_matmat_noalloc: this product needs " + std::to_string(need) +
+                               " bytes of scratch; the static scratch holds " +
+                               std::to_string(kStaticScratchBytes));
+  if (!ctx->static_scratch) return fail(LD_EHIP, "kernel_matmat_noalloc: no static scratch");
+  // the same path as kernel_matmat with the context's arena pointed at the
+  // static scratch for this call (external: never grown, never freed)
+  struct Swap {
+    ld_ctx* c;
+    Arena saved;
+    ~Swap() { c->arena = saved; }
+  } swap{ctx, ctx->arena};
+  ctx->arena = Arena();
+  ctx->arena.base = (char*)ctx->static_scratch;
+  ctx->arena.cap = kStaticScratchBytes;
+  ctx->arena.external = true;
+  const void* Xp = nullptr;
+  LD_TRY(path_points(ctx, op, &Xp));
+  MatmatArgs a = base_args(op, Xp);
+  a.s = s;
+  a.V = V;
+  a.Y = Y;
+  return matmat(ctx, is_f64(op), a);
 }
 
 ld_status kernel_materialize(ld_ctx* ctx, const ld_operator* op, void* M_out) {

@@ -88,6 +88,8 @@ struct ld_ctx {
   int bvariant = -1;
   // probe distribution of the single-problem estimators (ld_probe_kind)
   int probe_kind = 0;
+  // this device's static scratch (kernel_matmat_noalloc), set at creation
+  void* static_scratch = nullptr;
 };
 
 struct ld_precond {
@@ -158,6 +160,10 @@ struct MatmatArgs {
                              // from stored split-BF16 LD_TILED tiles)
 };
 ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a);
+// kernel_matmat_noalloc's static device scratch: its size, and its address
+// on `device` (which must be current), looked up once per device and kept
+constexpr size_t kStaticScratchBytes = (size_t)256 << 20;
+ld_status static_scratch_address(int device, void** out);
 size_t matmat_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int64_t s);
 constexpr int kEpiRows = 128;  // rows per output tile of the product
 constexpr int kEpiSplitMax = 16;  // most epilogue workgroups (dot partial rows) per output tile

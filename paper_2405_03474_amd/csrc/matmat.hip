@@ -22,6 +22,7 @@
 #include <algorithm>
 
 #include <cmath>
+#include <mutex>
 
 #include "kfun_dev.hpp"
 #include "ld_common.hpp"
@@ -1529,7 +1530,37 @@ void fly64_by_d(int NB, dim3 g, hipStream_t st, const double* X, int d, double v
   }
 }
 
+// ------------------------------------------------------- static scratch --
+// Scratch of kernel_matmat_noalloc: a file-scope device array that every
+// device the library runs on holds from the code object's load until the
+// process ends.  In host code `scratch` names a host-side stand-in, not a
+// device address: host code uses only the per-device address that
+// static_scratch_address looks up.
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 }  // namespace
+
+ld_status static_scratch_address(int device, void** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return fail(LD_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    int cur = -1;
+    LD_HIP(hipGetDevice(&cur));
+    if (cur != device) return fail(LD_EINVAL, "static scratch lookup: device is not current");
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      return fail(LD_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    addr[device] = p;
+  }
+  *out = addr[device];
+  return LD_OK;
+}
 
 KParams make_kparams(const ld_operator& op) {
   KParams kp{};

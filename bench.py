@@ -76,7 +76,12 @@ import workloads  # noqa: E402
 
 METRIC = "log-det estimates/s at ≤1e-3 rel err vs FP64; mixed/batched vs plain FP32"
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "bf16": 2.5e15}
-DTYPE_NAME = {0: "f64", 1: "f32", 2: "bf16x3+f32"}  # by ld_precision
+DTYPE_NAME = {0: "f64", 1: "f32", 2: "bf16x3+f32"}  # by ld_precision (on the fly)
+
+
+def dtype_name(precision, stored):
+    """BF16 products take three terms on the fly and four from stored FP32 tiles."""
+    return "bf16x4+f32" if (precision == 2 and stored) else DTYPE_NAME[precision]
 WORKLOADS = {"c2_matern_gm50k": workloads.C2, "c1_rbf_2k": workloads.C1,
              "c3_matern_200k": workloads.C3, "c4_batch256": None, "c5_surrogate": None}
 
@@ -93,7 +98,7 @@ PROFILED_TRAFFIC = {
                             "paper_2405_03474_amd/csrc/matmat.hip"),
     "c2_matern_gm50k/f32": ("profiles/c2_matern_gm50k_k_mm32_tf.md",
                             "paper_2405_03474_amd/csrc/matmat.hip"),
-    "c2_matern_gm50k/bf16x3+f32": ("profiles/c2_matern_gm50k_k_mm16_st.md",
+    "c2_matern_gm50k/bf16x4+f32": ("profiles/c2_matern_gm50k_k_mm16_tf.md",
                                    "paper_2405_03474_amd/csrc/matmat.hip"),
 }
 
@@ -689,7 +694,7 @@ def main():
     ap.add_argument("--compare-fp32", action="store_true",
                     help="precision form: also time the plain FP32 path on the same problem")
     ap.add_argument("--stored-bf16", action="store_true",
-                    help="stored workload in the precision form: M stored as split-BF16 tiles")
+                    help="stored workload in the precision form (same as --precision bf16)")
     ap.add_argument("--check-fp64", action="store_true",
                     help="precision form: also run the FP64 path on the same probes")
     ap.add_argument("--compare-plain", action="store_true",
@@ -759,7 +764,7 @@ def main():
     if kind == "c3" and args.plain_fp32:
         precision = L.LD_F32
     stored = kind == "c2"
-    dtype = DTYPE_NAME[precision]
+    dtype = dtype_name(precision, stored)
     # FP64 solves of the stored workload stop at 1e-10 (the estimate then
     # agrees with the oracle's exact solves to ~1e-12; tested at n = 20,000)
     tol = args.tol or (1e-10 if (kind == "c2" and precision == L.LD_F64) else 0.0)
@@ -826,7 +831,7 @@ def main():
         "config": {"workload": cfg.name, "n": cfg.n, "d": cfg.d,
                    "kernel": "matern52" if cfg.kind == 1 else "rbf", "points": cfg.points,
                    "lengthscale": cfg.lengthscale, "variance": cfg.variance, "noise": cfg.noise,
-                   "storage": (("stored_split_bf16_tiled" if precision == L.LD_BF16 else "stored_tiled")
+                   "storage": ("stored_tiled"
                                if stored else "on_the_fly"),
                    "orders": list(cfg.orders), "probes": cfg.probes, "rank": cfg.rank,
                    "oversample": cfg.oversample, "power_iters": cfg.power_iters,
@@ -847,20 +852,21 @@ def main():
     }
 
     if kind == "c2" and precision == L.LD_BF16:
-        # split-BF16 tiles move as many bytes as FP32 with a sixth of the
-        # matrix-core time: the product is bound by HBM
+        # the FP32 tiles' bytes with under a third of the FP32 matrix-core
+        # time: the product is bound by HBM
         gbps = (mm_bytes / max(mm_calls, 1)) / (avg_ms / 1e3) / 1e9
         line["roofline"].update({
             "bound": "hbm", "achieved": gbps, "peak": 8000.0, "unit": "GB/s", "frac": gbps / 8000.0,
             "traffic": traffic,
-            "kernel": "k_mm16_st<2> (split-BF16 MFMA 32x32x16, 3 terms, stored split tiles)",
+            "kernel": "k_mm16_tf<2> (BF16 MFMA 32x32x16, stored FP32 tiles split exactly into "
+                      "3 bf16 parts, V into 2, 4 terms)",
             "flops_TFLOPs": achieved / 1e12})
     if kind == "c2" and precision == L.LD_F64 and not args.no_forms:
         # the metric's other forms on the same problem and probes: plain FP32
         # and the split-BF16 precision form, each against this FP64 result
         forms = {}
         for fprec in (L.LD_F32, L.LD_BF16):
-            name = DTYPE_NAME[fprec]
+            name = dtype_name(fprec, stored)
             log(f"[bench] form {name}, same problem")
             fr = Runner(L, torch, ctx, cfg, fprec, stored, args.lanczos_steps, args.precond,
                         args.scaled, args.union_shifts)
@@ -876,7 +882,7 @@ def main():
         for f in forms.values():
             f["speedup_vs_plain_fp32"] = f["value"] / base
         line["forms"] = forms
-        line["speedup_vs_plain_fp32"] = {"bf16x3+f32": forms["bf16x3+f32"]["speedup_vs_plain_fp32"],
+        line["speedup_vs_plain_fp32"] = {"bf16x4+f32": forms["bf16x4+f32"]["speedup_vs_plain_fp32"],
                                          "f64": value / base}
     if exact is not None:
         within = [f"r{k}" for k in cfg.orders if accuracy[f"r{k}"]["within_1e-3"]]

@@ -58,11 +58,14 @@ typedef enum { LD_RBF = 0, LD_MATERN52 = 1 } ld_kernel;
  * and log det P are FP64 in every mode.
  *  LD_F64  FP64 products (FP64 matrix cores) and vectors.
  *  LD_F32  FP32 products (FP32 matrix cores) and vectors.
- *  LD_BF16 precision form: kernel values and distances in FP32, each
- *          operand split into bf16 hi + lo parts, products hi*hi + hi*lo +
- *          lo*hi on BF16 matrix cores with FP32 accumulation; vectors FP32
- *          (vector buffers use FP32).  On the fly, or from M stored as split
- *          BF16 tiles (LD_TILED only, see kernel_materialize). */
+ *  LD_BF16 precision form: products on BF16 matrix cores with FP32
+ *          accumulation, vectors FP32 (vector buffers use FP32).  On the
+ *          fly: kernel values and distances in FP32, each operand split
+ *          into bf16 hi + lo parts, products hi*hi + hi*lo + lo*hi.  From a
+ *          stored matrix (FP32, LD_TILED only: the same buffer as LD_F32):
+ *          each stored entry split exactly into three bf16 parts, each V
+ *          entry into hi + lo, four product terms (see kernel_materialize),
+ *          so the stored operator enters exactly as its FP32 values. */
 typedef enum { LD_F64 = 0, LD_F32 = 1, LD_BF16 = 2 } ld_precision;
 
 /* The matrix M = K(X, X) + noise * I (Section 3 kernels; formulas are the
@@ -79,10 +82,10 @@ typedef struct {
   double variance;        /* signal variance, > 0 */
   double noise;           /* noise variance added to the diagonal, >= 0 */
   int32_t precision;      /* ld_precision */
-  const void* M_stored;   /* device matrix M (FP64 for LD_F64, FP32 for LD_F32,
-                             split-BF16 tiles for LD_BF16; noise included) in
-                             layout `layout`, or NULL to generate kernel
-                             entries on the fly from X */
+  const void* M_stored;   /* device matrix M (FP64 for LD_F64, FP32 for LD_F32
+                             and LD_BF16; noise included) in layout `layout`,
+                             or NULL to generate kernel entries on the fly
+                             from X */
   int32_t layout;         /* ld_layout of M_stored (ignored when it is NULL) */
 } ld_operator;
 
@@ -239,13 +242,12 @@ ld_status kernel_matmat_noalloc(ld_ctx* ctx, const ld_operator* op, const void* 
                                 void* Y);
 
 /* Write M = K + noise I (device, ld_stored_elements(n, op->layout) elements,
- * FP64 for LD_F64, FP32 for LD_F32) in op->layout so that it can be passed
- * back as op->M_stored.  op->M_stored is ignored.  With LD_BF16 (LD_TILED only) the buffer has the same size in
- * bytes as the FP32 one and holds K - variance I (zero diagonal): each
- * 128 x 32 tile holds the 4096 values hi = bf16(m) (row-major inside the tile)
- * followed by the 4096 values bf16(m - hi), m the FP32 entry; the products add
- * (variance + noise) V in FP32, so the diagonal carries no BF16 rounding.
- * Asynchronous. */
+ * FP64 for LD_F64, FP32 for LD_F32 and LD_BF16) in op->layout so that it can
+ * be passed back as op->M_stored.  op->M_stored is ignored.  LD_BF16 needs
+ * LD_TILED and writes the same FP32 tiles as LD_F32: its products split each
+ * FP32 entry m in registers into h = bf16(m), c = bf16(m - h),
+ * l = bf16(m - h - c) (h + c + l = m exactly) and each V entry v into
+ * bf16 hi + lo, and take h*hi + h*lo + c*hi + l*hi.  Asynchronous. */
 ld_status kernel_materialize(ld_ctx* ctx, const ld_operator* op, void* M_out);
 
 /* Build the randomized truncated-SVD preconditioner P = D + U diag(lam) U^T

@@ -228,7 +228,7 @@ __global__ void k_d_and_inv(const double* __restrict__ U, const double* __restri
     }
     double dm = diag_const;
     const int64_t ii = stored_index(i, i, n, layout, mprec == LD_F64);
-    if (Mst && mprec != LD_BF16) {  // split-BF16 tiles store K - variance I: diag is diag_const
+    if (Mst) {  // FP64, or FP32 (LD_F32 and the LD_BF16 precision form)
       dm = mprec == LD_F64 ? ((const double*)Mst)[ii] : (double)((const float*)Mst)[ii];
     }
     double low = 0.0;
@@ -588,7 +588,7 @@ __global__ void k_pc_res_init(double* __restrict__ res, int64_t n, const void* _
                               int mprec, int layout, double diag_const) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     double dm = diag_const;
-    if (Mst && mprec != LD_BF16) {
+    if (Mst) {
       const int64_t ii = stored_index(i, i, n, layout, mprec == LD_F64);
       dm = mprec == LD_F64 ? ((const double*)Mst)[ii] : (double)((const float*)Mst)[ii];
     }
@@ -642,7 +642,7 @@ __global__ void k_pc_column(const double* __restrict__ X, int d, double var, dou
   const double* cp = C + p * rank;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     double m;
-    if (Mst && mprec != LD_BF16) {
+    if (Mst) {
       const int64_t ii = stored_index(i, p, n, layout, mprec == LD_F64);
       m = mprec == LD_F64 ? ((const double*)Mst)[ii] : (double)((const float*)Mst)[ii];
     } else {

@@ -23,6 +23,7 @@
 
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 
 #include "kfun_dev.hpp"
 #include "ld_common.hpp"
@@ -654,117 +655,52 @@ __device__ __forceinline__ void f16_compute(const __bf16* __restrict__ bh,
   }
 }
 
-// Stored split-BF16 K - variance I (LD_TILED, hi and lo planes per tile):
-// the product takes the three terms hi*hi + hi*lo + lo*hi on BF16 matrix
-// cores with FP32 accumulation like the on-the-fly form, reading as many
-// bytes as FP32 storage with a sixth of its matrix-core time, so it is bound
-// by HBM; the epilogue adds (variance + noise) V in FP32.  The diagonal is
-// kept out of the split because its rounding error would be the same in
-// every row and, multiplied by tr(M^-1) ~ n / noise, would shift log det.  Stage = one 128 x 32 tile (both
-// planes, 16 KB) and a 32 x 32 NB block of V split in the loader; in k-step q
-// lane half h supplies k = 16 q + 8 h + j (j < 8) for both operands.  A is
-// kept row-major (rows padded to 40 bf16), B transposed (k contiguous).
-constexpr int S16 = BK + 8;  // bf16 row stride of the A planes and of transposed B
+// Precision form from a stored FP32 matrix (LD_TILED fragment tiles, the
+// same buffer as the FP32 path): each FP32 entry m is split in registers
+// into three BF16 parts h = bf16(m), c = bf16(m - h), l = bf16(m - h - c),
+// whose sum is m exactly (each rounding leaves at most 8 significant bits
+// for the next part); each FP32 entry v of V into bf16 hi + lo (2^-17
+// relative).  The product takes h*hi + h*lo + c*hi + l*hi on BF16 matrix
+// cores with FP32 accumulation: against the high part of V the stored
+// operator enters exactly as its FP32 values; what is dropped (V's bits
+// below 2^-16 of each entry, and c*lo, l*lo, about 2^-16 and 2^-24 of each
+// term) depends on V and changes from one product to the next, like the
+// rounding of V itself, rather than perturbing the operator.  The four BF16
+// matrix-core steps per 16 k take a quarter of the FP32 matrix-core time of
+// k_mm32_tf; the splitting work on the vector ALUs is what remains.
+// A arrives straight into registers as in k_mm32_tf (lane half h holds
+// k = 16 h + t, t < 16, of its row); in BF16 k-step q lane half h supplies
+// k = 16 h + 8 q + j (j < 8) for both operands.  B is split by the loader
+// into hi and lo planes, kept transposed (k contiguous) and double buffered
+// in LDS.
+constexpr int S16 = BK + 8;  // bf16 row stride of transposed B (80 bytes)
 
-template <int NB>
-struct St16Tile {
-  u32x4 ah[2], al[2];  // 2 x 16 B of each plane per thread (128 x 32 bf16 = 512 x 16 B)
-  float v[4 * NB];     // pairs of consecutive k of one V column
-};
-
-template <int NB>
-__device__ __forceinline__ void st16_load(St16Tile<NB>& t, const __bf16* __restrict__ A,
-                                          const float* __restrict__ V, int64_t n, int64_t s,
-                                          int64_t tile, int64_t c0, int64_t k0, int tid) {
-  constexpr int NT = 32 * NB;
-  const u32x4* src = (const u32x4*)(A + tile * (2 * BM * BK));
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    t.ah[j] = __builtin_nontemporal_load(src + tid + 256 * j);
-    t.al[j] = __builtin_nontemporal_load(src + 512 + tid + 256 * j);
-  }
-#pragma unroll
-  for (int j = 0; j < 2 * NB; ++j) {
-    const int e = tid + 256 * j;
-    const int cc = e % NT, kp = e / NT;  // column, pair of k rows
-    const int64_t col = c0 + cc, kr = k0 + 2 * kp;
-    const bool cv = col < s;
-    // unconditional loads from clamped addresses, kept raw until the store
-    // masks them (masking here would make the wave wait for the loads at
-    // once; a select would let the compiler sink each load into a per-lane
-    // branch)
-    const int64_t cl = cv ? col : s - 1;
-    const int64_t r0 = kr < n ? kr : n - 1, r1 = kr + 1 < n ? kr + 1 : n - 1;
-    t.v[2 * j] = V[r0 * s + cl];
-    t.v[2 * j + 1] = V[r1 * s + cl];
-  }
+// x -> three bf16 parts (a pair at a time, packed two per word)
+__device__ __forceinline__ void split3(float x0, float x1, uint32_t& h, uint32_t& c, uint32_t& l) {
+  const f32x2 v = {x0, x1};
+  h = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+  const f32x2 r = {x0 - __builtin_bit_cast(float, h << 16),
+                   x1 - __builtin_bit_cast(float, h & 0xffff0000u)};
+  c = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2));
+  const f32x2 q = {r.x - __builtin_bit_cast(float, c << 16),
+                   r.y - __builtin_bit_cast(float, c & 0xffff0000u)};
+  l = __builtin_bit_cast(uint32_t, __builtin_convertvector(q, bf16x2));
 }
 
 template <int NB>
-__device__ __forceinline__ void st16_store(const St16Tile<NB>& t, __bf16* __restrict__ ah,
-                                           __bf16* __restrict__ al, __bf16* __restrict__ bh,
-                                           __bf16* __restrict__ bl, int tid, int64_t n, int64_t s,
-                                           int64_t c0, int64_t k0) {
-  constexpr int NT = 32 * NB;
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int c = tid + 256 * j;  // 16-byte chunk: row c / 4, bf16 columns 8 (c % 4) ..
-    const int off = (c >> 2) * S16 + 8 * (c & 3);
-    *(u32x4*)&ah[off] = t.ah[j];
-    *(u32x4*)&al[off] = t.al[j];
-  }
-#pragma unroll
-  for (int j = 0; j < 2 * NB; ++j) {
-    const int e = tid + 256 * j;
-    const int cc = e % NT, kp = e / NT;
-    const int64_t col = c0 + cc, kr = k0 + 2 * kp;
-    const bool cv = col < s;
-    // rows beyond n and columns beyond s were loaded from clamped addresses
-    const float v0 = t.v[2 * j] * ((cv && kr < n) ? 1.f : 0.f);
-    const float v1 = t.v[2 * j + 1] * ((cv && kr + 1 < n) ? 1.f : 0.f);
-    uint32_t h, l;
-    split2(v0, v1, h, l);
-    *(uint32_t*)&bh[cc * S16 + 2 * kp] = h;
-    *(uint32_t*)&bl[cc * S16 + 2 * kp] = l;
-  }
-}
-
-template <int NB>
-__device__ __forceinline__ void st16_compute(const __bf16* __restrict__ ah,
-                                             const __bf16* __restrict__ al,
-                                             const __bf16* __restrict__ bh,
-                                             const __bf16* __restrict__ bl, f32x16* acc, int wave,
-                                             int li, int lh) {
-#pragma unroll
-  for (int q = 0; q < BK / 16; ++q) {
-    const int aoff = (32 * wave + li) * S16 + 16 * q + 8 * lh;
-    const bf16x8 a_h = *(const bf16x8*)&ah[aoff];
-    const bf16x8 a_l = *(const bf16x8*)&al[aoff];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const int boff = (nb * 32 + li) * S16 + 16 * q + 8 * lh;
-      const bf16x8 b_h = *(const bf16x8*)&bh[boff];
-      const bf16x8 b_l = *(const bf16x8*)&bl[boff];
-      acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_h, acc[nb], 0, 0, 0);
-      acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_l, acc[nb], 0, 0, 0);
-      acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_l, b_h, acc[nb], 0, 0, 0);
-    }
-  }
-}
-
-template <int NB>
-__global__ __launch_bounds__(256, 2) void k_mm16_st(const __bf16* __restrict__ A,
+__global__ __launch_bounds__(256, 2) void k_mm16_tf(const float* __restrict__ A,
                                                     const float* __restrict__ V,
                                                     float* __restrict__ part, SK p) {
   constexpr int NT = 32 * NB;
-  __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM * S16];
-  __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM * S16];
+  constexpr int BP = 2 * NB;  // pairs of V values per thread per stage (32 x NT / 512)
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
   __shared__ __attribute__((aligned(16))) __bf16 Bh[2][NT * S16];
   __shared__ __attribute__((aligned(16))) __bf16 Bl[2][NT * S16];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 31, lh = lane >> 5;
   const int64_t n = p.n, s = p.s;
+
   const WGRange wr = wg_range(p, blockIdx.x);
   int64_t u = wr.u;
   const int64_t uend = wr.uend;
@@ -774,9 +710,10 @@ __global__ __launch_bounds__(256, 2) void k_mm16_st(const __bf16* __restrict__ A
     const int l0 = (int)(u - T * wr.Sx);
     const int l1 = (int)((int64_t)wr.Sx < l0 + (uend - u) ? (int64_t)wr.Sx : l0 + (uend - u));
     const int st0 = wr.sb + l0, st1 = wr.sb + l1;
-    const int64_t band = T % p.rt;
+    const int rtile = (int)(T % p.rt);
     const int64_t c0 = (T / p.rt) * NT;
-    const int64_t tile0 = band * p.S;
+    // this wave's quarter of tile (rtile, 0); stage st is st * 4096 floats further
+    const f32x4* abase = (const f32x4*)(A + (int64_t)rtile * p.S * (BM * BK) + wave * 1024) + lane;
 
     f32x16 acc[NB];
 #pragma unroll
@@ -784,35 +721,121 @@ __global__ __launch_bounds__(256, 2) void k_mm16_st(const __bf16* __restrict__ A
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
 
-    // Every stage load is issued unconditionally (past the segment's end it
-    // reloads the last stage, unused), so the number of loads in flight is
-    // the same on every path and the waits before each LDS store cover only
-    // that stage's loads (two stages stay in flight).
+    // the same load schedule as k_mm32_tf: identical loads on every path, B
+    // issued before A, two stages of A in flight
     const int last = st1 - 1;
-    St16Tile<NB> ta, tb;
-    st16_load<NB>(ta, A, V, n, s, tile0 + st0, c0, (int64_t)st0 * BK, tid);
-    {
-      const int nx = st0 + 1 < last ? st0 + 1 : last;
-      st16_load<NB>(tb, A, V, n, s, tile0 + nx, c0, (int64_t)nx * BK, tid);
-    }
-    __syncthreads();  // the previous segment's last stage is done with both buffers
-    for (int st = st0; st < st1; st += 2) {
-      st16_store<NB>(ta, Ah[0], Al[0], Bh[0], Bl[0], tid, n, s, c0, (int64_t)st * BK);
-      __syncthreads();
-      {
-        const int nx = st + 2 < last ? st + 2 : last;
-        st16_load<NB>(ta, A, V, n, s, tile0 + nx, c0, (int64_t)nx * BK, tid);
+    auto clampst = [&](int st) { return st < last ? st : last; };
+    f32x4 aq[2][4];
+    float bq[2 * BP];  // pairs (k, k + 1) of one column
+    auto load_a = [&](int st, f32x4* dst) {
+      const f32x4* src = abase + (int64_t)st * (BM * BK / 4);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dst[q] = __builtin_nontemporal_load(src + 64 * q);
+    };
+    // pair j of this thread: column c0 + e % NT, rows k0 + 2 (e / NT) (+1),
+    // e = tid + 256 j; clamped addresses, masked in store_b
+    // (both paths issue the same loads; a stage inside V, uniform over the
+    // workgroup, needs no clamping or masking)
+    auto inside = [&](int st) { return (int64_t)st * BK + BK <= n && c0 + NT <= s; };
+    auto load_b = [&](int st) {
+      const int64_t k0 = (int64_t)st * BK;
+      if (inside(st)) {
+        const float* src = V + (k0 + 2 * (tid / NT)) * s + c0 + tid % NT;
+#pragma unroll
+        for (int j = 0; j < BP; ++j) {
+          bq[2 * j] = src[(int64_t)(512 / NT) * j * s];
+          bq[2 * j + 1] = src[(int64_t)(512 / NT) * j * s + s];
+        }
+        return;
       }
-      st16_compute<NB>(Ah[0], Al[0], Bh[0], Bl[0], acc, wave, li, lh);
-      if (st + 1 >= st1) break;
-      st16_store<NB>(tb, Ah[1], Al[1], Bh[1], Bl[1], tid, n, s, c0, (int64_t)(st + 1) * BK);
-      __syncthreads();
-      {
-        const int nx = st + 3 < last ? st + 3 : last;
-        st16_load<NB>(tb, A, V, n, s, tile0 + nx, c0, (int64_t)nx * BK, tid);
+#pragma unroll
+      for (int j = 0; j < BP; ++j) {
+        const int e = tid + 256 * j;
+        const int64_t kr = k0 + 2 * (e / NT);
+        int64_t col = c0 + e % NT;
+        col = col < s ? col : s - 1;
+        const int64_t r0 = kr < n ? kr : n - 1, r1 = kr + 1 < n ? kr + 1 : n - 1;
+        bq[2 * j] = V[r0 * s + col];
+        bq[2 * j + 1] = V[r1 * s + col];
       }
-      st16_compute<NB>(Ah[1], Al[1], Bh[1], Bl[1], acc, wave, li, lh);
+    };
+    auto store_b = [&](__bf16* bh, __bf16* bl, int st) {
+      const int64_t k0 = (int64_t)st * BK;
+      const bool full = inside(st);
+#pragma unroll
+      for (int j = 0; j < BP; ++j) {
+        const int e = tid + 256 * j;
+        const int cc = e % NT, kp = e / NT;
+        float v0 = bq[2 * j], v1 = bq[2 * j + 1];
+        if (!full) {
+          const int64_t kr = k0 + 2 * kp;
+          const bool cv = c0 + cc < s;
+          v0 *= (cv && kr < n) ? 1.f : 0.f;
+          v1 *= (cv && kr + 1 < n) ? 1.f : 0.f;
+        }
+        uint32_t h, l;
+        split2(v0, v1, h, l);
+        *(uint32_t*)&bh[cc * S16 + 2 * kp] = h;
+        *(uint32_t*)&bl[cc * S16 + 2 * kp] = l;
+      }
+    };
+    auto stage = [&](int cur, auto dc) {
+      constexpr int D = decltype(dc)::value;
+      const int buf = (cur - st0) & 1;
+      // the three parts of this lane's 16 A values (k = 16 lh + t)
+      u32x4 ah[2], ac[2], al[2];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint32_t h0, c0w, l0w, h1, c1w, l1w;
+        split3(aq[D][q].x, aq[D][q].y, h0, c0w, l0w);
+        split3(aq[D][q].z, aq[D][q].w, h1, c1w, l1w);
+        const int w = 2 * (q & 1);
+        ah[q >> 1][w] = h0;
+        ac[q >> 1][w] = c0w;
+        al[q >> 1][w] = l0w;
+        ah[q >> 1][w + 1] = h1;
+        ac[q >> 1][w + 1] = c1w;
+        al[q >> 1][w + 1] = l1w;
+      }
+      // stage cur + 1 into the other buffer (last read in stage cur - 1,
+      // fenced by the barrier that ended it; past the end it is not read)
+      store_b(Bh[buf ^ 1], Bl[buf ^ 1], cur + 1);
+      load_b(clampst(cur + 2));
+      // keep B's loads ahead of A's (the scheduler would interleave them)
+      __builtin_amdgcn_sched_barrier(0);
+      load_a(clampst(cur + 2), aq[D]);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const bf16x8 a_h = __builtin_bit_cast(bf16x8, ah[q]);
+        const bf16x8 a_c = __builtin_bit_cast(bf16x8, ac[q]);
+        const bf16x8 a_l = __builtin_bit_cast(bf16x8, al[q]);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const int boff = (nb * 32 + li) * S16 + 16 * lh + 8 * q;
+          const bf16x8 b_h = *(const bf16x8*)&Bh[buf][boff];
+          const bf16x8 b_l = *(const bf16x8*)&Bl[buf][boff];
+          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_h, acc[nb], 0, 0, 0);
+          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_l, acc[nb], 0, 0, 0);
+          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_c, b_h, acc[nb], 0, 0, 0);
+          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_l, b_h, acc[nb], 0, 0, 0);
+        }
+      }
+      __syncthreads();
+    };
+
+    load_b(st0);
+    load_a(st0, aq[0]);
+    __syncthreads();  // the previous segment is done with both B buffers
+    store_b(Bh[0], Bl[0], st0);
+    load_b(clampst(st0 + 1));
+    load_a(clampst(st0 + 1), aq[1]);
+    __syncthreads();
+    int st = st0;
+    for (; st + 1 < st1; st += 2) {
+      stage(st, std::integral_constant<int, 0>{});
+      stage(st + 1, std::integral_constant<int, 1>{});
     }
+    if (st < st1) stage(st, std::integral_constant<int, 0>{});
 
     float* dst = part + ((int64_t)blockIdx.x * p.J + seg) * (int64_t)(BM * NT);
 #pragma unroll
@@ -1307,40 +1330,6 @@ __global__ __launch_bounds__(256) void k_materialize(const double* __restrict__ 
   }
 }
 
-// LD_TILED with split BF16 (precision form, stored): per 128 x 32 tile the
-// 4096 high parts bf16(m) and then the 4096 low parts bf16(m - hi) of the FP32
-// entries m of K - variance I (zero diagonal), both row-major inside the
-// tile; padding is zero.
-template <int KIND>
-__global__ __launch_bounds__(256) void k_materialize_tiled_bf16(const double* __restrict__ X,
-                                                                int64_t n, int d, double var,
-                                                                double c, double noise,
-                                                                int64_t total,
-                                                                __bf16* __restrict__ M) {
-  const int64_t kt = (n + kTileCols - 1) / kTileCols;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * 256) {
-    const int64_t tile = e / (kTileRows * kTileCols);
-    const int w = (int)(e % (kTileRows * kTileCols));
-    const int64_t i = (tile / kt) * kTileRows + w / kTileCols;
-    const int64_t k = (tile % kt) * kTileCols + w % kTileCols;
-    float out = 0.f;
-    if (i < n && k < n) {
-      double r2 = 0.0;
-      for (int dd = 0; dd < d; ++dd) {
-        const double df = X[i * d + dd] - X[k * d + dd];
-        r2 = fma(df, df, r2);
-      }
-      out = i == k ? 0.f : (float)kval64<KIND>(r2, var, c);  // diagonal added in FP32
-    }
-    const __bf16 hi = (__bf16)out;
-    const __bf16 lo = (__bf16)(out - (float)hi);
-    __bf16* t = M + tile * (2 * kTileRows * kTileCols);
-    t[w] = hi;
-    t[kTileRows * kTileCols + w] = lo;
-  }
-}
-
 // LD_TILED (FP32, fragment order inside the tile: tile_offset): walk the
 // storage linearly (coalesced writes), zero the padding.
 template <int KIND>
@@ -1693,11 +1682,11 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
     } else {
       const float* A = (const float*)a.A;
       const bool tiled = a.layout == LD_TILED;
-      if (a.bf16) {  // stored split-BF16 tiles
+      if (a.bf16) {  // precision form from the stored FP32 tiles
         if (NB == 2)
-          hipLaunchKernelGGL((k_mm16_st<2>), grid, dim3(256), 0, st, (const __bf16*)a.A, V, P, pl.p);
+          hipLaunchKernelGGL((k_mm16_tf<2>), grid, dim3(256), 0, st, A, V, P, pl.p);
         else
-          hipLaunchKernelGGL((k_mm16_st<1>), grid, dim3(256), 0, st, (const __bf16*)a.A, V, P, pl.p);
+          hipLaunchKernelGGL((k_mm16_tf<1>), grid, dim3(256), 0, st, A, V, P, pl.p);
       } else if (NB == 2 && tiled)
         hipLaunchKernelGGL((k_mm32_tf<2>), grid, dim3(256), 0, st, A, V, P, pl.p);
       else if (NB == 2)
@@ -1711,7 +1700,7 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
     const int64_t tiles = (int64_t)pl.p.rt * ((a.s + pl.NT - 1) / pl.NT);
     hipLaunchKernelGGL(k_epilogue<float>, dim3((unsigned)tiles, epi_split(tiles, pl.NT)), dim3(256), 0, st, P, pl.p, pl.NT,
                        (float*)a.Y, V,
-                       fly ? a.kp.noise : (a.bf16 ? a.kp.variance + a.kp.noise : 0.0),
+                       fly ? a.kp.noise : 0.0,
                        (const float*)a.X2, a.alpha2, a.dots);
   }
   if (a.dot_blocks)
@@ -1739,18 +1728,6 @@ void launch_materialize(hipStream_t st, const KParams& kp, const double* X, int6
                         int precision, int layout, void* M) {
   const double c = kp.kind == LD_RBF ? kp.c_rbf : kp.c_mat;
   const bool f64 = precision == LD_F64;
-  if (layout == LD_TILED && precision == LD_BF16) {
-    const int64_t total = stored_elements(n, LD_TILED);
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    if (kp.kind == LD_RBF)
-      hipLaunchKernelGGL((k_materialize_tiled_bf16<LD_RBF>), dim3((unsigned)blocks), dim3(256), 0,
-                         st, X, n, d, kp.variance, c, kp.noise, total, (__bf16*)M);
-    else
-      hipLaunchKernelGGL((k_materialize_tiled_bf16<LD_MATERN52>), dim3((unsigned)blocks), dim3(256),
-                         0, st, X, n, d, kp.variance, c, kp.noise, total, (__bf16*)M);
-    return;
-  }
   if (layout == LD_TILED && f64) {
     const int64_t total = stored_elements(n, LD_TILED);
     int64_t blocks = (total + 255) / 256;

@@ -5,12 +5,13 @@ Section 3 sweep over the dimension d of the index points.
 
 Each problem is stored once in FP64 (row-major, from the library's
 kernel_materialize).  Its exact log det, the yardstick of the paper's
-accuracy plots, comes from a Cholesky factorisation of that matrix (torch's
-linear algebra: a measurement of the estimator, not part of it).  Every
-estimate is a library call (preconditioner build plus Algorithm 1 or the
-multi-shift CG); its time includes the preconditioner, as the paper's
-timings do.  Errors are |estimate - log det M| (absolute, as in the paper's
-figures) and that divided by |log det M|.
+accuracy plots, is supplied by the caller (`exact_fn`: the benchmark and the
+tests factor the stored matrix outside this package; it is a measurement of
+the estimator, not part of it).  Every estimate is a library call
+(preconditioner build plus Algorithm 1 or the multi-shift CG); its time
+includes the preconditioner, as the paper's timings do.  Errors are
+|estimate - log det M| (absolute, as in the paper's figures) and that divided
+by |log det M|.
 """
 from __future__ import annotations
 
@@ -110,15 +111,6 @@ def stored_operator(ctx: B.Context, g, torch):
     return op
 
 
-def exact_logdet(ctx: B.Context, op, torch) -> float:
-    """log det M = 2 sum log diag(L) with M = L L^T, in FP64."""
-    ctx.synchronize()
-    Lf = torch.linalg.cholesky(op.M)
-    v = float(2.0 * torch.log(torch.diagonal(Lf)).sum())
-    del Lf
-    return v
-
-
 def estimate(ctx: B.Context, op, g, st: Setting):
     """One estimate of log det M with setting st; returns (value, seconds)."""
     ctx.set_probes(st.probe_kind)
@@ -140,15 +132,16 @@ def _print(msg: str):
     print(msg, flush=True)
 
 
-def sweep(ctx: B.Context, instances, settings: dict, torch, log=_print):
+def sweep(ctx: B.Context, instances, settings: dict, torch, exact_fn, log=_print):
     """Every setting of `settings` (name -> Setting) on every problem of
-    `instances`; the problem's matrix and exact log det are computed once.
+    `instances`; the problem's matrix and exact log det (exact_fn(ctx, op):
+    the caller's yardstick for the stored FP64 matrix op.M) are computed once.
     Returns ({name: Cell}, [exact log det per problem])."""
     cells = {name: Cell() for name in settings}
     exacts = []
     for i, g in enumerate(instances):
         op = stored_operator(ctx, g, torch)
-        exact = exact_logdet(ctx, op, torch)
+        exact = exact_fn(ctx, op)
         exacts.append(exact)
         if i == 0:      # first call on the device: library set-up outside the timings
             estimate(ctx, op, g, next(iter(settings.values())))

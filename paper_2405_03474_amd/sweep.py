@@ -1,7 +1,9 @@
 """Hyperparameter sweeps with the learned surrogate.
 
-Workflow (every numerical step runs in the library; this module only moves
-batches between its entry points):
+Workflow (the estimator, the preconditioners, the features, training and
+prediction run in the library; this module moves batches between its entry
+points and, per grid point, adds log det P to n times the predicted trace
+term and applies the fallback rule to those two host scalars):
   1. training data: the batched estimator (r_k, s probes) on a set of
      problems gives targets (log det - log det P) / n and, with the kept
      eigenvalues, the 38 features of each problem;

@@ -19,6 +19,13 @@ import paper_2405_03474_amd as L  # noqa: E402
 from paper_2405_03474_amd import sensitivity as S  # noqa: E402
 
 
+def exact_cholesky(ctx, op):
+    """Yardstick for the sweep: Cholesky log det of the stored FP64 matrix."""
+    ctx.synchronize()
+    Lf = torch.linalg.cholesky(op.M)
+    return float(2.0 * torch.log(torch.diagonal(Lf)).sum())
+
+
 @pytest.fixture(scope="module")
 def ctx():
     c = L.Context(0)
@@ -34,7 +41,7 @@ def test_sweep_matches_oracle(ctx):
                 # orthogonality (spectrum of M P^-1 up to ~50), and their output
                 # moves by ~1e-6 relative under 1e-15 perturbations of M
                 "pchol_r5": S.Setting(k=5, precond=L.LD_PRECOND_PCHOL, solver="cg", tol=1e-12)}
-    cells, exacts = S.sweep(ctx, insts, settings, torch)
+    cells, exacts = S.sweep(ctx, insts, settings, torch, exact_cholesky)
     for i, g in enumerate(insts):
         M = gp.dense_matrix(g.kind, g.X(), g.lengthscale, g.variance, g.noise)
         exact = oest.logdet_exact(M)

@@ -526,12 +526,12 @@ __global__ void k_copy2(const T* __restrict__ src, T* __restrict__ a, T* __restr
 // single-workgroup scalar kernels add only kSeg values per column.
 constexpr int kSeg = 32;
 
-__global__ __launch_bounds__(256) void k_colsum_seg(const double* __restrict__ parts, int nblk,
-                                                    int64_t s, double* __restrict__ out) {
+// one workgroup's share: columns 64 x .. 64 x + 63, segment seg
+__device__ void colsum_seg_block(const double* __restrict__ parts, int nblk, int64_t s,
+                                 double* __restrict__ out, int64_t x, int seg) {
   __shared__ double red[4][64];
   const int cl = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const int64_t c = (int64_t)blockIdx.x * 64 + cl;
-  const int seg = blockIdx.y;
+  const int64_t c = x * 64 + cl;
   const int chunk = (nblk + kSeg - 1) / kSeg;
   const int b0 = seg * chunk;
   const int b1 = b0 + chunk < nblk ? b0 + chunk : nblk;
@@ -551,6 +551,30 @@ __global__ __launch_bounds__(256) void k_colsum_seg(const double* __restrict__ p
   red[q][cl] = acc;
   __syncthreads();
   if (q == 0 && c < s) out[(int64_t)seg * s + c] = ((red[0][cl] + red[1][cl]) + red[2][cl]) + red[3][cl];
+}
+
+__global__ __launch_bounds__(256) void k_colsum_seg(const double* __restrict__ parts, int nblk,
+                                                    int64_t s, double* __restrict__ out) {
+  colsum_seg_block(parts, nblk, s, out, blockIdx.x, blockIdx.y);
+}
+
+// True in every thread of the workgroup that finishes last among the grid's
+// workgroups (device-scope counter, which that workgroup resets to 0 for the
+// next launch); every workgroup's global writes before the call are then
+// visible to it.  No workgroup waits for another.
+__device__ bool last_workgroup(int* counter) {
+  __shared__ int last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int total = (int)(gridDim.x * gridDim.y * gridDim.z);
+    last = atomicAdd(counter, 1) == total - 1;
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  if (threadIdx.x == 0) atomicExch(counter, 0);
+  return true;
 }
 
 // sum over b of parts[b][c] in order b = 0, 1, ...; the loads are issued
@@ -595,7 +619,8 @@ __global__ void k_scal_init(Scal S, const double* __restrict__ dots1, const doub
   }
 }
 
-__global__ void k_scal_alpha(Scal S, const double* __restrict__ dots, int nblk, int64_t s) {
+__device__ void scal_alpha_body(const Scal& S, const double* __restrict__ dots, int nblk,
+                                int64_t s) {
   for (int64_t c = threadIdx.x; c < s; c += blockDim.x) {
     double a = 0.0;
     if (S.active[c]) {
@@ -609,6 +634,19 @@ __global__ void k_scal_alpha(Scal S, const double* __restrict__ dots, int nblk, 
     }
     S.alpha[c] = a;
   }
+}
+
+__global__ void k_scal_alpha(Scal S, const double* __restrict__ dots, int nblk, int64_t s) {
+  scal_alpha_body(S, dots, nblk, s);
+}
+
+// k_colsum_seg over the product's dot blocks, then (last workgroup) the
+// alpha step on the kSeg partial sums: one launch, the same sums
+__global__ __launch_bounds__(256) void k_colsum_alpha(Scal S, const double* __restrict__ parts,
+                                                      int nblk, int64_t s,
+                                                      double* __restrict__ sg, int* counter) {
+  colsum_seg_block(parts, nblk, s, sg, blockIdx.x, blockIdx.y);
+  if (last_workgroup(counter)) scal_alpha_body(S, sg, kSeg, s);
 }
 
 // r -= alpha q and y += alpha w (w = P^-1 p): y converges to M^-1 z when the
@@ -639,8 +677,9 @@ __global__ void k_update_r(T* __restrict__ r, const T* __restrict__ q, const dou
 }
 
 // rho' = r^T u (dots1), z^T r (dots2); beta; shifted recurrences; convergence.
-__global__ void k_scal_beta(Scal S, const double* __restrict__ dots1, const double* __restrict__ dots2,
-                            int nblk, int64_t s, int J, const double* __restrict__ delta, double tol) {
+__device__ void scal_beta_body(const Scal& S, const double* __restrict__ dots1,
+                               const double* __restrict__ dots2, int nblk, int64_t s, int J,
+                               const double* __restrict__ delta, double tol) {
   __shared__ int cnt;
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
@@ -690,6 +729,26 @@ __global__ void k_scal_beta(Scal S, const double* __restrict__ dots1, const doub
   atomicAdd(&cnt, mine);
   __syncthreads();
   if (threadIdx.x == 0) S.status[0] = cnt;
+}
+
+__global__ void k_scal_beta(Scal S, const double* __restrict__ dots1, const double* __restrict__ dots2,
+                            int nblk, int64_t s, int J, const double* __restrict__ delta, double tol) {
+  scal_beta_body(S, dots1, dots2, nblk, s, J, delta, tol);
+}
+
+// k_colsum_seg over both Woodbury dot arrays (blockIdx.z), then (last
+// workgroup) the beta step: one launch, the same sums
+__global__ __launch_bounds__(256) void k_colsum_beta(Scal S, const double* __restrict__ d1,
+                                                     const double* __restrict__ d2, int nblk,
+                                                     int64_t s, double* __restrict__ sg1,
+                                                     double* __restrict__ sg2, int J,
+                                                     const double* __restrict__ delta, double tol,
+                                                     int* counter) {
+  if (blockIdx.z == 0)
+    colsum_seg_block(d1, nblk, s, sg1, blockIdx.x, blockIdx.y);
+  else
+    colsum_seg_block(d2, nblk, s, sg2, blockIdx.x, blockIdx.y);
+  if (last_workgroup(counter)) scal_beta_body(S, sg1, sg2, kSeg, s, J, delta, tol);
 }
 
 template <typename T>
@@ -912,7 +971,8 @@ __global__ void k_lz_scale(T* __restrict__ a, T* __restrict__ b, const double* _
   }
 }
 
-__global__ void k_lz_alpha(Lz L, const double* __restrict__ dots, int nblk, int64_t s, int l) {
+__device__ void lz_alpha_body(const Lz& L, const double* __restrict__ dots, int nblk, int64_t s,
+                              int l) {
   for (int64_t c = threadIdx.x; c < s; c += blockDim.x) {
     if (!L.active[c]) continue;
     const double a = block_colsum(dots, nblk, s, c);
@@ -924,6 +984,15 @@ __global__ void k_lz_alpha(Lz L, const double* __restrict__ dots, int nblk, int6
     L.alpha[(int64_t)l * s + c] = a;
     L.amax[c] = fmax(L.amax[c], fabs(a));
   }
+}
+
+// column sums of the product's dot blocks, then (last workgroup) alpha_l
+__global__ __launch_bounds__(256) void k_colsum_lz_alpha(Lz L, const double* __restrict__ parts,
+                                                         int nblk, int64_t s,
+                                                         double* __restrict__ sg, int l,
+                                                         int* counter) {
+  colsum_seg_block(parts, nblk, s, sg, blockIdx.x, blockIdx.y);
+  if (last_workgroup(counter)) lz_alpha_body(L, sg, kSeg, s, l);
 }
 
 template <typename T>
@@ -939,8 +1008,8 @@ __global__ void k_lz_resid(T* __restrict__ r, const T* __restrict__ q, const T* 
   }
 }
 
-__global__ void k_lz_beta(Lz L, const double* __restrict__ d1, const double* __restrict__ d2,
-                          int nblk, int64_t s, int l) {
+__device__ void lz_beta_body(const Lz& L, const double* __restrict__ d1,
+                             const double* __restrict__ d2, int nblk, int64_t s, int l) {
   __shared__ int cnt;
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
@@ -970,6 +1039,20 @@ __global__ void k_lz_beta(Lz L, const double* __restrict__ d1, const double* __r
   atomicAdd(&cnt, mine);
   __syncthreads();
   if (threadIdx.x == 0) L.status[0] = cnt;
+}
+
+// column sums of both Woodbury dot arrays (blockIdx.z), then (last
+// workgroup) beta_l
+__global__ __launch_bounds__(256) void k_colsum_lz_beta(Lz L, const double* __restrict__ d1,
+                                                        const double* __restrict__ d2, int nblk,
+                                                        int64_t s, double* __restrict__ sg1,
+                                                        double* __restrict__ sg2, int l,
+                                                        int* counter) {
+  if (blockIdx.z == 0)
+    colsum_seg_block(d1, nblk, s, sg1, blockIdx.x, blockIdx.y);
+  else
+    colsum_seg_block(d2, nblk, s, sg2, blockIdx.x, blockIdx.y);
+  if (last_workgroup(counter)) lz_beta_body(L, sg1, sg2, kSeg, s, l);
 }
 
 // Per probe: the Thomas algorithm for (T + a_j I) w = |v| e_1 (T + a_j I is
@@ -1046,7 +1129,7 @@ ld_status lanczos_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_pr
   double* sg1 = (double*)ctx->arena.take((size_t)kSeg * s * sizeof(double));
   double* sg2 = (double*)ctx->arena.take((size_t)kSeg * s * sizeof(double));
   double* sc = (double*)ctx->arena.take(((size_t)(3 * t + 1) * s + 8 * s + 3) * sizeof(double));
-  int* isc = (int*)ctx->arena.take((size_t)(2 * s + 2) * sizeof(int));
+  int* isc = (int*)ctx->arena.take((size_t)(2 * s + 4) * sizeof(int));
   if (!q || !qp || !r || !u || !ut || !dwq || !d1 || !d2 || !sg1 || !sg2 || !sc || !isc)
     return fail(LD_ENOMEM, "lanczos: scratch arena too small");
   Lz L;
@@ -1064,8 +1147,9 @@ ld_status lanczos_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_pr
   L.steps = isc;
   L.active = isc + s;
   L.status = isc + 2 * s;
+  int* counters = L.status + 2;  // last-workgroup counters of the fused scalar steps
   LD_TRY(ensure_pinned(ctx, (size_t)(2 * s + 8)));
-  LD_HIP(hipMemsetAsync(L.status, 0, 2 * sizeof(int), st));
+  LD_HIP(hipMemsetAsync(L.status, 0, 4 * sizeof(int), st));
   LD_HIP(hipMemsetAsync(qp, 0, vec * sizeof(T), st));
   const size_t mark = ctx->arena.top;
   const dim3 cs_grid((unsigned)((s + 63) / 64), kSeg);
@@ -1095,15 +1179,14 @@ ld_status lanczos_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_pr
     int nb = 0;
     a.dot_blocks = &nb;
     LD_TRY(matmat(ctx, f64, a));
-    hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, dwq, nb, s, sg1);
-    hipLaunchKernelGGL(k_lz_alpha, dim3(1), dim3(256), 0, st, L, sg1, kSeg, s, l);
+    hipLaunchKernelGGL(k_colsum_lz_alpha, cs_grid, dim3(256), 0, st, L, dwq, nb, s, sg1, l,
+                       counters);
     hipLaunchKernelGGL(k_lz_resid<T>, dim3(grid1(vec)), dim3(256), 0, st, r, q, qp,
                        L.alpha + (size_t)l * s, L.bprev, L.active, n, s);
     ctx->arena.top = mark;
     LD_TRY(wood_apply_t<T>(ctx, P, r, s, ut, Z, d1, d2));
-    hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, d1, (int)wrt, s, sg1);
-    hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, d2, (int)wrt, s, sg2);
-    hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(256), 0, st, L, sg1, sg2, kSeg, s, l);
+    hipLaunchKernelGGL(k_colsum_lz_beta, dim3(cs_grid.x, cs_grid.y, 2), dim3(256), 0, st, L, d1,
+                       d2, (int)wrt, s, sg1, sg2, l, counters + 1);
     hipLaunchKernelGGL(k_lz_scale<T>, dim3(grid1(vec)), dim3(256), 0, st, r, ut, L.inv, L.active,
                        n, s);
     LD_HIP(hipGetLastError());
@@ -1174,7 +1257,7 @@ size_t lanczos_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int rank, int64_t
   size_t b = 5 * (size_t)n * s * es + 1280;
   b += ((n + kEpiRows - 1) / kEpiRows * kEpiSplitMax + 2 * ((n + 63) / 64)) * (size_t)s * 8 + 768;
   b += 2 * (size_t)kSeg * s * 8 + 512;
-  b += ((size_t)(3 * t + 1) * s + 8 * s + 3) * 8 + (size_t)(2 * s + 2) * 4 + 512;
+  b += ((size_t)(3 * t + 1) * s + 8 * s + 3) * 8 + (size_t)(2 * s + 4) * 4 + 512;
   b += std::max(matmat_scratch_bytes(ctx, f64, n, s), woodbury_scratch_bytes(n, rank, s)) + 1024;
   return b;
 }
@@ -1275,7 +1358,7 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
   double* d1 = (double*)ctx->arena.take((size_t)wrt * s * sizeof(double));
   double* d2 = (double*)ctx->arena.take((size_t)wrt * s * sizeof(double));
   double* scal = (double*)ctx->arena.take((size_t)(7 * s + 4 * J * s + J) * sizeof(double));
-  int* iscal = (int*)ctx->arena.take((size_t)(J * s + s + 2) * sizeof(int));
+  int* iscal = (int*)ctx->arena.take((size_t)(J * s + s + 4) * sizeof(int));
   double* sg1 = (double*)ctx->arena.take((size_t)kSeg * s * sizeof(double));
   double* sg2 = (double*)ctx->arena.take((size_t)kSeg * s * sizeof(double));
   double* hut = (double*)ctx->arena.take((size_t)ncf * (s + 2) * sizeof(double));
@@ -1297,13 +1380,14 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
   S.frozen = iscal;
   S.active = iscal + J * s;
   S.status = iscal + J * s + s;
+  int* counters = S.status + 2;  // last-workgroup counters of the fused scalar steps
 
   std::vector<double> dl(J);
   for (int j = 0; j < J; ++j) dl[j] = shifts[j] - shifts[0];
   LD_TRY(ensure_pinned(ctx, (size_t)(2 * J * s + (ncf + 2) * s + 2 * ncf + 8)));
   std::copy(dl.begin(), dl.end(), ctx->pinned);
   LD_HIP(hipMemcpyAsync(delta, ctx->pinned, J * sizeof(double), hipMemcpyHostToDevice, st));
-  LD_HIP(hipMemsetAsync(S.status, 0, 2 * sizeof(int), st));
+  LD_HIP(hipMemsetAsync(S.status, 0, 4 * sizeof(int), st));
   // wait for the small upload before the pinned buffer is reused below
   LD_HIP(hipStreamSynchronize(st));
 
@@ -1341,8 +1425,7 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
     int nb = 0;
     a.dot_blocks = &nb;
     LD_TRY(matmat(ctx, f64, a));
-    hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, dwq, nb, s, sg1);
-    hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(256), 0, st, S, sg1, kSeg, s);
+    hipLaunchKernelGGL(k_colsum_alpha, cs_grid, dim3(256), 0, st, S, dwq, nb, s, sg1, counters);
     if (ysol)
       hipLaunchKernelGGL(k_update_ry<T>, dim3(grid1(vec)), dim3(256), 0, st, r, q, ysol, w,
                          S.alpha, n, s);
@@ -1350,10 +1433,8 @@ ld_status pcg_run(ld_ctx* ctx, bool f64, const MatmatArgs& base, const ld_precon
       hipLaunchKernelGGL(k_update_r<T>, dim3(grid1(vec)), dim3(256), 0, st, r, q, S.alpha, n, s);
     ctx->arena.top = mark;
     LD_TRY(wood_apply_t<T>(ctx, P, r, s, u, Z, d1, d2));
-    hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, d1, (int)wrt, s, sg1);
-    hipLaunchKernelGGL(k_colsum_seg, cs_grid, dim3(256), 0, st, d2, (int)wrt, s, sg2);
-    hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(256), 0, st, S, sg1, sg2, kSeg, s, J, delta,
-                       tol);
+    hipLaunchKernelGGL(k_colsum_beta, dim3(cs_grid.x, cs_grid.y, 2), dim3(256), 0, st, S, d1, d2,
+                       (int)wrt, s, sg1, sg2, J, delta, tol, counters + 1);
     hipLaunchKernelGGL(k_update_pw<T>, dim3(grid1(vec)), dim3(256), 0, st, p, w, r, u, S.beta,
                        S.active, n, s);
     LD_HIP(hipGetLastError());
@@ -1481,7 +1562,7 @@ size_t pcg_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int rank, int64_t s, 
   const size_t es = f64 ? 8 : 4;
   size_t b = 5 * (size_t)n * s * es + 1280;
   b += ((n + kEpiRows - 1) / kEpiRows * kEpiSplitMax + 2 * ((n + 63) / 64)) * (size_t)s * 8 + 768;
-  b += (size_t)(7 * s + 4 * J * s + J) * 8 + (size_t)(J * s + s + 2) * 4 + 512;
+  b += (size_t)(7 * s + 4 * J * s + J) * 8 + (size_t)(J * s + s + 4) * 4 + 512;
   b += 2 * (size_t)kSeg * s * 8 + 3 * (size_t)(s + 2) * 8 + 768;   // up to 3 estimates
   b += std::max(matmat_scratch_bytes(ctx, f64, n, s), woodbury_scratch_bytes(n, rank, s)) + 1024;
   return b;

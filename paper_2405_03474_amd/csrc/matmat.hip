@@ -1268,7 +1268,26 @@ __global__ __launch_bounds__(256) void k_epilogue(const T* __restrict__ part, SK
   double sum[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) sum[j] = 0.0;
-  for (int q = 0; q < ns; ++q) {
+  // four slots' loads in flight at a time (the partial tiles were written by
+  // other XCDs, so each load goes past this XCD's L2); added in slot order
+  int q = 0;
+  for (; q + 4 <= ns; q += 4) {
+    T v[4][8];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const T* src = part + slot[q + u] + e0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = tid + 256 * j;
+        v[u][j] = e < cnt ? src[e] : (T)0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sum[j] += (double)v[u][j];
+  }
+  for (; q < ns; ++q) {
     const T* src = part + slot[q] + e0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {

@@ -461,8 +461,10 @@ typedef struct {
  *   lambda_out  host array of count * lambda_stride doubles receiving each
  *               instance's kept eigenvalues (rank_i values, descending, rest
  *               of the row zero), or NULL; lambda_stride >= max rank_i
- * The product kernel's tile shape (4 or 2 waves per workgroup) is timed on
- * the first call and kept in the context.  Synchronizes. */
+ * The product kernel's tile shape (matrix-core shape, column blocks, 4 or 2
+ * waves per workgroup: up to four candidates for the probe count) is timed
+ * on the first call for a probe count and kept in the context.
+ * Synchronizes. */
 ld_status logdet_estimate_batched(ld_ctx* ctx, int32_t count, const ld_instance* instances,
                                   int32_t k, int32_t num_probes, int32_t oversample,
                                   int32_t power_iters, double tol, int32_t max_iters,

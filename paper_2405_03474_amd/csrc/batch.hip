@@ -7,8 +7,9 @@
 //  - kernel-matrix products: one workgroup per (instance, row block, column
 //    block), launched in decreasing n (longest first), each running the full
 //    k range on FP32 matrix cores and applying the epilogue itself, so no
-//    partial sums leave the workgroup; two tile shapes (4 or 2 waves) are
-//    timed once and the faster one is kept (autotuner);
+//    partial sums leave the workgroup; the candidate tile shapes (matrix-core
+//    shape, column blocks, 4 or 2 waves) are timed once per context and the
+//    fastest is kept (autotuner);
 //  - preconditioner: batched range finder, CholeskyQR, Rayleigh-Ritz with
 //    one-workgroup-per-instance Cholesky and triangular inverse
 //    (dense_dev.hpp) and a Householder + implicit QL eigen-solver, Woodbury
@@ -976,13 +977,14 @@ __global__ __launch_bounds__(256) void k_bsegsum(const BInst* __restrict__ inst,
 // Vector updates over the whole batch; padding rows are left at zero.
 __global__ void k_bupdate_r(const BInst* __restrict__ inst, const int* __restrict__ blk_inst,
                             int64_t R, int s, float* __restrict__ r, const float* __restrict__ q,
-                            const double* __restrict__ alpha) {
+                            const double* __restrict__ alpha, const int* __restrict__ iact) {
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < R * s;
        e += (int64_t)gridDim.x * 256) {
     const int64_t row = e / s;
     const int c = (int)(e % s);
     const int ii = blk_inst[row / BLK];
-    if (row - inst[ii].row0 >= inst[ii].n) continue;
+    // a converged instance has alpha = 0 in every column: r is unchanged
+    if (!iact[ii] || row - inst[ii].row0 >= inst[ii].n) continue;
     const double a = alpha[(int64_t)ii * s + c];
     r[e] = (float)((double)r[e] - a * (double)q[e]);
   }
@@ -991,13 +993,16 @@ __global__ void k_bupdate_r(const BInst* __restrict__ inst, const int* __restric
 __global__ void k_bupdate_pw(const BInst* __restrict__ inst, const int* __restrict__ blk_inst,
                              int64_t R, int s, float* __restrict__ p, float* __restrict__ w,
                              const float* __restrict__ r, const float* __restrict__ u,
-                             const double* __restrict__ beta, const int* __restrict__ active) {
+                             const double* __restrict__ beta, const int* __restrict__ active,
+                             const int* __restrict__ iact) {
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < R * s;
        e += (int64_t)gridDim.x * 256) {
     const int64_t row = e / s;
     const int c = (int)(e % s);
     const int ii = blk_inst[row / BLK];
-    if (row - inst[ii].row0 >= inst[ii].n) continue;
+    // iact (from the start of the iteration) is 0 only when every column of
+    // the instance was already inactive
+    if (!iact[ii] || row - inst[ii].row0 >= inst[ii].n) continue;
     const int64_t g = (int64_t)ii * s + c;
     if (!active[g]) continue;
     const double b = beta[g];
@@ -1098,22 +1103,26 @@ struct ProductPlan {
   int nb = 1;     // column sub-blocks: NT = mf * nb columns per workgroup
 };
 
-// Tile shape for ncols columns: the narrowest block that covers them (at most
-// 224 columns; wider blocks repeat).  variant 1 (2 waves) exists for blocks of
-// at most 64 columns.
+// The product tile shapes the autotuner times for ncols columns: matrix-core
+// shape (16x16x4 or 32x32x2), column sub-blocks and waves per workgroup (4
+// waves: 128 rows, 2 waves: 64 rows, which doubles the work items and evens
+// out the tail of small instances).  Every candidate covers ncols (at most
+// 224 columns per block; wider products repeat the block).
+struct Shape {
+  int mf, nb, waves;
+};
+std::vector<Shape> product_shapes(int ncols) {
+  if (ncols <= 16) return {{16, 1, 4}, {16, 1, 2}, {32, 1, 4}, {32, 1, 2}};
+  if (ncols <= 32) return {{32, 1, 4}, {32, 1, 2}, {32, 2, 4}, {32, 2, 2}};
+  if (ncols <= 64) return {{32, 2, 4}, {32, 2, 2}, {32, 4, 4}};
+  if (ncols <= 128) return {{32, 4, 4}, {32, 7, 4}};
+  return {{32, 7, 4}};
+}
+
 ld_status plan_product(ld_ctx* ctx, const Batch& b, int ncols, int variant, ProductPlan* pp) {
-  int mf = 32, nb = 7;
-  if (ncols <= 16) {
-    mf = 16;
-    nb = 1;
-  } else if (ncols <= 32) {
-    nb = 1;
-  } else if (ncols <= 64) {
-    nb = 2;
-  } else if (ncols <= 128) {
-    nb = 4;
-  }
-  const int waves = (variant == 1 && mf * nb <= 64) ? 2 : 4;
+  const std::vector<Shape> shapes = product_shapes(ncols);
+  const Shape sh = shapes[variant < (int)shapes.size() ? variant : 0];
+  const int mf = sh.mf, nb = sh.nb, waves = sh.waves;
   std::vector<BItem> items = make_items(b, 32 * waves, ncols, mf * nb);
   pp->d_items = (BItem*)ctx->arena.take(items.size() * sizeof(BItem));
   if (!pp->d_items) return fail(LD_ENOMEM, "batch: scratch arena too small for work items");
@@ -1145,6 +1154,7 @@ void launch_product(hipStream_t st, const Batch& b, const ProductPlan& pp, const
   } else {
     LD_BMM_LAUNCH(32, 7, 4);
   }
+  // (plan_product only produces the shapes above: product_shapes)
 #undef LD_BMM_LAUNCH
 }
 
@@ -1305,8 +1315,9 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
   add(B * 4);
   add(2 * 8);
   add(b.nblk * (size_t)cbs * sizeof(BItem));  // product work items: sketch
-  add(b.nblk * sizeof(BItem));                // solver, 128-row shape
-  add(b.nblk * sizeof(BItem));                // solver, 64-row shape
+  // solver: the autotuner's candidate shapes (at most four, each at most
+  // one item per 64-row block and 16 columns)
+  for (int q = 0; q < 4; ++q) add(b.nblk * (size_t)((s + 15) / 16) * sizeof(BItem));
   ctx->arena.reset();
   LD_TRY(ctx->arena.reserve(need));
   Arena& ar = ctx->arena;
@@ -1517,17 +1528,19 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
                      S.active, iact);
   LD_HIP(hipGetLastError());
 
-  // product tile shape: both shapes are timed once per context (or on request)
-  ProductPlan pv[2];
-  LD_TRY(with_stream(ctx, st, b, s, 0, &pv[0]));
-  LD_TRY(with_stream(ctx, st, b, s, 1, &pv[1]));
-  if (ctx->bvariant < 0 || (flags & LD_BATCH_RETUNE)) {
+  // product tile shape (autotuner): every candidate shape for s columns is
+  // timed once per context (or on request) on this batch's first product,
+  // and the fastest is kept
+  const int nshape = (int)product_shapes(s).size();
+  ProductPlan pv[4];
+  for (int v = 0; v < nshape; ++v) LD_TRY(with_stream(ctx, st, b, s, v, &pv[v]));
+  if (ctx->bvariant < 0 || ctx->bvariant_cols != s || (flags & LD_BATCH_RETUNE)) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     LD_HIP(hipEventCreate(&e0));
     LD_HIP(hipEventCreate(&e1));
     float best = 1e30f;
     int pick = 0;
-    for (int v = 0; v < 2; ++v) {
+    for (int v = 0; v < nshape; ++v) {
       float tot = 0.f;
       for (int rep = 0; rep < 3; ++rep) {
         float ms = 0.f;
@@ -1547,6 +1560,7 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
     (void)hipEventDestroy(e1);
     LD_HIP(hipGetLastError());
     ctx->bvariant = pick;
+    ctx->bvariant_cols = s;
   }
   const ProductPlan& pp = pv[ctx->bvariant];
   // Instrumentation (ctx->timing, eager form only): events around every
@@ -1566,13 +1580,13 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
     hipLaunchKernelGGL(k_bsegsum, dim3(B), dim3(256), 0, st, b.d_inst, s, dwq, sgw);
     launch_scal_alpha(st, S, sgw, 1, ncol);
     hipLaunchKernelGGL(k_bupdate_r, dim3(grid1(vec)), dim3(256), 0, st, b.d_inst, b.d_blk_inst, R,
-                       s, r, q, S.alpha);
+                       s, r, q, S.alpha, iact);
     woodbury(r, u, iact);
     hipLaunchKernelGGL(k_bsegsum, dim3(B), dim3(256), 0, st, b.d_inst, s, d1, sg1);
     hipLaunchKernelGGL(k_bsegsum, dim3(B), dim3(256), 0, st, b.d_inst, s, d2, sg2);
     launch_scal_beta(st, S, sg1, sg2, 1, ncol, J, delta, tol);
     hipLaunchKernelGGL(k_bupdate_pw, dim3(grid1(vec)), dim3(256), 0, st, b.d_inst, b.d_blk_inst, R,
-                       s, p, w, r, u, S.beta, S.active);
+                       s, p, w, r, u, S.beta, S.active, iact);
     hipLaunchKernelGGL(k_binst_active, dim3((count + 255) / 256), dim3(256), 0, st, count, s,
                        S.active, iact);
     return LD_OK;

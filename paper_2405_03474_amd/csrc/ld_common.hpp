@@ -86,6 +86,7 @@ struct ld_ctx {
   hipStream_t side = nullptr;
   hipEvent_t ev_join = nullptr;
   int bvariant = -1;
+  int bvariant_cols = -1;  // the column count bvariant was chosen for
   // probe distribution of the single-problem estimators (ld_probe_kind)
   int probe_kind = 0;
   // this device's static scratch (kernel_matmat_noalloc), set at creation

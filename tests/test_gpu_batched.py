@@ -199,6 +199,16 @@ def test_batched_full_c4_sampled(ctx):
     for i in order[:8]:
         strict += check_instance(insts[i], res[i], per[i], 3, 16)
     assert strict >= 5  # enough well-posed instances among the sampled
+    # the five instances farthest from their exact log det (R11 error rule:
+    # 17-104% here, the bias of r_3 on the spread spectra of short-lengthscale
+    # problems at rank min(200, n/10)) are oracle-matching too
+    for i in WORST_VS_EXACT:
+        check_instance(insts[i], res[i], per[i], 3, 16)
+
+
+# Indices of the five c4 instances with the largest error against the exact
+# log det in a measured batched run (n = 589, 6,407, 4,259, 3,304, 6,073).
+WORST_VS_EXACT = (22, 90, 244, 10, 145)
 
 
 def test_precond_only_and_eigenvalues(ctx):

@@ -474,20 +474,58 @@ def surrogate_main(args, torch, L):
     stream = torch.cuda.current_stream(0)
     ctx = L.Context(0, stream)
     cfg = sweep.Config()
-    if args.c5_train_family == "grid":
-        train_insts = workloads.surrogate_family_instances(args.c5_train_count, args.c5_train_n)
-    else:
-        train_insts = workloads.surrogate_training_instances(args.c5_train_count, args.c5_train_n)
-    grid = workloads.surrogate_grid(args.c5_eval_n, side=args.c5_side)
-    log(f"[bench] c5: {len(train_insts)} training problems at n={args.c5_train_n}, "
-        f"{len(grid)} grid points at n={args.c5_eval_n}")
+    if args.c5_chunk:
+        cfg.chunk = args.c5_chunk
+    rank = args.c5_rank or None
+
+    def training_set(start, count):
+        if args.c5_train_family == "grid":
+            assert start == 0, "--c5-train-start needs the batched family"
+            return workloads.surrogate_family_instances(count, args.c5_train_n)
+        return workloads.surrogate_training_instances(count, args.c5_train_n, rank=rank,
+                                                      start=start)
+
+    grid = workloads.surrogate_grid(args.c5_eval_n, side=args.c5_side, rank=rank)
     t0 = time.perf_counter()
-    res, lams, _ = sweep.estimate_all(ctx, train_insts, cfg, torch)
-    t_gen = time.perf_counter() - t0
-    ok = [i for i, r in enumerate(res) if r["converged_cols"] == cfg.probes]
-    train_used = [train_insts[i] for i in ok]
-    lams = [lams[i] for i in ok]
-    y = np.array([(res[i]["logdet"] - res[i]["logdet_P"]) / train_insts[i].n for i in ok])
+    if args.c5_data_in:
+        # training targets generated earlier by --c5-data-out runs (the same
+        # estimator on the same seeded problems)
+        train_used, lams, y, t_gen = [], [], [], 0.0
+        for path in args.c5_data_in.split(","):
+            z = np.load(path)
+            part = training_set(int(z["start"]), len(z["y"]))
+            keep = z["converged"].astype(bool)
+            train_used += [g for g, k in zip(part, keep) if k]
+            lams += [row[:g.rank].astype(np.float64) for row, g, k in zip(z["lam"], part, keep) if k]
+            y += [v for v, k in zip(z["y"], keep) if k]
+            t_gen += float(z["seconds"])
+        y = np.array(y)
+        train_count = len(y)
+        log(f"[bench] c5: {train_count} converged training problems loaded")
+    else:
+        train_insts = training_set(args.c5_train_start, args.c5_train_count)
+        train_count = len(train_insts)
+        log(f"[bench] c5: {len(train_insts)} training problems at n={args.c5_train_n}, "
+            f"{len(grid)} grid points at n={args.c5_eval_n}")
+        res, lams, _ = sweep.estimate_all(ctx, train_insts, cfg, torch, log=log)
+        t_gen = time.perf_counter() - t0
+        ok = [i for i, r in enumerate(res) if r["converged_cols"] == cfg.probes]
+        yall = np.array([(r["logdet"] - r["logdet_P"]) / g.n for r, g in zip(res, train_insts)])
+        if args.c5_data_out:
+            lam_rows = np.zeros((len(res), max(g.rank for g in train_insts)), dtype=np.float32)
+            for i, l in enumerate(lams):
+                lam_rows[i, :len(l)] = l
+            conv = np.array([r["converged_cols"] == cfg.probes for r in res])
+            np.savez(args.c5_data_out, start=args.c5_train_start, y=yall, lam=lam_rows,
+                     converged=conv, seconds=t_gen)
+            print(json.dumps({"c5_training_data": args.c5_data_out, "start": args.c5_train_start,
+                              "count": len(res), "converged": int(conv.sum()),
+                              "train_n": args.c5_train_n, "seconds": t_gen}), flush=True)
+            ctx.close()
+            return
+        train_used = [train_insts[i] for i in ok]
+        lams = [lams[i] for i in ok]
+        y = yall[ok]
     edges = sweep.feature_edges(lams, train_used)
     F = sweep.features(lams, train_used, edges)
     log(f"[bench] training data {t_gen:.2f} s")
@@ -504,40 +542,65 @@ def surrogate_main(args, torch, L):
     t_train = time.perf_counter() - t0
     log(f"[bench] training {t_train:.2f} s, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
 
-    # plain estimator on every grid point (error reference and the comparison);
-    # kernel events around its products give the roofline
-    ctx.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plain, _, items = sweep.estimate_all(ctx, grid, cfg, torch)
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    mm_ms, mm_calls, mm_flops, mm_bytes = ctx.read_timing()
-    ctx.set_timing(False)
-    log(f"[bench] plain sweep {t_plain:.2f} s")
-    for w in range(args.warmup):
-        sweep.sweep(ctx, S, grid, edges, cfg, torch, items=items)
-    times = []
-    for i in range(args.steps):
+    if args.c5_split_timing:
+        # one surrogate sweep, then the plain estimator on the points that did
+        # not fall back: the fallback estimates are the plain estimator's own
+        # values on those points, so every point is estimated once and the
+        # plain sweep's time is the fallback time plus the rest (two batched
+        # calls instead of one); kernel events over the whole give the roofline
+        ctx.set_timing(True)
         torch.cuda.synchronize()
-        logdet, fb, stages, _ = sweep.sweep(ctx, S, grid, edges, cfg, torch, items=items)
+        logdet, fb, stages, items = sweep.sweep(ctx, S, grid, edges, cfg, torch,
+                                                score_rest=True, log=log)
         torch.cuda.synchronize()
+        mm_ms, mm_calls, mm_flops, mm_bytes = ctx.read_timing()
+        ctx.set_timing(False)
         predicted, spread = stages.pop("predicted"), stages.pop("spread")
-        times.append(stages)
-        log(f"[bench] surrogate sweep {i}: {stages}")
+        plain = stages.pop("rest_plain")
+        t_plain = stages["fallback"] + stages["rest_seconds"]
+        times = [stages]
+        log(f"[bench] surrogate sweep: {stages}")
+    else:
+        # plain estimator on every grid point (error reference and the
+        # comparison); kernel events around its products give the roofline
+        ctx.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain, _, items = sweep.estimate_all(ctx, grid, cfg, torch, log=log)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        mm_ms, mm_calls, mm_flops, mm_bytes = ctx.read_timing()
+        ctx.set_timing(False)
+        log(f"[bench] plain sweep {t_plain:.2f} s")
+        for w in range(args.warmup):
+            sweep.sweep(ctx, S, grid, edges, cfg, torch, items=items)
+        times = []
+        for i in range(args.steps):
+            torch.cuda.synchronize()
+            logdet, fb, stages, _ = sweep.sweep(ctx, S, grid, edges, cfg, torch, items=items)
+            torch.cuda.synchronize()
+            predicted, spread = stages.pop("predicted"), stages.pop("spread")
+            times.append(stages)
+            log(f"[bench] surrogate sweep {i}: {stages}")
     t_sur = float(np.mean([st["total"] for st in times]))
     ref = np.array([r["logdet"] for r in plain])
-    plain_unconverged = int(sum(r["converged_cols"] < cfg.probes for r in plain))
+    # points where the plain FP32 estimator itself did not converge (a solver
+    # breakdown: smooth kernels with tiny noise are not numerically positive
+    # definite in FP32 products) cannot score a prediction
+    valid = np.array([r["converged_cols"] == cfg.probes for r in plain])
+    plain_unconverged = int((~valid).sum())
     if args.dump:
         Fg = sweep.features(sweep.estimate_all(ctx, grid, cfg, torch, precond_only=True,
                                                items=items)[1], grid, edges)
         np.savez(args.dump, F_train=F, y_train=y, F_grid=Fg, predicted=predicted, spread=spread,
                  ref=ref, logdet_P=np.array([r["logdet_P"] for r in plain]),
                  n_grid=np.array([g.n for g in grid]), edges=edges,
-                 logdet_train=np.array([res[i]["logdet"] for i in ok]),
-                 n_train=np.array([train_insts[i].n for i in ok]))
-    rel = np.abs(logdet - ref) / np.abs(ref)
-    rel_pred = np.abs(predicted - ref) / np.abs(ref)
+                 n_train=np.array([g.n for g in train_used]))
+    rel = (np.abs(logdet - ref) / np.abs(ref))[valid]
+    rel_pred = (np.abs(predicted - ref) / np.abs(ref))[valid]
+    fbv = fb[valid]
+    spread = spread[valid]
+    ref_v = ref[valid]
     avg_ms = mm_ms / max(mm_calls, 1)
     achieved = (mm_flops / max(mm_calls, 1)) / (avg_ms / 1e3) if mm_calls else 0.0
     line = {
@@ -546,24 +609,25 @@ def surrogate_main(args, torch, L):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
         "data": "synthetic",
         "config": {"workload": "c5_surrogate", "train_n": args.c5_train_n,
-                   "train_count": len(train_insts), "train_converged": len(ok),
+                   "train_count": train_count, "train_converged": len(y),
                    "train_family": args.c5_train_family,
                    "eval_n": args.c5_eval_n,
                    "grid": f"{args.c5_side}x{args.c5_side}", "order": cfg.k, "probes": cfg.probes,
-                   "rank": "n/40", "members": 5, "epochs": args.c5_epochs,
+                   "rank": args.c5_rank or "n/40", "members": 5, "epochs": args.c5_epochs,
                    "fallback_rel_tol": cfg.rel_tol, "spread_multiplier": cfg.kappa},
         "plain_estimator": {"value": len(grid) / t_plain, "seconds": t_plain,
                             "unconverged": plain_unconverged},
         "speedup_vs_plain": t_plain / t_sur,
         "stages_s": times[-1],
         "fallbacks": int(fb.sum()),
-        "error_vs_plain": {"max_rel": float(rel.max()), "median_rel": float(np.median(rel)),
+        "error_vs_plain": {"scored_points": int(valid.sum()),
+                           "max_rel": float(rel.max()), "median_rel": float(np.median(rel)),
                            "within_1e-3": int((rel <= 1e-3).sum()),
-                           "max_rel_predicted": float(rel[~fb].max()) if (~fb).any() else None},
+                           "max_rel_predicted": float(rel[~fbv].max()) if (~fbv).any() else None},
         "ensemble_only_error_vs_plain": {
             "median_rel": float(np.median(rel_pred)), "p90_rel": float(np.quantile(rel_pred, 0.9)),
             "within_1e-3": int((rel_pred <= 1e-3).sum()), "within_1e-2": int((rel_pred <= 1e-2).sum()),
-            "median_rel_spread": float(np.median(spread / np.abs(ref)))},
+            "median_rel_spread": float(np.median(spread / np.abs(ref_v)))},
         "training": {"data_seconds": t_gen, "train_seconds": t_train, "loss_first": hist[0],
                      "loss_last": hist[-1]},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12,
@@ -581,11 +645,18 @@ def surrogate_main(args, torch, L):
     ctx.close()
 
 
-def surrogate_cpu_baseline(grid, cfg, count):
-    """The oracle estimator on a few grid points, scaled to the whole grid."""
+def surrogate_cpu_baseline(grid, cfg, count, max_n=4000):
+    """The oracle estimator on a few grid points, scaled to the whole grid;
+    grid points larger than max_n are sampled at max_n (same recipe, rank
+    scaled with n) and the time scaled by (n / max_n)^3."""
     from oracle import estimate as oest
     from oracle import gp, precond
     pick = grid[:: max(1, len(grid) // max(1, min(count, 3)))][:3]
+    n_full = pick[0].n
+    scale = 1.0
+    if n_full > max_n:
+        pick = [g.with_n(max_n, rank=max(1, g.rank * max_n // n_full)) for g in pick]
+        scale = (n_full / max_n) ** 3
     t0 = time.perf_counter()
     for g in pick:
         M = gp.dense_matrix(g.kind, g.X(), g.lengthscale, g.variance, g.noise)
@@ -594,10 +665,11 @@ def surrogate_cpu_baseline(grid, cfg, count):
         oest.estimate_dense(M, P.dense(), P.logdet, cfg.k, oest.probes(g.probe_seed, g.n, cfg.probes))
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": len(pick) / dt, "unit": "log-det estimates/s", "cores": threads,
+    return {"value": len(pick) / (dt * scale), "unit": "log-det estimates/s", "cores": threads,
             "kind": "oracle",
             "sample": f"oracle (FP64, dense Cholesky shifted solves) on {len(pick)} grid points "
-                      f"at n={pick[0].n}: {dt:.2f} s"}
+                      f"at n={pick[0].n} (rank {pick[0].rank}): {dt:.2f} s"
+                      + (f", scaled to n={n_full} by (n/{max_n})^3" if scale != 1.0 else "")}
 
 
 def exact_logdet_stored(ctx, op):
@@ -719,6 +791,18 @@ def main():
     ap.add_argument("--c5-eval-n", type=int, default=5000)
     ap.add_argument("--c5-side", type=int, default=32)
     ap.add_argument("--c5-epochs", type=int, default=300)
+    ap.add_argument("--c5-rank", type=int, default=0,
+                    help="preconditioner rank of the training and grid problems (default n/40)")
+    ap.add_argument("--c5-chunk", type=int, default=0, help="problems per batched call")
+    ap.add_argument("--c5-train-start", type=int, default=0,
+                    help="first training problem of the seeded sequence")
+    ap.add_argument("--c5-data-out", default="",
+                    help="only generate the training targets and eigenvalues and save them here")
+    ap.add_argument("--c5-split-timing", action="store_true",
+                    help="estimate every grid point once: the surrogate sweep, then the plain "
+                         "estimator on the points that did not fall back (large n)")
+    ap.add_argument("--c5-data-in", default="",
+                    help="comma-separated files from --c5-data-out to train on")
     ap.add_argument("--c5-calibrate", action="store_true",
                     help="scale the ensemble spread by a factor calibrated on held-out "
                          "training problems before the fallback test")

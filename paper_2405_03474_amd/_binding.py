@@ -521,9 +521,12 @@ class BatchItem:
 def logdet_estimate_batched(ctx: Context, items, k: int, num_probes: int, oversample: int = 10,
                             power_iters: int = 2, tol: float = 1e-6, max_iters: int = 5000,
                             graph: bool = False, retune: bool = False, allow_noconv: bool = False,
-                            precond_only: bool = False, want_lambda: bool = False):
+                            precond_only: bool = False, want_lambda: bool = False,
+                            allow_breakdown: bool = False):
     """Returns (list of result dicts, per-probe values (count, num_probes), status name), and
-    with want_lambda also the kept eigenvalues (count, max rank), zero-padded."""
+    with want_lambda also the kept eigenvalues (count, max rank), zero-padded.  With
+    allow_breakdown a solver breakdown (LD_ENOTSPD: the results are still filled, the broken
+    probes counted as not converged) is returned instead of raised."""
     torch = _torch()
     count = len(items)
     arr = (Instance * count)()
@@ -544,7 +547,8 @@ def logdet_estimate_batched(ctx: Context, items, k: int, num_probes: int, oversa
                                         power_iters, tol, max_iters, flags, res,
                                         per.ctypes.data_as(pd),
                                         lam.ctypes.data_as(pd) if want_lambda else None, stride)
-    _check(st, allow=(LD_ENOCONV,) if allow_noconv else ())
+    allow = ((LD_ENOCONV,) if allow_noconv else ()) + ((LD_ENOTSPD,) if allow_breakdown else ())
+    _check(st, allow=allow)
     out = ([r.as_dict() for r in res[:count]], per[:count], STATUS_NAMES.get(st, st))
     return out + (lam[:count],) if want_lambda else out
 

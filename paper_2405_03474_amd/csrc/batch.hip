@@ -1011,6 +1011,51 @@ __global__ void k_bupdate_pw(const BInst* __restrict__ inst, const int* __restri
   }
 }
 
+// Hutchinson combination of every instance on the device, in FP64: per probe
+// t_c = b z^T z + sum_j c_j z^T x_j (the estimator's output, Algorithm 1),
+// then the instance's mean, standard error (sample deviation over sqrt(s)),
+// largest P^-1 residual ratio of its seed systems and converged count.  One
+// workgroup of 64 threads per instance (s <= 64), sums in probe order.
+struct BCoef {
+  double b;
+  double c[kMaxShifts];
+  int J;
+};
+__global__ __launch_bounds__(64) void k_bhutchinson(int s, int64_t ncol, BCoef cf,
+                                                    const double* __restrict__ ztx,
+                                                    const double* __restrict__ ztz,
+                                                    const double* __restrict__ rho,
+                                                    const double* __restrict__ rho0, double tol,
+                                                    double* __restrict__ per_probe,
+                                                    double* __restrict__ stats) {
+  __shared__ double tt[64], rr[64];
+  const int i = blockIdx.x, c = threadIdx.x;
+  if (c < s) {
+    const int64_t g = (int64_t)i * s + c;
+    double v = cf.b * ztz[g];
+    for (int j = 0; j < cf.J; ++j) v += cf.c[j] * ztx[(int64_t)j * ncol + g];
+    tt[c] = v;
+    rr[c] = sqrt(fmax(0.0, rho[g] / rho0[g]));
+    per_probe[g] = v;
+  }
+  __syncthreads();
+  if (c == 0) {
+    double mean = 0.0, worst = 0.0, conv = 0.0;
+    for (int q = 0; q < s; ++q) {
+      mean += tt[q];
+      worst = fmax(worst, rr[q]);
+      if (rr[q] <= tol) conv += 1.0;
+    }
+    mean /= s;
+    double var = 0.0;
+    for (int q = 0; q < s; ++q) var += (tt[q] - mean) * (tt[q] - mean);
+    stats[4 * i + 0] = mean;
+    stats[4 * i + 1] = s > 1 ? sqrt(var / (s - 1) / s) : (double)NAN;
+    stats[4 * i + 2] = worst;
+    stats[4 * i + 3] = conv;
+  }
+}
+
 // iact[i] = 1 while any probe column of instance i is still active
 __global__ void k_binst_active(int B, int s, const int* __restrict__ active, int* __restrict__ iact) {
   for (int i = blockIdx.x * 256 + threadIdx.x; i < B; i += gridDim.x * 256) {
@@ -1314,6 +1359,7 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
   add((size_t)(J * ncol + ncol + 2) * 4);
   add(B * 4);
   add(2 * 8);
+  add((size_t)(ncol + 4 * B) * 8);
   add(b.nblk * (size_t)cbs * sizeof(BItem));  // product work items: sketch
   // solver: the autotuner's candidate shapes (at most four, each at most
   // one item per 64-row block and 16 columns)
@@ -1363,6 +1409,7 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
   int* iscal = (int*)tk((size_t)(J * ncol + ncol + 2) * 4);
   int* iact = (int*)tk(B * 4);
   double* tacc = (double*)tk(2 * 8);
+  double* hut = (double*)tk((size_t)(ncol + 4 * count) * 8);  // per-probe values, statistics
   if (!tacc) return fail(LD_ENOMEM, "batch: scratch arena too small");
 
   // the graph form runs on a side stream that joins the context stream
@@ -1503,7 +1550,7 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
   S.frozen = iscal;
   S.active = iscal + J * ncol;
   S.status = iscal + J * ncol + ncol;
-  LD_TRY(ensure_pinned(ctx, (size_t)(J * ncol + 3 * ncol + 16)));
+  LD_TRY(ensure_pinned(ctx, (size_t)(J * ncol + 3 * ncol + 4 * count + 16)));
   for (int j = 0; j < J; ++j) ctx->pinned[j] = shifts[j] - shifts[0];
   LD_HIP(hipMemcpyAsync(delta, ctx->pinned, J * sizeof(double), hipMemcpyHostToDevice, st));
   LD_HIP(hipMemsetAsync(S.status, 0, 2 * sizeof(int), st));
@@ -1644,45 +1691,36 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
     ctx->mm_bytes += ctx->pinned[1];
   }
 
-  // ---- readback and the Hutchinson mean of every instance (FP64)
+  // ---- the Hutchinson combination of every instance on the device (FP64),
+  // then the per-probe values and per-instance statistics read back
+  BCoef bc{};
+  bc.b = bcoef;
+  bc.J = J;
+  for (int j = 0; j < J; ++j) bc.c[j] = ccoef[j];
+  hipLaunchKernelGGL(k_bhutchinson, dim3(count), dim3(64), 0, st, s, ncol, bc, S.ztx, S.ztz,
+                     S.rho, S.rho0, tol, hut, hut + ncol);
+  LD_HIP(hipGetLastError());
   double* hp = ctx->pinned;
-  LD_HIP(hipMemcpyAsync(hp, S.ztx, (size_t)J * ncol * 8, hipMemcpyDeviceToHost, st));
-  LD_HIP(hipMemcpyAsync(hp + J * ncol, S.ztz, ncol * 8, hipMemcpyDeviceToHost, st));
-  LD_HIP(hipMemcpyAsync(hp + J * ncol + ncol, S.rho, ncol * 8, hipMemcpyDeviceToHost, st));
-  LD_HIP(hipMemcpyAsync(hp + J * ncol + 2 * ncol, S.rho0, ncol * 8, hipMemcpyDeviceToHost, st));
+  LD_HIP(hipMemcpyAsync(hp, hut, (size_t)(ncol + 4 * count) * 8, hipMemcpyDeviceToHost, st));
   LD_HIP(hipStreamSynchronize(st));
   const double solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
   int unconverged = 0;
-  std::vector<double> t(s);
   for (int i = 0; i < count; ++i) {
-    double mean = 0.0, worst = 0.0;
-    int conv = 0;
-    for (int c = 0; c < s; ++c) {
-      const int64_t g = (int64_t)i * s + c;
-      double v = bcoef * hp[J * ncol + g];
-      for (int j = 0; j < J; ++j) v += ccoef[j] * hp[(int64_t)j * ncol + g];
-      t[c] = v;
-      mean += v;
-      const double rr = std::sqrt(std::max(0.0, hp[J * ncol + ncol + g] / hp[J * ncol + 2 * ncol + g]));
-      worst = std::max(worst, rr);
-      if (rr <= tol) ++conv;
-    }
-    mean /= s;
-    double var = 0.0;
-    for (int c = 0; c < s; ++c) var += (t[c] - mean) * (t[c] - mean);
+    const double* sv = hp + ncol + 4 * i;
+    const int conv = (int)sv[3];
     ld_result& o = out[i];
     o.logdet_P = logdetP[i];
-    o.trace_term = mean;
-    o.logdet = logdetP[i] + mean;
-    o.std_err = s > 1 ? std::sqrt(var / (s - 1) / s) : NAN;
-    o.rel_resid = worst;
+    o.trace_term = sv[0];
+    o.logdet = logdetP[i] + sv[0];
+    o.std_err = sv[1];
+    o.rel_resid = sv[2];
     o.seconds_solve = solve_s;
     o.seconds_precond = precond_s;
     o.iterations = std::min(it, max_iters);
     o.converged_cols = conv;
     o.k = J;
     o.num_probes = s;
-    if (per_probe) std::copy(t.begin(), t.end(), per_probe + (int64_t)i * s);
+    if (per_probe) std::copy(hp + (int64_t)i * s, hp + (int64_t)(i + 1) * s, per_probe + (int64_t)i * s);
     if (conv < s) ++unconverged;
   }
   if (breakdown) return fail(LD_ENOTSPD, "batch: non-positive curvature or residual in the solver");

@@ -43,18 +43,23 @@ class Config:
     max_iters: int = 5000     # solver iterations per batch (unconverged results are flagged)
 
 
-def estimate_all(ctx, insts, cfg: Config, torch, precond_only=False, items=None):
+def estimate_all(ctx, insts, cfg: Config, torch, precond_only=False, items=None, log=None):
     """Batched estimates (or preconditioners only) of a list of problems, in
-    chunks; returns (results, eigenvalue rows, items)."""
+    chunks; returns (results, eigenvalue rows, items).  log(msg), if given,
+    is called after every chunk."""
     items = items if items is not None else _items(insts, torch)
     res, lams = [], []
+    t0 = time.perf_counter()
     for c0 in range(0, len(items), cfg.chunk):
         r, _, _, lam = B.logdet_estimate_batched(
             ctx, items[c0:c0 + cfg.chunk], cfg.k, cfg.probes, cfg.oversample, cfg.power_iters,
             tol=cfg.tol, max_iters=cfg.max_iters, precond_only=precond_only, want_lambda=True,
-            allow_noconv=True)
+            allow_noconv=True, allow_breakdown=True)
         res += r
         lams += [row[:g.rank] for row, g in zip(lam, insts[c0:c0 + cfg.chunk])]
+        if log:
+            log(f"[sweep] {min(c0 + cfg.chunk, len(items))}/{len(items)} problems "
+                f"{time.perf_counter() - t0:.1f} s")
     return res, lams, items
 
 
@@ -129,10 +134,15 @@ def calibrate(S, F_hold, y_hold, torch, quantile: float = 0.99) -> float:
     return float(max(1.0, np.quantile(ratio, quantile)))
 
 
-def sweep(ctx, S, grid, edges, cfg: Config, torch, items=None):
+def sweep(ctx, S, grid, edges, cfg: Config, torch, items=None, score_rest=False, log=None):
     """Surrogate sweep over grid problems: returns per-point log det, whether
     the point fell back to the estimator, the stage times (s) together with
-    the ensemble's own log det and spread at every point, and the items."""
+    the ensemble's own log det and spread at every point, and the items.
+    With score_rest the plain estimator then also runs on the points that did
+    not fall back (after the timed sweep, not part of it): the stages also
+    carry "rest_plain" (its results, None at fallback points) and
+    "rest_seconds", so that fallback plus rest is the plain estimator on every
+    point, each point computed once."""
     t0 = time.perf_counter()
     pre, lams, items = estimate_all(ctx, grid, cfg, torch, precond_only=True, items=items)
     t1 = time.perf_counter()
@@ -148,10 +158,25 @@ def sweep(ctx, S, grid, edges, cfg: Config, torch, items=None):
     predicted = logdet.copy()
     t2 = time.perf_counter()
     fb = np.nonzero(fallback)[0]
+    plain_at = [None] * len(grid)
     if len(fb):
         res, _, _ = estimate_all(ctx, [grid[i] for i in fb], cfg, torch,
-                                 items=[items[i] for i in fb])
+                                 items=[items[i] for i in fb], log=log)
         logdet[fb] = [r["logdet"] for r in res]
+        for i, r in zip(fb, res):
+            plain_at[i] = r
     t3 = time.perf_counter()
-    return logdet, fallback, {"precond": t1 - t0, "predict": t2 - t1, "fallback": t3 - t2,
-                              "total": t3 - t0, "predicted": predicted, "spread": n * sd}, items
+    stages = {"precond": t1 - t0, "predict": t2 - t1, "fallback": t3 - t2, "total": t3 - t0,
+              "predicted": predicted, "spread": n * sd}
+    if score_rest:
+        rest = np.nonzero(~fallback)[0]
+        t4 = time.perf_counter()
+        if len(rest):
+            res, _, _ = estimate_all(ctx, [grid[i] for i in rest], cfg, torch,
+                                     items=[items[i] for i in rest], log=log)
+            for i, r in zip(rest, res):
+                plain_at[i] = r
+        torch.cuda.synchronize()
+        stages["rest_seconds"] = time.perf_counter() - t4
+        stages["rest_plain"] = plain_at
+    return logdet, fallback, stages, items

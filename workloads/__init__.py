@@ -118,20 +118,24 @@ def batch_instances(count: int = 256, seed: int = BASE_SEED + 3, n_lo: int = 500
 
 
 def surrogate_training_instances(count: int, n: int, seed: int = BASE_SEED + 4,
-                                 probes: int = 64):
+                                 probes: int = 64, rank: int | None = None, start: int = 0):
     """Training problems for the surrogate: the c4 hyperparameter distribution
-    at a fixed n, rank n/40."""
+    at a fixed n, rank n/40 unless given; problems start .. start + count - 1
+    of the seeded sequence."""
     g = np.random.default_rng(seed)
+    rank = rank or max(1, n // 40)
     out = []
-    for i in range(count):
+    for i in range(start + count):
         d = int(g.choice([2, 3, 8]))
         kind = int(g.integers(0, 2))
         ls = float(np.exp(g.uniform(np.log(0.02), np.log(0.5))))
         var = float(np.exp(g.uniform(np.log(0.5), np.log(2.0))))
         noise = float(np.exp(g.uniform(np.log(1e-4), np.log(1e-1))))
+        if i < start:
+            continue
         out.append(GPInstance(f"c5t_{i}", n=n, d=d, kind=kind, lengthscale=ls, variance=var,
                               noise=noise, points="uniform", seed=seed * 1000 + i,
-                              rank=max(1, n // 40), probes=probes, orders=(5,),
+                              rank=rank, probes=probes, orders=(5,),
                               probe_seed=seed + 10000 + i, precond_seed=seed + 20000 + i))
     return out
 
@@ -153,16 +157,19 @@ def surrogate_family_instances(count: int, n: int, seed: int = BASE_SEED + 7, pr
     return out
 
 
-def surrogate_grid(n: int, side: int = 32, seed: int = BASE_SEED + 5, probes: int = 64):
+def surrogate_grid(n: int, side: int = 32, seed: int = BASE_SEED + 5, probes: int = 64,
+                   rank: int | None = None):
     """The evaluation sweep: side x side log-spaced (lengthscale, noise) pairs,
-    variance 1, Matern-5/2, d = 3, one point cloud shared by the grid."""
+    variance 1, Matern-5/2, d = 3, one point cloud shared by the grid; rank
+    n/40 unless given."""
+    rank = rank or max(1, n // 40)
     out = []
     for a, ls in enumerate(np.exp(np.linspace(np.log(0.02), np.log(0.5), side))):
         for b, nz in enumerate(np.exp(np.linspace(np.log(1e-4), np.log(1e-1), side))):
             i = a * side + b
             out.append(GPInstance(f"c5g_{a}_{b}", n=n, d=3, kind=MATERN52, lengthscale=float(ls),
                                   variance=1.0, noise=float(nz), points="uniform", seed=seed,
-                                  rank=max(1, n // 40), probes=probes, orders=(5,),
+                                  rank=rank, probes=probes, orders=(5,),
                                   probe_seed=seed + 10000 + i, precond_seed=seed + 20000 + i))
     return out
 

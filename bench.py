@@ -507,22 +507,39 @@ def surrogate_main(args, torch, L):
         train_count = len(train_insts)
         log(f"[bench] c5: {len(train_insts)} training problems at n={args.c5_train_n}, "
             f"{len(grid)} grid points at n={args.c5_eval_n}")
-        res, lams, _ = sweep.estimate_all(ctx, train_insts, cfg, torch, log=log)
-        t_gen = time.perf_counter() - t0
-        ok = [i for i, r in enumerate(res) if r["converged_cols"] == cfg.probes]
-        yall = np.array([(r["logdet"] - r["logdet_P"]) / g.n for r, g in zip(res, train_insts)])
-        if args.c5_data_out:
-            lam_rows = np.zeros((len(res), max(g.rank for g in train_insts)), dtype=np.float32)
+        def save(res, lams, seconds):
+            # the problems done so far (rewritten after every chunk, so that
+            # an interrupted run keeps what it finished)
+            done = train_insts[:len(res)]
+            lam_rows = np.zeros((len(res), max(g.rank for g in done)), dtype=np.float32)
             for i, l in enumerate(lams):
                 lam_rows[i, :len(l)] = l
             conv = np.array([r["converged_cols"] == cfg.probes for r in res])
-            np.savez(args.c5_data_out, start=args.c5_train_start, y=yall, lam=lam_rows,
-                     converged=conv, seconds=t_gen)
+            y_done = np.array([(r["logdet"] - r["logdet_P"]) / g.n for r, g in zip(res, done)])
+            np.savez(args.c5_data_out, start=args.c5_train_start, y=y_done, lam=lam_rows,
+                     converged=conv, seconds=seconds)
+            return conv
+
+        if args.c5_data_out:
+            res, lams = [], []
+            for c0 in range(0, len(train_insts), cfg.chunk):
+                r, lm, _ = sweep.estimate_all(ctx, train_insts[c0:c0 + cfg.chunk], cfg, torch)
+                res += r
+                lams += lm
+                conv = save(res, lams, time.perf_counter() - t0)
+                log(f"[bench] c5 training data: {len(res)}/{len(train_insts)} problems "
+                    f"{time.perf_counter() - t0:.1f} s")
+            t_gen = time.perf_counter() - t0
+            conv = save(res, lams, t_gen)
             print(json.dumps({"c5_training_data": args.c5_data_out, "start": args.c5_train_start,
                               "count": len(res), "converged": int(conv.sum()),
                               "train_n": args.c5_train_n, "seconds": t_gen}), flush=True)
             ctx.close()
             return
+        res, lams, _ = sweep.estimate_all(ctx, train_insts, cfg, torch, log=log)
+        t_gen = time.perf_counter() - t0
+        ok = [i for i, r in enumerate(res) if r["converged_cols"] == cfg.probes]
+        yall = np.array([(r["logdet"] - r["logdet_P"]) / g.n for r, g in zip(res, train_insts)])
         train_used = [train_insts[i] for i in ok]
         lams = [lams[i] for i in ok]
         y = yall[ok]

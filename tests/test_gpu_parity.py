@@ -339,3 +339,41 @@ def test_estimate_bf16_parity(ctx, k):
     assert res["status"] == "LD_OK"
     assert res["logdet"] == pytest.approx(want.logdet, rel=1e-4)
     np.testing.assert_allclose(per, want.per_probe, rtol=2e-3)
+
+
+# ----------------------------------------- tiled storage: ragged and tiny n --
+@pytest.mark.parametrize("n", [1, 2, 31, 129, 333])
+@pytest.mark.parametrize("precision", [L.LD_F64, L.LD_F32, L.LD_BF16])
+def test_matmat_tiled_ragged_and_tiny(ctx, n, precision):
+    """Stored LD_TILED products where n leaves most of a 128 x 32 tile as
+    padding (n = 1, 2) or cuts through tiles in both directions."""
+    g = np.random.default_rng(19 * n + precision)
+    X = g.random((n, 3))
+    s = 5
+    V = g.standard_normal((n, s))
+    Mref = gp.dense_matrix(gp.MATERN52, X, 0.3, 1.3, 1e-2)
+    op = make_op(X, gp.MATERN52, 0.3, 1.3, 1e-2, precision=precision)
+    op.layout = L.LD_TILED
+    op.M = L.kernel_materialize(ctx, op)
+    dt = torch.float64 if precision == L.LD_F64 else torch.float32
+    Y = L.kernel_matmat(ctx, op, dev(V, dt))
+    ctx.synchronize()
+    Vd = host(dev(V, dt))
+    ref = Mref @ Vd
+    scale = np.abs(Mref) @ np.abs(Vd)
+    tol = {L.LD_F64: 1e-13, L.LD_F32: 1e-5, L.LD_BF16: 3e-5}[precision]
+    assert np.max(np.abs(host(Y) - ref) / scale) < tol
+
+
+@pytest.mark.parametrize("k", [1, 3, 5])
+def test_estimate_fp64_tiled_ragged_parity(ctx, k):
+    """FP64 estimate from the FP64 LD_TILED matrix at a size that is ragged in
+    both tile dimensions: oracle parity at 1e-10 (solves to 1e-11)."""
+    cfg = workloads.C2.with_n(1333, rank=60)
+    X, M, op, P, ref = _precond_pair(ctx, cfg, precision=L.LD_F64, stored="tiled")
+    res, per = L.logdet_estimate(ctx, op, P, k, cfg.probes, cfg.probe_seed + k, 1e-11, 5000)
+    want = _oracle_estimate(M, ref, k, cfg.probe_seed + k, cfg.probes)
+    assert res["status"] == "LD_OK" and res["converged_cols"] == cfg.probes
+    assert res["logdet"] == pytest.approx(want.logdet, rel=1e-10)
+    assert res["logdet_P"] == pytest.approx(ref.logdet, rel=1e-11)
+    assert np.max(np.abs(per - want.per_probe)) <= 1e-9 * np.max(np.abs(want.per_probe))

@@ -140,10 +140,23 @@ __global__ __launch_bounds__(256) void k_wood_out(const T* __restrict__ F,
                                                   const T* __restrict__ Z,
                                                   double* __restrict__ dot1,
                                                   double* __restrict__ dot2) {
-  __shared__ double Fs[WT][WK + 1];
-  __shared__ double Ts[WK][WT + 1];
-  __shared__ double red1[4][64][4];
-  __shared__ double red2[4][64][4];
+  // the column-dot reduction reuses the staging tiles' LDS after the rank
+  // loop (33.5 KB per workgroup: four workgroups fit a CU, so a 50,000-row
+  // apply runs as one wave of workgroups)
+  __shared__ union {
+    struct {
+      double F[WT][WK + 1];
+      double Tt[WK][WT + 1];
+    } st;
+    struct {
+      double r1[4][64][4];
+      double r2[4][64][4];
+    } rd;
+  } lds;
+  auto& Fs = lds.st.F;
+  auto& Ts = lds.st.Tt;
+  auto& red1 = lds.rd.r1;
+  auto& red2 = lds.rd.r2;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
   const int64_t i0 = (int64_t)blockIdx.x * WT;
@@ -205,6 +218,7 @@ __global__ __launch_bounds__(256) void k_wood_out(const T* __restrict__ F,
     }
   }
   if (dot1) {
+    __syncthreads();  // every wave is done reading the staging tiles
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       red1[wave][lane][c] = d1[c];
@@ -781,7 +795,8 @@ WoodPlan wood_plan(ld_ctx* ctx, int64_t n, int rank, int64_t s) {
   WoodPlan w{};
   w.ltiles = (rank + WT - 1) / WT;
   w.ctiles = (int)((s + WT - 1) / WT);
-  int64_t chunks = (int64_t)ctx->num_cu * 4 / ((int64_t)w.ltiles * w.ctiles);
+  // three workgroups of k_ft_partial fit a CU (registers): one wave of them
+  int64_t chunks = (int64_t)ctx->num_cu * 3 / ((int64_t)w.ltiles * w.ctiles);
   const int64_t maxc = (n + 255) / 256;
   if (chunks > maxc) chunks = maxc;
   if (chunks < 1) chunks = 1;

@@ -177,6 +177,20 @@ ld_status ld_ctx_set_timing(ld_ctx* ctx, int32_t on);
  * iterations are a dozen short kernels, run faster.  Off by default; ignored
  * while timing is on (events are not recorded inside graphs). */
 ld_status ld_ctx_set_graphs(ld_ctx* ctx, int32_t on);
+
+/* Symmetric reuse of generated kernel entries (M is symmetric, Section 2).
+ * With it on (the default), on-the-fly FP32 products of 33..64 columns at
+ * n >= 16,384 (the solver's products for 64 probes) cut M into 128 x 128
+ * blocks and generate only the blocks on and above the diagonal: block
+ * (I, J), J > I, is applied as K_IJ V_J to rows I and as K_IJ^T V_I to rows
+ * J, so about half of the entries are generated.  The partial sums of one
+ * product take about n^2 / 2 bytes of device scratch (20 GB at n = 200,000);
+ * products whose partial sums would exceed 32 GB, or that run on a caller's
+ * workspace (ld_set_workspace) too small for them, use the plain split, and
+ * so does kernel_matmat_noalloc.  Results are deterministic either way and
+ * agree with each other to FP32 rounding of the summation order.  Off: every
+ * product generates every entry. */
+ld_status ld_ctx_set_symmetric(ld_ctx* ctx, int32_t on);
 ld_status ld_ctx_read_timing(ld_ctx* ctx, double* ms, int64_t* calls, double* flops, double* bytes);
 
 /* Probe distributions of Algorithm 1 step 1 (mean 0, variance 1):
@@ -224,7 +238,9 @@ ld_status kernel_matmat(ld_ctx* ctx, const ld_operator* op, const void* V, int64
 
 /* kernel_matmat for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
- * the same product with the same kernels and bit-identical results, with its
+ * the same product with the same kernels and bit-identical results (those of
+ * kernel_matmat with ld_ctx_set_symmetric off: the symmetric split's partial
+ * sums grow as n^2 and are never taken here), with its
  * scratch (the stream-K partial sums and, on the FP32 / split-BF16
  * on-the-fly paths, the scaled FP32 copy of the points) taken from a static
  * device array of 256 MiB, which every device the library runs on holds from

@@ -33,7 +33,7 @@ STATUS_NAMES = {0: "LD_OK", -1: "LD_EINVAL", -2: "LD_ENOTSPD", -3: "LD_ENOCONV",
 
 EXPORTED = (
     "ld_ctx_create", "ld_ctx_destroy", "ld_last_error", "ld_ctx_set_timing", "ld_ctx_read_timing",
-    "ld_ctx_set_probes", "ld_ctx_set_graphs", "ld_workspace_bytes", "ld_set_workspace",
+    "ld_ctx_set_probes", "ld_ctx_set_graphs", "ld_ctx_set_symmetric", "ld_workspace_bytes", "ld_set_workspace",
     "ld_stored_elements", "ld_rational_coeffs", "ld_fill_probes",
     "ld_fill_gaussian", "kernel_matmat", "kernel_matmat_noalloc", "kernel_materialize",
     "logdet_precond_build",
@@ -107,6 +107,7 @@ def load():
         "ld_ctx_read_timing": (i32, [vp, pd, ctypes.POINTER(i64), pd, pd]),
         "ld_ctx_set_probes": (i32, [vp, i32]),
         "ld_ctx_set_graphs": (i32, [vp, i32]),
+        "ld_ctx_set_symmetric": (i32, [vp, i32]),
         "ld_stored_elements": (i64, [i64, i32]),
         "ld_rational_coeffs": (i32, [i32, pd, pd, pd]),
         "ld_fill_probes": (i32, [vp, u64, i64, i64, i32, vp]),
@@ -223,6 +224,11 @@ class Context:
     def set_graphs(self, on: bool = True):
         """Replay the solver's iterations from captured HIP graphs."""
         _check(load().ld_ctx_set_graphs(self.handle, 1 if on else 0))
+
+    def set_symmetric(self, on: bool = True):
+        """Generate each off-diagonal kernel entry once in the on-the-fly
+        FP32 products of 33..64 columns (on by default)."""
+        _check(load().ld_ctx_set_symmetric(self.handle, 1 if on else 0))
 
     def set_probes(self, kind: int):
         """Probe distribution (LD_PROBE_*) of later single-problem estimates."""

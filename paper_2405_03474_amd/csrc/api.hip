@@ -838,6 +838,12 @@ ld_status ld_ctx_set_graphs(ld_ctx* ctx, int32_t on) {
   return LD_OK;
 }
 
+ld_status ld_ctx_set_symmetric(ld_ctx* ctx, int32_t on) {
+  if (!ctx) return fail(LD_EINVAL, "context is NULL");
+  ctx->symmetric = on != 0;
+  return LD_OK;
+}
+
 ld_status ld_ctx_set_probes(ld_ctx* ctx, int32_t kind) {
   if (!ctx) return fail(LD_EINVAL, "context is NULL");
   if (kind != LD_PROBE_RADEMACHER && kind != LD_PROBE_GAUSSIAN && kind != LD_PROBE_ORTHOGONAL)
@@ -918,19 +924,25 @@ ld_status kernel_matmat_noalloc(ld_ctx* ctx, const ld_operator* op, const void* 
   LD_TRY(check_operator(op));
   if (!V || !Y || s < 1) return fail(LD_EINVAL, "bad V / Y / s");
   if (V == Y) return fail(LD_EINVAL, "Y must not alias V");
+  // the same path as kernel_matmat without symmetric reuse (whose partial
+  // sums grow as n^2), with the context's arena pointed at the static
+  // scratch for this call (external: never grown, never freed)
+  struct Swap {
+    ld_ctx* c;
+    Arena saved;
+    bool symmetric;
+    ~Swap() {
+      c->arena = saved;
+      c->symmetric = symmetric;
+    }
+  } swap{ctx, ctx->arena, ctx->symmetric};
+  ctx->symmetric = false;
   const size_t need = matmat_call_bytes(ctx, op, s);
   if (need > kStaticScratchBytes)
     return fail(LD_EINVAL, "kernel_matmat_noalloc: this product needs " + std::to_string(need) +
                                " bytes of scratch; the static scratch holds " +
                                std::to_string(kStaticScratchBytes));
   if (!ctx->static_scratch) return fail(LD_EHIP, "kernel_matmat_noalloc: no static scratch");
-  // the same path as kernel_matmat with the context's arena pointed at the
-  // static scratch for this call (external: never grown, never freed)
-  struct Swap {
-    ld_ctx* c;
-    Arena saved;
-    ~Swap() { c->arena = saved; }
-  } swap{ctx, ctx->arena};
   ctx->arena = Arena();
   ctx->arena.base = (char*)ctx->static_scratch;
   ctx->arena.cap = kStaticScratchBytes;

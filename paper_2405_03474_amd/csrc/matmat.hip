@@ -27,11 +27,13 @@
 
 #include "kfun_dev.hpp"
 #include "ld_common.hpp"
+#include "sym_split.hpp"
 
 namespace ld {
 namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 128;  // rows per workgroup tile
@@ -1324,6 +1326,328 @@ __global__ __launch_bounds__(256) void k_epilogue(const T* __restrict__ part, SK
   }
 }
 
+// ------------------------------------------ on the fly, symmetric blocks --
+// M is symmetric, so a fused product can generate each off-diagonal entry
+// once (the split and its slot indices: sym_split.hpp).  Block (I, J) with
+// J > I is used twice, Y_I += K_IJ V_J (direct: the lane-per-row A fragments
+// of k_mm32_fly) and Y_J += K_IJ^T V_I (transposed); diagonal blocks are
+// applied directly in full and blocks below the diagonal are skipped, so
+// about half of the entries are generated.  For the transposed product the
+// generated fragments go to LDS column-major and come back with one lane per
+// column: it runs on 16x16x4 FP32 matrix cores, wave w taking probe columns
+// 16 w .. 16 w + 15 (so a launch takes 33 to 64 columns), with V_I kept in
+// LDS, column-major, for the row tile.  Per stage a wave does as much
+// transposed matrix-core work as direct work.  A workgroup keeps the
+// transposed sums of its current strip in registers across row tiles and
+// writes them once per strip it touches; it writes the direct sum of each
+// unit to the unit's own slot.
+constexpr int SBK = 128;  // block edge of the symmetric split (= BM)
+
+template <int MS>
+__device__ __forceinline__ void sym_flush(f32x4 (&accT)[MS][4][2], float* __restrict__ dst,
+                                          int wave, int lq, int lg) {
+#pragma unroll
+  for (int b = 0; b < MS; ++b)
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 32 * st + 16 * mt + 4 * lg + r;
+          dst[(int64_t)b * (BM * 64) + row * 64 + 16 * wave + lq] = accT[b][st][mt][r];
+          accT[b][st][mt][r] = 0.f;
+        }
+}
+
+template <int KIND, int DT, int MS>
+__global__ __launch_bounds__(256, 2) void k_mm32_sym(const float* __restrict__ Xp, int d,
+                                                     float var, const float* __restrict__ V,
+                                                     float* __restrict__ part, SY p) {
+  constexpr int NB = 2, NT = 64;
+  constexpr int AS = BK + 4;
+  constexpr int KS = SBK + 4;  // row stride of the stage's column-major K
+  __shared__ __attribute__((aligned(16))) float Bt[2][NT * AS];
+  __shared__ float Xs[2][BK * DMAX];
+  __shared__ __attribute__((aligned(16))) float Kt[BK * KS];
+  __shared__ __attribute__((aligned(16))) float Vt[NT * KS];
+  const int dd_n = DT > 0 ? DT : d;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, lh = lane >> 5;
+  const int lq = lane & 15, lg = lane >> 4;
+  const int64_t n = p.n, s = p.s;
+  const int g = blockIdx.x;
+  int64_t u = sy_start(p, g);
+  const int64_t uend = sy_start(p, g + 1);
+  if (u >= uend) return;
+  int S = sy_strip(p, u);
+  int I = (int)(u - sy_u0(p, S));
+  const int Sfirst = S;
+
+  f32x4 accT[MS][4][2];
+#pragma unroll
+  for (int b = 0; b < MS; ++b)
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) accT[b][st][mt][r] = 0.f;
+
+  FlyTile<NB> tl;
+  fly_load<NB, DT>(tl, Xp, d, V, n, s, p.ld, 0, (int64_t)SBK * (I > MS * S ? I : MS * S), tid);
+  int buf = 0;
+  while (true) {
+    const int mS = MS * S;
+    const int me = sy_me(p, S);
+    const int64_t i0 = (int64_t)SBK * I;
+    int Sn = S, In = I + 1;
+    if (In >= me) {
+      Sn = S + 1;
+      In = 0;
+    }
+    // first column of the next unit (its stage is prefetched by this one's last)
+    const int64_t ncol = u + 1 < uend ? (int64_t)SBK * (In > MS * Sn ? In : MS * Sn) : -1;
+
+    float xr[DMAX];
+    {
+      const int64_t row = i0 + 32 * wave + li;
+#pragma unroll
+      for (int dd = 0; dd < DMAX; ++dd)
+        if (dd < dd_n) xr[dd] = row < n ? Xp[row * dd_n + dd] : 0.f;
+    }
+    // V_I, the transposed product's B operand, column-major in LDS (after
+    // the previous unit's last reads of it)
+    __syncthreads();
+    {
+      // thread: column tid % 64, rows tid / 64 + 4 j
+      const int c = tid % NT;
+      const int64_t r0 = i0 + tid / NT;
+      const float* vp = V + r0 * p.ld + c;
+      const int64_t step = 4 * p.ld;
+      float* vt = &Vt[c * KS + tid / NT];
+      float v[32];
+#pragma unroll
+      for (int j = 0; j < 32; ++j) {
+        v[j] = (c < s && r0 + 4 * j < n) ? *vp : 0.f;
+        vp += step;
+      }
+#pragma unroll
+      for (int j = 0; j < 32; ++j) vt[4 * j] = v[j];
+    }
+    f32x16 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
+
+#pragma unroll
+    for (int b = 0; b < MS; ++b) {
+      const int J = mS + b;
+      if (J < I || J >= me) continue;
+      const bool sym = J > I;
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int64_t col0 = (int64_t)SBK * J + BK * st;
+        float* bt = Bt[buf];
+        float* xs = Xs[buf];
+#pragma unroll
+        for (int j = 0; j < 4 * NB; ++j) {
+          const int e = tid + 256 * j;
+          bt[(e % NT) * AS + e / NT] = tl.v[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) xs[tid + 256 * j] = tl.x[j];
+        __syncthreads();
+        const int64_t nc = col0 + BK < (int64_t)SBK * me ? col0 + BK : ncol;
+        if (nc >= 0) fly_load<NB, DT>(tl, Xp, d, V, n, s, p.ld, 0, nc, tid);
+        float a[16], bv[NB][16];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const float4* bp = (const float4*)&bt[(nb * 32 + li) * AS + lh * 16];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float4 v = bp[q];
+            bv[nb][4 * q + 0] = v.x;
+            bv[nb][4 * q + 1] = v.y;
+            bv[nb][4 * q + 2] = v.z;
+            bv[nb][4 * q + 3] = v.w;
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          const float* xk = &xs[(lh * 16 + t) * DMAX];
+          float r2 = 0.f;
+#pragma unroll
+          for (int dd = 0; dd < DMAX; ++dd)
+            if (dd < dd_n) {
+              const float df = xr[dd] - xk[dd];
+              r2 = __builtin_fmaf(df, df, r2);
+            }
+          a[t] = kval32s<KIND>(r2, var);
+        }
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t], bv[nb][t], acc[nb], 0, 0, 0);
+        if (sym) {
+          // lane (li, lh) of wave w holds K[32 w + li][16 lh + t]: store it as
+          // Kt[column][row], then read a column per lane
+#pragma unroll
+          for (int t = 0; t < 16; ++t) Kt[(16 * lh + t) * KS + 32 * wave + li] = a[t];
+          __syncthreads();
+          // A: K[32 lg + k][16 mt + lq];  B: V_I[32 lg + k][16 wave + lq]
+          const float4* vp = (const float4*)&Vt[(16 * wave + lq) * KS + 32 * lg];
+          const float4* kp0 = (const float4*)&Kt[lq * KS + 32 * lg];
+          const float4* kp1 = (const float4*)&Kt[(16 + lq) * KS + 32 * lg];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const float4 vv = vp[q], k0 = kp0[q], k1 = kp1[q];
+            f32x4 c0 = accT[b][st][0], c1 = accT[b][st][1];
+            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(k0.x, vv.x, c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(k1.x, vv.x, c1, 0, 0, 0);
+            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(k0.y, vv.y, c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(k1.y, vv.y, c1, 0, 0, 0);
+            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(k0.z, vv.z, c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(k1.z, vv.z, c1, 0, 0, 0);
+            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(k0.w, vv.w, c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(k1.w, vv.w, c1, 0, 0, 0);
+            accT[b][st][0] = c0;
+            accT[b][st][1] = c1;
+          }
+        }
+        buf ^= 1;
+      }
+    }
+
+    float* dst = part + sy_dir_slot(p, S, I) * (int64_t)(BM * NT);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 32 * wave + 8 * (r >> 2) + 4 * lh + (r & 3);
+        dst[row * NT + nb * 32 + li] = acc[nb][r];
+      }
+    ++u;
+    if (u >= uend) break;
+    if (Sn != S)
+      sym_flush<MS>(accT, part + sy_tr_slot(p, g, Sfirst, S, MS * S) * (int64_t)(BM * NT), wave,
+                    lq, lg);
+    S = Sn;
+    I = In;
+  }
+  sym_flush<MS>(accT, part + sy_tr_slot(p, g, Sfirst, S, MS * S) * (int64_t)(BM * NT), wave, lq,
+                lg);
+}
+
+// Epilogue of the symmetric split, grid (blocks, epi_split): row tile R =
+// blockIdx.x, row slice blockIdx.y; the same outputs as k_epilogue.  A
+// thread keeps up to two float4 of the slice (the same four columns in
+// each) and has eight slots' loads in flight; slots are added in order.
+template <int MS>
+__global__ __launch_bounds__(256) void k_sym_epilogue(const float* __restrict__ part, SY p,
+                                                      float* __restrict__ Y,
+                                                      const float* __restrict__ V, double noise,
+                                                      const float* __restrict__ X2, double alpha2,
+                                                      double* __restrict__ dots) {
+  constexpr int NT = 64;
+  constexpr int64_t TILE = BM * NT;
+  constexpr int QF = 8;  // slots in flight
+  __shared__ double red[4][257];
+  __shared__ int64_t slot[kMaxContrib];
+  __shared__ int nslot;
+  const int tid = threadIdx.x;
+  const int R = blockIdx.x;
+  const int quarter = blockIdx.y, split = gridDim.y;
+  const int SR = R / MS;
+  if (tid == 0) nslot = sy_tr_list(p, R, slot, kMaxContrib);
+  __syncthreads();
+  const int ndir = p.ns - SR;
+  const int64_t dbase = sy_dir_base(p, R);  // == sy_dir_slot(p, SR, R)
+  const int ntot = ndir + (nslot < kMaxContrib ? nslot : kMaxContrib);
+  const int nf = (BM / split) * NT / 4;  // float4 of the slice (<= 512)
+  const int f0 = quarter * nf;
+  double sum[2][4];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sum[j][c] = 0.0;
+  int q = 0;
+  for (; q + QF <= ntot; q += QF) {
+    float4 v[QF][2];
+#pragma unroll
+    for (int w = 0; w < QF; ++w) {
+      const int qq = q + w;
+      const int64_t off = (qq < ndir ? dbase + qq : slot[qq - ndir]) * TILE;
+      const float4* src = (const float4*)(part + off) + f0;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int f = tid + 256 * j;
+        v[w][j] = f < nf ? src[f] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+#pragma unroll
+    for (int w = 0; w < QF; ++w)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        sum[j][0] += (double)v[w][j].x;
+        sum[j][1] += (double)v[w][j].y;
+        sum[j][2] += (double)v[w][j].z;
+        sum[j][3] += (double)v[w][j].w;
+      }
+  }
+  for (; q < ntot; ++q) {
+    const int64_t off = (q < ndir ? dbase + q : slot[q - ndir]) * TILE;
+    const float4* src = (const float4*)(part + off) + f0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int f = tid + 256 * j;
+      if (f < nf) {
+        const float4 v = src[f];
+        sum[j][0] += (double)v.x;
+        sum[j][1] += (double)v.y;
+        sum[j][2] += (double)v.z;
+        sum[j][3] += (double)v.w;
+      }
+    }
+  }
+  const int64_t i0 = (int64_t)R * BM;
+  const int cb = (4 * tid) % NT;  // this thread's four columns
+  double dacc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int f = tid + 256 * j;
+    if (f >= nf) continue;
+    const int64_t i = i0 + (4 * (f0 + f)) / NT;
+    if (i >= p.n) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int col = cb + c;
+      if (col >= p.s) continue;
+      const int64_t off = i * p.ld + col;
+      double v = sum[j][c];
+      if (noise != 0.0) v += noise * (double)V[off];
+      if (X2) v += alpha2 * (double)X2[off];
+      const float y = (float)v;
+      Y[off] = y;
+      dacc[c] += (double)V[off] * (double)y;
+    }
+  }
+  if (dots) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) red[c][tid] = dacc[c];
+    __syncthreads();
+    if (tid < NT) {
+      // column tid: component tid % 4 of the threads whose column group is tid / 4
+      double t = 0.0;
+      for (int k = tid / 4; k < 256; k += NT / 4) t += red[tid % 4][k];
+      if (tid < p.s) dots[((int64_t)R * split + quarter) * p.s + tid] = t;
+    }
+  }
+}
+
 // ------------------------------------------------------------ materialize --
 // DM = DMAX (the fused kernels' limit) or 64 (the largest d the ABI takes)
 template <typename T, int KIND, int DM>
@@ -1538,6 +1862,60 @@ void fly64_by_d(int NB, dim3 g, hipStream_t st, const double* X, int d, double v
   }
 }
 
+template <int KIND, int DT>
+void launch_sym32(dim3 g, hipStream_t st, const float* X, int d, float var, const float* V,
+                  float* part, const SY& p);
+
+template <int KIND>
+void sym32_by_d(dim3 g, hipStream_t st, const float* X, int d, float var, const float* V,
+                float* part, const SY& p) {
+  switch (d) {
+    case 2: launch_sym32<KIND, 2>(g, st, X, d, var, V, part, p); break;
+    case 3: launch_sym32<KIND, 3>(g, st, X, d, var, V, part, p); break;
+    case 8: launch_sym32<KIND, 8>(g, st, X, d, var, V, part, p); break;
+    default: launch_sym32<KIND, 0>(g, st, X, d, var, V, part, p); break;
+  }
+}
+
+// ------------------------------------------------- symmetric split: plan --
+constexpr int kSymMS = 2;                          // blocks per strip (256 columns)
+constexpr int64_t kSymMinN = 16384;                // smaller products keep the plain split
+constexpr size_t kSymMaxBytes = (size_t)32 << 30;  // partial sums of one product
+
+template <int KIND, int DT>
+void launch_sym32(dim3 g, hipStream_t st, const float* X, int d, float var, const float* V,
+                  float* part, const SY& p) {
+  hipLaunchKernelGGL((k_mm32_sym<KIND, DT, kSymMS>), g, dim3(256), 0, st, X, d, var, V, part, p);
+}
+
+struct SymPlan {
+  SY p;
+  size_t bytes;  // direct slots of every unit, then G * Jt * ms transposed slots
+};
+
+// The symmetric split of an n x s on-the-fly product, if it applies: 33..64
+// columns, n >= kSymMinN, partial sums within kSymMaxBytes, and every output
+// tile fed by at most kMaxContrib transposed slots.  Workgroups: two per CU,
+// fewer when a workgroup would get under four units' worth of blocks.
+bool make_sym_plan(ld_ctx* ctx, int64_t n, int64_t s, SymPlan* out) {
+  if (!ctx->symmetric || s <= 32 || s > 64 || n < kSymMinN) return false;
+  thread_local SymPlan cache{};
+  thread_local int cache_cu = -1;
+  thread_local bool cache_ok = false;
+  if (cache_cu == ctx->num_cu && cache.p.n == n && cache.p.s == s) {
+    if (cache_ok) *out = cache;
+    return cache_ok;
+  }
+  const SY p = sy_plan(n, s, kSymMS, ctx->num_cu * 2);
+  const SymPlan sp{p, (size_t)(p.units + (int64_t)p.G * p.Jt * p.ms) * BM * 64 * sizeof(float)};
+  const bool ok = sp.bytes <= kSymMaxBytes && sy_max_tr_list(p) <= kMaxContrib;
+  cache = sp;
+  cache_cu = ctx->num_cu;
+  cache_ok = ok;
+  if (ok) *out = sp;
+  return ok;
+}
+
 // ------------------------------------------------------- static scratch --
 // Scratch of kernel_matmat_noalloc: a file-scope device array that every
 // device the library runs on holds from the code object's load until the
@@ -1596,8 +1974,38 @@ size_t matmat_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int64_t s) {
     b = std::max(b, make_plan(ctx, false, n, s, BK16).part_bytes);
     b = std::max(b, make_plan(ctx, false, n, s, BK, true).part_bytes);
     b = std::max(b, make_plan(ctx, false, n, s, BK16, true).part_bytes);
+    // the symmetric split, when the arena can grow for it (a caller's
+    // workspace that is too small gets the plain split instead)
+    SymPlan sp;
+    if (!ctx->arena.external && make_sym_plan(ctx, n, s, &sp)) b = std::max(b, sp.bytes);
   }
   return b + 1024;
+}
+
+// the on-the-fly product over the symmetric split (FP32 matrix cores)
+ld_status matmat_sym(ld_ctx* ctx, const MatmatArgs& a, const SY& p, float* part) {
+  hipStream_t st = ctx->stream;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (a.timed && ctx->timing) {
+    const double nn = (double)a.n * (double)a.n;
+    LD_TRY(timing_pair(ctx, &ev0, &ev1, 2.0 * nn * (double)a.s, 2.0 * (double)a.n * a.s * 4.0));
+    LD_HIP(hipEventRecord(ev0, st));
+  }
+  const int kind = a.kp.kind;
+  const float var = (float)(kind == LD_RBF ? std::log2(a.kp.variance) : a.kp.variance);
+  const float* X = (const float*)a.X;
+  const float* V = (const float*)a.V;
+  if (kind == LD_RBF)
+    sym32_by_d<LD_RBF>(dim3(p.G), st, X, a.d, var, V, part, p);
+  else
+    sym32_by_d<LD_MATERN52>(dim3(p.G), st, X, a.d, var, V, part, p);
+  if (ev1) LD_HIP(hipEventRecord(ev1, st));
+  const int split = epi_split(p.nblk, 64);
+  hipLaunchKernelGGL((k_sym_epilogue<kSymMS>), dim3((unsigned)p.nblk, split), dim3(256), 0, st,
+                     part, p, (float*)a.Y, V, a.kp.noise, (const float*)a.X2, a.alpha2, a.dots);
+  if (a.dot_blocks) *a.dot_blocks = p.nblk * split;
+  LD_HIP(hipGetLastError());
+  return LD_OK;
 }
 
 ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
@@ -1622,6 +2030,14 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
       ctx->arena.top = mark;
     }
     return LD_OK;
+  }
+  if (fused32 && !split16) {
+    SymPlan sp;
+    if (make_sym_plan(ctx, a.n, a.s, &sp)) {
+      sp.p.ld = a.ld ? a.ld : a.s;
+      float* part = (float*)ctx->arena.take(sp.bytes);
+      if (part) return matmat_sym(ctx, a, sp.p, part);
+    }
   }
   Plan pl = make_plan(ctx, f64, a.n, a.s, split16 ? BK16 : BK, fused32);
   if (a.ld) pl.p.ld = a.ld;

@@ -179,18 +179,27 @@ ld_status ld_ctx_set_timing(ld_ctx* ctx, int32_t on);
 ld_status ld_ctx_set_graphs(ld_ctx* ctx, int32_t on);
 
 /* Symmetric reuse of generated kernel entries (M is symmetric, Section 2).
- * With it on (the default), on-the-fly FP32 products of 33..64 columns at
+ * For the forms whose bit is set, on-the-fly products of 33..64 columns at
  * n >= 16,384 (the solver's products for 64 probes) cut M into 128 x 128
  * blocks and generate only the blocks on and above the diagonal: block
  * (I, J), J > I, is applied as K_IJ V_J to rows I and as K_IJ^T V_I to rows
- * J, so about half of the entries are generated.  The partial sums of one
- * product take about n^2 / 2 bytes of device scratch (20 GB at n = 200,000);
- * products whose partial sums would exceed 32 GB, or that run on a caller's
- * workspace (ld_set_workspace) too small for them, use the plain split, and
- * so does kernel_matmat_noalloc.  Results are deterministic either way and
- * agree with each other to FP32 rounding of the summation order.  Off: every
- * product generates every entry. */
-ld_status ld_ctx_set_symmetric(ld_ctx* ctx, int32_t on);
+ * J, so about half of the entries are generated; the transposed products
+ * read the generated entries back from LDS with one lane per column.
+ *   LD_SYM_F32   FP32 matrix cores (strips of two blocks; partial sums about
+ *                n^2 / 2 bytes of device scratch, 20 GB at n = 200,000)
+ *   LD_SYM_BF16  split-BF16 matrix cores (strips of four blocks, n^2 / 4
+ *                bytes)
+ * The default is LD_SYM_F32: at n = 200,000 with 64 columns the FP32 product
+ * takes 56.9 ms against 59.1 ms without the split, while the split-BF16 one
+ * takes 32.7 ms against 30.7 ms (its transposed products are bound by LDS
+ * traffic rather than by generating entries).  Products whose partial sums
+ * would exceed 32 GB, or that run on a caller's workspace (ld_set_workspace)
+ * too small for them, use the plain split, and so does
+ * kernel_matmat_noalloc.  Results are deterministic either way and agree
+ * with each other to FP32 rounding of the summation order.  0: every product
+ * generates every entry. */
+typedef enum { LD_SYM_F32 = 1, LD_SYM_BF16 = 2 } ld_sym_form;
+ld_status ld_ctx_set_symmetric(ld_ctx* ctx, int32_t forms);
 ld_status ld_ctx_read_timing(ld_ctx* ctx, double* ms, int64_t* calls, double* flops, double* bytes);
 
 /* Probe distributions of Algorithm 1 step 1 (mean 0, variance 1):

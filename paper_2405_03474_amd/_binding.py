@@ -27,6 +27,7 @@ LD_LANCZOS_MAX = 128
  LD_PRECOND_PCHOL) = 0, 1, 2, 3, 4
 LD_PRECOND_SCALED = 1
 LD_PROBE_RADEMACHER, LD_PROBE_GAUSSIAN, LD_PROBE_ORTHOGONAL = 0, 1, 2
+LD_SYM_F32, LD_SYM_BF16 = 1, 2
 
 STATUS_NAMES = {0: "LD_OK", -1: "LD_EINVAL", -2: "LD_ENOTSPD", -3: "LD_ENOCONV", -4: "LD_EHIP",
                 -5: "LD_ENOMEM"}
@@ -225,10 +226,11 @@ class Context:
         """Replay the solver's iterations from captured HIP graphs."""
         _check(load().ld_ctx_set_graphs(self.handle, 1 if on else 0))
 
-    def set_symmetric(self, on: bool = True):
+    def set_symmetric(self, f32: bool = True, bf16: bool = False):
         """Generate each off-diagonal kernel entry once in the on-the-fly
-        FP32 products of 33..64 columns (on by default)."""
-        _check(load().ld_ctx_set_symmetric(self.handle, 1 if on else 0))
+        products of 33..64 columns of these forms (default: FP32 only)."""
+        forms = (LD_SYM_F32 if f32 else 0) | (LD_SYM_BF16 if bf16 else 0)
+        _check(load().ld_ctx_set_symmetric(self.handle, forms))
 
     def set_probes(self, kind: int):
         """Probe distribution (LD_PROBE_*) of later single-problem estimates."""

@@ -838,9 +838,10 @@ ld_status ld_ctx_set_graphs(ld_ctx* ctx, int32_t on) {
   return LD_OK;
 }
 
-ld_status ld_ctx_set_symmetric(ld_ctx* ctx, int32_t on) {
+ld_status ld_ctx_set_symmetric(ld_ctx* ctx, int32_t forms) {
   if (!ctx) return fail(LD_EINVAL, "context is NULL");
-  ctx->symmetric = on != 0;
+  if (forms & ~(LD_SYM_F32 | LD_SYM_BF16)) return fail(LD_EINVAL, "unknown symmetric-split form bits");
+  ctx->symmetric = forms;
   return LD_OK;
 }
 
@@ -930,13 +931,13 @@ ld_status kernel_matmat_noalloc(ld_ctx* ctx, const ld_operator* op, const void* 
   struct Swap {
     ld_ctx* c;
     Arena saved;
-    bool symmetric;
+    int symmetric;
     ~Swap() {
       c->arena = saved;
       c->symmetric = symmetric;
     }
   } swap{ctx, ctx->arena, ctx->symmetric};
-  ctx->symmetric = false;
+  ctx->symmetric = 0;
   const size_t need = matmat_call_bytes(ctx, op, s);
   if (need > kStaticScratchBytes)
     return fail(LD_EINVAL, "kernel_matmat_noalloc: this product needs " + std::to_string(need) +

@@ -74,9 +74,9 @@ struct ld_ctx {
   bool timing = false;
   // replay the solver's iterations from captured HIP graphs (ld_ctx_set_graphs)
   bool graphs = false;
-  // on-the-fly FP32 / split-BF16 products of 33..64 columns generate each
-  // off-diagonal kernel entry once (ld_ctx_set_symmetric; on by default)
-  bool symmetric = true;
+  // on-the-fly products of 33..64 columns that generate each off-diagonal
+  // kernel entry once (ld_ctx_set_symmetric): LD_SYM_F32 | LD_SYM_BF16 bits
+  int symmetric = LD_SYM_F32;
   std::vector<hipEvent_t> ev;  // pairs (start, stop)
   size_t ev_used = 0;          // events recorded and not yet collected
   double mm_ms = 0.0;

@@ -97,20 +97,18 @@ __device__ __forceinline__ void fly_load(FlyTile<NB>& t, const float* __restrict
                                          const float* __restrict__ V, int64_t n, int64_t s,
                                          int64_t ld, int64_t c0, int64_t k0, int tid) {
   constexpr int NT = 32 * NB;
-  constexpr int KSTEP = 256 / NT;  // k rows between a thread's consecutive loads
+  constexpr int RT = 4 * NB;  // consecutive k rows per thread (32 rows over 256 / NT threads)
   const int dd_n = DT > 0 ? DT : d;
-  // load j of this thread: column c0 + tid % NT, row k0 + tid / NT + KSTEP j
+  // load j of this thread: column c0 + tid % NT, row k0 + RT (tid / NT) + j
   const int64_t col = c0 + tid % NT;
-  const int64_t kr0 = k0 + tid / NT;
+  const int64_t kr0 = k0 + RT * (tid / NT);
   const float* p = V + kr0 * ld + col;
-  const int64_t step = (int64_t)KSTEP * ld;
   if (col < s && k0 + BK <= n) {
 #pragma unroll
-    for (int j = 0; j < 4 * NB; ++j) t.v[j] = p[j * step];
+    for (int j = 0; j < RT; ++j) t.v[j] = p[j * ld];
   } else {
 #pragma unroll
-    for (int j = 0; j < 4 * NB; ++j)
-      t.v[j] = (col < s && kr0 + KSTEP * j < n) ? p[j * step] : 0.f;
+    for (int j = 0; j < RT; ++j) t.v[j] = (col < s && kr0 + j < n) ? p[j * ld] : 0.f;
   }
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
@@ -119,6 +117,23 @@ __device__ __forceinline__ void fly_load(FlyTile<NB>& t, const float* __restrict
     const int64_t kr = k0 + kk;
     t.x[j] = (dd < dd_n && kr < n) ? Xp[kr * dd_n + dd] : 0.f;
   }
+}
+
+// the stage tile into LDS: V transposed (row stride AS, k contiguous), a
+// thread's RT consecutive k of one column as 16-byte writes (consecutive
+// lanes take consecutive columns, so a write's lanes fall in distinct banks)
+template <int NB>
+__device__ __forceinline__ void fly_store(const FlyTile<NB>& t, float* __restrict__ bt,
+                                          float* __restrict__ xs, int tid) {
+  constexpr int NT = 32 * NB;
+  constexpr int RT = 4 * NB;
+  constexpr int AS = BK + 4;
+  float4* dst = (float4*)&bt[(tid % NT) * AS + RT * (tid / NT)];
+#pragma unroll
+  for (int q = 0; q < RT / 4; ++q)
+    dst[q] = make_float4(t.v[4 * q], t.v[4 * q + 1], t.v[4 * q + 2], t.v[4 * q + 3]);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) xs[tid + 256 * j] = t.x[j];
 }
 
 template <int NB, int KIND, int DT>
@@ -170,13 +185,7 @@ __global__ __launch_bounds__(256, (NB == 4 && DT != 2 && DT != 3) ? 1 : 2) void 
     for (int st = st0; st < st1; ++st) {
       float* bt = Bt[buf];
       float* xs = Xs[buf];
-#pragma unroll
-      for (int j = 0; j < 4 * NB; ++j) {
-        const int e = tid + 256 * j;
-        bt[(e % NT) * AS + e / NT] = tl.v[j];
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) xs[tid + 256 * j] = tl.x[j];
+      fly_store<NB>(tl, bt, xs, tid);
       __syncthreads();
       if (st + 1 < st1) fly_load<NB, DT>(tl, Xp, d, V, n, s, p.ld, c0, (int64_t)(st + 1) * BK, tid);
       float a[16], b[NB][16];
@@ -557,7 +566,7 @@ constexpr int BS16 = BK16 + 8;  // bf16 row stride of transposed B (144 bytes)
 
 template <int NB>
 struct F16Tile {
-  float v[8 * NB];  // 64 x 32*NB V tile: pairs of consecutive k for one column
+  float v[8 * NB];  // 64 x 32*NB V tile: NB runs of 8 consecutive k of one column
   float x[4];       // stage points (64 x d <= 64 x 16 floats over 256 threads)
 };
 
@@ -566,26 +575,25 @@ __device__ __forceinline__ void f16_load(F16Tile<NB>& t, const float* __restrict
                                          const float* __restrict__ V, int64_t n, int64_t s,
                                          int64_t ld, int64_t c0, int64_t k0, int tid) {
   constexpr int NT = 32 * NB;
-  constexpr int KSTEP = 2 * (256 / NT);  // k rows between a thread's consecutive pairs
+  constexpr int G = 256 / NT;  // threads per column
   const int dd_n = DT > 0 ? DT : d;
-  // pair j of this thread: column c0 + tid % NT, rows k0 + 2 (tid / NT) + KSTEP j (+1)
+  // run h of this thread: column c0 + tid % NT, rows k0 + 8 (tid / NT + G h) + r, r < 8
   const int64_t col = c0 + tid % NT;
-  const int64_t kr0 = k0 + 2 * (tid / NT);
+  const int64_t kr0 = k0 + 8 * (tid / NT);
   const float* p = V + kr0 * ld + col;
-  const int64_t step = (int64_t)KSTEP * ld;
   if (col < s && k0 + BK16 <= n) {
 #pragma unroll
-    for (int j = 0; j < 4 * NB; ++j) {
-      t.v[2 * j] = p[j * step];
-      t.v[2 * j + 1] = p[j * step + ld];
-    }
+    for (int h = 0; h < NB; ++h)
+#pragma unroll
+      for (int r = 0; r < 8; ++r) t.v[8 * h + r] = p[(8 * G * h + r) * ld];
   } else {
 #pragma unroll
-    for (int j = 0; j < 4 * NB; ++j) {
-      const int64_t kr = kr0 + KSTEP * j;
-      t.v[2 * j] = (col < s && kr < n) ? p[j * step] : 0.f;
-      t.v[2 * j + 1] = (col < s && kr + 1 < n) ? p[j * step + ld] : 0.f;
-    }
+    for (int h = 0; h < NB; ++h)
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int64_t kr = kr0 + 8 * G * h + r;
+        t.v[8 * h + r] = (col < s && kr < n) ? p[(8 * G * h + r) * ld] : 0.f;
+      }
   }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -596,19 +604,33 @@ __device__ __forceinline__ void f16_load(F16Tile<NB>& t, const float* __restrict
   }
 }
 
+// a run of 8 consecutive k split into planes and written as one 16-byte word
+// per plane (consecutive lanes take consecutive columns)
+__device__ __forceinline__ void split_store8(const float* v, __bf16* __restrict__ bh,
+                                             __bf16* __restrict__ bl) {
+  u32x4 hw, lw;
+#pragma unroll
+  for (int jp = 0; jp < 4; ++jp) {
+    uint32_t h, l;
+    split2(v[2 * jp], v[2 * jp + 1], h, l);
+    hw[jp] = h;
+    lw[jp] = l;
+  }
+  *(u32x4*)bh = hw;
+  *(u32x4*)bl = lw;
+}
+
 template <int NB>
 __device__ __forceinline__ void f16_store(const F16Tile<NB>& t, __bf16* __restrict__ bh,
                                           __bf16* __restrict__ bl, float* __restrict__ xs,
                                           int tid) {
   constexpr int NT = 32 * NB;
+  constexpr int G = 256 / NT;
+  const int cc = tid % NT;
 #pragma unroll
-  for (int j = 0; j < 4 * NB; ++j) {
-    const int e = tid + 256 * j;
-    const int cc = e % NT, kp = e / NT;
-    uint32_t h, l;
-    split2(t.v[2 * j], t.v[2 * j + 1], h, l);
-    *(uint32_t*)&bh[cc * BS16 + 2 * kp] = h;
-    *(uint32_t*)&bl[cc * BS16 + 2 * kp] = l;
+  for (int h = 0; h < NB; ++h) {
+    const int off = cc * BS16 + 8 * (tid / NT + G * h);
+    split_store8(&t.v[8 * h], &bh[off], &bl[off]);
   }
 #pragma unroll
   for (int j = 0; j < 4; ++j) xs[tid + 256 * j] = t.x[j];
@@ -1452,13 +1474,7 @@ __global__ __launch_bounds__(256, 2) void k_mm32_sym(const float* __restrict__ X
         const int64_t col0 = (int64_t)SBK * J + BK * st;
         float* bt = Bt[buf];
         float* xs = Xs[buf];
-#pragma unroll
-        for (int j = 0; j < 4 * NB; ++j) {
-          const int e = tid + 256 * j;
-          bt[(e % NT) * AS + e / NT] = tl.v[j];
-        }
-#pragma unroll
-        for (int j = 0; j < 2; ++j) xs[tid + 256 * j] = tl.x[j];
+        fly_store<NB>(tl, bt, xs, tid);
         __syncthreads();
         const int64_t nc = col0 + BK < (int64_t)SBK * me ? col0 + BK : ncol;
         if (nc >= 0) fly_load<NB, DT>(tl, Xp, d, V, n, s, p.ld, 0, nc, tid);
@@ -1540,6 +1556,312 @@ __global__ __launch_bounds__(256, 2) void k_mm32_sym(const float* __restrict__ X
   }
   sym_flush<MS>(accT, part + sy_tr_slot(p, g, Sfirst, S, MS * S) * (int64_t)(BM * NT), wave, lq,
                 lg);
+}
+
+// Split-BF16 product on the fly over the symmetric split: the arithmetic of
+// k_mm16 (kernel values and V split into bf16 hi + lo, hi*hi + hi*lo + lo*hi
+// with FP32 accumulation) with each off-diagonal block generated once.  One
+// workgroup of 8 waves per CU shares the 160 KB of LDS: per 64-column stage,
+// wave (rg, ch) generates rows 32 rg .. + 31 of the row tile against stage
+// columns 32 ch .. + 31 and applies them directly (32x32x16 BF16 matrix
+// cores); the hi and lo planes of the generated entries go to LDS
+// column-major, and wave (ts, ch) applies stage columns 32 ch .. + 31
+// transposed against V_I's probe columns 16 ts .. + 15 (16x16x32 BF16 matrix
+// cores), so the direct and transposed work per wave and stage are equal.
+// Strips are four blocks (512 columns), so each wave keeps 64 transposed
+// sums per lane; V_I (split into planes) is double buffered in LDS and the
+// next row tile's is loaded while the current one's first stage runs.  The
+// two column halves' direct sums of a unit are added through LDS before the
+// unit's slot is written.
+constexpr int kSym16MS = 4;  // blocks per strip of the split-BF16 form
+
+struct S16Tile {
+  float v[8];  // 64 x 64 V tile: 8 consecutive k of one column
+  float x[2];  // stage points (64 x d <= 64 x 16 floats over 512 threads)
+};
+
+template <int DT>
+__device__ __forceinline__ void s16_load(S16Tile& t, const float* __restrict__ Xp, int d,
+                                         const float* __restrict__ V, int64_t n, int64_t s,
+                                         int64_t ld, int64_t k0, int tid) {
+  const int dd_n = DT > 0 ? DT : d;
+  // column tid % 64, rows k0 + 8 (tid / 64) + r, r < 8
+  const int64_t col = tid % 64;
+  const int64_t kr0 = k0 + 8 * (tid / 64);
+  const float* q = V + kr0 * ld + col;
+  if (col < s && k0 + BK16 <= n) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) t.v[r] = q[r * ld];
+  } else {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) t.v[r] = (col < s && kr0 + r < n) ? q[r * ld] : 0.f;
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int e = tid + 512 * j;
+    const int kk = e / DMAX, dd = e % DMAX;
+    const int64_t kr = k0 + kk;
+    t.x[j] = (dd < dd_n && kr < n) ? Xp[kr * dd_n + dd] : 0.f;
+  }
+}
+
+template <int KIND, int DT>
+__global__ __launch_bounds__(512, 1) void k_mm16_sym(const float* __restrict__ Xp, int d,
+                                                     float var, const float* __restrict__ V,
+                                                     float* __restrict__ part, SY p) {
+  constexpr int NB = 2, NT = 64, MS = kSym16MS;
+  constexpr int KS16 = SBK + 8;  // bf16 row stride of the column-major K and V_I planes
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[2][NT * BS16];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[2][NT * BS16];
+  __shared__ float Xs[2][BK16 * DMAX];
+  __shared__ __attribute__((aligned(16))) __bf16 Kt[2][BK16 * KS16];      // [plane][col][row]
+  __shared__ __attribute__((aligned(16))) __bf16 Vt[2][2][NT * KS16];     // [buf][plane][col][row]
+  float* cmb = (float*)&Kt[0][0];  // 128 x 64 direct sums of the upper column half
+  const int dd_n = DT > 0 ? DT : d;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int rg = wave & 3, ch = wave >> 2;
+  const int li = lane & 31, lh = lane >> 5;
+  const int lq = lane & 15, lg = lane >> 4;
+  const int64_t n = p.n, s = p.s;
+  const int g = blockIdx.x;
+  int64_t u = sy_start(p, g);
+  const int64_t uend = sy_start(p, g + 1);
+  if (u >= uend) return;
+  int S = sy_strip(p, u);
+  int I = (int)(u - sy_u0(p, S));
+  const int Sfirst = S;
+
+  // V_I of row tile I into planes: thread column tid % 64, row pairs tid / 64 + 8 j
+  auto vi_load = [&](int It, float (&vr)[16]) {
+    const int c = tid % 64;
+    const int64_t r0 = (int64_t)SBK * It + 2 * (tid / 64);
+    const float* q = V + r0 * p.ld + c;
+    const int64_t step = 16 * p.ld;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int64_t r = r0 + 16 * j;
+      vr[2 * j] = (c < s && r < n) ? q[0] : 0.f;
+      vr[2 * j + 1] = (c < s && r + 1 < n) ? q[p.ld] : 0.f;
+      q += step;
+    }
+  };
+  auto vi_store = [&](int vb, const float (&vr)[16]) {
+    const int c = tid % 64;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int row = 2 * (tid / 64) + 16 * j;
+      uint32_t h, l;
+      split2(vr[2 * j], vr[2 * j + 1], h, l);
+      *(uint32_t*)&Vt[vb][0][c * KS16 + row] = h;
+      *(uint32_t*)&Vt[vb][1][c * KS16 + row] = l;
+    }
+  };
+
+  f32x4 accT[MS][2][2];
+#pragma unroll
+  for (int b = 0; b < MS; ++b)
+#pragma unroll
+    for (int sg = 0; sg < 2; ++sg)
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) accT[b][sg][mt][r] = 0.f;
+  auto flushT = [&](int Sx) {
+    float* dst = part + sy_tr_slot(p, g, Sfirst, Sx, MS * Sx) * (int64_t)(BM * NT);
+#pragma unroll
+    for (int b = 0; b < MS; ++b)
+#pragma unroll
+      for (int sg = 0; sg < 2; ++sg)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 64 * sg + 32 * ch + 16 * mt + 4 * lg + r;
+            dst[(int64_t)b * (BM * NT) + row * NT + 16 * rg + lq] = accT[b][sg][mt][r];
+            accT[b][sg][mt][r] = 0.f;
+          }
+  };
+
+  int vb = 0;
+  {
+    float vr[16];
+    vi_load(I, vr);
+    vi_store(0, vr);
+  }
+  S16Tile tl;
+  s16_load<DT>(tl, Xp, d, V, n, s, p.ld, (int64_t)SBK * (I > MS * S ? I : MS * S), tid);
+  int buf = 0;
+  while (true) {
+    const int mS = MS * S;
+    const int me = sy_me(p, S);
+    const int64_t i0 = (int64_t)SBK * I;
+    int Sn = S, In = I + 1;
+    if (In >= me) {
+      Sn = S + 1;
+      In = 0;
+    }
+    const bool more = u + 1 < uend;
+    const int64_t ncol = more ? (int64_t)SBK * (In > MS * Sn ? In : MS * Sn) : -1;
+    float xr[DMAX];
+    {
+      const int64_t row = i0 + 32 * rg + li;
+#pragma unroll
+      for (int dd = 0; dd < DMAX; ++dd)
+        if (dd < dd_n) xr[dd] = row < n ? Xp[row * dd_n + dd] : 0.f;
+    }
+    // the next row tile's V_I: loads issued now, stored after the first stage
+    float vn[16];
+    if (more) vi_load(In, vn);
+    bool first = true;
+    f32x16 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
+
+#pragma unroll
+    for (int b = 0; b < MS; ++b) {
+      const int J = mS + b;
+      if (J < I || J >= me) continue;
+      const bool sym = J > I;
+#pragma unroll
+      for (int sg = 0; sg < 2; ++sg) {
+        const int64_t col0 = (int64_t)SBK * J + BK16 * sg;
+        {
+          // stage tile: V split into planes (transposed, k contiguous), points
+          const int off = (tid % 64) * BS16 + 8 * (tid / 64);
+          split_store8(tl.v, &Bh[buf][off], &Bl[buf][off]);
+#pragma unroll
+          for (int j = 0; j < 2; ++j) Xs[buf][tid + 512 * j] = tl.x[j];
+        }
+        __syncthreads();
+        const int64_t nc = col0 + BK16 < (int64_t)SBK * me ? col0 + BK16 : ncol;
+        if (nc >= 0) s16_load<DT>(tl, Xp, d, V, n, s, p.ld, nc, tid);
+        const float* xs = Xs[buf];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          // columns 32 ch + 16 q + 8 lh + j of the stage, row 32 rg + li
+          const int cb = 32 * ch + 16 * q + 8 * lh;
+          float kv[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const float* xk = &xs[(cb + j) * DMAX];
+            float r2 = 0.f;
+#pragma unroll
+            for (int dd = 0; dd < DMAX; ++dd)
+              if (dd < dd_n) {
+                const float df = xr[dd] - xk[dd];
+                r2 = __builtin_fmaf(df, df, r2);
+              }
+            kv[j] = kval32s<KIND>(r2, var);
+          }
+          u32x4 hw, lw;
+#pragma unroll
+          for (int jp = 0; jp < 4; ++jp) {
+            uint32_t h, l;
+            split2(kv[2 * jp], kv[2 * jp + 1], h, l);
+            hw[jp] = h;
+            lw[jp] = l;
+          }
+          const bf16x8 ah = __builtin_bit_cast(bf16x8, hw);
+          const bf16x8 al = __builtin_bit_cast(bf16x8, lw);
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const int off = (nb * 32 + li) * BS16 + cb;
+            const bf16x8 bhv = *(const bf16x8*)&Bh[buf][off];
+            const bf16x8 blv = *(const bf16x8*)&Bl[buf][off];
+            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bhv, acc[nb], 0, 0, 0);
+            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, blv, acc[nb], 0, 0, 0);
+            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bhv, acc[nb], 0, 0, 0);
+          }
+          if (sym) {
+            // planes column-major, Kt[plane][column][row], written a word (two
+            // rows) at a time: lanes 2i and 2i + 1 (rows r, r + 1) swap half
+            // of their columns, the even lane then writes columns cb .. cb + 3
+            // and the odd lane cb + 4 .. cb + 7
+            const bool odd = li & 1;
+            const int cA = cb + (odd ? 4 : 0);
+            const int rE = 32 * rg + (li & ~1);
+#pragma unroll
+            for (int pl = 0; pl < 2; ++pl) {
+              const u32x4 w = pl ? lw : hw;
+              const uint32_t x0 = odd ? w[0] : w[2], x1 = odd ? w[1] : w[3];
+              // swap with the neighbouring lane (DPP quad_perm 1, 0, 3, 2)
+              const uint32_t y0 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x0, 0xB1, 0xF, 0xF, false);
+              const uint32_t y1 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x1, 0xB1, 0xF, 0xF, false);
+              const uint32_t m0 = odd ? y0 : w[0], m1 = odd ? w[2] : y0;  // rows r, r + 1
+              const uint32_t m2 = odd ? y1 : w[1], m3 = odd ? w[3] : y1;
+              __bf16* kt = &Kt[pl][cA * KS16 + rE];
+              *(uint32_t*)&kt[0] = __builtin_amdgcn_perm(m1, m0, 0x05040100u);
+              *(uint32_t*)&kt[KS16] = __builtin_amdgcn_perm(m1, m0, 0x07060302u);
+              *(uint32_t*)&kt[2 * KS16] = __builtin_amdgcn_perm(m3, m2, 0x05040100u);
+              *(uint32_t*)&kt[3 * KS16] = __builtin_amdgcn_perm(m3, m2, 0x07060302u);
+            }
+          }
+        }
+        if (sym) {
+          __syncthreads();
+          // A: K[32 k + 8 lg + j][32 ch + 16 mt + lq];  B: V_I[32 k + 8 lg + j][16 rg + lq]
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int r0 = 32 * k + 8 * lg;
+            const int vo = (16 * rg + lq) * KS16 + r0;
+            const bf16x8 vh = *(const bf16x8*)&Vt[vb][0][vo];
+            const bf16x8 vl = *(const bf16x8*)&Vt[vb][1][vo];
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+              const int ko = (32 * ch + 16 * mt + lq) * KS16 + r0;
+              const bf16x8 kh = *(const bf16x8*)&Kt[0][ko];
+              const bf16x8 kl = *(const bf16x8*)&Kt[1][ko];
+              f32x4 c = accT[b][sg][mt];
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vh, c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vl, c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kl, vh, c, 0, 0, 0);
+              accT[b][sg][mt] = c;
+            }
+          }
+        }
+        if (first) {
+          // the next row tile's V_I goes to the other buffer (last read by the
+          // unit before this one, which every wave has finished)
+          if (more) vi_store(vb ^ 1, vn);
+          first = false;
+        }
+        buf ^= 1;
+      }
+    }
+
+    // direct sums: the upper column half through LDS, then one slot per unit
+    __syncthreads();  // every wave is done with Kt
+    if (ch == 1) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = 32 * rg + 8 * (r >> 2) + 4 * lh + (r & 3);
+          cmb[row * NT + nb * 32 + li] = acc[nb][r];
+        }
+    }
+    __syncthreads();
+    if (ch == 0) {
+      float* dst = part + sy_dir_slot(p, S, I) * (int64_t)(BM * NT);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = 32 * rg + 8 * (r >> 2) + 4 * lh + (r & 3);
+          dst[row * NT + nb * 32 + li] = acc[nb][r] + cmb[row * NT + nb * 32 + li];
+        }
+    }
+    ++u;
+    if (!more) break;
+    if (Sn != S) flushT(S);
+    S = Sn;
+    I = In;
+    vb ^= 1;
+  }
+  flushT(S);
 }
 
 // Epilogue of the symmetric split, grid (blocks, epi_split): row tile R =
@@ -1888,6 +2210,23 @@ void launch_sym32(dim3 g, hipStream_t st, const float* X, int d, float var, cons
   hipLaunchKernelGGL((k_mm32_sym<KIND, DT, kSymMS>), g, dim3(256), 0, st, X, d, var, V, part, p);
 }
 
+template <int KIND, int DT>
+void launch_sym16(dim3 g, hipStream_t st, const float* X, int d, float var, const float* V,
+                  float* part, const SY& p) {
+  hipLaunchKernelGGL((k_mm16_sym<KIND, DT>), g, dim3(512), 0, st, X, d, var, V, part, p);
+}
+
+template <int KIND>
+void sym16_by_d(dim3 g, hipStream_t st, const float* X, int d, float var, const float* V,
+                float* part, const SY& p) {
+  switch (d) {
+    case 2: launch_sym16<KIND, 2>(g, st, X, d, var, V, part, p); break;
+    case 3: launch_sym16<KIND, 3>(g, st, X, d, var, V, part, p); break;
+    case 8: launch_sym16<KIND, 8>(g, st, X, d, var, V, part, p); break;
+    default: launch_sym16<KIND, 0>(g, st, X, d, var, V, part, p); break;
+  }
+}
+
 struct SymPlan {
   SY p;
   size_t bytes;  // direct slots of every unit, then G * Jt * ms transposed slots
@@ -1895,25 +2234,31 @@ struct SymPlan {
 
 // The symmetric split of an n x s on-the-fly product, if it applies: 33..64
 // columns, n >= kSymMinN, partial sums within kSymMaxBytes, and every output
-// tile fed by at most kMaxContrib transposed slots.  Workgroups: two per CU,
-// fewer when a workgroup would get under four units' worth of blocks.
-bool make_sym_plan(ld_ctx* ctx, int64_t n, int64_t s, SymPlan* out) {
-  if (!ctx->symmetric || s <= 32 || s > 64 || n < kSymMinN) return false;
-  thread_local SymPlan cache{};
-  thread_local int cache_cu = -1;
-  thread_local bool cache_ok = false;
-  if (cache_cu == ctx->num_cu && cache.p.n == n && cache.p.s == s) {
-    if (cache_ok) *out = cache;
-    return cache_ok;
+// tile fed by at most kMaxContrib transposed slots.  bf16: the split-BF16
+// form (strips of kSym16MS blocks, one 8-wave workgroup per CU); otherwise
+// the FP32 form (strips of kSymMS blocks, two 4-wave workgroups per CU).
+// Either gets fewer workgroups when one would have under four units' worth
+// of blocks.
+bool make_sym_plan(ld_ctx* ctx, int64_t n, int64_t s, bool bf16, SymPlan* out) {
+  if (!(ctx->symmetric & (bf16 ? LD_SYM_BF16 : LD_SYM_F32)) || s <= 32 || s > 64 || n < kSymMinN)
+    return false;
+  struct Entry {
+    SymPlan sp;
+    int cu = -1;
+    bool ok = false;
+  };
+  thread_local Entry cache[2];
+  Entry& e = cache[bf16 ? 1 : 0];
+  if (e.cu == ctx->num_cu && e.sp.p.n == n && e.sp.p.s == s) {
+    if (e.ok) *out = e.sp;
+    return e.ok;
   }
-  const SY p = sy_plan(n, s, kSymMS, ctx->num_cu * 2);
-  const SymPlan sp{p, (size_t)(p.units + (int64_t)p.G * p.Jt * p.ms) * BM * 64 * sizeof(float)};
-  const bool ok = sp.bytes <= kSymMaxBytes && sy_max_tr_list(p) <= kMaxContrib;
-  cache = sp;
-  cache_cu = ctx->num_cu;
-  cache_ok = ok;
-  if (ok) *out = sp;
-  return ok;
+  const SY p = bf16 ? sy_plan(n, s, kSym16MS, ctx->num_cu) : sy_plan(n, s, kSymMS, ctx->num_cu * 2);
+  e.sp = SymPlan{p, (size_t)(p.units + (int64_t)p.G * p.Jt * p.ms) * BM * 64 * sizeof(float)};
+  e.cu = ctx->num_cu;
+  e.ok = e.sp.bytes <= kSymMaxBytes && sy_max_tr_list(p) <= kMaxContrib;
+  if (e.ok) *out = e.sp;
+  return e.ok;
 }
 
 // ------------------------------------------------------- static scratch --
@@ -1977,13 +2322,14 @@ size_t matmat_scratch_bytes(ld_ctx* ctx, bool f64, int64_t n, int64_t s) {
     // the symmetric split, when the arena can grow for it (a caller's
     // workspace that is too small gets the plain split instead)
     SymPlan sp;
-    if (!ctx->arena.external && make_sym_plan(ctx, n, s, &sp)) b = std::max(b, sp.bytes);
+    if (!ctx->arena.external && make_sym_plan(ctx, n, s, false, &sp)) b = std::max(b, sp.bytes);
+    if (!ctx->arena.external && make_sym_plan(ctx, n, s, true, &sp)) b = std::max(b, sp.bytes);
   }
   return b + 1024;
 }
 
-// the on-the-fly product over the symmetric split (FP32 matrix cores)
-ld_status matmat_sym(ld_ctx* ctx, const MatmatArgs& a, const SY& p, float* part) {
+// the on-the-fly product over the symmetric split (FP32 or split-BF16 matrix cores)
+ld_status matmat_sym(ld_ctx* ctx, const MatmatArgs& a, const SY& p, bool bf16, float* part) {
   hipStream_t st = ctx->stream;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (a.timed && ctx->timing) {
@@ -1995,14 +2341,24 @@ ld_status matmat_sym(ld_ctx* ctx, const MatmatArgs& a, const SY& p, float* part)
   const float var = (float)(kind == LD_RBF ? std::log2(a.kp.variance) : a.kp.variance);
   const float* X = (const float*)a.X;
   const float* V = (const float*)a.V;
-  if (kind == LD_RBF)
+  if (bf16 && kind == LD_RBF)
+    sym16_by_d<LD_RBF>(dim3(p.G), st, X, a.d, var, V, part, p);
+  else if (bf16)
+    sym16_by_d<LD_MATERN52>(dim3(p.G), st, X, a.d, var, V, part, p);
+  else if (kind == LD_RBF)
     sym32_by_d<LD_RBF>(dim3(p.G), st, X, a.d, var, V, part, p);
   else
     sym32_by_d<LD_MATERN52>(dim3(p.G), st, X, a.d, var, V, part, p);
   if (ev1) LD_HIP(hipEventRecord(ev1, st));
   const int split = epi_split(p.nblk, 64);
-  hipLaunchKernelGGL((k_sym_epilogue<kSymMS>), dim3((unsigned)p.nblk, split), dim3(256), 0, st,
-                     part, p, (float*)a.Y, V, a.kp.noise, (const float*)a.X2, a.alpha2, a.dots);
+  if (p.ms == kSym16MS)
+    hipLaunchKernelGGL((k_sym_epilogue<kSym16MS>), dim3((unsigned)p.nblk, split), dim3(256), 0,
+                       st, part, p, (float*)a.Y, V, a.kp.noise, (const float*)a.X2, a.alpha2,
+                       a.dots);
+  else
+    hipLaunchKernelGGL((k_sym_epilogue<kSymMS>), dim3((unsigned)p.nblk, split), dim3(256), 0, st,
+                       part, p, (float*)a.Y, V, a.kp.noise, (const float*)a.X2, a.alpha2,
+                       a.dots);
   if (a.dot_blocks) *a.dot_blocks = p.nblk * split;
   LD_HIP(hipGetLastError());
   return LD_OK;
@@ -2031,12 +2387,12 @@ ld_status matmat(ld_ctx* ctx, bool f64, const MatmatArgs& a) {
     }
     return LD_OK;
   }
-  if (fused32 && !split16) {
+  if (fused32) {
     SymPlan sp;
-    if (make_sym_plan(ctx, a.n, a.s, &sp)) {
+    if (make_sym_plan(ctx, a.n, a.s, split16, &sp)) {
       sp.p.ld = a.ld ? a.ld : a.s;
       float* part = (float*)ctx->arena.take(sp.bytes);
-      if (part) return matmat_sym(ctx, a, sp.p, part);
+      if (part) return matmat_sym(ctx, a, sp.p, split16, part);
     }
   }
   Plan pl = make_plan(ctx, f64, a.n, a.s, split16 ? BK16 : BK, fused32);

@@ -756,51 +756,50 @@ __global__ __launch_bounds__(256, 2) void k_mm16_tf(const float* __restrict__ A,
 #pragma unroll
       for (int q = 0; q < 4; ++q) dst[q] = __builtin_nontemporal_load(src + 64 * q);
     };
-    // pair j of this thread: column c0 + e % NT, rows k0 + 2 (e / NT) (+1),
-    // e = tid + 256 j; clamped addresses, masked in store_b
-    // (both paths issue the same loads; a stage inside V, uniform over the
-    // workgroup, needs no clamping or masking)
+    // thread column c0 + tid % NT, 2 BP consecutive rows from 2 BP (tid / NT);
+    // clamped addresses, masked in store_b (both paths issue the same loads;
+    // a stage inside V, uniform over the workgroup, needs no clamping or
+    // masking); the planes are stored as one 8- or 16-byte write per thread
+    // whose lanes fall in distinct banks
     auto inside = [&](int st) { return (int64_t)st * BK + BK <= n && c0 + NT <= s; };
     auto load_b = [&](int st) {
-      const int64_t k0 = (int64_t)st * BK;
+      const int64_t k0 = (int64_t)st * BK + 2 * BP * (tid / NT);
+      const int64_t col = c0 + tid % NT;
       if (inside(st)) {
-        const float* src = V + (k0 + 2 * (tid / NT)) * s + c0 + tid % NT;
+        const float* src = V + k0 * s + col;
 #pragma unroll
-        for (int j = 0; j < BP; ++j) {
-          bq[2 * j] = src[(int64_t)(512 / NT) * j * s];
-          bq[2 * j + 1] = src[(int64_t)(512 / NT) * j * s + s];
-        }
+        for (int j = 0; j < 2 * BP; ++j) bq[j] = src[(int64_t)j * s];
         return;
       }
+      const int64_t cl = col < s ? col : s - 1;
 #pragma unroll
-      for (int j = 0; j < BP; ++j) {
-        const int e = tid + 256 * j;
-        const int64_t kr = k0 + 2 * (e / NT);
-        int64_t col = c0 + e % NT;
-        col = col < s ? col : s - 1;
-        const int64_t r0 = kr < n ? kr : n - 1, r1 = kr + 1 < n ? kr + 1 : n - 1;
-        bq[2 * j] = V[r0 * s + col];
-        bq[2 * j + 1] = V[r1 * s + col];
+      for (int j = 0; j < 2 * BP; ++j) {
+        const int64_t r = k0 + j < n ? k0 + j : n - 1;
+        bq[j] = V[r * s + cl];
       }
     };
     auto store_b = [&](__bf16* bh, __bf16* bl, int st) {
-      const int64_t k0 = (int64_t)st * BK;
+      const int64_t k0 = (int64_t)st * BK + 2 * BP * (tid / NT);
       const bool full = inside(st);
+      const bool cv = c0 + tid % NT < s;
+      uint32_t hw[BP], lw[BP];
 #pragma unroll
       for (int j = 0; j < BP; ++j) {
-        const int e = tid + 256 * j;
-        const int cc = e % NT, kp = e / NT;
         float v0 = bq[2 * j], v1 = bq[2 * j + 1];
         if (!full) {
-          const int64_t kr = k0 + 2 * kp;
-          const bool cv = c0 + cc < s;
-          v0 *= (cv && kr < n) ? 1.f : 0.f;
-          v1 *= (cv && kr + 1 < n) ? 1.f : 0.f;
+          v0 *= (cv && k0 + 2 * j < n) ? 1.f : 0.f;
+          v1 *= (cv && k0 + 2 * j + 1 < n) ? 1.f : 0.f;
         }
-        uint32_t h, l;
-        split2(v0, v1, h, l);
-        *(uint32_t*)&bh[cc * S16 + 2 * kp] = h;
-        *(uint32_t*)&bl[cc * S16 + 2 * kp] = l;
+        split2(v0, v1, hw[j], lw[j]);
+      }
+      const int off = (tid % NT) * S16 + 2 * BP * (tid / NT);
+      if constexpr (BP == 4) {
+        *(u32x4*)&bh[off] = u32x4{hw[0], hw[1], hw[2], hw[3]};
+        *(u32x4*)&bl[off] = u32x4{lw[0], lw[1], lw[2], lw[3]};
+      } else {
+        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+        *(u32x2*)&bh[off] = u32x2{hw[0], hw[1]};
+        *(u32x2*)&bl[off] = u32x2{lw[0], lw[1]};
       }
     };
     auto stage = [&](int cur, auto dc) {
@@ -1147,28 +1146,26 @@ __global__ __launch_bounds__(256, 2) void k_mm64_tf(const double* __restrict__ A
           dst[q] = __builtin_nontemporal_load(src + 64 * q);
         }
     };
+    // B: thread column tid % NT, BL consecutive k from BL (tid / NT), so that
+    // the transposed store is BL / 2 16-byte writes whose lanes fall in
+    // distinct banks
     auto load_b = [&](int st) {
-      const int64_t k0 = (int64_t)st * BK;
-      if (k0 + BK <= n && c0 + NT <= s) {
+      const int64_t k0 = (int64_t)st * BK + BL * (tid / NT);
+      const int64_t col = c0 + tid % NT;
+      const double* src = V + k0 * s + col;
+      if ((int64_t)st * BK + BK <= n && c0 + NT <= s) {
         // the whole stage is inside V (uniform over the workgroup)
-        const double* src = V + (k0 + tid / NT) * s + c0 + tid % NT;
 #pragma unroll
-        for (int j = 0; j < BL; ++j) bq[j] = src[(int64_t)(256 / NT) * j * s];
+        for (int j = 0; j < BL; ++j) bq[j] = src[(int64_t)j * s];
         return;
       }
 #pragma unroll
-      for (int j = 0; j < BL; ++j) {
-        const int e = tid + 256 * j;
-        const int64_t kr = k0 + e / NT, col = c0 + e % NT;
-        bq[j] = (kr < n && col < s) ? V[kr * s + col] : 0.0;
-      }
+      for (int j = 0; j < BL; ++j) bq[j] = (k0 + j < n && col < s) ? src[(int64_t)j * s] : 0.0;
     };
     auto store_b = [&](double* bt) {
+      f64x2* dst = (f64x2*)&bt[(tid % NT) * ST64 + BL * (tid / NT)];
 #pragma unroll
-      for (int j = 0; j < BL; ++j) {
-        const int e = tid + 256 * j;
-        bt[(e % NT) * ST64 + e / NT] = bq[j];
-      }
+      for (int j = 0; j < BL / 2; ++j) dst[j] = f64x2{bq[2 * j], bq[2 * j + 1]};
     };
 
     load_a_half(st0, aq[0], 0);

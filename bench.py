@@ -779,6 +779,9 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=8000)
     ap.add_argument("--graphs", action="store_true",
                     help="replay the solver's iterations from captured HIP graphs")
+    ap.add_argument("--symmetric", default="", choices=["", "none", "f32", "bf16", "both"],
+                    help="on-the-fly forms that generate each off-diagonal block once "
+                         "(default: the library's, FP32 only)")
     ap.add_argument("--kernel-kind", default="", choices=["", "rbf", "matern52"],
                     help="override the workload's covariance kernel (same points and sizes)")
     ap.add_argument("--plain-fp32", action="store_true",
@@ -892,6 +895,9 @@ def main():
     ctx = L.Context(0, stream)
     ctx.set_probes({"rademacher": L.LD_PROBE_RADEMACHER, "gaussian": L.LD_PROBE_GAUSSIAN,
                     "orthogonal": L.LD_PROBE_ORTHOGONAL}[args.probes])
+    if args.symmetric:
+        ctx.set_symmetric(f32=args.symmetric in ("f32", "both"),
+                          bf16=args.symmetric in ("bf16", "both"))
     runner = Runner(L, torch, ctx, cfg, precision, stored, args.lanczos_steps, args.precond,
                     args.scaled, args.union_shifts, tol)
     if args.graphs:
@@ -930,6 +936,9 @@ def main():
         kname = "k_mm64_tf<4> (FP64 MFMA 16x16x4, stored LD_TILED fragment tiles)"
     if kind == "c3" and precision == L.LD_F32:
         kname = "k_mm32_fly (FP32 MFMA 32x32x2, kernel entries generated on the fly)"
+        if cfg.n >= 16384 and 32 < cfg.probes <= 64 and args.symmetric in ("", "f32", "both"):
+            kname = ("k_mm32_sym (FP32 MFMA over the symmetric split: blocks on and above the "
+                     "diagonal generated once, applied directly 32x32x2 and transposed 16x16x4)")
     traffic = profiled_traffic(f"{cfg.name}/{dtype}") if not args.n and stored else None
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": traffic, "kernel": kname,
@@ -954,7 +963,8 @@ def main():
                               if args.lanczos_steps else
                               {"kind": "multishift_pcg", "tol": runner.tol,
                                "orders_share_probes": bool(args.union_shifts),
-                               "graph_replay": bool(args.graphs)})},
+                               "graph_replay": bool(args.graphs)}),
+                   "symmetric_split": args.symmetric or "f32"},
         "probe_solves_per_s": cfg.probes * n_est / (ms_total / 1e3),
         # the same estimates without the preconditioner build and M (host wall
         # time of each solve as the library reports it)

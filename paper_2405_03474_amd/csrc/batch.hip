@@ -37,7 +37,7 @@ constexpr int BDX = 8;      // point stride (max dimension of a batched instance
 constexpr int BBK = 32;     // k per stage
 constexpr int BLK = 64;     // row block of the segmented reductions
 constexpr int kChunk = 8;   // solver iterations per host check / graph replay
-constexpr int FTC = 2048;   // rows per partial of the Woodbury projection F^T R
+constexpr int FTC = 1024;   // rows per partial of the Woodbury projection F^T R
 
 struct BInst {
   const double* X64;

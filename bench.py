@@ -300,8 +300,9 @@ class BatchRunner:
 
     K, S, OVER, POWER = 3, 16, 10, 2
 
-    def __init__(self, L, torch, ctx, insts, graph=True):
+    def __init__(self, L, torch, ctx, insts, graph=True, symmetric=False):
         self.L, self.ctx, self.insts, self.graph = L, ctx, insts, graph
+        self.symmetric = symmetric
         dev = torch.device("cuda:0")
         self.items = [L.BatchItem(X=torch.as_tensor(g.X(), dtype=torch.float64, device=dev),
                                   kind=g.kind, lengthscale=g.lengthscale, variance=g.variance,
@@ -312,7 +313,7 @@ class BatchRunner:
     def step(self):
         res, per, status = self.L.logdet_estimate_batched(
             self.ctx, self.items, self.K, self.S, self.OVER, self.POWER, tol=self.tol,
-            max_iters=5000, graph=self.graph)
+            max_iters=5000, graph=self.graph, symmetric=self.symmetric)
         return {self.K: res}
 
 
@@ -362,7 +363,8 @@ def batch_main(args, torch, L):
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream(0)
     ctx = L.Context(0, stream)
-    runner = BatchRunner(L, torch, ctx, insts, graph=not args.no_graph)
+    runner = BatchRunner(L, torch, ctx, insts, graph=not args.no_graph,
+                         symmetric=args.batch_form == "symmetric")
     results, ms_total, wall, (mm_ms, mm_calls, mm_flops, mm_bytes) = timed_steps(
         runner, args.steps, args.warmup, stream, torch)
     count = len(insts)
@@ -372,7 +374,8 @@ def batch_main(args, torch, L):
         # kernel events cannot sit inside the replayed graph: the product
         # kernel is timed over a second timed region of eager steps
         log("[bench] eager steps (kernel timing)")
-        eager = BatchRunner(L, torch, ctx, insts, graph=False)
+        eager = BatchRunner(L, torch, ctx, insts, graph=False,
+                            symmetric=args.batch_form == "symmetric")
         eager.items = runner.items
         _, ems, _, (mm_ms, mm_calls, mm_flops, mm_bytes) = timed_steps(eager, args.steps, 0,
                                                                       stream, torch)
@@ -400,8 +403,11 @@ def batch_main(args, torch, L):
     achieved = (mm_flops / max(mm_calls, 1)) / (avg_ms / 1e3) if mm_calls else 0.0
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK["fp32"], "traffic": None,
-                "kernel": "k_bmm (FP32 MFMA 32x32x2, kernel entries generated on the fly, "
-                          "one workgroup per instance row block)",
+                "kernel": ("k_bmm_sym + k_bsym_reduce (FP32 MFMA, blocks on and above the "
+                           "diagonal generated once, feeding both rows)"
+                           if args.batch_form == "symmetric" else
+                           "k_bmm (FP32 MFMA 32x32x2, kernel entries generated on the fly, "
+                           "one workgroup per instance row block)"),
                 "avg_launch_ms": avg_ms, "launches": mm_calls,
                 "algorithmic_GBps": (mm_bytes / max(mm_calls, 1)) / (avg_ms / 1e3) / 1e9
                 if mm_calls else 0.0,
@@ -416,7 +422,7 @@ def batch_main(args, torch, L):
                    "orders": [BatchRunner.K], "probes": BatchRunner.S,
                    "rank": "min(200, n/10)", "oversample": BatchRunner.OVER,
                    "power_iters": BatchRunner.POWER, "tol": runner.tol,
-                   "graph": not args.no_graph},
+                   "graph": not args.no_graph, "batch_form": args.batch_form},
         "probe_solves_per_s": BatchRunner.S * value,
         "eager_value": eager_value,
         "wall_s": wall, "accuracy": accuracy, "roofline": roofline,
@@ -779,6 +785,9 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=8000)
     ap.add_argument("--graphs", action="store_true",
                     help="replay the solver's iterations from captured HIP graphs")
+    ap.add_argument("--batch-form", default="symmetric", choices=["symmetric", "tiled"],
+                    help="batched product: the symmetric form, or the tile shape the autotuner "
+                         "times fastest")
     ap.add_argument("--symmetric", default="", choices=["", "none", "f32", "bf16", "both"],
                     help="on-the-fly forms that generate each off-diagonal block once "
                          "(default: the library's, FP32 only)")

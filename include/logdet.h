@@ -460,6 +460,9 @@ typedef struct {
 #define LD_BATCH_PRECOND_ONLY 4  /* build the preconditioners only: results carry
                                     logdet_P (logdet = logdet_P, trace_term = 0,
                                     iterations = 0) and lambda_out is filled */
+#define LD_BATCH_NO_SYMMETRIC 8  /* up to 16 probes: use the autotuned tile
+                                    shapes instead of the symmetric product
+                                    form (below) */
 
 /* The estimator of logdet_estimate applied to `count` independent problems
  * of uneven size in one pass (the same method per instance, Section 2 and
@@ -488,8 +491,14 @@ typedef struct {
  *               of the row zero), or NULL; lambda_stride >= max rank_i
  * The product kernel's tile shape (matrix-core shape, column blocks, 4 or 2
  * waves per workgroup: up to four candidates for the probe count) is timed
- * on the first call for a probe count and kept in the context.
- * Synchronizes. */
+ * on the first call for a probe count and kept in the context.  For up to
+ * 16 probes (unless LD_BATCH_NO_SYMMETRIC) the symmetric form is used
+ * instead: each instance's kernel matrix in 128 x 128 blocks, only those on
+ * and above the diagonal generated, each off-diagonal block applied to its
+ * rows and, transposed, to its columns (one workgroup per instance, 256-column
+ * strip and run of at most 16 row tiles; partial sums added per row tile by
+ * a second kernel in a fixed order; 8 KB of partial sums per (strip, row
+ * tile) pair in the scratch arena).  Synchronizes. */
 ld_status logdet_estimate_batched(ld_ctx* ctx, int32_t count, const ld_instance* instances,
                                   int32_t k, int32_t num_probes, int32_t oversample,
                                   int32_t power_iters, double tol, int32_t max_iters,

@@ -20,7 +20,7 @@ LD_OK, LD_EINVAL, LD_ENOTSPD, LD_ENOCONV, LD_EHIP, LD_ENOMEM = 0, -1, -2, -3, -4
 LD_RBF, LD_MATERN52 = 0, 1
 LD_F64, LD_F32, LD_BF16 = 0, 1, 2
 LD_ROW_MAJOR, LD_TILED = 0, 1
-LD_BATCH_GRAPH, LD_BATCH_RETUNE, LD_BATCH_PRECOND_ONLY = 1, 2, 4
+LD_BATCH_GRAPH, LD_BATCH_RETUNE, LD_BATCH_PRECOND_ONLY, LD_BATCH_NO_SYMMETRIC = 1, 2, 4, 8
 LD_SUR_FEATURES, LD_SUR_WIDTH, LD_SUR_BINS = 38, 256, 32
 LD_LANCZOS_MAX = 128
 (LD_PRECOND_RSVD, LD_PRECOND_IDENTITY, LD_PRECOND_DIAGONAL, LD_PRECOND_RANK_ONE,
@@ -530,7 +530,7 @@ def logdet_estimate_batched(ctx: Context, items, k: int, num_probes: int, oversa
                             power_iters: int = 2, tol: float = 1e-6, max_iters: int = 5000,
                             graph: bool = False, retune: bool = False, allow_noconv: bool = False,
                             precond_only: bool = False, want_lambda: bool = False,
-                            allow_breakdown: bool = False):
+                            allow_breakdown: bool = False, symmetric: bool = True):
     """Returns (list of result dicts, per-probe values (count, num_probes), status name), and
     with want_lambda also the kept eigenvalues (count, max rank), zero-padded.  With
     allow_breakdown a solver breakdown (LD_ENOTSPD: the results are still filled, the broken
@@ -547,7 +547,8 @@ def logdet_estimate_batched(ctx: Context, items, k: int, num_probes: int, oversa
     res = (Result * max(count, 1))()
     per = np.zeros((max(count, 1), num_probes), dtype=np.float64)
     flags = ((LD_BATCH_GRAPH if graph else 0) | (LD_BATCH_RETUNE if retune else 0)
-             | (LD_BATCH_PRECOND_ONLY if precond_only else 0))
+             | (LD_BATCH_PRECOND_ONLY if precond_only else 0)
+             | (0 if symmetric else LD_BATCH_NO_SYMMETRIC))
     stride = max([it.rank for it in items] + [1])
     lam = np.zeros((max(count, 1), stride), dtype=np.float64) if want_lambda else None
     pd = ctypes.POINTER(ctypes.c_double)

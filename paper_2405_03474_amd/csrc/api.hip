@@ -1497,7 +1497,7 @@ ld_status logdet_estimate_batched(ld_ctx* ctx, int32_t count, const ld_instance*
   if (power_iters < 0 || power_iters > 16) return fail(LD_EINVAL, "power_iters must be in 0..16");
   if (!(tol > 0.0) || !std::isfinite(tol)) return fail(LD_EINVAL, "tol must be finite and > 0");
   if (max_iters < 1) return fail(LD_EINVAL, "max_iters must be >= 1");
-  if (flags & ~(LD_BATCH_GRAPH | LD_BATCH_RETUNE | LD_BATCH_PRECOND_ONLY))
+  if (flags & ~(LD_BATCH_GRAPH | LD_BATCH_RETUNE | LD_BATCH_PRECOND_ONLY | LD_BATCH_NO_SYMMETRIC))
     return fail(LD_EINVAL, "unknown flag bits");
   for (int32_t i = 0; i < count; ++i) {
     const ld_instance& x = instances[i];

@@ -352,6 +352,332 @@ __global__ __launch_bounds__(64 * WAVES) void k_bmm(const BInst* __restrict__ in
 #undef LD_BMM_CASE
 }
 
+// -------------------------------------------- batched product, symmetric --
+// M_i is symmetric, so each instance's off-diagonal kernel entries can be
+// generated once: 128 x 128 blocks on and above the diagonal only, block
+// (I, J), J > I, applied to rows I directly and to rows J transposed.  One
+// workgroup per work item (instance, strip of SMS blocks, range of row
+// tiles), for up to 16 probe columns: it runs the row tiles I of its range
+// (unit (S, I): the blocks J >= I of the strip), each wave generating its 32
+// rows of a 32-column stage.  The direct product is k_bmm's 16x16x4 path.
+// For the transposed one a wave writes its generated 32 x 32 entries
+// column-major to its own LDS slice and reads them back one column per lane
+// (no wave waits for another), with the V rows of the wave in registers.
+// Each wave keeps the transposed sums of its rows over the whole item; they
+// are added across the four waves in LDS once per item (always in wave
+// order) and written to the item's SMS transposed slots.  A strip's row
+// tiles are cut into items of at most SCH, so that no item runs more than
+// SCH SMS blocks (the last strips of a large instance would otherwise be the
+// critical path of the launch once the small instances have converged).
+// Each unit's direct sum goes to its own slot; k_bsym_reduce adds, per row
+// tile, the direct slots of the strips from its own to the last, then the
+// transposed slots of the items of its own strip that hold rows above it,
+// in item order.
+constexpr int SMS = 2;    // blocks of 128 per strip (256 columns)
+constexpr int SCH = 16;   // row tiles per item at most
+constexpr int SBB = 128;  // block edge
+constexpr int STILE = SBB * 16;  // floats per partial slot (128 rows x 16 columns)
+
+struct BSym {     // an instance's partial slots (in tiles of STILE floats)
+  int64_t dir;    // first direct slot; row tile R's slots start dir + base(R)
+  int nblk, ns;   // blocks, strips
+};
+struct BSItem {   // product work item: row tiles [i0, i1) of strip S
+  int inst, S, i0, i1;
+  int64_t tr;     // its SMS transposed slots (one per block of the strip)
+};
+struct BRItem {   // reduce work item: row tile R
+  int inst, R, ntr;  // ntr transposed slots, SMS apart from tr
+  int64_t tr;
+};
+
+// first direct slot of row tile R of an instance (the row tiles before it
+// have ns - R' / SMS slots each: one per strip at or right of their own)
+__host__ __device__ inline int64_t bsym_dir_base(int ns, int64_t R) {
+  const int64_t q = R / SMS, r = R % SMS;
+  return R * ns - (SMS * (q * (q - 1) / 2) + q * r);
+}
+
+template <int KIND, int D>
+__device__ __forceinline__ void bsym_body(const BInst& I, const BSym& Q, const BSItem& it,
+                                          const float* __restrict__ X32,
+                                          const float* __restrict__ V, int ld,
+                                          float* __restrict__ part, float* __restrict__ Bt,
+                                          float* __restrict__ Xs, float* __restrict__ Kw,
+                                          float* __restrict__ red) {
+  constexpr int AS = BBK + 4;   // row stride of the transposed V stage
+  constexpr int KWS = 32 + 4;   // row stride of a wave's column-major K slice
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lj = lane & 15, lg = lane >> 4;
+  const int64_t n = I.n;
+  const float kv = I.kv;
+  const float* Vi = V + I.row0 * ld;
+  const float* Xi = X32 + I.row0 * BDX;
+  float* kw = Kw + wave * (32 * KWS);
+  const int S = it.S;
+  const int mS = SMS * S;
+  const int me = mS + SMS < Q.nblk ? mS + SMS : Q.nblk;
+
+  f32x4v accT[SMS][4][2];
+#pragma unroll
+  for (int b = 0; b < SMS; ++b)
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) accT[b][st][mt] = f32x4v{0.f, 0.f, 0.f, 0.f};
+
+  // stage prefetch: V rows k0 + 2 (tid / 16) (+1) of column tid % 16, one
+  // point coordinate
+  float tv[2], tx;
+  auto load = [&](int64_t k0) {
+    const int c = tid % 16;
+    const int64_t r = k0 + 2 * (tid / 16);
+    tv[0] = (r < n && c < ld) ? Vi[r * ld + c] : 0.f;
+    tv[1] = (r + 1 < n && c < ld) ? Vi[(r + 1) * ld + c] : 0.f;
+    const int64_t kr = k0 + tid / BDX;
+    tx = kr < n ? Xi[kr * BDX + tid % BDX] : 0.f;
+  };
+  auto entry = [&](const float* xr_, const float* xk) {
+    float r2 = 0.f;
+#pragma unroll
+    for (int dd = 0; dd < D; ++dd) {
+      const float df = xr_[dd] - xk[dd];
+      r2 = __builtin_fmaf(df, df, r2);
+    }
+    return dev::kval32s<KIND>(r2, kv);
+  };
+  load((int64_t)SBB * (it.i0 > mS ? it.i0 : mS));
+  int buf = 0;
+  for (int I0 = it.i0; I0 < it.i1; ++I0) {
+    const int64_t i0 = (int64_t)SBB * I0;
+    const int jf = I0 > mS ? I0 : mS;
+    const int64_t ncol = I0 + 1 < it.i1 ? (int64_t)SBB * (I0 + 1 > mS ? I0 + 1 : mS) : -1;
+    float xr[2][D];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t lr = i0 + 32 * wave + 16 * h + lj;
+#pragma unroll
+      for (int dd = 0; dd < D; ++dd) xr[h][dd] = lr < n ? Xi[lr * BDX + dd] : 0.f;
+    }
+    // V rows of this wave as the transposed product's B operand: rows
+    // 32 wave + 8 lg + t, column lj
+    float vi[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t lr = i0 + 32 * wave + 8 * lg + t;
+      vi[t] = (lr < n && lj < ld) ? Vi[lr * ld + lj] : 0.f;
+    }
+    f32x4v acc[2];
+    acc[0] = f32x4v{0.f, 0.f, 0.f, 0.f};
+    acc[1] = acc[0];
+#pragma unroll
+    for (int b = 0; b < SMS; ++b) {
+      const int J = mS + b;
+      if (J < jf || J >= me) continue;
+      const bool sym = J > I0;
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int64_t col0 = (int64_t)SBB * J + BBK * st;
+        float* bt = Bt + buf * 16 * AS;
+        float* xs = Xs + buf * BBK * BDX;
+        *(float2*)&bt[(tid % 16) * AS + 2 * (tid / 16)] = make_float2(tv[0], tv[1]);
+        xs[tid] = tx;
+        __syncthreads();
+        const int64_t nc = col0 + BBK < (int64_t)SBB * me ? col0 + BBK : ncol;
+        if (nc >= 0) load(nc);
+        float a[2][8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const float* xk = &xs[(lg * 8 + t) * BDX];
+          a[0][t] = entry(xr[0], xk);
+          a[1][t] = entry(xr[1], xk);
+        }
+#pragma unroll
+        for (int t4 = 0; t4 < 8; t4 += 4) {
+          const float4 bv = *(const float4*)&bt[lj * AS + lg * 8 + t4];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[h][t4 + 0], bv.x, acc[h], 0, 0, 0);
+            acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[h][t4 + 1], bv.y, acc[h], 0, 0, 0);
+            acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[h][t4 + 2], bv.z, acc[h], 0, 0, 0);
+            acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[h][t4 + 3], bv.w, acc[h], 0, 0, 0);
+          }
+        }
+        if (sym) {
+          // lane (lj, lg) holds K[16 h + lj][8 lg + t] of the wave's rows:
+          // store column-major, read a column per lane
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            kw[(8 * lg + t) * KWS + lj] = a[0][t];
+            kw[(8 * lg + t) * KWS + 16 + lj] = a[1][t];
+          }
+          __builtin_amdgcn_wave_barrier();
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt) {
+            const float4* kp = (const float4*)&kw[(16 * mt + lj) * KWS + 8 * lg];
+            const float4 k0v = kp[0], k1v = kp[1];
+            f32x4v c = accT[b][st][mt];
+            c = __builtin_amdgcn_mfma_f32_16x16x4f32(k0v.x, vi[0], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x4f32(k0v.y, vi[1], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x4f32(k0v.z, vi[2], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x4f32(k0v.w, vi[3], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x4f32(k1v.x, vi[4], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x4f32(k1v.y, vi[5], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x4f32(k1v.z, vi[6], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x4f32(k1v.w, vi[7], c, 0, 0, 0);
+            accT[b][st][mt] = c;
+          }
+          __builtin_amdgcn_wave_barrier();
+        }
+        buf ^= 1;
+      }
+    }
+    // the unit's direct sum (rows 32 wave + 16 h + 4 lg + r, column lj)
+    float* dst = part + (Q.dir + bsym_dir_base(Q.ns, I0) + (S - I0 / SMS)) * STILE;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dst[(32 * wave + 16 * h + 4 * lg + r) * 16 + lj] = acc[h][r];
+  }
+  // transposed sums: rows (columns of M) 32 st + 16 mt + 4 lg + r of block
+  // b, column lj; added over the waves in order
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int b = 0; b < SMS; ++b)
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int e = b * STILE + (32 * st + 16 * mt + 4 * lg + r) * 16 + lj;
+              red[e] = w == 0 ? accT[b][st][mt][r] : red[e] + accT[b][st][mt][r];
+            }
+    }
+    __syncthreads();
+  }
+  float* dst = part + it.tr * STILE;
+  for (int e = tid; e < SMS * STILE; e += 256) dst[e] = red[e];
+}
+
+__global__ __launch_bounds__(256) void k_bmm_sym(const BInst* __restrict__ inst,
+                                                 const BSym* __restrict__ sym,
+                                                 const BSItem* __restrict__ items,
+                                                 const float* __restrict__ X32,
+                                                 const float* __restrict__ V, int ld,
+                                                 float* __restrict__ part,
+                                                 const int* __restrict__ iact) {
+  __shared__ __attribute__((aligned(16))) float Bt[2 * 16 * (BBK + 4)];
+  __shared__ float Xs[2 * BBK * BDX];
+  __shared__ __attribute__((aligned(16))) float Kw[4 * 32 * (32 + 4)];
+  __shared__ float red[SMS * STILE];
+  const BSItem it = items[blockIdx.x];
+  if (iact && !iact[it.inst]) return;  // every probe of this instance has converged
+  const BInst I = inst[it.inst];
+  const BSym Q = sym[it.inst];
+  const int dcat = I.d <= 2 ? 2 : (I.d == 3 ? 3 : (I.d == 4 ? 4 : 8));
+#define LD_BSYM_CASE(KIND, DD) \
+  bsym_body<KIND, DD>(I, Q, it, X32, V, ld, part, Bt, Xs, Kw, red)
+  if (I.kind == LD_RBF) {
+    switch (dcat) {
+      case 2: LD_BSYM_CASE(LD_RBF, 2); break;
+      case 3: LD_BSYM_CASE(LD_RBF, 3); break;
+      case 4: LD_BSYM_CASE(LD_RBF, 4); break;
+      default: LD_BSYM_CASE(LD_RBF, 8); break;
+    }
+  } else {
+    switch (dcat) {
+      case 2: LD_BSYM_CASE(LD_MATERN52, 2); break;
+      case 3: LD_BSYM_CASE(LD_MATERN52, 3); break;
+      case 4: LD_BSYM_CASE(LD_MATERN52, 4); break;
+      default: LD_BSYM_CASE(LD_MATERN52, 8); break;
+    }
+  }
+#undef LD_BSYM_CASE
+}
+
+// Y of row tile (instance, R) = its direct slots in strip order + its
+// transposed slots in item order (+ noise V + alpha2 X2); padded rows
+// written as zero;
+// dots[b][c] = sum over the 64-row block b of V .* Y (the outputs of k_bmm).
+__global__ __launch_bounds__(256) void k_bsym_reduce(const BInst* __restrict__ inst,
+                                                     const BSym* __restrict__ sym,
+                                                     const BRItem* __restrict__ items,
+                                                     const float* __restrict__ part,
+                                                     const float* __restrict__ V, int ld,
+                                                     float* __restrict__ Y,
+                                                     const float* __restrict__ X2, float alpha2,
+                                                     double* __restrict__ dots,
+                                                     const int* __restrict__ iact) {
+  __shared__ double red[256];
+  const BRItem it = items[blockIdx.x];
+  if (iact && !iact[it.inst]) return;
+  const BInst I = inst[it.inst];
+  const BSym Q = sym[it.inst];
+  const int R = it.R;
+  const int tid = threadIdx.x;
+  const int SR = R / SMS;
+  const int ndir = Q.ns - SR;
+  const float* dir = part + (Q.dir + bsym_dir_base(Q.ns, R)) * STILE;
+  const int c = tid % 16;  // 256 threads: rows tid / 16 + 16 j, column c
+  double sum[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) sum[j] = 0.0;
+  int q = 0;
+  for (; q + 4 <= ndir; q += 4) {
+    float v[4][8];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[u][j] = dir[(int64_t)(q + u) * STILE + tid + 256 * j];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sum[j] += (double)v[u][j];
+  }
+  for (; q < ndir; ++q)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sum[j] += (double)dir[(int64_t)q * STILE + tid + 256 * j];
+  for (int c = 0; c < it.ntr; ++c) {
+    const float* trs = part + (it.tr + (int64_t)SMS * c) * STILE;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sum[j] += (double)trs[tid + 256 * j];
+  }
+  double dq[2] = {0.0, 0.0};
+  const int64_t r0 = I.row0 + (int64_t)SBB * R;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int row = tid / 16 + 16 * j;
+    if (c >= ld) continue;
+    const int64_t grow = r0 + row;
+    float y = 0.f;
+    if ((int64_t)SBB * R + row < I.n) {
+      const int64_t off = grow * ld + c;
+      double v = sum[j] + (double)I.noise * (double)V[off];
+      if (X2) v += (double)alpha2 * (double)X2[off];
+      y = (float)v;
+      dq[row / BLK] += (double)V[off] * (double)y;
+    }
+    Y[grow * ld + c] = y;
+  }
+  if (dots) {
+    // 64-row block q: rows 64 q .. 64 q + 63, threads tid / 16 + 16 j with j in 4 q .. 4 q + 3
+#pragma unroll
+    for (int qb = 0; qb < 2; ++qb) {
+      red[tid] = dq[qb];
+      __syncthreads();
+      if (tid < 16 && tid < ld) {
+        double tsum = 0.0;
+        for (int k = tid; k < 256; k += 16) tsum += red[k];
+        dots[(r0 / BLK + qb) * (int64_t)ld + tid] = tsum;
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // -------------------------------------------------------- dense, batched --
 // G_i (mdim_i x mdim_i, leading dimension mdim_i, at i * gstride) =
 // A_i^T diag(w_i) B_i over the instance's rows; 64 x 64 tile per workgroup.
@@ -1146,7 +1472,69 @@ struct ProductPlan {
   int waves = 4;  // 4 waves x 128 rows or 2 waves x 64 rows per workgroup
   int mf = 32;    // matrix-core shape (32: 32x32x2, 16: 16x16x4)
   int nb = 1;     // column sub-blocks: NT = mf * nb columns per workgroup
+  // the symmetric form (k_bmm_sym + k_bsym_reduce; up to 16 columns)
+  bool sym = false;
+  BSym* d_sym = nullptr;
+  BSItem* d_sitems = nullptr;  // (instance, strip, row tiles), most blocks first
+  BRItem* d_ritems = nullptr;  // (instance, row tile)
+  int nsitems = 0, nritems = 0;
+  float* part = nullptr;
 };
+
+// the symmetric form's slots and work items for the batch's instances:
+// direct slots of every instance first, then the transposed slots (SMS per
+// item, an instance's items in strip order and, within a strip, in row order)
+struct SymLayout {
+  std::vector<BSym> sym;
+  std::vector<BSItem> items;
+  std::vector<BRItem> ritems;
+  int64_t slots = 0;
+};
+SymLayout sym_layout(const Batch& b) {
+  SymLayout L;
+  int64_t dir = 0;
+  for (int i = 0; i < b.B; ++i) {
+    BSym q{};
+    q.nblk = (int)((b.h[i].n + SBB - 1) / SBB);
+    q.ns = (q.nblk + SMS - 1) / SMS;
+    q.dir = dir;
+    dir += bsym_dir_base(q.ns, q.nblk);  // one slot per (strip, row tile) unit
+    L.sym.push_back(q);
+  }
+  std::vector<std::pair<int64_t, BSItem>> cost;
+  int64_t tr = dir;
+  for (int i = 0; i < b.B; ++i) {
+    const BSym& q = L.sym[i];
+    std::vector<int64_t> first(q.ns);  // first transposed slot of each strip
+    for (int S = 0; S < q.ns; ++S) {
+      const int mS = SMS * S, me = std::min(mS + SMS, q.nblk);
+      first[S] = tr;
+      for (int i0 = 0; i0 < me; i0 += SCH) {
+        const int i1 = std::min(i0 + SCH, me);
+        int64_t c = 0;  // blocks the item runs
+        for (int I0 = i0; I0 < i1; ++I0) c += me - std::max(I0, mS);
+        cost.push_back({c, BSItem{i, S, i0, i1, tr}});
+        tr += SMS;
+      }
+    }
+    // row tile R takes the items of its strip that hold rows above it
+    for (int R = 0; R < q.nblk; ++R) {
+      const int SR = R / SMS;
+      L.ritems.push_back(BRItem{i, R, (R + SCH - 1) / SCH, first[SR] + (R - SMS * SR)});
+    }
+  }
+  L.slots = tr;
+  std::stable_sort(cost.begin(), cost.end(),
+                   [](const auto& x, const auto& y) { return x.first > y.first; });
+  for (const auto& c : cost) L.items.push_back(c.second);
+  return L;
+}
+
+size_t sym_scratch_bytes(const Batch& b) {
+  const SymLayout L = sym_layout(b);
+  return L.sym.size() * sizeof(BSym) + L.items.size() * sizeof(BSItem) +
+         L.ritems.size() * sizeof(BRItem) + (size_t)L.slots * STILE * sizeof(float) + 4 * 256;
+}
 
 // The product tile shapes the autotuner times for ncols columns: matrix-core
 // shape (16x16x4 or 32x32x2), column sub-blocks and waves per workgroup (4
@@ -1164,8 +1552,34 @@ std::vector<Shape> product_shapes(int ncols) {
   return {{32, 7, 4}};
 }
 
+// the symmetric form is the plan after the tile shapes; it serves products
+// of up to 16 columns unless the tile shapes are asked for (the autotuner
+// does not time it: its first launch, every instance active, does not show
+// the late launches where only the large instances remain)
+bool sym_form(int ncols, int flags) { return !(flags & LD_BATCH_NO_SYMMETRIC) && ncols <= 16; }
+
 ld_status plan_product(ld_ctx* ctx, const Batch& b, int ncols, int variant, ProductPlan* pp) {
   const std::vector<Shape> shapes = product_shapes(ncols);
+  if (ncols <= 16 && variant == (int)shapes.size()) {
+    const SymLayout L = sym_layout(b);
+    pp->sym = true;
+    pp->d_sym = (BSym*)ctx->arena.take(L.sym.size() * sizeof(BSym));
+    pp->d_sitems = (BSItem*)ctx->arena.take(L.items.size() * sizeof(BSItem));
+    pp->d_ritems = (BRItem*)ctx->arena.take(L.ritems.size() * sizeof(BRItem));
+    pp->part = (float*)ctx->arena.take((size_t)L.slots * STILE * sizeof(float));
+    if (!pp->d_sym || !pp->d_sitems || !pp->d_ritems || !pp->part)
+      return fail(LD_ENOMEM, "batch: scratch arena too small for the symmetric product");
+    LD_HIP(hipMemcpyAsync(pp->d_sym, L.sym.data(), L.sym.size() * sizeof(BSym),
+                          hipMemcpyHostToDevice, ctx->stream));
+    LD_HIP(hipMemcpyAsync(pp->d_sitems, L.items.data(), L.items.size() * sizeof(BSItem),
+                          hipMemcpyHostToDevice, ctx->stream));
+    LD_HIP(hipMemcpyAsync(pp->d_ritems, L.ritems.data(), L.ritems.size() * sizeof(BRItem),
+                          hipMemcpyHostToDevice, ctx->stream));
+    LD_HIP(hipStreamSynchronize(ctx->stream));  // the host vectors are released on return
+    pp->nsitems = (int)L.items.size();
+    pp->nritems = (int)L.ritems.size();
+    return LD_OK;
+  }
   const Shape sh = shapes[variant < (int)shapes.size() ? variant : 0];
   const int mf = sh.mf, nb = sh.nb, waves = sh.waves;
   std::vector<BItem> items = make_items(b, 32 * waves, ncols, mf * nb);
@@ -1183,6 +1597,13 @@ ld_status plan_product(ld_ctx* ctx, const Batch& b, int ncols, int variant, Prod
 
 void launch_product(hipStream_t st, const Batch& b, const ProductPlan& pp, const float* V, int ld,
                     float* Y, const float* X2, float alpha2, double* dots, const int* iact) {
+  if (pp.sym) {
+    hipLaunchKernelGGL(k_bmm_sym, dim3(pp.nsitems), dim3(256), 0, st, b.d_inst, pp.d_sym,
+                       pp.d_sitems, b.X32, V, ld, pp.part, iact);
+    hipLaunchKernelGGL(k_bsym_reduce, dim3(pp.nritems), dim3(256), 0, st, b.d_inst, pp.d_sym,
+                       pp.d_ritems, pp.part, V, ld, Y, X2, alpha2, dots, iact);
+    return;
+  }
   const dim3 g(pp.count);
 #define LD_BMM_LAUNCH(MF, NB, W)                                                               \
   hipLaunchKernelGGL((k_bmm<MF, NB, W>), g, dim3(64 * W), 0, st, b.d_inst, pp.d_items, b.X32, V, \
@@ -1364,6 +1785,7 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
   // solver: the autotuner's candidate shapes (at most four, each at most
   // one item per 64-row block and 16 columns)
   for (int q = 0; q < 4; ++q) add(b.nblk * (size_t)((s + 15) / 16) * sizeof(BItem));
+  if (sym_form(s, flags)) add(sym_scratch_bytes(b));
   ctx->arena.reset();
   LD_TRY(ctx->arena.reserve(need));
   Arena& ar = ctx->arena;
@@ -1577,11 +1999,13 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
 
   // product tile shape (autotuner): every candidate shape for s columns is
   // timed once per context (or on request) on this batch's first product,
-  // and the fastest is kept
+  // and the fastest is kept; the symmetric form, where it applies, replaces it
+  const bool use_sym = sym_form(s, flags);
   const int nshape = (int)product_shapes(s).size();
-  ProductPlan pv[4];
-  for (int v = 0; v < nshape; ++v) LD_TRY(with_stream(ctx, st, b, s, v, &pv[v]));
-  if (ctx->bvariant < 0 || ctx->bvariant_cols != s || (flags & LD_BATCH_RETUNE)) {
+  ProductPlan pv[5];
+  for (int v = 0; v < nshape + (use_sym ? 1 : 0); ++v)
+    LD_TRY(with_stream(ctx, st, b, s, v, &pv[v]));
+  if (!use_sym && (ctx->bvariant < 0 || ctx->bvariant_cols != s || (flags & LD_BATCH_RETUNE))) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     LD_HIP(hipEventCreate(&e0));
     LD_HIP(hipEventCreate(&e1));
@@ -1609,7 +2033,7 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
     ctx->bvariant = pick;
     ctx->bvariant_cols = s;
   }
-  const ProductPlan& pp = pv[ctx->bvariant];
+  const ProductPlan& pp = pv[use_sym ? nshape : ctx->bvariant];
   // Instrumentation (ctx->timing, eager form only): events around every
   // product launch and the launch's algorithmic work summed on the device.
   const bool timed = ctx->timing && !use_graph;

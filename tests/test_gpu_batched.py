@@ -107,12 +107,14 @@ def check_instance(g, r, pp, k, s):
     return False
 
 
+@pytest.mark.parametrize("symmetric", [False, True])
 @pytest.mark.parametrize("k", [1, 3, 5])
-def test_batched_matches_oracle(ctx, k):
+def test_batched_matches_oracle(ctx, k, symmetric):
     insts = small_batch()
     s = 16
+    print(f"[batched] k {k} symmetric {symmetric}", flush=True)
     res, per, status = L.logdet_estimate_batched(ctx, items_of(insts), k, s, OVERSAMPLE, POWER,
-                                                 tol=1e-6, max_iters=3000)
+                                                 tol=1e-6, max_iters=3000, symmetric=symmetric)
     assert status == "LD_OK"
     strict = 0
     for g, r, pp in zip(insts, res, per):
@@ -121,18 +123,19 @@ def test_batched_matches_oracle(ctx, k):
     assert strict >= len(insts) - 1
 
 
-def test_batched_graph_equals_eager_and_instances_independent(ctx):
+@pytest.mark.parametrize("symmetric", [False, True])
+def test_batched_graph_equals_eager_and_instances_independent(ctx, symmetric):
     insts = small_batch()
     items = items_of(insts)
-    eager, pe, _ = L.logdet_estimate_batched(ctx, items, 3, 8, OVERSAMPLE, POWER, tol=1e-6)
-    graph, pg, _ = L.logdet_estimate_batched(ctx, items, 3, 8, OVERSAMPLE, POWER, tol=1e-6,
-                                             graph=True)
+    kw = dict(tol=1e-6, symmetric=symmetric)
+    eager, pe, _ = L.logdet_estimate_batched(ctx, items, 3, 8, OVERSAMPLE, POWER, **kw)
+    graph, pg, _ = L.logdet_estimate_batched(ctx, items, 3, 8, OVERSAMPLE, POWER, graph=True, **kw)
     np.testing.assert_array_equal(pe, pg)
     assert [r["logdet"] for r in eager] == [r["logdet"] for r in graph]
     # an instance alone gives bit-for-bit what it gives inside the batch:
     # nothing leaks across the instance segments
     for j in (0, len(insts) - 1):
-        alone, pa, _ = L.logdet_estimate_batched(ctx, [items[j]], 3, 8, OVERSAMPLE, POWER, tol=1e-6)
+        alone, pa, _ = L.logdet_estimate_batched(ctx, [items[j]], 3, 8, OVERSAMPLE, POWER, **kw)
         np.testing.assert_array_equal(pa[0], pe[j])
         assert alone[0]["logdet_P"] == eager[j]["logdet_P"]
 
@@ -185,13 +188,17 @@ def test_batched_error_paths(ctx):
         call([L.BatchItem(**{**it.__dict__, "lengthscale": 0.0})])
 
 
-def test_batched_full_c4_sampled(ctx):
+@pytest.mark.parametrize("symmetric", [False, True])
+def test_batched_full_c4_sampled(ctx, symmetric):
     """The 256-instance heterogeneous batch at full size, in the graph launch
-    the benchmark times; the smallest instances are checked against the
-    oracle one by one and every instance must converge."""
+    the benchmark times (tuned tile shape, and the symmetric form); the
+    smallest instances are checked against the oracle one by one and every
+    instance must converge."""
     insts = workloads.batch_instances()
+    print(f"[batched] c4 symmetric {symmetric}", flush=True)
     res, per, status = L.logdet_estimate_batched(ctx, items_of(insts), 3, 16, OVERSAMPLE, POWER,
-                                                 tol=1e-6, max_iters=3000, graph=True)
+                                                 tol=1e-6, max_iters=3000, graph=True,
+                                                 symmetric=symmetric)
     assert status == "LD_OK"
     assert all(r["converged_cols"] == 16 and np.isfinite(r["logdet"]) for r in res)
     order = np.argsort([g.n for g in insts])

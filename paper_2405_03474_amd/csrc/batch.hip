@@ -562,7 +562,7 @@ __device__ __forceinline__ void bsym_body(const BInst& I, const BSym& Q, const B
   for (int e = tid; e < SMS * STILE; e += 256) dst[e] = red[e];
 }
 
-__global__ __launch_bounds__(256) void k_bmm_sym(const BInst* __restrict__ inst,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_bmm_sym(const BInst* __restrict__ inst,
                                                  const BSym* __restrict__ sym,
                                                  const BSItem* __restrict__ items,
                                                  const float* __restrict__ X32,

@@ -125,36 +125,35 @@ __global__ void k_sum_parts(const double* __restrict__ part, int chunks, int64_t
 }
 
 // OUT = Dinv .* R - F t (t: rank x s FP64) on a 64-row x 64-column tile, the
-// product F t on FP64 matrix cores: stages of 32 rank indices of F (64 rows,
-// coalesced row segments) and of t go through LDS, the next stage prefetched
-// in registers; wave w owns rows 16 w .. 16 w + 15, lane group g supplies
-// rank index 4 step + g.  Optional per-row-tile column dots: dot1 = sum
-// R .* OUT, dot2 = sum Z .* R.
-constexpr int WK = 32;  // rank indices per stage
-template <typename T>
-__global__ __launch_bounds__(256) void k_wood_out(const T* __restrict__ F,
-                                                  const T* __restrict__ Dinv,
+// product F t on FP64 matrix cores; wave w owns rows 16 w .. 16 w + 15.  F
+// goes from HBM straight into the matrix-core registers: in a stage of 32
+// rank indices k0 .. k0 + 31, lane (i, g) = (lane % 16, lane / 16) holds
+// F[row i][k0 + 8 q + 2 g + e], q < 4, e < 2 (four 16-byte loads; in each,
+// the four lanes of a row read 64 consecutive bytes), fetched two stages
+// ahead, and matrix-core step 2 q + e pairs it with t[k0 + 8 q + 2 g + e][c].
+// The stage of t (32 x 64, shared by the four waves) is loaded one stage
+// ahead into registers and kept k-contiguous per column in a double-buffered
+// LDS tile, one barrier per stage.  Optional per-row-tile column dots: dot1 =
+// sum R .* OUT, dot2 = sum Z .* R.
+constexpr int WK = 32;       // rank indices per stage
+constexpr int TKS = WK + 2;  // LDS stride (doubles) of a column of the t stage
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_wood_out(const double* __restrict__ F,
+                                                  const double* __restrict__ Dinv,
                                                   const double* __restrict__ t,
-                                                  const T* __restrict__ R, int64_t n, int rank,
-                                                  int64_t s, T* __restrict__ OUT,
-                                                  const T* __restrict__ Z,
+                                                  const double* __restrict__ R, int64_t n,
+                                                  int rank, int64_t s, double* __restrict__ OUT,
+                                                  const double* __restrict__ Z,
                                                   double* __restrict__ dot1,
                                                   double* __restrict__ dot2) {
-  // the column-dot reduction reuses the staging tiles' LDS after the rank
-  // loop (33.5 KB per workgroup: four workgroups fit a CU, so a 50,000-row
-  // apply runs as one wave of workgroups)
-  __shared__ union {
-    struct {
-      double F[WT][WK + 1];
-      double Tt[WK][WT + 1];
-    } st;
+  typedef double f64x2 __attribute__((ext_vector_type(2)));
+  // the column-dot reduction reuses the t stages' LDS after the rank loop
+  __shared__ __attribute__((aligned(16))) union {
+    double Tt[2][WT * TKS];
     struct {
       double r1[4][64][4];
       double r2[4][64][4];
     } rd;
   } lds;
-  auto& Fs = lds.st.F;
-  auto& Ts = lds.st.Tt;
   auto& red1 = lds.rd.r1;
   auto& red2 = lds.rd.r2;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -162,41 +161,89 @@ __global__ __launch_bounds__(256) void k_wood_out(const T* __restrict__ F,
   const int64_t i0 = (int64_t)blockIdx.x * WT;
   const int64_t c0 = (int64_t)blockIdx.y * WT;
   const int ctl = (int)((s - c0 < WT ? s - c0 + 15 : WT + 15) / 16);
+  const int nst = (rank + WK - 1) / WK;
+  const int64_t arow = i0 + 16 * wave + li;
+  const double* frow = F + arow * rank;
   f64x4w acc[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) acc[c] = f64x4w{0.0, 0.0, 0.0, 0.0};
-  T pf[8];
-  double pt[8];
-  auto fetch = [&](int k0) {
+
+  auto kbase = [&](int st) { return st * WK; };
+  // this lane's 8 F values of stage st (zero past the rank or the rows)
+  auto load_a = [&](int st, double (&a)[8]) {
+    const int k0 = kbase(st);
+    if (arow < n && k0 + WK <= rank && (rank & 1) == 0) {
+      const f64x2* src = (const f64x2*)(frow + k0 + 2 * lg);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f64x2 v = __builtin_nontemporal_load(src + 4 * q);
+        a[2 * q] = v.x;
+        a[2 * q + 1] = v.y;
+      }
+      return;
+    }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int e = tid + 256 * j;
-      const int rr = e / WK, kk = e % WK;  // F: 64 rows x 32 rank indices
-      const int64_t row = i0 + rr;
-      pf[j] = (row < n && k0 + kk < rank) ? F[row * rank + k0 + kk] : (T)0;
-      const int tk = e / WT, tc = e % WT;  // t: 32 rank indices x 64 columns
-      pt[j] = (k0 + tk < rank && c0 + tc < s) ? t[(int64_t)(k0 + tk) * s + c0 + tc] : 0.0;
+      const int k = k0 + 8 * (j >> 1) + 2 * lg + (j & 1);
+      a[j] = (arow < n && k < rank) ? frow[k] : 0.0;
     }
   };
-  fetch(0);
-  for (int k0 = 0; k0 < rank; k0 += WK) {
-    __syncthreads();
+  // t stage: thread column tid % 64, rank indices 8 (tid / 64) + j
+  double tq[8];
+  auto load_t = [&](int st) {
+    const int k = kbase(st) + 8 * (tid / 64);
+    const int64_t col = c0 + tid % 64;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int e = tid + 256 * j;
-      Fs[e / WK][e % WK] = (double)pf[j];
-      Ts[e / WT][e % WT] = pt[j];
-    }
-    __syncthreads();
-    if (k0 + WK < rank) fetch(k0 + WK);
-#pragma unroll 2
-    for (int st = 0; st < WK / 4; ++st) {
-      const int k = 4 * st + lg;
-      const double a = Fs[16 * wave + li][k];
+    for (int j = 0; j < 8; ++j) tq[j] = (k + j < rank && col < s) ? t[(int64_t)(k + j) * s + col] : 0.0;
+  };
+  auto store_t = [&](double* tt) {
+    f64x2* dst = (f64x2*)&tt[(tid % 64) * TKS + 8 * (tid / 64)];
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-        if (c < ctl)
-          acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Ts[k][c * 16 + li], acc[c], 0, 0, 0);
+    for (int q = 0; q < 4; ++q) dst[q] = f64x2{tq[2 * q], tq[2 * q + 1]};
+  };
+
+  double a[2][8];
+  load_a(0, a[0]);
+  if (nst > 1) load_a(1, a[1]);
+  load_t(0);
+  store_t(lds.Tt[0]);
+  if (nst > 1) load_t(1);
+  __syncthreads();
+  for (int st = 0; st < nst; st += 2) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int cur = st + d;
+      if (cur < nst) {
+        // stage cur + 1 into the other buffer (last read in stage cur - 1,
+        // fenced by the barrier that ended it)
+        if (cur + 1 < nst) store_t(lds.Tt[(cur + 1) & 1]);
+        if (cur + 2 < nst) load_t(cur + 2);
+        const double* tt = lds.Tt[cur & 1];
+        // two halves of four steps; in each, the four column tiles' chains
+        // interleave (independent accumulators back to back; tiles past s
+        // multiply the zero columns of the t stage)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          double b[4][4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const f64x2* bp = (const f64x2*)&tt[(c * 16 + li) * TKS + 16 * h + 2 * lg];
+            const f64x2 v0 = bp[0], v1 = bp[4];
+            b[c][0] = v0.x;
+            b[c][1] = v0.y;
+            b[c][2] = v1.x;
+            b[c][3] = v1.y;
+          }
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+              acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[d][4 * h + jj], b[c][jj], acc[c], 0,
+                                                            0, 0);
+        }
+        if (cur + 2 < nst) load_a(cur + 2, a[d]);
+        __syncthreads();
+      }
     }
   }
   double d1[4] = {0.0, 0.0, 0.0, 0.0}, d2[4] = {0.0, 0.0, 0.0, 0.0};
@@ -210,11 +257,11 @@ __global__ __launch_bounds__(256) void k_wood_out(const T* __restrict__ F,
       const int64_t row = i0 + 16 * wave + lg + 4 * r;
       if (row >= n) continue;
       const int64_t off = row * s + cc;
-      const double rv = (double)R[off];
-      const T o = (T)((double)Dinv[row] * rv - acc[c][r]);
+      const double rv = R[off];
+      const double o = Dinv[row] * rv - acc[c][r];
       OUT[off] = o;
-      d1[c] += rv * (double)o;
-      if (dot2) d2[c] += (double)Z[off] * rv;
+      d1[c] += rv * o;
+      if (dot2) d2[c] += Z[off] * rv;
     }
   }
   if (dot1) {
@@ -836,7 +883,7 @@ ld_status wood_apply_t<double>(ld_ctx* ctx, const ld_precond* P, const double* R
                      0, st, P->F64, R, n, rank, s, w.chunk, part);
   hipLaunchKernelGGL(k_sum_parts, dim3(grid1((int64_t)rank * s)), dim3(256), 0, st, part,
                      (int)w.chunks, (int64_t)rank * s, t);
-  hipLaunchKernelGGL(k_wood_out<double>, dim3((unsigned)w.rtiles, w.ctiles), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_wood_out, dim3((unsigned)w.rtiles, w.ctiles), dim3(256), 0, st,
                      P->F64, P->Dinv64, t, R, n, rank, s, OUT, Z, dot1, dot2);
   LD_HIP(hipGetLastError());
   return LD_OK;

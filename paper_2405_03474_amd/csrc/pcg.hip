@@ -114,12 +114,23 @@ __global__ __launch_bounds__(256) void k_ft_partial(const T* __restrict__ F,
   }
 }
 
-__global__ void k_sum_parts(const double* __restrict__ part, int chunks, int64_t count,
-                            double* __restrict__ out) {
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count;
-       e += (int64_t)gridDim.x * 256) {
+// out[e] = sum over the chunks of part[c][e], in chunk order; 64-thread
+// workgroups (more of them in flight) with eight chunks' loads issued
+// together
+__global__ __launch_bounds__(64) void k_sum_parts(const double* __restrict__ part, int chunks,
+                                                  int64_t count, double* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * 64) {
     double s = 0.0;
-    for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * count + e];
+    int c = 0;
+    for (; c + 8 <= chunks; c += 8) {
+      double v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = part[(int64_t)(c + j) * count + e];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s += v[j];
+    }
+    for (; c < chunks; ++c) s += part[(int64_t)c * count + e];
     out[e] = s;
   }
 }
@@ -881,7 +892,7 @@ ld_status wood_apply_t<double>(ld_ctx* ctx, const ld_precond* P, const double* R
   hipStream_t st = ctx->stream;
   hipLaunchKernelGGL(k_ft_partial<double>, dim3((unsigned)w.chunks, w.ltiles, w.ctiles), dim3(256),
                      0, st, P->F64, R, n, rank, s, w.chunk, part);
-  hipLaunchKernelGGL(k_sum_parts, dim3(grid1((int64_t)rank * s)), dim3(256), 0, st, part,
+  hipLaunchKernelGGL(k_sum_parts, dim3(grid1((int64_t)rank * s * 4)), dim3(64), 0, st, part,
                      (int)w.chunks, (int64_t)rank * s, t);
   hipLaunchKernelGGL(k_wood_out, dim3((unsigned)w.rtiles, w.ctiles), dim3(256), 0, st,
                      P->F64, P->Dinv64, t, R, n, rank, s, OUT, Z, dot1, dot2);

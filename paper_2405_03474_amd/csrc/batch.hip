@@ -1191,9 +1191,20 @@ __global__ __launch_bounds__(256) void k_bft_sum(const BInst* __restrict__ inst,
   if (iact && !iact[blockIdx.x]) return;
   const BInst I = inst[blockIdx.x];
   const int64_t cnt = (int64_t)I.rank * s;
+  const int64_t cs = (int64_t)lmax * s;  // stride between chunks
   for (int64_t e = threadIdx.x; e < cnt; e += 256) {
+    const double* src = part + (int64_t)I.ch0 * cs + e;
     double v = 0.0;
-    for (int g = 0; g < I.nch; ++g) v += part[(int64_t)(I.ch0 + g) * lmax * s + e];
+    int g = 0;
+    // in chunk order, eight chunks' loads issued together
+    for (; g + 8 <= I.nch; g += 8) {
+      double x[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) x[j] = src[(int64_t)(g + j) * cs];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v += x[j];
+    }
+    for (; g < I.nch; ++g) v += src[(int64_t)g * cs];
     t[(int64_t)blockIdx.x * lmax * s + e] = v;
   }
 }

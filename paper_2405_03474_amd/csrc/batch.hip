@@ -38,6 +38,12 @@ constexpr int BBK = 32;     // k per stage
 constexpr int BLK = 64;     // row block of the segmented reductions
 constexpr int kChunk = 8;   // solver iterations per host check / graph replay
 constexpr int FTC = 1024;   // rows per partial of the Woodbury projection F^T R
+// Stage points in LDS: point k of a BBK-point stage starts at xrow(k), eight
+// floats further per block of eight points, so that lanes reading points 8
+// (or 16) apart hit different banks; element e = k BDX + dd sits at xs_pos(e)
+constexpr int XSTAGE = BBK * BDX + 8 * (BBK / 8);
+__device__ __forceinline__ int xrow(int k) { return k * BDX + 8 * (k >> 3); }
+__device__ __forceinline__ int xs_pos(int e) { return e + 8 * (e >> 6); }
 
 struct BInst {
   const double* X64;
@@ -207,14 +213,14 @@ __device__ __forceinline__ void bmm_body(const BInst& I, const BItem& it, const 
   int buf = 0;
   for (int st = 0; st < S; ++st) {
     float* bt = Bt + buf * NT * AS;
-    float* xs = Xs + buf * BBK * BDX;
+    float* xs = Xs + buf * XSTAGE;
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int e = tid + NTH * j;
       bt[(e % NT) * AS + e / NT] = tv[j];
     }
 #pragma unroll
-    for (int j = 0; j < XPT; ++j) xs[tid + NTH * j] = tx[j];
+    for (int j = 0; j < XPT; ++j) xs[xs_pos(tid + NTH * j)] = tx[j];
     __syncthreads();
     if (st + 1 < S) load(st + 1);
     if constexpr (MF == 32) {
@@ -223,7 +229,7 @@ __device__ __forceinline__ void bmm_body(const BInst& I, const BItem& it, const 
       for (int t4 = 0; t4 < 16; t4 += 4) {
         float a[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) a[t] = entry(xr[0], &xs[(lh * 16 + t4 + t) * BDX]);
+        for (int t = 0; t < 4; ++t) a[t] = entry(xr[0], &xs[xrow(lh * 16 + t4 + t)]);
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
           const float4 b = *(const float4*)&bt[(nb * 32 + li) * AS + lh * 16 + t4];
@@ -240,7 +246,7 @@ __device__ __forceinline__ void bmm_body(const BInst& I, const BItem& it, const 
         float a[2][4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          const float* xk = &xs[(lg * 8 + t4 + t) * BDX];
+          const float* xk = &xs[xrow(lg * 8 + t4 + t)];
           a[0][t] = entry(xr[0], xk);
           a[1][t] = entry(xr[1], xk);
         }
@@ -326,7 +332,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_bmm(const BInst* __restrict__ in
   constexpr int NT = BmmShape<MF, NB>::NT;
   constexpr int AS = BmmShape<MF, NB>::AS;
   __shared__ __attribute__((aligned(16))) float Bt[2 * NT * AS];
-  __shared__ float Xs[2 * BBK * BDX];
+  __shared__ __attribute__((aligned(16))) float Xs[2 * XSTAGE];
   __shared__ double red[WAVES * 64 * NB];
   const BItem it = items[blockIdx.x];
   if (iact && !iact[it.inst]) return;  // every probe of this instance has converged
@@ -479,16 +485,16 @@ __device__ __forceinline__ void bsym_body(const BInst& I, const BSym& Q, const B
       for (int st = 0; st < 4; ++st) {
         const int64_t col0 = (int64_t)SBB * J + BBK * st;
         float* bt = Bt + buf * 16 * AS;
-        float* xs = Xs + buf * BBK * BDX;
+        float* xs = Xs + buf * XSTAGE;
         *(float2*)&bt[(tid % 16) * AS + 2 * (tid / 16)] = make_float2(tv[0], tv[1]);
-        xs[tid] = tx;
+        xs[xs_pos(tid)] = tx;
         __syncthreads();
         const int64_t nc = col0 + BBK < (int64_t)SBB * me ? col0 + BBK : ncol;
         if (nc >= 0) load(nc);
         float a[2][8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-          const float* xk = &xs[(lg * 8 + t) * BDX];
+          const float* xk = &xs[xrow(lg * 8 + t)];
           a[0][t] = entry(xr[0], xk);
           a[1][t] = entry(xr[1], xk);
         }
@@ -505,16 +511,21 @@ __device__ __forceinline__ void bsym_body(const BInst& I, const BSym& Q, const B
         }
         if (sym) {
           // lane (lj, lg) holds K[16 h + lj][8 lg + t] of the wave's rows:
-          // store column-major, read a column per lane
+          // store column-major, read a column per lane.  Column c keeps its
+          // two 16-row halves swapped when bits 3 and 4 of c differ, so
+          // that the four lane groups of a store (columns 8 apart) fall in
+          // different banks; a read stays four consecutive rows.
+          const int sw = 16 * ((lg & 1) ^ (lg >> 1));
 #pragma unroll
           for (int t = 0; t < 8; ++t) {
-            kw[(8 * lg + t) * KWS + lj] = a[0][t];
-            kw[(8 * lg + t) * KWS + 16 + lj] = a[1][t];
+            kw[(8 * lg + t) * KWS + (lj ^ sw)] = a[0][t];
+            kw[(8 * lg + t) * KWS + ((16 + lj) ^ sw)] = a[1][t];
           }
           __builtin_amdgcn_wave_barrier();
 #pragma unroll
           for (int mt = 0; mt < 2; ++mt) {
-            const float4* kp = (const float4*)&kw[(16 * mt + lj) * KWS + 8 * lg];
+            const int sr = 16 * (((lj >> 3) & 1) ^ mt);
+            const float4* kp = (const float4*)&kw[(16 * mt + lj) * KWS + ((8 * lg) ^ sr)];
             const float4 k0v = kp[0], k1v = kp[1];
             f32x4v c = accT[b][st][mt];
             c = __builtin_amdgcn_mfma_f32_16x16x4f32(k0v.x, vi[0], c, 0, 0, 0);
@@ -570,7 +581,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                                                  float* __restrict__ part,
                                                  const int* __restrict__ iact) {
   __shared__ __attribute__((aligned(16))) float Bt[2 * 16 * (BBK + 4)];
-  __shared__ float Xs[2 * BBK * BDX];
+  __shared__ __attribute__((aligned(16))) float Xs[2 * XSTAGE];
   __shared__ __attribute__((aligned(16))) float Kw[4 * 32 * (32 + 4)];
   __shared__ float red[SMS * STILE];
   const BSItem it = items[blockIdx.x];

@@ -496,7 +496,7 @@ typedef struct {
  * instead: each instance's kernel matrix in 128 x 128 blocks, only those on
  * and above the diagonal generated, each off-diagonal block applied to its
  * rows and, transposed, to its columns (one workgroup per instance, 256-column
- * strip and run of at most 16 row tiles; partial sums added per row tile by
+ * strip and run of at most 8 row tiles; partial sums added per row tile by
  * a second kernel in a fixed order; 8 KB of partial sums per (strip, row
  * tile) pair in the scratch arena).  Synchronizes. */
 ld_status logdet_estimate_batched(ld_ctx* ctx, int32_t count, const ld_instance* instances,

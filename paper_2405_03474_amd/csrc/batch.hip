@@ -380,7 +380,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_bmm(const BInst* __restrict__ in
 // transposed slots of the items of its own strip that hold rows above it,
 // in item order.
 constexpr int SMS = 2;    // blocks of 128 per strip (256 columns)
-constexpr int SCH = 16;   // row tiles per item at most
+constexpr int SCH = 8;    // row tiles per item at most
 constexpr int SBB = 128;  // block edge
 constexpr int STILE = SBB * 16;  // floats per partial slot (128 rows x 16 columns)
 

@@ -75,9 +75,9 @@ def small_batch():
         workloads.GPInstance("ragged_129", n=129, d=8, kind=workloads.RBF, lengthscale=0.9,
                              variance=1.0, noise=1e-3, points="uniform", seed=31, rank=20,
                              probe_seed=32, precond_seed=33),
-        # 20 row tiles of 128: the symmetric form cuts the rows of strips 8
-        # and 9 into two runs (the first 16 row tiles, then the rest), so row
-        # tiles 17..19 add the transposed sums of two runs
+        # 20 row tiles of 128: the symmetric form cuts the rows of strips 4..9
+        # into runs of at most 8 row tiles (three runs from strip 8 on), so
+        # row tiles 17..19 add the transposed sums of three runs
         workloads.GPInstance("two_runs", n=2433, d=3, kind=workloads.MATERN52, lengthscale=0.2,
                              variance=1.1, noise=2e-3, points="uniform", seed=41, rank=40,
                              probe_seed=42, precond_seed=43),

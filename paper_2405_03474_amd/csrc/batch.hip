@@ -184,14 +184,32 @@ __device__ __forceinline__ void bmm_body(const BInst& I, const BItem& it, const 
   }
 
   const int S = (int)((n + BBK - 1) / BBK);
+  // V stage: where the (column, 4 consecutive k) units divide evenly over the
+  // threads, a thread loads such units and stores each as one 16-byte write
+  // (lanes on consecutive columns, AS apart: distinct banks); otherwise one
+  // value per thread and step
+  constexpr bool VEC = (NT * (BBK / 4)) % NTH == 0;
   float tv[VPT], tx[XPT];
   auto load = [&](int st) {
     const int64_t k0 = (int64_t)st * BBK;
+    if constexpr (VEC) {
 #pragma unroll
-    for (int j = 0; j < VPT; ++j) {
-      const int e = tid + NTH * j;
-      const int kk = e / NT, cc = e % NT;
-      tv[j] = (k0 + kk < n && c0 + cc < ld) ? Vi[(k0 + kk) * ld + c0 + cc] : 0.f;
+      for (int j = 0; j < VPT / 4; ++j) {
+        const int u = tid + NTH * j;
+        const int kq = u / NT, cc = u % NT;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t kk = k0 + 4 * kq + i;
+          tv[4 * j + i] = (kk < n && c0 + cc < ld) ? Vi[kk * ld + c0 + cc] : 0.f;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < VPT; ++j) {
+        const int e = tid + NTH * j;
+        const int kk = e / NT, cc = e % NT;
+        tv[j] = (k0 + kk < n && c0 + cc < ld) ? Vi[(k0 + kk) * ld + c0 + cc] : 0.f;
+      }
     }
 #pragma unroll
     for (int j = 0; j < XPT; ++j) {
@@ -214,10 +232,19 @@ __device__ __forceinline__ void bmm_body(const BInst& I, const BItem& it, const 
   for (int st = 0; st < S; ++st) {
     float* bt = Bt + buf * NT * AS;
     float* xs = Xs + buf * XSTAGE;
+    if constexpr (VEC) {
 #pragma unroll
-    for (int j = 0; j < VPT; ++j) {
-      const int e = tid + NTH * j;
-      bt[(e % NT) * AS + e / NT] = tv[j];
+      for (int j = 0; j < VPT / 4; ++j) {
+        const int u = tid + NTH * j;
+        *(float4*)&bt[(u % NT) * AS + 4 * (u / NT)] =
+            make_float4(tv[4 * j], tv[4 * j + 1], tv[4 * j + 2], tv[4 * j + 3]);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < VPT; ++j) {
+        const int e = tid + NTH * j;
+        bt[(e % NT) * AS + e / NT] = tv[j];
+      }
     }
 #pragma unroll
     for (int j = 0; j < XPT; ++j) xs[xs_pos(tid + NTH * j)] = tx[j];
@@ -320,8 +347,12 @@ __device__ __forceinline__ void bmm_body(const BInst& I, const BItem& it, const 
   }
 }
 
+// The 224-column range-finder shape (NB = 7) runs two waves per SIMD: its
+// 112 accumulators then share the 256 registers with the rest (about 33
+// spilled), which still beats one wave per SIMD (51.6 against 60.1 ms per
+// launch on the 256-instance batch)
 template <int MF, int NB, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_bmm(const BInst* __restrict__ inst,
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(NB == 7 ? 2 : 1))) void k_bmm(const BInst* __restrict__ inst,
                                                     const BItem* __restrict__ items,
                                                     const float* __restrict__ X32,
                                                     const float* __restrict__ V, int ld,

@@ -1252,8 +1252,18 @@ __global__ __launch_bounds__(256) void k_bft_sum(const BInst* __restrict__ inst,
 }
 
 // OUT = Dinv R - F t on one 64-row block (wave w: rows 16 w .. 16 w + 15) on
-// FP64 matrix cores, k = the rank index (lane group g supplies k = 4 step + g);
-// dots dot1 = R .* OUT and dot2 = Z .* R per column (s <= 64).
+// FP64 matrix cores over stages of 32 rank indices; dots dot1 = R .* OUT and
+// dot2 = Z .* R per column (s <= 64).  F goes straight into the matrix-core
+// registers: in stage k0, lane (i, g) = (lane % 16, lane / 16) holds
+// F[row i][k0 + 16 h + 4 g + e], h < 2, e < 4 (two 16-byte loads; the four
+// lanes of a row read 64 consecutive bytes), fetched two stages ahead, and
+// step 4 h + e pairs it with t[k0 + 16 h + 4 g + e][c].  The t stage (32 x
+// 64, zero past the instance's rank) is kept k-contiguous per column in a
+// double-buffered LDS tile, loaded one stage ahead, one barrier per stage.
+// F's rows hold ldf (a multiple of 16) values; those at or past the rank
+// enter as zero.
+constexpr int BTK = 32 + 2;  // LDS stride (doubles) of a column of the t stage
+template <int CT>  // 16-column tiles of the output (ceil(s / 16))
 __global__ __launch_bounds__(256) void k_bwout(const BInst* __restrict__ inst,
                                                const int* __restrict__ blk_inst,
                                                const float* __restrict__ F, int ldf,
@@ -1263,39 +1273,106 @@ __global__ __launch_bounds__(256) void k_bwout(const BInst* __restrict__ inst,
                                                float* __restrict__ OUT, const float* __restrict__ Z,
                                                double* __restrict__ dot1, double* __restrict__ dot2,
                                                const int* __restrict__ iact) {
-  __shared__ double red1[4][64][4];
-  __shared__ double red2[4][64][4];
+  typedef double f64x2 __attribute__((ext_vector_type(2)));
+  __shared__ __attribute__((aligned(16))) union {
+    double Tt[2][64 * BTK];
+    struct {
+      double r1[4][64][4];
+      double r2[4][64][4];
+    } rd;
+  } lds;
+  auto& red1 = lds.rd.r1;
+  auto& red2 = lds.rd.r2;
   const int ii = blk_inst[blockIdx.x];
   if (iact && !iact[ii]) return;
   const BInst I = inst[ii];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
   const int64_t b0 = (int64_t)blockIdx.x * 64;
   const int64_t nrow = I.row0 + I.n;  // rows at or past nrow are padding
   const double* tin = t + (int64_t)ii * lmax * s;
-  const int ct = (s + 15) / 16;
+  const int rank = I.rank;
+  const int nst = (rank + 31) / 32;
   const int64_t arow = b0 + 16 * wave + li;  // the row this lane feeds as A operand
   const bool av_ok = arow < nrow;
-  f64x4 acc[4];
+  const float* frow = F + arow * (int64_t)ldf;
+  f64x4 acc[CT];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) acc[c] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < I.rank; k0 += 4) {
-    const int k = k0 + lg;
-    const bool kv = k < I.rank;
-    const double a = (kv && av_ok) ? (double)F[arow * ldf + k] : 0.0;
+  for (int c = 0; c < CT; ++c) acc[c] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  auto load_a = [&](int st, float (&a)[8]) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      if (c < ct) {
-        const int cc = c * 16 + li;
-        const double b = (kv && cc < s) ? tin[(int64_t)k * s + cc] : 0.0;
-        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+    for (int h = 0; h < 2; ++h) {
+      const int k = 32 * st + 16 * h + 4 * lg;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (av_ok && 32 * st + 16 * h < ldf) v = *(const float4*)(frow + k);
+      a[4 * h + 0] = k + 0 < rank ? v.x : 0.f;
+      a[4 * h + 1] = k + 1 < rank ? v.y : 0.f;
+      a[4 * h + 2] = k + 2 < rank ? v.z : 0.f;
+      a[4 * h + 3] = k + 3 < rank ? v.w : 0.f;
+    }
+  };
+  // t stage: thread column tid % 64, rank indices 8 (tid / 64) + j
+  double tq[8];
+  auto load_t = [&](int st) {
+    const int k = 32 * st + 8 * (tid / 64);
+    const int col = tid % 64;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) tq[j] = (k + j < rank && col < s) ? tin[(int64_t)(k + j) * s + col] : 0.0;
+  };
+  auto store_t = [&](double* tt) {
+    f64x2* dst = (f64x2*)&tt[(tid % 64) * BTK + 8 * (tid / 64)];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[q] = f64x2{tq[2 * q], tq[2 * q + 1]};
+  };
+
+  if (nst > 0) {
+    float a[2][8];
+    load_a(0, a[0]);
+    if (nst > 1) load_a(1, a[1]);
+    load_t(0);
+    store_t(lds.Tt[0]);
+    if (nst > 1) load_t(1);
+    __syncthreads();
+    for (int st = 0; st < nst; st += 2) {
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const int cur = st + d;
+        if (cur < nst) {
+          // stage cur + 1 into the other buffer (last read in stage cur - 1,
+          // fenced by the barrier that ended it)
+          if (cur + 1 < nst) store_t(lds.Tt[(cur + 1) & 1]);
+          if (cur + 2 < nst) load_t(cur + 2);
+          const double* tt = lds.Tt[cur & 1];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            double b[CT][4];
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+              const f64x2* bp = (const f64x2*)&tt[(c * 16 + li) * BTK + 16 * h + 4 * lg];
+              const f64x2 v0 = bp[0], v1 = bp[1];
+              b[c][0] = v0.x;
+              b[c][1] = v0.y;
+              b[c][2] = v1.x;
+              b[c][3] = v1.y;
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+              for (int c = 0; c < CT; ++c)
+                acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a[d][4 * h + e], b[c][e],
+                                                              acc[c], 0, 0, 0);
+          }
+          if (cur + 2 < nst) load_a(cur + 2, a[d]);
+          __syncthreads();
+        }
       }
     }
   }
   double d1[4] = {0.0, 0.0, 0.0, 0.0}, d2[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    if (c >= ct) continue;
+  for (int c = 0; c < CT; ++c) {
     const int cc = c * 16 + li;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -2037,8 +2114,17 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
     hipLaunchKernelGGL(k_bft, dim3(nchunks), dim3(256), 0, st, b.d_inst, d_ch_inst, f.F32, b.lmax,
                        rin, s, b.lmax, tpart, act);
     hipLaunchKernelGGL(k_bft_sum, dim3(B), dim3(256), 0, st, b.d_inst, s, b.lmax, tpart, tl, act);
-    hipLaunchKernelGGL(k_bwout, dim3((unsigned)b.nblk), dim3(256), 0, st, b.d_inst, b.d_blk_inst,
-                       f.F32, b.lmax, f.Dinv32, tl, b.lmax, rin, s, uout, Z, d1, d2, act);
+#define LD_BWOUT(CT)                                                                          \
+  hipLaunchKernelGGL((k_bwout<CT>), dim3((unsigned)b.nblk), dim3(256), 0, st, b.d_inst,        \
+                     b.d_blk_inst, f.F32, b.lmax, f.Dinv32, tl, b.lmax, rin, s, uout, Z, d1, d2, \
+                     act)
+    switch ((s + 15) / 16) {
+      case 1: LD_BWOUT(1); break;
+      case 2: LD_BWOUT(2); break;
+      case 3: LD_BWOUT(3); break;
+      default: LD_BWOUT(4); break;
+    }
+#undef LD_BWOUT
   };
   hipLaunchKernelGGL(k_bcopy2, dim3(grid1(vec)), dim3(256), 0, st, Z, r, p, vec);
   woodbury(r, u, nullptr);

@@ -1111,12 +1111,15 @@ __global__ __launch_bounds__(256) void k_blogdet(const BInst* __restrict__ inst,
 // accumulation).  Stages of 32 rows of F (one pass covers up to FT_PW of
 // the rank columns) and of R are loaded with 16-byte reads, prefetched in
 // registers while the previous stage is multiplied out of LDS.  The output is
-// cut into 16 x 16 (l, c) tiles, at most four per wave per pass; in step t a
+// cut into 16 x 16 (l, c) tiles, at most FT_TW per wave per pass (128-column
+// passes: three waves per SIMD, where 256-column passes held two); in step t a
 // wave consumes rows 4t .. 4t+3 of the stage, lane group g = lane/16
 // supplying row 4t + g.  Output lane l, register r: tile row l/16 + 4 r,
 // column l % 16.  Requires ldf % 4 == 0 (16-byte rows of F) and s <= 64.
 constexpr int FT_ROWS = 32;
-constexpr int FT_PW = 256;  // widest column pass (s <= 16; 128 for s <= 32, 64 above)
+constexpr int FT_PW = 128;  // widest column pass (s <= 16; 64 for s <= 32, 32 above)
+constexpr int FT_F4 = FT_ROWS * FT_PW / 4 / 256;  // float4 of the F stage per thread
+constexpr int FT_TW = FT_PW / 64;                 // 16 x 16 tiles per wave at most
 __global__ __launch_bounds__(256) void k_bft(const BInst* __restrict__ inst,
                                              const int* __restrict__ ch_inst,
                                              const float* __restrict__ F, int ldf,
@@ -1141,17 +1144,17 @@ __global__ __launch_bounds__(256) void k_bft(const BInst* __restrict__ inst,
   for (int lbase = 0; lbase < I.rank; lbase += pw) {
     const int lw = I.rank - lbase < pw ? I.rank - lbase : pw;  // columns this pass
     const int lw4 = (lw + 3) / 4;
-    const int tiles = ((lw + 15) / 16) * ct;  // <= 16
-    f64x4 acc[4];
+    const int tiles = ((lw + 15) / 16) * ct;  // <= 4 FT_TW
+    f64x4 acc[FT_TW];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
-    // register prefetch of one stage: F as float4 (<= 8 per thread), R as
+    for (int q = 0; q < FT_TW; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // register prefetch of one stage: F as float4 (FT_F4 per thread), R as
     // floats (the stage's 32 rows of R are contiguous: <= 8 per thread)
-    float4 pf[8];
+    float4 pf[FT_F4];
     float pr[8];
     auto fetch = [&](int64_t row0) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
+      for (int j = 0; j < FT_F4; ++j) {
         const int e = tid + 256 * j;  // float4 index within the stage
         const int rr = e / lw4, c4 = e % lw4;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1172,7 +1175,7 @@ __global__ __launch_bounds__(256) void k_bft(const BInst* __restrict__ inst,
     for (int64_t row0 = lo; row0 < hi; row0 += FT_ROWS) {
       __syncthreads();  // the previous stage has been consumed
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
+      for (int j = 0; j < FT_F4; ++j) {
         const int e = tid + 256 * j;
         const int rr = e / lw4, c4 = e % lw4;
         if (rr < FT_ROWS) {
@@ -1194,7 +1197,7 @@ __global__ __launch_bounds__(256) void k_bft(const BInst* __restrict__ inst,
       __syncthreads();
       if (row0 + FT_ROWS < hi) fetch(row0 + FT_ROWS);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < FT_TW; ++q) {
         const int p = wave + 4 * q;
         if (p < tiles) {
           const int lt = p / ct, cs = p % ct;
@@ -1209,7 +1212,7 @@ __global__ __launch_bounds__(256) void k_bft(const BInst* __restrict__ inst,
       }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < FT_TW; ++q) {
       const int p = wave + 4 * q;
       if (p < tiles) {
         const int lt = p / ct, cs = p % ct;

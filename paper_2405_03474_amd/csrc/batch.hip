@@ -37,7 +37,7 @@ constexpr int BDX = 8;      // point stride (max dimension of a batched instance
 constexpr int BBK = 32;     // k per stage
 constexpr int BLK = 64;     // row block of the segmented reductions
 constexpr int kChunk = 8;   // solver iterations per host check / graph replay
-constexpr int FTC = 1024;   // rows per partial of the Woodbury projection F^T R
+constexpr int FTC = 256;    // rows per partial of the Woodbury projection F^T R
 // Stage points in LDS: point k of a BBK-point stage starts at xrow(k), eight
 // floats further per block of eight points, so that lanes reading points 8
 // (or 16) apart hit different banks; element e = k BDX + dd sits at xs_pos(e)
@@ -1228,16 +1228,19 @@ __global__ __launch_bounds__(256) void k_bft(const BInst* __restrict__ inst,
   }
 }
 
-// t_i = sum of the instance's chunk partials (rank_i x s at i * lmax * s)
-__global__ __launch_bounds__(256) void k_bft_sum(const BInst* __restrict__ inst, int s, int lmax,
-                                                 const double* __restrict__ part,
-                                                 double* __restrict__ t,
-                                                 const int* __restrict__ iact) {
+// t_i = sum of the instance's chunk partials (rank_i x s at i * lmax * s);
+// grid (instances, lmax * s / 64): workgroup (i, y) sums elements 64 y ..
+// 64 y + 63, one per thread
+__global__ __launch_bounds__(64) void k_bft_sum(const BInst* __restrict__ inst, int s, int lmax,
+                                                const double* __restrict__ part,
+                                                double* __restrict__ t,
+                                                const int* __restrict__ iact) {
   if (iact && !iact[blockIdx.x]) return;
   const BInst I = inst[blockIdx.x];
   const int64_t cnt = (int64_t)I.rank * s;
   const int64_t cs = (int64_t)lmax * s;  // stride between chunks
-  for (int64_t e = threadIdx.x; e < cnt; e += 256) {
+  const int64_t e = (int64_t)blockIdx.y * 64 + threadIdx.x;
+  if (e < cnt) {
     const double* src = part + (int64_t)I.ch0 * cs + e;
     double v = 0.0;
     int g = 0;
@@ -2116,7 +2119,8 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
   auto woodbury = [&](const float* rin, float* uout, const int* act) {
     hipLaunchKernelGGL(k_bft, dim3(nchunks), dim3(256), 0, st, b.d_inst, d_ch_inst, f.F32, b.lmax,
                        rin, s, b.lmax, tpart, act);
-    hipLaunchKernelGGL(k_bft_sum, dim3(B), dim3(256), 0, st, b.d_inst, s, b.lmax, tpart, tl, act);
+    hipLaunchKernelGGL(k_bft_sum, dim3(B, (unsigned)((b.lmax * s + 63) / 64)), dim3(64), 0, st,
+                       b.d_inst, s, b.lmax, tpart, tl, act);
 #define LD_BWOUT(CT)                                                                          \
   hipLaunchKernelGGL((k_bwout<CT>), dim3((unsigned)b.nblk), dim3(256), 0, st, b.d_inst,        \
                      b.d_blk_inst, f.F32, b.lmax, f.Dinv32, tl, b.lmax, rin, s, uout, Z, d1, d2, \

@@ -38,6 +38,7 @@ constexpr int BBK = 32;     // k per stage
 constexpr int BLK = 64;     // row block of the segmented reductions
 constexpr int kChunk = 8;   // solver iterations per host check / graph replay
 constexpr int FTC = 256;    // rows per partial of the Woodbury projection F^T R
+constexpr int GCH = 2048;   // rows per partial of the preconditioner's Gram products
 // Stage points in LDS: point k of a BBK-point stage starts at xrow(k), eight
 // floats further per block of eight points, so that lanes reading points 8
 // (or 16) apart hit different banks; element e = k BDX + dd sits at xs_pos(e)
@@ -50,6 +51,7 @@ struct BInst {
   int64_t n, row0;
   int d, kind, m, rank;
   int ch0, nch;  // first FTC-row chunk (global index) and chunk count
+  int gp0, gnch; // GCH-row chunks of the Gram products; first partial slot when gnch > 1
   float kv, noise;       // kv: log2(variance) for RBF, variance for Matern
   double pscale;         // FP32 points are stored times this (see kval32s)
   double diag, floor_v, shift_c;
@@ -722,27 +724,38 @@ __global__ __launch_bounds__(256) void k_bsym_reduce(const BInst* __restrict__ i
 
 // -------------------------------------------------------- dense, batched --
 // G_i (mdim_i x mdim_i, leading dimension mdim_i, at i * gstride) =
-// A_i^T diag(w_i) B_i over the instance's rows; 64 x 64 tile per workgroup.
-__global__ __launch_bounds__(256) void k_bgram(const BInst* __restrict__ inst, int use_rank,
+// A_i^T diag(w_i) B_i over the instance's rows; 64 x 64 tile per workgroup
+// and GCH-row chunk (work item blockIdx.z = (instance, chunk)): an instance
+// of one chunk writes G_i, one of several writes a partial per chunk that
+// k_bgram_sum adds in chunk order (a single workgroup streaming all the rows
+// of a 20,000-point instance was the launch's critical path).  With sym
+// (B = A) only the tiles on and above the diagonal are computed and each
+// off-diagonal one is also written transposed.
+__global__ __launch_bounds__(256) void k_bgram(const BInst* __restrict__ inst,
+                                               const int2* __restrict__ gitems, int use_rank,
                                                const double* __restrict__ A, int lda,
                                                const double* __restrict__ B, int ldb,
                                                const double* __restrict__ w,
-                                               double* __restrict__ G, int64_t gstride) {
+                                               double* __restrict__ G, double* __restrict__ gpart,
+                                               int64_t gstride, int sym) {
   __shared__ double As[16][65];
   __shared__ double Bs[16][65];
-  const BInst I = inst[blockIdx.z];
+  const int2 gi = gitems[blockIdx.z];
+  const BInst I = inst[gi.x];
   const int md = use_rank ? I.rank : I.m;
   const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
-  if (i0 >= md || j0 >= md) return;
+  if (i0 >= md || j0 >= md || (sym && i0 > j0)) return;
+  const int64_t r0 = (int64_t)gi.y * GCH;
+  const int64_t r1 = r0 + GCH < I.n ? r0 + GCH : I.n;
   const int tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
   double acc[4][4] = {};
-  for (int64_t rb = 0; rb < I.n; rb += 16) {
+  for (int64_t rb = r0; rb < r1; rb += 16) {
     __syncthreads();
     for (int e = tid; e < 16 * 64; e += 256) {
       const int rr = e / 64, cc = e % 64;
       const int64_t lr = rb + rr, row = I.row0 + lr;
       double av = 0.0, bv = 0.0;
-      if (lr < I.n) {
+      if (lr < r1) {
         const double wr = w ? w[row] : 1.0;
         if (i0 + cc < md) av = A[row * lda + i0 + cc] * wr;
         if (j0 + cc < md) bv = B[row * ldb + j0 + cc];
@@ -765,14 +778,34 @@ __global__ __launch_bounds__(256) void k_bgram(const BInst* __restrict__ inst, i
         for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
     }
   }
-  double* Gi = G + blockIdx.z * gstride;
+  double* Gi = I.gnch > 1 ? gpart + (I.gp0 + gi.y) * gstride : G + gi.x * gstride;
+  const bool mirror = sym && i0 < j0;
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
     for (int y = 0; y < 4; ++y) {
       const int i = i0 + ti + 16 * x, j = j0 + tj + 16 * y;
-      if (i < md && j < md) Gi[(int64_t)i * md + j] = acc[x][y];
+      if (i < md && j < md) {
+        Gi[(int64_t)i * md + j] = acc[x][y];
+        if (mirror) Gi[(int64_t)j * md + i] = acc[x][y];
+      }
     }
+}
+
+// G_i = sum of its chunk partials, in chunk order (instances of several
+// GCH-row chunks only); grid (instances, mmax^2 / 256)
+__global__ __launch_bounds__(256) void k_bgram_sum(const BInst* __restrict__ inst, int use_rank,
+                                                   const double* __restrict__ gpart,
+                                                   double* __restrict__ G, int64_t gstride) {
+  const BInst I = inst[blockIdx.x];
+  if (I.gnch <= 1) return;
+  const int md = use_rank ? I.rank : I.m;
+  const int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x;
+  if (e >= (int64_t)md * md) return;
+  const double* src = gpart + I.gp0 * gstride + e;
+  double v = 0.0;
+  for (int c = 0; c < I.gnch; ++c) v += src[c * gstride];
+  G[blockIdx.x * gstride + e] = v;
 }
 
 __global__ __launch_bounds__(256) void k_bshift(const BInst* __restrict__ inst,
@@ -1585,7 +1618,13 @@ struct Batch {
   BInst* d_inst = nullptr;
   int* d_blk_inst = nullptr;
   float* X32 = nullptr;
+  int2* d_gitems = nullptr;  // Gram work items (instance, GCH-row chunk)
+  int ngitems = 0;
+  double* gpart = nullptr;   // Gram partials of the instances of several chunks
 };
+
+// grid rows of k_bgram_sum (mmax^2 elements per instance)
+unsigned gsum_rows(const Batch& b) { return (unsigned)((b.gstride + 255) / 256); }
 
 // Work items of the batched product, longest instances first.
 std::vector<BItem> make_items(const Batch& b, int bmw, int ncols, int nt) {
@@ -1794,8 +1833,11 @@ void b_orth(hipStream_t st, const Batch& b, Bufs& f, double* Y, double* W, int p
   double* src = Y;
   double* dst = W;
   for (int pass = 0; pass < passes; ++pass) {
-    hipLaunchKernelGGL(k_bgram, dim3(tiles, tiles, b.B), dim3(256), 0, st, b.d_inst, 0, src, b.mmax,
-                       src, b.mmax, (const double*)nullptr, f.G, b.gstride);
+    hipLaunchKernelGGL(k_bgram, dim3(tiles, tiles, b.ngitems), dim3(256), 0, st, b.d_inst, b.d_gitems,
+                       0, src, b.mmax, src, b.mmax, (const double*)nullptr, f.G, b.gpart,
+                       b.gstride, 1);
+    hipLaunchKernelGGL(k_bgram_sum, dim3(b.B, gsum_rows(b)), dim3(256), 0, st, b.d_inst, 0, b.gpart, f.G,
+                       b.gstride);
     if (pass == 0)
       hipLaunchKernelGGL(k_bshift, dim3(b.B), dim3(256), 0, st, b.d_inst, f.G, b.gstride);
     hipLaunchKernelGGL(k_bchol, dim3(b.B), dim3(dev::CT), 0, st, b.d_inst, 0, f.G, b.gstride,
@@ -1840,6 +1882,7 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
   b.s = s;
   int64_t row0 = 0;
   int nchunks = 0;
+  int ngpart = 0;  // Gram partial slots
   for (int i = 0; i < count; ++i) {
     const ld_instance& x = in[i];
     BInst I{};
@@ -1853,6 +1896,9 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
     I.ch0 = nchunks;
     I.nch = (int)((x.n + FTC - 1) / FTC);
     nchunks += I.nch;
+    I.gnch = (int)((x.n + GCH - 1) / GCH);
+    I.gp0 = ngpart;
+    if (I.gnch > 1) ngpart += I.gnch;
     // points pre-scaled so that r2 is the base-2 exponent (RBF) or its
     // square root is (Matern): kval32s
     const double l2e = 1.4426950408889634;
@@ -1875,11 +1921,21 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
   b.nblk = b.R / BLK;
   b.gstride = (int64_t)b.mmax * b.mmax;
   std::vector<int> blk_inst(b.nblk), ch_inst(nchunks);
+  std::vector<int2> gitems;  // Gram work items (instance, chunk), largest instances first
   for (int i = 0; i < count; ++i) {
     const int64_t first = b.h[i].row0 / BLK, nb = (b.h[i].n + BROWS - 1) / BROWS * (BROWS / BLK);
     for (int64_t q = 0; q < nb; ++q) blk_inst[first + q] = i;
     for (int g = 0; g < b.h[i].nch; ++g) ch_inst[b.h[i].ch0 + g] = i;
   }
+  {
+    std::vector<int> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b.h[x].n > b.h[y].n; });
+    for (int i : order)
+      for (int g = 0; g < b.h[i].gnch; ++g) gitems.push_back(make_int2(i, g));
+  }
+  const int ngitems = (int)gitems.size();
+  b.ngitems = ngitems;
   const int64_t R = b.R, B = count;
   const int64_t ncol = B * s;
   const int cbs = (b.mmax + 63) / 64;
@@ -1890,6 +1946,8 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
   add(B * sizeof(BInst));
   add(b.nblk * sizeof(int));
   add(nchunks * sizeof(int));
+  add(ngitems * sizeof(int2));
+  add((size_t)ngpart * b.gstride * 8);
   add(R * BDX * 4);
   add(R * b.mmax * 8);
   add(R * b.mmax * 8);
@@ -1929,6 +1987,8 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
   b.d_inst = (BInst*)tk(B * sizeof(BInst));
   b.d_blk_inst = (int*)tk(b.nblk * sizeof(int));
   int* d_ch_inst = (int*)tk(nchunks * sizeof(int));
+  b.d_gitems = (int2*)tk(ngitems * sizeof(int2));
+  b.gpart = (double*)tk((size_t)ngpart * b.gstride * 8);
   b.X32 = (float*)tk(R * BDX * 4);
   Bufs f{};
   f.Q = (double*)tk(R * b.mmax * 8);
@@ -1994,6 +2054,7 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
   LD_HIP(hipMemcpyAsync(b.d_inst, b.h.data(), B * sizeof(BInst), hipMemcpyHostToDevice, st));
   LD_HIP(hipMemcpyAsync(b.d_blk_inst, blk_inst.data(), b.nblk * sizeof(int), hipMemcpyHostToDevice, st));
   LD_HIP(hipMemcpyAsync(d_ch_inst, ch_inst.data(), nchunks * sizeof(int), hipMemcpyHostToDevice, st));
+  LD_HIP(hipMemcpyAsync(b.d_gitems, gitems.data(), ngitems * sizeof(int2), hipMemcpyHostToDevice, st));
   LD_HIP(hipMemsetAsync(f.fail, 0, B * 4, st));
   LD_HIP(hipMemsetAsync(f.jstat, 0, B * 4, st));
   hipLaunchKernelGGL(k_bx32, dim3(grid1(R * BDX)), dim3(256), 0, st, b.d_inst, b.d_blk_inst, R, b.X32);
@@ -2014,8 +2075,10 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
   double* MQ = Qb == f.Q ? f.Y : f.Q;
   b_apply(st, b, f, sketch, Qb, MQ);
   const int tiles = (b.mmax + 63) / 64;
-  hipLaunchKernelGGL(k_bgram, dim3(tiles, tiles, B), dim3(256), 0, st, b.d_inst, 0, Qb, b.mmax, MQ,
-                     b.mmax, (const double*)nullptr, f.G, b.gstride);
+  hipLaunchKernelGGL(k_bgram, dim3(tiles, tiles, b.ngitems), dim3(256), 0, st, b.d_inst, b.d_gitems, 0,
+                     Qb, b.mmax, MQ, b.mmax, (const double*)nullptr, f.G, b.gpart, b.gstride, 0);
+  hipLaunchKernelGGL(k_bgram_sum, dim3(B, gsum_rows(b)), dim3(256), 0, st, b.d_inst, 0, b.gpart, f.G,
+                     b.gstride);
   hipLaunchKernelGGL(k_beigh, dim3(B), dim3(1024), 0, st, b.d_inst, f.G, b.gstride, f.jwork,
                      2 * (int64_t)b.mmax * b.mmax, f.evals, b.mmax, f.evecs, f.jstat);
   LD_HIP(hipGetLastError());
@@ -2049,8 +2112,10 @@ ld_status batched_estimate(ld_ctx* ctx, int count, const ld_instance* in, int J,
   hipLaunchKernelGGL(k_bd, dim3(grid1(R)), dim3(256), 0, st, b.d_inst, b.d_blk_inst, R, f.U, b.lmax,
                      f.evals, b.mmax, f.D, f.Dinv64);
   const int ltiles = (b.lmax + 63) / 64;
-  hipLaunchKernelGGL(k_bgram, dim3(ltiles, ltiles, B), dim3(256), 0, st, b.d_inst, 1, f.U, b.lmax,
-                     f.U, b.lmax, f.Dinv64, f.G, b.gstride);
+  hipLaunchKernelGGL(k_bgram, dim3(ltiles, ltiles, b.ngitems), dim3(256), 0, st, b.d_inst, b.d_gitems,
+                     1, f.U, b.lmax, f.U, b.lmax, f.Dinv64, f.G, b.gpart, b.gstride, 1);
+  hipLaunchKernelGGL(k_bgram_sum, dim3(B, gsum_rows(b)), dim3(256), 0, st, b.d_inst, 1, b.gpart, f.G,
+                     b.gstride);
   hipLaunchKernelGGL(k_bcapdiag, dim3(B), dim3(256), 0, st, b.d_inst, f.G, b.gstride, f.evals, b.mmax);
   LD_HIP(hipMemsetAsync(f.fail, 0, B * 4, st));
   hipLaunchKernelGGL(k_bchol, dim3(B), dim3(dev::CT), 0, st, b.d_inst, 1, f.G, b.gstride, f.fail);

@@ -238,18 +238,39 @@ __device__ inline void gemm64_tile(const double* __restrict__ A, int64_t lda,
     for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[rb][nb][r] = 0.0;
-  for (int k0 = 0; k0 < K; k0 += GM_BK) {
-    __syncthreads();
-    for (int e = tid; e < GM_BM * GM_BK; e += 256) {
+  // the next stage is fetched into registers while this one is multiplied
+  constexpr int APT = GM_BM * GM_BK / 256, BPT = GM_BK * GM_BN / 256;
+  double pa[APT], pb[BPT];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+      const int e = tid + 256 * j;
       const int rr = e / GM_BK, kk = e % GM_BK;
       const int64_t row = i0 + rr;
-      As[rr * AS + kk] = (row < n && k0 + kk < K) ? A[row * lda + k0 + kk] : 0.0;
+      pa[j] = (row < n && k0 + kk < K) ? A[row * lda + k0 + kk] : 0.0;
     }
-    for (int e = tid; e < GM_BK * GM_BN; e += 256) {
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int e = tid + 256 * j;
       const int kk = e / GM_BN, cc = e % GM_BN;
-      Bs[kk * BS + cc] = (k0 + kk < K && j0 + cc < N) ? B[(int64_t)(k0 + kk) * ldb + j0 + cc] : 0.0;
+      pb[j] = (k0 + kk < K && j0 + cc < N) ? B[(int64_t)(k0 + kk) * ldb + j0 + cc] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += GM_BK) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+      const int e = tid + 256 * j;
+      As[(e / GM_BK) * AS + e % GM_BK] = pa[j];
+    }
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int e = tid + 256 * j;
+      Bs[(e / GM_BN) * BS + e % GM_BN] = pb[j];
     }
     __syncthreads();
+    if (k0 + GM_BK < K) fetch(k0 + GM_BK);
     double a[2][4];
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
